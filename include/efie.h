@@ -1,0 +1,203 @@
+/*
+ * efie.h -- C ABI of libefie, a gfx950 (MI355X) implementation of the dense
+ * RWG-discretised electric field integral equation (EFIE) for PEC scatterers
+ * and of the Calderon product preconditioner built on it.
+ *
+ * Formulation (readings of the paper where it is silent are listed per call):
+ *   time factor e^{+j omega t}, Green's function G_k(R) = exp(-j k R)/(4 pi R)
+ *     -- the convention fixed by the Hankel function H0^(2) of the paper's
+ *        Green's function (Sec. II, eq. 5), carried to 3-D;
+ *   Galerkin matrices (O)_mn = (f_m, O f_n) over RWG functions f_n
+ *     -- the paper's operator-matrix notation of Sec. III with RWG as the basis;
+ *   Z = eta (j k T_A + T_Phi/(j k)),  (T_A)_mn = <f_m, G f_n>,
+ *   (T_Phi)_mn = <div f_m, G div f_n>,  Z J = V,  V_m = <f_m, E_inc>;
+ *   Calderon product  T_BC(k~) Gmix^-1 Z(k)  with k~ = k - 0.4 j k^(1/3) a^(-2/3)
+ *     -- the multiplicative structure and the complex wavenumber of the
+ *        Calderon-stabilised operator of Sec. III.
+ *
+ * Conventions for every call:
+ *   - Return value: efie_status.  0 = EFIE_OK, 1 = EFIE_NOT_CONVERGED (a warning:
+ *     outputs are filled), < 0 = error; efie_last_error() then holds a message
+ *     (thread-local, valid until the next call on the same thread).
+ *   - No C++ exception crosses this boundary.
+ *   - "dev" pointers are device memory owned by the caller (allocated e.g. by
+ *     torch); the library never frees them and never allocates device memory
+ *     except where a call says so.  "host" pointers are ordinary host memory.
+ *   - Complex buffers are interleaved (re, im): complex128 = 2 doubles,
+ *     complex64 = 2 floats.  Vectors and multi-vectors are row-major
+ *     (nrhs, N): right-hand side s occupies N consecutive complex numbers.
+ *   - Z is N x N row-major; it is symmetric (Z = Z^T), so rows and columns
+ *     may be exchanged freely.
+ *   - Device work is enqueued on the given stream; calls that return host
+ *     values synchronise that stream before returning.
+ *   - Calls on one mesh handle are not thread-safe.
+ */
+#ifndef EFIE_H
+#define EFIE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EFIE_ABI_VERSION 1
+
+typedef enum {
+    EFIE_OK = 0,
+    EFIE_NOT_CONVERGED = 1,
+    EFIE_ERR_ARG = -1,              /* bad argument (null, size, range)            */
+    EFIE_ERR_MESH_OPEN = -2,        /* an edge belongs to one triangle only        */
+    EFIE_ERR_MESH_NONMANIFOLD = -3, /* an edge belongs to more than two triangles  */
+    EFIE_ERR_MESH_ORIENT = -4,      /* neighbouring triangles oriented inconsistently */
+    EFIE_ERR_DEGENERATE = -5,       /* zero-area triangle                           */
+    EFIE_ERR_HIP = -6,              /* a HIP runtime call failed                    */
+    EFIE_ERR_BREAKDOWN = -7,        /* Krylov breakdown (zero denominator)          */
+    EFIE_ERR_NAN = -8,              /* NaN/Inf met in a residual                    */
+    EFIE_ERR_STATE = -9             /* call order violated (e.g. tables not uploaded) */
+} efie_status;
+
+typedef enum { EFIE_C128 = 0, EFIE_C64 = 1 } efie_dtype;
+typedef enum { EFIE_COCG = 0, EFIE_CGS = 1 } efie_solver;
+
+typedef struct efie_mesh_s* efie_mesh;
+
+/* Library version of this header's ABI. */
+int efie_abi_version(void);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* efie_last_error(void);
+
+/* ------------------------------------------------------------------ mesh */
+
+/*
+ * Build the RWG topology of a closed, consistently oriented triangle mesh
+ * (outward normals, counter-clockwise vertex order seen from outside).
+ *   xyz  host, nv x 3 doubles (metres);  tri host, nt x 3 vertex ids.
+ *   near_factor > 0: triangle pairs that share a vertex or whose centroid
+ *   distance is below near_factor * max(longest edge of either) are "near"
+ *   and get singularity extraction (reading: the paper gives no near rule).
+ * RWG numbering: interior edges (a, b), a < b, in lexicographic order; T+ is the
+ * triangle whose boundary runs a -> b, T- the one running b -> a (RWG 1982).
+ * Errors: EFIE_ERR_ARG, EFIE_ERR_MESH_*, EFIE_ERR_DEGENERATE.  *out is set
+ * only on success; release it with efie_mesh_destroy.
+ */
+int efie_mesh_create(const double* xyz, int64_t nv, const int32_t* tri, int64_t nt,
+                     double near_factor, efie_mesh* out);
+
+void efie_mesh_destroy(efie_mesh mesh);
+
+/* Sizes: RWG count N, triangle count T, ordered near pairs (incl. self pairs),
+ * and the byte size of the device tables required by efie_mesh_upload. */
+int efie_mesh_sizes(efie_mesh mesh, int64_t* n_rwg, int64_t* n_tri, int64_t* n_near,
+                    size_t* table_bytes);
+
+/* Host copy of the numbering: edge_v (N x 2 vertex ids a < b), edge_t (N x 2:
+ * T+, T-).  Either pointer may be NULL. */
+int efie_mesh_rwg_table(efie_mesh mesh, int32_t* edge_v, int32_t* edge_t);
+
+/* Copy the structure-of-arrays geometry tables into dev (table_bytes bytes,
+ * 256-byte aligned, caller-owned, must outlive every later call on the mesh).
+ * Synchronises the stream. */
+int efie_mesh_upload(efie_mesh mesh, void* dev, size_t bytes, hipStream_t stream);
+
+/* -------------------------------------------------------------- assembly */
+
+/*
+ * Z = eta (j k T_A + T_Phi/(j k)) for complex k = k_re + j k_im (k_im <= 0),
+ * 7-point degree-5 rule per triangle (reading: the paper names no rule), 7x7
+ * product rule per triangle pair; near pairs split G into (exp(-jkR)-1)/(4 pi R)
+ * (same rule; -jk/(4 pi) at R = 0) plus 1/(4 pi R), the latter with the
+ * closed-form inner integrals of Wilton et al. 1984 / Graglia 1993 over the
+ * source triangle and the 7-point rule over the test triangle, averaged with
+ * its transpose so that Z is exactly symmetric (reading).
+ *   Z dev, N x N complex of type dtype.
+ *   EFIE_C128: every pair in FP64.
+ *   EFIE_C64 : far pairs in FP32 arithmetic, near pairs in FP64, stored as complex64.
+ * parts != 0 returns T_A in Z and T_Phi in Z2 (dev, same shape) instead of Z
+ * (eta and k then only enter the Green's function); otherwise Z2 is ignored.
+ */
+int efie_assemble(efie_mesh mesh, double k_re, double k_im, double eta, int dtype,
+                  void* Z, void* Z2, int parts, hipStream_t stream);
+
+/* ------------------------------------------------------------ excitation */
+
+/*
+ * V[s][m] = int f_m . E0 pol_s exp(-j k khat_s . r) dS by the 7-point rule.
+ *   khat, pol dev, nrhs x 3 doubles (unit propagation vector, polarisation);
+ *   V dev, nrhs x N complex128.
+ */
+int efie_excite_planewave(efie_mesh mesh, double k, const double* khat, const double* pol,
+                          int64_t nrhs, double e0, void* V, hipStream_t stream);
+
+/* --------------------------------------------------------------- far field */
+
+/*
+ * Far-field pattern F(rhat) = -(j k eta/4 pi) (I - rhat rhat) . sum_n J_n
+ * int f_n exp(j k rhat . r') dS' (7-point rule), in (theta-hat, phi-hat)
+ * components; RCS = 4 pi |F|^2 / |E0|^2.
+ *   J dev (nrhs, N) complex128;  dirs dev (ndir, 3) unit vectors;
+ *   F dev (nrhs, ndir, 2) complex128.
+ *   ws dev workspace of at least efie_farfield_workspace_size bytes.
+ */
+int efie_farfield_workspace_size(efie_mesh mesh, int64_t ndir, size_t* bytes);
+int efie_farfield(efie_mesh mesh, double k, double eta, const void* J, int64_t nrhs,
+                  const double* dirs, int64_t ndir, void* F, void* ws, size_t ws_bytes,
+                  hipStream_t stream);
+
+/* ----------------------------------------------------------- Z . X products */
+
+/*
+ * Y = Z X for a dense complex matrix Z (n x n, row-major, either dtype) and
+ * nrhs vectors X (nrhs, n).  X and Y have the dtype of Z.
+ *   nrhs == 1: HBM-bound GEMV (accumulation in FP64 for both dtypes);
+ *   nrhs > 1 : EFIE_C64 -> FP32 matrix-core (MFMA) GEMM with FP32 accumulation,
+ *              EFIE_C128 -> FP64 GEMM.
+ */
+int efie_zx(const void* Z, int dtype, int64_t n, const void* X, void* Y, int64_t nrhs,
+            hipStream_t stream);
+
+/* ------------------------------------------------------------------ solve */
+
+typedef struct {
+    int32_t solver;       /* EFIE_COCG (default) or EFIE_CGS                         */
+    int32_t maxit;        /* iteration cap of one Krylov solve                       */
+    double tol;           /* target ||V - Z J||_2 / ||V||_2 per right-hand side      */
+    int32_t max_refine;   /* EFIE_C64 only: outer refinement steps (>= 1)            */
+    double inner_tol;     /* EFIE_C64 only: relative tolerance of each inner solve   */
+} efie_solve_opts;
+
+typedef struct {
+    int32_t iters;        /* Krylov iterations (summed over refinement steps)        */
+    int32_t status;       /* EFIE_OK, EFIE_NOT_CONVERGED or an error code             */
+    double relres_recur;  /* last recurrence residual of the (last inner) solve       */
+    double relres_true;   /* ||V - Z J|| / ||V|| recomputed at exit (FP64 accumulation) */
+} efie_rhs_stats;
+
+/*
+ * Solve Z J = V for nrhs right-hand sides, x0 = 0 (readings: the paper names CG
+ * and CGS without stating them; "CG" is COCG, CG with the unconjugated bilinear
+ * form, valid since Z = Z^T; CGS is Sonneveld's with shadow residual r0).
+ *   Z dev (dtype as assembled), V dev (nrhs, N) complex128, J dev (nrhs, N)
+ *   complex128 (output).  FP64 vectors and inner products in both cases.
+ *   EFIE_C128: one Krylov solve with FP64 products.
+ *   EFIE_C64 : mixed precision -- inner Krylov solves whose Z X products run on
+ *              FP32 matrix cores, wrapped in an outer refinement loop whose
+ *              residual V - Z J is accumulated in FP64 from the stored complex64 Z.
+ *   stats host, nrhs entries (may be NULL).
+ *   ws dev workspace of efie_solve_workspace_size bytes.
+ * Returns EFIE_NOT_CONVERGED if any right-hand side missed tol.  Synchronises.
+ */
+int efie_solve_workspace_size(int64_t n, int64_t nrhs, int dtype, size_t* bytes);
+int efie_solve(const void* Z, int dtype, int64_t n, const void* V, void* J, int64_t nrhs,
+               const efie_solve_opts* opts, efie_rhs_stats* stats, void* ws, size_t ws_bytes,
+               hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EFIE_H */

@@ -1,0 +1,290 @@
+"""Python binding of libefie (gfx950 EFIE hot path).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of `libefie.so`; torch supplies device memory and the current stream.
+Importing this package does not need a GPU; calling anything that launches
+work does, and fails loudly if the library or the device is missing.
+
+Layouts follow include/efie.h: complex tensors are interleaved (torch complex
+dtypes), multi-vectors are (nrhs, N) row-major, Z is (N, N).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+__all__ = [
+    "lib", "library_path", "EfieError", "Mesh", "assemble", "excite_planewave", "farfield", "zx", "solve",
+    "SolveStats", "ktilde", "ETA0", "C128", "C64", "COCG", "CGS",
+]
+
+ETA0 = 376.730313668
+C128, C64 = 0, 1
+COCG, CGS = 0, 1
+_STATUS = {
+    0: "EFIE_OK", 1: "EFIE_NOT_CONVERGED", -1: "EFIE_ERR_ARG", -2: "EFIE_ERR_MESH_OPEN",
+    -3: "EFIE_ERR_MESH_NONMANIFOLD", -4: "EFIE_ERR_MESH_ORIENT", -5: "EFIE_ERR_DEGENERATE", -6: "EFIE_ERR_HIP",
+    -7: "EFIE_ERR_BREAKDOWN", -8: "EFIE_ERR_NAN", -9: "EFIE_ERR_STATE",
+}
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(HERE, "libefie.so")
+
+# symbols declared in include/efie.h (checked by the CPU tests)
+EXPORTED = [
+    "efie_abi_version", "efie_last_error", "efie_mesh_create", "efie_mesh_destroy", "efie_mesh_sizes",
+    "efie_mesh_rwg_table", "efie_mesh_upload", "efie_assemble", "efie_excite_planewave",
+    "efie_farfield_workspace_size", "efie_farfield", "efie_zx", "efie_solve_workspace_size", "efie_solve",
+]
+
+
+class EfieError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _SolveOpts(ctypes.Structure):
+    _fields_ = [("solver", ctypes.c_int32), ("maxit", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("max_refine", ctypes.c_int32), ("inner_tol", ctypes.c_double)]
+
+
+class _RhsStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("relres_recur", ctypes.c_double),
+                ("relres_true", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libefie.so (built in-tree by paper_2310_15644_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(library_path):
+        raise RuntimeError(f"{library_path} is missing: run `python -m paper_2310_15644_amd.build`")
+    L = ctypes.CDLL(library_path)
+    P, I64, I32, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    sig = {
+        "efie_abi_version": ([], ctypes.c_int),
+        "efie_last_error": ([], ctypes.c_char_p),
+        "efie_mesh_create": ([P, I64, P, I64, D, ctypes.POINTER(P)], ctypes.c_int),
+        "efie_mesh_destroy": ([P], None),
+        "efie_mesh_sizes": ([P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I64),
+                             ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "efie_mesh_rwg_table": ([P, P, P], ctypes.c_int),
+        "efie_mesh_upload": ([P, P, ctypes.c_size_t, P], ctypes.c_int),
+        "efie_assemble": ([P, D, D, D, ctypes.c_int, P, P, ctypes.c_int, P], ctypes.c_int),
+        "efie_excite_planewave": ([P, D, P, P, I64, D, P, P], ctypes.c_int),
+        "efie_farfield_workspace_size": ([P, I64, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "efie_farfield": ([P, D, D, P, I64, P, I64, P, P, ctypes.c_size_t, P], ctypes.c_int),
+        "efie_zx": ([P, ctypes.c_int, I64, P, P, I64, P], ctypes.c_int),
+        "efie_solve_workspace_size": ([I64, I64, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "efie_solve": ([P, ctypes.c_int, I64, P, P, I64, ctypes.POINTER(_SolveOpts), ctypes.POINTER(_RhsStats),
+                        P, ctypes.c_size_t, P], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _check(code, allow_not_converged=False):
+    if code == 0 or (allow_not_converged and code == 1):
+        return code
+    msg = lib().efie_last_error().decode()
+    raise EfieError(code, msg)
+
+
+# ------------------------------------------------------------------ torch glue
+def _torch():
+    import torch
+
+    return torch
+
+
+def _stream(device=None):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _require_cuda(t, name):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def ktilde(k: float, a: float = 1.0) -> complex:
+    """Complex wavenumber of the Calderon preconditioner (paper, Sec. III):
+    k~ = k - 0.4 j k^(1/3) a^(-2/3), a an average radius of curvature."""
+    return complex(k, -0.4 * k ** (1.0 / 3.0) * a ** (-2.0 / 3.0))
+
+
+class Mesh:
+    """Closed triangle mesh with RWG topology (host) and device tables (torch-owned)."""
+
+    def __init__(self, vertices, triangles, near_factor: float = 2.0, device=None):
+        L = lib()
+        v = np.ascontiguousarray(vertices, dtype=np.float64)
+        t = np.ascontiguousarray(triangles, dtype=np.int32)
+        h = ctypes.c_void_p()
+        _check(L.efie_mesh_create(v.ctypes.data, len(v), t.ctypes.data, len(t), float(near_factor), ctypes.byref(h)))
+        self._h = h
+        n, nt, nn, tb = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_size_t()
+        _check(L.efie_mesh_sizes(h, ctypes.byref(n), ctypes.byref(nt), ctypes.byref(nn), ctypes.byref(tb)))
+        self.n, self.t, self.n_near, self.table_bytes = n.value, nt.value, nn.value, tb.value
+        self.nv = len(v)
+        self.vertices = v
+        self.triangles = t
+        self.near_factor = near_factor
+        self._dev = None
+        self._device = device
+
+    def rwg_table(self):
+        ev = np.zeros((self.n, 2), dtype=np.int32)
+        et = np.zeros((self.n, 2), dtype=np.int32)
+        _check(lib().efie_mesh_rwg_table(self._h, ev.ctypes.data, et.ctypes.data))
+        return ev, et
+
+    def upload(self, device=None):
+        """Copy the geometry tables to a torch-owned device buffer (kept by this object)."""
+        torch = _torch()
+        device = device or self._device or "cuda"
+        buf = torch.empty(self.table_bytes + 256, dtype=torch.uint8, device=device)
+        off = (-buf.data_ptr()) % 256
+        view = buf[off:off + self.table_bytes]
+        _check(lib().efie_mesh_upload(self._h, ctypes.c_void_p(view.data_ptr()), self.table_bytes,
+                                      _stream(buf.device)))
+        self._dev = buf
+        self._device = buf.device
+        return self
+
+    @property
+    def device(self):
+        if self._dev is None:
+            self.upload()
+        return self._device
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.efie_mesh_destroy(h)
+            self._h = None
+
+
+def _cdtype(dtype):
+    torch = _torch()
+    if dtype in (C128, "c128", torch.complex128):
+        return C128, torch.complex128
+    if dtype in (C64, "c64", torch.complex64):
+        return C64, torch.complex64
+    raise ValueError(f"bad dtype {dtype}")
+
+
+def assemble(mesh: Mesh, k, eta: float = ETA0, dtype=C128, parts: bool = False, out=None, out2=None):
+    """Dense Z (N, N) on the device; parts=True returns (T_A, T_Phi) instead."""
+    torch = _torch()
+    dev = mesh.device
+    code, tdt = _cdtype(dtype)
+    k = complex(k)
+    Z = out if out is not None else torch.empty((mesh.n, mesh.n), dtype=tdt, device=dev)
+    Z2 = None
+    if parts:
+        Z2 = out2 if out2 is not None else torch.empty((mesh.n, mesh.n), dtype=tdt, device=dev)
+    _require_cuda(Z, "Z")
+    _check(lib().efie_assemble(mesh._h, k.real, k.imag, float(eta), code, _ptr(Z),
+                               _ptr(Z2) if Z2 is not None else None, int(parts), _stream(dev)))
+    return (Z, Z2) if parts else Z
+
+
+def excite_planewave(mesh: Mesh, k: float, khat, pol, e0: float = 1.0, out=None):
+    """V (nrhs, N) complex128 for plane waves E0 pol exp(-j k khat . r)."""
+    torch = _torch()
+    dev = mesh.device
+    kh = torch.as_tensor(np.atleast_2d(khat), dtype=torch.float64).to(dev).contiguous()
+    po = torch.as_tensor(np.atleast_2d(pol), dtype=torch.float64).to(dev).contiguous()
+    S = kh.shape[0]
+    V = out if out is not None else torch.empty((S, mesh.n), dtype=torch.complex128, device=dev)
+    _check(lib().efie_excite_planewave(mesh._h, float(k), _ptr(kh), _ptr(po), S, float(e0), _ptr(V), _stream(dev)))
+    return V
+
+
+def farfield(mesh: Mesh, k: float, J, dirs, eta: float = ETA0):
+    """F (nrhs, ndir, 2) complex128: (theta, phi) components of the far-field pattern."""
+    torch = _torch()
+    dev = mesh.device
+    J = J.reshape(-1, mesh.n)
+    _require_cuda(J, "J")
+    d = torch.as_tensor(np.atleast_2d(dirs), dtype=torch.float64).to(dev).contiguous()
+    nd = d.shape[0]
+    nb = ctypes.c_size_t()
+    _check(lib().efie_farfield_workspace_size(mesh._h, nd, ctypes.byref(nb)))
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+    F = torch.empty((J.shape[0], nd, 2), dtype=torch.complex128, device=dev)
+    _check(lib().efie_farfield(mesh._h, float(k), float(eta), _ptr(J), J.shape[0], _ptr(d), nd, _ptr(F), _ptr(ws),
+                               nb.value, _stream(dev)))
+    return F
+
+
+def zx(Z, X):
+    """Y = Z X for X (nrhs, N) of Z's dtype (one right-hand side: GEMV; complex64: MFMA GEMM)."""
+    torch = _torch()
+    code, tdt = _cdtype(Z.dtype)
+    _require_cuda(Z, "Z")
+    X = X.reshape(-1, Z.shape[0])
+    if X.dtype != tdt:
+        raise ValueError("X must have the dtype of Z")
+    _require_cuda(X, "X")
+    Y = torch.empty_like(X)
+    _check(lib().efie_zx(_ptr(Z), code, Z.shape[0], _ptr(X), _ptr(Y), X.shape[0], _stream(Z.device)))
+    return Y
+
+
+@dataclass
+class SolveStats:
+    iters: np.ndarray
+    status: np.ndarray
+    relres_recur: np.ndarray
+    relres_true: np.ndarray
+    code: int
+
+
+def solve(Z, V, solver=COCG, tol=1e-8, maxit=1000, max_refine=4, inner_tol=1e-3, out=None):
+    """Solve Z J = V for V (nrhs, N) complex128; Z complex128 (FP64) or complex64 (mixed)."""
+    torch = _torch()
+    code_dt, _ = _cdtype(Z.dtype)
+    _require_cuda(Z, "Z")
+    n = Z.shape[0]
+    V = V.reshape(-1, n)
+    _require_cuda(V, "V")
+    if V.dtype != torch.complex128:
+        raise ValueError("V must be complex128")
+    S = V.shape[0]
+    J = out if out is not None else torch.empty_like(V)
+    nb = ctypes.c_size_t()
+    _check(lib().efie_solve_workspace_size(n, S, code_dt, ctypes.byref(nb)))
+    ws = torch.empty(nb.value + 256, dtype=torch.uint8, device=Z.device)
+    off = (-ws.data_ptr()) % 256
+    opts = _SolveOpts(int(solver), int(maxit), float(tol), int(max_refine), float(inner_tol))
+    st = (_RhsStats * S)()
+    code = lib().efie_solve(_ptr(Z), code_dt, n, _ptr(V), _ptr(J), S, ctypes.byref(opts), st,
+                            ctypes.c_void_p(ws.data_ptr() + off), nb.value, _stream(Z.device))
+    _check(code, allow_not_converged=True)
+    stats = SolveStats(
+        iters=np.array([s.iters for s in st]), status=np.array([s.status for s in st]),
+        relres_recur=np.array([s.relres_recur for s in st]), relres_true=np.array([s.relres_true for s in st]),
+        code=code,
+    )
+    return J, stats

@@ -1,0 +1,108 @@
+// Internal declarations of libefie (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/efie.h"
+
+namespace efie {
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string& msg);
+void clear_error();
+
+struct Error {
+    int code;
+    std::string msg;
+};
+
+#define EFIE_HIP_CHECK(expr)                                                          \
+    do {                                                                              \
+        hipError_t _e = (expr);                                                       \
+        if (_e != hipSuccess)                                                         \
+            throw ::efie::Error{EFIE_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(_e)}; \
+    } while (0)
+
+#define EFIE_REQUIRE(cond, code, msg)                                                 \
+    do {                                                                              \
+        if (!(cond)) throw ::efie::Error{(code), (msg)};                              \
+    } while (0)
+
+// Wrap an ABI body: converts Error / std::exception into status + message.
+template <class F>
+int guarded(F&& f) {
+    try {
+        clear_error();
+        return f();
+    } catch (const Error& e) {
+        set_error(e.msg);
+        return e.code;
+    } catch (const std::exception& e) {
+        set_error(std::string("internal: ") + e.what());
+        return EFIE_ERR_ARG;
+    }
+}
+
+constexpr int NQ = 7;   // points of the triangle rule
+
+// --------------------------------------------------- device geometry tables
+// Structure-of-arrays tables of one mesh, all device pointers into the caller's
+// blob.  Index conventions: per-triangle arrays of length T; per (point, tri)
+// arrays are [a * T + t]; per (local vertex i, tri) arrays are [i * T + t].
+// Local edge i of a triangle is the edge opposite its local vertex i, so that
+// vertex i is the free vertex of the RWG half-function carried by that edge.
+struct DevMesh {
+    int32_t T, N, nqb;          // triangles, RWGs, 64-wide source blocks per row of the near mask
+    int32_t n_near;             // ordered near pairs
+    // FP64.  Positions are stored relative to the triangle centroid (cx, cy, cz):
+    // offsets are O(h), so products of offsets keep their relative precision.
+    const double *cx, *cy, *cz;          // centroids [T]
+    const double *qx, *qy, *qz, *qw;     // quadrature point offsets and weights*area [7][T]
+    const double *vx, *vy, *vz;          // vertex offsets [3][T]
+    const double *cf;                    // s l / (2A)            [3][T]
+    const double *dv;                    // s l / A (divergence)  [3][T]
+    const double *nx, *ny, *nz;          // unit normal [T]
+    const double *hm;                    // longest edge [T]
+    // FP32 copies for the complex64 far-pair kernel
+    const float *qx32, *qy32, *qz32, *qw32, *vx32, *vy32, *vz32, *cf32, *dv32;
+    // topology
+    const int32_t* te;                   // RWG index of local edge i [3][T]
+    const uint64_t* near_mask;           // [T][nqb], bit q%64 of word q/64: pair (p,q) is near
+    const int32_t *near_p, *near_q;      // ordered near pairs (incl. p == q)
+    const int32_t *et;                   // RWG -> (T+, T-) [2][N]
+    const int32_t *el;                   // RWG -> local edge index in T+ / T- [2][N]
+};
+
+}  // namespace efie
+
+struct efie_mesh_s {
+    int64_t nv = 0, T = 0, N = 0;
+    double near_factor = 2.0;
+    std::vector<double> xyz;                 // nv*3
+    std::vector<int32_t> tri;                // T*3
+    std::vector<int32_t> edge_v, edge_t, edge_l;  // N*2 each (edge_l: local index in T+/T-)
+    std::vector<double> edge_len;            // N
+    std::vector<int32_t> tri_edge, tri_sign; // T*3
+    std::vector<double> area, normal, centroid, hmax;
+    std::vector<int32_t> near_p, near_q;     // ordered near pairs, sorted by p then q
+    int32_t nqb = 0;
+    std::vector<uint64_t> near_mask;         // T * nqb
+    // device tables (caller-owned blob)
+    void* dev = nullptr;
+    size_t dev_bytes = 0;
+    efie::DevMesh dm{};
+    std::vector<char> host_blob;             // packed image of the device tables
+    std::vector<size_t> offs;                // byte offsets of each table in the blob
+};
+
+namespace efie {
+// mesh.cpp
+void build_mesh(efie_mesh_s& m, const double* xyz, int64_t nv, const int32_t* tri, int64_t nt,
+                double near_factor);
+void pack_tables(efie_mesh_s& m);            // fills host_blob, offs, returns size via host_blob.size()
+void bind_tables(efie_mesh_s& m, void* dev); // sets m.dm pointers into dev
+}  // namespace efie

@@ -1,0 +1,539 @@
+// Krylov solves of Z J = V for many right-hand sides (columns), x0 = 0.
+//
+// The paper names CG and CGS but states neither; the readings implemented are
+//   COCG (van der Vorst and Melissen 1990): CG with the unconjugated bilinear
+//        form a^T b, valid because Z = Z^T; one product Z p per iteration;
+//   CGS  (Sonneveld 1989): conjugated inner products, shadow residual r~ = r0;
+//        two products per iteration.
+// Stopping rule: ||r_k||_2 <= tol ||b||_2 on the recurrence residual.
+//
+// Structure.  The host drives the iteration.  Each iteration launches the
+// Z-products for all columns at once (GEMV for one column, GEMM otherwise) and
+// one fused kernel per algorithm step in which one thread block owns one column:
+// it reduces the inner products (FP64, fixed order, hence deterministic),
+// forms the scalars and updates the vectors, and clears the column's active flag
+// on convergence, breakdown or NaN.  The host reads the number of active
+// columns after each iteration (one 4-byte copy).
+//
+// Mixed precision (complex64 Z): an outer refinement loop computes the residual
+// V - Z J with FP64 accumulation from the stored complex64 Z and solves
+// Z d = residual by an inner Krylov solve whose Z-products run on FP32 matrix
+// cores; J += d.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <vector>
+
+#include "efie_internal.h"
+#include "linalg.h"
+
+namespace efie {
+
+struct Col {
+    double rho_r, rho_i;    // current rho (COCG: r^T r, CGS: r~^H r)
+    double alpha_r, alpha_i;
+    double bn2;             // ||b||^2
+    double rn2;             // ||r||^2 (recurrence)
+    double tol2;            // tol^2 ||b||^2
+    int active, iters, status, pad;
+};
+
+constexpr int KB = 512;   // threads per column block
+
+struct C2 {
+    double r, i;
+};
+__device__ __forceinline__ C2 cmul(C2 a, C2 b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
+__device__ __forceinline__ C2 cdiv(C2 a, C2 b) {
+    double d = b.r * b.r + b.i * b.i;
+    return {(a.r * b.r + a.i * b.i) / d, (a.i * b.r - a.r * b.i) / d};
+}
+
+// Block-wide sum of NV doubles; every thread gets the totals.
+template <int NV>
+__device__ void block_sum(double (&v)[NV], double* sh) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) sh[w * NV + k] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double s = 0.0;
+        for (int u = 0; u < KB / 64; ++u) s += sh[u * NV + k];
+        v[k] = s;
+    }
+}
+
+__device__ __forceinline__ void finish_check(Col& c, double rn2) {
+    c.rn2 = rn2;
+    if (!(rn2 == rn2) || rn2 > 1e300) {
+        c.status = EFIE_ERR_NAN;
+        c.active = 0;
+    } else if (rn2 <= c.tol2) {
+        c.status = EFIE_OK;
+        c.active = 0;
+    }
+}
+
+// ------------------------------------------------------------------ COCG
+// init: x = 0, r = b, p = r, rho = r^T r
+__global__ __launch_bounds__(KB) void cocg_init(const double2* b, double2* x, double2* r, double2* p, Col* cols,
+                                                int n, double tol) {
+    __shared__ double sh[KB / 64 * 4];
+    const int s = blockIdx.x;
+    const double2* bs = b + size_t(s) * n;
+    double v[4] = {0, 0, 0, 0};   // rho_r, rho_i, ||b||^2
+    for (int k = threadIdx.x; k < n; k += KB) {
+        double2 e = bs[k];
+        x[size_t(s) * n + k] = make_double2(0, 0);
+        r[size_t(s) * n + k] = e;
+        p[size_t(s) * n + k] = e;
+        v[0] += e.x * e.x - e.y * e.y;
+        v[1] += 2.0 * e.x * e.y;
+        v[2] += e.x * e.x + e.y * e.y;
+    }
+    block_sum<4>(v, sh);
+    if (threadIdx.x == 0) {
+        Col c{};
+        c.rho_r = v[0];
+        c.rho_i = v[1];
+        c.bn2 = v[2];
+        c.tol2 = tol * tol * v[2];
+        c.active = 1;
+        c.status = EFIE_NOT_CONVERGED;
+        c.iters = 0;
+        finish_check(c, v[2]);
+        if (v[2] == 0.0) c.status = EFIE_OK;
+        cols[s] = c;
+    }
+}
+
+// one COCG step after q = Z p:  mu = p^T q, alpha = rho/mu, x += alpha p,
+// r -= alpha q, rho' = r^T r, beta = rho'/rho, p = r + beta p.
+__global__ __launch_bounds__(KB) void cocg_step(double2* x, double2* r, double2* p, const double2* q, Col* cols,
+                                                int n, int* nactive) {
+    __shared__ double sh[KB / 64 * 4];
+    __shared__ int go;
+    const int s = blockIdx.x;
+    if (threadIdx.x == 0) go = cols[s].active;
+    __syncthreads();
+    if (!go) return;
+    const size_t o = size_t(s) * n;
+    double v[4] = {0, 0, 0, 0};
+    for (int k = threadIdx.x; k < n; k += KB) {
+        double2 pp = p[o + k], qq = q[o + k];
+        v[0] += pp.x * qq.x - pp.y * qq.y;
+        v[1] += pp.x * qq.y + pp.y * qq.x;
+    }
+    block_sum<4>(v, sh);
+    Col c = cols[s];
+    const C2 mu{v[0], v[1]};
+    if (mu.r == 0.0 && mu.i == 0.0) {
+        if (threadIdx.x == 0) {
+            cols[s].status = EFIE_ERR_BREAKDOWN;
+            cols[s].active = 0;
+        }
+        return;
+    }
+    const C2 alpha = cdiv(C2{c.rho_r, c.rho_i}, mu);
+    double w[4] = {0, 0, 0, 0};
+    for (int k = threadIdx.x; k < n; k += KB) {
+        double2 pp = p[o + k], qq = q[o + k], xx = x[o + k], rr = r[o + k];
+        xx.x += alpha.r * pp.x - alpha.i * pp.y;
+        xx.y += alpha.r * pp.y + alpha.i * pp.x;
+        rr.x -= alpha.r * qq.x - alpha.i * qq.y;
+        rr.y -= alpha.r * qq.y + alpha.i * qq.x;
+        x[o + k] = xx;
+        r[o + k] = rr;
+        w[0] += rr.x * rr.x - rr.y * rr.y;
+        w[1] += 2.0 * rr.x * rr.y;
+        w[2] += rr.x * rr.x + rr.y * rr.y;
+    }
+    block_sum<4>(w, sh);
+    const C2 rho_new{w[0], w[1]};
+    if (rho_new.r == 0.0 && rho_new.i == 0.0 && w[2] > c.tol2) {
+        if (threadIdx.x == 0) {
+            cols[s].status = EFIE_ERR_BREAKDOWN;
+            cols[s].active = 0;
+            cols[s].rn2 = w[2];
+            cols[s].iters = c.iters + 1;
+        }
+        return;
+    }
+    const C2 beta = cdiv(rho_new, C2{c.rho_r, c.rho_i});
+    for (int k = threadIdx.x; k < n; k += KB) {
+        double2 pp = p[o + k], rr = r[o + k];
+        double2 np;
+        np.x = rr.x + beta.r * pp.x - beta.i * pp.y;
+        np.y = rr.y + beta.r * pp.y + beta.i * pp.x;
+        p[o + k] = np;
+    }
+    if (threadIdx.x == 0) {
+        c.rho_r = rho_new.r;
+        c.rho_i = rho_new.i;
+        c.iters += 1;
+        finish_check(c, w[2]);
+        cols[s] = c;
+        if (c.active) atomicAdd(nactive, 1);
+    }
+}
+
+// ------------------------------------------------------------------- CGS
+// vectors: r, rt (shadow), u, p, q, v (also holds t), w
+__global__ __launch_bounds__(KB) void cgs_init(const double2* b, double2* x, double2* r, double2* rt, double2* u,
+                                               double2* p, Col* cols, int n, double tol) {
+    __shared__ double sh[KB / 64 * 4];
+    const int s = blockIdx.x;
+    const size_t o = size_t(s) * n;
+    double v[4] = {0, 0, 0, 0};
+    for (int k = threadIdx.x; k < n; k += KB) {
+        double2 e = b[o + k];
+        x[o + k] = make_double2(0, 0);
+        r[o + k] = e;
+        rt[o + k] = e;
+        u[o + k] = e;
+        p[o + k] = e;
+        v[0] += e.x * e.x + e.y * e.y;
+    }
+    block_sum<4>(v, sh);
+    if (threadIdx.x == 0) {
+        Col c{};
+        c.rho_r = v[0];   // r~^H r = ||r0||^2
+        c.rho_i = 0.0;
+        c.bn2 = v[0];
+        c.tol2 = tol * tol * v[0];
+        c.active = 1;
+        c.status = EFIE_NOT_CONVERGED;
+        finish_check(c, v[0]);
+        if (v[0] == 0.0) c.status = EFIE_OK;
+        cols[s] = c;
+    }
+}
+
+// after v = Z p: sigma = r~^H v, alpha = rho/sigma, q = u - alpha v, w = u + q, x += alpha w
+__global__ __launch_bounds__(KB) void cgs_step1(double2* x, const double2* rt, const double2* u, const double2* v,
+                                                double2* q, double2* w, Col* cols, int n) {
+    __shared__ double sh[KB / 64 * 4];
+    __shared__ int go;
+    const int s = blockIdx.x;
+    if (threadIdx.x == 0) go = cols[s].active;
+    __syncthreads();
+    if (!go) return;
+    const size_t o = size_t(s) * n;
+    double a[4] = {0, 0, 0, 0};
+    for (int k = threadIdx.x; k < n; k += KB) {
+        double2 t = rt[o + k], vv = v[o + k];
+        a[0] += t.x * vv.x + t.y * vv.y;    // conj(rt) v
+        a[1] += t.x * vv.y - t.y * vv.x;
+    }
+    block_sum<4>(a, sh);
+    const C2 sigma{a[0], a[1]};
+    Col c = cols[s];
+    if (sigma.r == 0.0 && sigma.i == 0.0) {
+        if (threadIdx.x == 0) {
+            cols[s].status = EFIE_ERR_BREAKDOWN;
+            cols[s].active = 0;
+        }
+        return;
+    }
+    const C2 alpha = cdiv(C2{c.rho_r, c.rho_i}, sigma);
+    for (int k = threadIdx.x; k < n; k += KB) {
+        double2 uu = u[o + k], vv = v[o + k], xx = x[o + k];
+        double2 qq, ww;
+        qq.x = uu.x - (alpha.r * vv.x - alpha.i * vv.y);
+        qq.y = uu.y - (alpha.r * vv.y + alpha.i * vv.x);
+        ww.x = uu.x + qq.x;
+        ww.y = uu.y + qq.y;
+        xx.x += alpha.r * ww.x - alpha.i * ww.y;
+        xx.y += alpha.r * ww.y + alpha.i * ww.x;
+        q[o + k] = qq;
+        w[o + k] = ww;
+        x[o + k] = xx;
+    }
+    if (threadIdx.x == 0) {
+        cols[s].alpha_r = alpha.r;
+        cols[s].alpha_i = alpha.i;
+    }
+}
+
+// after t = Z w: r -= alpha t, rho' = r~^H r, beta = rho'/rho, u = r + beta q,
+// p = u + beta (q + beta p)
+__global__ __launch_bounds__(KB) void cgs_step2(double2* r, const double2* rt, double2* u, double2* p,
+                                                const double2* q, const double2* t, Col* cols, int n, int* nactive) {
+    __shared__ double sh[KB / 64 * 4];
+    __shared__ int go;
+    const int s = blockIdx.x;
+    if (threadIdx.x == 0) go = cols[s].active;
+    __syncthreads();
+    if (!go) return;
+    const size_t o = size_t(s) * n;
+    Col c = cols[s];
+    const C2 alpha{c.alpha_r, c.alpha_i};
+    double a[4] = {0, 0, 0, 0};
+    for (int k = threadIdx.x; k < n; k += KB) {
+        double2 rr = r[o + k], tt = t[o + k], sh_ = rt[o + k];
+        rr.x -= alpha.r * tt.x - alpha.i * tt.y;
+        rr.y -= alpha.r * tt.y + alpha.i * tt.x;
+        r[o + k] = rr;
+        a[0] += sh_.x * rr.x + sh_.y * rr.y;
+        a[1] += sh_.x * rr.y - sh_.y * rr.x;
+        a[2] += rr.x * rr.x + rr.y * rr.y;
+    }
+    block_sum<4>(a, sh);
+    const C2 rho_new{a[0], a[1]};
+    if (rho_new.r == 0.0 && rho_new.i == 0.0 && a[2] > c.tol2) {
+        if (threadIdx.x == 0) {
+            cols[s].status = EFIE_ERR_BREAKDOWN;
+            cols[s].active = 0;
+            cols[s].rn2 = a[2];
+            cols[s].iters = c.iters + 1;
+        }
+        return;
+    }
+    const C2 beta = cdiv(rho_new, C2{c.rho_r, c.rho_i});
+    for (int k = threadIdx.x; k < n; k += KB) {
+        double2 rr = r[o + k], qq = q[o + k], pp = p[o + k];
+        double2 uu, np, tq;
+        uu.x = rr.x + beta.r * qq.x - beta.i * qq.y;
+        uu.y = rr.y + beta.r * qq.y + beta.i * qq.x;
+        tq.x = qq.x + beta.r * pp.x - beta.i * pp.y;
+        tq.y = qq.y + beta.r * pp.y + beta.i * pp.x;
+        np.x = uu.x + beta.r * tq.x - beta.i * tq.y;
+        np.y = uu.y + beta.r * tq.y + beta.i * tq.x;
+        u[o + k] = uu;
+        p[o + k] = np;
+    }
+    if (threadIdx.x == 0) {
+        c.rho_r = rho_new.r;
+        c.rho_i = rho_new.i;
+        c.iters += 1;
+        finish_check(c, a[2]);
+        cols[s] = c;
+        if (c.active) atomicAdd(nactive, 1);
+    }
+}
+
+// ----------------------------------------------------------- helper kernels
+// out = b - y, and per-column ||out||^2 into nrm[s]
+__global__ __launch_bounds__(KB) void residual_kernel(const double2* b, const double2* y, double2* out, double* nrm,
+                                                      double* bnrm, int n) {
+    __shared__ double sh[KB / 64 * 4];
+    const int s = blockIdx.x;
+    const size_t o = size_t(s) * n;
+    double a[4] = {0, 0, 0, 0};
+    for (int k = threadIdx.x; k < n; k += KB) {
+        double2 bb = b[o + k], yy = y[o + k];
+        double2 d = make_double2(bb.x - yy.x, bb.y - yy.y);
+        if (out) out[o + k] = d;
+        a[0] += d.x * d.x + d.y * d.y;
+        a[1] += bb.x * bb.x + bb.y * bb.y;
+    }
+    block_sum<4>(a, sh);
+    if (threadIdx.x == 0) {
+        nrm[s] = a[0];
+        bnrm[s] = a[1];
+    }
+}
+
+__global__ void axpy_inplace_kernel(double2* x, const double2* d, size_t n) {
+    for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
+        double2 a = x[i], b = d[i];
+        x[i] = make_double2(a.x + b.x, a.y + b.y);
+    }
+}
+
+namespace {
+
+struct Ws {
+    double2 *r, *rt, *u, *p, *q, *v, *w;   // Krylov vectors (S x n each)
+    double2 *res, *dlt;                     // outer refinement: residual and correction
+    float2 *x32, *y32;                      // complex64 staging for matrix-core products
+    Col* cols;
+    double *nrm, *bnrm;
+    int* nactive;
+};
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+size_t layout(int64_t n, int64_t S, int dtype, Ws* ws, char* base) {
+    const size_t vec = align256(size_t(n) * size_t(S) * 16);
+    const size_t vec32 = dtype == EFIE_C64 && S > 1 ? align256(size_t(n) * size_t(S) * 8) : 0;
+    const size_t outer = dtype == EFIE_C64 ? vec : 0;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* p = base ? base + off : nullptr;
+        off += align256(bytes);
+        return p;
+    };
+    Ws w{};
+    w.r = (double2*)take(vec); w.rt = (double2*)take(vec); w.u = (double2*)take(vec); w.p = (double2*)take(vec);
+    w.q = (double2*)take(vec); w.v = (double2*)take(vec); w.w = (double2*)take(vec);
+    w.res = (double2*)take(outer); w.dlt = (double2*)take(outer);
+    w.x32 = (float2*)take(vec32); w.y32 = (float2*)take(vec32);
+    w.cols = (Col*)take(sizeof(Col) * size_t(S));
+    w.nrm = (double*)take(sizeof(double) * size_t(S));
+    w.bnrm = (double*)take(sizeof(double) * size_t(S));
+    w.nactive = (int*)take(sizeof(int) * 4);
+    if (ws) *ws = w;
+    return off;
+}
+
+// Y = Z X for FP64 vectors; complex64 Z goes through complex64 staging and the
+// matrix-core GEMM when S > 1 (GEMV reads FP64 vectors directly otherwise).
+void product(const void* Z, int zdt, int n, const double2* X, double2* Y, int S, const Ws& w, hipStream_t st) {
+    if (zdt == EFIE_C64 && S > 1) {
+        cast_c128_to_c64(X, w.x32, size_t(n) * S, st);
+        cgemm_mfma(w.x32, Z, w.y32, S, n, st);
+        cast_c64_to_c128(w.y32, Y, size_t(n) * S, st);
+    } else {
+        zx_product(Z, zdt, n, X, EFIE_C128, Y, S, st);
+    }
+}
+
+// FP64-accumulated residual out = b - Z x (Z of either dtype); norms into w.nrm / w.bnrm.
+void true_residual(const void* Z, int zdt, int n, const double2* b, const double2* x, double2* out, int S,
+                   const Ws& w, hipStream_t st) {
+    double2* y = w.q;   // scratch
+    if (S == 1)
+        gemv(Z, zdt, n, x, EFIE_C128, y, EFIE_C128, st);
+    else
+        zgemm_nt(x, EFIE_C128, Z, zdt, y, EFIE_C128, S, n, n, n, n, n, 1.0, 0.0, false, st);
+    hipLaunchKernelGGL(residual_kernel, dim3(S), dim3(KB), 0, st, b, y, out, w.nrm, w.bnrm, n);
+}
+
+// One Krylov solve of Z x = b for S columns.  Returns per-column Col states in host memory.
+void krylov(const void* Z, int zdt, int n, const double2* b, double2* x, int S, int solver, double tol, int maxit,
+            const Ws& w, std::vector<Col>& out, hipStream_t st) {
+    int h_active = 0;
+    if (solver == EFIE_COCG) {
+        hipLaunchKernelGGL(cocg_init, dim3(S), dim3(KB), 0, st, b, x, w.r, w.p, w.cols, n, tol);
+        for (int it = 0; it < maxit; ++it) {
+            product(Z, zdt, n, w.p, w.q, S, w, st);
+            EFIE_HIP_CHECK(hipMemsetAsync(w.nactive, 0, sizeof(int), st));
+            hipLaunchKernelGGL(cocg_step, dim3(S), dim3(KB), 0, st, x, w.r, w.p, w.q, w.cols, n, w.nactive);
+            EFIE_HIP_CHECK(hipMemcpyAsync(&h_active, w.nactive, sizeof(int), hipMemcpyDeviceToHost, st));
+            EFIE_HIP_CHECK(hipStreamSynchronize(st));
+            if (h_active == 0) break;
+        }
+    } else {
+        hipLaunchKernelGGL(cgs_init, dim3(S), dim3(KB), 0, st, b, x, w.r, w.rt, w.u, w.p, w.cols, n, tol);
+        for (int it = 0; it < maxit; ++it) {
+            product(Z, zdt, n, w.p, w.v, S, w, st);
+            hipLaunchKernelGGL(cgs_step1, dim3(S), dim3(KB), 0, st, x, w.rt, w.u, w.v, w.q, w.w, w.cols, n);
+            product(Z, zdt, n, w.w, w.v, S, w, st);
+            EFIE_HIP_CHECK(hipMemsetAsync(w.nactive, 0, sizeof(int), st));
+            hipLaunchKernelGGL(cgs_step2, dim3(S), dim3(KB), 0, st, w.r, w.rt, w.u, w.p, w.q, w.v, w.cols, n,
+                               w.nactive);
+            EFIE_HIP_CHECK(hipMemcpyAsync(&h_active, w.nactive, sizeof(int), hipMemcpyDeviceToHost, st));
+            EFIE_HIP_CHECK(hipStreamSynchronize(st));
+            if (h_active == 0) break;
+        }
+    }
+    EFIE_HIP_CHECK(hipGetLastError());
+    out.resize(S);
+    EFIE_HIP_CHECK(hipMemcpyAsync(out.data(), w.cols, sizeof(Col) * S, hipMemcpyDeviceToHost, st));
+    EFIE_HIP_CHECK(hipStreamSynchronize(st));
+}
+
+}  // namespace
+}  // namespace efie
+
+extern "C" int efie_solve_workspace_size(int64_t n, int64_t nrhs, int dtype, size_t* bytes) {
+    return efie::guarded([&]() {
+        EFIE_REQUIRE(bytes && n >= 1 && nrhs >= 1, EFIE_ERR_ARG, "solve_workspace_size: bad argument");
+        EFIE_REQUIRE(dtype == EFIE_C128 || dtype == EFIE_C64, EFIE_ERR_ARG, "solve_workspace_size: bad dtype");
+        *bytes = efie::layout(n, nrhs, dtype, nullptr, nullptr);
+        return int(EFIE_OK);
+    });
+}
+
+extern "C" int efie_solve(const void* Z, int dtype, int64_t n, const void* V, void* J, int64_t nrhs,
+                          const efie_solve_opts* opts, efie_rhs_stats* stats, void* ws, size_t ws_bytes,
+                          hipStream_t stream) {
+    using namespace efie;
+    return guarded([&]() {
+        EFIE_REQUIRE(Z && V && J && opts && ws, EFIE_ERR_ARG, "solve: null argument");
+        EFIE_REQUIRE(dtype == EFIE_C128 || dtype == EFIE_C64, EFIE_ERR_ARG, "solve: bad dtype");
+        EFIE_REQUIRE(n >= 1 && n < (int64_t(1) << 31) && nrhs >= 1 && nrhs <= 65535, EFIE_ERR_ARG,
+                     "solve: bad sizes");
+        EFIE_REQUIRE(opts->solver == EFIE_COCG || opts->solver == EFIE_CGS, EFIE_ERR_ARG, "solve: bad solver");
+        EFIE_REQUIRE(opts->maxit >= 1 && opts->tol > 0.0, EFIE_ERR_ARG, "solve: need maxit >= 1 and tol > 0");
+        const size_t need = layout(n, nrhs, dtype, nullptr, nullptr);
+        EFIE_REQUIRE(ws_bytes >= need, EFIE_ERR_ARG, "solve: workspace too small");
+        EFIE_REQUIRE((reinterpret_cast<uintptr_t>(ws) & 255) == 0, EFIE_ERR_ARG, "solve: workspace not 256-aligned");
+        Ws w;
+        layout(n, nrhs, dtype, &w, static_cast<char*>(ws));
+        const int S = int(nrhs), nn = int(n);
+        const double2* b = static_cast<const double2*>(V);
+        double2* x = static_cast<double2*>(J);
+        std::vector<Col> cols;
+        std::vector<int> iters(S, 0);
+        std::vector<double> recur(S, 0.0);
+        if (dtype == EFIE_C128) {
+            krylov(Z, dtype, nn, b, x, S, opts->solver, opts->tol, opts->maxit, w, cols, stream);
+            for (int s = 0; s < S; ++s) {
+                iters[s] = cols[s].iters;
+                recur[s] = cols[s].bn2 > 0 ? std::sqrt(cols[s].rn2 / cols[s].bn2) : 0.0;
+            }
+        } else {
+            EFIE_REQUIRE(opts->max_refine >= 1 && opts->inner_tol > 0.0, EFIE_ERR_ARG,
+                         "solve: mixed precision needs max_refine >= 1 and inner_tol > 0");
+            fill_zero_bytes(x, size_t(nn) * S * 16, stream);
+            std::vector<double> h_nrm(S), h_bn(S);
+            for (int outer = 0; outer < opts->max_refine; ++outer) {
+                if (outer > 0) {
+                    true_residual(Z, dtype, nn, b, x, w.res, S, w, stream);
+                    EFIE_HIP_CHECK(hipMemcpyAsync(h_nrm.data(), w.nrm, sizeof(double) * S, hipMemcpyDeviceToHost, stream));
+                    EFIE_HIP_CHECK(hipMemcpyAsync(h_bn.data(), w.bnrm, sizeof(double) * S, hipMemcpyDeviceToHost, stream));
+                    EFIE_HIP_CHECK(hipStreamSynchronize(stream));
+                    bool done = true;
+                    for (int s = 0; s < S; ++s)
+                        if (h_nrm[s] > opts->tol * opts->tol * h_bn[s]) done = false;
+                    if (done) break;
+                } else {
+                    EFIE_HIP_CHECK(hipMemcpyAsync(w.res, b, size_t(nn) * S * 16, hipMemcpyDeviceToDevice, stream));
+                }
+                // inner solve Z d = res to inner_tol (columns already converged have a
+                // residual below tol; the inner solve then stops at once or adds little)
+                krylov(Z, dtype, nn, w.res, w.dlt, S, opts->solver, opts->inner_tol, opts->maxit, w, cols, stream);
+                const size_t tot = size_t(nn) * S;
+                hipLaunchKernelGGL(axpy_inplace_kernel, dim3(int(std::min<size_t>((tot + 255) / 256, 16384))),
+                                   dim3(256), 0, stream, x, w.dlt, tot);
+                for (int s = 0; s < S; ++s) {
+                    iters[s] += cols[s].iters;
+                    recur[s] = cols[s].bn2 > 0 ? std::sqrt(cols[s].rn2 / cols[s].bn2) : 0.0;
+                }
+            }
+        }
+        // true residual at exit (FP64 accumulation)
+        true_residual(Z, dtype, nn, b, x, nullptr, S, w, stream);
+        std::vector<double> h_nrm(S), h_bn(S);
+        EFIE_HIP_CHECK(hipMemcpyAsync(h_nrm.data(), w.nrm, sizeof(double) * S, hipMemcpyDeviceToHost, stream));
+        EFIE_HIP_CHECK(hipMemcpyAsync(h_bn.data(), w.bnrm, sizeof(double) * S, hipMemcpyDeviceToHost, stream));
+        EFIE_HIP_CHECK(hipStreamSynchronize(stream));
+        int ret = EFIE_OK;
+        for (int s = 0; s < S; ++s) {
+            const double rel = h_bn[s] > 0 ? std::sqrt(h_nrm[s] / h_bn[s]) : 0.0;
+            // FP64 operator: the recurrence stopping rule decides; mixed precision:
+            // the FP64-accumulated true residual of the outer loop decides.
+            int st = cols[s].status;
+            if (dtype == EFIE_C64 && st >= 0) st = rel <= opts->tol ? EFIE_OK : EFIE_NOT_CONVERGED;
+            if (!(rel == rel)) st = EFIE_ERR_NAN;
+            if (stats) {
+                stats[s].iters = iters[s];
+                stats[s].status = st;
+                stats[s].relres_recur = recur[s];
+                stats[s].relres_true = rel;
+            }
+            if (st < 0 && ret >= 0) ret = st;
+            else if (st == EFIE_NOT_CONVERGED && ret == EFIE_OK) ret = EFIE_NOT_CONVERGED;
+        }
+        return ret;
+    });
+}

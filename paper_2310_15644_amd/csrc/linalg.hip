@@ -1,0 +1,242 @@
+// Dense complex products for the EFIE operator on gfx950.
+//
+//   gemv:      y = Z x, one wavefront per row of Z, 16-byte loads, FP64 accumulation
+//              (single right-hand side: HBM-bound, 1 or 0.5 flop per byte).
+//   zgemm_nt:  C[M][Nc] = sum_k A[M][k] B[Nc][k] with both operands k-contiguous,
+//              LDS-tiled, FP64 accumulation; B may be complex64 or complex128.
+//              Z X for many right-hand sides is this product with A = X (nrhs x N),
+//              B = Z (N x N, symmetric), C = Y (nrhs x N).
+//   cast kernels between complex64 and complex128.
+#include <hip/hip_runtime.h>
+
+#include "efie_internal.h"
+#include "linalg.h"
+
+namespace efie {
+
+// ------------------------------------------------------------------ GEMV
+template <typename T>
+struct CT;   // complex element traits: load one element as FP64 pair
+template <>
+struct CT<double2> {
+    __device__ static double2 ld(const double2* p, size_t i) { return p[i]; }
+};
+template <>
+struct CT<float2> {
+    __device__ static double2 ld(const float2* p, size_t i) {
+        float2 v = p[i];
+        return make_double2(v.x, v.y);
+    }
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <typename YT>
+__device__ __forceinline__ void store_c(YT* y, size_t i, double re, double im);
+template <>
+__device__ __forceinline__ void store_c<double2>(double2* y, size_t i, double re, double im) {
+    y[i] = make_double2(re, im);
+}
+template <>
+__device__ __forceinline__ void store_c<float2>(float2* y, size_t i, double re, double im) {
+    y[i] = make_float2(float(re), float(im));
+}
+
+// one element per lane per load, 4 loads in flight (16-byte loads for complex128;
+// also the fallback for complex64 matrices of odd order).
+template <typename ZT, typename XT, typename YT>
+__global__ __launch_bounds__(256) void gemv_elem_kernel(const ZT* __restrict__ Z, const XT* __restrict__ x,
+                                                        YT* __restrict__ y, int n) {
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= n) return;
+    const ZT* zr = Z + size_t(row) * n;
+    double ar = 0, ai = 0;
+    int k = lane;
+    for (; k + 192 < n; k += 256) {
+        double2 z0 = CT<ZT>::ld(zr, k), z1 = CT<ZT>::ld(zr, k + 64), z2 = CT<ZT>::ld(zr, k + 128),
+                z3 = CT<ZT>::ld(zr, k + 192);
+        double2 x0 = CT<XT>::ld(x, k), x1 = CT<XT>::ld(x, k + 64), x2 = CT<XT>::ld(x, k + 128),
+                x3 = CT<XT>::ld(x, k + 192);
+        ar += z0.x * x0.x - z0.y * x0.y + z1.x * x1.x - z1.y * x1.y + z2.x * x2.x - z2.y * x2.y + z3.x * x3.x -
+              z3.y * x3.y;
+        ai += z0.x * x0.y + z0.y * x0.x + z1.x * x1.y + z1.y * x1.x + z2.x * x2.y + z2.y * x2.x + z3.x * x3.y +
+              z3.y * x3.x;
+    }
+    for (; k < n; k += 64) {
+        double2 z0 = CT<ZT>::ld(zr, k), x0 = CT<XT>::ld(x, k);
+        ar += z0.x * x0.x - z0.y * x0.y;
+        ai += z0.x * x0.y + z0.y * x0.x;
+    }
+    ar = wave_sum(ar);
+    ai = wave_sum(ai);
+    if (lane == 0) store_c<YT>(y, row, ar, ai);
+}
+
+// complex64 Z: each lane reads two elements (16 bytes) per load; needs n even.
+template <typename XT, typename YT>
+__global__ __launch_bounds__(256) void gemv_c64_kernel(const float2* __restrict__ Z, const XT* __restrict__ x,
+                                                       YT* __restrict__ y, int n) {
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= n) return;
+    const float4* zr = reinterpret_cast<const float4*>(Z + size_t(row) * n);
+    const int n2 = n >> 1;
+    double ar = 0, ai = 0;
+    int k = lane;
+    for (; k + 192 < n2; k += 256) {
+        float4 z[4] = {zr[k], zr[k + 64], zr[k + 128], zr[k + 192]};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int kk = 2 * (k + 64 * u);
+            double2 xa = CT<XT>::ld(x, kk), xb = CT<XT>::ld(x, kk + 1);
+            ar += double(z[u].x) * xa.x - double(z[u].y) * xa.y + double(z[u].z) * xb.x - double(z[u].w) * xb.y;
+            ai += double(z[u].x) * xa.y + double(z[u].y) * xa.x + double(z[u].z) * xb.y + double(z[u].w) * xb.x;
+        }
+    }
+    for (; k < n2; k += 64) {
+        float4 z0 = zr[k];
+        double2 xa = CT<XT>::ld(x, 2 * k), xb = CT<XT>::ld(x, 2 * k + 1);
+        ar += double(z0.x) * xa.x - double(z0.y) * xa.y + double(z0.z) * xb.x - double(z0.w) * xb.y;
+        ai += double(z0.x) * xa.y + double(z0.y) * xa.x + double(z0.z) * xb.y + double(z0.w) * xb.x;
+    }
+    ar = wave_sum(ar);
+    ai = wave_sum(ai);
+    if (lane == 0) store_c<YT>(y, row, ar, ai);
+}
+
+// ------------------------------------------------------------- tiled GEMM
+// C[M][Nc] (+)= alpha * sum_k A[M][k] B[Nc][k]; 64 x 64 output tile per block of
+// 256 threads (4 x 4 complex outputs each), k-chunks of 16 staged in LDS.
+constexpr int GT = 64, GK = 16;
+
+template <typename AT, typename BT, typename CTy>
+__global__ __launch_bounds__(256) void zgemm_nt_kernel(const AT* __restrict__ A, const BT* __restrict__ B,
+                                                       CTy* __restrict__ C, int M, int Nc, int K, int lda, int ldb,
+                                                       int ldc, double alr, double ali, int accumulate) {
+    __shared__ double2 As[GK][GT + 1];
+    __shared__ double2 Bs[GK][GT + 1];
+    const int tid = threadIdx.x;
+    const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
+    const int tm = tid / 16, tn = tid % 16;   // 16 x 16 threads, each 4 x 4 outputs (strided by 16)
+    double cr[4][4], ci[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) cr[i][j] = ci[i][j] = 0.0;
+    for (int k0 = 0; k0 < K; k0 += GK) {
+        // 64 x 16 elements of A and of B: 1024 each, 4 per thread
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            const int e = tid + 256 * l;
+            const int r = e / GK, kk = e % GK;
+            const int gm = m0 + r, gn = n0 + r, gk = k0 + kk;
+            As[kk][r] = (gm < M && gk < K) ? CT<AT>::ld(A, size_t(gm) * lda + gk) : make_double2(0, 0);
+            Bs[kk][r] = (gn < Nc && gk < K) ? CT<BT>::ld(B, size_t(gn) * ldb + gk) : make_double2(0, 0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < GK; ++kk) {
+            double2 a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = As[kk][tm + 16 * i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tn + 16 * j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    cr[i][j] += a[i].x * b[j].x - a[i].y * b[j].y;
+                    ci[i][j] += a[i].x * b[j].y + a[i].y * b[j].x;
+                }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int gm = m0 + tm + 16 * i;
+        if (gm >= M) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int gn = n0 + tn + 16 * j;
+            if (gn >= Nc) continue;
+            double re = alr * cr[i][j] - ali * ci[i][j];
+            double im = alr * ci[i][j] + ali * cr[i][j];
+            const size_t o = size_t(gm) * ldc + gn;
+            if (accumulate) {
+                double2 old = CT<CTy>::ld(C, o);
+                re += old.x;
+                im += old.y;
+            }
+            store_c<CTy>(C, o, re, im);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ casts
+__global__ void cast_c128_to_c64_kernel(const double2* __restrict__ a, float2* __restrict__ b, size_t n) {
+    for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
+        b[i] = make_float2(float(a[i].x), float(a[i].y));
+}
+__global__ void cast_c64_to_c128_kernel(const float2* __restrict__ a, double2* __restrict__ b, size_t n) {
+    for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
+        b[i] = make_double2(a[i].x, a[i].y);
+}
+
+static int grid_for(size_t n) { return int(std::min<size_t>((n + 255) / 256, 16384)); }
+
+void cast_c128_to_c64(const void* a, void* b, size_t n, hipStream_t s) {
+    if (n) hipLaunchKernelGGL(cast_c128_to_c64_kernel, dim3(grid_for(n)), dim3(256), 0, s,
+                              static_cast<const double2*>(a), static_cast<float2*>(b), n);
+}
+void cast_c64_to_c128(const void* a, void* b, size_t n, hipStream_t s) {
+    if (n) hipLaunchKernelGGL(cast_c64_to_c128_kernel, dim3(grid_for(n)), dim3(256), 0, s,
+                              static_cast<const float2*>(a), static_cast<double2*>(b), n);
+}
+
+// ------------------------------------------------------------- dispatchers
+void gemv(const void* Z, int zdt, int n, const void* x, int xdt, void* y, int ydt, hipStream_t s) {
+    dim3 grid((n + 3) / 4), blk(256);
+#define GEMV_CASE(KER, ZTy, XTy, YTy) \
+    hipLaunchKernelGGL((KER), grid, blk, 0, s, static_cast<const ZTy*>(Z), static_cast<const XTy*>(x), \
+                       static_cast<YTy*>(y), n)
+    if (zdt == EFIE_C128) {
+        if (xdt == EFIE_C128 && ydt == EFIE_C128)
+            GEMV_CASE((gemv_elem_kernel<double2, double2, double2>), double2, double2, double2);
+        else if (xdt == EFIE_C64 && ydt == EFIE_C64)
+            GEMV_CASE((gemv_elem_kernel<double2, float2, float2>), double2, float2, float2);
+        else throw Error{EFIE_ERR_ARG, "gemv: unsupported dtype combination"};
+    } else if (n % 2 == 0) {
+        if (xdt == EFIE_C128 && ydt == EFIE_C128) GEMV_CASE((gemv_c64_kernel<double2, double2>), float2, double2, double2);
+        else if (xdt == EFIE_C64 && ydt == EFIE_C64) GEMV_CASE((gemv_c64_kernel<float2, float2>), float2, float2, float2);
+        else throw Error{EFIE_ERR_ARG, "gemv: unsupported dtype combination"};
+    } else {
+        if (xdt == EFIE_C128 && ydt == EFIE_C128)
+            GEMV_CASE((gemv_elem_kernel<float2, double2, double2>), float2, double2, double2);
+        else if (xdt == EFIE_C64 && ydt == EFIE_C64)
+            GEMV_CASE((gemv_elem_kernel<float2, float2, float2>), float2, float2, float2);
+        else throw Error{EFIE_ERR_ARG, "gemv: unsupported dtype combination"};
+    }
+#undef GEMV_CASE
+}
+
+void zgemm_nt(const void* A, int adt, const void* B, int bdt, void* C, int cdt, int M, int Nc, int K, int lda,
+              int ldb, int ldc, double alr, double ali, bool accumulate, hipStream_t s) {
+    dim3 grid((Nc + GT - 1) / GT, (M + GT - 1) / GT), blk(256);
+    EFIE_REQUIRE(grid.y <= 65535, EFIE_ERR_ARG, "zgemm: too many rows");
+#define ZG(ATy, BTy, CTy2)                                                                                     \
+    hipLaunchKernelGGL((zgemm_nt_kernel<ATy, BTy, CTy2>), grid, blk, 0, s, static_cast<const ATy*>(A),         \
+                       static_cast<const BTy*>(B), static_cast<CTy2*>(C), M, Nc, K, lda, ldb, ldc, alr, ali, \
+                       int(accumulate))
+    if (adt == EFIE_C128 && bdt == EFIE_C128 && cdt == EFIE_C128) ZG(double2, double2, double2);
+    else if (adt == EFIE_C128 && bdt == EFIE_C64 && cdt == EFIE_C128) ZG(double2, float2, double2);
+    else if (adt == EFIE_C64 && bdt == EFIE_C64 && cdt == EFIE_C64) ZG(float2, float2, float2);
+    else throw Error{EFIE_ERR_ARG, "zgemm: unsupported dtype combination"};
+#undef ZG
+}
+
+}  // namespace efie

@@ -1,0 +1,259 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Tolerances (derived in the design notes):
+  FP64 operator entries: max |dZ| <= 1e-11 max |Z| (rounding-order differences only);
+  complex64 operator: max |dZ| <= 2e-5 max |Z| (FP32 phase/distance rounding);
+  excitation, far field: 1e-12 relative;
+  solves: ||J - J_LU|| <= 10 tol kappa-bounded, iteration counts within +-2 of the oracle's
+  own Krylov on the same operator.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import efie as oefie
+from oracle import krylov as okrylov
+from oracle import rwg
+
+from .gpu_common import bipyramid, flush, icosphere, oracle_mesh, rel_max, tetrahedron
+
+torch = pytest.importorskip("torch")
+P = pytest.importorskip("paper_2310_15644_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    P.lib()
+    return torch.device("cuda:0")
+
+
+def gmesh(v, f, dev, nf=2.0):
+    return P.Mesh(v, f, near_factor=nf).upload(dev)
+
+
+# ------------------------------------------------------------ assembly
+@pytest.mark.parametrize("k", [1.0, 3.0])
+def test_assemble_c128_l2_full(dev, k):
+    flush(f"assemble c128 L2 k={k}")
+    v, f = icosphere(2)
+    Zg = P.assemble(gmesh(v, f, dev), k).cpu().numpy()
+    Zo = oefie.assemble(oracle_mesh(2), k)
+    assert rel_max(Zg, Zo) <= 1e-11
+    assert np.abs(Zg - Zg.T).max() <= 1e-14 * np.abs(Zg).max()
+
+
+@pytest.mark.parametrize("k", [1.0 - 0.4j, 5.0 - 0.68399j])
+def test_assemble_parts_complex_k(dev, k):
+    flush(f"assemble parts L1 k={k}")
+    v, f = icosphere(1)
+    TA, TP = P.assemble(gmesh(v, f, dev), k, parts=True)
+    _, TAo, TPo = oefie.assemble(oracle_mesh(1), k, parts=True)
+    assert rel_max(TA.cpu().numpy(), TAo) <= 1e-11
+    assert rel_max(TP.cpu().numpy(), TPo) <= 1e-11
+
+
+def test_assemble_complex_k_z(dev):
+    k = P.ktilde(3.0)
+    v, f = icosphere(2)
+    Zg = P.assemble(gmesh(v, f, dev), k).cpu().numpy()
+    Zo = oefie.assemble(oracle_mesh(2), k)
+    assert rel_max(Zg, Zo) <= 1e-11
+
+
+def test_assemble_c64_l2(dev):
+    flush("assemble c64 L2")
+    v, f = icosphere(2)
+    Zg = P.assemble(gmesh(v, f, dev), 1.0, dtype=P.C64).cpu().numpy()
+    Zo = oefie.assemble(oracle_mesh(2), 1.0)
+    err = rel_max(Zg.astype(np.complex128), Zo)
+    flush(f"  c64 max rel err {err:.3e}")
+    assert err <= 2e-5
+
+
+@pytest.mark.parametrize("shape", ["tetrahedron", "bipyramid"])
+def test_assemble_tiny_meshes(dev, shape):
+    v, f = {"tetrahedron": tetrahedron, "bipyramid": bipyramid}[shape]()
+    om = rwg.build(v, f)
+    for k in (0.7, 2.0 - 0.3j):
+        Zg = P.assemble(gmesh(v, f, dev), k).cpu().numpy()
+        assert rel_max(Zg, oefie.assemble(om, k)) <= 1e-11
+
+
+@pytest.mark.parametrize("nf", [1.0, 3.0])
+def test_assemble_near_factor(dev, nf):
+    v, f = icosphere(1)
+    Zg = P.assemble(gmesh(v, f, dev, nf), 2.0).cpu().numpy()
+    assert rel_max(Zg, oefie.assemble(oracle_mesh(1), 2.0, near_factor=nf)) <= 1e-11
+
+
+@pytest.mark.parametrize("k", [0.1, 5.0])
+def test_assemble_l4_sampled_rows(dev, k):
+    flush(f"assemble L4 k={k} sampled rows")
+    v, f = icosphere(4)
+    Zg = P.assemble(gmesh(v, f, dev), k)
+    rows = [0, 3001, 7679]
+    got = Zg[rows].cpu().numpy()
+    ref = oefie.z_rows(oracle_mesh(4), k, rows)
+    for r in range(len(rows)):
+        assert rel_max(got[r], ref[r]) <= 1e-11
+    # symmetry at full size, sampled block
+    blk = Zg[:512, :512].cpu().numpy()
+    assert np.abs(blk - blk.T).max() <= 1e-14 * np.abs(blk).max()
+
+
+# ------------------------------------------------------- excitation / far field
+def test_excitation_l2(dev):
+    v, f = icosphere(2)
+    m = gmesh(v, f, dev)
+    rhat, khat, pol, _, _ = synth.monostatic_grid(2, 3)
+    Vg = P.excite_planewave(m, 2.5, khat, pol).cpu().numpy()
+    Vo = oefie.excitation(oracle_mesh(2), 2.5, khat, pol)
+    assert rel_max(Vg, Vo) <= 1e-12
+
+
+def test_farfield_l2(dev):
+    v, f = icosphere(2)
+    m = gmesh(v, f, dev)
+    om = oracle_mesh(2)
+    rng = np.random.default_rng(3)
+    J = rng.standard_normal((3, m.n)) + 1j * rng.standard_normal((3, m.n))
+    dirs = synth.uniform_directions(17, seed=4)
+    dirs = np.concatenate([dirs, [[0, 0, 1.0], [0, 0, -1.0]]])       # poles
+    Fg = P.farfield(m, 1.5, torch.as_tensor(J, device=dev), dirs).cpu().numpy()
+    Fo = oefie.farfield(om, 1.5, J, dirs)
+    assert rel_max(Fg, Fo) <= 1e-12
+
+
+# ------------------------------------------------------------- products
+@pytest.mark.parametrize("n,nrhs", [(481, 1), (481, 3), (480, 64), (257, 130), (9, 2)])
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_zx_random(dev, n, nrhs, dt):
+    rng = np.random.default_rng(n + nrhs)
+    Z = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    X = rng.standard_normal((nrhs, n)) + 1j * rng.standard_normal((nrhs, n))
+    tdt = torch.complex128 if dt == "c128" else torch.complex64
+    Zt = torch.as_tensor(Z, dtype=tdt, device=dev)
+    Xt = torch.as_tensor(X, dtype=tdt, device=dev)
+    Y = P.zx(Zt, Xt).cpu().numpy().astype(np.complex128)
+    # reference from the values actually stored (rounded to the storage type)
+    Zr = Zt.cpu().numpy().astype(np.complex128)
+    Xr = Xt.cpu().numpy().astype(np.complex128)
+    ref = Xr @ Zr.T
+    err = np.linalg.norm(Y - ref) / np.linalg.norm(ref)
+    tol = 1e-14 if dt == "c128" else (1e-7 if nrhs == 1 else 2e-6)   # GEMV accumulates in FP64
+    assert err <= tol, err
+
+
+# ---------------------------------------------------------------- solves
+@pytest.fixture(scope="module")
+def l2_system(dev):
+    v, f = icosphere(2)
+    m = gmesh(v, f, dev)
+    om = oracle_mesh(2)
+    k = 1.0
+    Zo = oefie.assemble(om, k)
+    kh, pol = synth.planewave_x_along_minus_z()
+    Vo = oefie.excitation(om, k, kh, pol)
+    Jo = np.linalg.solve(Zo, Vo[0])
+    return m, k, Zo, Vo, Jo
+
+
+@pytest.mark.parametrize("solver", ["cocg", "cgs"])
+def test_solve_l2_vs_lu(dev, l2_system, solver):
+    m, k, Zo, Vo, Jo = l2_system
+    Zg = P.assemble(m, k)
+    Vg = P.excite_planewave(m, k, *synth.planewave_x_along_minus_z())
+    code = P.COCG if solver == "cocg" else P.CGS
+    J, st = P.solve(Zg, Vg, solver=code, tol=1e-8, maxit=2000)
+    assert st.code == 0 and st.status[0] == 0
+    assert st.relres_true[0] <= 2e-8
+    Jg = J.cpu().numpy()[0]
+    assert np.linalg.norm(Jg - Jo) <= 1e-5 * np.linalg.norm(Jo)
+    # iteration count against the oracle's own Krylov on the oracle operator
+    ref = (okrylov.cocg if solver == "cocg" else okrylov.cgs)(lambda x: Zo @ x, Vo[0], 1e-8, 2000)
+    assert abs(int(st.iters[0]) - ref[1]) <= 2
+
+
+def test_solve_multi_rhs_equals_single(dev, l2_system):
+    m, k, Zo, Vo, Jo = l2_system
+    Zg = P.assemble(m, k)
+    rhat, khat, pol, _, _ = synth.monostatic_grid(1, 5)
+    V = P.excite_planewave(m, k, khat, pol)
+    J, st = P.solve(Zg, V, tol=1e-10, maxit=2000)
+    assert np.all(st.status == 0)
+    Vo5 = oefie.excitation(oracle_mesh(2), k, khat, pol)
+    Jlu = np.linalg.solve(Zo, Vo5.T).T
+    for s in range(5):
+        J1, st1 = P.solve(Zg, V[s:s + 1].contiguous(), tol=1e-10, maxit=2000)
+        assert int(st1.iters[0]) == int(st.iters[s])
+        # GEMM (several columns) and GEMV (one column) sum in different orders
+        assert np.abs(J1.cpu().numpy()[0] - J.cpu().numpy()[s]).max() <= 1e-10 * np.abs(Jlu[s]).max()
+        assert np.linalg.norm(J.cpu().numpy()[s] - Jlu[s]) <= 1e-7 * np.linalg.norm(Jlu[s])
+
+
+@pytest.mark.parametrize("nrhs", [1, 4])
+def test_solve_mixed_l2(dev, l2_system, nrhs):
+    m, k, Zo, Vo, Jo = l2_system
+    Z32 = P.assemble(m, k, dtype=P.C64)
+    rhat, khat, pol, _, _ = synth.monostatic_grid(1, nrhs)
+    V = P.excite_planewave(m, k, khat, pol)
+    J, st = P.solve(Z32, V, tol=1e-8, maxit=2000, max_refine=6, inner_tol=1e-3)
+    assert np.all(st.status == 0), st
+    assert np.all(st.relres_true <= 1e-8)
+    Vo_ = oefie.excitation(oracle_mesh(2), k, khat, pol)
+    Jlu = np.linalg.solve(Zo, Vo_.T).T
+    err = np.linalg.norm(J.cpu().numpy() - Jlu) / np.linalg.norm(Jlu)
+    flush(f"  mixed L2 current error vs FP64 LU: {err:.3e}")
+    assert err <= 1e-4
+
+
+def test_solve_tiny_odd_order(dev):
+    v, f = bipyramid()
+    m = gmesh(v, f, dev)
+    om = rwg.build(v, f)
+    Zo = oefie.assemble(om, 1.3)
+    Vo = oefie.excitation(om, 1.3, *synth.planewave_x_along_minus_z())
+    for dt in (P.C128, P.C64):
+        Z = P.assemble(m, 1.3, dtype=dt)
+        V = P.excite_planewave(m, 1.3, *synth.planewave_x_along_minus_z())
+        J, st = P.solve(Z, V, tol=1e-10, maxit=200, max_refine=8)
+        assert st.status[0] == 0
+        Jlu = np.linalg.solve(Zo, Vo[0])
+        tol = 1e-8 if dt == P.C128 else 1e-4
+        assert np.linalg.norm(J.cpu().numpy()[0] - Jlu) <= tol * np.linalg.norm(Jlu)
+
+
+def test_solve_zero_rhs_and_maxit(dev, l2_system):
+    m, k, Zo, Vo, Jo = l2_system
+    Zg = P.assemble(m, k)
+    V = torch.zeros((2, m.n), dtype=torch.complex128, device=dev)
+    V[1] = P.excite_planewave(m, k, *synth.planewave_x_along_minus_z())[0]
+    J, st = P.solve(Zg, V, tol=1e-8, maxit=3)
+    assert st.status[0] == 0 and st.iters[0] == 0 and float(J[0].abs().max()) == 0.0
+    assert st.status[1] == 1 and st.code == 1 and st.iters[1] == 3
+
+
+# ------------------------------------------------ end to end vs oracle and Mie
+def test_end_to_end_l2_rcs(dev, l2_system):
+    from oracle import mie
+
+    m, k, Zo, Vo, Jo = l2_system
+    Z = P.assemble(m, k)
+    V = P.excite_planewave(m, k, *synth.planewave_x_along_minus_z())
+    J, st = P.solve(Z, V, tol=1e-10, maxit=2000)
+    ts = np.linspace(0, math.pi, 181)
+    for phi in (0.0, math.pi / 2):
+        d = np.stack([np.sin(ts) * math.cos(phi), np.sin(ts) * math.sin(phi), -np.cos(ts)], 1)
+        F = P.farfield(m, k, J, d).cpu().numpy()
+        Fo = oefie.farfield(oracle_mesh(2), k, Jo[None], d)
+        s_g = oefie.rcs(F)[0]
+        s_o = oefie.rcs(Fo)[0]
+        assert np.max(np.abs(10 * np.log10(s_g / s_o))) <= 1e-6
+        s_m = mie.bistatic_rcs(1.0, 1.0, ts, phi)
+        assert np.max(np.abs(10 * np.log10(s_g / s_m))) <= 0.5     # L2 discretisation vs Mie
