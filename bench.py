@@ -1,0 +1,254 @@
+#!/usr/bin/env python
+"""Benchmark of the EFIE hot path on one MI355X.
+
+Workload (default): PEC unit sphere, icosphere level 5 (T = 20480 triangles,
+N = 30720 RWG unknowns), k = 10 rad/m, 512 plane waves on the uniform
+16 (theta) x 32 (phi) grid, incidence from rhat with theta-hat polarisation,
+monostatic observation.  Mixed precision: complex64 operator (far pairs in
+FP32, near pairs in FP64), COCG with Z X on FP32 matrix cores, FP64 outer
+refinement to ||V - Z J|| <= 1e-6 ||V|| per right-hand side.
+
+One step = the whole hot path on inputs already resident in HBM:
+assembly (far + near), excitation of the 512 right-hand sides, the multi-RHS
+solve, and the far field in the 512 monostatic directions.
+
+Printed JSON line: `value` is the complex Z.X throughput (8 M N K real flops per
+launch / mean launch time, HIP events around every launch inside the timed
+steps), plus assembly Mentries/s and the time-to-solve; `roofline` describes
+the dominant kernel (the matrix-core GEMM); `cpu_baseline` times the FP64
+oracle's own Z.X (numpy) on a bounded sample on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP32_MFMA = 157.3      # TFLOP/s, MI355X dense FP32 matrix
+PEAK_HBM = 8000.0           # GB/s
+PEAK_FP32_VALU = 78.6       # TFLOP/s with FMA = 2 flops, packed FP32 disabled (256 CU x 64 lanes x 2.4 GHz x 2)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(level, n_sample_rows, nrhs, k, seconds):
+    """FP64 oracle on the host: its Z.X product (numpy) on a row sample of the same
+    shape, and its assembly on a few rows of the same mesh."""
+    import numpy as np
+
+    try:
+        from threadpoolctl import threadpool_info
+
+        threads = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    import synth
+    from oracle import efie, rwg
+
+    v, f = synth.icosphere(level)
+    om = rwg.build(v, f)
+    N = om.n
+    rng = np.random.default_rng(0)
+    rows = n_sample_rows
+    Zs = rng.standard_normal((rows, N)) + 1j * rng.standard_normal((rows, N))
+    X = rng.standard_normal((N, nrhs)) + 1j * rng.standard_normal((N, nrhs))
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        Y = Zs @ X                       # the oracle's product (numpy/BLAS, complex128)
+        reps += 1
+        if time.perf_counter() - t0 > seconds * 0.6:
+            break
+    tz = (time.perf_counter() - t0) / reps
+    gflops = 8.0 * rows * N * nrhs / tz / 1e9
+    geo = efie.Geometry(om)
+    t1 = time.perf_counter()
+    nrow = 0
+    while True:
+        efie.z_rows(om, k, [nrow * 997 % N], geo=geo)
+        nrow += 1
+        if time.perf_counter() - t1 > seconds * 0.4:
+            break
+    ta = time.perf_counter() - t1
+    return {
+        "value": round(gflops, 3),
+        "unit": "GFLOP/s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": (f"oracle Z.X (numpy complex128) of a {rows} x {N} row block of Z times {N} x {nrhs}, "
+                   f"{reps} repetitions; oracle assembly of {nrow} rows of the level-{level} Z at k={k}: "
+                   f"{nrow * N / ta / 1e6:.4f} Mentries/s on 1 core"),
+        "assembly_mentries_per_s": round(nrow * N / ta / 1e6, 5),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--level", type=int, default=5)
+    ap.add_argument("--k", type=float, default=10.0)
+    ap.add_argument("--ntheta", type=int, default=16)
+    ap.add_argument("--nphi", type=int, default=32)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--maxit", type=int, default=3000)
+    ap.add_argument("--dtype", choices=["c64", "c128"], default="c64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the sharded path is a design, "
+              "not built; see the multi-GPU section of DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2310_15644_amd as P
+    import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    v, f = synth.icosphere(args.level)
+    m = P.Mesh(v, f).upload(dev)
+    N = m.n
+    rhat, khat, pol, _, _ = synth.monostatic_grid(args.ntheta, args.nphi)
+    S = len(khat)
+    dt = P.C64 if args.dtype == "c64" else P.C128
+    tdt = torch.complex64 if dt == P.C64 else torch.complex128
+    log(f"bench: level {args.level} N={N} T={m.t} near={m.n_near} k={args.k} nrhs={S} dtype={args.dtype}")
+    # inputs resident in HBM before the timed region
+    kh_d = torch.as_tensor(khat, dtype=torch.float64, device=dev).contiguous()
+    po_d = torch.as_tensor(pol, dtype=torch.float64, device=dev).contiguous()
+    rh_d = torch.as_tensor(rhat, dtype=torch.float64, device=dev).contiguous()
+    Z = torch.empty((N, N), dtype=tdt, device=dev)
+    V = torch.empty((S, N), dtype=torch.complex128, device=dev)
+    J = torch.empty((S, N), dtype=torch.complex128, device=dev)
+    tuning = None
+    if dt == P.C64:
+        P.assemble(m, args.k, dtype=dt, out=Z)
+        tuning = P.gemm_autotune(Z, S, reps=2)
+        log(f"bench: GEMM tiles {tuning}")
+
+    def sync():
+        torch.cuda.synchronize()
+
+    def step(rec):
+        t0 = time.perf_counter()
+        P.assemble(m, args.k, dtype=dt, out=Z)
+        P.excite_planewave(m, args.k, kh_d, po_d, out=V)
+        _, st = P.solve(Z, V, solver=P.COCG, tol=args.tol, maxit=args.maxit, max_refine=6, inner_tol=1e-3, out=J)
+        sync()
+        t1 = time.perf_counter()
+        F = P.farfield(m, args.k, J, rh_d)
+        sync()
+        t2 = time.perf_counter()
+        rec.append({"solve_s": t1 - t0, "step_s": t2 - t0, "iters": st.iters, "relres": st.relres_true,
+                    "status": st.status, "F": F})
+
+    warm = []
+    for i in range(args.warmup):
+        log(f"bench: warmup step {i + 1}/{args.warmup}")
+        step(warm)
+    P.prof_reset()
+    P.prof_enable(True)
+    rec = []
+    sync()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        log(f"bench: timed step {i + 1}/{args.steps}")
+        step(rec)
+    sync()
+    wall = time.perf_counter() - t0
+    prof = P.prof_read(with_work=True)
+    P.prof_enable(False)
+
+    ms_step = 1e3 * wall / args.steps
+    gemm_key = "mfma" if dt == P.C64 else "zgemm"
+    n_mm, ms_mm, fl_mm = prof[gemm_key]
+    # Z.X launches inside the solve run over the active (unconverged) columns only:
+    # the algorithmic flops 8 M N N are summed per launch with its own M.
+    avg_mm = ms_mm / max(n_mm, 1)
+    flops = fl_mm / max(n_mm, 1)                 # mean algorithmic flops per launch
+    zx_gflops = fl_mm / (ms_mm * 1e-3) / 1e9 if n_mm else float("nan")
+    n_far, ms_far, _ = prof["far"]
+    n_near, ms_near, _ = prof["near"]
+    asm_ms = (ms_far + ms_near) / args.steps
+    mentries = N * N / (asm_ms * 1e-3) / 1e6
+    last = rec[-1]
+    F = last["F"]
+    # reciprocity of the bistatic matrix S_ij = theta_j . F_i(rhat_j)
+    Sm = F[:, :, 0].cpu().numpy()
+    recip = float(np.abs(Sm - Sm.T).max() / np.abs(Sm).max())
+    tts = float(np.mean([r["solve_s"] for r in rec]))
+    out = {
+        "metric": "Z·X complex GFLOP/s + assembly Mentries/s; time-to-solve @ rel.res 1e-6",
+        "value": round(zx_gflops, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64" if dt == P.C64 else "c128",
+        "data": "synthetic",
+        "config": {
+            "workload": f"PEC unit sphere icosphere level {args.level} (N={N} RWG), k={args.k}, "
+                        f"{S} plane waves on a {args.ntheta}x{args.nphi} (theta,phi) grid, monostatic; "
+                        f"{'mixed precision (complex64 Z, FP32 MFMA, FP64 refinement)' if dt == P.C64 else 'FP64'}",
+            "n_unknowns": N,
+            "nrhs": S,
+            "k": args.k,
+            "tol": args.tol,
+        },
+        "zx_gflops": round(zx_gflops, 2),
+        "zx_launches": n_mm,
+        "zx_ms_per_launch": round(avg_mm, 4),
+        "assembly_mentries_per_s": round(mentries, 1),
+        "assembly_ms": round(asm_ms, 3),
+        "time_to_solve_s": round(tts, 3),
+        "iters_max": int(np.max(last["iters"])),
+        "iters_mean": round(float(np.mean(last["iters"])), 1),
+        "relres_true_max": float(np.max(last["relres"])),
+        "all_converged": bool(np.all(last["status"] == 0)),
+        "reciprocity_rel": recip,
+        "roofline": {
+            "bound": "mfma",
+            "achieved": round(flops / (avg_mm * 1e-3) / 1e12, 3),
+            "peak": PEAK_FP32_MFMA if dt == P.C64 else 78.6,
+            "unit": "TFLOP/s",
+            "frac": round(flops / (avg_mm * 1e-3) / 1e12 / (PEAK_FP32_MFMA if dt == P.C64 else 78.6), 4),
+            "traffic": None,
+        },
+        "assembly_roofline": {
+            "bound": "alu",
+            "kernel": "far_pairs_kernel",
+            "achieved_mentries_per_s": round(mentries, 1),
+            "hbm_gbs": round(N * N * (8 if dt == P.C64 else 16) / (asm_ms * 1e-3) / 1e9, 1),
+            "hbm_frac": round(N * N * (8 if dt == P.C64 else 16) / (asm_ms * 1e-3) / 1e9 / PEAK_HBM, 4),
+        },
+        "kernel_ms": {kname: [n, round(ms, 3)] for kname, (n, ms, _) in prof.items()},
+        "gemm_tiles": None if tuning is None else {"acc32": tuning["tiles"][tuning["acc32"]],
+                                                   "acc64": tuning["tiles"][tuning["acc64"]], "ms": tuning["ms"]},
+    }
+    if not args.no_cpu_baseline:
+        log("bench: cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(args.level, 2048, S, args.k, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

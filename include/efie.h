@@ -160,6 +160,25 @@ int efie_farfield(efie_mesh mesh, double k, double eta, const void* J, int64_t n
 int efie_zx(const void* Z, int dtype, int64_t n, const void* X, void* Y, int64_t nrhs,
             hipStream_t stream);
 
+/* ------------------------------------------------------- GEMM autotuning */
+
+/*
+ * The complex64 matrix-core GEMM has several tile shapes (block tile of BM
+ * right-hand sides x BN real columns, K chunk KC), for two paths: complex64
+ * output (efie_zx) and FP64-flushed output into the Krylov vectors (solves).
+ * efie_gemm_autotune times every variant on the caller's Z (n x n complex64) and
+ * X (M x n complex64) with HIP events (reps launches each, after one warm-up),
+ * writes the mean milliseconds per launch into ms[variant] (host, count
+ * entries), returns the fastest in *best, and does not change the selection.
+ * ws: dev scratch of at least M*n*(acc64 ? 16 : 8) bytes rounded up to 256, plus
+ * 4*M bytes.  efie_gemm_select sets the variant used by later calls (process-wide).
+ */
+int efie_gemm_variants(int* count);
+int efie_gemm_variant_info(int variant, int* bm, int* bn, int* kc);
+int efie_gemm_autotune(const void* Z, int64_t n, const void* X, int64_t M, int acc64, void* ws,
+                       size_t ws_bytes, int reps, double* ms, int* best, hipStream_t stream);
+int efie_gemm_select(int acc64, int variant, int* previous);
+
 /* ------------------------------------------------------------------ solve */
 
 typedef struct {
@@ -184,17 +203,39 @@ typedef struct {
  *   Z dev (dtype as assembled), V dev (nrhs, N) complex128, J dev (nrhs, N)
  *   complex128 (output).  FP64 vectors and inner products in both cases.
  *   EFIE_C128: one Krylov solve with FP64 products.
- *   EFIE_C64 : mixed precision -- inner Krylov solves whose Z X products run on
- *              FP32 matrix cores, wrapped in an outer refinement loop whose
- *              residual V - Z J is accumulated in FP64 from the stored complex64 Z.
+ *   EFIE_C64 : mixed precision -- Z X products of more than 8 active columns run
+ *              on FP32 matrix cores with FP64 accumulation of 16-element partial
+ *              sums; COCG replaces its recursive residual by the true residual
+ *              V - Z J (FP64 accumulation from the stored complex64 Z) whenever it
+ *              has dropped tenfold (reliable updates) and converges only on it;
+ *              CGS runs inner solves to inner_tol inside an outer refinement loop
+ *              (max_refine steps) on the same true residual.
  *   stats host, nrhs entries (may be NULL).
  *   ws dev workspace of efie_solve_workspace_size bytes.
- * Returns EFIE_NOT_CONVERGED if any right-hand side missed tol.  Synchronises.
+ * Returns EFIE_NOT_CONVERGED if any right-hand side missed tol or broke down
+ * (per-column EFIE_ERR_BREAKDOWN / EFIE_ERR_NAN in stats[s].status); negative
+ * return codes are reserved for argument and HIP errors.  Synchronises.
  */
 int efie_solve_workspace_size(int64_t n, int64_t nrhs, int dtype, size_t* bytes);
 int efie_solve(const void* Z, int dtype, int64_t n, const void* V, void* J, int64_t nrhs,
                const efie_solve_opts* opts, efie_rhs_stats* stats, void* ws, size_t ws_bytes,
                hipStream_t stream);
+
+/* ------------------------------------------------------------ measurement */
+
+/*
+ * Optional HIP-event timing of the library's kernels (off by default).  While
+ * enabled, every launch of the timed kernels is bracketed by two events on its
+ * stream.  Kernel ids: 0 far-pair assembly, 1 near-pair assembly, 2 complex64
+ * matrix-core GEMM, 3 GEMV, 4 FP64 GEMM, 5 Krylov vector kernels, 6 excitation,
+ * 7 far field.  efie_prof_read waits for the recorded events and returns the
+ * launch count, summed milliseconds and summed algorithmic work (real flops for
+ * the GEMMs, 8 M n n per complex product; Z bytes read for the GEMVs; 0 where
+ * not defined) since the last efie_prof_reset.  total_work may be NULL.
+ */
+int efie_prof_enable(int on);
+int efie_prof_reset(void);
+int efie_prof_read(int kernel_id, int64_t* launches, double* total_ms, double* total_work);
 
 #ifdef __cplusplus
 }

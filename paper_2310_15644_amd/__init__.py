@@ -32,14 +32,17 @@ _STATUS = {
 }
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-library_path = os.path.join(HERE, "libefie.so")
+library_path = os.environ.get("EFIE_LIBRARY") or os.path.join(HERE, "libefie.so")
 
 # symbols declared in include/efie.h (checked by the CPU tests)
 EXPORTED = [
     "efie_abi_version", "efie_last_error", "efie_mesh_create", "efie_mesh_destroy", "efie_mesh_sizes",
     "efie_mesh_rwg_table", "efie_mesh_upload", "efie_assemble", "efie_excite_planewave",
     "efie_farfield_workspace_size", "efie_farfield", "efie_zx", "efie_solve_workspace_size", "efie_solve",
+    "efie_prof_enable", "efie_prof_reset", "efie_prof_read",
+    "efie_gemm_variants", "efie_gemm_variant_info", "efie_gemm_autotune", "efie_gemm_select",
 ]
+PROF_IDS = {"far": 0, "near": 1, "mfma": 2, "gemv": 3, "zgemm": 4, "krylov": 5, "excite": 6, "farfield": 7}
 
 
 class EfieError(RuntimeError):
@@ -87,6 +90,15 @@ def lib():
         "efie_solve_workspace_size": ([I64, I64, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "efie_solve": ([P, ctypes.c_int, I64, P, P, I64, ctypes.POINTER(_SolveOpts), ctypes.POINTER(_RhsStats),
                         P, ctypes.c_size_t, P], ctypes.c_int),
+        "efie_prof_enable": ([ctypes.c_int], ctypes.c_int),
+        "efie_prof_reset": ([], ctypes.c_int),
+        "efie_prof_read": ([ctypes.c_int, ctypes.POINTER(I64), ctypes.POINTER(D), ctypes.POINTER(D)], ctypes.c_int),
+        "efie_gemm_variants": ([ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+        "efie_gemm_variant_info": ([ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                    ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+        "efie_gemm_autotune": ([P, I64, P, I64, ctypes.c_int, P, ctypes.c_size_t, ctypes.c_int,
+                                ctypes.POINTER(D), ctypes.POINTER(ctypes.c_int), P], ctypes.c_int),
+        "efie_gemm_select": ([ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -209,12 +221,22 @@ def assemble(mesh: Mesh, k, eta: float = ETA0, dtype=C128, parts: bool = False, 
     return (Z, Z2) if parts else Z
 
 
+def _dev_vectors(a, dev):
+    """(n, 3) float64 device tensor from a numpy array or a torch tensor."""
+    torch = _torch()
+    if isinstance(a, torch.Tensor):
+        t = a.to(device=dev, dtype=torch.float64)
+    else:
+        t = torch.as_tensor(np.atleast_2d(np.asarray(a, dtype=np.float64)), device=dev)
+    return t.reshape(-1, 3).contiguous()
+
+
 def excite_planewave(mesh: Mesh, k: float, khat, pol, e0: float = 1.0, out=None):
     """V (nrhs, N) complex128 for plane waves E0 pol exp(-j k khat . r)."""
     torch = _torch()
     dev = mesh.device
-    kh = torch.as_tensor(np.atleast_2d(khat), dtype=torch.float64).to(dev).contiguous()
-    po = torch.as_tensor(np.atleast_2d(pol), dtype=torch.float64).to(dev).contiguous()
+    kh = _dev_vectors(khat, dev)
+    po = _dev_vectors(pol, dev)
     S = kh.shape[0]
     V = out if out is not None else torch.empty((S, mesh.n), dtype=torch.complex128, device=dev)
     _check(lib().efie_excite_planewave(mesh._h, float(k), _ptr(kh), _ptr(po), S, float(e0), _ptr(V), _stream(dev)))
@@ -227,7 +249,7 @@ def farfield(mesh: Mesh, k: float, J, dirs, eta: float = ETA0):
     dev = mesh.device
     J = J.reshape(-1, mesh.n)
     _require_cuda(J, "J")
-    d = torch.as_tensor(np.atleast_2d(dirs), dtype=torch.float64).to(dev).contiguous()
+    d = _dev_vectors(dirs, dev)
     nd = d.shape[0]
     nb = ctypes.c_size_t()
     _check(lib().efie_farfield_workspace_size(mesh._h, nd, ctypes.byref(nb)))
@@ -288,3 +310,97 @@ def solve(Z, V, solver=COCG, tol=1e-8, maxit=1000, max_refine=4, inner_tol=1e-3,
         code=code,
     )
     return J, stats
+
+
+def prof_enable(on: bool = True):
+    """Turn the library's HIP-event launch timing on or off."""
+    _check(lib().efie_prof_enable(int(on)))
+
+
+def prof_reset():
+    _check(lib().efie_prof_reset())
+
+
+def prof_read(with_work: bool = False):
+    """{kernel: (launches, total_ms[, total_work])} since the last prof_reset (waits for the events)."""
+    out = {}
+    for name, i in PROF_IDS.items():
+        n, ms, wk = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+        _check(lib().efie_prof_read(i, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(wk)))
+        out[name] = (n.value, ms.value, wk.value) if with_work else (n.value, ms.value)
+    return out
+
+
+# ------------------------------------------------------------- GEMM tile autotuner
+def gemm_variants():
+    """[(bm, bn, kc)] of the complex64 matrix-core GEMM tile variants."""
+    L = lib()
+    c = ctypes.c_int()
+    _check(L.efie_gemm_variants(ctypes.byref(c)))
+    out = []
+    for v in range(c.value):
+        bm, bn, kc = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(L.efie_gemm_variant_info(v, ctypes.byref(bm), ctypes.byref(bn), ctypes.byref(kc)))
+        out.append((bm.value, bn.value, kc.value))
+    return out
+
+
+def gemm_select(acc64: bool, variant: int) -> int:
+    prev = ctypes.c_int()
+    _check(lib().efie_gemm_select(int(acc64), int(variant), ctypes.byref(prev)))
+    return prev.value
+
+
+def default_tuning_cache():
+    return os.path.join(os.path.expanduser("~"), ".cache", "efie", "gemm_tiles.json")
+
+
+def gemm_autotune(Z, M: int, reps: int = 3, cache: str | None = None, force: bool = False):
+    """Pick the fastest matrix-core tile shape for Z (n x n complex64) times M
+    right-hand sides, for both GEMM paths, and select it.  Results are kept in a
+    JSON cache keyed by device name, n and M; a cached entry is reused unless force.
+    Returns {"acc32": variant, "acc64": variant, "ms": {...}, "tiles": [...]}."""
+    import json
+
+    torch = _torch()
+    if Z.dtype != torch.complex64:
+        raise ValueError("autotuning is for the complex64 matrix-core GEMM")
+    n = Z.shape[0]
+    cache = cache or default_tuning_cache()
+    key = f"{torch.cuda.get_device_name(Z.device)}|n={n}|M={M}"
+    db = {}
+    if os.path.exists(cache):
+        try:
+            db = json.load(open(cache))
+        except (OSError, ValueError):
+            db = {}
+    tiles = gemm_variants()
+    if key in db and not force and len(db[key].get("tiles", [])) == len(tiles):
+        ent = db[key]
+    else:
+        g = torch.Generator(device=Z.device).manual_seed(0)
+        X = torch.randn((M, n), dtype=torch.complex64, device=Z.device, generator=g)
+        ws_bytes = ((M * n * 16 + 255) // 256) * 256 + 4 * M
+        ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=Z.device)
+        off = (-ws.data_ptr()) % 256
+        ent = {"tiles": tiles, "ms": {}}
+        for acc64 in (0, 1):
+            ms = (ctypes.c_double * len(tiles))()
+            best = ctypes.c_int()
+            _check(lib().efie_gemm_autotune(_ptr(Z), n, _ptr(X), M, acc64, ctypes.c_void_p(ws.data_ptr() + off),
+                                            ws_bytes, int(reps), ms, ctypes.byref(best), _stream(Z.device)))
+            name = "acc64" if acc64 else "acc32"
+            ent[name] = best.value
+            ent["ms"][name] = [round(x, 4) for x in ms]
+        del X, ws
+        db[key] = ent
+        try:
+            os.makedirs(os.path.dirname(cache), exist_ok=True)
+            tmp = cache + ".tmp"
+            json.dump(db, open(tmp, "w"), indent=1)
+            os.replace(tmp, cache)
+        except OSError:
+            pass
+    gemm_select(False, ent["acc32"])
+    gemm_select(True, ent["acc64"])
+    return ent

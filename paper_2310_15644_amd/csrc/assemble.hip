@@ -391,19 +391,23 @@ void launch_far(const DevMesh& m, double kr, double ki, const Scale& sc, void* Z
     EFIE_REQUIRE(nblk < (size_t(1) << 31), EFIE_ERR_ARG, "assemble: mesh too large for one launch");
     const bool ck = ki != 0.0;
     const R kphase = std::is_same<R, float>::value ? R(kr / (2.0 * PI)) : R(kr);
+    prof_begin(PROF_FAR, s);
     if (ck)
         hipLaunchKernelGGL((far_pairs_kernel<R, true, PARTS>), dim3(unsigned(nblk)), dim3(FAR_BLOCK), 0, s, m,
                            tables<R>(m), kphase, R(ki), sc, Z, Z2, nqblk);
     else
         hipLaunchKernelGGL((far_pairs_kernel<R, false, PARTS>), dim3(unsigned(nblk)), dim3(FAR_BLOCK), 0, s, m,
                            tables<R>(m), kphase, R(ki), sc, Z, Z2, nqblk);
+    prof_end(PROF_FAR, s);
 }
 
 template <typename ZT, bool PARTS>
 void launch_near(const DevMesh& m, double kr, double ki, const Scale& sc, void* Z, void* Z2, hipStream_t s) {
     if (m.n_near == 0) return;
+    prof_begin(PROF_NEAR, s);
     hipLaunchKernelGGL((near_pairs_kernel<ZT, PARTS>), dim3((m.n_near + 127) / 128), dim3(128), 0, s, m, kr, ki,
                        sc, Z, Z2);
+    prof_end(PROF_NEAR, s);
 }
 
 }  // namespace

@@ -106,3 +106,14 @@ void build_mesh(efie_mesh_s& m, const double* xyz, int64_t nv, const int32_t* tr
 void pack_tables(efie_mesh_s& m);            // fills host_blob, offs, returns size via host_blob.size()
 void bind_tables(efie_mesh_s& m, void* dev); // sets m.dm pointers into dev
 }  // namespace efie
+
+namespace efie {
+// ------------------------------------------------------- launch timing
+// Optional HIP-event timing of the library's main kernels, for measurement
+// (enabled through efie_prof_enable).  Each begin/end pair brackets one launch
+// on the launch stream.
+enum ProfId { PROF_FAR = 0, PROF_NEAR = 1, PROF_MFMA = 2, PROF_GEMV = 3, PROF_ZGEMM = 4, PROF_KRYLOV = 5,
+              PROF_EXCITE = 6, PROF_FARFIELD = 7, PROF_COUNT = 8 };
+void prof_begin(int id, hipStream_t s);
+void prof_end(int id, hipStream_t s, double work = 0.0);   // work: algorithmic flops or bytes of the launch
+}  // namespace efie

@@ -95,8 +95,10 @@ extern "C" int efie_excite_planewave(efie_mesh mesh, double k, const double* kha
         EFIE_REQUIRE(mesh->dev != nullptr, EFIE_ERR_STATE, "excite: mesh tables not uploaded");
         EFIE_REQUIRE(nrhs >= 1 && nrhs * mesh->N < (int64_t(1) << 31), EFIE_ERR_ARG, "excite: bad nrhs");
         const int tot = int(nrhs * mesh->N);
+        efie::prof_begin(efie::PROF_EXCITE, stream);
         hipLaunchKernelGGL(efie::excite_kernel, dim3((tot + 255) / 256), dim3(256), 0, stream, mesh->dm, k, khat, pol,
                            int(nrhs), e0, static_cast<double2*>(V));
+        efie::prof_end(efie::PROF_EXCITE, stream);
         EFIE_HIP_CHECK(hipGetLastError());
         return int(EFIE_OK);
     });
@@ -120,8 +122,10 @@ extern "C" int efie_farfield(efie_mesh mesh, double k, double eta, const void* J
         EFIE_REQUIRE(ws_bytes >= size_t(2 * ndir) * size_t(mesh->N) * 16, EFIE_ERR_ARG, "farfield: workspace too small");
         const int N = int(mesh->N);
         const int tot = int(ndir) * N;
+        efie::prof_begin(efie::PROF_FARFIELD, stream);
         hipLaunchKernelGGL(efie::radiation_kernel, dim3((tot + 255) / 256), dim3(256), 0, stream, mesh->dm, k, eta,
                            dirs, int(ndir), static_cast<double2*>(ws));
+        efie::prof_end(efie::PROF_FARFIELD, stream);
         // F[s][e] = sum_n J[s][n] R[e][n]
         efie::zgemm_nt(J, EFIE_C128, ws, EFIE_C128, F, EFIE_C128, int(nrhs), int(2 * ndir), N, N, N, int(2 * ndir),
                        1.0, 0.0, false, stream);

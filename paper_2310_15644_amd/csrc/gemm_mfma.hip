@@ -25,9 +25,15 @@ namespace efie {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-template <int BM, int BN, int KC>
+// ACC64: the FP32 matrix-core partial sums are flushed into FP64 accumulators after
+// every FLUSH complex elements of K, and the result is written as complex128 to
+// the rows Y[yrow[r]] (the Krylov vectors); this bounds the FP32 accumulation
+// error to short partial sums.  Otherwise complex64 is written to Y[r].
+template <int BM, int BN, int KC, bool ACC64>
 __global__ __launch_bounds__(256) void cgemm_mfma_kernel(const float2* __restrict__ X, const float2* __restrict__ Z,
-                                                         float2* __restrict__ Y, int M, int n) {
+                                                         void* __restrict__ Yv, int M, int n,
+                                                         const int* __restrict__ yrow) {
+    constexpr int FLUSH = 1;           // chunks of KC between FP64 flushes (1: every chunk; cheapest and most accurate)
     constexpr int AP = 2 * KC + 4;     // floats per LDS row of the X tile (padded)
     constexpr int BNC = BN / 2;        // unknowns per tile
     constexpr int BP = KC + 1;         // float2 per LDS row of the Z tile (padded)
@@ -46,10 +52,20 @@ __global__ __launch_bounds__(256) void cgemm_mfma_kernel(const float2* __restric
     const int s0 = bm * BM, i0 = bn * BNC;
 
     floatx4 acc[TM][TN];
+    double acc64[ACC64 ? TM : 1][ACC64 ? TN : 1][4];
 #pragma unroll
     for (int a = 0; a < TM; ++a)
 #pragma unroll
         for (int b = 0; b < TN; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+    if (ACC64) {
+#pragma unroll
+        for (int a = 0; a < (ACC64 ? TM : 1); ++a)
+#pragma unroll
+            for (int b = 0; b < (ACC64 ? TN : 1); ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc64[a][b][r] = 0.0;
+    }
+    int chunk = 0;
 
     const int kq = lane >> 4;          // 0..3: real k within an instruction
     const int l16 = lane & 15;
@@ -89,8 +105,18 @@ __global__ __launch_bounds__(256) void cgemm_mfma_kernel(const float2* __restric
                     acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
         }
         __syncthreads();
+        if (ACC64 && (++chunk == FLUSH || j0 + KC >= n)) {
+            chunk = 0;
+#pragma unroll
+            for (int a = 0; a < (ACC64 ? TM : 1); ++a)
+#pragma unroll
+                for (int b = 0; b < (ACC64 ? TN : 1); ++b) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc64[a][b][r] += double(acc[a][b][r]);
+                    acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+                }
+        }
     }
-    float* Yf = reinterpret_cast<float*>(Y);
 #pragma unroll
     for (int a = 0; a < TM; ++a)
 #pragma unroll
@@ -99,20 +125,67 @@ __global__ __launch_bounds__(256) void cgemm_mfma_kernel(const float2* __restric
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = s0 + wm * WM + a * 16 + 4 * kq + r;
-                if (row < M && col < 2 * n) Yf[size_t(row) * 2 * n + col] = acc[a][b][r];
+                if (row < M && col < 2 * n) {
+                    if (ACC64)
+                        reinterpret_cast<double*>(Yv)[size_t(yrow[row]) * 2 * n + col] =
+                            acc64[ACC64 ? a : 0][ACC64 ? b : 0][r];
+                    else
+                        reinterpret_cast<float*>(Yv)[size_t(row) * 2 * n + col] = acc[a][b][r];
+                }
             }
         }
 }
 
 bool cgemm_mfma_supported(int M, int n) { return M >= 1 && n >= 1; }
 
-void cgemm_mfma(const void* X, const void* Z, void* Y, int M, int n, hipStream_t s) {
-    constexpr int BM = 128, BN = 128, KC = 16;
+// ------------------------------------------------------------ tile variants
+// Block tile BM (right-hand sides) x BN (real columns = BN/2 unknowns), K chunk KC.
+// The FP64-flush path needs 3x the accumulator registers, so smaller wavefront
+// tiles win there; efie_gemm_autotune measures and selects per path.
+struct Variant {
+    int bm, bn, kc;
+};
+static const Variant kVariants[] = {{128, 128, 16}, {128, 64, 16}, {64, 128, 16}, {64, 64, 16}, {256, 64, 16},
+                                    {128, 128, 32}};
+static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+static int g_variant[2] = {0, 1};   // defaults: complex64 output, FP64-flush output
+
+template <int BM, int BN, int KC, bool A64>
+static void launch_v(const void* X, const void* Z, void* Y, const int* yrow, int M, int n, hipStream_t s) {
     const int nbm = (M + BM - 1) / BM, nbn = (n + BN / 2 - 1) / (BN / 2);
     const size_t nblk = size_t(nbm) * nbn;
     EFIE_REQUIRE(nblk < (size_t(1) << 31), EFIE_ERR_ARG, "cgemm: problem too large");
-    hipLaunchKernelGGL((cgemm_mfma_kernel<BM, BN, KC>), dim3(unsigned(nblk)), dim3(256), 0, s,
-                       static_cast<const float2*>(X), static_cast<const float2*>(Z), static_cast<float2*>(Y), M, n);
+    hipLaunchKernelGGL((cgemm_mfma_kernel<BM, BN, KC, A64>), dim3(unsigned(nblk)), dim3(256), 0, s,
+                       static_cast<const float2*>(X), static_cast<const float2*>(Z), Y, M, n, yrow);
+}
+
+template <bool A64>
+static void launch_variant(int v, const void* X, const void* Z, void* Y, const int* yrow, int M, int n,
+                           hipStream_t s) {
+    switch (v) {
+        case 0: launch_v<128, 128, 16, A64>(X, Z, Y, yrow, M, n, s); break;
+        case 1: launch_v<128, 64, 16, A64>(X, Z, Y, yrow, M, n, s); break;
+        case 2: launch_v<64, 128, 16, A64>(X, Z, Y, yrow, M, n, s); break;
+        case 3: launch_v<64, 64, 16, A64>(X, Z, Y, yrow, M, n, s); break;
+        case 4: launch_v<256, 64, 16, A64>(X, Z, Y, yrow, M, n, s); break;
+        default: launch_v<128, 128, 32, A64>(X, Z, Y, yrow, M, n, s); break;
+    }
+}
+
+void cgemm_mfma(const void* X, const void* Z, void* Y, int M, int n, hipStream_t s) {
+    prof_begin(PROF_MFMA, s);
+    launch_variant<false>(g_variant[0], X, Z, Y, nullptr, M, n, s);
+    prof_end(PROF_MFMA, s, 8.0 * M * double(n) * n);
+}
+
+void cgemm_mfma_acc64(const void* X, const void* Z, double2* Y, const int* yrow, int M, int n, hipStream_t s) {
+    prof_begin(PROF_MFMA, s);
+    launch_variant<true>(g_variant[1], X, Z, Y, yrow, M, n, s);
+    prof_end(PROF_MFMA, s, 8.0 * M * double(n) * n);
+}
+
+__global__ void iota_rows_kernel(int* idx, int M) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < M; i += gridDim.x * blockDim.x) idx[i] = i;
 }
 
 void zx_product(const void* Z, int zdt, int n, const void* X, int xdt, void* Y, int nrhs, hipStream_t s) {
@@ -126,6 +199,77 @@ void zx_product(const void* Z, int zdt, int n, const void* X, int xdt, void* Y, 
 }
 
 }  // namespace efie
+
+extern "C" int efie_gemm_variants(int* count) {
+    return efie::guarded([&]() {
+        EFIE_REQUIRE(count != nullptr, EFIE_ERR_ARG, "gemm_variants: null");
+        *count = efie::kNumVariants;
+        return int(EFIE_OK);
+    });
+}
+
+extern "C" int efie_gemm_variant_info(int v, int* bm, int* bn, int* kc) {
+    return efie::guarded([&]() {
+        EFIE_REQUIRE(v >= 0 && v < efie::kNumVariants && bm && bn && kc, EFIE_ERR_ARG, "gemm_variant_info: bad argument");
+        *bm = efie::kVariants[v].bm;
+        *bn = efie::kVariants[v].bn;
+        *kc = efie::kVariants[v].kc;
+        return int(EFIE_OK);
+    });
+}
+
+extern "C" int efie_gemm_select(int acc64, int variant, int* previous) {
+    return efie::guarded([&]() {
+        EFIE_REQUIRE((acc64 == 0 || acc64 == 1) && variant >= 0 && variant < efie::kNumVariants, EFIE_ERR_ARG,
+                     "gemm_select: bad argument");
+        if (previous) *previous = efie::g_variant[acc64];
+        efie::g_variant[acc64] = variant;
+        return int(EFIE_OK);
+    });
+}
+
+extern "C" int efie_gemm_autotune(const void* Z, int64_t n, const void* X, int64_t M, int acc64, void* ws,
+                                  size_t ws_bytes, int reps, double* ms, int* best, hipStream_t stream) {
+    return efie::guarded([&]() {
+        EFIE_REQUIRE(Z && X && ws && ms && best && reps >= 1, EFIE_ERR_ARG, "gemm_autotune: bad argument");
+        EFIE_REQUIRE(n >= 1 && n < (int64_t(1) << 31) && M >= 1 && M < 65536, EFIE_ERR_ARG, "gemm_autotune: bad sizes");
+        const size_t ybytes = size_t(M) * size_t(n) * (acc64 ? 16 : 8);
+        const size_t need = ((ybytes + 255) & ~size_t(255)) + size_t(M) * sizeof(int);
+        EFIE_REQUIRE(ws_bytes >= need, EFIE_ERR_ARG, "gemm_autotune: workspace too small");
+        void* Y = ws;
+        int* idx = reinterpret_cast<int*>(static_cast<char*>(ws) + ((ybytes + 255) & ~size_t(255)));
+        hipLaunchKernelGGL(efie::iota_rows_kernel, dim3(int((M + 255) / 256)), dim3(256), 0, stream, idx, int(M));
+        hipEvent_t e0, e1;
+        EFIE_HIP_CHECK(hipEventCreate(&e0));
+        EFIE_HIP_CHECK(hipEventCreate(&e1));
+        double best_ms = 1e300;
+        *best = 0;
+        for (int v = 0; v < efie::kNumVariants; ++v) {
+            auto run = [&]() {
+                if (acc64)
+                    efie::launch_variant<true>(v, X, Z, Y, idx, int(M), int(n), stream);
+                else
+                    efie::launch_variant<false>(v, X, Z, Y, nullptr, int(M), int(n), stream);
+            };
+            run();   // warm-up
+            EFIE_HIP_CHECK(hipEventRecord(e0, stream));
+            for (int r = 0; r < reps; ++r) run();
+            EFIE_HIP_CHECK(hipEventRecord(e1, stream));
+            EFIE_HIP_CHECK(hipEventSynchronize(e1));
+            float t = 0.f;
+            EFIE_HIP_CHECK(hipEventElapsedTime(&t, e0, e1));
+            ms[v] = double(t) / reps;
+            if (ms[v] < best_ms) {
+                best_ms = ms[v];
+                *best = v;
+            }
+        }
+        EFIE_HIP_CHECK(hipEventDestroy(e0));
+        EFIE_HIP_CHECK(hipEventDestroy(e1));
+        EFIE_HIP_CHECK(hipGetLastError());
+        return int(EFIE_OK);
+    });
+}
 
 extern "C" int efie_zx(const void* Z, int dtype, int64_t n, const void* X, void* Y, int64_t nrhs,
                        hipStream_t stream) {

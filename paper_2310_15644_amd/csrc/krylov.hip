@@ -1,5 +1,9 @@
 // Krylov solves of Z J = V for many right-hand sides (columns), x0 = 0.
 //
+// Only active (unconverged) columns enter the Z-products: a compaction kernel
+// lists them after every step, up to 8 columns use a multi-column GEMV (Z read
+// once, FP64 accumulation) and more use the GEMM on the gathered columns.
+//
 // The paper names CG and CGS but states neither; the readings implemented are
 //   COCG (van der Vorst and Melissen 1990): CG with the unconjugated bilinear
 //        form a^T b, valid because Z = Z^T; one product Z p per iteration;
@@ -15,13 +19,21 @@
 // on convergence, breakdown or NaN.  The host reads the number of active
 // columns after each iteration (one 4-byte copy).
 //
-// Mixed precision (complex64 Z): an outer refinement loop computes the residual
-// V - Z J with FP64 accumulation from the stored complex64 Z and solves
-// Z d = residual by an inner Krylov solve whose Z-products run on FP32 matrix
-// cores; J += d.
+// Mixed precision (complex64 Z).  COCG: one Krylov solve whose Z-products run on
+// FP32 matrix cores, with reliable updates (Sleijpen and van der Vorst,
+// Computing 56, 1996): whenever a column's recursive residual has dropped by a
+// factor 10 since its last replacement, or claims convergence, it is replaced by
+// the true residual V - Z J accumulated in FP64 from the stored complex64 Z, and
+// only the true residual may declare convergence.  This keeps the FP32
+// accumulation error of the products (~1e-5 ||Z|| ||p||, amplified along
+// near-resonant directions) out of the recurrence.  CGS: an outer refinement
+// loop around inner CGS solves.
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <vector>
 
 #include "efie_internal.h"
@@ -35,7 +47,11 @@ struct Col {
     double bn2;             // ||b||^2
     double rn2;             // ||r||^2 (recurrence)
     double tol2;            // tol^2 ||b||^2
-    int active, iters, status, pad;
+    double rn2_ref;         // ||r||^2 at the last true-residual replacement (reliable updates)
+    int active, iters, status, upd;   // upd: true residual requested (mixed-precision COCG)
+    int since;              // iterations since the last replacement
+    int rst;                // restart the search direction at the next replacement
+    int pad2[2];
 };
 
 constexpr int KB = 512;   // threads per column block
@@ -105,9 +121,13 @@ __global__ __launch_bounds__(KB) void cocg_init(const double2* b, double2* x, do
         c.rho_i = v[1];
         c.bn2 = v[2];
         c.tol2 = tol * tol * v[2];
+        c.rn2_ref = v[2];
         c.active = 1;
         c.status = EFIE_NOT_CONVERGED;
         c.iters = 0;
+        c.upd = 0;
+        c.since = 0;
+        c.rst = 0;
         finish_check(c, v[2]);
         if (v[2] == 0.0) c.status = EFIE_OK;
         cols[s] = c;
@@ -117,7 +137,7 @@ __global__ __launch_bounds__(KB) void cocg_init(const double2* b, double2* x, do
 // one COCG step after q = Z p:  mu = p^T q, alpha = rho/mu, x += alpha p,
 // r -= alpha q, rho' = r^T r, beta = rho'/rho, p = r + beta p.
 __global__ __launch_bounds__(KB) void cocg_step(double2* x, double2* r, double2* p, const double2* q, Col* cols,
-                                                int n, int* nactive) {
+                                                int n, int* counters, int reliable) {
     __shared__ double sh[KB / 64 * 4];
     __shared__ int go;
     const int s = blockIdx.x;
@@ -178,9 +198,62 @@ __global__ __launch_bounds__(KB) void cocg_step(double2* x, double2* r, double2*
         c.rho_r = rho_new.r;
         c.rho_i = rho_new.i;
         c.iters += 1;
-        finish_check(c, w[2]);
+        if (reliable) {
+            // the recursive residual only requests a true one; it never converges alone.
+            // Replacement after a tenfold drop, on a convergence claim, or after
+            // 100 iterations without one (bounds the drift of a stalled column).
+            c.rn2 = w[2];
+            c.since += 1;
+            if (!(w[2] == w[2]) || w[2] > 1e300) {
+                c.status = EFIE_ERR_NAN;
+                c.active = 0;
+            } else if (w[2] <= c.tol2 || w[2] < 0.01 * c.rn2_ref || c.since >= 100) {
+                c.upd = 1;
+                atomicAdd(counters + 1, 1);
+            }
+        } else {
+            finish_check(c, w[2]);
+        }
         cols[s] = c;
-        if (c.active) atomicAdd(nactive, 1);
+        if (c.active) atomicAdd(counters, 1);
+    }
+}
+
+// Reliable update of the flagged columns: r = b - y (y = Z x with FP64
+// accumulation), rho = r^T r, and convergence decided on the true residual.
+// If the true residual norm exceeds the recursive one by more than sqrt(10), the
+// recurrence has lost track of it (or a restart was requested): the search
+// direction restarts, p = r.
+__global__ __launch_bounds__(KB) void cocg_replace(const double2* b, double2* r, double2* p, const double2* y,
+                                                   Col* cols, int n, const int* idx, int* counters) {
+    __shared__ double sh[KB / 64 * 4];
+    const int s = idx[blockIdx.x];
+    const size_t o = size_t(s) * n;
+    const double rec = cols[s].rn2;   // read before block_sum's barriers; thread 0 rewrites cols[s] after them
+    const int rst = cols[s].rst;
+    double a[4] = {0, 0, 0, 0};
+    for (int k = threadIdx.x; k < n; k += KB) {
+        const double2 bb = b[o + k], yy = y[o + k];
+        const double2 d = make_double2(bb.x - yy.x, bb.y - yy.y);
+        r[o + k] = d;
+        a[0] += d.x * d.x - d.y * d.y;
+        a[1] += 2.0 * d.x * d.y;
+        a[2] += d.x * d.x + d.y * d.y;
+    }
+    block_sum<4>(a, sh);
+    if (a[2] > 10.0 * rec || rst)
+        for (int k = threadIdx.x; k < n; k += KB) p[o + k] = r[o + k];
+    if (threadIdx.x == 0) {
+        Col c = cols[s];
+        c.rho_r = a[0];
+        c.rho_i = a[1];
+        c.rn2_ref = a[2];
+        c.upd = 0;
+        c.since = 0;
+        c.rst = 0;
+        finish_check(c, a[2]);
+        cols[s] = c;
+        if (!c.active) atomicSub(counters, 1);
     }
 }
 
@@ -265,7 +338,7 @@ __global__ __launch_bounds__(KB) void cgs_step1(double2* x, const double2* rt, c
 // after t = Z w: r -= alpha t, rho' = r~^H r, beta = rho'/rho, u = r + beta q,
 // p = u + beta (q + beta p)
 __global__ __launch_bounds__(KB) void cgs_step2(double2* r, const double2* rt, double2* u, double2* p,
-                                                const double2* q, const double2* t, Col* cols, int n, int* nactive) {
+                                                const double2* q, const double2* t, Col* cols, int n, int* counters) {
     __shared__ double sh[KB / 64 * 4];
     __shared__ int go;
     const int s = blockIdx.x;
@@ -315,11 +388,44 @@ __global__ __launch_bounds__(KB) void cgs_step2(double2* r, const double2* rt, d
         c.iters += 1;
         finish_check(c, a[2]);
         cols[s] = c;
-        if (c.active) atomicAdd(nactive, 1);
+        if (c.active) atomicAdd(counters, 1);
     }
 }
 
 // ----------------------------------------------------------- helper kernels
+// List the columns whose flag (active, or upd) is set, in increasing order; one block.
+__global__ __launch_bounds__(1024) void compact_kernel(const Col* cols, int S, int which, int* idx, int* count) {
+    __shared__ int wsum[16];
+    __shared__ int base;
+    if (threadIdx.x == 0) base = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int s0 = 0; s0 < S; s0 += 1024) {
+        const int s = s0 + threadIdx.x;
+        const int f = s < S ? (which == 0 ? cols[s].active : cols[s].upd) : 0;
+        // inclusive scan inside the wavefront
+        int v = f;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(v, o, 64);
+            if (lane >= o) v += t;
+        }
+        if (lane == 63) wsum[w] = v;
+        __syncthreads();
+        int off = base;
+        for (int u = 0; u < w; ++u) off += wsum[u];
+        if (f) idx[off + v - 1] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int tot = 0;
+            for (int u = 0; u < 16; ++u) tot += wsum[u];
+            base += tot;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *count = base;
+}
+
 // out = b - y, and per-column ||out||^2 into nrm[s]
 __global__ __launch_bounds__(KB) void residual_kernel(const double2* b, const double2* y, double2* out, double* nrm,
                                                       double* bnrm, int n) {
@@ -348,18 +454,46 @@ __global__ void axpy_inplace_kernel(double2* x, const double2* d, size_t n) {
     }
 }
 
+// flag every active column for a replacement with restart
+__global__ void force_replace_kernel(Col* cols, int S, int* counters) {
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < S; s += gridDim.x * blockDim.x)
+        if (cols[s].active) {
+            cols[s].upd = 1;
+            cols[s].rst = 1;
+            atomicAdd(counters + 1, 1);
+        }
+}
+
+__global__ void iota_kernel(int* idx, int S) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < S; i += gridDim.x * blockDim.x) idx[i] = i;
+}
+
 namespace {
 
 struct Ws {
     double2 *r, *rt, *u, *p, *q, *v, *w;   // Krylov vectors (S x n each)
-    double2 *res, *dlt;                     // outer refinement: residual and correction
-    float2 *x32, *y32;                      // complex64 staging for matrix-core products
+    double2 *res, *dlt;                     // outer refinement (CGS, mixed): residual and correction
+    float2 *x32, *y32;                      // complex64 staging of the product input (y32 unused)
     Col* cols;
     double *nrm, *bnrm;
-    int* nactive;
+    int* counters;                          // [0] active, [1] flagged for a true residual, [2] count
+    int *idx_a, *idx_u, *idx_all;           // column lists: active, flagged, all
 };
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// EFIE_VERBOSE=1 prints solver progress to stderr (iteration counts, active columns, time)
+bool verbose() {
+    static int v = -1;
+    if (v < 0) {
+        const char* e = std::getenv("EFIE_VERBOSE");
+        v = (e && *e && *e != '0') ? 1 : 0;
+    }
+    return v == 1;
+}
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
 
 size_t layout(int64_t n, int64_t S, int dtype, Ws* ws, char* base) {
     const size_t vec = align256(size_t(n) * size_t(S) * 16);
@@ -379,60 +513,93 @@ size_t layout(int64_t n, int64_t S, int dtype, Ws* ws, char* base) {
     w.cols = (Col*)take(sizeof(Col) * size_t(S));
     w.nrm = (double*)take(sizeof(double) * size_t(S));
     w.bnrm = (double*)take(sizeof(double) * size_t(S));
-    w.nactive = (int*)take(sizeof(int) * 4);
+    w.counters = (int*)take(sizeof(int) * 4);
+    w.idx_a = (int*)take(sizeof(int) * size_t(S));
+    w.idx_u = (int*)take(sizeof(int) * size_t(S));
+    w.idx_all = (int*)take(sizeof(int) * size_t(S));
     if (ws) *ws = w;
     return off;
 }
 
-// Y = Z X for FP64 vectors; complex64 Z goes through complex64 staging and the
-// matrix-core GEMM when S > 1 (GEMV reads FP64 vectors directly otherwise).
-void product(const void* Z, int zdt, int n, const double2* X, double2* Y, int S, const Ws& w, hipStream_t st) {
-    if (zdt == EFIE_C64 && S > 1) {
-        cast_c128_to_c64(X, w.x32, size_t(n) * S, st);
-        cgemm_mfma(w.x32, Z, w.y32, S, n, st);
-        cast_c64_to_c128(w.y32, Y, size_t(n) * S, st);
+// Y[idx[c]] = Z X[idx[c]] for the m listed columns.  exact64: FP64 accumulation
+// for every m (true residuals); otherwise complex64 Z with m > 8 uses the FP32
+// matrix cores on complex64 copies of the columns.
+void product(const void* Z, int zdt, int n, const double2* X, double2* Y, const int* idx, int m, bool exact64,
+             const Ws& w, hipStream_t st) {
+    if (m <= 0) return;
+    if (m <= 8) {
+        gemv_multi(Z, zdt, n, X, idx, m, Y, st);
+    } else if (zdt == EFIE_C64 && !exact64) {
+        gather_cast(X, idx, m, n, w.x32, st);
+        cgemm_mfma_acc64(w.x32, Z, Y, idx, m, n, st);
     } else {
-        zx_product(Z, zdt, n, X, EFIE_C128, Y, S, st);
+        zgemm_nt(X, EFIE_C128, Z, zdt, Y, EFIE_C128, m, n, n, n, n, n, 1.0, 0.0, false, st, idx, idx);
     }
+}
+
+int compact(const Ws& w, int S, int which, int* idx, hipStream_t st) {
+    hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(1024), 0, st, w.cols, S, which, idx, w.counters + 2);
+    int h = 0;
+    EFIE_HIP_CHECK(hipMemcpyAsync(&h, w.counters + 2, sizeof(int), hipMemcpyDeviceToHost, st));
+    EFIE_HIP_CHECK(hipStreamSynchronize(st));
+    return h;
 }
 
 // FP64-accumulated residual out = b - Z x (Z of either dtype); norms into w.nrm / w.bnrm.
 void true_residual(const void* Z, int zdt, int n, const double2* b, const double2* x, double2* out, int S,
                    const Ws& w, hipStream_t st) {
     double2* y = w.q;   // scratch
-    if (S == 1)
-        gemv(Z, zdt, n, x, EFIE_C128, y, EFIE_C128, st);
-    else
-        zgemm_nt(x, EFIE_C128, Z, zdt, y, EFIE_C128, S, n, n, n, n, n, 1.0, 0.0, false, st);
+    product(Z, zdt, n, x, y, w.idx_all, S, true, w, st);
     hipLaunchKernelGGL(residual_kernel, dim3(S), dim3(KB), 0, st, b, y, out, w.nrm, w.bnrm, n);
 }
 
 // One Krylov solve of Z x = b for S columns.  Returns per-column Col states in host memory.
 void krylov(const void* Z, int zdt, int n, const double2* b, double2* x, int S, int solver, double tol, int maxit,
-            const Ws& w, std::vector<Col>& out, hipStream_t st) {
-    int h_active = 0;
+            bool reliable, const Ws& w, std::vector<Col>& out, hipStream_t st) {
+    int h[2] = {0, 0};
     if (solver == EFIE_COCG) {
         hipLaunchKernelGGL(cocg_init, dim3(S), dim3(KB), 0, st, b, x, w.r, w.p, w.cols, n, tol);
-        for (int it = 0; it < maxit; ++it) {
-            product(Z, zdt, n, w.p, w.q, S, w, st);
-            EFIE_HIP_CHECK(hipMemsetAsync(w.nactive, 0, sizeof(int), st));
-            hipLaunchKernelGGL(cocg_step, dim3(S), dim3(KB), 0, st, x, w.r, w.p, w.q, w.cols, n, w.nactive);
-            EFIE_HIP_CHECK(hipMemcpyAsync(&h_active, w.nactive, sizeof(int), hipMemcpyDeviceToHost, st));
+        int m = compact(w, S, 0, w.idx_a, st);
+        // products are FP64-accurate once at most 8 columns remain: on entering that
+        // regime every remaining column restarts from its true residual
+        bool exact_regime = !reliable || m <= 8;
+        for (int it = 0; it < maxit && m > 0; ++it) {
+            product(Z, zdt, n, w.p, w.q, w.idx_a, m, false, w, st);
+            EFIE_HIP_CHECK(hipMemsetAsync(w.counters, 0, 2 * sizeof(int), st));
+            hipLaunchKernelGGL(cocg_step, dim3(S), dim3(KB), 0, st, x, w.r, w.p, w.q, w.cols, n, w.counters,
+                               int(reliable));
+            if (!exact_regime && m <= 8) {
+                exact_regime = true;
+                hipLaunchKernelGGL(force_replace_kernel, dim3((S + 255) / 256), dim3(256), 0, st, w.cols, S,
+                                   w.counters);
+            }
+            EFIE_HIP_CHECK(hipMemcpyAsync(h, w.counters, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
             EFIE_HIP_CHECK(hipStreamSynchronize(st));
-            if (h_active == 0) break;
+            if (reliable && h[1] > 0) {
+                const int mu = compact(w, S, 1, w.idx_u, st);
+                product(Z, zdt, n, x, w.v, w.idx_u, mu, true, w, st);
+                hipLaunchKernelGGL(cocg_replace, dim3(mu), dim3(KB), 0, st, b, w.r, w.p, w.v, w.cols, n, w.idx_u,
+                                   w.counters);
+            }
+            m = compact(w, S, 0, w.idx_a, st);
+            if (verbose() && (it % 50 == 0 || m == 0))
+                std::fprintf(stderr, "[efie] cocg it %d active %d/%d replaced %d t=%.3f\n", it, m, S,
+                             reliable ? h[1] : 0, now_s()),
+                    std::fflush(stderr);
         }
     } else {
         hipLaunchKernelGGL(cgs_init, dim3(S), dim3(KB), 0, st, b, x, w.r, w.rt, w.u, w.p, w.cols, n, tol);
-        for (int it = 0; it < maxit; ++it) {
-            product(Z, zdt, n, w.p, w.v, S, w, st);
+        int m = compact(w, S, 0, w.idx_a, st);
+        for (int it = 0; it < maxit && m > 0; ++it) {
+            product(Z, zdt, n, w.p, w.v, w.idx_a, m, false, w, st);
             hipLaunchKernelGGL(cgs_step1, dim3(S), dim3(KB), 0, st, x, w.rt, w.u, w.v, w.q, w.w, w.cols, n);
-            product(Z, zdt, n, w.w, w.v, S, w, st);
-            EFIE_HIP_CHECK(hipMemsetAsync(w.nactive, 0, sizeof(int), st));
+            product(Z, zdt, n, w.w, w.v, w.idx_a, m, false, w, st);
+            EFIE_HIP_CHECK(hipMemsetAsync(w.counters, 0, 2 * sizeof(int), st));
             hipLaunchKernelGGL(cgs_step2, dim3(S), dim3(KB), 0, st, w.r, w.rt, w.u, w.p, w.q, w.v, w.cols, n,
-                               w.nactive);
-            EFIE_HIP_CHECK(hipMemcpyAsync(&h_active, w.nactive, sizeof(int), hipMemcpyDeviceToHost, st));
-            EFIE_HIP_CHECK(hipStreamSynchronize(st));
-            if (h_active == 0) break;
+                               w.counters);
+            m = compact(w, S, 0, w.idx_a, st);
+            if (verbose() && (it % 50 == 0 || m == 0))
+                std::fprintf(stderr, "[efie] cgs it %d active %d/%d t=%.3f\n", it, m, S, now_s()), std::fflush(stderr);
         }
     }
     EFIE_HIP_CHECK(hipGetLastError());
@@ -470,13 +637,15 @@ extern "C" int efie_solve(const void* Z, int dtype, int64_t n, const void* V, vo
         Ws w;
         layout(n, nrhs, dtype, &w, static_cast<char*>(ws));
         const int S = int(nrhs), nn = int(n);
+        hipLaunchKernelGGL(iota_kernel, dim3((S + 255) / 256), dim3(256), 0, stream, w.idx_all, S);
         const double2* b = static_cast<const double2*>(V);
         double2* x = static_cast<double2*>(J);
         std::vector<Col> cols;
         std::vector<int> iters(S, 0);
         std::vector<double> recur(S, 0.0);
-        if (dtype == EFIE_C128) {
-            krylov(Z, dtype, nn, b, x, S, opts->solver, opts->tol, opts->maxit, w, cols, stream);
+        if (dtype == EFIE_C128 || opts->solver == EFIE_COCG) {
+            // FP64 operator, or mixed precision with reliable updates
+            krylov(Z, dtype, nn, b, x, S, opts->solver, opts->tol, opts->maxit, dtype == EFIE_C64, w, cols, stream);
             for (int s = 0; s < S; ++s) {
                 iters[s] = cols[s].iters;
                 recur[s] = cols[s].bn2 > 0 ? std::sqrt(cols[s].rn2 / cols[s].bn2) : 0.0;
@@ -493,15 +662,22 @@ extern "C" int efie_solve(const void* Z, int dtype, int64_t n, const void* V, vo
                     EFIE_HIP_CHECK(hipMemcpyAsync(h_bn.data(), w.bnrm, sizeof(double) * S, hipMemcpyDeviceToHost, stream));
                     EFIE_HIP_CHECK(hipStreamSynchronize(stream));
                     bool done = true;
-                    for (int s = 0; s < S; ++s)
+                    double worst = 0.0;
+                    for (int s = 0; s < S; ++s) {
                         if (h_nrm[s] > opts->tol * opts->tol * h_bn[s]) done = false;
+                        worst = std::max(worst, h_bn[s] > 0 ? std::sqrt(h_nrm[s] / h_bn[s]) : 0.0);
+                    }
+                    if (verbose())
+                        std::fprintf(stderr, "[efie] refine %d worst relres %.3e t=%.3f\n", outer, worst, now_s()),
+                            std::fflush(stderr);
                     if (done) break;
                 } else {
                     EFIE_HIP_CHECK(hipMemcpyAsync(w.res, b, size_t(nn) * S * 16, hipMemcpyDeviceToDevice, stream));
                 }
                 // inner solve Z d = res to inner_tol (columns already converged have a
                 // residual below tol; the inner solve then stops at once or adds little)
-                krylov(Z, dtype, nn, w.res, w.dlt, S, opts->solver, opts->inner_tol, opts->maxit, w, cols, stream);
+                krylov(Z, dtype, nn, w.res, w.dlt, S, opts->solver, opts->inner_tol, opts->maxit, false, w, cols,
+                       stream);
                 const size_t tot = size_t(nn) * S;
                 hipLaunchKernelGGL(axpy_inplace_kernel, dim3(int(std::min<size_t>((tot + 255) / 256, 16384))),
                                    dim3(256), 0, stream, x, w.dlt, tot);
@@ -531,8 +707,8 @@ extern "C" int efie_solve(const void* Z, int dtype, int64_t n, const void* V, vo
                 stats[s].relres_recur = recur[s];
                 stats[s].relres_true = rel;
             }
-            if (st < 0 && ret >= 0) ret = st;
-            else if (st == EFIE_NOT_CONVERGED && ret == EFIE_OK) ret = EFIE_NOT_CONVERGED;
+            // per-column breakdown / NaN is reported in stats; the call returns a warning
+            if (st != EFIE_OK) ret = EFIE_NOT_CONVERGED;
         }
         return ret;
     });

@@ -109,6 +109,75 @@ __global__ __launch_bounds__(256) void gemv_c64_kernel(const float2* __restrict_
     if (lane == 0) store_c<YT>(y, row, ar, ai);
 }
 
+// Y[idx[c]][i] = sum_k Z[i][k] X[idx[c]][k] for c < m <= MC columns of FP64 vectors:
+// one wavefront per row, Z read once for all m columns, FP64 accumulation.
+template <typename ZT, int MC>
+__global__ __launch_bounds__(256) void gemv_multi_kernel(const ZT* __restrict__ Z, const double2* __restrict__ X,
+                                                         const int* __restrict__ idx, int m,
+                                                         double2* __restrict__ Y, int n) {
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= n) return;
+    const ZT* zr = Z + size_t(row) * n;
+    const double2* xc[MC];
+#pragma unroll
+    for (int c = 0; c < MC; ++c) xc[c] = X + size_t(idx[c < m ? c : 0]) * n;
+    double ar[MC], ai[MC];
+#pragma unroll
+    for (int c = 0; c < MC; ++c) ar[c] = ai[c] = 0.0;
+    int k = lane;
+    for (; k + 64 < n; k += 128) {
+        const double2 z0 = CT<ZT>::ld(zr, k), z1 = CT<ZT>::ld(zr, k + 64);
+#pragma unroll
+        for (int c = 0; c < MC; ++c) {
+            if (c < m) {
+                const double2 x0 = xc[c][k], x1 = xc[c][k + 64];
+                ar[c] += z0.x * x0.x - z0.y * x0.y + z1.x * x1.x - z1.y * x1.y;
+                ai[c] += z0.x * x0.y + z0.y * x0.x + z1.x * x1.y + z1.y * x1.x;
+            }
+        }
+    }
+    for (; k < n; k += 64) {
+        const double2 z0 = CT<ZT>::ld(zr, k);
+#pragma unroll
+        for (int c = 0; c < MC; ++c) {
+            if (c < m) {
+                const double2 x0 = xc[c][k];
+                ar[c] += z0.x * x0.x - z0.y * x0.y;
+                ai[c] += z0.x * x0.y + z0.y * x0.x;
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < MC; ++c) {
+        if (c < m) {
+            const double re = wave_sum(ar[c]), im = wave_sum(ai[c]);
+            if (lane == 0) Y[size_t(idx[c]) * n + row] = make_double2(re, im);
+        }
+    }
+}
+
+// out[r][k] = (complex64) X[idx[r]][k]
+__global__ void gather_cast_kernel(const double2* __restrict__ X, const int* __restrict__ idx, int m, int n,
+                                   float2* __restrict__ out) {
+    const size_t tot = size_t(m) * n;
+    for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < tot; e += size_t(gridDim.x) * blockDim.x) {
+        const size_t r = e / n, k = e - r * n;
+        const double2 v = X[size_t(idx[r]) * n + k];
+        out[e] = make_float2(float(v.x), float(v.y));
+    }
+}
+// Y[idx[r]][k] = (complex128) in[r][k]
+__global__ void scatter_cast_kernel(const float2* __restrict__ in, const int* __restrict__ idx, int m, int n,
+                                    double2* __restrict__ Y) {
+    const size_t tot = size_t(m) * n;
+    for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < tot; e += size_t(gridDim.x) * blockDim.x) {
+        const size_t r = e / n, k = e - r * n;
+        const float2 v = in[e];
+        Y[size_t(idx[r]) * n + k] = make_double2(v.x, v.y);
+    }
+}
+
 // ------------------------------------------------------------- tiled GEMM
 // C[M][Nc] (+)= alpha * sum_k A[M][k] B[Nc][k]; 64 x 64 output tile per block of
 // 256 threads (4 x 4 complex outputs each), k-chunks of 16 staged in LDS.
@@ -117,7 +186,8 @@ constexpr int GT = 64, GK = 16;
 template <typename AT, typename BT, typename CTy>
 __global__ __launch_bounds__(256) void zgemm_nt_kernel(const AT* __restrict__ A, const BT* __restrict__ B,
                                                        CTy* __restrict__ C, int M, int Nc, int K, int lda, int ldb,
-                                                       int ldc, double alr, double ali, int accumulate) {
+                                                       int ldc, double alr, double ali, int accumulate,
+                                                       const int* __restrict__ arow, const int* __restrict__ crow) {
     __shared__ double2 As[GK][GT + 1];
     __shared__ double2 Bs[GK][GT + 1];
     const int tid = threadIdx.x;
@@ -135,7 +205,8 @@ __global__ __launch_bounds__(256) void zgemm_nt_kernel(const AT* __restrict__ A,
             const int e = tid + 256 * l;
             const int r = e / GK, kk = e % GK;
             const int gm = m0 + r, gn = n0 + r, gk = k0 + kk;
-            As[kk][r] = (gm < M && gk < K) ? CT<AT>::ld(A, size_t(gm) * lda + gk) : make_double2(0, 0);
+            const int am = gm < M ? (arow ? arow[gm] : gm) : 0;
+            As[kk][r] = (gm < M && gk < K) ? CT<AT>::ld(A, size_t(am) * lda + gk) : make_double2(0, 0);
             Bs[kk][r] = (gn < Nc && gk < K) ? CT<BT>::ld(B, size_t(gn) * ldb + gk) : make_double2(0, 0);
         }
         __syncthreads();
@@ -166,7 +237,7 @@ __global__ __launch_bounds__(256) void zgemm_nt_kernel(const AT* __restrict__ A,
             if (gn >= Nc) continue;
             double re = alr * cr[i][j] - ali * ci[i][j];
             double im = alr * ci[i][j] + ali * cr[i][j];
-            const size_t o = size_t(gm) * ldc + gn;
+            const size_t o = size_t(crow ? crow[gm] : gm) * ldc + gn;
             if (accumulate) {
                 double2 old = CT<CTy>::ld(C, o);
                 re += old.x;
@@ -199,8 +270,33 @@ void cast_c64_to_c128(const void* a, void* b, size_t n, hipStream_t s) {
 }
 
 // ------------------------------------------------------------- dispatchers
+void gemv_multi(const void* Z, int zdt, int n, const double2* X, const int* idx, int m, double2* Y, hipStream_t s) {
+    EFIE_REQUIRE(m >= 1 && m <= 8, EFIE_ERR_ARG, "gemv_multi: 1..8 columns");
+    dim3 grid((n + 3) / 4), blk(256);
+    prof_begin(PROF_GEMV, s);
+#define GM(ZTy, MC) \
+    hipLaunchKernelGGL((gemv_multi_kernel<ZTy, MC>), grid, blk, 0, s, static_cast<const ZTy*>(Z), X, idx, m, Y, n)
+    if (zdt == EFIE_C128) {
+        if (m == 1) GM(double2, 1); else if (m == 2) GM(double2, 2); else if (m <= 4) GM(double2, 4); else GM(double2, 8);
+    } else {
+        if (m == 1) GM(float2, 1); else if (m == 2) GM(float2, 2); else if (m <= 4) GM(float2, 4); else GM(float2, 8);
+    }
+#undef GM
+    prof_end(PROF_GEMV, s, double(n) * n * (zdt == EFIE_C128 ? 16 : 8));
+}
+
+void gather_cast(const double2* X, const int* idx, int m, int n, float2* out, hipStream_t s) {
+    const size_t tot = size_t(m) * n;
+    if (tot) hipLaunchKernelGGL(gather_cast_kernel, dim3(grid_for(tot)), dim3(256), 0, s, X, idx, m, n, out);
+}
+void scatter_cast(const float2* in, const int* idx, int m, int n, double2* Y, hipStream_t s) {
+    const size_t tot = size_t(m) * n;
+    if (tot) hipLaunchKernelGGL(scatter_cast_kernel, dim3(grid_for(tot)), dim3(256), 0, s, in, idx, m, n, Y);
+}
+
 void gemv(const void* Z, int zdt, int n, const void* x, int xdt, void* y, int ydt, hipStream_t s) {
     dim3 grid((n + 3) / 4), blk(256);
+    prof_begin(PROF_GEMV, s);
 #define GEMV_CASE(KER, ZTy, XTy, YTy) \
     hipLaunchKernelGGL((KER), grid, blk, 0, s, static_cast<const ZTy*>(Z), static_cast<const XTy*>(x), \
                        static_cast<YTy*>(y), n)
@@ -221,21 +317,25 @@ void gemv(const void* Z, int zdt, int n, const void* x, int xdt, void* y, int yd
             GEMV_CASE((gemv_elem_kernel<float2, float2, float2>), float2, float2, float2);
         else throw Error{EFIE_ERR_ARG, "gemv: unsupported dtype combination"};
     }
+    prof_end(PROF_GEMV, s, double(n) * n * (zdt == EFIE_C128 ? 16 : 8));
 #undef GEMV_CASE
 }
 
 void zgemm_nt(const void* A, int adt, const void* B, int bdt, void* C, int cdt, int M, int Nc, int K, int lda,
-              int ldb, int ldc, double alr, double ali, bool accumulate, hipStream_t s) {
+              int ldb, int ldc, double alr, double ali, bool accumulate, hipStream_t s, const int* arow,
+              const int* crow) {
     dim3 grid((Nc + GT - 1) / GT, (M + GT - 1) / GT), blk(256);
     EFIE_REQUIRE(grid.y <= 65535, EFIE_ERR_ARG, "zgemm: too many rows");
+    prof_begin(PROF_ZGEMM, s);
 #define ZG(ATy, BTy, CTy2)                                                                                     \
     hipLaunchKernelGGL((zgemm_nt_kernel<ATy, BTy, CTy2>), grid, blk, 0, s, static_cast<const ATy*>(A),         \
                        static_cast<const BTy*>(B), static_cast<CTy2*>(C), M, Nc, K, lda, ldb, ldc, alr, ali, \
-                       int(accumulate))
+                       int(accumulate), arow, crow)
     if (adt == EFIE_C128 && bdt == EFIE_C128 && cdt == EFIE_C128) ZG(double2, double2, double2);
     else if (adt == EFIE_C128 && bdt == EFIE_C64 && cdt == EFIE_C128) ZG(double2, float2, double2);
     else if (adt == EFIE_C64 && bdt == EFIE_C64 && cdt == EFIE_C64) ZG(float2, float2, float2);
     else throw Error{EFIE_ERR_ARG, "zgemm: unsupported dtype combination"};
+    prof_end(PROF_ZGEMM, s, 8.0 * M * double(Nc) * K);
 #undef ZG
 }
 
