@@ -221,6 +221,48 @@ int efie_solve(const void* Z, int dtype, int64_t n, const void* V, void* J, int6
                const efie_solve_opts* opts, efie_rhs_stats* stats, void* ws, size_t ws_bytes,
                hipStream_t stream);
 
+/* --------------------------------------------------------------- Calderon */
+
+/*
+ * Calderon preconditioner of the EFIE (the paper's Sec. III, eq. 16 structure:
+ * second operator at the complex wavenumber k~ = k - 0.4 j k^(1/3) a^(-2/3),
+ * times a Gram inverse, times the first operator).  Readings for 3-D: the second
+ * operator is the EFIE on Buffa-Christiansen functions g_n built on the
+ * barycentric refinement (equal charge per barycentric triangle of each dual cell,
+ * no flux across the primal edge), T_BC(k~) = R^T T_bary(k~) R with
+ * g_n = sum_e R[e][n] f_e over barycentric RWGs; the Gram matrix is the mixed
+ * (G_mix)_mn = int (n x f_m) . g_n dS.  The preconditioned system is
+ * P Z J = P V with P = T_BC(k~) G_mix^-1 (dense, complex128, N x N).
+ *
+ * efie_calderon_create: host refinement, R and G_mix for a mesh (kept alive by
+ *   the caller; at most 65535 barycentric RWGs).  efie_calderon_upload: like
+ *   efie_mesh_upload, table_bytes from efie_calderon_sizes.
+ * efie_calderon_host_matrices: dense host copies (R: N_bary x N, G: N x N, either
+ *   may be NULL) for inspection of small meshes.
+ * efie_calderon_assemble: P into dev P (N x N complex128); optionally T_BC into
+ *   dev Tbc_out (may be NULL).  Rows of P solve G_mix^T p = T_BC row by CGNR to
+ *   the relative residual tol (maxit steps); *relres (host, may be NULL) gets the
+ *   worst achieved.  ws: dev workspace of ws_bytes from efie_calderon_sizes
+ *   (dominated by T_bary: 16 N_bary^2 bytes).  EFIE_NOT_CONVERGED if tol missed.
+ * efie_solve_precond: CGS on P Z J = P V (complex128 Z, FP64 throughout; the loop
+ *   tests the preconditioned recurrence residual, stats report the
+ *   unpreconditioned true residual ||V - Z J|| / ||V||).
+ */
+typedef struct efie_calderon_s* efie_calderon;
+int efie_calderon_create(efie_mesh mesh, efie_calderon* out);
+void efie_calderon_destroy(efie_calderon c);
+int efie_calderon_sizes(efie_calderon c, int64_t* n_bary_rwg, int64_t* n_bary_tri, size_t* table_bytes,
+                        size_t* ws_bytes);
+int efie_calderon_upload(efie_calderon c, void* dev, size_t bytes, hipStream_t stream);
+int efie_calderon_host_matrices(efie_calderon c, double* R, double* G);
+int efie_calderon_assemble(efie_calderon c, double kt_re, double kt_im, double eta, void* P, void* Tbc_out,
+                           double tol, int32_t maxit, double* relres, void* ws, size_t ws_bytes,
+                           hipStream_t stream);
+int efie_solve_precond_workspace_size(int64_t n, int64_t nrhs, size_t* bytes);
+int efie_solve_precond(const void* Z, const void* P, int64_t n, const void* V, void* J, int64_t nrhs,
+                       const efie_solve_opts* opts, efie_rhs_stats* stats, void* ws, size_t ws_bytes,
+                       hipStream_t stream);
+
 /* ------------------------------------------------------------ measurement */
 
 /*

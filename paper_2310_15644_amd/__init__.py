@@ -41,6 +41,8 @@ EXPORTED = [
     "efie_farfield_workspace_size", "efie_farfield", "efie_zx", "efie_solve_workspace_size", "efie_solve",
     "efie_prof_enable", "efie_prof_reset", "efie_prof_read",
     "efie_gemm_variants", "efie_gemm_variant_info", "efie_gemm_autotune", "efie_gemm_select",
+    "efie_calderon_create", "efie_calderon_destroy", "efie_calderon_sizes", "efie_calderon_upload",
+    "efie_calderon_host_matrices", "efie_calderon_assemble", "efie_solve_precond_workspace_size", "efie_solve_precond",
 ]
 PROF_IDS = {"far": 0, "near": 1, "mfma": 2, "gemv": 3, "zgemm": 4, "krylov": 5, "excite": 6, "farfield": 7}
 
@@ -99,6 +101,16 @@ def lib():
         "efie_gemm_autotune": ([P, I64, P, I64, ctypes.c_int, P, ctypes.c_size_t, ctypes.c_int,
                                 ctypes.POINTER(D), ctypes.POINTER(ctypes.c_int), P], ctypes.c_int),
         "efie_gemm_select": ([ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+        "efie_calderon_create": ([P, ctypes.POINTER(P)], ctypes.c_int),
+        "efie_calderon_destroy": ([P], None),
+        "efie_calderon_sizes": ([P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(ctypes.c_size_t),
+                                 ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "efie_calderon_upload": ([P, P, ctypes.c_size_t, P], ctypes.c_int),
+        "efie_calderon_host_matrices": ([P, P, P], ctypes.c_int),
+        "efie_calderon_assemble": ([P, D, D, D, P, P, D, I32, ctypes.POINTER(D), P, ctypes.c_size_t, P], ctypes.c_int),
+        "efie_solve_precond_workspace_size": ([I64, I64, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "efie_solve_precond": ([P, P, I64, P, P, I64, ctypes.POINTER(_SolveOpts), ctypes.POINTER(_RhsStats), P,
+                                ctypes.c_size_t, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -404,3 +416,91 @@ def gemm_autotune(Z, M: int, reps: int = 3, cache: str | None = None, force: boo
     gemm_select(False, ent["acc32"])
     gemm_select(True, ent["acc64"])
     return ent
+
+
+# ------------------------------------------------------------------ Calderon
+class Calderon:
+    """Calderon preconditioner of a mesh (paper, Sec. III, eq. 16 structure):
+    P = T_BC(k~) G_mix^-1 with Buffa-Christiansen functions on the barycentric
+    refinement; solves P Z J = P V."""
+
+    def __init__(self, mesh: Mesh):
+        L = lib()
+        h = ctypes.c_void_p()
+        _check(L.efie_calderon_create(mesh._h, ctypes.byref(h)))
+        self._h = h
+        self.mesh = mesh          # keeps the primal handle alive
+        nb, tb, tbytes, wbytes = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_size_t(), ctypes.c_size_t()
+        _check(L.efie_calderon_sizes(h, ctypes.byref(nb), ctypes.byref(tb), ctypes.byref(tbytes), ctypes.byref(wbytes)))
+        self.n_bary, self.t_bary, self.table_bytes, self.ws_bytes = nb.value, tb.value, tbytes.value, wbytes.value
+        self._dev = None
+
+    def host_matrices(self):
+        """Dense (R: N_bary x N, G_mix: N x N) host copies (small meshes)."""
+        R = np.zeros((self.n_bary, self.mesh.n))
+        G = np.zeros((self.mesh.n, self.mesh.n))
+        _check(lib().efie_calderon_host_matrices(self._h, R.ctypes.data, G.ctypes.data))
+        return R, G
+
+    def upload(self, device=None):
+        torch = _torch()
+        device = device or self.mesh.device
+        buf = torch.empty(self.table_bytes + 256, dtype=torch.uint8, device=device)
+        off = (-buf.data_ptr()) % 256
+        _check(lib().efie_calderon_upload(self._h, ctypes.c_void_p(buf.data_ptr() + off), self.table_bytes,
+                                          _stream(buf.device)))
+        self._dev = buf
+        return self
+
+    def assemble(self, ktilde_value, eta: float = ETA0, tol: float = 1e-13, maxit: int = 500, with_tbc=False):
+        """P (N x N complex128) on the device; with_tbc also returns T_BC."""
+        torch = _torch()
+        if self._dev is None:
+            self.upload()
+        dev = self.mesh.device
+        n = self.mesh.n
+        kt = complex(ktilde_value)
+        Pm = torch.empty((n, n), dtype=torch.complex128, device=dev)
+        T = torch.empty((n, n), dtype=torch.complex128, device=dev) if with_tbc else None
+        ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=dev)
+        off = (-ws.data_ptr()) % 256
+        rel = ctypes.c_double()
+        code = lib().efie_calderon_assemble(self._h, kt.real, kt.imag, float(eta), _ptr(Pm),
+                                            _ptr(T) if T is not None else None, float(tol), int(maxit),
+                                            ctypes.byref(rel), ctypes.c_void_p(ws.data_ptr() + off), self.ws_bytes,
+                                            _stream(dev))
+        _check(code, allow_not_converged=True)
+        del ws
+        self.gram_relres = rel.value
+        return (Pm, T) if with_tbc else Pm
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.efie_calderon_destroy(h)
+            self._h = None
+
+
+def solve_precond(Z, Pm, V, tol=1e-8, maxit=1000, out=None):
+    """CGS on P Z J = P V (complex128); stats report the unpreconditioned true residual."""
+    torch = _torch()
+    _require_cuda(Z, "Z")
+    _require_cuda(Pm, "P")
+    n = Z.shape[0]
+    V = V.reshape(-1, n)
+    S = V.shape[0]
+    J = out if out is not None else torch.empty_like(V)
+    nb = ctypes.c_size_t()
+    _check(lib().efie_solve_precond_workspace_size(n, S, ctypes.byref(nb)))
+    ws = torch.empty(nb.value + 256, dtype=torch.uint8, device=Z.device)
+    off = (-ws.data_ptr()) % 256
+    opts = _SolveOpts(CGS, int(maxit), float(tol), 1, 1e-3)
+    st = (_RhsStats * S)()
+    code = lib().efie_solve_precond(_ptr(Z), _ptr(Pm), n, _ptr(V), _ptr(J), S, ctypes.byref(opts), st,
+                                    ctypes.c_void_p(ws.data_ptr() + off), nb.value, _stream(Z.device))
+    _check(code, allow_not_converged=True)
+    return J, SolveStats(
+        iters=np.array([s.iters for s in st]), status=np.array([s.status for s in st]),
+        relres_recur=np.array([s.relres_recur for s in st]), relres_true=np.array([s.relres_true for s in st]),
+        code=code,
+    )

@@ -20,7 +20,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libefie.so")
 BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
 
-SOURCES = ["abi.cpp", "mesh.cpp", "prof.cpp", "assemble.hip", "linalg.hip", "gemm_mfma.hip", "krylov.hip", "excite.hip"]
+SOURCES = ["abi.cpp", "mesh.cpp", "prof.cpp", "assemble.hip", "linalg.hip", "gemm_mfma.hip", "krylov.hip", "excite.hip", "calderon.cpp", "calderon.hip"]
 
 ARCH = "gfx950"
 
@@ -47,7 +47,7 @@ def flags():
 
 def _compile(src):
     os.makedirs(BUILD_DIR, exist_ok=True)
-    obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
+    obj = os.path.join(BUILD_DIR, src + ".o")
     cmd = [hipcc()] + flags() + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

@@ -1,0 +1,225 @@
+// Host side of the Calderon preconditioner: barycentric refinement, the
+// Buffa-Christiansen coefficient matrix R (g_n = sum_e R[e][n] f_e over the
+// barycentric RWGs f_e) and the sparse mixed Gram matrix
+// (G_mix)_mn = int (n x f_m) . g_n dS.
+//
+// Construction (readings; the paper fixes only the multiplicative structure and
+// k~ of its Sec. III):
+//  * each triangle (v0,v1,v2) with centroid c and edge midpoints m01, m12, m20
+//    becomes (v0,m01,c), (m01,v1,c), (v1,m12,c), (m12,v2,c), (v2,m20,c), (m20,v0,c);
+//    barycentric vertex ids: original, then midpoints in RWG order, then centroids;
+//  * g_n (primal edge n = (a, b), a < b) flows from the dual cell of a to the dual
+//    cell of b through the two halves of the dual edge (flux 1/2 each), puts equal
+//    charge +1/N_a (-1/N_b) on each barycentric triangle of cell(a) (cell(b)) and
+//    no flux across the two halves of edge n (Buffa-Christiansen 2007; Andriulli
+//    et al. 2008 for the multiplicative Calderon use);
+//  * G_mix by the 7-point rule on every barycentric triangle (exact: the integrand
+//    is quadratic there).
+#include <algorithm>
+#include <cmath>
+#include <map>
+
+#include "calderon.h"
+
+namespace efie {
+
+namespace {
+struct V3 {
+    double x, y, z;
+};
+inline V3 sub(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+inline V3 cross(V3 a, V3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+inline double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+
+void radon7(double bary[7][3], double w[7]) {
+    const double s = std::sqrt(15.0);
+    const double a1 = (9.0 - 2.0 * s) / 21.0, b1 = (6.0 + s) / 21.0;
+    const double a2 = (9.0 + 2.0 * s) / 21.0, b2 = (6.0 - s) / 21.0;
+    const double w1 = (155.0 + s) / 1200.0, w2 = (155.0 - s) / 1200.0;
+    const double B[7][3] = {{1.0 / 3.0, 1.0 / 3.0, 1.0 / 3.0}, {a1, b1, b1}, {b1, a1, b1}, {b1, b1, a1},
+                            {a2, b2, b2}, {b2, a2, b2}, {b2, b2, a2}};
+    const double W[7] = {9.0 / 40.0, w1, w1, w1, w2, w2, w2};
+    for (int i = 0; i < 7; ++i) {
+        w[i] = W[i];
+        for (int j = 0; j < 3; ++j) bary[i][j] = B[i][j];
+    }
+}
+
+// value of the RWG half-function carried by local edge i of triangle t at r
+V3 rwg_value(const efie_mesh_s& m, int64_t t, int i, V3 r) {
+    const int32_t e = m.tri_edge[3 * t + i];
+    const double c = m.tri_sign[3 * t + i] * m.edge_len[e] / (2.0 * m.area[t]);
+    const int32_t v = m.tri[3 * t + i];
+    const V3 p{m.xyz[3 * v], m.xyz[3 * v + 1], m.xyz[3 * v + 2]};
+    const V3 d = sub(r, p);
+    return {c * d.x, c * d.y, c * d.z};
+}
+}  // namespace
+
+void build_calderon(efie_calderon_s& C, const efie_mesh_s& m) {
+    const int64_t V = m.nv, N = m.N, T = m.T;
+    // ---------------------------------------------------- barycentric refinement
+    std::vector<double> xyz(3 * size_t(V + N + T));
+    for (int64_t i = 0; i < 3 * V; ++i) xyz[i] = m.xyz[i];
+    for (int64_t n = 0; n < N; ++n)
+        for (int d = 0; d < 3; ++d)
+            xyz[3 * (V + n) + d] = 0.5 * (m.xyz[3 * size_t(m.edge_v[2 * n]) + d] + m.xyz[3 * size_t(m.edge_v[2 * n + 1]) + d]);
+    for (int64_t t = 0; t < T; ++t)
+        for (int d = 0; d < 3; ++d)
+            xyz[3 * (V + N + t) + d] = (m.xyz[3 * size_t(m.tri[3 * t]) + d] + m.xyz[3 * size_t(m.tri[3 * t + 1]) + d] +
+                                        m.xyz[3 * size_t(m.tri[3 * t + 2]) + d]) / 3.0;
+    std::vector<int32_t> tri(18 * size_t(T));
+    for (int64_t t = 0; t < T; ++t) {
+        const int32_t v0 = m.tri[3 * t], v1 = m.tri[3 * t + 1], v2 = m.tri[3 * t + 2];
+        const int32_t m12 = int32_t(V + m.tri_edge[3 * t]), m20 = int32_t(V + m.tri_edge[3 * t + 1]),
+                      m01 = int32_t(V + m.tri_edge[3 * t + 2]);
+        const int32_t c = int32_t(V + N + t);
+        const int32_t sub6[6][3] = {{v0, m01, c}, {m01, v1, c}, {v1, m12, c}, {m12, v2, c}, {v2, m20, c}, {m20, v0, c}};
+        for (int k = 0; k < 6; ++k)
+            for (int j = 0; j < 3; ++j) tri[18 * t + 3 * k + j] = sub6[k][j];
+    }
+    build_mesh(C.bary, xyz.data(), V + N + T, tri.data(), 6 * T, m.near_factor);
+    pack_tables(C.bary);
+    const efie_mesh_s& b = C.bary;
+
+    // --------------------------------------------------- Buffa-Christiansen R
+    std::map<std::pair<int32_t, int32_t>, int32_t> bedge;
+    for (int64_t e = 0; e < b.N; ++e) bedge[{b.edge_v[2 * e], b.edge_v[2 * e + 1]}] = int32_t(e);
+    auto edge_of = [&](int32_t p, int32_t q) { return bedge.at({std::min(p, q), std::max(p, q)}); };
+    // triangles around each barycentric vertex, rotated to start there: (tri, X, Y)
+    struct Corner {
+        int32_t t, X, Y;
+    };
+    std::vector<std::vector<Corner>> around(static_cast<size_t>(b.nv));
+    for (int64_t t = 0; t < b.T; ++t) {
+        const int32_t p = b.tri[3 * t], q = b.tri[3 * t + 1], r = b.tri[3 * t + 2];
+        around[size_t(p)].push_back({int32_t(t), q, r});
+        around[size_t(q)].push_back({int32_t(t), r, p});
+        around[size_t(r)].push_back({int32_t(t), p, q});
+    }
+    auto from_plus = [&](int32_t t, int32_t e) { return b.edge_t[2 * e] == t ? 1.0 : -1.0; };
+    std::vector<std::map<int32_t, double>> cols(static_cast<size_t>(N));
+    for (int64_t n = 0; n < N; ++n) {
+        const int32_t mid = int32_t(V + n);
+        for (int side = 0; side < 2; ++side) {
+            const int32_t c = m.edge_v[2 * n + side];
+            const double sigma = side == 0 ? 1.0 : -1.0;
+            const auto& ring = around[size_t(c)];
+            const int Nc = int(ring.size());
+            // counter-clockwise order starting with the triangle (c, mid, *)
+            std::vector<Corner> order;
+            order.reserve(Nc);
+            auto find_X = [&](int32_t X) {
+                for (const auto& k : ring)
+                    if (k.X == X) return k;
+                throw Error{EFIE_ERR_MESH_ORIENT, "calderon: broken vertex ring"};
+            };
+            order.push_back(find_X(mid));
+            while (int(order.size()) < Nc) order.push_back(find_X(order.back().Y));
+            double x = 0.0;
+            for (int i = 0; i < Nc; ++i) {
+                const Corner& k = order[size_t(i)];
+                const double o = (k.X == mid || k.Y == mid) ? sigma / 2.0 : 0.0;
+                x += sigma / Nc - o;   // flux from t_i into t_{i+1}
+                if (i < Nc - 1) {
+                    const int32_t e = edge_of(c, k.Y);
+                    cols[size_t(n)][e] += from_plus(k.t, e) * x / b.edge_len[e];
+                }
+            }
+            if (side == 0) {
+                for (const Corner* k : {&order.front(), &order.back()}) {
+                    const int32_t e = edge_of(k->X, k->Y);
+                    cols[size_t(n)][e] += from_plus(k->t, e) * 0.5 / b.edge_len[e];
+                }
+            }
+        }
+    }
+    C.r_ptr.assign(size_t(N) + 1, 0);
+    C.r_idx.clear();
+    C.r_val.clear();
+    for (int64_t n = 0; n < N; ++n) {
+        for (const auto& kv : cols[size_t(n)]) {
+            if (kv.second == 0.0) continue;
+            C.r_idx.push_back(kv.first);
+            C.r_val.push_back(kv.second);
+        }
+        C.r_ptr[size_t(n) + 1] = int32_t(C.r_idx.size());
+    }
+    // the same coefficients by barycentric edge (rows of R)
+    C.re_ptr.assign(size_t(b.N) + 1, 0);
+    for (int32_t e : C.r_idx) C.re_ptr[size_t(e) + 1]++;
+    for (int64_t e = 0; e < b.N; ++e) C.re_ptr[size_t(e) + 1] += C.re_ptr[size_t(e)];
+    C.re_idx.assign(C.r_idx.size(), 0);
+    C.re_val.assign(C.r_val.size(), 0.0);
+    {
+        std::vector<int32_t> fill(C.re_ptr.begin(), C.re_ptr.end() - 1);
+        for (int64_t n = 0; n < N; ++n)
+            for (int32_t k = C.r_ptr[size_t(n)]; k < C.r_ptr[size_t(n) + 1]; ++k) {
+                const int32_t e = C.r_idx[size_t(k)];
+                C.re_idx[size_t(fill[size_t(e)])] = int32_t(n);
+                C.re_val[size_t(fill[size_t(e)])] = C.r_val[size_t(k)];
+                fill[size_t(e)]++;
+            }
+    }
+
+    // ----------------------------------------------------------- mixed Gram
+    double qb[7][3], qw[7];
+    radon7(qb, qw);
+    std::vector<std::map<int32_t, double>> grows(static_cast<size_t>(N));
+    for (int64_t bt = 0; bt < b.T; ++bt) {
+        const int64_t t = bt / 6;
+        const V3 nrm{m.normal[3 * t], m.normal[3 * t + 1], m.normal[3 * t + 2]};
+        V3 P[3];
+        for (int j = 0; j < 3; ++j) {
+            const int32_t v = b.tri[3 * bt + j];
+            P[j] = {b.xyz[3 * v], b.xyz[3 * v + 1], b.xyz[3 * v + 2]};
+        }
+        double I[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};   // int (n x f_primal_i) . f_bary_j
+        for (int a = 0; a < 7; ++a) {
+            const V3 r{qb[a][0] * P[0].x + qb[a][1] * P[1].x + qb[a][2] * P[2].x,
+                       qb[a][0] * P[0].y + qb[a][1] * P[1].y + qb[a][2] * P[2].y,
+                       qb[a][0] * P[0].z + qb[a][1] * P[1].z + qb[a][2] * P[2].z};
+            const double w = qw[a] * b.area[bt];
+            for (int i = 0; i < 3; ++i) {
+                const V3 nf = cross(nrm, rwg_value(m, t, i, r));
+                for (int j = 0; j < 3; ++j) I[i][j] += w * dot(nf, rwg_value(b, bt, j, r));
+            }
+        }
+        for (int i = 0; i < 3; ++i) {
+            const int32_t row = m.tri_edge[3 * t + i];
+            for (int j = 0; j < 3; ++j) {
+                const int32_t e = b.tri_edge[3 * bt + j];
+                // every BC function that uses barycentric RWG e
+                for (int32_t k = C.re_ptr[size_t(e)]; k < C.re_ptr[size_t(e) + 1]; ++k)
+                    grows[size_t(row)][C.re_idx[size_t(k)]] += I[i][j] * C.re_val[size_t(k)];
+            }
+        }
+    }
+    C.g_ptr.assign(size_t(N) + 1, 0);
+    C.g_idx.clear();
+    C.g_val.clear();
+    for (int64_t r = 0; r < N; ++r) {
+        for (const auto& kv : grows[size_t(r)]) {
+            C.g_idx.push_back(kv.first);
+            C.g_val.push_back(kv.second);
+        }
+        C.g_ptr[size_t(r) + 1] = int32_t(C.g_idx.size());
+    }
+    // transpose of G
+    C.gt_ptr.assign(size_t(N) + 1, 0);
+    for (int32_t c : C.g_idx) C.gt_ptr[size_t(c) + 1]++;
+    for (int64_t r = 0; r < N; ++r) C.gt_ptr[size_t(r) + 1] += C.gt_ptr[size_t(r)];
+    C.gt_idx.assign(C.g_idx.size(), 0);
+    C.gt_val.assign(C.g_val.size(), 0.0);
+    std::vector<int32_t> fill(C.gt_ptr.begin(), C.gt_ptr.end() - 1);
+    for (int64_t r = 0; r < N; ++r)
+        for (int32_t k = C.g_ptr[size_t(r)]; k < C.g_ptr[size_t(r) + 1]; ++k) {
+            const int32_t c = C.g_idx[size_t(k)];
+            C.gt_idx[size_t(fill[size_t(c)])] = int32_t(r);
+            C.gt_val[size_t(fill[size_t(c)])] = C.g_val[size_t(k)];
+            fill[size_t(c)]++;
+        }
+    C.N = N;
+}
+
+}  // namespace efie

@@ -537,6 +537,25 @@ void product(const void* Z, int zdt, int n, const double2* X, double2* Y, const 
     }
 }
 
+// The operator of a solve: Z, or P Z with a dense FP64 left factor P (the
+// Calderon product); tmp holds Z X for the rows in flight.
+struct Op {
+    const void* Z;
+    int zdt;
+    const double2* P;
+    double2* tmp;
+};
+
+void op_product(const Op& op, int n, const double2* X, double2* Y, const int* idx, int m, bool exact64, const Ws& w,
+                hipStream_t st) {
+    if (!op.P) {
+        product(op.Z, op.zdt, n, X, Y, idx, m, exact64, w, st);
+        return;
+    }
+    product(op.Z, op.zdt, n, X, op.tmp, idx, m, exact64, w, st);
+    product(op.P, EFIE_C128, n, op.tmp, Y, idx, m, true, w, st);
+}
+
 int compact(const Ws& w, int S, int which, int* idx, hipStream_t st) {
     hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(1024), 0, st, w.cols, S, which, idx, w.counters + 2);
     int h = 0;
@@ -554,8 +573,10 @@ void true_residual(const void* Z, int zdt, int n, const double2* b, const double
 }
 
 // One Krylov solve of Z x = b for S columns.  Returns per-column Col states in host memory.
-void krylov(const void* Z, int zdt, int n, const double2* b, double2* x, int S, int solver, double tol, int maxit,
+void krylov(const Op& op, int n, const double2* b, double2* x, int S, int solver, double tol, int maxit,
             bool reliable, const Ws& w, std::vector<Col>& out, hipStream_t st) {
+    const void* Z = op.Z;
+    const int zdt = op.zdt;
     int h[2] = {0, 0};
     if (solver == EFIE_COCG) {
         hipLaunchKernelGGL(cocg_init, dim3(S), dim3(KB), 0, st, b, x, w.r, w.p, w.cols, n, tol);
@@ -564,7 +585,7 @@ void krylov(const void* Z, int zdt, int n, const double2* b, double2* x, int S, 
         // regime every remaining column restarts from its true residual
         bool exact_regime = !reliable || m <= 8;
         for (int it = 0; it < maxit && m > 0; ++it) {
-            product(Z, zdt, n, w.p, w.q, w.idx_a, m, false, w, st);
+            op_product(op, n, w.p, w.q, w.idx_a, m, false, w, st);
             EFIE_HIP_CHECK(hipMemsetAsync(w.counters, 0, 2 * sizeof(int), st));
             hipLaunchKernelGGL(cocg_step, dim3(S), dim3(KB), 0, st, x, w.r, w.p, w.q, w.cols, n, w.counters,
                                int(reliable));
@@ -577,7 +598,7 @@ void krylov(const void* Z, int zdt, int n, const double2* b, double2* x, int S, 
             EFIE_HIP_CHECK(hipStreamSynchronize(st));
             if (reliable && h[1] > 0) {
                 const int mu = compact(w, S, 1, w.idx_u, st);
-                product(Z, zdt, n, x, w.v, w.idx_u, mu, true, w, st);
+                op_product(op, n, x, w.v, w.idx_u, mu, true, w, st);
                 hipLaunchKernelGGL(cocg_replace, dim3(mu), dim3(KB), 0, st, b, w.r, w.p, w.v, w.cols, n, w.idx_u,
                                    w.counters);
             }
@@ -591,9 +612,9 @@ void krylov(const void* Z, int zdt, int n, const double2* b, double2* x, int S, 
         hipLaunchKernelGGL(cgs_init, dim3(S), dim3(KB), 0, st, b, x, w.r, w.rt, w.u, w.p, w.cols, n, tol);
         int m = compact(w, S, 0, w.idx_a, st);
         for (int it = 0; it < maxit && m > 0; ++it) {
-            product(Z, zdt, n, w.p, w.v, w.idx_a, m, false, w, st);
+            op_product(op, n, w.p, w.v, w.idx_a, m, false, w, st);
             hipLaunchKernelGGL(cgs_step1, dim3(S), dim3(KB), 0, st, x, w.rt, w.u, w.v, w.q, w.w, w.cols, n);
-            product(Z, zdt, n, w.w, w.v, w.idx_a, m, false, w, st);
+            op_product(op, n, w.w, w.v, w.idx_a, m, false, w, st);
             EFIE_HIP_CHECK(hipMemsetAsync(w.counters, 0, 2 * sizeof(int), st));
             hipLaunchKernelGGL(cgs_step2, dim3(S), dim3(KB), 0, st, w.r, w.rt, w.u, w.p, w.q, w.v, w.cols, n,
                                w.counters);
@@ -645,7 +666,8 @@ extern "C" int efie_solve(const void* Z, int dtype, int64_t n, const void* V, vo
         std::vector<double> recur(S, 0.0);
         if (dtype == EFIE_C128 || opts->solver == EFIE_COCG) {
             // FP64 operator, or mixed precision with reliable updates
-            krylov(Z, dtype, nn, b, x, S, opts->solver, opts->tol, opts->maxit, dtype == EFIE_C64, w, cols, stream);
+            krylov(Op{Z, dtype, nullptr, nullptr}, nn, b, x, S, opts->solver, opts->tol, opts->maxit, dtype == EFIE_C64, w,
+                   cols, stream);
             for (int s = 0; s < S; ++s) {
                 iters[s] = cols[s].iters;
                 recur[s] = cols[s].bn2 > 0 ? std::sqrt(cols[s].rn2 / cols[s].bn2) : 0.0;
@@ -676,8 +698,8 @@ extern "C" int efie_solve(const void* Z, int dtype, int64_t n, const void* V, vo
                 }
                 // inner solve Z d = res to inner_tol (columns already converged have a
                 // residual below tol; the inner solve then stops at once or adds little)
-                krylov(Z, dtype, nn, w.res, w.dlt, S, opts->solver, opts->inner_tol, opts->maxit, false, w, cols,
-                       stream);
+                krylov(Op{Z, dtype, nullptr, nullptr}, nn, w.res, w.dlt, S, opts->solver, opts->inner_tol, opts->maxit,
+                       false, w, cols, stream);
                 const size_t tot = size_t(nn) * S;
                 hipLaunchKernelGGL(axpy_inplace_kernel, dim3(int(std::min<size_t>((tot + 255) / 256, 16384))),
                                    dim3(256), 0, stream, x, w.dlt, tot);
@@ -708,6 +730,66 @@ extern "C" int efie_solve(const void* Z, int dtype, int64_t n, const void* V, vo
                 stats[s].relres_true = rel;
             }
             // per-column breakdown / NaN is reported in stats; the call returns a warning
+            if (st != EFIE_OK) ret = EFIE_NOT_CONVERGED;
+        }
+        return ret;
+    });
+}
+
+extern "C" int efie_solve_precond_workspace_size(int64_t n, int64_t nrhs, size_t* bytes) {
+    return efie::guarded([&]() {
+        EFIE_REQUIRE(bytes && n >= 1 && nrhs >= 1, EFIE_ERR_ARG, "solve_precond_workspace_size: bad argument");
+        const size_t vec = efie::align256(size_t(n) * size_t(nrhs) * 16);
+        *bytes = efie::layout(n, nrhs, EFIE_C128, nullptr, nullptr) + 2 * vec;
+        return int(EFIE_OK);
+    });
+}
+
+extern "C" int efie_solve_precond(const void* Z, const void* P, int64_t n, const void* V, void* J, int64_t nrhs,
+                                  const efie_solve_opts* opts, efie_rhs_stats* stats, void* ws, size_t ws_bytes,
+                                  hipStream_t stream) {
+    using namespace efie;
+    return guarded([&]() {
+        EFIE_REQUIRE(Z && P && V && J && opts && ws, EFIE_ERR_ARG, "solve_precond: null argument");
+        EFIE_REQUIRE(n >= 1 && n < (int64_t(1) << 31) && nrhs >= 1 && nrhs <= 65535, EFIE_ERR_ARG,
+                     "solve_precond: bad sizes");
+        EFIE_REQUIRE(opts->solver == EFIE_CGS, EFIE_ERR_ARG,
+                     "solve_precond: the preconditioned operator is not symmetric; use EFIE_CGS");
+        EFIE_REQUIRE(opts->maxit >= 1 && opts->tol > 0.0, EFIE_ERR_ARG, "solve_precond: need maxit >= 1 and tol > 0");
+        const size_t base = layout(n, nrhs, EFIE_C128, nullptr, nullptr);
+        const size_t vec = align256(size_t(n) * size_t(nrhs) * 16);
+        EFIE_REQUIRE(ws_bytes >= base + 2 * vec, EFIE_ERR_ARG, "solve_precond: workspace too small");
+        EFIE_REQUIRE((reinterpret_cast<uintptr_t>(ws) & 255) == 0, EFIE_ERR_ARG, "solve_precond: ws not aligned");
+        Ws w;
+        layout(n, nrhs, EFIE_C128, &w, static_cast<char*>(ws));
+        double2* tmp = reinterpret_cast<double2*>(static_cast<char*>(ws) + base);
+        double2* pb = reinterpret_cast<double2*>(static_cast<char*>(ws) + base + vec);
+        const int S = int(nrhs), nn = int(n);
+        hipLaunchKernelGGL(iota_kernel, dim3((S + 255) / 256), dim3(256), 0, stream, w.idx_all, S);
+        const double2* b = static_cast<const double2*>(V);
+        double2* x = static_cast<double2*>(J);
+        // right-hand side P V
+        product(P, EFIE_C128, nn, b, pb, w.idx_all, S, true, w, stream);
+        std::vector<Col> cols;
+        krylov(Op{Z, EFIE_C128, static_cast<const double2*>(P), tmp}, nn, pb, x, S, EFIE_CGS, opts->tol, opts->maxit,
+               false, w, cols, stream);
+        // unpreconditioned true residual V - Z J
+        true_residual(Z, EFIE_C128, nn, b, x, nullptr, S, w, stream);
+        std::vector<double> h_nrm(S), h_bn(S);
+        EFIE_HIP_CHECK(hipMemcpyAsync(h_nrm.data(), w.nrm, sizeof(double) * S, hipMemcpyDeviceToHost, stream));
+        EFIE_HIP_CHECK(hipMemcpyAsync(h_bn.data(), w.bnrm, sizeof(double) * S, hipMemcpyDeviceToHost, stream));
+        EFIE_HIP_CHECK(hipStreamSynchronize(stream));
+        int ret = EFIE_OK;
+        for (int s = 0; s < S; ++s) {
+            const double rel = h_bn[s] > 0 ? std::sqrt(h_nrm[s] / h_bn[s]) : 0.0;
+            int st = cols[s].status;
+            if (!(rel == rel)) st = EFIE_ERR_NAN;
+            if (stats) {
+                stats[s].iters = cols[s].iters;
+                stats[s].status = st;
+                stats[s].relres_recur = cols[s].bn2 > 0 ? std::sqrt(cols[s].rn2 / cols[s].bn2) : 0.0;
+                stats[s].relres_true = rel;
+            }
             if (st != EFIE_OK) ret = EFIE_NOT_CONVERGED;
         }
         return ret;
