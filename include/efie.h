@@ -263,6 +263,39 @@ int efie_solve_precond(const void* Z, const void* P, int64_t n, const void* V, v
                        const efie_solve_opts* opts, efie_rhs_stats* stats, void* ws, size_t ws_bytes,
                        hipStream_t stream);
 
+/* ---------------------------------------------------------- many meshes */
+
+/*
+ * A batch of uploaded meshes (uneven sizes) assembled in ONE persistent launch
+ * and solved together (one right-hand side per mesh).
+ * Layout: the Z of mesh i (caller order) occupies N_i^2 consecutive complex
+ * elements of Zcat starting at sum_{j<i} N_j^2 (row-major, as efie_assemble);
+ * vectors occupy N_i consecutive complex128 elements of Vcat / Jcat starting at
+ * sum_{j<i} N_j.
+ * efie_batch_create: meshes must stay alive and uploaded.  efie_batch_sizes:
+ *   table_bytes for efie_batch_upload, ws_bytes for assemble/solve, total Z and
+ *   vector elements, and the number of work items of the persistent launch.
+ * efie_batch_assemble: k host array (nmesh, real, > 0); far pairs in FP32
+ *   (EFIE_C64) or FP64 (EFIE_C128), near pairs in FP64, same formulas as
+ *   efie_assemble; work items (one test triangle x 256 source triangles, or 256
+ *   near pairs) are taken from one atomic queue, largest meshes first.
+ *   Synchronises.
+ * efie_batch_solve: COCG per mesh (FP64 vectors), one grouped GEMV launch (FP64
+ *   accumulation) and one grouped update launch per iteration; stats host nmesh.
+ *   Per-mesh failures give EFIE_NOT_CONVERGED with the status in stats.
+ */
+typedef struct efie_batch_s* efie_batch;
+int efie_batch_create(const efie_mesh* meshes, int32_t nmesh, efie_batch* out);
+void efie_batch_destroy(efie_batch b);
+int efie_batch_sizes(efie_batch b, size_t* table_bytes, size_t* ws_bytes, int64_t* z_elems, int64_t* v_elems,
+                     int64_t* items);
+int efie_batch_upload(efie_batch b, void* dev, size_t bytes, hipStream_t stream);
+int efie_batch_assemble(efie_batch b, const double* k, double eta, int dtype, void* Zcat, void* ws,
+                        size_t ws_bytes, hipStream_t stream);
+int efie_batch_solve(efie_batch b, const void* Zcat, int dtype, const void* Vcat, void* Jcat,
+                     const efie_solve_opts* opts, efie_rhs_stats* stats, void* ws, size_t ws_bytes,
+                     hipStream_t stream);
+
 /* ------------------------------------------------------------ measurement */
 
 /*

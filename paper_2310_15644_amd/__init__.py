@@ -43,6 +43,8 @@ EXPORTED = [
     "efie_gemm_variants", "efie_gemm_variant_info", "efie_gemm_autotune", "efie_gemm_select",
     "efie_calderon_create", "efie_calderon_destroy", "efie_calderon_sizes", "efie_calderon_upload",
     "efie_calderon_host_matrices", "efie_calderon_assemble", "efie_solve_precond_workspace_size", "efie_solve_precond",
+    "efie_batch_create", "efie_batch_destroy", "efie_batch_sizes", "efie_batch_upload", "efie_batch_assemble",
+    "efie_batch_solve",
 ]
 PROF_IDS = {"far": 0, "near": 1, "mfma": 2, "gemv": 3, "zgemm": 4, "krylov": 5, "excite": 6, "farfield": 7}
 
@@ -111,6 +113,14 @@ def lib():
         "efie_solve_precond_workspace_size": ([I64, I64, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "efie_solve_precond": ([P, P, I64, P, P, I64, ctypes.POINTER(_SolveOpts), ctypes.POINTER(_RhsStats), P,
                                 ctypes.c_size_t, P], ctypes.c_int),
+        "efie_batch_create": ([P, I32, ctypes.POINTER(P)], ctypes.c_int),
+        "efie_batch_destroy": ([P], None),
+        "efie_batch_sizes": ([P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
+                              ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I64)], ctypes.c_int),
+        "efie_batch_upload": ([P, P, ctypes.c_size_t, P], ctypes.c_int),
+        "efie_batch_assemble": ([P, P, D, ctypes.c_int, P, P, ctypes.c_size_t, P], ctypes.c_int),
+        "efie_batch_solve": ([P, P, ctypes.c_int, P, P, ctypes.POINTER(_SolveOpts), ctypes.POINTER(_RhsStats), P,
+                              ctypes.c_size_t, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -504,3 +514,71 @@ def solve_precond(Z, Pm, V, tol=1e-8, maxit=1000, out=None):
         relres_recur=np.array([s.relres_recur for s in st]), relres_true=np.array([s.relres_true for s in st]),
         code=code,
     )
+
+
+# --------------------------------------------------------------- many meshes
+class Batch:
+    """Uneven meshes assembled in one persistent launch and solved together
+    (one right-hand side per mesh).  Z of mesh i is Zcat[zoff[i] : zoff[i] + N_i^2]
+    viewed as (N_i, N_i); vectors are Vcat[voff[i] : voff[i+1]]."""
+
+    def __init__(self, meshes):
+        L = lib()
+        for m in meshes:
+            m.device   # uploads if needed
+        arr = (ctypes.c_void_p * len(meshes))(*[m._h.value for m in meshes])
+        h = ctypes.c_void_p()
+        _check(L.efie_batch_create(arr, len(meshes), ctypes.byref(h)))
+        self._h = h
+        self.meshes = list(meshes)
+        tb, wb, ze, ve, it = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(L.efie_batch_sizes(h, ctypes.byref(tb), ctypes.byref(wb), ctypes.byref(ze), ctypes.byref(ve),
+                                  ctypes.byref(it)))
+        self.table_bytes, self.ws_bytes, self.z_elems, self.v_elems, self.items = (
+            tb.value, wb.value, ze.value, ve.value, it.value)
+        ns = [m.n for m in meshes]
+        self.zoff = np.concatenate([[0], np.cumsum([n * n for n in ns])[:-1]]).astype(np.int64)
+        self.voff = np.concatenate([[0], np.cumsum(ns)]).astype(np.int64)
+        torch = _torch()
+        dev = meshes[0].device
+        self._dev = torch.empty(self.table_bytes + 256, dtype=torch.uint8, device=dev)
+        off = (-self._dev.data_ptr()) % 256
+        _check(L.efie_batch_upload(h, ctypes.c_void_p(self._dev.data_ptr() + off), self.table_bytes, _stream(dev)))
+        self._ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=dev)
+        self._ws_ptr = ctypes.c_void_p(self._ws.data_ptr() + (-self._ws.data_ptr()) % 256)
+        self.device = dev
+
+    def assemble(self, k, eta: float = ETA0, dtype=C64, out=None):
+        """Concatenated Z of every mesh (flat complex tensor of z_elems)."""
+        torch = _torch()
+        code, tdt = _cdtype(dtype)
+        ks = np.ascontiguousarray(np.broadcast_to(np.asarray(k, dtype=np.float64), (len(self.meshes),)))
+        Z = out if out is not None else torch.empty(self.z_elems, dtype=tdt, device=self.device)
+        _check(lib().efie_batch_assemble(self._h, ks.ctypes.data, float(eta), code, _ptr(Z), self._ws_ptr,
+                                         self.ws_bytes, _stream(self.device)))
+        return Z
+
+    def z_of(self, Zcat, i):
+        n = self.meshes[i].n
+        return Zcat[self.zoff[i]:self.zoff[i] + n * n].view(n, n)
+
+    def solve(self, Zcat, Vcat, tol=1e-6, maxit=2000, out=None):
+        torch = _torch()
+        code, _ = _cdtype(Zcat.dtype)
+        J = out if out is not None else torch.empty(self.v_elems, dtype=torch.complex128, device=self.device)
+        opts = _SolveOpts(COCG, int(maxit), float(tol), 1, 1e-3)
+        st = (_RhsStats * len(self.meshes))()
+        rc = lib().efie_batch_solve(self._h, _ptr(Zcat), code, _ptr(Vcat), _ptr(J), ctypes.byref(opts), st,
+                                    self._ws_ptr, self.ws_bytes, _stream(self.device))
+        _check(rc, allow_not_converged=True)
+        return J, SolveStats(
+            iters=np.array([s.iters for s in st]), status=np.array([s.status for s in st]),
+            relres_recur=np.array([s.relres_recur for s in st]), relres_true=np.array([s.relres_true for s in st]),
+            code=rc,
+        )
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.efie_batch_destroy(h)
+            self._h = None

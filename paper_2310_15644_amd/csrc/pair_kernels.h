@@ -1,0 +1,339 @@
+// Device code shared by the single-mesh and the batched assembly kernels:
+// Green's function evaluations, the far-pair moment accumulation, the
+// closed-form potentials of the singular part and the near-pair blocks.
+// (Formulas and readings are described in assemble.hip.)
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "efie_internal.h"
+
+namespace efie {
+
+constexpr double PI = 3.14159265358979323846;
+constexpr int FAR_BLOCK = 256;
+
+struct Scale {          // Z contribution = A * T_A + P * T_Phi (complex), or parts mode
+    double ar, ai, pr, pi;
+};
+
+template <typename R>
+struct Tables {
+    const R *qx, *qy, *qz, *qw, *vx, *vy, *vz, *cf, *dv;
+};
+
+// ------------------------------------------------------------------ helpers
+template <typename R>
+__device__ __forceinline__ void atomic_add_c(void* Z, size_t idx, R re, R im);
+
+template <>
+__device__ __forceinline__ void atomic_add_c<double>(void* Z, size_t idx, double re, double im) {
+    double* z = static_cast<double*>(Z) + 2 * idx;
+    atomicAdd(z, re);
+    atomicAdd(z + 1, im);
+}
+template <>
+__device__ __forceinline__ void atomic_add_c<float>(void* Z, size_t idx, float re, float im) {
+    float* z = static_cast<float*>(Z) + 2 * idx;
+    atomicAdd(z, re);
+    atomicAdd(z + 1, im);
+}
+
+// exp(-j k R) / R for k = kr + j ki.  FP64: library sincos/exp.
+__device__ __forceinline__ void green_far(double kr, double ki, bool ck, double R2, double& gr, double& gi) {
+    double rinv = rsqrt(R2);
+    double R = R2 * rinv;
+    double s, c;
+    sincos(kr * R, &s, &c);
+    double e = ck ? exp(ki * R) * rinv : rinv;
+    gr = c * e;
+    gi = -s * e;
+}
+// FP32: the phase is passed in revolutions (k / 2 pi) and evaluated with the
+// hardware sine/cosine, whose input is in revolutions (valid for |x| < 256).
+__device__ __forceinline__ void green_far(float krev, float ki, bool ck, float R2, float& gr, float& gi) {
+    float rinv = __builtin_amdgcn_rsqf(R2);
+    float R = R2 * rinv;
+    float x = krev * R;
+    float s = __builtin_amdgcn_sinf(x);
+    float c = __builtin_amdgcn_cosf(x);
+    float e = ck ? __expf(ki * R) * rinv : rinv;
+    gr = c * e;
+    gi = -s * e;
+}
+
+// -------------------------------------------------------- far-pair kernel
+// The pair (p, q) of one mesh; contributions are added to Z (and Z2 in parts mode).
+template <typename R, bool CK, bool PARTS>
+__device__ __forceinline__ void far_pair(const DevMesh& m, const Tables<R>& tb, int p, int q, R kphase, R ki,
+                                         const Scale& sc, void* Z, void* Z2) {
+    const int T = m.T;
+    if ((m.near_mask[size_t(p) * m.nqb + (q >> 6)] >> (q & 63)) & 1ull) return;
+
+    const R Dx = R(m.cx[p] - m.cx[q]);
+    const R Dy = R(m.cy[p] - m.cy[q]);
+    const R Dz = R(m.cz[p] - m.cz[q]);
+    R sx[NQ], sy[NQ], sz[NQ], sw[NQ];
+#pragma unroll
+    for (int b = 0; b < NQ; ++b) {
+        sx[b] = tb.qx[b * T + q];
+        sy[b] = tb.qy[b * T + q];
+        sz[b] = tb.qz[b * T + q];
+        sw[b] = tb.qw[b * T + q];
+    }
+    R m0r = 0, m0i = 0;
+    R mdr[3] = {0, 0, 0}, mdi[3] = {0, 0, 0};     // sum W W G d_a
+    R mpr[3] = {0, 0, 0}, mpi[3] = {0, 0, 0};     // sum W W G d'_b
+    R mmr = 0, mmi = 0;                             // sum W W G d_a . d'_b
+#pragma unroll 1
+    for (int a = 0; a < NQ; ++a) {
+        const R ax = tb.qx[a * T + p], ay = tb.qy[a * T + p], az = tb.qz[a * T + p], wa = tb.qw[a * T + p];
+        const R ox = Dx + ax, oy = Dy + ay, oz = Dz + az;
+        R s0r = 0, s0i = 0, s1r[3] = {0, 0, 0}, s1i[3] = {0, 0, 0};
+#pragma unroll
+        for (int b = 0; b < NQ; ++b) {
+            const R dx = ox - sx[b], dy = oy - sy[b], dz = oz - sz[b];
+            const R R2 = dx * dx + dy * dy + dz * dz;
+            R gr, gi;
+            green_far(kphase, ki, CK, R2, gr, gi);
+            gr *= sw[b];
+            gi *= sw[b];
+            s0r += gr;
+            s0i += gi;
+            s1r[0] += gr * sx[b]; s1i[0] += gi * sx[b];
+            s1r[1] += gr * sy[b]; s1i[1] += gi * sy[b];
+            s1r[2] += gr * sz[b]; s1i[2] += gi * sz[b];
+        }
+        m0r += wa * s0r;
+        m0i += wa * s0i;
+        const R av[3] = {ax, ay, az};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            mdr[d] += wa * av[d] * s0r;
+            mdi[d] += wa * av[d] * s0i;
+            mpr[d] += wa * s1r[d];
+            mpi[d] += wa * s1i[d];
+        }
+        mmr += wa * (ax * s1r[0] + ay * s1r[1] + az * s1r[2]);
+        mmi += wa * (ax * s1i[0] + ay * s1i[1] + az * s1i[2]);
+    }
+    // nine half-function products and their contributions to Z
+    R uq[3][3], cq[3], gq[3];
+    int nq[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        uq[j][0] = tb.vx[j * T + q];
+        uq[j][1] = tb.vy[j * T + q];
+        uq[j][2] = tb.vz[j * T + q];
+        cq[j] = tb.cf[j * T + q];
+        gq[j] = tb.dv[j * T + q];
+        nq[j] = m.te[j * T + q];
+    }
+    const size_t N = size_t(m.N);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const R ux = tb.vx[i * T + p], uy = tb.vy[i * T + p], uz = tb.vz[i * T + p];
+        const R ci = tb.cf[i * T + p], gi_ = tb.dv[i * T + p];
+        const size_t row = size_t(m.te[i * T + p]) * N;
+        // terms that depend on i only
+        const R bir = mmr - (ux * mpr[0] + uy * mpr[1] + uz * mpr[2]);
+        const R bii = mmi - (ux * mpi[0] + uy * mpi[1] + uz * mpi[2]);
+        const R er[3] = {mdr[0] - ux * m0r, mdr[1] - uy * m0r, mdr[2] - uz * m0r};
+        const R ei[3] = {mdi[0] - ux * m0i, mdi[1] - uy * m0i, mdi[2] - uz * m0i};
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            // Mdd' - u_i.Md' - u'_j.(Md - u_i M0)
+            const R tar = ci * cq[j] * (bir - (uq[j][0] * er[0] + uq[j][1] * er[1] + uq[j][2] * er[2]));
+            const R tai = ci * cq[j] * (bii - (uq[j][0] * ei[0] + uq[j][1] * ei[1] + uq[j][2] * ei[2]));
+            const R gg = gi_ * gq[j];
+            const R tpr = gg * m0r, tpi = gg * m0i;
+            const size_t idx = row + size_t(nq[j]);
+            if (PARTS) {
+                atomic_add_c<R>(Z, idx, tar * R(sc.ar), tai * R(sc.ar));
+                atomic_add_c<R>(Z2, idx, tpr * R(sc.ar), tpi * R(sc.ar));
+            } else {
+                const R zr = R(sc.ar) * tar - R(sc.ai) * tai + R(sc.pr) * tpr - R(sc.pi) * tpi;
+                const R zi = R(sc.ar) * tai + R(sc.ai) * tar + R(sc.pr) * tpi + R(sc.pi) * tpr;
+                atomic_add_c<R>(Z, idx, zr, zi);
+            }
+        }
+    }
+}
+
+// ----------------------------------------------------- closed-form potentials
+// I0 = int 1/|r - r'| dS' and I1 = int (rho' - rho)/|r - r'| dS' over the flat
+// triangle with vertex positions u[0..2] (counter-clockwise about the unit normal
+// n); r, u relative to the same origin.  Edge-sum formulas of Wilton et al. 1984.
+static __device__ void potentials(const double r[3], const double u[3][3], const double n[3], double h, double& I0,
+                           double I1[3]) {
+    const double d = n[0] * (r[0] - u[0][0]) + n[1] * (r[1] - u[0][1]) + n[2] * (r[2] - u[0][2]);
+    const double ad = fabs(d);
+    const double rho[3] = {r[0] - d * n[0], r[1] - d * n[1], r[2] - d * n[2]};
+    I0 = 0.0;
+    I1[0] = I1[1] = I1[2] = 0.0;
+#pragma unroll 1
+    for (int e = 0; e < 3; ++e) {
+        const double* rm = u[e];
+        const double* rp = u[(e + 1) % 3];
+        double lt[3] = {rp[0] - rm[0], rp[1] - rm[1], rp[2] - rm[2]};
+        const double len = sqrt(lt[0] * lt[0] + lt[1] * lt[1] + lt[2] * lt[2]);
+        lt[0] /= len; lt[1] /= len; lt[2] /= len;
+        const double uu[3] = {lt[1] * n[2] - lt[2] * n[1], lt[2] * n[0] - lt[0] * n[2], lt[0] * n[1] - lt[1] * n[0]};
+        const double lp = (rp[0] - rho[0]) * lt[0] + (rp[1] - rho[1]) * lt[1] + (rp[2] - rho[2]) * lt[2];
+        const double lm = (rm[0] - rho[0]) * lt[0] + (rm[1] - rho[1]) * lt[1] + (rm[2] - rho[2]) * lt[2];
+        const double P0 = (rm[0] - rho[0]) * uu[0] + (rm[1] - rho[1]) * uu[1] + (rm[2] - rho[2]) * uu[2];
+        const double R02 = P0 * P0 + d * d;
+        const double Rp = sqrt((r[0] - rp[0]) * (r[0] - rp[0]) + (r[1] - rp[1]) * (r[1] - rp[1]) +
+                               (r[2] - rp[2]) * (r[2] - rp[2]));
+        const double Rm = sqrt((r[0] - rm[0]) * (r[0] - rm[0]) + (r[1] - rm[1]) * (r[1] - rm[1]) +
+                               (r[2] - rm[2]) * (r[2] - rm[2]));
+        double lg = 0.0, at = 0.0;
+        if (sqrt(R02) >= 1e-12 * h) {
+            // R + l, written as R0^2 / (R - l) for l < 0 (same value, no cancellation)
+            const double fp = lp >= 0.0 ? Rp + lp : R02 / (Rp - lp);
+            const double fm = lm >= 0.0 ? Rm + lm : R02 / (Rm - lm);
+            lg = log(fp / fm);
+            at = atan(P0 * lp / (R02 + ad * Rp)) - atan(P0 * lm / (R02 + ad * Rm));
+        }
+        I0 += P0 * lg - ad * at;
+        const double c1 = 0.5 * (R02 * lg + lp * Rp - lm * Rm);
+        I1[0] += c1 * uu[0];
+        I1[1] += c1 * uu[1];
+        I1[2] += c1 * uu[2];
+    }
+}
+
+// Singular block X(i,j) = sum_a W_a f_i(r_a) . int_s f_j(r')/R dS' and the scalar
+// s0 = sum_a W_a int_s 1/R dS', for test triangle t and source triangle s.
+static __device__ void singular_block(const DevMesh& m, int t, int s, double X[3][3], double& s0) {
+    const int T = m.T;
+    // everything relative to the source centroid
+    const double D[3] = {m.cx[t] - m.cx[s], m.cy[t] - m.cy[s], m.cz[t] - m.cz[s]};
+    double us[3][3], ut[3][3];
+    for (int k = 0; k < 3; ++k) {
+        us[k][0] = m.vx[k * T + s]; us[k][1] = m.vy[k * T + s]; us[k][2] = m.vz[k * T + s];
+        ut[k][0] = m.vx[k * T + t]; ut[k][1] = m.vy[k * T + t]; ut[k][2] = m.vz[k * T + t];
+    }
+    const double n[3] = {m.nx[s], m.ny[s], m.nz[s]};
+    const double h = m.hm[s];
+    double cs[3], ct[3];
+    for (int k = 0; k < 3; ++k) {
+        cs[k] = m.cf[k * T + s];
+        ct[k] = m.cf[k * T + t];
+    }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) X[i][j] = 0.0;
+    s0 = 0.0;
+#pragma unroll 1
+    for (int a = 0; a < NQ; ++a) {
+        const double da[3] = {m.qx[a * T + t], m.qy[a * T + t], m.qz[a * T + t]};
+        const double wa = m.qw[a * T + t];
+        const double r[3] = {D[0] + da[0], D[1] + da[1], D[2] + da[2]};
+        double I0, I1[3];
+        potentials(r, us, n, h, I0, I1);
+        const double dd = n[0] * (r[0] - us[0][0]) + n[1] * (r[1] - us[0][1]) + n[2] * (r[2] - us[0][2]);
+        const double rho[3] = {r[0] - dd * n[0], r[1] - dd * n[1], r[2] - dd * n[2]};
+        s0 += wa * I0;
+        double inner[3][3];
+        for (int j = 0; j < 3; ++j)
+            for (int x = 0; x < 3; ++x) inner[j][x] = cs[j] * (I1[x] + (rho[x] - us[j][x]) * I0);
+        for (int i = 0; i < 3; ++i) {
+            const double f[3] = {ct[i] * (da[0] - ut[i][0]), ct[i] * (da[1] - ut[i][1]), ct[i] * (da[2] - ut[i][2])};
+            for (int j = 0; j < 3; ++j)
+                X[i][j] += wa * (f[0] * inner[j][0] + f[1] * inner[j][1] + f[2] * inner[j][2]);
+        }
+    }
+}
+
+// (exp(-jkR) - 1)/R with exp(z) - 1 = expm1(x) cos y - 2 sin^2(y/2) + j exp(x) sin y,
+// z = -j k R = x + j y; value -j k at R = 0.
+static __device__ __forceinline__ void green_smooth(double kr, double ki, double R2, double& gr, double& gi) {
+    if (R2 == 0.0) {
+        gr = ki;
+        gi = -kr;
+        return;
+    }
+    const double R = sqrt(R2);
+    const double x = ki * R, y = -kr * R;
+    double s2, c2;
+    sincos(0.5 * y, &s2, &c2);
+    const double siny = 2.0 * s2 * c2;
+    const double cosy = 1.0 - 2.0 * s2 * s2;
+    const double nr = expm1(x) * cosy - 2.0 * s2 * s2;
+    const double ni = exp(x) * siny;
+    gr = nr / R;
+    gi = ni / R;
+}
+
+template <typename ZT, bool PARTS>
+__device__ void near_pair(const DevMesh& m, int e, double kr, double ki, const Scale& sc, void* Z, void* Z2) {
+    const int p = m.near_p[e], q = m.near_q[e];
+    const int T = m.T;
+    // smooth part, 7 x 7 rule, offsets from the centroids as in the far kernel
+    const double D[3] = {m.cx[p] - m.cx[q], m.cy[p] - m.cy[q], m.cz[p] - m.cz[q]};
+    double m0r = 0, m0i = 0, mdr[3] = {0, 0, 0}, mdi[3] = {0, 0, 0}, mpr[3] = {0, 0, 0}, mpi[3] = {0, 0, 0};
+    double mmr = 0, mmi = 0;
+#pragma unroll 1
+    for (int a = 0; a < NQ; ++a) {
+        const double ax = m.qx[a * T + p], ay = m.qy[a * T + p], az = m.qz[a * T + p], wa = m.qw[a * T + p];
+        double s0r = 0, s0i = 0, s1r[3] = {0, 0, 0}, s1i[3] = {0, 0, 0};
+#pragma unroll 1
+        for (int b = 0; b < NQ; ++b) {
+            const double bx = m.qx[b * T + q], by = m.qy[b * T + q], bz = m.qz[b * T + q], wb = m.qw[b * T + q];
+            const double dx = D[0] + ax - bx, dy = D[1] + ay - by, dz = D[2] + az - bz;
+            double gr, gi;
+            green_smooth(kr, ki, dx * dx + dy * dy + dz * dz, gr, gi);
+            gr *= wb;
+            gi *= wb;
+            s0r += gr; s0i += gi;
+            s1r[0] += gr * bx; s1i[0] += gi * bx;
+            s1r[1] += gr * by; s1i[1] += gi * by;
+            s1r[2] += gr * bz; s1i[2] += gi * bz;
+        }
+        m0r += wa * s0r;
+        m0i += wa * s0i;
+        const double av[3] = {ax, ay, az};
+        for (int d = 0; d < 3; ++d) {
+            mdr[d] += wa * av[d] * s0r; mdi[d] += wa * av[d] * s0i;
+            mpr[d] += wa * s1r[d]; mpi[d] += wa * s1i[d];
+        }
+        mmr += wa * (ax * s1r[0] + ay * s1r[1] + az * s1r[2]);
+        mmi += wa * (ax * s1i[0] + ay * s1i[1] + az * s1i[2]);
+    }
+    // singular part, symmetrised
+    double Xpq[3][3], Xqp[3][3], s0pq, s0qp;
+    singular_block(m, p, q, Xpq, s0pq);
+    singular_block(m, q, p, Xqp, s0qp);
+    const double s0 = 0.5 * (s0pq + s0qp);
+    const size_t N = size_t(m.N);
+    for (int i = 0; i < 3; ++i) {
+        const double ux = m.vx[i * T + p], uy = m.vy[i * T + p], uz = m.vz[i * T + p];
+        const double ci = m.cf[i * T + p], gi_ = m.dv[i * T + p];
+        const size_t row = size_t(m.te[i * T + p]) * N;
+        for (int j = 0; j < 3; ++j) {
+            const double vx = m.vx[j * T + q], vy = m.vy[j * T + q], vz = m.vz[j * T + q];
+            const double cj = m.cf[j * T + q], gj = m.dv[j * T + q];
+            const double br = mmr - (ux * mpr[0] + uy * mpr[1] + uz * mpr[2]) -
+                              (vx * (mdr[0] - ux * m0r) + vy * (mdr[1] - uy * m0r) + vz * (mdr[2] - uz * m0r));
+            const double bi = mmi - (ux * mpi[0] + uy * mpi[1] + uz * mpi[2]) -
+                              (vx * (mdi[0] - ux * m0i) + vy * (mdi[1] - uy * m0i) + vz * (mdi[2] - uz * m0i));
+            const double tar = ci * cj * br + 0.5 * (Xpq[i][j] + Xqp[j][i]);
+            const double tai = ci * cj * bi;
+            const double gg = gi_ * gj;
+            const double tpr = gg * (m0r + s0), tpi = gg * m0i;
+            const size_t idx = row + size_t(m.te[j * T + q]);
+            if (PARTS) {
+                atomic_add_c<ZT>(Z, idx, ZT(tar * sc.ar), ZT(tai * sc.ar));
+                atomic_add_c<ZT>(Z2, idx, ZT(tpr * sc.ar), ZT(tpi * sc.ar));
+            } else {
+                const double zr = sc.ar * tar - sc.ai * tai + sc.pr * tpr - sc.pi * tpi;
+                const double zi = sc.ar * tai + sc.ai * tar + sc.pr * tpi + sc.pi * tpr;
+                atomic_add_c<ZT>(Z, idx, ZT(zr), ZT(zi));
+            }
+        }
+    }
+}
+
+}  // namespace efie
