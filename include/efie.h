@@ -148,6 +148,44 @@ int efie_farfield(efie_mesh mesh, double k, double eta, const void* J, int64_t n
                   const double* dirs, int64_t ndir, void* F, void* ws, size_t ws_bytes,
                   hipStream_t stream);
 
+/*
+ * Adjoint source of the far field: G[s][n] = sum_{d,c} W[s][d][c] R_dc,n with
+ * R_dc,n = -(j k eta/4 pi) e_c(rhat_d) . int f_n exp(j k rhat_d . r') dS', the
+ * matrix that maps a current to its far field (F = R J).  With W = conj(F) this
+ * is dJ/dJ^T of J = sum |F|^2, the right-hand side of the adjoint solve
+ * Z lambda = G (Z = Z^T).
+ *   W dev (nrhs, ndir, 2) complex128;  dirs dev (ndir, 3);  G dev (nrhs, N)
+ *   complex128;  ws as for efie_farfield (same size).
+ */
+int efie_farfield_adjoint(efie_mesh mesh, double k, double eta, const void* W, int64_t nrhs,
+                          const double* dirs, int64_t ndir, void* G, void* ws, size_t ws_bytes,
+                          hipStream_t stream);
+
+/* -------------------------------------------------------- vertex gradient */
+
+/*
+ * Gradient with respect to the vertex positions of an objective J(F) of the far
+ * field F = R(x) J of the solution of Z(x) J = V(x), for one right-hand side
+ * (plane wave khat, pol, e0) -- the shape-derivative use of the discretised
+ * operator (the EFIE of Sec. II with the matrices of Sec. III as functions of
+ * the mesh vertices x).  Given J, the adjoint lambda (Z lambda = R^T W) and
+ * W = dJ/dF (W = conj(F) for J = sum |F|^2), it returns
+ *   dxyz = 2 Re[ W^T (dR/dx) J + lambda^T (dV/dx) - lambda^T (dZ/dx) J ].
+ * Z is the k-real operator of efie_assemble (same quadrature, near rule frozen
+ * at the mesh's current classification, singular parts symmetrised).  Far pairs
+ * are differentiated analytically, near pairs by forward-mode dual numbers
+ * through the smooth part and the closed-form singular integrals.  FP64.
+ *   J, lambda dev (N) complex128;  W dev (ndir, 2) complex128;  dirs dev
+ *   (ndir, 3);  khat, pol host 3 doubles;  dxyz dev (nv, 3) doubles
+ *   (overwritten);  ws dev, efie_vertex_grad_workspace_size bytes (T x 9
+ *   doubles).  Asynchronous on stream.
+ */
+int efie_vertex_grad_workspace_size(efie_mesh mesh, size_t* bytes);
+int efie_vertex_grad(efie_mesh mesh, double k, double eta, const void* J, const void* lambda,
+                     const void* W, const double* dirs, int64_t ndir, const double* khat,
+                     const double* pol, double e0, double* dxyz, void* ws, size_t ws_bytes,
+                     hipStream_t stream);
+
 /* ----------------------------------------------------------- Z . X products */
 
 /*
@@ -303,10 +341,13 @@ int efie_batch_solve(efie_batch b, const void* Zcat, int dtype, const void* Vcat
  * enabled, every launch of the timed kernels is bracketed by two events on its
  * stream.  Kernel ids: 0 far-pair assembly, 1 near-pair assembly, 2 complex64
  * matrix-core GEMM, 3 GEMV, 4 FP64 GEMM, 5 Krylov vector kernels, 6 excitation,
- * 7 far field.  efie_prof_read waits for the recorded events and returns the
+ * 7 far field, 8 / 9 / 10 vertex gradient far pairs / near pairs / per-triangle
+ * excitation and radiation terms.  efie_prof_read waits for the recorded events and returns the
  * launch count, summed milliseconds and summed algorithmic work (real flops for
- * the GEMMs, 8 M n n per complex product; Z bytes read for the GEMVs; 0 where
- * not defined) since the last efie_prof_reset.  total_work may be NULL.
+ * the GEMMs, 8 M n n per complex product; Z bytes read for the GEMVs; triangle
+ * pairs for the gradient pair kernels and triangles for its per-triangle
+ * kernel; 0 where not defined) since the last efie_prof_reset.  total_work may
+ * be NULL.
  */
 int efie_prof_enable(int on);
 int efie_prof_reset(void);

@@ -44,9 +44,10 @@ EXPORTED = [
     "efie_calderon_create", "efie_calderon_destroy", "efie_calderon_sizes", "efie_calderon_upload",
     "efie_calderon_host_matrices", "efie_calderon_assemble", "efie_solve_precond_workspace_size", "efie_solve_precond",
     "efie_batch_create", "efie_batch_destroy", "efie_batch_sizes", "efie_batch_upload", "efie_batch_assemble",
-    "efie_batch_solve",
+    "efie_batch_solve", "efie_farfield_adjoint", "efie_vertex_grad_workspace_size", "efie_vertex_grad",
 ]
-PROF_IDS = {"far": 0, "near": 1, "mfma": 2, "gemv": 3, "zgemm": 4, "krylov": 5, "excite": 6, "farfield": 7}
+PROF_IDS = {"far": 0, "near": 1, "mfma": 2, "gemv": 3, "zgemm": 4, "krylov": 5, "excite": 6, "farfield": 7, "grad_far": 8,
+            "grad_near": 9, "grad_tri": 10}
 
 
 class EfieError(RuntimeError):
@@ -121,6 +122,10 @@ def lib():
         "efie_batch_assemble": ([P, P, D, ctypes.c_int, P, P, ctypes.c_size_t, P], ctypes.c_int),
         "efie_batch_solve": ([P, P, ctypes.c_int, P, P, ctypes.POINTER(_SolveOpts), ctypes.POINTER(_RhsStats), P,
                               ctypes.c_size_t, P], ctypes.c_int),
+        "efie_farfield_adjoint": ([P, D, D, P, I64, P, I64, P, P, ctypes.c_size_t, P], ctypes.c_int),
+        "efie_vertex_grad_workspace_size": ([P, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "efie_vertex_grad": ([P, D, D, P, P, P, P, I64, ctypes.POINTER(D), ctypes.POINTER(D), D, P, P,
+                              ctypes.c_size_t, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -158,6 +163,9 @@ def _require_cuda(t, name):
         raise ValueError(f"{name} must be a device tensor")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
+    if t.is_complex() and (t.is_conj() or t.is_neg()):
+        # a lazy conjugate/negative view: its memory holds the unconjugated values
+        raise ValueError(f"{name} is a lazy conj/neg view: call .resolve_conj() / .resolve_neg() first")
 
 
 def ktilde(k: float, a: float = 1.0) -> complex:
@@ -280,6 +288,50 @@ def farfield(mesh: Mesh, k: float, J, dirs, eta: float = ETA0):
     _check(lib().efie_farfield(mesh._h, float(k), float(eta), _ptr(J), J.shape[0], _ptr(d), nd, _ptr(F), _ptr(ws),
                                nb.value, _stream(dev)))
     return F
+
+
+def farfield_adjoint(mesh: Mesh, k: float, W, dirs, eta: float = ETA0):
+    """G (nrhs, N) complex128 with G[s] = R^T W[s], R the far-field matrix (F = R J).
+
+    W (nrhs, ndir, 2) complex128 on the device (W = conj(F) for J = sum |F|^2)."""
+    torch = _torch()
+    dev = mesh.device
+    d = _dev_vectors(dirs, dev)
+    nd = d.shape[0]
+    W = W.reshape(-1, nd, 2)
+    _require_cuda(W, "W")
+    if W.dtype != torch.complex128:
+        raise ValueError("W must be complex128")
+    nb = ctypes.c_size_t()
+    _check(lib().efie_farfield_workspace_size(mesh._h, nd, ctypes.byref(nb)))
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+    G = torch.empty((W.shape[0], mesh.n), dtype=torch.complex128, device=dev)
+    _check(lib().efie_farfield_adjoint(mesh._h, float(k), float(eta), _ptr(W), W.shape[0], _ptr(d), nd, _ptr(G),
+                                       _ptr(ws), nb.value, _stream(dev)))
+    return G
+
+
+def vertex_grad(mesh: Mesh, k: float, J, lam, W, dirs, khat, pol, e0: float = 1.0, eta: float = ETA0):
+    """(nv, 3) float64: 2 Re[W^T dR/dx J + lam^T dV/dx - lam^T dZ/dx J] for one right-hand side."""
+    torch = _torch()
+    dev = mesh.device
+    d = _dev_vectors(dirs, dev)
+    nd = d.shape[0]
+    for t, name in ((J, "J"), (lam, "lambda"), (W, "W")):
+        _require_cuda(t, name)
+        if t.dtype != torch.complex128:
+            raise ValueError(f"{name} must be complex128")
+    if J.numel() != mesh.n or lam.numel() != mesh.n or W.numel() != 2 * nd:
+        raise ValueError("J, lambda must hold N values and W 2 ndir values")
+    kh = (ctypes.c_double * 3)(*np.asarray(khat, dtype=np.float64).reshape(3))
+    po = (ctypes.c_double * 3)(*np.asarray(pol, dtype=np.float64).reshape(3))
+    nb = ctypes.c_size_t()
+    _check(lib().efie_vertex_grad_workspace_size(mesh._h, ctypes.byref(nb)))
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+    out = torch.empty((mesh.nv, 3), dtype=torch.float64, device=dev)
+    _check(lib().efie_vertex_grad(mesh._h, float(k), float(eta), _ptr(J), _ptr(lam), _ptr(W), _ptr(d), nd, kh, po,
+                                  float(e0), _ptr(out), _ptr(ws), nb.value, _stream(dev)))
+    return out
 
 
 def zx(Z, X):

@@ -31,20 +31,6 @@ inline V3 sub(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
 inline V3 cross(V3 a, V3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
 inline double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
 
-void radon7(double bary[7][3], double w[7]) {
-    const double s = std::sqrt(15.0);
-    const double a1 = (9.0 - 2.0 * s) / 21.0, b1 = (6.0 + s) / 21.0;
-    const double a2 = (9.0 + 2.0 * s) / 21.0, b2 = (6.0 - s) / 21.0;
-    const double w1 = (155.0 + s) / 1200.0, w2 = (155.0 - s) / 1200.0;
-    const double B[7][3] = {{1.0 / 3.0, 1.0 / 3.0, 1.0 / 3.0}, {a1, b1, b1}, {b1, a1, b1}, {b1, b1, a1},
-                            {a2, b2, b2}, {b2, a2, b2}, {b2, b2, a2}};
-    const double W[7] = {9.0 / 40.0, w1, w1, w1, w2, w2, w2};
-    for (int i = 0; i < 7; ++i) {
-        w[i] = W[i];
-        for (int j = 0; j < 3; ++j) bary[i][j] = B[i][j];
-    }
-}
-
 // value of the RWG half-function carried by local edge i of triangle t at r
 V3 rwg_value(const efie_mesh_s& m, int64_t t, int i, V3 r) {
     const int32_t e = m.tri_edge[3 * t + i];

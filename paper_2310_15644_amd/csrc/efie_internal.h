@@ -71,6 +71,7 @@ struct DevMesh {
     const float *qx32, *qy32, *qz32, *qw32, *vx32, *vy32, *vz32, *cf32, *dv32;
     // topology
     const int32_t* te;                   // RWG index of local edge i [3][T]
+    const int32_t* tv;                   // vertex id of local vertex i [3][T]
     const uint64_t* near_mask;           // [T][nqb], bit q%64 of word q/64: pair (p,q) is near
     const int32_t *near_p, *near_q;      // ordered near pairs (incl. p == q)
     const int32_t *et;                   // RWG -> (T+, T-) [2][N]
@@ -105,6 +106,9 @@ void build_mesh(efie_mesh_s& m, const double* xyz, int64_t nv, const int32_t* tr
                 double near_factor);
 void pack_tables(efie_mesh_s& m);            // fills host_blob, offs, returns size via host_blob.size()
 void bind_tables(efie_mesh_s& m, void* dev); // sets m.dm pointers into dev
+// Radon's 7-point degree-5 triangle rule: barycentric points and weights (sum 1),
+// in the order the quadrature tables use.
+void radon7(double bary[7][3], double w[7]);
 }  // namespace efie
 
 namespace efie {
@@ -113,7 +117,8 @@ namespace efie {
 // (enabled through efie_prof_enable).  Each begin/end pair brackets one launch
 // on the launch stream.
 enum ProfId { PROF_FAR = 0, PROF_NEAR = 1, PROF_MFMA = 2, PROF_GEMV = 3, PROF_ZGEMM = 4, PROF_KRYLOV = 5,
-              PROF_EXCITE = 6, PROF_FARFIELD = 7, PROF_COUNT = 8 };
+              PROF_EXCITE = 6, PROF_FARFIELD = 7, PROF_GRAD_FAR = 8, PROF_GRAD_NEAR = 9, PROF_GRAD_TRI = 10,
+              PROF_COUNT = 11 };
 void prof_begin(int id, hipStream_t s);
 void prof_end(int id, hipStream_t s, double work = 0.0);   // work: algorithmic flops or bytes of the launch
 }  // namespace efie

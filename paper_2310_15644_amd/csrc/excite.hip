@@ -86,6 +86,23 @@ __global__ __launch_bounds__(256) void radiation_kernel(DevMesh m, double k, dou
     Rm[size_t(2 * d + 1) * N + n] = make_double2(cc * ap_i, -cc * ap_r);
 }
 
+// adjoint source of the far field: G[s][n] = sum_e W[s][e] R[e][n], R the
+// radiation matrix (2 ndir x N, row 2d + c) that forms F = J R^T
+__global__ __launch_bounds__(256) void radiation_adjoint_kernel(const double2* __restrict__ Rm,
+                                                                const double2* __restrict__ W, int ne, int N, int nrhs,
+                                                                double2* __restrict__ G) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = blockIdx.y;
+    if (n >= N || s >= nrhs) return;
+    double gr = 0.0, gi = 0.0;
+    for (int e = 0; e < ne; ++e) {
+        const double2 r = Rm[size_t(e) * N + n], w = W[size_t(s) * ne + e];
+        gr += r.x * w.x - r.y * w.y;
+        gi += r.x * w.y + r.y * w.x;
+    }
+    G[size_t(s) * N + n] = make_double2(gr, gi);
+}
+
 }  // namespace efie
 
 extern "C" int efie_excite_planewave(efie_mesh mesh, double k, const double* khat, const double* pol, int64_t nrhs,
@@ -129,6 +146,28 @@ extern "C" int efie_farfield(efie_mesh mesh, double k, double eta, const void* J
         // F[s][e] = sum_n J[s][n] R[e][n]
         efie::zgemm_nt(J, EFIE_C128, ws, EFIE_C128, F, EFIE_C128, int(nrhs), int(2 * ndir), N, N, N, int(2 * ndir),
                        1.0, 0.0, false, stream);
+        EFIE_HIP_CHECK(hipGetLastError());
+        return int(EFIE_OK);
+    });
+}
+
+extern "C" int efie_farfield_adjoint(efie_mesh mesh, double k, double eta, const void* W, int64_t nrhs,
+                                     const double* dirs, int64_t ndir, void* G, void* ws, size_t ws_bytes,
+                                     hipStream_t stream) {
+    return efie::guarded([&]() {
+        EFIE_REQUIRE(mesh && W && dirs && G && ws, EFIE_ERR_ARG, "farfield_adjoint: null argument");
+        EFIE_REQUIRE(mesh->dev != nullptr, EFIE_ERR_STATE, "farfield_adjoint: mesh tables not uploaded");
+        EFIE_REQUIRE(nrhs >= 1 && ndir >= 1 && nrhs < 65536 && 2 * ndir * mesh->N < (int64_t(1) << 31),
+                     EFIE_ERR_ARG, "farfield_adjoint: bad sizes");
+        EFIE_REQUIRE(ws_bytes >= size_t(2 * ndir) * size_t(mesh->N) * 16, EFIE_ERR_ARG,
+                     "farfield_adjoint: workspace too small");
+        const int N = int(mesh->N);
+        const int tot = int(ndir) * N;
+        hipLaunchKernelGGL(efie::radiation_kernel, dim3((tot + 255) / 256), dim3(256), 0, stream, mesh->dm, k, eta,
+                           dirs, int(ndir), static_cast<double2*>(ws));
+        hipLaunchKernelGGL(efie::radiation_adjoint_kernel, dim3((N + 255) / 256, unsigned(nrhs)), dim3(256), 0, stream,
+                           static_cast<const double2*>(ws), static_cast<const double2*>(W), int(2 * ndir), N, int(nrhs),
+                           static_cast<double2*>(G));
         EFIE_HIP_CHECK(hipGetLastError());
         return int(EFIE_OK);
     });

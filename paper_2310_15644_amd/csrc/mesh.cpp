@@ -25,6 +25,8 @@ inline V3 cross(V3 a, V3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b
 inline double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
 inline double norm(V3 a) { return std::sqrt(dot(a, a)); }
 
+}  // namespace
+
 // Radon's 7-point degree-5 rule on a triangle (Stroud T2:5-1), barycentric.
 void radon7(double bary[7][3], double w[7]) {
     const double s = std::sqrt(15.0);
@@ -41,7 +43,6 @@ void radon7(double bary[7][3], double w[7]) {
     }
 }
 
-}  // namespace
 
 void build_mesh(efie_mesh_s& m, const double* xyz, int64_t nv, const int32_t* tri, int64_t nt,
                 double near_factor) {
@@ -214,7 +215,7 @@ void pack_tables(efie_mesh_s& m) {
     radon7(bary, w);
     std::vector<double> cx(T), cy(T), cz(T), qx(7 * T), qy(7 * T), qz(7 * T), qw(7 * T);
     std::vector<double> vx(3 * T), vy(3 * T), vz(3 * T), cf(3 * T), dv(3 * T), nx(T), ny(T), nz(T), hm(T);
-    std::vector<int32_t> te(3 * T), et(2 * N), el(2 * N);
+    std::vector<int32_t> te(3 * T), tv(3 * T), et(2 * N), el(2 * N);
     for (int64_t t = 0; t < T; ++t) {
         // vertex offsets from the centroid; points r = sum_k lambda_k p_k become
         // sum_k lambda_k (p_k - c) since the barycentric weights sum to one
@@ -240,6 +241,7 @@ void pack_tables(efie_mesh_s& m) {
             cf[i * T + t] = s * m.edge_len[e] / (2.0 * m.area[t]);
             dv[i * T + t] = s * m.edge_len[e] / m.area[t];
             te[i * T + t] = e;
+            tv[i * T + t] = m.tri[3 * t + i];
         }
         nx[t] = m.normal[3 * t];
         ny[t] = m.normal[3 * t + 1];
@@ -264,6 +266,7 @@ void pack_tables(efie_mesh_s& m) {
     pk.add(f32(qx)); pk.add(f32(qy)); pk.add(f32(qz)); pk.add(f32(qw));
     pk.add(f32(vx)); pk.add(f32(vy)); pk.add(f32(vz)); pk.add(f32(cf)); pk.add(f32(dv));
     pk.add(te);
+    pk.add(tv);
     pk.add(m.near_mask);
     pk.add(m.near_p); pk.add(m.near_q);
     pk.add(et); pk.add(el);
@@ -291,6 +294,7 @@ void bind_tables(efie_mesh_s& m, void* dev) {
     d.qx32 = F(); d.qy32 = F(); d.qz32 = F(); d.qw32 = F();
     d.vx32 = F(); d.vy32 = F(); d.vz32 = F(); d.cf32 = F(); d.dv32 = F();
     d.te = I();
+    d.tv = I();
     d.near_mask = reinterpret_cast<const uint64_t*>(b + o[i++]);
     d.near_p = I(); d.near_q = I();
     d.et = I(); d.el = I();
