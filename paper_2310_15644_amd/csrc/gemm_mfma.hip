@@ -26,30 +26,43 @@ namespace efie {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 // ACC64: the FP32 matrix-core partial sums are flushed into FP64 accumulators after
-// every FLUSH complex elements of K, and the result is written as complex128 to
-// the rows Y[yrow[r]] (the Krylov vectors); this bounds the FP32 accumulation
-// error to short partial sums.  Otherwise complex64 is written to Y[r].
+// every K chunk, and the result is written as complex128 to the rows Y[yrow[r]]
+// (the Krylov vectors); this bounds the FP32 accumulation error to short partial
+// sums.  Otherwise complex64 is written to Y[r].
+//
+// Pipeline: two LDS buffers; the global loads of chunk c+1 (16-byte loads into
+// registers when n is even, 8-byte otherwise) are in flight while chunk c is
+// multiplied, then written to the other buffer; one barrier per chunk.
+// Block order: workgroups are dealt to the 8 XCDs round-robin by id, so the ids
+// are remapped to give each XCD a contiguous run of tiles, walking the
+// right-hand-side tiles of one Z column strip first: the blocks that read the
+// same strip of Z share one XCD's L2 and run at about the same time.
 template <int BM, int BN, int KC, bool ACC64>
 __global__ __launch_bounds__(256) void cgemm_mfma_kernel(const float2* __restrict__ X, const float2* __restrict__ Z,
                                                          void* __restrict__ Yv, int M, int n,
                                                          const int* __restrict__ yrow) {
-    constexpr int FLUSH = 1;           // chunks of KC between FP64 flushes (1: every chunk; cheapest and most accurate)
-    constexpr int AP = 2 * KC + 4;     // floats per LDS row of the X tile (padded)
+    constexpr int AP = 2 * KC + 4;     // floats per LDS row of the X tile (padded, 16-byte rows)
     constexpr int BNC = BN / 2;        // unknowns per tile
-    constexpr int BP = KC + 1;         // float2 per LDS row of the Z tile (padded)
+    constexpr int BP = KC + 2;         // float2 per LDS row of the Z tile (padded, 16-byte rows)
     constexpr int WM = BM / 2, WN = BN / 2;   // wavefront tile
     constexpr int TM = WM / 16, TN = WN / 16;
-    __shared__ float As[BM * AP];
-    __shared__ float2 Bs[BNC * BP];
+    constexpr int KV = KC / 2;         // two-element (16-byte) groups per row of a chunk
+    constexpr int NA = BM * KV / 256, NB = BNC * KV / 256;
+    static_assert(BM * KV % 256 == 0 && BNC * KV % 256 == 0, "tile not divisible by the block");
+    __shared__ float As[2][BM * AP];
+    __shared__ float2 Bs[2][BNC * BP];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
     const int wm = w >> 1, wn = w & 1;
-    // XCD-friendly order: consecutive block ids walk the right-hand-side tiles of
-    // one column tile first, so blocks sharing a Z tile run close together.
     const int nbm = (M + BM - 1) / BM;
-    const int bm = blockIdx.x % nbm, bn = blockIdx.x / nbm;
+    const int nblk = int(gridDim.x);
+    const int xcd = int(blockIdx.x) & 7, idx = int(blockIdx.x) >> 3;
+    const int per = nblk >> 3, rem = nblk & 7;
+    const int logical = xcd * per + min(xcd, rem) + idx;
+    const int bm = logical % nbm, bn = logical / nbm;
     const int s0 = bm * BM, i0 = bn * BNC;
+    const bool vec = (n & 1) == 0 && ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Z)) & 15) == 0;
 
     floatx4 acc[TM][TN];
     double acc64[ACC64 ? TM : 1][ACC64 ? TN : 1][4];
@@ -65,36 +78,64 @@ __global__ __launch_bounds__(256) void cgemm_mfma_kernel(const float2* __restric
 #pragma unroll
                 for (int r = 0; r < 4; ++r) acc64[a][b][r] = 0.0;
     }
-    int chunk = 0;
+
+    float4 ra[NA], rb[NB];
+    auto load2 = [&](const float2* base, int row, int nrows, int j) -> float4 {
+        // elements j and j+1 of row `row` (zero outside the matrix)
+        if (row >= nrows || j >= n) return make_float4(0.f, 0.f, 0.f, 0.f);
+        const float2* p = base + size_t(row) * n + j;
+        if (vec) return *reinterpret_cast<const float4*>(p);
+        const float2 u = p[0];
+        const float2 v = j + 1 < n ? p[1] : make_float2(0.f, 0.f);
+        return make_float4(u.x, u.y, v.x, v.y);
+    };
+    auto gload = [&](int j0) {
+#pragma unroll
+        for (int q = 0; q < NA; ++q) {
+            const int e = tid + 256 * q, r = e / KV, c = e % KV;
+            ra[q] = load2(X, s0 + r, M, j0 + 2 * c);
+        }
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int e = tid + 256 * q, r = e / KV, c = e % KV;
+            rb[q] = load2(Z, i0 + r, n, j0 + 2 * c);
+        }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < NA; ++q) {
+            const int e = tid + 256 * q, r = e / KV, c = e % KV;
+            *reinterpret_cast<float4*>(&As[buf][r * AP + 4 * c]) = ra[q];
+        }
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int e = tid + 256 * q, r = e / KV, c = e % KV;
+            *reinterpret_cast<float4*>(&Bs[buf][r * BP + 2 * c]) = rb[q];
+        }
+    };
 
     const int kq = lane >> 4;          // 0..3: real k within an instruction
     const int l16 = lane & 15;
-    for (int j0 = 0; j0 < n; j0 += KC) {
-        // stage X[s0 .. s0+BM)[j0 .. j0+KC) and Z[i0 .. i0+BNC)[j0 .. j0+KC)
-        for (int e = tid; e < BM * KC; e += 256) {
-            const int r = e / KC, jj = e % KC;
-            const int s = s0 + r, j = j0 + jj;
-            float2 v = (s < M && j < n) ? X[size_t(s) * n + j] : make_float2(0.f, 0.f);
-            As[r * AP + 2 * jj] = v.x;
-            As[r * AP + 2 * jj + 1] = v.y;
-        }
-        for (int e = tid; e < BNC * KC; e += 256) {
-            const int r = e / KC, jj = e % KC;
-            const int i = i0 + r, j = j0 + jj;
-            Bs[r * BP + jj] = (i < n && j < n) ? Z[size_t(i) * n + j] : make_float2(0.f, 0.f);
-        }
-        __syncthreads();
+    const int nch = (n + KC - 1) / KC;
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int ch = 0; ch < nch; ++ch) {
+        const int buf = ch & 1;
+        if (ch + 1 < nch) gload((ch + 1) * KC);
+        const float* A_ = As[buf];
+        const float2* B_ = Bs[buf];
 #pragma unroll
         for (int st = 0; st < KC / 2; ++st) {
             const int kf = 4 * st + kq;        // real k index inside the chunk
             const int jj = kf >> 1, t = kf & 1;
             float av[TM], bv[TN];
 #pragma unroll
-            for (int a = 0; a < TM; ++a) av[a] = As[(wm * WM + a * 16 + l16) * AP + kf];
+            for (int a = 0; a < TM; ++a) av[a] = A_[(wm * WM + a * 16 + l16) * AP + kf];
 #pragma unroll
             for (int b = 0; b < TN; ++b) {
                 const int col = wn * WN + b * 16 + l16;     // real column inside the tile
-                const float2 z = Bs[(col >> 1) * BP + jj];
+                const float2 z = B_[(col >> 1) * BP + jj];
                 const int u = col & 1;
                 bv[b] = u == 0 ? (t == 0 ? z.x : -z.y) : (t == 0 ? z.y : z.x);
             }
@@ -104,9 +145,7 @@ __global__ __launch_bounds__(256) void cgemm_mfma_kernel(const float2* __restric
                 for (int b = 0; b < TN; ++b)
                     acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
         }
-        __syncthreads();
-        if (ACC64 && (++chunk == FLUSH || j0 + KC >= n)) {
-            chunk = 0;
+        if (ACC64) {
 #pragma unroll
             for (int a = 0; a < (ACC64 ? TM : 1); ++a)
 #pragma unroll
@@ -116,6 +155,8 @@ __global__ __launch_bounds__(256) void cgemm_mfma_kernel(const float2* __restric
                     acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
                 }
         }
+        if (ch + 1 < nch) lstore(buf ^ 1);
+        __syncthreads();
     }
 #pragma unroll
     for (int a = 0; a < TM; ++a)

@@ -150,6 +150,25 @@ def test_zx_random(dev, n, nrhs, dt):
     assert err <= tol, err
 
 
+@pytest.mark.parametrize("n", [480, 481])
+def test_zx_c64_unaligned_operands(dev, n):
+    """Matrix-core product with X and Z starting 8 bytes past a 16-byte boundary
+    (views into larger buffers): the 16-byte load path must not be taken."""
+    rng = np.random.default_rng(n)
+    nrhs = 40
+    Z = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    X = rng.standard_normal((nrhs, n)) + 1j * rng.standard_normal((nrhs, n))
+    zb = torch.zeros(n * n + 1, dtype=torch.complex64, device=dev)
+    xb = torch.zeros(nrhs * n + 1, dtype=torch.complex64, device=dev)
+    zb[1:] = torch.as_tensor(Z.reshape(-1), dtype=torch.complex64, device=dev)
+    xb[1:] = torch.as_tensor(X.reshape(-1), dtype=torch.complex64, device=dev)
+    Zt, Xt = zb[1:].view(n, n), xb[1:].view(nrhs, n)
+    assert Zt.data_ptr() % 16 == 8 and Xt.data_ptr() % 16 == 8
+    Y = P.zx(Zt, Xt).cpu().numpy().astype(np.complex128)
+    ref = Xt.cpu().numpy().astype(np.complex128) @ Zt.cpu().numpy().astype(np.complex128).T
+    assert np.linalg.norm(Y - ref) / np.linalg.norm(ref) <= 2e-6
+
+
 # ---------------------------------------------------------------- solves
 @pytest.fixture(scope="module")
 def l2_system(dev):
