@@ -473,7 +473,8 @@ namespace {
 struct Ws {
     double2 *r, *rt, *u, *p, *q, *v, *w;   // Krylov vectors (S x n each)
     double2 *res, *dlt;                     // outer refinement (CGS, mixed): residual and correction
-    float2 *x32, *y32;                      // complex64 staging of the product input (y32 unused)
+    float2* x32;                            // complex64 staging of the product input
+    double2* part;                          // partial sums of the K-split product of <= 8 columns
     Col* cols;
     double *nrm, *bnrm;
     int* counters;                          // [0] active, [1] flagged for a true residual, [2] count
@@ -509,7 +510,8 @@ size_t layout(int64_t n, int64_t S, int dtype, Ws* ws, char* base) {
     w.r = (double2*)take(vec); w.rt = (double2*)take(vec); w.u = (double2*)take(vec); w.p = (double2*)take(vec);
     w.q = (double2*)take(vec); w.v = (double2*)take(vec); w.w = (double2*)take(vec);
     w.res = (double2*)take(outer); w.dlt = (double2*)take(outer);
-    w.x32 = (float2*)take(vec32); w.y32 = (float2*)take(vec32);
+    w.x32 = (float2*)take(vec32);
+    w.part = (double2*)take(gemv_multi_part_bytes(int(n)));
     w.cols = (Col*)take(sizeof(Col) * size_t(S));
     w.nrm = (double*)take(sizeof(double) * size_t(S));
     w.bnrm = (double*)take(sizeof(double) * size_t(S));
@@ -528,7 +530,7 @@ void product(const void* Z, int zdt, int n, const double2* X, double2* Y, const 
              const Ws& w, hipStream_t st) {
     if (m <= 0) return;
     if (m <= 8) {
-        gemv_multi(Z, zdt, n, X, idx, m, Y, st);
+        gemv_multi(Z, zdt, n, X, idx, m, Y, st, w.part);
     } else if (zdt == EFIE_C64 && !exact64) {
         gather_cast(X, idx, m, n, w.x32, st);
         cgemm_mfma_acc64(w.x32, Z, Y, idx, m, n, st);

