@@ -397,12 +397,154 @@ void gemv(const void* Z, int zdt, int n, const void* x, int xdt, void* y, int yd
 #undef GEMV_CASE
 }
 
+// ------------------------------------------------- FP64 matrix-core product
+// C[crow[s]][i] = sum_k A[arow[s]][k] B[i][k] (complex128 A and C, complex128 or
+// complex64 B; B square n x n with K = n here) on v_mfma_f64_16x16x4f64, in the
+// real 4M form used by the complex64 kernel: A viewed as reals A[s][2k+t],
+// B built on the fly from the 2 x 2 real blocks of each complex B[i][k], so every
+// complex multiply-add is four real FP64 multiply-adds on the matrix cores.
+// Operand layouts of v_mfma_f64_16x16x4f64: lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; accumulator register r of lane l holds D[l/16 + 4*r][l%16]
+// (rows interleaved, unlike the FP32 16x16x4 form).
+// Tiling as the complex64 kernel: 4 wavefronts (2 x 2), a BM x BN real tile,
+// K chunks of KC complex elements double-buffered in LDS with register prefetch,
+// XCD-aware block order.
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <int BM, int BN, int KC, typename BT>
+__global__ __launch_bounds__(256) void zgemm_mfma_kernel(const double2* __restrict__ A, const BT* __restrict__ B,
+                                                         double2* __restrict__ C, int M, int n, int lda, int ldc,
+                                                         const int* __restrict__ arow, const int* __restrict__ crow) {
+    constexpr int AP = 2 * KC + 2;     // doubles per LDS row of the A tile (16-byte rows)
+    constexpr int BNC = BN / 2;        // complex columns of C per tile
+    constexpr int BP = KC + 1;         // double2 per LDS row of the B tile
+    constexpr int WM = BM / 2, WN = BN / 2;
+    constexpr int TM = WM / 16, TN = WN / 16;
+    constexpr int NA = BM * KC / 256, NB = BNC * KC / 256;
+    static_assert(BM * KC % 256 == 0 && BNC * KC % 256 == 0, "tile not divisible by the block");
+    __shared__ double As[2][BM * AP];
+    __shared__ double2 Bs[2][BNC * BP];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    const int nbm = (M + BM - 1) / BM;
+    const int nblk = int(gridDim.x);
+    const int xcd = int(blockIdx.x) & 7, idx = int(blockIdx.x) >> 3;
+    const int per = nblk >> 3, rem = nblk & 7;
+    const int logical = xcd * per + min(xcd, rem) + idx;
+    const int bm = logical % nbm, bn = logical / nbm;
+    const int s0 = bm * BM, i0 = bn * BNC;
+
+    doublex4 acc[TM][TN];
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) acc[a][b] = doublex4{0.0, 0.0, 0.0, 0.0};
+
+    double2 ra[NA], rb[NB];
+    auto gload = [&](int j0) {
+#pragma unroll
+        for (int q = 0; q < NA; ++q) {
+            const int e = tid + 256 * q, r = e / KC, c = e % KC;
+            const int srow = s0 + r, j = j0 + c;
+            ra[q] = (srow < M && j < n) ? A[size_t(arow ? arow[srow] : srow) * lda + j] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int e = tid + 256 * q, r = e / KC, c = e % KC;
+            const int i = i0 + r, j = j0 + c;
+            rb[q] = (i < n && j < n) ? CT<BT>::ld(B, size_t(i) * n + j) : make_double2(0.0, 0.0);
+        }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < NA; ++q) {
+            const int e = tid + 256 * q, r = e / KC, c = e % KC;
+            *reinterpret_cast<double2*>(&As[buf][r * AP + 2 * c]) = ra[q];
+        }
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int e = tid + 256 * q, r = e / KC, c = e % KC;
+            Bs[buf][r * BP + c] = rb[q];
+        }
+    };
+
+    const int kq = lane >> 4, l16 = lane & 15;
+    const int nch = (n + KC - 1) / KC;
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int ch = 0; ch < nch; ++ch) {
+        const int buf = ch & 1;
+        if (ch + 1 < nch) gload((ch + 1) * KC);
+        const double* A_ = As[buf];
+        const double2* B_ = Bs[buf];
+#pragma unroll
+        for (int st = 0; st < KC / 2; ++st) {
+            const int kf = 4 * st + kq;
+            const int jj = kf >> 1, t = kf & 1;
+            double av[TM], bv[TN];
+#pragma unroll
+            for (int a = 0; a < TM; ++a) av[a] = A_[(wm * WM + a * 16 + l16) * AP + kf];
+#pragma unroll
+            for (int b = 0; b < TN; ++b) {
+                const int col = wn * WN + b * 16 + l16;
+                const double2 z = B_[(col >> 1) * BP + jj];
+                const int u = col & 1;
+                bv[b] = u == 0 ? (t == 0 ? z.x : -z.y) : (t == 0 ? z.y : z.x);
+            }
+#pragma unroll
+            for (int a = 0; a < TM; ++a)
+#pragma unroll
+                for (int b = 0; b < TN; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+        }
+        if (ch + 1 < nch) lstore(buf ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
+            const int col = 2 * i0 + wn * WN + b * 16 + l16;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = s0 + wm * WM + a * 16 + kq + 4 * r;
+                if (row < M && col < 2 * n)
+                    reinterpret_cast<double*>(C)[size_t(crow ? crow[row] : row) * 2 * ldc + col] = acc[a][b][r];
+            }
+        }
+}
+
+template <typename BT>
+static void launch_zgemm_mfma(const double2* A, const BT* B, double2* C, int M, int n, int lda, int ldc,
+                              const int* arow, const int* crow, hipStream_t s) {
+    constexpr int BM = 64, BN = 64, KC = 16;
+    const size_t nblk = size_t((M + BM - 1) / BM) * size_t((n + BN / 2 - 1) / (BN / 2));
+    EFIE_REQUIRE(nblk < (size_t(1) << 31), EFIE_ERR_ARG, "zgemm: problem too large");
+    hipLaunchKernelGGL((zgemm_mfma_kernel<BM, BN, KC, BT>), dim3(unsigned(nblk)), dim3(256), 0, s, A, B, C, M, n, lda,
+                       ldc, arow, crow);
+}
+
 void zgemm_nt(const void* A, int adt, const void* B, int bdt, void* C, int cdt, int M, int Nc, int K, int lda,
               int ldb, int ldc, double alr, double ali, bool accumulate, hipStream_t s, const int* arow,
               const int* crow) {
     dim3 grid((Nc + GT - 1) / GT, (M + GT - 1) / GT), blk(256);
     EFIE_REQUIRE(grid.y <= 65535, EFIE_ERR_ARG, "zgemm: too many rows");
     prof_begin(PROF_ZGEMM, s);
+    // the operator products (B square, K = n, plain product): FP64 matrix cores
+    if (adt == EFIE_C128 && cdt == EFIE_C128 && (bdt == EFIE_C128 || bdt == EFIE_C64) && Nc == K && ldb == K &&
+        alr == 1.0 && ali == 0.0 && !accumulate && M >= 16) {
+        if (bdt == EFIE_C128)
+            launch_zgemm_mfma(static_cast<const double2*>(A), static_cast<const double2*>(B), static_cast<double2*>(C), M,
+                              K, lda, ldc, arow, crow, s);
+        else
+            launch_zgemm_mfma(static_cast<const double2*>(A), static_cast<const float2*>(B), static_cast<double2*>(C), M,
+                              K, lda, ldc, arow, crow, s);
+        prof_end(PROF_ZGEMM, s, 8.0 * M * double(Nc) * K);
+        return;
+    }
 #define ZG(ATy, BTy, CTy2)                                                                                     \
     hipLaunchKernelGGL((zgemm_nt_kernel<ATy, BTy, CTy2>), grid, blk, 0, s, static_cast<const ATy*>(A),         \
                        static_cast<const BTy*>(B), static_cast<CTy2*>(C), M, Nc, K, lda, ldb, ldc, alr, ali, \
