@@ -186,8 +186,8 @@ bool cgemm_mfma_supported(int M, int n) { return M >= 1 && n >= 1; }
 struct Variant {
     int bm, bn, kc;
 };
-static const Variant kVariants[] = {{128, 128, 16}, {128, 64, 16}, {64, 128, 16}, {64, 64, 16}, {256, 64, 16},
-                                    {128, 128, 32}};
+static const Variant kVariants[] = {{128, 128, 16}, {128, 64, 16}, {64, 128, 16}, {64, 64, 16}, {64, 64, 32},
+                                    {128, 128, 32}, {64, 128, 32}, {32, 128, 16}};
 static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 static int g_variant[2] = {0, 1};   // defaults: complex64 output, FP64-flush output
 
@@ -208,8 +208,10 @@ static void launch_variant(int v, const void* X, const void* Z, void* Y, const i
         case 1: launch_v<128, 64, 16, A64>(X, Z, Y, yrow, M, n, s); break;
         case 2: launch_v<64, 128, 16, A64>(X, Z, Y, yrow, M, n, s); break;
         case 3: launch_v<64, 64, 16, A64>(X, Z, Y, yrow, M, n, s); break;
-        case 4: launch_v<256, 64, 16, A64>(X, Z, Y, yrow, M, n, s); break;
-        default: launch_v<128, 128, 32, A64>(X, Z, Y, yrow, M, n, s); break;
+        case 4: launch_v<64, 64, 32, A64>(X, Z, Y, yrow, M, n, s); break;
+        case 5: launch_v<128, 128, 32, A64>(X, Z, Y, yrow, M, n, s); break;
+        case 6: launch_v<64, 128, 32, A64>(X, Z, Y, yrow, M, n, s); break;
+        default: launch_v<32, 128, 16, A64>(X, Z, Y, yrow, M, n, s); break;
     }
 }
 

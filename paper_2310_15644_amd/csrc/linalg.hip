@@ -406,28 +406,32 @@ void gemv(const void* Z, int zdt, int n, const void* x, int xdt, void* y, int yd
 // Operand layouts of v_mfma_f64_16x16x4f64: lane l supplies A[l%16][l/16] and
 // B[l/16][l%16]; accumulator register r of lane l holds D[l/16 + 4*r][l%16]
 // (rows interleaved, unlike the FP32 16x16x4 form).
-// Tiling as the complex64 kernel: 4 wavefronts (2 x 2), a BM x BN real tile,
-// K chunks of KC complex elements double-buffered in LDS with register prefetch,
-// XCD-aware block order.
+// Tiling as the complex64 kernel: 4 wavefronts (WGM along the right-hand sides x
+// 4/WGM along the columns), a BM x BN real tile, K chunks of KC complex elements
+// double-buffered in LDS with register prefetch, XCD-aware block order.  Few
+// right-hand sides (the residual products of a handful of columns) use a 16-row
+// tile with all four wavefronts along the columns, so Z is read once.
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
-template <int BM, int BN, int KC, typename BT>
+template <int BM, int BN, int KC, int WGM, typename BT>
 __global__ __launch_bounds__(256) void zgemm_mfma_kernel(const double2* __restrict__ A, const BT* __restrict__ B,
                                                          double2* __restrict__ C, int M, int n, int lda, int ldc,
                                                          const int* __restrict__ arow, const int* __restrict__ crow) {
     constexpr int AP = 2 * KC + 2;     // doubles per LDS row of the A tile (16-byte rows)
     constexpr int BNC = BN / 2;        // complex columns of C per tile
     constexpr int BP = KC + 1;         // double2 per LDS row of the B tile
-    constexpr int WM = BM / 2, WN = BN / 2;
+    constexpr int WGN = 4 / WGM;
+    constexpr int WM = BM / WGM, WN = BN / WGN;
     constexpr int TM = WM / 16, TN = WN / 16;
     constexpr int NA = BM * KC / 256, NB = BNC * KC / 256;
+    static_assert(WGM * WGN == 4 && TM >= 1 && TN >= 1, "bad wavefront arrangement");
     static_assert(BM * KC % 256 == 0 && BNC * KC % 256 == 0, "tile not divisible by the block");
     __shared__ double As[2][BM * AP];
     __shared__ double2 Bs[2][BNC * BP];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
-    const int wm = w >> 1, wn = w & 1;
+    const int wm = w / WGN, wn = w % WGN;
     const int nbm = (M + BM - 1) / BM;
     const int nblk = int(gridDim.x);
     const int xcd = int(blockIdx.x) & 7, idx = int(blockIdx.x) >> 3;
@@ -442,7 +446,8 @@ __global__ __launch_bounds__(256) void zgemm_mfma_kernel(const double2* __restri
 #pragma unroll
         for (int b = 0; b < TN; ++b) acc[a][b] = doublex4{0.0, 0.0, 0.0, 0.0};
 
-    double2 ra[NA], rb[NB];
+    double2 ra[NA];
+    BT rb[NB];   // raw storage type: converted when written to LDS, so the loads stay in flight
     auto gload = [&](int j0) {
 #pragma unroll
         for (int q = 0; q < NA; ++q) {
@@ -454,7 +459,7 @@ __global__ __launch_bounds__(256) void zgemm_mfma_kernel(const double2* __restri
         for (int q = 0; q < NB; ++q) {
             const int e = tid + 256 * q, r = e / KC, c = e % KC;
             const int i = i0 + r, j = j0 + c;
-            rb[q] = (i < n && j < n) ? CT<BT>::ld(B, size_t(i) * n + j) : make_double2(0.0, 0.0);
+            rb[q] = (i < n && j < n) ? B[size_t(i) * n + j] : BT{0, 0};
         }
     };
     auto lstore = [&](int buf) {
@@ -466,7 +471,7 @@ __global__ __launch_bounds__(256) void zgemm_mfma_kernel(const double2* __restri
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
             const int e = tid + 256 * q, r = e / KC, c = e % KC;
-            Bs[buf][r * BP + c] = rb[q];
+            Bs[buf][r * BP + c] = to_d2(rb[q]);
         }
     };
 
@@ -517,14 +522,24 @@ __global__ __launch_bounds__(256) void zgemm_mfma_kernel(const double2* __restri
         }
 }
 
+template <int BM, int BN, int KC, int WGM, typename BT>
+static void launch_zgemm_tile(const double2* A, const BT* B, double2* C, int M, int n, int lda, int ldc,
+                              const int* arow, const int* crow, hipStream_t s) {
+    const size_t nblk = size_t((M + BM - 1) / BM) * size_t((n + BN / 2 - 1) / (BN / 2));
+    EFIE_REQUIRE(nblk < (size_t(1) << 31), EFIE_ERR_ARG, "zgemm: problem too large");
+    hipLaunchKernelGGL((zgemm_mfma_kernel<BM, BN, KC, WGM, BT>), dim3(unsigned(nblk)), dim3(256), 0, s, A, B, C, M, n,
+                       lda, ldc, arow, crow);
+}
+
 template <typename BT>
 static void launch_zgemm_mfma(const double2* A, const BT* B, double2* C, int M, int n, int lda, int ldc,
                               const int* arow, const int* crow, hipStream_t s) {
-    constexpr int BM = 64, BN = 64, KC = 16;
-    const size_t nblk = size_t((M + BM - 1) / BM) * size_t((n + BN / 2 - 1) / (BN / 2));
-    EFIE_REQUIRE(nblk < (size_t(1) << 31), EFIE_ERR_ARG, "zgemm: problem too large");
-    hipLaunchKernelGGL((zgemm_mfma_kernel<BM, BN, KC, BT>), dim3(unsigned(nblk)), dim3(256), 0, s, A, B, C, M, n, lda,
-                       ldc, arow, crow);
+    if (M <= 16)
+        launch_zgemm_tile<16, 256, 16, 1>(A, B, C, M, n, lda, ldc, arow, crow, s);
+    else if (M <= 64)
+        launch_zgemm_tile<32, 128, 16, 1>(A, B, C, M, n, lda, ldc, arow, crow, s);
+    else
+        launch_zgemm_tile<64, 64, 16, 2>(A, B, C, M, n, lda, ldc, arow, crow, s);
 }
 
 void zgemm_nt(const void* A, int adt, const void* B, int bdt, void* C, int cdt, int M, int Nc, int K, int lda,
@@ -535,7 +550,7 @@ void zgemm_nt(const void* A, int adt, const void* B, int bdt, void* C, int cdt, 
     prof_begin(PROF_ZGEMM, s);
     // the operator products (B square, K = n, plain product): FP64 matrix cores
     if (adt == EFIE_C128 && cdt == EFIE_C128 && (bdt == EFIE_C128 || bdt == EFIE_C64) && Nc == K && ldb == K &&
-        alr == 1.0 && ali == 0.0 && !accumulate && M >= 16) {
+        alr == 1.0 && ali == 0.0 && !accumulate && M >= 9) {
         if (bdt == EFIE_C128)
             launch_zgemm_mfma(static_cast<const double2*>(A), static_cast<const double2*>(B), static_cast<double2*>(C), M,
                               K, lda, ldc, arow, crow, s);

@@ -131,7 +131,7 @@ def test_farfield_l2(dev):
 
 
 # ------------------------------------------------------------- products
-@pytest.mark.parametrize("n,nrhs", [(481, 1), (481, 3), (480, 64), (257, 130), (9, 2)])
+@pytest.mark.parametrize("n,nrhs", [(481, 1), (481, 3), (480, 64), (257, 130), (9, 2), (481, 12), (257, 40)])
 @pytest.mark.parametrize("dt", ["c128", "c64"])
 def test_zx_random(dev, n, nrhs, dt):
     rng = np.random.default_rng(n + nrhs)
