@@ -91,6 +91,44 @@ def cpu_baseline(level, n_sample_rows, nrhs, k, seconds):
     }
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cgemm_mfma_acc64_l5_k10_512rhs_hbm_traffic.md")
+GEMM_SOURCE = os.path.join(ROOT, "paper_2310_15644_amd", "csrc", "gemm_mfma.hip")
+
+
+def measured_traffic(tiles, n, nrhs):
+    """HBM bytes per launch of the in-solve matrix-core GEMM, from the committed
+    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE per dispatch, each divided
+    by the factor the same counter reads for a plain 1 GiB copy).  None when the
+    summary is for another tile shape or workload, or the GEMM source has changed
+    since the counters were taken."""
+    import hashlib
+
+    if tiles is None or not os.path.exists(TRAFFIC_FILE):
+        return None, None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if line.startswith("- ") and ": " in line:
+            key, val = line[2:].split(": ", 1)
+            kv[key.strip()] = val.strip().strip("`")
+    sha = hashlib.sha256(open(GEMM_SOURCE, "rb").read()).hexdigest()
+    want = f"cgemm_mfma_kernel<{tiles[0]}, {tiles[1]}, {tiles[2]}, true>"
+    if kv.get("gemm_source_sha256") != sha or kv.get("kernel") != want or kv.get("workload") != f"n={n} nrhs={nrhs}":
+        return None, None
+    return float(kv["hbm_bytes_per_launch"]), os.path.relpath(TRAFFIC_FILE, ROOT)
+
+
+def copy_calibration(torch):
+    """A plain elementwise kernel that reads 1 GiB and writes 1 GiB, three times:
+    the reference reading of the HBM byte counters."""
+    log("bench: copy calibration (3 x 1 GiB read + 1 GiB write)")
+    x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.neg(x, out=y)
+    torch.cuda.synchronize()
+    del x, y
+
+
 def bench_ellipsoids(args, P, synth, torch, np, dev):
     """64 seeded ellipsoids (geodesic frequency 6..16, semi-axes U[0.5, 1.5]), k = 2,
     x-polarised plane wave along -z: one persistent assembly launch (complex64, FP32
@@ -164,6 +202,8 @@ def main():
                     help="sphere: the 512-RHS level-5 sphere (default); ellipsoids: 64 uneven ellipsoids")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the run, copy 1 GiB three times with a plain elementwise kernel (for HBM counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -306,9 +346,14 @@ def main():
         "gemm_tiles": None if tuning is None else {"acc32": tuning["tiles"][tuning["acc32"]],
                                                    "acc64": tuning["tiles"][tuning["acc64"]], "ms": tuning["ms"]},
     }
+    tiles_acc64 = None if tuning is None else tuning["tiles"][tuning["acc64"]]
+    out["roofline"]["traffic"], out["roofline"]["traffic_source"] = measured_traffic(
+        tiles_acc64, out["config"]["n_unknowns"], S)
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(args.level, 2048, S, args.k, args.cpu_seconds)
+    if args.copy_calibration:
+        copy_calibration(torch)
     print(json.dumps(out), flush=True)
 
 
