@@ -123,6 +123,19 @@ int efie_mesh_upload(efie_mesh mesh, void* dev, size_t bytes, hipStream_t stream
 int efie_assemble(efie_mesh mesh, double k_re, double k_im, double eta, int dtype,
                   void* Z, void* Z2, int parts, hipStream_t stream);
 
+/*
+ * The same Z as efie_assemble (parts = 0) without atomics: the far-pair values are
+ * written per chunk of test triangles into the caller's workspace and then added
+ * row by row, so the result is deterministic (bit-identical between runs).  Any
+ * ws_bytes >= min_bytes works (chunks of ws_bytes / min_bytes test triangles);
+ * full_bytes (= T x min_bytes) holds all triangles in one chunk.
+ *   min_bytes = 6 N x (16 for EFIE_C128, 8 for EFIE_C64);  ws dev, 16-byte aligned.
+ * Errors: EFIE_ERR_ARG if ws_bytes < min_bytes.
+ */
+int efie_assemble_workspace_size(efie_mesh mesh, int dtype, size_t* min_bytes, size_t* full_bytes);
+int efie_assemble_ws(efie_mesh mesh, double k_re, double k_im, double eta, int dtype, void* Z,
+                     void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* ------------------------------------------------------------ excitation */
 
 /*

@@ -45,6 +45,7 @@ EXPORTED = [
     "efie_calderon_host_matrices", "efie_calderon_assemble", "efie_solve_precond_workspace_size", "efie_solve_precond",
     "efie_batch_create", "efie_batch_destroy", "efie_batch_sizes", "efie_batch_upload", "efie_batch_assemble",
     "efie_batch_solve", "efie_farfield_adjoint", "efie_vertex_grad_workspace_size", "efie_vertex_grad",
+    "efie_assemble_workspace_size", "efie_assemble_ws",
 ]
 PROF_IDS = {"far": 0, "near": 1, "mfma": 2, "gemv": 3, "zgemm": 4, "krylov": 5, "excite": 6, "farfield": 7, "grad_far": 8,
             "grad_near": 9, "grad_tri": 10}
@@ -123,6 +124,9 @@ def lib():
         "efie_batch_solve": ([P, P, ctypes.c_int, P, P, ctypes.POINTER(_SolveOpts), ctypes.POINTER(_RhsStats), P,
                               ctypes.c_size_t, P], ctypes.c_int),
         "efie_farfield_adjoint": ([P, D, D, P, I64, P, I64, P, P, ctypes.c_size_t, P], ctypes.c_int),
+        "efie_assemble_workspace_size": ([P, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t),
+                                          ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "efie_assemble_ws": ([P, D, D, D, ctypes.c_int, P, P, ctypes.c_size_t, P], ctypes.c_int),
         "efie_vertex_grad_workspace_size": ([P, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "efie_vertex_grad": ([P, D, D, P, P, P, P, I64, ctypes.POINTER(D), ctypes.POINTER(D), D, P, P,
                               ctypes.c_size_t, P], ctypes.c_int),
@@ -235,8 +239,16 @@ def _cdtype(dtype):
     raise ValueError(f"bad dtype {dtype}")
 
 
-def assemble(mesh: Mesh, k, eta: float = ETA0, dtype=C128, parts: bool = False, out=None, out2=None):
-    """Dense Z (N, N) on the device; parts=True returns (T_A, T_Phi) instead."""
+ASSEMBLY_WORKSPACE_BYTES = 2 << 30   # default bound of the far-pair workspace (2 GiB)
+
+
+def assemble(mesh: Mesh, k, eta: float = ETA0, dtype=C128, parts: bool = False, out=None, out2=None,
+             atomic: bool = False, workspace_bytes: int | None = None):
+    """Dense Z (N, N) on the device; parts=True returns (T_A, T_Phi) instead.
+
+    By default the far pairs go through the atomic-free two-pass path
+    (efie_assemble_ws) with a workspace of at most `workspace_bytes`
+    (ASSEMBLY_WORKSPACE_BYTES); atomic=True (and parts mode) use efie_assemble."""
     torch = _torch()
     dev = mesh.device
     code, tdt = _cdtype(dtype)
@@ -246,6 +258,16 @@ def assemble(mesh: Mesh, k, eta: float = ETA0, dtype=C128, parts: bool = False, 
     if parts:
         Z2 = out2 if out2 is not None else torch.empty((mesh.n, mesh.n), dtype=tdt, device=dev)
     _require_cuda(Z, "Z")
+    if not parts and not atomic:
+        lo, full = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(lib().efie_assemble_workspace_size(mesh._h, code, ctypes.byref(lo), ctypes.byref(full)))
+        budget = ASSEMBLY_WORKSPACE_BYTES if workspace_bytes is None else int(workspace_bytes)
+        nb = min(full.value, max(lo.value, budget))
+        ws = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
+        off = (-ws.data_ptr()) % 256
+        _check(lib().efie_assemble_ws(mesh._h, k.real, k.imag, float(eta), code, _ptr(Z),
+                                      ctypes.c_void_p(ws.data_ptr() + off), nb, _stream(dev)))
+        return Z
     _check(lib().efie_assemble(mesh._h, k.real, k.imag, float(eta), code, _ptr(Z),
                                _ptr(Z2) if Z2 is not None else None, int(parts), _stream(dev)))
     return (Z, Z2) if parts else Z

@@ -65,13 +65,14 @@ __device__ __forceinline__ void green_far(float krev, float ki, bool ck, float R
 }
 
 // -------------------------------------------------------- far-pair kernel
-// The pair (p, q) of one mesh; contributions are added to Z (and Z2 in parts mode).
-template <typename R, bool CK, bool PARTS>
-__device__ __forceinline__ void far_pair(const DevMesh& m, const Tables<R>& tb, int p, int q, R kphase, R ki,
-                                         const Scale& sc, void* Z, void* Z2) {
+// The pair (p, q) of one mesh (not near): the 7 x 7 Green's function moments and
+// the nine half-function products.  emit(i, j, zr, zi) receives the Z
+// contribution of test edge i of p and source edge j of q (PARTS: zr, zi are the
+// T_A part and emit2 gets the T_Phi part).
+template <typename R, bool CK, bool PARTS, typename Emit, typename Emit2>
+__device__ __forceinline__ void far_pair_emit(const DevMesh& m, const Tables<R>& tb, int p, int q, R kphase, R ki,
+                                              const Scale& sc, Emit emit, Emit2 emit2) {
     const int T = m.T;
-    if ((m.near_mask[size_t(p) * m.nqb + (q >> 6)] >> (q & 63)) & 1ull) return;
-
     const R Dx = R(m.cx[p] - m.cx[q]);
     const R Dy = R(m.cy[p] - m.cy[q]);
     const R Dz = R(m.cz[p] - m.cz[q]);
@@ -119,9 +120,8 @@ __device__ __forceinline__ void far_pair(const DevMesh& m, const Tables<R>& tb, 
         mmr += wa * (ax * s1r[0] + ay * s1r[1] + az * s1r[2]);
         mmi += wa * (ax * s1i[0] + ay * s1i[1] + az * s1i[2]);
     }
-    // nine half-function products and their contributions to Z
+    // nine half-function products
     R uq[3][3], cq[3], gq[3];
-    int nq[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
         uq[j][0] = tb.vx[j * T + q];
@@ -129,14 +129,11 @@ __device__ __forceinline__ void far_pair(const DevMesh& m, const Tables<R>& tb, 
         uq[j][2] = tb.vz[j * T + q];
         cq[j] = tb.cf[j * T + q];
         gq[j] = tb.dv[j * T + q];
-        nq[j] = m.te[j * T + q];
     }
-    const size_t N = size_t(m.N);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         const R ux = tb.vx[i * T + p], uy = tb.vy[i * T + p], uz = tb.vz[i * T + p];
         const R ci = tb.cf[i * T + p], gi_ = tb.dv[i * T + p];
-        const size_t row = size_t(m.te[i * T + p]) * N;
         // terms that depend on i only
         const R bir = mmr - (ux * mpr[0] + uy * mpr[1] + uz * mpr[2]);
         const R bii = mmi - (ux * mpi[0] + uy * mpi[1] + uz * mpi[2]);
@@ -149,17 +146,31 @@ __device__ __forceinline__ void far_pair(const DevMesh& m, const Tables<R>& tb, 
             const R tai = ci * cq[j] * (bii - (uq[j][0] * ei[0] + uq[j][1] * ei[1] + uq[j][2] * ei[2]));
             const R gg = gi_ * gq[j];
             const R tpr = gg * m0r, tpi = gg * m0i;
-            const size_t idx = row + size_t(nq[j]);
             if (PARTS) {
-                atomic_add_c<R>(Z, idx, tar * R(sc.ar), tai * R(sc.ar));
-                atomic_add_c<R>(Z2, idx, tpr * R(sc.ar), tpi * R(sc.ar));
+                emit(i, j, tar * R(sc.ar), tai * R(sc.ar));
+                emit2(i, j, tpr * R(sc.ar), tpi * R(sc.ar));
             } else {
                 const R zr = R(sc.ar) * tar - R(sc.ai) * tai + R(sc.pr) * tpr - R(sc.pi) * tpi;
                 const R zi = R(sc.ar) * tai + R(sc.ai) * tar + R(sc.pr) * tpi + R(sc.pi) * tpr;
-                atomic_add_c<R>(Z, idx, zr, zi);
+                emit(i, j, zr, zi);
             }
         }
     }
+}
+
+// The pair (p, q) added to Z (and Z2 in parts mode) with atomics; near pairs skipped.
+template <typename R, bool CK, bool PARTS>
+__device__ __forceinline__ void far_pair(const DevMesh& m, const Tables<R>& tb, int p, int q, R kphase, R ki,
+                                         const Scale& sc, void* Z, void* Z2) {
+    const int T = m.T;
+    if ((m.near_mask[size_t(p) * m.nqb + (q >> 6)] >> (q & 63)) & 1ull) return;
+    const size_t N = size_t(m.N);
+    auto at = [&](void* dst) {
+        return [=, &m](int i, int j, R re, R im) {
+            atomic_add_c<R>(dst, size_t(m.te[i * T + p]) * N + size_t(m.te[j * T + q]), re, im);
+        };
+    };
+    far_pair_emit<R, CK, PARTS>(m, tb, p, q, kphase, ki, sc, at(Z), at(Z2));
 }
 
 // ----------------------------------------------------- closed-form potentials
@@ -267,8 +278,11 @@ static __device__ __forceinline__ void green_smooth(double kr, double ki, double
     gi = ni / R;
 }
 
-template <typename ZT, bool PARTS>
-__device__ void near_pair(const DevMesh& m, int e, double kr, double ki, const Scale& sc, void* Z, void* Z2) {
+// Near pair e of the ordered list: emit(i, j, zr, zi) receives the FP64 Z
+// contribution of test edge i and source edge j (PARTS: T_A part; emit2: T_Phi).
+template <bool PARTS, typename Emit, typename Emit2>
+__device__ void near_pair_emit(const DevMesh& m, int e, double kr, double ki, const Scale& sc, Emit emit,
+                               Emit2 emit2) {
     const int p = m.near_p[e], q = m.near_q[e];
     const int T = m.T;
     // smooth part, 7 x 7 rule, offsets from the centroids as in the far kernel
@@ -307,11 +321,9 @@ __device__ void near_pair(const DevMesh& m, int e, double kr, double ki, const S
     singular_block(m, p, q, Xpq, s0pq);
     singular_block(m, q, p, Xqp, s0qp);
     const double s0 = 0.5 * (s0pq + s0qp);
-    const size_t N = size_t(m.N);
     for (int i = 0; i < 3; ++i) {
         const double ux = m.vx[i * T + p], uy = m.vy[i * T + p], uz = m.vz[i * T + p];
         const double ci = m.cf[i * T + p], gi_ = m.dv[i * T + p];
-        const size_t row = size_t(m.te[i * T + p]) * N;
         for (int j = 0; j < 3; ++j) {
             const double vx = m.vx[j * T + q], vy = m.vy[j * T + q], vz = m.vz[j * T + q];
             const double cj = m.cf[j * T + q], gj = m.dv[j * T + q];
@@ -323,17 +335,30 @@ __device__ void near_pair(const DevMesh& m, int e, double kr, double ki, const S
             const double tai = ci * cj * bi;
             const double gg = gi_ * gj;
             const double tpr = gg * (m0r + s0), tpi = gg * m0i;
-            const size_t idx = row + size_t(m.te[j * T + q]);
             if (PARTS) {
-                atomic_add_c<ZT>(Z, idx, ZT(tar * sc.ar), ZT(tai * sc.ar));
-                atomic_add_c<ZT>(Z2, idx, ZT(tpr * sc.ar), ZT(tpi * sc.ar));
+                emit(i, j, tar * sc.ar, tai * sc.ar);
+                emit2(i, j, tpr * sc.ar, tpi * sc.ar);
             } else {
                 const double zr = sc.ar * tar - sc.ai * tai + sc.pr * tpr - sc.pi * tpi;
                 const double zi = sc.ar * tai + sc.ai * tar + sc.pr * tpi + sc.pi * tpr;
-                atomic_add_c<ZT>(Z, idx, ZT(zr), ZT(zi));
+                emit(i, j, zr, zi);
             }
         }
     }
+}
+
+// near pair e added to Z (and Z2 in parts mode) with atomics, in ZT precision
+template <typename ZT, bool PARTS>
+__device__ void near_pair(const DevMesh& m, int e, double kr, double ki, const Scale& sc, void* Z, void* Z2) {
+    const int p = m.near_p[e], q = m.near_q[e];
+    const int T = m.T;
+    const size_t N = size_t(m.N);
+    auto at = [&](void* dst) {
+        return [=, &m](int i, int j, double re, double im) {
+            atomic_add_c<ZT>(dst, size_t(m.te[i * T + p]) * N + size_t(m.te[j * T + q]), ZT(re), ZT(im));
+        };
+    };
+    near_pair_emit<PARTS>(m, e, kr, ki, sc, at(Z), at(Z2));
 }
 
 }  // namespace efie

@@ -7,6 +7,7 @@ Tolerances (derived in the design notes):
   solves: ||J - J_LU|| <= 10 tol kappa-bounded, iteration counts within +-2 of the oracle's
   own Krylov on the same operator.
 """
+import ctypes
 import math
 
 import numpy as np
@@ -90,6 +91,40 @@ def test_assemble_near_factor(dev, nf):
     v, f = icosphere(1)
     Zg = P.assemble(gmesh(v, f, dev, nf), 2.0).cpu().numpy()
     assert rel_max(Zg, oefie.assemble(oracle_mesh(1), 2.0, near_factor=nf)) <= 1e-11
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_assemble_two_pass_vs_atomic(dev, dt):
+    """The atomic-free path in many chunks (7 test triangles each, ragged last chunk)
+    against the atomic path, and bit-identical when repeated."""
+    flush(f"assemble two-pass vs atomic {dt}")
+    v, f = icosphere(2)
+    m = gmesh(v, f, dev)
+    code = P.C128 if dt == "c128" else P.C64
+    lo, full = ctypes.c_size_t(), ctypes.c_size_t()
+    assert P.lib().efie_assemble_workspace_size(m._h, code, ctypes.byref(lo), ctypes.byref(full)) == 0
+    assert lo.value == 6 * m.n * (16 if dt == "c128" else 8) and full.value == m.t * lo.value
+    wsb = 7 * lo.value + lo.value // 2
+    Za = P.assemble(m, 2.0, dtype=code, atomic=True).cpu().numpy()
+    Z1 = P.assemble(m, 2.0, dtype=code, workspace_bytes=wsb).cpu().numpy()
+    Z2 = P.assemble(m, 2.0, dtype=code, workspace_bytes=wsb).cpu().numpy()
+    Zf = P.assemble(m, 2.0, dtype=code, workspace_bytes=full.value).cpu().numpy()
+    assert np.array_equal(Z1, Z2)
+    tol = 1e-14 if dt == "c128" else 2e-7
+    assert rel_max(Z1, Za) <= tol and rel_max(Zf, Za) <= tol
+    assert np.abs(Z1 - Z1.T).max() <= tol * np.abs(Z1).max()
+
+
+def test_assemble_ws_too_small(dev):
+    v, f = icosphere(1)
+    m = gmesh(v, f, dev)
+    lo, full = ctypes.c_size_t(), ctypes.c_size_t()
+    assert P.lib().efie_assemble_workspace_size(m._h, P.C128, ctypes.byref(lo), ctypes.byref(full)) == 0
+    Z = torch.empty((m.n, m.n), dtype=torch.complex128, device=dev)
+    ws = torch.empty(lo.value, dtype=torch.uint8, device=dev)
+    rc = P.lib().efie_assemble_ws(m._h, 1.0, 0.0, P.ETA0, P.C128, P._ptr(Z), P._ptr(ws), lo.value - 16,
+                                  P._stream(dev))
+    assert rc == -1 and b"workspace" in P.lib().efie_last_error()
 
 
 @pytest.mark.parametrize("k", [0.1, 5.0])
