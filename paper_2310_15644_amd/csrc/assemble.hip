@@ -39,7 +39,9 @@
 // transposed (q, p) block so that Z = Z^T exactly.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "efie_internal.h"
 #include "pair_kernels.h"
@@ -111,10 +113,11 @@ __global__ __launch_bounds__(FAR_BLOCK) void far_rows_kernel(DevMesh m, Tables<R
 // wrote (one thread per ordered near pair, FP64 arithmetic)
 template <typename R>
 __global__ __launch_bounds__(128) void near_rows_kernel(DevMesh m, double kr, double ki, Scale sc,
-                                                        typename Cplx<R>::T* __restrict__ W, int c0, int c1) {
+                                                        typename Cplx<R>::T* __restrict__ W, int c0, int c1, int e0,
+                                                        int e1) {
     using C2 = typename Cplx<R>::T;
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= m.n_near) return;
+    const int e = e0 + int(blockIdx.x * blockDim.x + threadIdx.x);
+    if (e >= e1) return;
     const int p = m.near_p[e], q = m.near_q[e];
     if (p < c0 || p >= c1) return;
     const int T = m.T;
@@ -143,22 +146,35 @@ __global__ __launch_bounds__(256) void gather_rows_kernel(DevMesh m, const typen
     const int ip = m.el[mm], im = m.el[N + mm];
     const bool in_p = tp >= c0 && tp < c1, in_m = tm >= c0 && tm < c1;
     if (p != tp && in_p) return;          // the T+ block of this chunk owns the row
+    // chunks run in increasing order: a row none of whose triangles lies in an earlier
+    // chunk is written here for the first time (no zero fill, no read of Z)
+    const bool first = tp >= c0 && tm >= c0;
     const C2* wp = in_p ? W + (size_t(tp - c0) * 3 + ip) * 2 * size_t(N) : nullptr;
     const C2* wm = in_m ? W + (size_t(tm - c0) * 3 + im) * 2 * size_t(N) : nullptr;
     C2* zr = Z + size_t(mm) * N;
-    for (int n = threadIdx.x; n < N; n += blockDim.x) {
-        C2 acc = zr[n];
-        if (wp) {
-            const C2 a = wp[2 * n], b = wp[2 * n + 1];
-            acc.x += a.x + b.x;
-            acc.y += a.y + b.y;
+    // U elements per thread per step, all loads issued before the adds
+    constexpr int U = 4;
+    const int step = int(blockDim.x) * U;
+    for (int n0 = threadIdx.x; n0 < N; n0 += step) {
+        C2 acc[U], a[U], b[U], c[U], d[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int n = n0 + u * int(blockDim.x);
+            if (n < N) {
+                acc[u] = first ? C2{0, 0} : zr[n];
+                if (wp) { a[u] = wp[2 * n]; b[u] = wp[2 * n + 1]; }
+                if (wm) { c[u] = wm[2 * n]; d[u] = wm[2 * n + 1]; }
+            }
         }
-        if (wm) {
-            const C2 a = wm[2 * n], b = wm[2 * n + 1];
-            acc.x += a.x + b.x;
-            acc.y += a.y + b.y;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int n = n0 + u * int(blockDim.x);
+            if (n < N) {
+                if (wp) { acc[u].x += a[u].x + b[u].x; acc[u].y += a[u].y + b[u].y; }
+                if (wm) { acc[u].x += c[u].x + d[u].x; acc[u].y += c[u].y + d[u].y; }
+                zr[n] = acc[u];
+            }
         }
-        zr[n] = acc;
     }
 }
 
@@ -207,9 +223,11 @@ void launch_far(const DevMesh& m, double kr, double ki, const Scale& sc, void* Z
 }
 
 // far pairs without atomics, in chunks of test triangles that fit the workspace
+// near_p: host copy of the ordered near list's test triangles (sorted), to launch
+// only the chunk's near pairs
 template <typename R>
 void launch_far_rows(const DevMesh& m, double kr, double ki, const Scale& sc, void* Z, void* ws, size_t ws_bytes,
-                     hipStream_t s) {
+                     const std::vector<int32_t>& near_p, hipStream_t s) {
     using C2 = typename Cplx<R>::T;
     const size_t per_tri = size_t(6) * size_t(m.N) * sizeof(C2);
     const int chunk = int(std::min<size_t>(size_t(m.T), ws_bytes / per_tri));
@@ -229,9 +247,11 @@ void launch_far_rows(const DevMesh& m, double kr, double ki, const Scale& sc, vo
         else
             hipLaunchKernelGGL((far_rows_kernel<R, false>), g1, dim3(FAR_BLOCK), 0, s, m, tables<R>(m), kphase, R(ki),
                                sc, W, c0, nqblk);
-        if (m.n_near)
-            hipLaunchKernelGGL((near_rows_kernel<R>), dim3((m.n_near + 127) / 128), dim3(128), 0, s, m, kr, ki, sc, W,
-                               c0, c1);
+        const int e0 = int(std::lower_bound(near_p.begin(), near_p.end(), c0) - near_p.begin());
+        const int e1 = int(std::lower_bound(near_p.begin(), near_p.end(), c1) - near_p.begin());
+        if (e1 > e0)
+            hipLaunchKernelGGL((near_rows_kernel<R>), dim3((e1 - e0 + 127) / 128), dim3(128), 0, s, m, kr, ki, sc, W,
+                               c0, c1, e0, e1);
         hipLaunchKernelGGL((gather_rows_kernel<R>), dim3(unsigned(3 * np)), dim3(256), 0, s, m, W, c0, c1,
                            static_cast<C2*>(Z));
     }
@@ -251,10 +271,10 @@ void launch_near(const DevMesh& m, double kr, double ki, const Scale& sc, void* 
 
 // ws != nullptr (and not parts): far pairs by the two-pass path in that workspace
 static void assemble_impl(const DevMesh& m, double kr, double ki, double eta, int dtype, void* Z, void* Z2, int parts,
-                          hipStream_t s, void* ws, size_t ws_bytes) {
+                          hipStream_t s, void* ws, size_t ws_bytes, const std::vector<int32_t>* near_p) {
     const size_t N = size_t(m.N);
     const size_t esz = dtype == EFIE_C128 ? 16 : 8;
-    fill_zero_bytes(Z, N * N * esz, s);
+    if (!ws || parts) fill_zero_bytes(Z, N * N * esz, s);   // the two-pass path writes every entry
     if (parts) fill_zero_bytes(Z2, N * N * esz, s);
     Scale sc{};
     if (parts) {
@@ -274,7 +294,7 @@ static void assemble_impl(const DevMesh& m, double kr, double ki, double eta, in
             launch_near<double, true>(m, kr, ki, sc, Z, Z2, s);
         } else {
             if (ws) {
-                launch_far_rows<double>(m, kr, ki, sc, Z, ws, ws_bytes, s);   // near pairs included
+                launch_far_rows<double>(m, kr, ki, sc, Z, ws, ws_bytes, *near_p, s);   // near pairs included
             } else {
                 launch_far<double, false>(m, kr, ki, sc, Z, Z2, s);
                 launch_near<double, false>(m, kr, ki, sc, Z, Z2, s);
@@ -286,7 +306,7 @@ static void assemble_impl(const DevMesh& m, double kr, double ki, double eta, in
             launch_near<float, true>(m, kr, ki, sc, Z, Z2, s);
         } else {
             if (ws) {
-                launch_far_rows<float>(m, kr, ki, sc, Z, ws, ws_bytes, s);    // near pairs included
+                launch_far_rows<float>(m, kr, ki, sc, Z, ws, ws_bytes, *near_p, s);    // near pairs included
             } else {
                 launch_far<float, false>(m, kr, ki, sc, Z, Z2, s);
                 launch_near<float, false>(m, kr, ki, sc, Z, Z2, s);
@@ -298,7 +318,7 @@ static void assemble_impl(const DevMesh& m, double kr, double ki, double eta, in
 
 void assemble_into(const DevMesh& m, double kr, double ki, double eta, int dtype, void* Z, void* Z2, int parts,
                    hipStream_t s) {
-    assemble_impl(m, kr, ki, eta, dtype, Z, Z2, parts, s, nullptr, 0);
+    assemble_impl(m, kr, ki, eta, dtype, Z, Z2, parts, s, nullptr, 0, nullptr);
 }
 
 }  // namespace efie
@@ -339,7 +359,7 @@ extern "C" int efie_assemble_ws(efie_mesh mesh, double k_re, double k_im, double
         EFIE_REQUIRE(std::isfinite(k_re) && std::isfinite(k_im) && k_im <= 0.0 && (k_re != 0.0 || k_im != 0.0),
                      EFIE_ERR_ARG, "assemble_ws: need finite nonzero k with Im k <= 0");
         EFIE_REQUIRE((reinterpret_cast<uintptr_t>(ws) & 15) == 0, EFIE_ERR_ARG, "assemble_ws: workspace not 16-byte aligned");
-        efie::assemble_impl(mesh->dm, k_re, k_im, eta, dtype, Z, nullptr, 0, stream, ws, ws_bytes);
+        efie::assemble_impl(mesh->dm, k_re, k_im, eta, dtype, Z, nullptr, 0, stream, ws, ws_bytes, &mesh->near_p);
         return int(EFIE_OK);
     });
 }
