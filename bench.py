@@ -191,6 +191,97 @@ def bench_ellipsoids(args, P, synth, torch, np, dev):
     print(json.dumps(out), flush=True)
 
 
+def _timed(torch, fn):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t0
+
+
+def bench_calderon(args, P, synth, torch, np, dev):
+    """Level-4 sphere (N = 7680), x-polarised plane wave along -z, k = 0.1 and 5:
+    unpreconditioned CGS against CGS on the Calderon product P Z J = P V with
+    P = T_BC(k~) G_mix^-1 (everything FP64), stopping at a relative (preconditioned)
+    residual of 1e-6; the reported residual is the unpreconditioned true one."""
+    v, f = synth.icosphere(4)
+    m = P.Mesh(v, f).upload(dev)
+    kh, pol = synth.planewave_x_along_minus_z()
+    cal = P.Calderon(m).upload(dev)
+    res = {}
+    for k in (0.1, 5.0):
+        Z, t_asm = _timed(torch, lambda: P.assemble(m, k))
+        V = P.excite_planewave(m, k, kh, pol)
+        (_, st0), t_plain = _timed(torch, lambda: P.solve(Z, V, solver=P.CGS, tol=1e-6, maxit=4000))
+        Pm, t_build = _timed(torch, lambda: cal.assemble(P.ktilde(k)))
+        (_, st1), t_prec = _timed(torch, lambda: P.solve_precond(Z, Pm, V, tol=1e-6, maxit=2000))
+        res[str(k)] = {
+            "ktilde": [P.ktilde(k).real, P.ktilde(k).imag], "assembly_s": round(t_asm, 4),
+            "cgs_iters": int(st0.iters[0]), "cgs_converged": bool(st0.status[0] == 0), "cgs_s": round(t_plain, 4),
+            "cgs_relres_true": float(st0.relres_true[0]),
+            "calderon_build_s": round(t_build, 4), "calderon_cgs_iters": int(st1.iters[0]),
+            "calderon_cgs_s": round(t_prec, 4), "calderon_relres_true": float(st1.relres_true[0]),
+            "gram_relres": cal.gram_relres,
+        }
+        log(f"bench: k={k} {res[str(k)]}")
+        del Z, Pm
+    tot = res["5.0"]["calderon_build_s"] + res["5.0"]["calderon_cgs_s"]
+    out = {
+        "metric": "Calderon-preconditioned CGS vs unpreconditioned CGS: iterations and time-to-solve @ 1e-6",
+        "value": round(tot, 4), "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": round(1e3 * tot, 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "c128", "data": "synthetic",
+        "config": {"workload": "PEC unit sphere icosphere level 4 (N=7680 RWG), x-polarised plane wave along -z, "
+                               "k=0.1 and k=5, FP64; value = Calderon build + solve at k=5",
+                   "n_unknowns": m.n, "n_bary_rwg": cal.n_bary},
+        "results": res,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_mixed_fp64(args, P, synth, torch, np, dev):
+    """Level-5 sphere (N = 30720), k = 10, x-polarised plane wave along -z: the mixed
+    form (complex64 Z, FP32 far pairs, FP32 matrix-core products, FP64 refinement)
+    against the FP64 GPU path on the same input; current difference, RCS difference
+    over the 512 monostatic-grid directions, and both times-to-solve @ 1e-6
+    (assembly + excitation + solve)."""
+    v, f = synth.icosphere(5)
+    m = P.Mesh(v, f).upload(dev)
+    k = 10.0
+    kh, pol = synth.planewave_x_along_minus_z()
+    rhat, _, _, _, _ = synth.monostatic_grid(16, 32)
+
+    def run(dt):
+        Z = P.assemble(m, k, dtype=dt)
+        V = P.excite_planewave(m, k, kh, pol)
+        J, st = P.solve(Z, V, solver=P.COCG, tol=1e-6, maxit=5000, max_refine=8, inner_tol=1e-3)
+        return J, st
+
+    run(P.C64)   # warm-up (library load, first launches)
+    (J32, st32), t32 = _timed(torch, lambda: run(P.C64))
+    (J64, st64), t64 = _timed(torch, lambda: run(P.C128))
+    dj = float(torch.linalg.norm(J32 - J64) / torch.linalg.norm(J64))
+    F32 = P.farfield(m, k, J32, rhat).cpu().numpy()[0]
+    F64 = P.farfield(m, k, J64, rhat).cpu().numpy()[0]
+    r32 = 10 * np.log10(4 * math.pi * np.sum(np.abs(F32) ** 2, axis=1))
+    r64 = 10 * np.log10(4 * math.pi * np.sum(np.abs(F64) ** 2, axis=1))
+    keep = r64 >= r64.max() - 40.0
+    out = {
+        "metric": "mixed precision vs FP64: time-to-solve @ rel.res 1e-6 and solution difference",
+        "value": round(t32, 4), "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": round(1e3 * t32, 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+        "config": {"workload": "PEC unit sphere icosphere level 5 (N=30720 RWG), k=10, x-polarised plane wave "
+                               "along -z; value = mixed-path time-to-solve (assembly + excitation + solve)",
+                   "n_unknowns": m.n},
+        "fp64_time_to_solve_s": round(t64, 4),
+        "mixed_iters": int(st32.iters[0]), "fp64_iters": int(st64.iters[0]),
+        "mixed_relres_true": float(st32.relres_true[0]), "fp64_relres_true": float(st64.relres_true[0]),
+        "current_rel_diff": dj,
+        "rcs_db_max_abs_diff": float(np.abs(r32 - r64).max()),
+        "rcs_db_max_abs_diff_within_40db": float(np.abs(r32 - r64)[keep].max()),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -203,8 +294,9 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--maxit", type=int, default=3000)
     ap.add_argument("--dtype", choices=["c64", "c128"], default="c64")
-    ap.add_argument("--workload", choices=["sphere", "ellipsoids"], default="sphere",
-                    help="sphere: the 512-RHS level-5 sphere (default); ellipsoids: 64 uneven ellipsoids")
+    ap.add_argument("--workload", choices=["sphere", "ellipsoids", "calderon", "mixed-fp64"], default="sphere",
+                    help="sphere: the 512-RHS level-5 sphere (default); ellipsoids: 64 uneven ellipsoids; "
+                         "calderon: level-4 Calderon vs plain CGS; mixed-fp64: level-5 mixed vs FP64 path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -226,6 +318,12 @@ def main():
     dev = torch.device("cuda:0")
     if args.workload == "ellipsoids":
         bench_ellipsoids(args, P, synth, torch, np, dev)
+        return
+    if args.workload == "calderon":
+        bench_calderon(args, P, synth, torch, np, dev)
+        return
+    if args.workload == "mixed-fp64":
+        bench_mixed_fp64(args, P, synth, torch, np, dev)
         return
     v, f = synth.icosphere(args.level)
     m = P.Mesh(v, f).upload(dev)

@@ -295,9 +295,13 @@ int efie_solve(const void* Z, int dtype, int64_t n, const void* V, void* J, int6
  *   the relative residual tol (maxit steps); *relres (host, may be NULL) gets the
  *   worst achieved.  ws: dev workspace of ws_bytes from efie_calderon_sizes
  *   (dominated by T_bary: 16 N_bary^2 bytes).  EFIE_NOT_CONVERGED if tol missed.
- * efie_solve_precond: CGS on P Z J = P V (complex128 Z, FP64 throughout; the loop
- *   tests the preconditioned recurrence residual, stats report the
- *   unpreconditioned true residual ||V - Z J|| / ||V||).
+ * efie_solve_precond: CGS on P Z J = P V (complex128 Z, FP64 throughout).  CGS
+ *   tests the preconditioned recurrence residual; an outer refinement on the
+ *   unpreconditioned FP64 true residual r = V - Z J then solves P Z d = P r for the
+ *   columns still above tol (tolerance scaled by the observed ratio of true to
+ *   preconditioned reduction) and adds d, up to opts->max_refine passes (>= 1).
+ *   A column is EFIE_OK when ||V - Z J|| <= tol ||V||; stats report that residual
+ *   and the CGS iterations summed over the passes.
  */
 typedef struct efie_calderon_s* efie_calderon;
 int efie_calderon_create(efie_mesh mesh, efie_calderon* out);

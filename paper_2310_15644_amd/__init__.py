@@ -565,8 +565,10 @@ class Calderon:
             self._h = None
 
 
-def solve_precond(Z, Pm, V, tol=1e-8, maxit=1000, out=None):
-    """CGS on P Z J = P V (complex128); stats report the unpreconditioned true residual."""
+def solve_precond(Z, Pm, V, tol=1e-8, maxit=1000, max_refine=6, out=None):
+    """CGS on P Z J = P V (complex128) with outer refinement on the unpreconditioned
+    FP64 true residual (up to max_refine passes); stats report that residual and the
+    iterations summed over the passes."""
     torch = _torch()
     _require_cuda(Z, "Z")
     _require_cuda(Pm, "P")
@@ -578,7 +580,7 @@ def solve_precond(Z, Pm, V, tol=1e-8, maxit=1000, out=None):
     _check(lib().efie_solve_precond_workspace_size(n, S, ctypes.byref(nb)))
     ws = torch.empty(nb.value + 256, dtype=torch.uint8, device=Z.device)
     off = (-ws.data_ptr()) % 256
-    opts = _SolveOpts(CGS, int(maxit), float(tol), 1, 1e-3)
+    opts = _SolveOpts(CGS, int(maxit), float(tol), int(max_refine), 1e-3)
     st = (_RhsStats * S)()
     code = lib().efie_solve_precond(_ptr(Z), _ptr(Pm), n, _ptr(V), _ptr(J), S, ctypes.byref(opts), st,
                                     ctypes.c_void_p(ws.data_ptr() + off), nb.value, _stream(Z.device))

@@ -30,6 +30,8 @@
 // loop around inner CGS solves.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -454,6 +456,14 @@ __global__ void axpy_inplace_kernel(double2* x, const double2* d, size_t n) {
     }
 }
 
+// zero column s of r when its true residual already meets tol (||r||^2 <= tol^2 ||b||^2)
+__global__ __launch_bounds__(KB) void zero_done_kernel(double2* r, const double* nrm, const double* bnrm, double tol,
+                                                       int n) {
+    const int s = blockIdx.x;
+    if (!(nrm[s] <= tol * tol * bnrm[s])) return;
+    for (int k = threadIdx.x; k < n; k += KB) r[size_t(s) * n + k] = make_double2(0.0, 0.0);
+}
+
 // flag every active column for a replacement with restart
 __global__ void force_replace_kernel(Col* cols, int S, int* counters) {
     for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < S; s += gridDim.x * blockDim.x)
@@ -742,7 +752,7 @@ extern "C" int efie_solve_precond_workspace_size(int64_t n, int64_t nrhs, size_t
     return efie::guarded([&]() {
         EFIE_REQUIRE(bytes && n >= 1 && nrhs >= 1, EFIE_ERR_ARG, "solve_precond_workspace_size: bad argument");
         const size_t vec = efie::align256(size_t(n) * size_t(nrhs) * 16);
-        *bytes = efie::layout(n, nrhs, EFIE_C128, nullptr, nullptr) + 2 * vec;
+        *bytes = efie::layout(n, nrhs, EFIE_C128, nullptr, nullptr) + 4 * vec;
         return int(EFIE_OK);
     });
 }
@@ -760,37 +770,76 @@ extern "C" int efie_solve_precond(const void* Z, const void* P, int64_t n, const
         EFIE_REQUIRE(opts->maxit >= 1 && opts->tol > 0.0, EFIE_ERR_ARG, "solve_precond: need maxit >= 1 and tol > 0");
         const size_t base = layout(n, nrhs, EFIE_C128, nullptr, nullptr);
         const size_t vec = align256(size_t(n) * size_t(nrhs) * 16);
-        EFIE_REQUIRE(ws_bytes >= base + 2 * vec, EFIE_ERR_ARG, "solve_precond: workspace too small");
+        EFIE_REQUIRE(ws_bytes >= base + 4 * vec, EFIE_ERR_ARG, "solve_precond: workspace too small");
         EFIE_REQUIRE((reinterpret_cast<uintptr_t>(ws) & 255) == 0, EFIE_ERR_ARG, "solve_precond: ws not aligned");
         Ws w;
         layout(n, nrhs, EFIE_C128, &w, static_cast<char*>(ws));
         double2* tmp = reinterpret_cast<double2*>(static_cast<char*>(ws) + base);
         double2* pb = reinterpret_cast<double2*>(static_cast<char*>(ws) + base + vec);
+        double2* rt = reinterpret_cast<double2*>(static_cast<char*>(ws) + base + 2 * vec);   // true residual
+        double2* dl = reinterpret_cast<double2*>(static_cast<char*>(ws) + base + 3 * vec);   // correction
         const int S = int(nrhs), nn = int(n);
         hipLaunchKernelGGL(iota_kernel, dim3((S + 255) / 256), dim3(256), 0, stream, w.idx_all, S);
         const double2* b = static_cast<const double2*>(V);
         double2* x = static_cast<double2*>(J);
-        // right-hand side P V
-        product(P, EFIE_C128, nn, b, pb, w.idx_all, S, true, w, stream);
+        // CGS on P Z J = P V stops on the preconditioned residual; the true residual
+        // V - Z J can be larger by the conditioning of P.  Outer refinement on the
+        // FP64 true residual: solve P Z d = P r for the columns still above tol, with
+        // a tolerance scaled by the observed ratio of true to preconditioned
+        // reduction, and add d, up to max_refine passes.
+        const Op op{Z, EFIE_C128, static_cast<const double2*>(P), tmp};
         std::vector<Col> cols;
-        krylov(Op{Z, EFIE_C128, static_cast<const double2*>(P), tmp}, nn, pb, x, S, EFIE_CGS, opts->tol, opts->maxit,
-               false, w, cols, stream);
-        // unpreconditioned true residual V - Z J
-        true_residual(Z, EFIE_C128, nn, b, x, nullptr, S, w, stream);
-        std::vector<double> h_nrm(S), h_bn(S);
-        EFIE_HIP_CHECK(hipMemcpyAsync(h_nrm.data(), w.nrm, sizeof(double) * S, hipMemcpyDeviceToHost, stream));
-        EFIE_HIP_CHECK(hipMemcpyAsync(h_bn.data(), w.bnrm, sizeof(double) * S, hipMemcpyDeviceToHost, stream));
-        EFIE_HIP_CHECK(hipStreamSynchronize(stream));
+        std::vector<int> iters(S, 0);
+        std::vector<double> recur(S, 0.0), ratio(S, 1.0), rel(S, 0.0), h_nrm(S), h_bn(S);
+        const size_t tot = size_t(nn) * S;
+        const int passes = std::max(1, opts->max_refine);
+        double tau = opts->tol;
+        for (int pass = 0; pass < passes; ++pass) {
+            const double2* rhs = pass == 0 ? b : rt;
+            product(P, EFIE_C128, nn, rhs, pb, w.idx_all, S, true, w, stream);
+            double2* dst = pass == 0 ? x : dl;
+            krylov(op, nn, pb, dst, S, EFIE_CGS, tau, opts->maxit, false, w, cols, stream);
+            if (pass > 0)
+                hipLaunchKernelGGL(axpy_inplace_kernel, dim3(int(std::min<size_t>((tot + 255) / 256, 16384))),
+                                   dim3(256), 0, stream, x, dl, tot);
+            true_residual(Z, EFIE_C128, nn, b, x, rt, S, w, stream);
+            EFIE_HIP_CHECK(hipMemcpyAsync(h_nrm.data(), w.nrm, sizeof(double) * S, hipMemcpyDeviceToHost, stream));
+            EFIE_HIP_CHECK(hipMemcpyAsync(h_bn.data(), w.bnrm, sizeof(double) * S, hipMemcpyDeviceToHost, stream));
+            EFIE_HIP_CHECK(hipStreamSynchronize(stream));
+            double need = 0.5;   // next pass tolerance (relative to its right-hand side)
+            bool done = true;
+            for (int s = 0; s < S; ++s) {
+                iters[s] += cols[s].iters;
+                const double r_in = pass == 0 ? 1.0 : rel[s];   // rhs norm of this pass / ||b||
+                const double now = h_bn[s] > 0 ? std::sqrt(h_nrm[s] / h_bn[s]) : 0.0;
+                const double pre = cols[s].bn2 > 0 ? std::sqrt(cols[s].rn2 / cols[s].bn2) : 0.0;
+                if (r_in > 0 && pre > 0) ratio[s] = std::max(1.0, (now / r_in) / pre);
+                recur[s] = pre;
+                rel[s] = now;
+                if (now > opts->tol) {
+                    done = false;
+                    need = std::min(need, 0.5 * opts->tol / (now * ratio[s]));
+                }
+            }
+            if (verbose())
+                std::fprintf(stderr, "[efie] precond pass %d worst true relres %.3e\n", pass,
+                             *std::max_element(rel.begin(), rel.end())),
+                    std::fflush(stderr);
+            if (done) break;
+            tau = std::max(need, 1e-13);
+            // columns already converged get a zero right-hand side (no further work)
+            hipLaunchKernelGGL(zero_done_kernel, dim3(S), dim3(KB), 0, stream, rt, w.nrm, w.bnrm, opts->tol, nn);
+        }
         int ret = EFIE_OK;
         for (int s = 0; s < S; ++s) {
-            const double rel = h_bn[s] > 0 ? std::sqrt(h_nrm[s] / h_bn[s]) : 0.0;
             int st = cols[s].status;
-            if (!(rel == rel)) st = EFIE_ERR_NAN;
+            if (st >= 0) st = rel[s] <= opts->tol ? EFIE_OK : EFIE_NOT_CONVERGED;
+            if (!(rel[s] == rel[s])) st = EFIE_ERR_NAN;
             if (stats) {
-                stats[s].iters = cols[s].iters;
+                stats[s].iters = iters[s];
                 stats[s].status = st;
-                stats[s].relres_recur = cols[s].bn2 > 0 ? std::sqrt(cols[s].rn2 / cols[s].bn2) : 0.0;
-                stats[s].relres_true = rel;
+                stats[s].relres_recur = recur[s];
+                stats[s].relres_true = rel[s];
             }
             if (st != EFIE_OK) ret = EFIE_NOT_CONVERGED;
         }

@@ -40,12 +40,16 @@ def test_calderon_l1_parity(dev, k):
     Z = P.assemble(m, k)
     kh, pol = synth.planewave_x_along_minus_z()
     V = P.excite_planewave(m, k, kh, pol)
-    J, st = P.solve_precond(Z, Pm, V, tol=1e-10, maxit=200)
+    # one CGS pass (the oracle's CGS has no outer refinement) for the iteration count
+    J, st = P.solve_precond(Z, Pm, V, tol=1e-10, maxit=200, max_refine=1)
     Vo = oefie.excitation(oracle_mesh(1), k, kh, pol)[0]
     Jlu = np.linalg.solve(C.Z, Vo)
     ref = okrylov.cgs(lambda y: C.M @ y, C.rhs(Vo), 1e-10, 200)
     flush(f"  iters gpu {st.iters[0]} oracle {ref[1]} relres_true {st.relres_true[0]:.2e}")
-    assert st.status[0] == 0 and abs(int(st.iters[0]) - ref[1]) <= 2
+    assert abs(int(st.iters[0]) - ref[1]) <= 2
+    # with the outer refinement the unpreconditioned true residual meets tol
+    J, st = P.solve_precond(Z, Pm, V, tol=1e-10, maxit=200)
+    assert st.status[0] == 0 and st.relres_true[0] <= 1e-10
     assert np.linalg.norm(J.cpu().numpy()[0] - Jlu) <= 1e-7 * np.linalg.norm(Jlu)
 
 
@@ -91,9 +95,10 @@ def test_calderon_l4_iteration_counts(dev, k):
     Jq, stq = P.solve(Z, V, solver=P.COCG, tol=1e-6, maxit=4000)
     flush(f"  L4 k={k}: calderon CGS {stc.iters[0]} (true relres {stc.relres_true[0]:.2e}), "
           f"plain CGS {stp.iters[0]} (status {stp.status[0]}), plain COCG {stq.iters[0]}")
-    # the loop stops on the preconditioned residual (1e-6); the unpreconditioned one
-    # differs by the conditioning of P (measured 8.7e-5 at k = 0.1, 1.2e-6 at k = 5)
-    assert stc.status[0] == 0 and stc.relres_true[0] <= 1e-3
+    # CGS stops on the preconditioned residual, which differs from the true one by
+    # the conditioning of P (8.7e-5 vs 1e-6 at k = 0.1 after the first pass); the
+    # outer refinement brings the true residual below 1e-6
+    assert stc.status[0] == 0 and stc.relres_true[0] <= 1e-6
     assert stc.iters[0] < min(stp.iters[0], stq.iters[0])
     err = float((Jc - Jq).norm() / Jq.norm())
     flush(f"  current difference Calderon vs plain COCG: {err:.2e}")
