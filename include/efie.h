@@ -286,16 +286,27 @@ int efie_solve(const void* Z, int dtype, int64_t n, const void* V, void* J, int6
  * P Z J = P V with P = T_BC(k~) G_mix^-1 (dense, complex128, N x N).
  *
  * efie_calderon_create: host refinement, R and G_mix for a mesh (kept alive by
- *   the caller; at most 65535 barycentric RWGs).  efie_calderon_upload: like
- *   efie_mesh_upload, table_bytes from efie_calderon_sizes.
+ *   the caller).  efie_calderon_upload: like efie_mesh_upload, table_bytes from
+ *   efie_calderon_sizes.
  * efie_calderon_host_matrices: dense host copies (R: N_bary x N, G: N x N, either
  *   may be NULL) for inspection of small meshes.
  * efie_calderon_assemble: P into dev P (N x N complex128); optionally T_BC into
- *   dev Tbc_out (may be NULL).  Rows of P solve G_mix^T p = T_BC row by CGNR to
- *   the relative residual tol (maxit steps); *relres (host, may be NULL) gets the
- *   worst achieved.  ws: dev workspace of ws_bytes from efie_calderon_sizes
- *   (dominated by T_bary: 16 N_bary^2 bytes).  EFIE_NOT_CONVERGED if tol missed.
- * efie_solve_precond: CGS on P Z J = P V (complex128 Z, FP64 throughout).  CGS
+ *   dev Tbc_out (may be NULL).  T_BC is accumulated without forming T_bary: the
+ *   barycentric pair values of a chunk of test triangles go to workspace rows
+ *   (at most 2 GiB) that are contracted with R at once.  Rows of P solve
+ *   G_mix^T p = T_BC row by CGNR (batches of rows, column layout) to the relative
+ *   residual tol (maxit steps); *relres (host, may be NULL) gets the worst
+ *   achieved.  ws: dev workspace of ws_bytes from efie_calderon_sizes (T_BC,
+ *   16 N^2 bytes, plus a few GiB).  EFIE_NOT_CONVERGED if tol missed.
+ * efie_calderon_assemble_ex: the same with bary_dtype EFIE_C128 (as above) or
+ *   EFIE_C64: barycentric far pairs in FP32 (near pairs FP64) and complex64
+ *   workspace rows; contractions, T_BC and P stay FP64 (a preconditioner only
+ *   has to be fixed, not exact: P then differs from T_BC G^-1 by ~1e-6).
+ * efie_solve_precond: CGS on P Z J = P V (complex128 Z and P, FP64 throughout).
+ *   efie_solve_precond_ex: Z and P of either dtype; with a complex64 factor the
+ *   CGS products of more than 8 columns run on FP32 matrix cores (FP64 flushes)
+ *   and each pass stops no lower than opts->inner_tol, the outer refinement
+ *   (FP64 products, against the stored Z) making the result accurate.  CGS
  *   tests the preconditioned recurrence residual; an outer refinement on the
  *   unpreconditioned FP64 true residual r = V - Z J then solves P Z d = P r for the
  *   columns still above tol (tolerance scaled by the observed ratio of true to
@@ -313,10 +324,16 @@ int efie_calderon_host_matrices(efie_calderon c, double* R, double* G);
 int efie_calderon_assemble(efie_calderon c, double kt_re, double kt_im, double eta, void* P, void* Tbc_out,
                            double tol, int32_t maxit, double* relres, void* ws, size_t ws_bytes,
                            hipStream_t stream);
+int efie_calderon_assemble_ex(efie_calderon c, double kt_re, double kt_im, double eta, int bary_dtype, void* P,
+                              void* Tbc_out, double tol, int32_t maxit, double* relres, void* ws,
+                              size_t ws_bytes, hipStream_t stream);
 int efie_solve_precond_workspace_size(int64_t n, int64_t nrhs, size_t* bytes);
 int efie_solve_precond(const void* Z, const void* P, int64_t n, const void* V, void* J, int64_t nrhs,
                        const efie_solve_opts* opts, efie_rhs_stats* stats, void* ws, size_t ws_bytes,
                        hipStream_t stream);
+int efie_solve_precond_ex(const void* Z, int zdt, const void* P, int pdt, int64_t n, const void* V, void* J,
+                          int64_t nrhs, const efie_solve_opts* opts, efie_rhs_stats* stats, void* ws,
+                          size_t ws_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------- many meshes */
 
@@ -350,6 +367,15 @@ int efie_batch_assemble(efie_batch b, const double* k, double eta, int dtype, vo
 int efie_batch_solve(efie_batch b, const void* Zcat, int dtype, const void* Vcat, void* Jcat,
                      const efie_solve_opts* opts, efie_rhs_stats* stats, void* ws, size_t ws_bytes,
                      hipStream_t stream);
+
+/* -------------------------------------------------------------- utilities */
+
+/*
+ * dst = src elementwise for count complex numbers, converting between complex128
+ * and complex64 (round to nearest) when the dtypes differ.  Both dev.  Used to
+ * store an operator or a preconditioner in complex64 for the mixed form.
+ */
+int efie_convert(const void* src, int src_dtype, void* dst, int dst_dtype, int64_t count, hipStream_t stream);
 
 /* ------------------------------------------------------------ measurement */
 

@@ -45,7 +45,8 @@ EXPORTED = [
     "efie_calderon_host_matrices", "efie_calderon_assemble", "efie_solve_precond_workspace_size", "efie_solve_precond",
     "efie_batch_create", "efie_batch_destroy", "efie_batch_sizes", "efie_batch_upload", "efie_batch_assemble",
     "efie_batch_solve", "efie_farfield_adjoint", "efie_vertex_grad_workspace_size", "efie_vertex_grad",
-    "efie_assemble_workspace_size", "efie_assemble_ws",
+    "efie_assemble_workspace_size", "efie_assemble_ws", "efie_calderon_assemble_ex", "efie_solve_precond_ex",
+    "efie_convert",
 ]
 PROF_IDS = {"far": 0, "near": 1, "mfma": 2, "gemv": 3, "zgemm": 4, "krylov": 5, "excite": 6, "farfield": 7, "grad_far": 8,
             "grad_near": 9, "grad_tri": 10}
@@ -112,6 +113,11 @@ def lib():
         "efie_calderon_upload": ([P, P, ctypes.c_size_t, P], ctypes.c_int),
         "efie_calderon_host_matrices": ([P, P, P], ctypes.c_int),
         "efie_calderon_assemble": ([P, D, D, D, P, P, D, I32, ctypes.POINTER(D), P, ctypes.c_size_t, P], ctypes.c_int),
+        "efie_calderon_assemble_ex": ([P, D, D, D, ctypes.c_int, P, P, D, I32, ctypes.POINTER(D), P, ctypes.c_size_t,
+                                       P], ctypes.c_int),
+        "efie_convert": ([P, ctypes.c_int, P, ctypes.c_int, I64, P], ctypes.c_int),
+        "efie_solve_precond_ex": ([P, ctypes.c_int, P, ctypes.c_int, I64, P, P, I64, ctypes.POINTER(_SolveOpts),
+                                   ctypes.POINTER(_RhsStats), P, ctypes.c_size_t, P], ctypes.c_int),
         "efie_solve_precond_workspace_size": ([I64, I64, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "efie_solve_precond": ([P, P, I64, P, P, I64, ctypes.POINTER(_SolveOpts), ctypes.POINTER(_RhsStats), P,
                                 ctypes.c_size_t, P], ctypes.c_int),
@@ -356,6 +362,17 @@ def vertex_grad(mesh: Mesh, k: float, J, lam, W, dirs, khat, pol, e0: float = 1.
     return out
 
 
+def convert(A, dtype):
+    """A copy of the complex device tensor A in dtype (C128 or C64), made by the library."""
+    torch = _torch()
+    _require_cuda(A, "A")
+    src, _ = _cdtype(A.dtype)
+    dst, tdt = _cdtype(dtype)
+    out = torch.empty(A.shape, dtype=tdt, device=A.device)
+    _check(lib().efie_convert(_ptr(A), src, _ptr(out), dst, A.numel(), _stream(A.device)))
+    return out
+
+
 def zx(Z, X):
     """Y = Z X for X (nrhs, N) of Z's dtype (one right-hand side: GEMV; complex64: MFMA GEMM)."""
     torch = _torch()
@@ -536,8 +553,11 @@ class Calderon:
         self._dev = buf
         return self
 
-    def assemble(self, ktilde_value, eta: float = ETA0, tol: float = 1e-13, maxit: int = 500, with_tbc=False):
-        """P (N x N complex128) on the device; with_tbc also returns T_BC."""
+    def assemble(self, ktilde_value, eta: float = ETA0, tol: float = 1e-13, maxit: int = 500, with_tbc=False,
+                 bary_dtype=C128):
+        """P (N x N complex128) on the device; with_tbc also returns T_BC.  bary_dtype
+        C64 computes the barycentric far pairs in FP32 (the contractions, T_BC and P
+        stay FP64)."""
         torch = _torch()
         if self._dev is None:
             self.upload()
@@ -549,10 +569,10 @@ class Calderon:
         ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=dev)
         off = (-ws.data_ptr()) % 256
         rel = ctypes.c_double()
-        code = lib().efie_calderon_assemble(self._h, kt.real, kt.imag, float(eta), _ptr(Pm),
-                                            _ptr(T) if T is not None else None, float(tol), int(maxit),
-                                            ctypes.byref(rel), ctypes.c_void_p(ws.data_ptr() + off), self.ws_bytes,
-                                            _stream(dev))
+        code = lib().efie_calderon_assemble_ex(self._h, kt.real, kt.imag, float(eta), _cdtype(bary_dtype)[0],
+                                               _ptr(Pm), _ptr(T) if T is not None else None, float(tol), int(maxit),
+                                               ctypes.byref(rel), ctypes.c_void_p(ws.data_ptr() + off),
+                                               self.ws_bytes, _stream(dev))
         _check(code, allow_not_converged=True)
         del ws
         self.gram_relres = rel.value
@@ -565,25 +585,30 @@ class Calderon:
             self._h = None
 
 
-def solve_precond(Z, Pm, V, tol=1e-8, maxit=1000, max_refine=6, out=None):
-    """CGS on P Z J = P V (complex128) with outer refinement on the unpreconditioned
-    FP64 true residual (up to max_refine passes); stats report that residual and the
-    iterations summed over the passes."""
+def solve_precond(Z, Pm, V, tol=1e-8, maxit=1000, max_refine=6, inner_tol=1e-4, out=None):
+    """CGS on P Z J = P V with outer refinement on the unpreconditioned FP64 true
+    residual (up to max_refine passes); Z and P complex128 (FP64 throughout) or
+    complex64 (FP32 matrix-core products inside CGS, each pass to at least
+    inner_tol).  Stats report the true residual and the iterations summed over
+    the passes."""
     torch = _torch()
     _require_cuda(Z, "Z")
     _require_cuda(Pm, "P")
+    zdt, _ = _cdtype(Z.dtype)
+    pdt, _ = _cdtype(Pm.dtype)
     n = Z.shape[0]
     V = V.reshape(-1, n)
+    _require_cuda(V, "V")
     S = V.shape[0]
     J = out if out is not None else torch.empty_like(V)
     nb = ctypes.c_size_t()
     _check(lib().efie_solve_precond_workspace_size(n, S, ctypes.byref(nb)))
     ws = torch.empty(nb.value + 256, dtype=torch.uint8, device=Z.device)
     off = (-ws.data_ptr()) % 256
-    opts = _SolveOpts(CGS, int(maxit), float(tol), int(max_refine), 1e-3)
+    opts = _SolveOpts(CGS, int(maxit), float(tol), int(max_refine), float(inner_tol))
     st = (_RhsStats * S)()
-    code = lib().efie_solve_precond(_ptr(Z), _ptr(Pm), n, _ptr(V), _ptr(J), S, ctypes.byref(opts), st,
-                                    ctypes.c_void_p(ws.data_ptr() + off), nb.value, _stream(Z.device))
+    code = lib().efie_solve_precond_ex(_ptr(Z), zdt, _ptr(Pm), pdt, n, _ptr(V), _ptr(J), S, ctypes.byref(opts), st,
+                                       ctypes.c_void_p(ws.data_ptr() + off), nb.value, _stream(Z.device))
     _check(code, allow_not_converged=True)
     return J, SolveStats(
         iters=np.array([s.iters for s in st]), status=np.array([s.status for s in st]),

@@ -269,6 +269,52 @@ void launch_near(const DevMesh& m, double kr, double ki, const Scale& sc, void* 
 
 }  // namespace
 
+static Scale operator_scale(double kr, double ki, double eta) {
+    // A = eta j k / (4 pi),  P = eta / (j k) / (4 pi) = -j eta conj(k) / (|k|^2 4 pi)
+    Scale sc{};
+    const double f = eta / (4.0 * PI);
+    sc.ar = -f * ki;
+    sc.ai = f * kr;
+    const double k2 = kr * kr + ki * ki;
+    sc.pr = -f * ki / k2;
+    sc.pi = -f * kr / k2;
+    return sc;
+}
+
+// First pass of the atomic-free assembly for test triangles [c0, c1): every pair
+// value of Z = eta (j k T_A + T_Phi / (j k)) (far pairs in the storage precision,
+// near pairs in FP64) into rows W[p - c0][i][n][side] of complex64 (dtype
+// EFIE_C64) or complex128 elements.  Used by the Calderon build, which contracts
+// these rows without forming the matrix.
+void pair_rows_chunk(const DevMesh& m, double kr, double ki, double eta, int dtype, void* W, int c0, int c1,
+                     const std::vector<int32_t>& near_p, hipStream_t s) {
+    const Scale sc = operator_scale(kr, ki, eta);
+    const int nqblk = (m.T + FAR_BLOCK - 1) / FAR_BLOCK;
+    const int np = c1 - c0;
+    EFIE_REQUIRE(np >= 1 && size_t(np) * nqblk < (size_t(1) << 31), EFIE_ERR_ARG, "pair_rows_chunk: bad chunk");
+    const bool ck = ki != 0.0;
+    const dim3 g1(unsigned(size_t(np) * nqblk));
+    const int e0 = int(std::lower_bound(near_p.begin(), near_p.end(), c0) - near_p.begin());
+    const int e1 = int(std::lower_bound(near_p.begin(), near_p.end(), c1) - near_p.begin());
+    auto run = [&](auto tag) {
+        using R = decltype(tag);
+        using C2 = typename Cplx<R>::T;
+        const R kphase = std::is_same<R, float>::value ? R(kr / (2.0 * PI)) : R(kr);
+        C2* w = static_cast<C2*>(W);
+        if (ck)
+            hipLaunchKernelGGL((far_rows_kernel<R, true>), g1, dim3(FAR_BLOCK), 0, s, m, tables<R>(m), kphase, R(ki),
+                               sc, w, c0, nqblk);
+        else
+            hipLaunchKernelGGL((far_rows_kernel<R, false>), g1, dim3(FAR_BLOCK), 0, s, m, tables<R>(m), kphase, R(ki),
+                               sc, w, c0, nqblk);
+        if (e1 > e0)
+            hipLaunchKernelGGL((near_rows_kernel<R>), dim3((e1 - e0 + 127) / 128), dim3(128), 0, s, m, kr, ki, sc, w,
+                               c0, c1, e0, e1);
+    };
+    if (dtype == EFIE_C64) run(float{});
+    else run(double{});
+}
+
 // ws != nullptr (and not parts): far pairs by the two-pass path in that workspace
 static void assemble_impl(const DevMesh& m, double kr, double ki, double eta, int dtype, void* Z, void* Z2, int parts,
                           hipStream_t s, void* ws, size_t ws_bytes, const std::vector<int32_t>* near_p) {
@@ -277,17 +323,8 @@ static void assemble_impl(const DevMesh& m, double kr, double ki, double eta, in
     if (!ws || parts) fill_zero_bytes(Z, N * N * esz, s);   // the two-pass path writes every entry
     if (parts) fill_zero_bytes(Z2, N * N * esz, s);
     Scale sc{};
-    if (parts) {
-        sc.ar = 1.0 / (4.0 * PI);
-    } else {
-        // A = eta j k / (4 pi),  P = eta / (j k) / (4 pi) = -j eta conj(k) / (|k|^2 4 pi)
-        const double f = eta / (4.0 * PI);
-        sc.ar = -f * ki;
-        sc.ai = f * kr;
-        const double k2 = kr * kr + ki * ki;
-        sc.pr = -f * ki / k2;
-        sc.pi = -f * kr / k2;
-    }
+    if (parts) sc.ar = 1.0 / (4.0 * PI);
+    else sc = operator_scale(kr, ki, eta);
     if (dtype == EFIE_C128) {
         if (parts) {
             launch_far<double, true>(m, kr, ki, sc, Z, Z2, s);

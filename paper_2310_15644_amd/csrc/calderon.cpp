@@ -205,6 +205,40 @@ void build_calderon(efie_calderon_s& C, const efie_mesh_s& m) {
             C.gt_val[size_t(fill[size_t(c)])] = C.g_val[size_t(k)];
             fill[size_t(c)]++;
         }
+    // a spatially coherent order of the primal RWGs (Morton code of the edge midpoint
+    // in the bounding box, 21 bits per axis): the device contractions walk BC
+    // functions and Gram rows in this order so that neighbouring threads gather
+    // neighbouring data
+    {
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        for (int64_t v = 0; v < V; ++v)
+            for (int d = 0; d < 3; ++d) {
+                lo[d] = std::min(lo[d], m.xyz[3 * size_t(v) + d]);
+                hi[d] = std::max(hi[d], m.xyz[3 * size_t(v) + d]);
+            }
+        auto spread = [](uint64_t x) {   // 21 bits -> every third bit
+            x &= 0x1fffff;
+            x = (x | x << 32) & 0x1f00000000ffffull;
+            x = (x | x << 16) & 0x1f0000ff0000ffull;
+            x = (x | x << 8) & 0x100f00f00f00f00full;
+            x = (x | x << 4) & 0x10c30c30c30c30c3ull;
+            x = (x | x << 2) & 0x1249249249249249ull;
+            return x;
+        };
+        std::vector<std::pair<uint64_t, int32_t>> key(static_cast<size_t>(N));
+        for (int64_t n = 0; n < N; ++n) {
+            uint64_t code = 0;
+            for (int d = 0; d < 3; ++d) {
+                const double mid = 0.5 * (m.xyz[3 * size_t(m.edge_v[2 * n]) + d] + m.xyz[3 * size_t(m.edge_v[2 * n + 1]) + d]);
+                const double u = hi[d] > lo[d] ? (mid - lo[d]) / (hi[d] - lo[d]) : 0.0;
+                code |= spread(uint64_t(std::min(2097151.0, std::max(0.0, u * 2097151.0)))) << d;
+            }
+            key[size_t(n)] = {code, int32_t(n)};
+        }
+        std::sort(key.begin(), key.end());
+        C.n_order.resize(static_cast<size_t>(N));
+        for (int64_t n = 0; n < N; ++n) C.n_order[size_t(n)] = key[size_t(n)].second;
+    }
     C.N = N;
 }
 

@@ -16,6 +16,7 @@ struct efie_calderon_s {
     // mixed Gram matrix G (CSR by primal RWG m) and its transpose
     std::vector<int32_t> g_ptr, g_idx, gt_ptr, gt_idx;
     std::vector<double> g_val, gt_val;
+    std::vector<int32_t> n_order;            // primal RWGs in a spatially coherent (Morton) order
     // device copies (caller-owned blob)
     void* dev = nullptr;
     std::vector<char> host_blob;             // sparse arrays packed for upload

@@ -1,26 +1,37 @@
 // Device side of the Calderon preconditioner (structure of the paper's Sec. III,
 // eq. 16: second operator at k~, times a Gram inverse, times the first operator).
 //
-//   T_bary(k~)   dense EFIE matrix on the barycentric RWGs (the assembly kernels)
-//   Y = T_bary R           one thread per output, gathers along a row of T_bary
-//   T_BC = R^T Y           one thread per output, coalesced rows of Y
-//   P = T_BC G_mix^{-1}    row s of P solves G_mix^T p_s = row s of T_BC; block CGNR
-//                          (CG on the normal equations, one thread block per row,
-//                          FP64), G_mix well conditioned so a few tens of steps.
-// The preconditioned operator P Z is then applied as two dense products.
+//   T_BC = R^T T_bary(k~) R   without forming T_bary (N_b x N_b, 543 GB in complex128
+//       for the level-5 sphere): per chunk of barycentric test triangles p,
+//         W[p][i][f][side]       every pair value (the first pass of the atomic-free
+//                                assembly, complex k~),
+//         Yw[(p,i)][n] = sum_f (W[p][i][f][0] + W[p][i][f][1]) R[f][n]
+//                                (R by BC function n, CSC: a gather along the row),
+//         T_BC[m][:] += sum R[e(p,i)][m] Yw[(p,i)][:]
+//                                (one block per BC row m touched by the chunk, from
+//                                host-built lists; no atomics);
+//   P = T_BC G_mix^{-1}       row s of P solves G_mix^T p_s = row s of T_BC = column s
+//       (T_BC is symmetric), by CGNR (CG on G G^T y = G b) for a batch of columns at
+//       once in column layout X[j][s], so that every sparse product reads rows of
+//       the batch coalesced; the solution block is then transposed into P.
+// The preconditioned operator P Z is applied as two dense products.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <vector>
 
 #include "calderon.h"
 #include "linalg.h"
 
 namespace efie {
 
-void assemble_into(const DevMesh& m, double kr, double ki, double eta, int dtype, void* Z, void* Z2, int parts,
-                   hipStream_t s);
+void pair_rows_chunk(const DevMesh& m, double kr, double ki, double eta, int dtype, void* W, int c0, int c1,
+                     const std::vector<int32_t>& near_p, hipStream_t s);
+bool verbose();
+double now_s();
 
 struct DevCald {
     int N, Nb;
@@ -28,220 +39,323 @@ struct DevCald {
     const double* r_val;
     const int32_t *g_ptr, *g_idx, *gt_ptr, *gt_idx;
     const double *g_val, *gt_val;
+    const int32_t* n_order;         // primal RWGs in a spatially coherent order
 };
 
-// Y[i][n] = sum_k Tb[i][r_idx[k]] r_val[k], k over column n of R
-__global__ __launch_bounds__(256) void bc_right_kernel(DevCald c, const double2* __restrict__ Tb,
-                                                       double2* __restrict__ Y) {
-    const int n = blockIdx.x * 256 + threadIdx.x;
-    const int i = blockIdx.y;
-    if (n >= c.N) return;
-    const double2* row = Tb + size_t(i) * c.Nb;
-    double ar = 0, ai = 0;
-    for (int k = c.r_ptr[n]; k < c.r_ptr[n + 1]; ++k) {
-        const double2 t = row[c.r_idx[k]];
-        ar += t.x * c.r_val[k];
-        ai += t.y * c.r_val[k];
+// Yw[row][n] = sum_k (W[row][f][0] + W[row][f][1]) r_val[k], f = r_idx[k], k over
+// column n of R (row = 3 (p - c0) + i; W rows hold 2 N_b elements, the two sides
+// of an RWG adjacent).  A thread takes one BC function n (in the spatial order)
+// and BC_RR rows: the column's indices are loaded once into registers and the
+// BC_RR x |column| workspace loads are independent, so they overlap.
+constexpr int BC_RR = 4;
+constexpr int BC_MAXK = 8;    // R column entries per group (24 per column on icosphere meshes)
+template <typename C2>
+__global__ __launch_bounds__(256) void bc_src_kernel(DevCald c, const C2* __restrict__ W, double2* __restrict__ Yw,
+                                                     int nrows) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= c.N) return;
+    const int n = c.n_order[t];   // neighbouring threads: neighbouring BC functions
+    const int r0 = blockIdx.y * BC_RR;
+    double ar[BC_RR], ai[BC_RR];
+#pragma unroll
+    for (int u = 0; u < BC_RR; ++u) ar[u] = ai[u] = 0.0;
+    // the column in groups of BC_MAXK entries: all index loads of a group first, then
+    // all BC_RR x BC_MAXK workspace loads
+    for (int kb = c.r_ptr[n], ke = c.r_ptr[n + 1]; kb < ke; kb += BC_MAXK) {
+        int f[BC_MAXK];
+        double v[BC_MAXK];
+#pragma unroll
+        for (int q = 0; q < BC_MAXK; ++q) {
+            const bool ok = kb + q < ke;
+            f[q] = ok ? c.r_idx[kb + q] : 0;
+            v[q] = ok ? c.r_val[kb + q] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < BC_MAXK; ++q)
+#pragma unroll
+            for (int u = 0; u < BC_RR; ++u) {
+                const int row = min(r0 + u, nrows - 1);   // rows past the end: read a valid row, result dropped
+                const C2* w = W + size_t(row) * 2 * size_t(c.Nb) + 2 * size_t(f[q]);
+                const C2 x0 = w[0], x1 = w[1];
+                ar[u] += v[q] * (double(x0.x) + double(x1.x));
+                ai[u] += v[q] * (double(x0.y) + double(x1.y));
+            }
     }
-    Y[size_t(i) * c.N + n] = make_double2(ar, ai);
+#pragma unroll
+    for (int u = 0; u < BC_RR; ++u)
+        if (r0 + u < nrows) Yw[size_t(r0 + u) * c.N + n] = make_double2(ar[u], ai[u]);
 }
 
-// Tbc[m][n] = sum_k r_val[k] Y[r_idx[k]][n], k over column m of R
-__global__ __launch_bounds__(256) void bc_left_kernel(DevCald c, const double2* __restrict__ Y,
-                                                      double2* __restrict__ Tbc) {
+// Tbc[m][n] += sum_k coef[k] Yw[rows[k]][n] over the list of BC row m = ml[blockIdx.y]
+__global__ __launch_bounds__(256) void bc_test_kernel(const int32_t* __restrict__ ml, const int32_t* __restrict__ mptr,
+                                                      const int32_t* __restrict__ rows,
+                                                      const double* __restrict__ coef,
+                                                      const double2* __restrict__ Yw, double2* __restrict__ Tbc,
+                                                      int N) {
     const int n = blockIdx.x * 256 + threadIdx.x;
-    const int m = blockIdx.y;
-    if (n >= c.N) return;
-    double ar = 0, ai = 0;
-    for (int k = c.r_ptr[m]; k < c.r_ptr[m + 1]; ++k) {
-        const double2 y = Y[size_t(c.r_idx[k]) * c.N + n];
-        ar += c.r_val[k] * y.x;
-        ai += c.r_val[k] * y.y;
+    const int mi = blockIdx.y;
+    if (n >= N) return;
+    const size_t o = size_t(ml[mi]) * N + n;
+    double2 acc = Tbc[o];
+    for (int k = mptr[mi]; k < mptr[mi + 1]; ++k) {
+        const double2 y = Yw[size_t(rows[k]) * N + n];
+        acc.x += coef[k] * y.x;
+        acc.y += coef[k] * y.y;
     }
-    Tbc[size_t(m) * c.N + n] = make_double2(ar, ai);
+    Tbc[o] = acc;
 }
 
-// Out[s][j] = sum_k val[k] X[s][idx[k]], k over row j of a real CSR matrix
-__global__ __launch_bounds__(256) void spmm_kernel(const int32_t* __restrict__ ptr, const int32_t* __restrict__ idx,
-                                                   const double* __restrict__ val, const double2* __restrict__ X,
-                                                   double2* __restrict__ Out, int N) {
-    const int j = blockIdx.x * 256 + threadIdx.x;
-    const int s = blockIdx.y;
-    if (j >= N) return;
-    const double2* x = X + size_t(s) * N;
+// ---------------------------------------------- CGNR in column layout X[j][s]
+// Out[j][s] = sum_k val[k] X[idx[k]][s], k over row j of a real CSR matrix;
+// grid (N rows, column tiles of 256)
+__global__ __launch_bounds__(256) void cspmm_kernel(const int32_t* __restrict__ ptr, const int32_t* __restrict__ idx,
+                                                    const double* __restrict__ val, const double2* __restrict__ X,
+                                                    int ldx, double2* __restrict__ Out, int S,
+                                                    const int32_t* __restrict__ order) {
+    const int j = order[blockIdx.x];   // rows in a spatially coherent order
+    const int s = blockIdx.y * 256 + threadIdx.x;
+    if (s >= S) return;
     double ar = 0, ai = 0;
     for (int k = ptr[j]; k < ptr[j + 1]; ++k) {
-        const double2 v = x[idx[k]];
+        const double2 v = X[size_t(idx[k]) * ldx + s];
         ar += val[k] * v.x;
         ai += val[k] * v.y;
     }
-    Out[size_t(s) * N + j] = make_double2(ar, ai);
+    Out[size_t(j) * S + s] = make_double2(ar, ai);
 }
 
-// ------------------------------------------------------------- block CGNR
+constexpr int CJS = 32;   // row slices of the column reductions
+// part[js][s] = sum over rows j of slice js of |X[j][s]|^2; block = 64 columns x 4
+// row stripes, grid (column tiles of 64, CJS slices)
+__global__ __launch_bounds__(256) void colsq_part_kernel(const double2* __restrict__ X, int ld, int N, int S,
+                                                         double* __restrict__ part) {
+    __shared__ double sh[4][64];
+    const int cl = threadIdx.x & 63, st = threadIdx.x >> 6;
+    const int s = blockIdx.x * 64 + cl;
+    const int per = (N + CJS - 1) / CJS;
+    const int j0 = blockIdx.y * per, j1 = min(N, j0 + per);
+    double a = 0.0;
+    if (s < S)
+        for (int j = j0 + st; j < j1; j += 4) {
+            const double2 v = X[size_t(j) * ld + s];
+            a += v.x * v.x + v.y * v.y;
+        }
+    sh[st][cl] = a;
+    __syncthreads();
+    if (st == 0 && s < S) part[size_t(blockIdx.y) * S + s] = sh[0][cl] + sh[1][cl] + sh[2][cl] + sh[3][cl];
+}
+__global__ void colsq_final_kernel(const double* __restrict__ part, int S, double* __restrict__ out) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    double a = 0.0;
+    for (int js = 0; js < CJS; ++js) a += part[size_t(js) * S + s];
+    out[s] = a;
+}
+
 struct CgnrCol {
     double gamma, bn2, rn2, tol2;
     int active, iters, pad[2];
 };
-constexpr int CB = 256;
 
-__device__ void csum(double (&v)[2], double* sh) {
-#pragma unroll
-    for (int k = 0; k < 2; ++k)
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) {
-        sh[2 * w] = v[0];
-        sh[2 * w + 1] = v[1];
-    }
-    __syncthreads();
-    v[0] = v[1] = 0.0;
-    for (int u = 0; u < CB / 64; ++u) {
-        v[0] += sh[2 * u];
-        v[1] += sh[2 * u + 1];
+// w = 0, r = b (b[j][s] with leading dimension ldb)
+__global__ void cgnr_init_kernel(const double2* __restrict__ b, int ldb, double2* __restrict__ w,
+                                 double2* __restrict__ r, int N, int S) {
+    const size_t tot = size_t(N) * S;
+    for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < tot; e += size_t(gridDim.x) * blockDim.x) {
+        const size_t j = e / S, s = e - j * S;
+        w[e] = make_double2(0.0, 0.0);
+        r[e] = b[j * ldb + s];
     }
 }
-
-// w = 0, r = b, ||b||^2
-__global__ __launch_bounds__(CB) void cgnr_init(const double2* b, double2* w, double2* r, CgnrCol* cols, int N,
-                                                double tol) {
-    __shared__ double sh[2 * CB / 64];
-    const int s = blockIdx.x;
-    const size_t o = size_t(s) * N;
-    double v[2] = {0, 0};
-    for (int k = threadIdx.x; k < N; k += CB) {
-        const double2 x = b[o + k];
-        w[o + k] = make_double2(0, 0);
-        r[o + k] = x;
-        v[0] += x.x * x.x + x.y * x.y;
-    }
-    csum(v, sh);
-    if (threadIdx.x == 0) {
-        CgnrCol c{};
-        c.bn2 = v[0];
-        c.rn2 = v[0];
-        c.tol2 = tol * tol * v[0];
-        c.active = v[0] > 0.0;
-        cols[s] = c;
+__global__ void cgnr_setup_kernel(CgnrCol* cols, const double* bn2, const double* zz, double tol, int S) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    CgnrCol c{};
+    c.gamma = zz[s];
+    c.bn2 = bn2[s];
+    c.rn2 = bn2[s];
+    c.tol2 = tol * tol * bn2[s];
+    c.active = bn2[s] > 0.0 && zz[s] > 0.0;
+    cols[s] = c;
+}
+// after t = G^T p, tt = ||t||^2: alpha = gamma / tt, w += alpha p, r -= alpha t
+__global__ void cgnr_upd1_kernel(double2* __restrict__ w, double2* __restrict__ r, const double2* __restrict__ p,
+                                 const double2* __restrict__ t, const CgnrCol* __restrict__ cols,
+                                 const double* __restrict__ tt, int N, int S) {
+    const size_t tot = size_t(N) * S;
+    for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < tot; e += size_t(gridDim.x) * blockDim.x) {
+        const int s = int(e % S);
+        if (!cols[s].active || !(tt[s] > 0.0)) continue;
+        const double al = cols[s].gamma / tt[s];
+        const double2 pp = p[e], tv = t[e];
+        double2 ww = w[e], rr = r[e];
+        ww.x += al * pp.x;
+        ww.y += al * pp.y;
+        rr.x -= al * tv.x;
+        rr.y -= al * tv.y;
+        w[e] = ww;
+        r[e] = rr;
     }
 }
-
-// after z = G r (first time): p = z, gamma = ||z||^2
-__global__ __launch_bounds__(CB) void cgnr_start(const double2* z, double2* p, CgnrCol* cols, int N) {
-    __shared__ double sh[2 * CB / 64];
-    const int s = blockIdx.x;
-    const size_t o = size_t(s) * N;
-    double v[2] = {0, 0};
-    for (int k = threadIdx.x; k < N; k += CB) {
-        const double2 x = z[o + k];
-        p[o + k] = x;
-        v[0] += x.x * x.x + x.y * x.y;
-    }
-    csum(v, sh);
-    if (threadIdx.x == 0) cols[s].gamma = v[0];
+__global__ void cgnr_check_kernel(CgnrCol* cols, const double* rn2, const double* tt, int S, int* nactive) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    CgnrCol c = cols[s];
+    if (!c.active) return;
+    c.rn2 = rn2[s];
+    c.iters += 1;
+    if (rn2[s] <= c.tol2 || !(rn2[s] == rn2[s]) || !(tt[s] > 0.0)) c.active = 0;
+    cols[s] = c;
+    if (c.active) atomicAdd(nactive, 1);
 }
-
-// after t = G^T p: alpha = gamma / ||t||^2, w += alpha p, r -= alpha t
-__global__ __launch_bounds__(CB) void cgnr_step1(double2* w, double2* r, const double2* p, const double2* t,
-                                                 CgnrCol* cols, int N, int* nactive) {
-    __shared__ double sh[2 * CB / 64];
-    __shared__ int go;
-    const int s = blockIdx.x;
-    if (threadIdx.x == 0) go = cols[s].active;
+// after z = G r, zz = ||z||^2: p = z + (zz / gamma) p for active columns
+__global__ void cgnr_upd2_kernel(double2* __restrict__ p, const double2* __restrict__ z,
+                                 const CgnrCol* __restrict__ cols, const double* __restrict__ zz, int N, int S) {
+    const size_t tot = size_t(N) * S;
+    for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < tot; e += size_t(gridDim.x) * blockDim.x) {
+        const int s = int(e % S);
+        if (!cols[s].active) continue;
+        const double be = zz[s] / cols[s].gamma;
+        double2 pp = p[e];
+        const double2 zv = z[e];
+        pp.x = zv.x + be * pp.x;
+        pp.y = zv.y + be * pp.y;
+        p[e] = pp;
+    }
+}
+__global__ void cgnr_gamma_kernel(CgnrCol* cols, const double* zz, int S) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < S && cols[s].active) cols[s].gamma = zz[s];
+}
+// P[s0 + s][j] = w[j][s] (32 x 32 tiles through LDS)
+__global__ __launch_bounds__(256) void transpose_kernel(const double2* __restrict__ w, int S, int N,
+                                                        double2* __restrict__ P, int s0) {
+    __shared__ double2 tile[32][33];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+    const int sb = blockIdx.x * 32, jb = blockIdx.y * 32;
+    for (int r = ty; r < 32; r += 8) {
+        const int j = jb + r, s = sb + tx;
+        if (j < N && s < S) tile[r][tx] = w[size_t(j) * S + s];
+    }
     __syncthreads();
-    if (!go) return;
-    const size_t o = size_t(s) * N;
-    double v[2] = {0, 0};
-    for (int k = threadIdx.x; k < N; k += CB) {
-        const double2 x = t[o + k];
-        v[0] += x.x * x.x + x.y * x.y;
+    for (int r = ty; r < 32; r += 8) {
+        const int s = sb + r, j = jb + tx;
+        if (s < S && j < N) P[size_t(s0 + s) * N + j] = tile[tx][r];
     }
-    csum(v, sh);
-    const double gamma = cols[s].gamma;
-    const double alpha = v[0] > 0.0 ? gamma / v[0] : 0.0;
-    double u[2] = {0, 0};
-    for (int k = threadIdx.x; k < N; k += CB) {
-        double2 ww = w[o + k], rr = r[o + k];
-        const double2 pp = p[o + k], tt = t[o + k];
-        ww.x += alpha * pp.x;
-        ww.y += alpha * pp.y;
-        rr.x -= alpha * tt.x;
-        rr.y -= alpha * tt.y;
-        w[o + k] = ww;
-        r[o + k] = rr;
-        u[0] += rr.x * rr.x + rr.y * rr.y;
-    }
-    csum(u, sh);
-    if (threadIdx.x == 0) {
-        CgnrCol c = cols[s];
-        c.rn2 = u[0];
-        c.iters += 1;
-        if (u[0] <= c.tol2 || !(u[0] == u[0]) || v[0] == 0.0) c.active = 0;
-        cols[s] = c;
-        if (c.active) atomicAdd(nactive, 1);
-    }
-}
-
-// after z = G r: beta = ||z||^2 / gamma, p = z + beta p
-__global__ __launch_bounds__(CB) void cgnr_step2(const double2* z, double2* p, CgnrCol* cols, int N) {
-    __shared__ double sh[2 * CB / 64];
-    __shared__ int go;
-    const int s = blockIdx.x;
-    // read before the barriers below: thread 0 rewrites gamma at the end
-    const double gamma = cols[s].gamma;
-    if (threadIdx.x == 0) go = cols[s].active;
-    __syncthreads();
-    if (!go) return;
-    const size_t o = size_t(s) * N;
-    double v[2] = {0, 0};
-    for (int k = threadIdx.x; k < N; k += CB) {
-        const double2 x = z[o + k];
-        v[0] += x.x * x.x + x.y * x.y;
-    }
-    csum(v, sh);
-    const double beta = v[0] / gamma;
-    for (int k = threadIdx.x; k < N; k += CB) {
-        double2 pp = p[o + k];
-        const double2 zz = z[o + k];
-        pp.x = zz.x + beta * pp.x;
-        pp.y = zz.y + beta * pp.y;
-        p[o + k] = pp;
-    }
-    if (threadIdx.x == 0) cols[s].gamma = v[0];
 }
 
 namespace {
 
 size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
 
+constexpr size_t CALD_W_BUDGET = size_t(2) << 30;    // workspace rows of one chunk of test triangles
+constexpr size_t CALD_CG_BUDGET = size_t(6) << 30;   // CGNR vectors of one column batch
+
+struct CaldPlan {
+    int chunk = 1, nchunks = 1, Sb = 1;
+    size_t entries = 0;   // (BC row, workspace row, coefficient) list entries over all chunks
+};
+
+CaldPlan cald_plan(const efie_calderon_s& C, int bary_dtype) {
+    CaldPlan pl;
+    const size_t esz = bary_dtype == EFIE_C64 ? 8 : 16;
+    const size_t per_tri = size_t(6) * size_t(C.bary.N) * esz;
+    const size_t Tb = size_t(C.bary.T);
+    // grid limits: 3 rows per triangle (bc_src) and at most 18 BC rows per triangle (bc_test)
+    pl.chunk = int(std::max<size_t>(1, std::min<size_t>({Tb, CALD_W_BUDGET / per_tri, 3640})));
+    pl.nchunks = int((Tb + size_t(pl.chunk) - 1) / size_t(pl.chunk));
+    const size_t N = size_t(C.N);
+    pl.Sb = int(std::max<size_t>(64, std::min<size_t>(N, CALD_CG_BUDGET / (5 * N * 16))));
+    pl.entries = 2 * C.re_idx.size();
+    return pl;
+}
+
 struct CaldWs {
-    double2 *Tb, *Y, *Tbc, *r, *z, *p, *t;
+    void* W;
+    double2* Yw;
+    int32_t *ml, *mptr, *rows;
+    double* coef;
+    double2* Tbc;
+    double2 *w, *r, *z, *p, *t;
+    double *part, *bn2, *tt, *rn2, *zz;
     CgnrCol* cols;
     int* counter;
 };
 
-size_t cald_layout(int64_t N, int64_t Nb, CaldWs* w, char* base) {
+size_t cald_layout(const efie_calderon_s& C, const CaldPlan& pl, int bary_dtype, CaldWs* w, char* base) {
     size_t off = 0;
     auto take = [&](size_t bytes) {
         char* p = base ? base + off : nullptr;
         off += a256(bytes);
         return p;
     };
+    const size_t N = size_t(C.N), Nb = size_t(C.bary.N), Sb = size_t(pl.Sb);
+    const size_t esz = bary_dtype == EFIE_C64 ? 8 : 16;
     CaldWs x{};
-    const size_t nn = size_t(N) * size_t(N) * 16;
-    x.Tb = (double2*)take(size_t(Nb) * size_t(Nb) * 16);
-    x.Y = (double2*)take(size_t(Nb) * size_t(N) * 16);
-    x.Tbc = (double2*)take(nn);
-    x.r = (double2*)take(nn);
-    x.z = (double2*)take(nn);
-    x.p = (double2*)take(nn);
-    x.t = (double2*)take(nn);
-    x.cols = (CgnrCol*)take(sizeof(CgnrCol) * size_t(N));
+    x.W = take(size_t(pl.chunk) * 6 * Nb * esz);
+    x.Yw = (double2*)take(size_t(pl.chunk) * 3 * N * 16);
+    x.ml = (int32_t*)take(4 * pl.entries);
+    x.mptr = (int32_t*)take(4 * (pl.entries + size_t(pl.nchunks)));
+    x.rows = (int32_t*)take(4 * pl.entries);
+    x.coef = (double*)take(8 * pl.entries);
+    x.Tbc = (double2*)take(N * N * 16);
+    x.w = (double2*)take(N * Sb * 16);
+    x.r = (double2*)take(N * Sb * 16);
+    x.z = (double2*)take(N * Sb * 16);
+    x.p = (double2*)take(N * Sb * 16);
+    x.t = (double2*)take(N * Sb * 16);
+    x.part = (double*)take(8 * size_t(CJS) * Sb);
+    x.bn2 = (double*)take(8 * Sb);
+    x.tt = (double*)take(8 * Sb);
+    x.rn2 = (double*)take(8 * Sb);
+    x.zz = (double*)take(8 * Sb);
+    x.cols = (CgnrCol*)take(sizeof(CgnrCol) * Sb);
     x.counter = (int*)take(16);
     if (w) *w = x;
     return off;
+}
+
+// Host lists of the test-side contraction, per chunk of barycentric test triangles:
+// for every BC row m touched by the chunk, the workspace rows 3 (p - c0) + i whose
+// barycentric RWG e(p, i) has R[e][m] != 0, with that coefficient.
+struct CaldLists {
+    std::vector<int32_t> ml, mptr, rows;
+    std::vector<double> coef;
+    std::vector<int64_t> m0, nm, mp0;   // per chunk: first entry in ml, count, first entry in mptr
+};
+
+CaldLists cald_lists(const efie_calderon_s& C, const CaldPlan& pl) {
+    CaldLists L;
+    const int64_t Tb = C.bary.T;
+    struct E {
+        int32_t m, row;
+        double c;
+    };
+    std::vector<E> es;
+    for (int ch = 0; ch < pl.nchunks; ++ch) {
+        const int64_t c0 = int64_t(ch) * pl.chunk, c1 = std::min<int64_t>(Tb, c0 + pl.chunk);
+        es.clear();
+        for (int64_t p = c0; p < c1; ++p)
+            for (int i = 0; i < 3; ++i) {
+                const int32_t e = C.bary.tri_edge[size_t(3 * p + i)];
+                for (int32_t k = C.re_ptr[size_t(e)]; k < C.re_ptr[size_t(e) + 1]; ++k)
+                    es.push_back({C.re_idx[size_t(k)], int32_t(3 * (p - c0) + i), C.re_val[size_t(k)]});
+            }
+        std::stable_sort(es.begin(), es.end(), [](const E& a, const E& b) { return a.m < b.m; });
+        L.m0.push_back(int64_t(L.ml.size()));
+        L.mp0.push_back(int64_t(L.mptr.size()));
+        for (size_t q = 0; q < es.size(); ++q) {
+            if (q == 0 || es[q].m != es[q - 1].m) {
+                L.ml.push_back(es[q].m);
+                L.mptr.push_back(int32_t(L.rows.size()));
+            }
+            L.rows.push_back(es[q].row);
+            L.coef.push_back(es[q].c);
+        }
+        L.mptr.push_back(int32_t(L.rows.size()));
+        L.nm.push_back(int64_t(L.ml.size()) - L.m0.back());
+    }
+    return L;
 }
 
 DevCald dev_cald(const efie_calderon_s& C) {
@@ -259,6 +373,7 @@ DevCald dev_cald(const efie_calderon_s& C) {
     d.gt_ptr = reinterpret_cast<const int32_t*>(b + o[6]);
     d.gt_idx = reinterpret_cast<const int32_t*>(b + o[7]);
     d.gt_val = reinterpret_cast<const double*>(b + o[8]);
+    d.n_order = reinterpret_cast<const int32_t*>(b + o[9]);
     return d;
 }
 
@@ -295,6 +410,7 @@ int efie_calderon_create(efie_mesh mesh, efie_calderon* out) {
             efie::put(blob, offs, C->gt_ptr);
             efie::put(blob, offs, C->gt_idx);
             efie::put(blob, offs, C->gt_val);
+            efie::put(blob, offs, C->n_order);
             blob.resize(efie::a256(blob.size()));
             C->host_blob.swap(blob);
             C->offs.swap(offs);
@@ -317,7 +433,9 @@ int efie_calderon_sizes(efie_calderon c, int64_t* n_bary_rwg, int64_t* n_bary_tr
         if (n_bary_rwg) *n_bary_rwg = c->bary.N;
         if (n_bary_tri) *n_bary_tri = c->bary.T;
         if (table_bytes) *table_bytes = efie::a256(c->bary_bytes) + c->host_blob.size();
-        if (ws_bytes) *ws_bytes = efie::cald_layout(c->N, c->bary.N, nullptr, nullptr);
+        if (ws_bytes)
+            *ws_bytes = std::max(efie::cald_layout(*c, efie::cald_plan(*c, EFIE_C128), EFIE_C128, nullptr, nullptr),
+                                 efie::cald_layout(*c, efie::cald_plan(*c, EFIE_C64), EFIE_C64, nullptr, nullptr));
         return int(EFIE_OK);
     });
 }
@@ -356,57 +474,116 @@ int efie_calderon_host_matrices(efie_calderon c, double* R, double* G) {
     });
 }
 
-int efie_calderon_assemble(efie_calderon c, double kt_re, double kt_im, double eta, void* P, void* Tbc_out,
-                           double tol, int32_t maxit, double* relres, void* ws, size_t ws_bytes, hipStream_t stream) {
+int efie_calderon_assemble_ex(efie_calderon c, double kt_re, double kt_im, double eta, int bary_dtype, void* P,
+                              void* Tbc_out, double tol, int32_t maxit, double* relres, void* ws, size_t ws_bytes,
+                              hipStream_t stream) {
     using namespace efie;
     return guarded([&]() {
         EFIE_REQUIRE(c && P && ws, EFIE_ERR_ARG, "calderon_assemble: null argument");
         EFIE_REQUIRE(c->dev != nullptr, EFIE_ERR_STATE, "calderon_assemble: tables not uploaded");
+        EFIE_REQUIRE(bary_dtype == EFIE_C128 || bary_dtype == EFIE_C64, EFIE_ERR_ARG, "calderon_assemble: bad dtype");
         EFIE_REQUIRE(kt_im <= 0.0 && (kt_re != 0.0 || kt_im != 0.0), EFIE_ERR_ARG, "calderon_assemble: bad k~");
         EFIE_REQUIRE(tol > 0.0 && maxit >= 1, EFIE_ERR_ARG, "calderon_assemble: bad tol/maxit");
-        const int64_t N = c->N, Nb = c->bary.N;
-        EFIE_REQUIRE(N <= 65535 && Nb <= 65535, EFIE_ERR_ARG,
-                     "calderon_assemble: at most 65535 primal and barycentric RWGs (one grid row per RWG)");
-        const size_t need = cald_layout(N, Nb, nullptr, nullptr);
+        const int N = int(c->N);
+        const CaldPlan pl = cald_plan(*c, bary_dtype);
+        const size_t need = cald_layout(*c, pl, bary_dtype, nullptr, nullptr);
         EFIE_REQUIRE(ws_bytes >= need, EFIE_ERR_ARG, "calderon_assemble: workspace too small");
         EFIE_REQUIRE((reinterpret_cast<uintptr_t>(ws) & 255) == 0, EFIE_ERR_ARG, "calderon_assemble: ws not aligned");
         CaldWs w;
-        cald_layout(N, Nb, &w, static_cast<char*>(ws));
+        cald_layout(*c, pl, bary_dtype, &w, static_cast<char*>(ws));
         const DevCald d = dev_cald(*c);
-        // second operator on the barycentric RWGs at k~
-        assemble_into(c->bary.dm, kt_re, kt_im, eta, EFIE_C128, w.Tb, nullptr, 0, stream);
-        dim3 g1(unsigned((N + 255) / 256), unsigned(Nb)), g2(unsigned((N + 255) / 256), unsigned(N));
-        hipLaunchKernelGGL(bc_right_kernel, g1, dim3(256), 0, stream, d, w.Tb, w.Y);
-        hipLaunchKernelGGL(bc_left_kernel, g2, dim3(256), 0, stream, d, w.Y, w.Tbc);
-        if (Tbc_out)
-            EFIE_HIP_CHECK(hipMemcpyAsync(Tbc_out, w.Tbc, size_t(N) * size_t(N) * 16, hipMemcpyDeviceToDevice, stream));
-        // P: rows p_s solve G^T p_s = Tbc_s by CGNR (CG on G G^T y = G b)
-        double2* X = static_cast<double2*>(P);
-        const int S = int(N);
-        dim3 gs(unsigned((N + 255) / 256), unsigned(S));
-        hipLaunchKernelGGL(cgnr_init, dim3(S), dim3(CB), 0, stream, w.Tbc, X, w.r, w.cols, int(N), tol);
-        hipLaunchKernelGGL(spmm_kernel, gs, dim3(256), 0, stream, d.g_ptr, d.g_idx, d.g_val, w.r, w.z, int(N));
-        hipLaunchKernelGGL(cgnr_start, dim3(S), dim3(CB), 0, stream, w.z, w.p, w.cols, int(N));
-        int h_active = S;
-        int it = 0;
-        for (; it < maxit && h_active > 0; ++it) {
-            hipLaunchKernelGGL(spmm_kernel, gs, dim3(256), 0, stream, d.gt_ptr, d.gt_idx, d.gt_val, w.p, w.t, int(N));
-            EFIE_HIP_CHECK(hipMemsetAsync(w.counter, 0, sizeof(int), stream));
-            hipLaunchKernelGGL(cgnr_step1, dim3(S), dim3(CB), 0, stream, X, w.r, w.p, w.t, w.cols, int(N), w.counter);
-            hipLaunchKernelGGL(spmm_kernel, gs, dim3(256), 0, stream, d.g_ptr, d.g_idx, d.g_val, w.r, w.z, int(N));
-            hipLaunchKernelGGL(cgnr_step2, dim3(S), dim3(CB), 0, stream, w.z, w.p, w.cols, int(N));
-            EFIE_HIP_CHECK(hipMemcpyAsync(&h_active, w.counter, sizeof(int), hipMemcpyDeviceToHost, stream));
-            EFIE_HIP_CHECK(hipStreamSynchronize(stream));
+        // ---- T_BC = R^T T_bary(k~) R, streamed over chunks of barycentric test triangles
+        const CaldLists L = cald_lists(*c, pl);
+        EFIE_HIP_CHECK(hipMemcpyAsync(w.ml, L.ml.data(), 4 * L.ml.size(), hipMemcpyHostToDevice, stream));
+        EFIE_HIP_CHECK(hipMemcpyAsync(w.mptr, L.mptr.data(), 4 * L.mptr.size(), hipMemcpyHostToDevice, stream));
+        EFIE_HIP_CHECK(hipMemcpyAsync(w.rows, L.rows.data(), 4 * L.rows.size(), hipMemcpyHostToDevice, stream));
+        EFIE_HIP_CHECK(hipMemcpyAsync(w.coef, L.coef.data(), 8 * L.coef.size(), hipMemcpyHostToDevice, stream));
+        fill_zero_bytes(w.Tbc, size_t(N) * N * 16, stream);
+        const int Tb = int(c->bary.T);
+        const unsigned nx = unsigned((N + 255) / 256);
+        for (int ch = 0; ch < pl.nchunks; ++ch) {
+            const int c0 = ch * pl.chunk, c1 = std::min(Tb, c0 + pl.chunk), np = c1 - c0;
+            pair_rows_chunk(c->bary.dm, kt_re, kt_im, eta, bary_dtype, w.W, c0, c1, c->bary.near_p, stream);
+            if (bary_dtype == EFIE_C64)
+                hipLaunchKernelGGL(bc_src_kernel<float2>, dim3(nx, unsigned((3 * np + BC_RR - 1) / BC_RR)), dim3(256),
+                                   0, stream, d, static_cast<const float2*>(w.W), w.Yw, 3 * np);
+            else
+                hipLaunchKernelGGL(bc_src_kernel<double2>, dim3(nx, unsigned((3 * np + BC_RR - 1) / BC_RR)),
+                                   dim3(256), 0, stream, d, static_cast<const double2*>(w.W), w.Yw, 3 * np);
+            if (L.nm[size_t(ch)] > 0)
+                hipLaunchKernelGGL(bc_test_kernel, dim3(nx, unsigned(L.nm[size_t(ch)])), dim3(256), 0, stream,
+                                   w.ml + L.m0[size_t(ch)], w.mptr + L.mp0[size_t(ch)], w.rows, w.coef, w.Yw, w.Tbc, N);
+            if (verbose() && (ch % 64 == 63 || ch + 1 == pl.nchunks)) {
+                EFIE_HIP_CHECK(hipStreamSynchronize(stream));
+                std::fprintf(stderr, "[efie] calderon T_BC chunk %d/%d t=%.3f\n", ch + 1, pl.nchunks, now_s());
+                std::fflush(stderr);
+            }
         }
-        std::vector<CgnrCol> cols(static_cast<size_t>(S));
-        EFIE_HIP_CHECK(hipMemcpyAsync(cols.data(), w.cols, sizeof(CgnrCol) * size_t(S), hipMemcpyDeviceToHost, stream));
-        EFIE_HIP_CHECK(hipStreamSynchronize(stream));
+        if (Tbc_out)
+            EFIE_HIP_CHECK(hipMemcpyAsync(Tbc_out, w.Tbc, size_t(N) * N * 16, hipMemcpyDeviceToDevice, stream));
+        // ---- P = T_BC G^{-1}: column batches of G^T Y = T_BC (column s = row s of T_BC), P = Y^T
+        double2* Pout = static_cast<double2*>(P);
         double worst = 0.0;
-        for (const auto& cc : cols) worst = std::max(worst, cc.bn2 > 0 ? std::sqrt(cc.rn2 / cc.bn2) : 0.0);
+        auto colsq = [&](const double2* X, int ld, int S, double* out) {
+            hipLaunchKernelGGL(colsq_part_kernel, dim3(unsigned((S + 63) / 64), unsigned(CJS)), dim3(256), 0, stream,
+                               X, ld, N, S, w.part);
+            hipLaunchKernelGGL(colsq_final_kernel, dim3(unsigned((S + 255) / 256)), dim3(256), 0, stream, w.part, S,
+                               out);
+        };
+        for (int s0 = 0; s0 < N; s0 += pl.Sb) {
+            const int S = std::min(pl.Sb, N - s0);
+            const size_t tot = size_t(N) * S;
+            const int ge = int(std::min<size_t>((tot + 255) / 256, 16384));
+            const dim3 gs(unsigned(N), unsigned((S + 255) / 256));
+            hipLaunchKernelGGL(cgnr_init_kernel, dim3(ge), dim3(256), 0, stream, w.Tbc + s0, N, w.w, w.r, N, S);
+            colsq(w.r, S, S, w.bn2);
+            hipLaunchKernelGGL(cspmm_kernel, gs, dim3(256), 0, stream, d.g_ptr, d.g_idx, d.g_val, w.r, S, w.z, S,
+                               d.n_order);
+            colsq(w.z, S, S, w.zz);
+            EFIE_HIP_CHECK(hipMemcpyAsync(w.p, w.z, tot * 16, hipMemcpyDeviceToDevice, stream));
+            hipLaunchKernelGGL(cgnr_setup_kernel, dim3(unsigned((S + 255) / 256)), dim3(256), 0, stream, w.cols, w.bn2,
+                               w.zz, tol, S);
+            int h_active = S;
+            for (int it = 0; it < maxit && h_active > 0; ++it) {
+                hipLaunchKernelGGL(cspmm_kernel, gs, dim3(256), 0, stream, d.gt_ptr, d.gt_idx, d.gt_val, w.p, S, w.t,
+                                   S, d.n_order);
+                colsq(w.t, S, S, w.tt);
+                hipLaunchKernelGGL(cgnr_upd1_kernel, dim3(ge), dim3(256), 0, stream, w.w, w.r, w.p, w.t, w.cols, w.tt,
+                                   N, S);
+                colsq(w.r, S, S, w.rn2);
+                EFIE_HIP_CHECK(hipMemsetAsync(w.counter, 0, sizeof(int), stream));
+                hipLaunchKernelGGL(cgnr_check_kernel, dim3(unsigned((S + 255) / 256)), dim3(256), 0, stream, w.cols,
+                                   w.rn2, w.tt, S, w.counter);
+                hipLaunchKernelGGL(cspmm_kernel, gs, dim3(256), 0, stream, d.g_ptr, d.g_idx, d.g_val, w.r, S, w.z, S,
+                               d.n_order);
+                colsq(w.z, S, S, w.zz);
+                hipLaunchKernelGGL(cgnr_upd2_kernel, dim3(ge), dim3(256), 0, stream, w.p, w.z, w.cols, w.zz, N, S);
+                hipLaunchKernelGGL(cgnr_gamma_kernel, dim3(unsigned((S + 255) / 256)), dim3(256), 0, stream, w.cols,
+                                   w.zz, S);
+                EFIE_HIP_CHECK(hipMemcpyAsync(&h_active, w.counter, sizeof(int), hipMemcpyDeviceToHost, stream));
+                EFIE_HIP_CHECK(hipStreamSynchronize(stream));
+            }
+            hipLaunchKernelGGL(transpose_kernel, dim3(unsigned((S + 31) / 32), unsigned((N + 31) / 32)), dim3(256), 0,
+                               stream, w.w, S, N, Pout, s0);
+            if (verbose())
+                std::fprintf(stderr, "[efie] calderon CGNR columns %d..%d done t=%.3f\n", s0, s0 + S, now_s()),
+                    std::fflush(stderr);
+            std::vector<CgnrCol> cols(static_cast<size_t>(S));
+            EFIE_HIP_CHECK(
+                hipMemcpyAsync(cols.data(), w.cols, sizeof(CgnrCol) * size_t(S), hipMemcpyDeviceToHost, stream));
+            EFIE_HIP_CHECK(hipStreamSynchronize(stream));
+            for (const auto& cc : cols) worst = std::max(worst, cc.bn2 > 0 ? std::sqrt(cc.rn2 / cc.bn2) : 0.0);
+        }
         if (relres) *relres = worst;
         EFIE_HIP_CHECK(hipGetLastError());
         return worst <= tol ? int(EFIE_OK) : int(EFIE_NOT_CONVERGED);
     });
+}
+
+int efie_calderon_assemble(efie_calderon c, double kt_re, double kt_im, double eta, void* P, void* Tbc_out,
+                           double tol, int32_t maxit, double* relres, void* ws, size_t ws_bytes, hipStream_t stream) {
+    return efie_calderon_assemble_ex(c, kt_re, kt_im, eta, EFIE_C128, P, Tbc_out, tol, maxit, relres, ws, ws_bytes,
+                                     stream);
 }
 
 }  // extern "C"

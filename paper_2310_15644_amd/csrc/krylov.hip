@@ -478,6 +478,19 @@ __global__ void iota_kernel(int* idx, int S) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < S; i += gridDim.x * blockDim.x) idx[i] = i;
 }
 
+// EFIE_VERBOSE=1 prints solver and Calderon-build progress to stderr (iteration counts, active columns, time)
+bool verbose() {
+    static int v = -1;
+    if (v < 0) {
+        const char* e = std::getenv("EFIE_VERBOSE");
+        v = (e && *e && *e != '0') ? 1 : 0;
+    }
+    return v == 1;
+}
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
 namespace {
 
 struct Ws {
@@ -493,18 +506,6 @@ struct Ws {
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
-// EFIE_VERBOSE=1 prints solver progress to stderr (iteration counts, active columns, time)
-bool verbose() {
-    static int v = -1;
-    if (v < 0) {
-        const char* e = std::getenv("EFIE_VERBOSE");
-        v = (e && *e && *e != '0') ? 1 : 0;
-    }
-    return v == 1;
-}
-double now_s() {
-    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
-}
 
 size_t layout(int64_t n, int64_t S, int dtype, Ws* ws, char* base) {
     const size_t vec = align256(size_t(n) * size_t(S) * 16);
@@ -554,8 +555,9 @@ void product(const void* Z, int zdt, int n, const double2* X, double2* Y, const 
 struct Op {
     const void* Z;
     int zdt;
-    const double2* P;
+    const void* P;   // optional left factor (dtype pdt)
     double2* tmp;
+    int pdt = EFIE_C128;
 };
 
 void op_product(const Op& op, int n, const double2* X, double2* Y, const int* idx, int m, bool exact64, const Ws& w,
@@ -565,7 +567,7 @@ void op_product(const Op& op, int n, const double2* X, double2* Y, const int* id
         return;
     }
     product(op.Z, op.zdt, n, X, op.tmp, idx, m, exact64, w, st);
-    product(op.P, EFIE_C128, n, op.tmp, Y, idx, m, true, w, st);
+    product(op.P, op.pdt, n, op.tmp, Y, idx, m, exact64 || op.pdt == EFIE_C128, w, st);
 }
 
 int compact(const Ws& w, int S, int which, int* idx, hipStream_t st) {
@@ -752,28 +754,32 @@ extern "C" int efie_solve_precond_workspace_size(int64_t n, int64_t nrhs, size_t
     return efie::guarded([&]() {
         EFIE_REQUIRE(bytes && n >= 1 && nrhs >= 1, EFIE_ERR_ARG, "solve_precond_workspace_size: bad argument");
         const size_t vec = efie::align256(size_t(n) * size_t(nrhs) * 16);
-        *bytes = efie::layout(n, nrhs, EFIE_C128, nullptr, nullptr) + 4 * vec;
+        // the complex64 staging of the mixed form is included, so one size serves both
+        *bytes = efie::layout(n, nrhs, EFIE_C64, nullptr, nullptr) + 4 * vec;
         return int(EFIE_OK);
     });
 }
 
-extern "C" int efie_solve_precond(const void* Z, const void* P, int64_t n, const void* V, void* J, int64_t nrhs,
-                                  const efie_solve_opts* opts, efie_rhs_stats* stats, void* ws, size_t ws_bytes,
-                                  hipStream_t stream) {
+extern "C" int efie_solve_precond_ex(const void* Z, int zdt, const void* P, int pdt, int64_t n, const void* V,
+                                     void* J, int64_t nrhs, const efie_solve_opts* opts, efie_rhs_stats* stats,
+                                     void* ws, size_t ws_bytes, hipStream_t stream) {
     using namespace efie;
     return guarded([&]() {
+        EFIE_REQUIRE((zdt == EFIE_C128 || zdt == EFIE_C64) && (pdt == EFIE_C128 || pdt == EFIE_C64), EFIE_ERR_ARG,
+                     "solve_precond: bad dtype");
+        const bool mixed = zdt == EFIE_C64 || pdt == EFIE_C64;
         EFIE_REQUIRE(Z && P && V && J && opts && ws, EFIE_ERR_ARG, "solve_precond: null argument");
         EFIE_REQUIRE(n >= 1 && n < (int64_t(1) << 31) && nrhs >= 1 && nrhs <= 65535, EFIE_ERR_ARG,
                      "solve_precond: bad sizes");
         EFIE_REQUIRE(opts->solver == EFIE_CGS, EFIE_ERR_ARG,
                      "solve_precond: the preconditioned operator is not symmetric; use EFIE_CGS");
         EFIE_REQUIRE(opts->maxit >= 1 && opts->tol > 0.0, EFIE_ERR_ARG, "solve_precond: need maxit >= 1 and tol > 0");
-        const size_t base = layout(n, nrhs, EFIE_C128, nullptr, nullptr);
+        const size_t base = layout(n, nrhs, EFIE_C64, nullptr, nullptr);
         const size_t vec = align256(size_t(n) * size_t(nrhs) * 16);
         EFIE_REQUIRE(ws_bytes >= base + 4 * vec, EFIE_ERR_ARG, "solve_precond: workspace too small");
         EFIE_REQUIRE((reinterpret_cast<uintptr_t>(ws) & 255) == 0, EFIE_ERR_ARG, "solve_precond: ws not aligned");
         Ws w;
-        layout(n, nrhs, EFIE_C128, &w, static_cast<char*>(ws));
+        layout(n, nrhs, EFIE_C64, &w, static_cast<char*>(ws));
         double2* tmp = reinterpret_cast<double2*>(static_cast<char*>(ws) + base);
         double2* pb = reinterpret_cast<double2*>(static_cast<char*>(ws) + base + vec);
         double2* rt = reinterpret_cast<double2*>(static_cast<char*>(ws) + base + 2 * vec);   // true residual
@@ -787,22 +793,26 @@ extern "C" int efie_solve_precond(const void* Z, const void* P, int64_t n, const
         // FP64 true residual: solve P Z d = P r for the columns still above tol, with
         // a tolerance scaled by the observed ratio of true to preconditioned
         // reduction, and add d, up to max_refine passes.
-        const Op op{Z, EFIE_C128, static_cast<const double2*>(P), tmp};
+        const Op op{Z, zdt, P, tmp, pdt};
         std::vector<Col> cols;
         std::vector<int> iters(S, 0);
         std::vector<double> recur(S, 0.0), ratio(S, 1.0), rel(S, 0.0), h_nrm(S), h_bn(S);
         const size_t tot = size_t(nn) * S;
         const int passes = std::max(1, opts->max_refine);
-        double tau = opts->tol;
+        // first pass a little below tol (the true residual is usually a few times the
+        // preconditioned one); the mixed form never asks the FP32 products for more than
+        // inner_tol per pass
+        const double floor_tau = mixed ? std::max(opts->inner_tol, 1e-13) : 1e-13;
+        double tau = std::max(0.25 * opts->tol, floor_tau);
         for (int pass = 0; pass < passes; ++pass) {
             const double2* rhs = pass == 0 ? b : rt;
-            product(P, EFIE_C128, nn, rhs, pb, w.idx_all, S, true, w, stream);
+            product(P, pdt, nn, rhs, pb, w.idx_all, S, true, w, stream);
             double2* dst = pass == 0 ? x : dl;
             krylov(op, nn, pb, dst, S, EFIE_CGS, tau, opts->maxit, false, w, cols, stream);
             if (pass > 0)
                 hipLaunchKernelGGL(axpy_inplace_kernel, dim3(int(std::min<size_t>((tot + 255) / 256, 16384))),
                                    dim3(256), 0, stream, x, dl, tot);
-            true_residual(Z, EFIE_C128, nn, b, x, rt, S, w, stream);
+            true_residual(Z, zdt, nn, b, x, rt, S, w, stream);
             EFIE_HIP_CHECK(hipMemcpyAsync(h_nrm.data(), w.nrm, sizeof(double) * S, hipMemcpyDeviceToHost, stream));
             EFIE_HIP_CHECK(hipMemcpyAsync(h_bn.data(), w.bnrm, sizeof(double) * S, hipMemcpyDeviceToHost, stream));
             EFIE_HIP_CHECK(hipStreamSynchronize(stream));
@@ -826,7 +836,7 @@ extern "C" int efie_solve_precond(const void* Z, const void* P, int64_t n, const
                              *std::max_element(rel.begin(), rel.end())),
                     std::fflush(stderr);
             if (done) break;
-            tau = std::max(need, 1e-13);
+            tau = std::max(need, floor_tau);
             // columns already converged get a zero right-hand side (no further work)
             hipLaunchKernelGGL(zero_done_kernel, dim3(S), dim3(KB), 0, stream, rt, w.nrm, w.bnrm, opts->tol, nn);
         }
@@ -845,4 +855,10 @@ extern "C" int efie_solve_precond(const void* Z, const void* P, int64_t n, const
         }
         return ret;
     });
+}
+
+extern "C" int efie_solve_precond(const void* Z, const void* P, int64_t n, const void* V, void* J, int64_t nrhs,
+                                  const efie_solve_opts* opts, efie_rhs_stats* stats, void* ws, size_t ws_bytes,
+                                  hipStream_t stream) {
+    return efie_solve_precond_ex(Z, EFIE_C128, P, EFIE_C128, n, V, J, nrhs, opts, stats, ws, ws_bytes, stream);
 }

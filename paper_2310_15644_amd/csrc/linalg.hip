@@ -573,3 +573,22 @@ void zgemm_nt(const void* A, int adt, const void* B, int bdt, void* C, int cdt, 
 }
 
 }  // namespace efie
+
+extern "C" int efie_convert(const void* src, int src_dtype, void* dst, int dst_dtype, int64_t count, hipStream_t stream) {
+    return efie::guarded([&]() {
+        EFIE_REQUIRE(src && dst && count >= 0, EFIE_ERR_ARG, "convert: bad argument");
+        EFIE_REQUIRE((src_dtype == EFIE_C128 || src_dtype == EFIE_C64) && (dst_dtype == EFIE_C128 || dst_dtype == EFIE_C64),
+                     EFIE_ERR_ARG, "convert: bad dtype");
+        const size_t n = size_t(count);
+        if (src_dtype == dst_dtype) {
+            EFIE_HIP_CHECK(hipMemcpyAsync(dst, src, n * (src_dtype == EFIE_C128 ? 16 : 8), hipMemcpyDeviceToDevice,
+                                          stream));
+        } else if (src_dtype == EFIE_C128) {
+            efie::cast_c128_to_c64(src, dst, n, stream);
+        } else {
+            efie::cast_c64_to_c128(src, dst, n, stream);
+        }
+        EFIE_HIP_CHECK(hipGetLastError());
+        return int(EFIE_OK);
+    });
+}

@@ -103,3 +103,38 @@ def test_calderon_l4_iteration_counts(dev, k):
     err = float((Jc - Jq).norm() / Jq.norm())
     flush(f"  current difference Calderon vs plain COCG: {err:.2e}")
     assert err <= 1e-3
+
+
+def test_calderon_c64_bary_and_mixed_solve(dev):
+    """Level 3 (N = 1920), k = 3, 16 plane waves: P from FP32 barycentric far pairs
+    against the FP64 build, and the mixed preconditioned solve (complex64 Z and P,
+    FP32 matrix-core products inside CGS, FP64 true-residual refinement) against the
+    FP64 one."""
+    flush("calderon L3 complex64 variants")
+    v, f = icosphere(3)
+    m = P.Mesh(v, f).upload(dev)
+    cal = P.Calderon(m).upload(dev)
+    k = 3.0
+    P64 = cal.assemble(P.ktilde(k), tol=1e-10)
+    P32b = cal.assemble(P.ktilde(k), tol=1e-10, bary_dtype=P.C64)
+    d = float((P32b - P64).abs().max() / P64.abs().max())
+    flush(f"  P with FP32 barycentric pairs vs FP64: {d:.2e}")
+    assert d <= 1e-5
+    # efie_convert round trip: complex128 -> complex64 -> complex128 is rounding only
+    P32 = P.convert(P64, P.C64)
+    back = P.convert(P32, P.C128)
+    assert float((back - P64).abs().max() / P64.abs().max()) <= 1e-7
+    assert torch.equal(P.convert(P32, P.C64), P32)
+    rhat, khat, pol, _, _ = synth.monostatic_grid(4, 4)
+    V = P.excite_planewave(m, k, khat, pol)
+    Z64 = P.assemble(m, k)
+    Z32 = P.assemble(m, k, dtype=P.C64)
+    J64, st64 = P.solve_precond(Z64, P64, V, tol=1e-6, maxit=500)
+    J32, st32 = P.solve_precond(Z32, P32, V, tol=1e-6, maxit=500, inner_tol=1e-3)
+    flush(f"  FP64 iters max {st64.iters.max()}, mixed iters max {st32.iters.max()}, "
+          f"mixed true relres max {st32.relres_true.max():.2e}")
+    assert np.all(st64.status == 0) and np.all(st32.status == 0)
+    assert st64.relres_true.max() <= 1e-6 and st32.relres_true.max() <= 1e-6
+    err = float((torch.linalg.norm(J32 - J64, dim=1) / torch.linalg.norm(J64, dim=1)).max())
+    flush(f"  mixed vs FP64 currents: {err:.2e}")
+    assert err <= 1e-4
