@@ -9,8 +9,12 @@ FP32, near pairs in FP64), COCG with Z X on FP32 matrix cores, FP64 outer
 refinement to ||V - Z J|| <= 1e-6 ||V|| per right-hand side.
 
 One step = the whole hot path on inputs already resident in HBM:
-assembly (far + near), excitation of the 512 right-hand sides, the multi-RHS
-solve, and the far field in the 512 monostatic directions.
+assembly (far + near), excitation of the 512 right-hand sides, the Calderon
+preconditioner P = T_BC(k~) G_mix^-1 (barycentric second operator at the complex
+wavenumber, mixed Gram inverse), the preconditioned multi-RHS solve (CGS on
+P Z J = P V, complex64 Z and P on FP32 matrix cores, FP64 true-residual
+refinement; --solver cocg: unpreconditioned COCG instead), and the far field in
+the 512 monostatic directions.
 
 Printed JSON line: `value` is the complex Z.X throughput (8 M N K real flops per
 launch / mean launch time, HIP events around every launch inside the timed
@@ -100,7 +104,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cgemm_mfma_acc64_l5_k10_512rhs_hb
 GEMM_SOURCE = os.path.join(ROOT, "paper_2310_15644_amd", "csrc", "gemm_mfma.hip")
 
 
-def measured_traffic(tiles, n, nrhs):
+def measured_traffic(tiles, n, nrhs, solver):
     """HBM bytes per launch of the in-solve matrix-core GEMM, from the committed
     rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE per dispatch, each divided
     by the factor the same counter reads for a plain 1 GiB copy).  None when the
@@ -117,7 +121,8 @@ def measured_traffic(tiles, n, nrhs):
             kv[key.strip()] = val.strip().strip("`")
     sha = hashlib.sha256(open(GEMM_SOURCE, "rb").read()).hexdigest()
     want = f"cgemm_mfma_kernel<{tiles[0]}, {tiles[1]}, {tiles[2]}, true>"
-    if kv.get("gemm_source_sha256") != sha or kv.get("kernel") != want or kv.get("workload") != f"n={n} nrhs={nrhs}":
+    if (kv.get("gemm_source_sha256") != sha or kv.get("kernel") != want
+            or kv.get("workload") != f"n={n} nrhs={nrhs} solver={solver}"):
         return None, None
     return float(kv["hbm_bytes_per_launch"]), os.path.relpath(TRAFFIC_FILE, ROOT)
 
@@ -294,6 +299,9 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--maxit", type=int, default=3000)
     ap.add_argument("--dtype", choices=["c64", "c128"], default="c64")
+    ap.add_argument("--solver", choices=["calderon", "cocg"], default="calderon",
+                    help="calderon: CGS on P Z J = P V with P = T_BC(k~) G_mix^-1 built in the step (default); "
+                         "cocg: unpreconditioned COCG")
     ap.add_argument("--workload", choices=["sphere", "ellipsoids", "calderon", "mixed-fp64"], default="sphere",
                     help="sphere: the 512-RHS level-5 sphere (default); ellipsoids: 64 uneven ellipsoids; "
                          "calderon: level-4 Calderon vs plain CGS; mixed-fp64: level-5 mixed vs FP64 path")
@@ -349,18 +357,34 @@ def main():
     def sync():
         torch.cuda.synchronize()
 
+    cal = None
+    if args.solver == "calderon":
+        cal = P.Calderon(m).upload(dev)        # host refinement and BC tables: mesh preprocessing
+        log(f"bench: Calderon tables: {cal.n_bary} barycentric RWGs")
+
     def step(rec):
         t0 = time.perf_counter()
         P.assemble(m, args.k, dtype=dt, out=Z)
         P.excite_planewave(m, args.k, kh_d, po_d, out=V)
-        _, st = P.solve(Z, V, solver=P.COCG, tol=args.tol, maxit=args.maxit, max_refine=6, inner_tol=1e-3, out=J)
+        tb = 0.0
+        if cal is not None:
+            Pm = cal.assemble(P.ktilde(args.k), tol=1e-6, bary_dtype=P.C64)
+            if dt == P.C64:
+                Pm = P.convert(Pm, P.C64)
+            sync()
+            tb = time.perf_counter() - t0
+            _, st = P.solve_precond(Z, Pm, V, tol=args.tol, maxit=args.maxit, inner_tol=1e-3, out=J)
+            del Pm
+        else:
+            _, st = P.solve(Z, V, solver=P.COCG, tol=args.tol, maxit=args.maxit, max_refine=6, inner_tol=1e-3,
+                            out=J)
         sync()
         t1 = time.perf_counter()
         F = P.farfield(m, args.k, J, rh_d)
         sync()
         t2 = time.perf_counter()
-        rec.append({"solve_s": t1 - t0, "step_s": t2 - t0, "iters": st.iters, "relres": st.relres_true,
-                    "status": st.status, "F": F})
+        rec.append({"solve_s": t1 - t0, "step_s": t2 - t0, "build_s": tb, "iters": st.iters,
+                    "relres": st.relres_true, "status": st.status, "F": F})
 
     warm = []
     for i in range(args.warmup):
@@ -413,7 +437,10 @@ def main():
         "config": {
             "workload": f"PEC unit sphere icosphere level {args.level} (N={N} RWG), k={args.k}, "
                         f"{S} plane waves on a {args.ntheta}x{args.nphi} (theta,phi) grid, monostatic; "
-                        f"{'mixed precision (complex64 Z, FP32 MFMA, FP64 refinement)' if dt == P.C64 else 'FP64'}",
+                        f"{'mixed precision (complex64 Z, FP32 MFMA, FP64 refinement)' if dt == P.C64 else 'FP64'}; "
+                        + ("Calderon-preconditioned CGS (P = T_BC(k~) G_mix^-1 built in the step)"
+                           if args.solver == "calderon" else "unpreconditioned COCG"),
+            "solver": args.solver,
             "n_unknowns": N,
             "nrhs": S,
             "k": args.k,
@@ -425,6 +452,8 @@ def main():
         "assembly_mentries_per_s": round(mentries, 1),
         "assembly_ms": round(asm_ms, 3),
         "time_to_solve_s": round(tts, 3),
+        "calderon_build_s": round(float(np.mean([r["build_s"] for r in rec])), 3) if args.solver == "calderon"
+        else None,
         "iters_max": int(np.max(last["iters"])),
         "iters_mean": round(float(np.mean(last["iters"])), 1),
         "relres_true_max": float(np.max(last["relres"])),
@@ -454,7 +483,7 @@ def main():
     }
     tiles_acc64 = None if tuning is None else tuning["tiles"][tuning["acc64"]]
     out["roofline"]["traffic"], out["roofline"]["traffic_source"] = measured_traffic(
-        tiles_acc64, out["config"]["n_unknowns"], S)
+        tiles_acc64, out["config"]["n_unknowns"], S, args.solver)
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(args.level, 2048, S, args.k, args.cpu_seconds)
