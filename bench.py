@@ -100,11 +100,12 @@ def cpu_baseline(level, n_sample_rows, nrhs, k, seconds):
     }
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cgemm_mfma_acc64_l5_k10_512rhs_hbm_traffic.md")
+TRAFFIC_FILES = {False: os.path.join(ROOT, "profiles", "cgemm_mfma_acc32_l5_k10_512rhs_hbm_traffic.md"),
+                 True: os.path.join(ROOT, "profiles", "cgemm_mfma_acc64_l5_k10_512rhs_hbm_traffic.md")}
 GEMM_SOURCE = os.path.join(ROOT, "paper_2310_15644_amd", "csrc", "gemm_mfma.hip")
 
 
-def measured_traffic(tiles, n, nrhs, solver):
+def measured_traffic(tiles, acc64, n, nrhs, solver):
     """HBM bytes per launch of the in-solve matrix-core GEMM, from the committed
     rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE per dispatch, each divided
     by the factor the same counter reads for a plain 1 GiB copy).  None when the
@@ -112,19 +113,20 @@ def measured_traffic(tiles, n, nrhs, solver):
     since the counters were taken."""
     import hashlib
 
-    if tiles is None or not os.path.exists(TRAFFIC_FILE):
+    path = TRAFFIC_FILES[bool(acc64)]
+    if tiles is None or not os.path.exists(path):
         return None, None
     kv = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if line.startswith("- ") and ": " in line:
             key, val = line[2:].split(": ", 1)
             kv[key.strip()] = val.strip().strip("`")
     sha = hashlib.sha256(open(GEMM_SOURCE, "rb").read()).hexdigest()
-    want = f"cgemm_mfma_kernel<{tiles[0]}, {tiles[1]}, {tiles[2]}, true>"
+    want = f"cgemm_mfma_kernel<{tiles[0]}, {tiles[1]}, {tiles[2]}, {'true' if acc64 else 'false'}>"
     if (kv.get("gemm_source_sha256") != sha or kv.get("kernel") != want
             or kv.get("workload") != f"n={n} nrhs={nrhs} solver={solver}"):
         return None, None
-    return float(kv["hbm_bytes_per_launch"]), os.path.relpath(TRAFFIC_FILE, ROOT)
+    return float(kv["hbm_bytes_per_launch"]), os.path.relpath(path, ROOT)
 
 
 def copy_calibration(torch):
@@ -351,6 +353,9 @@ def main():
                     help="sphere: the 512-RHS level-5 sphere (default); ellipsoids: 64 uneven ellipsoids; "
                          "calderon: level-4 Calderon vs plain CGS; mixed-fp64: level-5 mixed vs FP64 path; "
                          "gradient: level-4 adjoint vertex gradient")
+    ap.add_argument("--fp32-acc", action="store_true",
+                    help="mixed solve: accumulate the matrix-core products in FP32 instead of flushing "
+                         "the partial sums into FP64 every K chunk")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -423,11 +428,12 @@ def main():
                 Pm = P.convert(Pm, P.C64)
             sync()
             tb = time.perf_counter() - t0
-            _, st = P.solve_precond(Z, Pm, V, tol=args.tol, maxit=args.maxit, inner_tol=1e-3, out=J)
+            _, st = P.solve_precond(Z, Pm, V, tol=args.tol, maxit=args.maxit, inner_tol=1e-3, fp32_acc=args.fp32_acc,
+                                    out=J)
             del Pm
         else:
             _, st = P.solve(Z, V, solver=P.COCG, tol=args.tol, maxit=args.maxit, max_refine=6, inner_tol=1e-3,
-                            out=J)
+                            fp32_acc=args.fp32_acc, out=J)
         sync()
         t1 = time.perf_counter()
         F = P.farfield(m, args.k, J, rh_d)
@@ -487,10 +493,13 @@ def main():
         "config": {
             "workload": f"PEC unit sphere icosphere level {args.level} (N={N} RWG), k={args.k}, "
                         f"{S} plane waves on a {args.ntheta}x{args.nphi} (theta,phi) grid, monostatic; "
-                        f"{'mixed precision (complex64 Z, FP32 MFMA, FP64 refinement)' if dt == P.C64 else 'FP64'}; "
+                        + ((f"mixed precision (complex64 Z, FP32 MFMA with "
+                            f"{'FP32 accumulation' if args.fp32_acc else 'FP64 flushes'}, FP64 refinement)")
+                           if dt == P.C64 else "FP64") + "; "
                         + ("Calderon-preconditioned CGS (P = T_BC(k~) G_mix^-1 built in the step)"
                            if args.solver == "calderon" else "unpreconditioned COCG"),
             "solver": args.solver,
+            "accumulation": ("fp32" if args.fp32_acc else "fp64-flush") if dt == P.C64 else "fp64",
             "n_unknowns": N,
             "nrhs": S,
             "k": args.k,
@@ -531,9 +540,12 @@ def main():
         "gemm_tiles": None if tuning is None else {"acc32": tuning["tiles"][tuning["acc32"]],
                                                    "acc64": tuning["tiles"][tuning["acc64"]], "ms": tuning["ms"]},
     }
-    tiles_acc64 = None if tuning is None else tuning["tiles"][tuning["acc64"]]
+    tiles = None if tuning is None else tuning["tiles"][tuning["acc32" if args.fp32_acc else "acc64"]]
+    out["roofline"]["kernel"] = (None if tiles is None else
+                                 f"cgemm_mfma_kernel<{tiles[0]}, {tiles[1]}, {tiles[2]}, "
+                                 f"{'false' if args.fp32_acc else 'true'}>")
     out["roofline"]["traffic"], out["roofline"]["traffic_source"] = measured_traffic(
-        tiles_acc64, out["config"]["n_unknowns"], S, args.solver)
+        tiles, not args.fp32_acc, out["config"]["n_unknowns"], S, args.solver)
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(args.level, 2048, S, args.k, args.cpu_seconds)

@@ -238,6 +238,9 @@ typedef struct {
     double tol;           /* target ||V - Z J||_2 / ||V||_2 per right-hand side      */
     int32_t max_refine;   /* EFIE_C64 only: outer refinement steps (>= 1)            */
     double inner_tol;     /* EFIE_C64 only: relative tolerance of each inner solve   */
+    int32_t fp32_acc;     /* EFIE_C64 only: 0 (default) = flush the FP32 matrix-core */
+                          /* partial sums into FP64 every K chunk; 1 = accumulate in */
+                          /* FP32 (faster products, more Krylov iterations)          */
 } efie_solve_opts;
 
 typedef struct {
@@ -255,8 +258,8 @@ typedef struct {
  *   complex128 (output).  FP64 vectors and inner products in both cases.
  *   EFIE_C128: one Krylov solve with FP64 products.
  *   EFIE_C64 : mixed precision -- Z X products of more than 8 active columns run
- *              on FP32 matrix cores with FP64 accumulation of 16-element partial
- *              sums; COCG replaces its recursive residual by the true residual
+ *              on FP32 matrix cores with FP64 accumulation of the K-chunk partial
+ *              sums (opts->fp32_acc = 1: FP32 accumulation); COCG replaces its recursive residual by the true residual
  *              V - Z J (FP64 accumulation from the stored complex64 Z) whenever it
  *              has dropped tenfold (reliable updates) and converges only on it;
  *              CGS runs inner solves to inner_tol inside an outer refinement loop

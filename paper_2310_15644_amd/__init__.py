@@ -60,7 +60,7 @@ class EfieError(RuntimeError):
 
 class _SolveOpts(ctypes.Structure):
     _fields_ = [("solver", ctypes.c_int32), ("maxit", ctypes.c_int32), ("tol", ctypes.c_double),
-                ("max_refine", ctypes.c_int32), ("inner_tol", ctypes.c_double)]
+                ("max_refine", ctypes.c_int32), ("inner_tol", ctypes.c_double), ("fp32_acc", ctypes.c_int32)]
 
 
 class _RhsStats(ctypes.Structure):
@@ -396,8 +396,10 @@ class SolveStats:
     code: int
 
 
-def solve(Z, V, solver=COCG, tol=1e-8, maxit=1000, max_refine=4, inner_tol=1e-3, out=None):
-    """Solve Z J = V for V (nrhs, N) complex128; Z complex128 (FP64) or complex64 (mixed)."""
+def solve(Z, V, solver=COCG, tol=1e-8, maxit=1000, max_refine=4, inner_tol=1e-3, fp32_acc=False, out=None):
+    """Solve Z J = V for V (nrhs, N) complex128; Z complex128 (FP64) or complex64 (mixed:
+    FP32 matrix-core products with their partial sums flushed into FP64 every K chunk,
+    or with fp32_acc accumulated in FP32)."""
     torch = _torch()
     code_dt, _ = _cdtype(Z.dtype)
     _require_cuda(Z, "Z")
@@ -412,7 +414,7 @@ def solve(Z, V, solver=COCG, tol=1e-8, maxit=1000, max_refine=4, inner_tol=1e-3,
     _check(lib().efie_solve_workspace_size(n, S, code_dt, ctypes.byref(nb)))
     ws = torch.empty(nb.value + 256, dtype=torch.uint8, device=Z.device)
     off = (-ws.data_ptr()) % 256
-    opts = _SolveOpts(int(solver), int(maxit), float(tol), int(max_refine), float(inner_tol))
+    opts = _SolveOpts(int(solver), int(maxit), float(tol), int(max_refine), float(inner_tol), int(bool(fp32_acc)))
     st = (_RhsStats * S)()
     code = lib().efie_solve(_ptr(Z), code_dt, n, _ptr(V), _ptr(J), S, ctypes.byref(opts), st,
                             ctypes.c_void_p(ws.data_ptr() + off), nb.value, _stream(Z.device))
@@ -585,12 +587,12 @@ class Calderon:
             self._h = None
 
 
-def solve_precond(Z, Pm, V, tol=1e-8, maxit=1000, max_refine=6, inner_tol=1e-4, out=None):
+def solve_precond(Z, Pm, V, tol=1e-8, maxit=1000, max_refine=6, inner_tol=1e-4, fp32_acc=False, out=None):
     """CGS on P Z J = P V with outer refinement on the unpreconditioned FP64 true
     residual (up to max_refine passes); Z and P complex128 (FP64 throughout) or
-    complex64 (FP32 matrix-core products inside CGS, each pass to at least
-    inner_tol).  Stats report the true residual and the iterations summed over
-    the passes."""
+    complex64 (FP32 matrix-core products inside CGS, flushed into FP64 per K chunk
+    or with fp32_acc accumulated in FP32; each pass to at least inner_tol).  Stats report the
+    true residual and the iterations summed over the passes."""
     torch = _torch()
     _require_cuda(Z, "Z")
     _require_cuda(Pm, "P")
@@ -605,7 +607,7 @@ def solve_precond(Z, Pm, V, tol=1e-8, maxit=1000, max_refine=6, inner_tol=1e-4, 
     _check(lib().efie_solve_precond_workspace_size(n, S, ctypes.byref(nb)))
     ws = torch.empty(nb.value + 256, dtype=torch.uint8, device=Z.device)
     off = (-ws.data_ptr()) % 256
-    opts = _SolveOpts(CGS, int(maxit), float(tol), int(max_refine), float(inner_tol))
+    opts = _SolveOpts(CGS, int(maxit), float(tol), int(max_refine), float(inner_tol), int(bool(fp32_acc)))
     st = (_RhsStats * S)()
     code = lib().efie_solve_precond_ex(_ptr(Z), zdt, _ptr(Pm), pdt, n, _ptr(V), _ptr(J), S, ctypes.byref(opts), st,
                                        ctypes.c_void_p(ws.data_ptr() + off), nb.value, _stream(Z.device))
@@ -667,7 +669,7 @@ class Batch:
         torch = _torch()
         code, _ = _cdtype(Zcat.dtype)
         J = out if out is not None else torch.empty(self.v_elems, dtype=torch.complex128, device=self.device)
-        opts = _SolveOpts(COCG, int(maxit), float(tol), 1, 1e-3)
+        opts = _SolveOpts(COCG, int(maxit), float(tol), 1, 1e-3, 0)
         st = (_RhsStats * len(self.meshes))()
         rc = lib().efie_batch_solve(self._h, _ptr(Zcat), code, _ptr(Vcat), _ptr(J), ctypes.byref(opts), st,
                                     self._ws_ptr, self.ws_bytes, _stream(self.device))

@@ -497,6 +497,8 @@ struct Ws {
     double2 *r, *rt, *u, *p, *q, *v, *w;   // Krylov vectors (S x n each)
     double2 *res, *dlt;                     // outer refinement (CGS, mixed): residual and correction
     float2* x32;                            // complex64 staging of the product input
+    float2* y32;                            // complex64 product output (FP32 accumulation)
+    bool acc64;                             // FP64 flush of the matrix-core partial sums
     double2* part;                          // partial sums of the K-split product of <= 8 columns
     Col* cols;
     double *nrm, *bnrm;
@@ -522,6 +524,7 @@ size_t layout(int64_t n, int64_t S, int dtype, Ws* ws, char* base) {
     w.q = (double2*)take(vec); w.v = (double2*)take(vec); w.w = (double2*)take(vec);
     w.res = (double2*)take(outer); w.dlt = (double2*)take(outer);
     w.x32 = (float2*)take(vec32);
+    w.y32 = (float2*)take(vec32);
     w.part = (double2*)take(gemv_multi_part_bytes(int(n)));
     w.cols = (Col*)take(sizeof(Col) * size_t(S));
     w.nrm = (double*)take(sizeof(double) * size_t(S));
@@ -536,7 +539,9 @@ size_t layout(int64_t n, int64_t S, int dtype, Ws* ws, char* base) {
 
 // Y[idx[c]] = Z X[idx[c]] for the m listed columns.  exact64: FP64 accumulation
 // for every m (true residuals); otherwise complex64 Z with m > 8 uses the FP32
-// matrix cores on complex64 copies of the columns.
+// matrix cores on complex64 copies of the columns, accumulating in FP32 (the
+// complex64 result is then widened into the rows) or, with w.acc64, flushing the
+// partial sums of every K chunk into FP64 accumulators.
 void product(const void* Z, int zdt, int n, const double2* X, double2* Y, const int* idx, int m, bool exact64,
              const Ws& w, hipStream_t st) {
     if (m <= 0) return;
@@ -544,7 +549,12 @@ void product(const void* Z, int zdt, int n, const double2* X, double2* Y, const 
         gemv_multi(Z, zdt, n, X, idx, m, Y, st, w.part);
     } else if (zdt == EFIE_C64 && !exact64) {
         gather_cast(X, idx, m, n, w.x32, st);
-        cgemm_mfma_acc64(w.x32, Z, Y, idx, m, n, st);
+        if (w.acc64) {
+            cgemm_mfma_acc64(w.x32, Z, Y, idx, m, n, st);
+        } else {
+            cgemm_mfma(w.x32, Z, w.y32, m, n, st);
+            scatter_cast(w.y32, idx, m, n, Y, st);
+        }
     } else {
         zgemm_nt(X, EFIE_C128, Z, zdt, Y, EFIE_C128, m, n, n, n, n, n, 1.0, 0.0, false, st, idx, idx);
     }
@@ -671,6 +681,7 @@ extern "C" int efie_solve(const void* Z, int dtype, int64_t n, const void* V, vo
         EFIE_REQUIRE((reinterpret_cast<uintptr_t>(ws) & 255) == 0, EFIE_ERR_ARG, "solve: workspace not 256-aligned");
         Ws w;
         layout(n, nrhs, dtype, &w, static_cast<char*>(ws));
+        w.acc64 = opts->fp32_acc == 0;
         const int S = int(nrhs), nn = int(n);
         hipLaunchKernelGGL(iota_kernel, dim3((S + 255) / 256), dim3(256), 0, stream, w.idx_all, S);
         const double2* b = static_cast<const double2*>(V);
@@ -780,6 +791,7 @@ extern "C" int efie_solve_precond_ex(const void* Z, int zdt, const void* P, int 
         EFIE_REQUIRE((reinterpret_cast<uintptr_t>(ws) & 255) == 0, EFIE_ERR_ARG, "solve_precond: ws not aligned");
         Ws w;
         layout(n, nrhs, EFIE_C64, &w, static_cast<char*>(ws));
+        w.acc64 = opts->fp32_acc == 0;
         double2* tmp = reinterpret_cast<double2*>(static_cast<char*>(ws) + base);
         double2* pb = reinterpret_cast<double2*>(static_cast<char*>(ws) + base + vec);
         double2* rt = reinterpret_cast<double2*>(static_cast<char*>(ws) + base + 2 * vec);   // true residual

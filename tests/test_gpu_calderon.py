@@ -105,12 +105,13 @@ def test_calderon_l4_iteration_counts(dev, k):
     assert err <= 1e-3
 
 
-def test_calderon_c64_bary_and_mixed_solve(dev):
+@pytest.mark.parametrize("fp32_acc", [False, True])
+def test_calderon_c64_bary_and_mixed_solve(dev, fp32_acc):
     """Level 3 (N = 1920), k = 3, 16 plane waves: P from FP32 barycentric far pairs
     against the FP64 build, and the mixed preconditioned solve (complex64 Z and P,
     FP32 matrix-core products inside CGS, FP64 true-residual refinement) against the
     FP64 one."""
-    flush("calderon L3 complex64 variants")
+    flush(f"calderon L3 complex64 variants fp32_acc={fp32_acc}")
     v, f = icosphere(3)
     m = P.Mesh(v, f).upload(dev)
     cal = P.Calderon(m).upload(dev)
@@ -130,7 +131,7 @@ def test_calderon_c64_bary_and_mixed_solve(dev):
     Z64 = P.assemble(m, k)
     Z32 = P.assemble(m, k, dtype=P.C64)
     J64, st64 = P.solve_precond(Z64, P64, V, tol=1e-6, maxit=500)
-    J32, st32 = P.solve_precond(Z32, P32, V, tol=1e-6, maxit=500, inner_tol=1e-3)
+    J32, st32 = P.solve_precond(Z32, P32, V, tol=1e-6, maxit=500, inner_tol=1e-3, fp32_acc=fp32_acc)
     flush(f"  FP64 iters max {st64.iters.max()}, mixed iters max {st32.iters.max()}, "
           f"mixed true relres max {st32.relres_true.max():.2e}")
     assert np.all(st64.status == 0) and np.all(st32.status == 0)

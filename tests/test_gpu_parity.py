@@ -313,12 +313,14 @@ def test_end_to_end_l2_rcs(dev, l2_system):
         assert np.max(np.abs(10 * np.log10(s_g / s_m))) <= 0.5     # L2 discretisation vs Mie
 
 
+@pytest.mark.parametrize("fp32_acc", [False, True])
 @pytest.mark.parametrize("solver", ["cocg", "cgs"])
-def test_solve_mixed_many_rhs_matrix_cores(dev, solver):
+def test_solve_mixed_many_rhs_matrix_cores(dev, solver, fp32_acc):
     """16 right-hand sides: the mixed-precision solve runs its products on the FP32
-    matrix cores (more than 8 active columns) and must still reach the FP64-accumulated
-    true residual, with currents close to the FP64 solution."""
-    flush(f"mixed 16-rhs {solver}")
+    matrix cores (more than 8 active columns; FP64 flushes per K chunk, or FP32
+    accumulation) and must still reach the FP64-accumulated true residual, with currents
+    close to the FP64 solution."""
+    flush(f"mixed 16-rhs {solver} fp32_acc={fp32_acc}")
     v, f = icosphere(3)
     m = gmesh(v, f, dev)
     k = 2.0
@@ -327,7 +329,7 @@ def test_solve_mixed_many_rhs_matrix_cores(dev, solver):
     Z64 = P.assemble(m, k)
     V = P.excite_planewave(m, k, khat, pol)
     code = P.COCG if solver == "cocg" else P.CGS
-    J32, st32 = P.solve(Z32, V, solver=code, tol=1e-7, maxit=2000, max_refine=8, inner_tol=1e-2)
+    J32, st32 = P.solve(Z32, V, solver=code, tol=1e-7, maxit=2000, max_refine=8, inner_tol=1e-2, fp32_acc=fp32_acc)
     J64, st64 = P.solve(Z64, V, solver=code, tol=1e-10, maxit=2000)
     assert np.all(st32.status == 0) and np.all(st32.relres_true <= 1e-7), st32
     err = float((J32 - J64).norm() / J64.norm())
