@@ -100,8 +100,8 @@ def cpu_baseline(level, n_sample_rows, nrhs, k, seconds):
     }
 
 
-TRAFFIC_FILES = {False: os.path.join(ROOT, "profiles", "cgemm_mfma_acc32_l5_k10_512rhs_hbm_traffic.md"),
-                 True: os.path.join(ROOT, "profiles", "cgemm_mfma_acc64_l5_k10_512rhs_hbm_traffic.md")}
+TRAFFIC_FILES = {False: os.path.join(ROOT, "profiles", "cgemm_planar_fp32acc_l5_k10_512rhs_hbm_traffic.md"),
+                 True: os.path.join(ROOT, "profiles", "cgemm_planar_flush64_l5_k10_512rhs_hbm_traffic.md")}
 GEMM_SOURCE = os.path.join(ROOT, "paper_2310_15644_amd", "csrc", "gemm_mfma.hip")
 
 
@@ -122,7 +122,9 @@ def measured_traffic(tiles, acc64, n, nrhs, solver):
             key, val = line[2:].split(": ", 1)
             kv[key.strip()] = val.strip().strip("`")
     sha = hashlib.sha256(open(GEMM_SOURCE, "rb").read()).hexdigest()
-    want = f"cgemm_mfma_kernel<{tiles[0]}, {tiles[1]}, {tiles[2]}, {'true' if acc64 else 'false'}>"
+    from paper_2310_15644_amd import gemm_kernel_name
+
+    want = gemm_kernel_name(tiles, acc64)
     if (kv.get("gemm_source_sha256") != sha or kv.get("kernel") != want
             or kv.get("workload") != f"n={n} nrhs={nrhs} solver={solver}"):
         return None, None
@@ -541,9 +543,7 @@ def main():
                                                    "acc64": tuning["tiles"][tuning["acc64"]], "ms": tuning["ms"]},
     }
     tiles = None if tuning is None else tuning["tiles"][tuning["acc32" if args.fp32_acc else "acc64"]]
-    out["roofline"]["kernel"] = (None if tiles is None else
-                                 f"cgemm_mfma_kernel<{tiles[0]}, {tiles[1]}, {tiles[2]}, "
-                                 f"{'false' if args.fp32_acc else 'true'}>")
+    out["roofline"]["kernel"] = None if tiles is None else P.gemm_kernel_name(tiles, not args.fp32_acc)
     out["roofline"]["traffic"], out["roofline"]["traffic_source"] = measured_traffic(
         tiles, not args.fp32_acc, out["config"]["n_unknowns"], S, args.solver)
     if not args.no_cpu_baseline:

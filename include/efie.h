@@ -211,11 +211,24 @@ int efie_vertex_grad(efie_mesh mesh, double k, double eta, const void* J, const 
 int efie_zx(const void* Z, int dtype, int64_t n, const void* X, void* Y, int64_t nrhs,
             hipStream_t stream);
 
+/*
+ * The mixed solves' product as a call of its own: Y = Z X with Z complex64
+ * (n x n) and X, Y complex128 (nrhs, n).  X is rounded to complex64 and
+ * multiplied on the FP32 matrix cores with the partial sums of every K chunk
+ * flushed into FP64 accumulators; Y is written in complex128.  Any nrhs >= 1
+ * takes the matrix cores here.  ws: dev scratch of at least
+ * efie_zx_flush64_workspace_size bytes, 16-byte aligned.  Y must not overlap X.
+ */
+int efie_zx_flush64_workspace_size(int64_t n, int64_t nrhs, size_t* bytes);
+int efie_zx_flush64(const void* Z, int64_t n, const void* X, void* Y, int64_t nrhs, void* ws,
+                    size_t ws_bytes, hipStream_t stream);
+
 /* ------------------------------------------------------- GEMM autotuning */
 
 /*
  * The complex64 matrix-core GEMM has several tile shapes (block tile of BM
- * right-hand sides x BN real columns, K chunk KC), for two paths: complex64
+ * right-hand sides x BN unknowns, K chunk KC of complex elements), for two
+ * paths: complex64
  * output (efie_zx) and FP64-flushed output into the Krylov vectors (solves).
  * efie_gemm_autotune times every variant on the caller's Z (n x n complex64) and
  * X (M x n complex64) with HIP events (reps launches each, after one warm-up),

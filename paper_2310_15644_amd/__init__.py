@@ -41,6 +41,7 @@ EXPORTED = [
     "efie_farfield_workspace_size", "efie_farfield", "efie_zx", "efie_solve_workspace_size", "efie_solve",
     "efie_prof_enable", "efie_prof_reset", "efie_prof_read",
     "efie_gemm_variants", "efie_gemm_variant_info", "efie_gemm_autotune", "efie_gemm_select",
+    "efie_zx_flush64_workspace_size", "efie_zx_flush64",
     "efie_calderon_create", "efie_calderon_destroy", "efie_calderon_sizes", "efie_calderon_upload",
     "efie_calderon_host_matrices", "efie_calderon_assemble", "efie_solve_precond_workspace_size", "efie_solve_precond",
     "efie_batch_create", "efie_batch_destroy", "efie_batch_sizes", "efie_batch_upload", "efie_batch_assemble",
@@ -94,6 +95,8 @@ def lib():
         "efie_farfield_workspace_size": ([P, I64, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "efie_farfield": ([P, D, D, P, I64, P, I64, P, P, ctypes.c_size_t, P], ctypes.c_int),
         "efie_zx": ([P, ctypes.c_int, I64, P, P, I64, P], ctypes.c_int),
+        "efie_zx_flush64_workspace_size": ([I64, I64, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "efie_zx_flush64": ([P, I64, P, P, I64, P, ctypes.c_size_t, P], ctypes.c_int),
         "efie_solve_workspace_size": ([I64, I64, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "efie_solve": ([P, ctypes.c_int, I64, P, P, I64, ctypes.POINTER(_SolveOpts), ctypes.POINTER(_RhsStats),
                         P, ctypes.c_size_t, P], ctypes.c_int),
@@ -448,7 +451,8 @@ def prof_read(with_work: bool = False):
 
 # ------------------------------------------------------------- GEMM tile autotuner
 def gemm_variants():
-    """[(bm, bn, kc)] of the complex64 matrix-core GEMM tile variants."""
+    """[(bm, bn, kc)] of the complex64 matrix-core GEMM: block tile of bm right-hand
+    sides x bn unknowns, K chunk of kc complex elements."""
     L = lib()
     c = ctypes.c_int()
     _check(L.efie_gemm_variants(ctypes.byref(c)))
@@ -458,6 +462,35 @@ def gemm_variants():
         _check(L.efie_gemm_variant_info(v, ctypes.byref(bm), ctypes.byref(bn), ctypes.byref(kc)))
         out.append((bm.value, bn.value, kc.value))
     return out
+
+
+def gemm_kernel_name(variant, acc64: bool) -> str:
+    """The kernel's name as profilers print it (template arguments included)."""
+    bm, bn, kc = variant[:3]
+    return f"cgemm_planar_kernel<{bm}, {bn}, {kc}, {'true' if acc64 else 'false'}>"
+
+
+def zx_flush64(Z, X):
+    """Y = Z X with Z complex64 and X complex128 (nrhs, N): the mixed solves' product
+    (FP32 matrix cores, partial sums flushed into FP64 every K chunk), Y complex128."""
+    torch = _torch()
+    _require_cuda(Z, "Z")
+    if Z.dtype != torch.complex64:
+        raise ValueError("Z must be complex64")
+    n = Z.shape[0]
+    X = X.reshape(-1, n)
+    _require_cuda(X, "X")
+    if X.dtype != torch.complex128:
+        raise ValueError("X must be complex128")
+    S = X.shape[0]
+    Y = torch.empty_like(X)
+    nb = ctypes.c_size_t()
+    _check(lib().efie_zx_flush64_workspace_size(n, S, ctypes.byref(nb)))
+    ws = torch.empty(nb.value + 256, dtype=torch.uint8, device=Z.device)
+    off = (-ws.data_ptr()) % 256
+    _check(lib().efie_zx_flush64(_ptr(Z), n, _ptr(X), _ptr(Y), S, ctypes.c_void_p(ws.data_ptr() + off), nb.value,
+                                 _stream(Z.device)))
+    return Y
 
 
 def gemm_select(acc64: bool, variant: int) -> int:
@@ -490,7 +523,7 @@ def gemm_autotune(Z, M: int, reps: int = 3, cache: str | None = None, force: boo
         except (OSError, ValueError):
             db = {}
     tiles = gemm_variants()
-    if key in db and not force and len(db[key].get("tiles", [])) == len(tiles):
+    if key in db and not force and [list(t) for t in db[key].get("tiles", [])] == [list(t) for t in tiles]:
         ent = db[key]
     else:
         g = torch.Generator(device=Z.device).manual_seed(0)

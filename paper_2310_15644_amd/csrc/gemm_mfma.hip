@@ -1,21 +1,34 @@
-// Complex64 Y = X Z^T on FP32 matrix cores (MFMA), FP32 accumulation.
+// Complex64 Y = X Z^T on FP32 matrix cores (MFMA).
 //
-// The complex product is carried out as one real product ("4M": every complex
-// multiply-add costs four real ones, 8 M n K flops in total):
-//   A (M x 2n) = X viewed as floats,  A[s][2j+t] = (Re, Im)[t] X[s][j];
-//   B (2n x 2n) built on the fly from the 2 x 2 real blocks of Z,
-//     B[2j][2i] = Re Z[i][j], B[2j+1][2i] = -Im Z[i][j],
-//     B[2j][2i+1] = Im Z[i][j], B[2j+1][2i+1] = Re Z[i][j];
-//   C = A B is then Y viewed as floats, interleaved (re, im), row by row.
-// So X and Y keep the ABI's interleaved complex64 layout and no operand is
-// converted or copied.
+// Planar complex form: the K chunks of X (right-hand sides) and Z (the
+// symmetric operator, whose rows are the output unknowns) are staged in LDS as
+// complex (re, im) rows.  In v_mfma_f32_16x16x4f32 lane l supplies A[l%16][l/16]
+// and B[l/16][l%16], and accumulator register r of lane l holds
+// D[4*(l/16)+r][l%16]; here a lane's operand element is one complex value,
+// fetched with one 8-byte LDS read, and each 16 x 16 complex output block takes
+// four real instructions per 4 complex K:
+//   Yr += Ar Br + (-Ai) Bi,   Yi += Ar Bi + Ai Br
+// (8 M n K real flops in all).  X and Y keep the ABI's interleaved complex
+// layouts; no operand is converted or copied.
 //
-// Tiling: a block of 256 threads (4 wavefronts, 2 x 2) owns a BM x BN tile of C
-// (BM right-hand sides, BN/2 unknowns).  K is walked in chunks of KC complex
-// elements staged in LDS; each wavefront issues v_mfma_f32_16x16x4f32 on 16 x 16
-// sub-tiles (K = 4 reals = 2 complex elements per instruction).
-// Operand layouts of v_mfma_f32_16x16x4f32: lane l supplies A[l%16][l/16] and
-// B[l/16][l%16]; accumulator register r of lane l holds D[4*(l/16)+r][l%16].
+// Tiling: a block of 256 threads (4 wavefronts, 2 x 2) owns BM right-hand sides
+// x BNC unknowns; K is walked in chunks of KC complex elements.
+// ACC64: the FP32 matrix-core partial sums are flushed into FP64 accumulators after
+// every K chunk, and the result is written as complex128 to the rows Y[yrow[r]]
+// (the Krylov vectors); this bounds the FP32 accumulation error to short partial
+// sums.  Otherwise complex64 is written to Y[r].
+//
+// Pipeline: two LDS buffers; the global loads of chunk c+1 (16-byte loads into
+// registers when n is even and the operands 16-byte aligned, 8-byte otherwise;
+// without per-element bounds tests when the tile lies wholly inside the
+// matrices) are in flight while chunk c is multiplied, then written to the other
+// buffer; one barrier per chunk.  LDS rows are padded to KC + 2 complex values,
+// which keeps them 16-byte aligned and the 8-byte reads of a wavefront free of
+// bank conflicts.
+// Block order: workgroups are dealt to the 8 XCDs round-robin by id, so the ids
+// are remapped to give each XCD a contiguous run of tiles, walking the
+// right-hand-side tiles of one Z row strip first: the blocks that read the
+// same strip of Z share one XCD's L2 and run at about the same time.
 #include <hip/hip_runtime.h>
 
 #include "efie_internal.h"
@@ -25,32 +38,19 @@ namespace efie {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-// ACC64: the FP32 matrix-core partial sums are flushed into FP64 accumulators after
-// every K chunk, and the result is written as complex128 to the rows Y[yrow[r]]
-// (the Krylov vectors); this bounds the FP32 accumulation error to short partial
-// sums.  Otherwise complex64 is written to Y[r].
-//
-// Pipeline: two LDS buffers; the global loads of chunk c+1 (16-byte loads into
-// registers when n is even, 8-byte otherwise) are in flight while chunk c is
-// multiplied, then written to the other buffer; one barrier per chunk.
-// Block order: workgroups are dealt to the 8 XCDs round-robin by id, so the ids
-// are remapped to give each XCD a contiguous run of tiles, walking the
-// right-hand-side tiles of one Z column strip first: the blocks that read the
-// same strip of Z share one XCD's L2 and run at about the same time.
-template <int BM, int BN, int KC, bool ACC64>
-__global__ __launch_bounds__(256) void cgemm_mfma_kernel(const float2* __restrict__ X, const float2* __restrict__ Z,
-                                                         void* __restrict__ Yv, int M, int n,
-                                                         const int* __restrict__ yrow) {
-    constexpr int AP = 2 * KC + 4;     // floats per LDS row of the X tile (padded, 16-byte rows)
-    constexpr int BNC = BN / 2;        // unknowns per tile
-    constexpr int BP = KC + 2;         // float2 per LDS row of the Z tile (padded, 16-byte rows)
-    constexpr int WM = BM / 2, WN = BN / 2;   // wavefront tile
+template <int BM, int BNC, int KC, bool ACC64>
+__global__ __launch_bounds__(256) void cgemm_planar_kernel(const float2* __restrict__ X, const float2* __restrict__ Z,
+                                                           void* __restrict__ Yv, int M, int n,
+                                                           const int* __restrict__ yrow) {
+    constexpr int AS = KC + 2;             // float2 per LDS row (16-byte rows, conflict-free 8-byte reads)
+    constexpr int WM = BM / 2, WN = BNC / 2;
     constexpr int TM = WM / 16, TN = WN / 16;
-    constexpr int KV = KC / 2;         // two-element (16-byte) groups per row of a chunk
+    constexpr int KV = KC / 2;             // 16-byte groups per row of a chunk
     constexpr int NA = BM * KV / 256, NB = BNC * KV / 256;
+    static_assert(TM >= 1 && TN >= 1 && NA >= 1 && NB >= 1, "tile too small for the block");
     static_assert(BM * KV % 256 == 0 && BNC * KV % 256 == 0, "tile not divisible by the block");
-    __shared__ float As[2][BM * AP];
-    __shared__ float2 Bs[2][BNC * BP];
+    __shared__ float2 As[2][BM * AS];
+    __shared__ float2 Bs[2][BNC * AS];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
@@ -63,25 +63,29 @@ __global__ __launch_bounds__(256) void cgemm_mfma_kernel(const float2* __restric
     const int bm = logical % nbm, bn = logical / nbm;
     const int s0 = bm * BM, i0 = bn * BNC;
     const bool vec = (n & 1) == 0 && ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Z)) & 15) == 0;
+    const bool inside = vec && s0 + BM <= M && i0 + BNC <= n;
 
-    floatx4 acc[TM][TN];
-    double acc64[ACC64 ? TM : 1][ACC64 ? TN : 1][4];
+    floatx4 accr[TM][TN], acci[TM][TN];
+    double dr[ACC64 ? TM : 1][ACC64 ? TN : 1][4], di[ACC64 ? TM : 1][ACC64 ? TN : 1][4];
 #pragma unroll
     for (int a = 0; a < TM; ++a)
 #pragma unroll
-        for (int b = 0; b < TN; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int b = 0; b < TN; ++b) {
+            accr[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+            acci[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+        }
     if (ACC64) {
 #pragma unroll
         for (int a = 0; a < (ACC64 ? TM : 1); ++a)
 #pragma unroll
             for (int b = 0; b < (ACC64 ? TN : 1); ++b)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) acc64[a][b][r] = 0.0;
+                for (int r = 0; r < 4; ++r) dr[a][b][r] = di[a][b][r] = 0.0;
     }
 
     float4 ra[NA], rb[NB];
     auto load2 = [&](const float2* base, int row, int nrows, int j) -> float4 {
-        // elements j and j+1 of row `row` (zero outside the matrix)
+        // complex elements j and j+1 of row `row` (zero outside the matrix)
         if (row >= nrows || j >= n) return make_float4(0.f, 0.f, 0.f, 0.f);
         const float2* p = base + size_t(row) * n + j;
         if (vec) return *reinterpret_cast<const float4*>(p);
@@ -90,31 +94,44 @@ __global__ __launch_bounds__(256) void cgemm_mfma_kernel(const float2* __restric
         return make_float4(u.x, u.y, v.x, v.y);
     };
     auto gload = [&](int j0) {
+        if (inside && j0 + KC <= n) {
 #pragma unroll
-        for (int q = 0; q < NA; ++q) {
-            const int e = tid + 256 * q, r = e / KV, c = e % KV;
-            ra[q] = load2(X, s0 + r, M, j0 + 2 * c);
-        }
+            for (int q = 0; q < NA; ++q) {
+                const int e = tid + 256 * q, r = e / KV, c = e % KV;
+                ra[q] = *reinterpret_cast<const float4*>(X + size_t(s0 + r) * n + j0 + 2 * c);
+            }
 #pragma unroll
-        for (int q = 0; q < NB; ++q) {
-            const int e = tid + 256 * q, r = e / KV, c = e % KV;
-            rb[q] = load2(Z, i0 + r, n, j0 + 2 * c);
+            for (int q = 0; q < NB; ++q) {
+                const int e = tid + 256 * q, r = e / KV, c = e % KV;
+                rb[q] = *reinterpret_cast<const float4*>(Z + size_t(i0 + r) * n + j0 + 2 * c);
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < NA; ++q) {
+                const int e = tid + 256 * q, r = e / KV, c = e % KV;
+                ra[q] = load2(X, s0 + r, M, j0 + 2 * c);
+            }
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const int e = tid + 256 * q, r = e / KV, c = e % KV;
+                rb[q] = load2(Z, i0 + r, n, j0 + 2 * c);
+            }
         }
     };
     auto lstore = [&](int buf) {
 #pragma unroll
         for (int q = 0; q < NA; ++q) {
             const int e = tid + 256 * q, r = e / KV, c = e % KV;
-            *reinterpret_cast<float4*>(&As[buf][r * AP + 4 * c]) = ra[q];
+            *reinterpret_cast<float4*>(&As[buf][r * AS + 2 * c]) = ra[q];
         }
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
             const int e = tid + 256 * q, r = e / KV, c = e % KV;
-            *reinterpret_cast<float4*>(&Bs[buf][r * BP + 2 * c]) = rb[q];
+            *reinterpret_cast<float4*>(&Bs[buf][r * AS + 2 * c]) = rb[q];
         }
     };
 
-    const int kq = lane >> 4;          // 0..3: real k within an instruction
+    const int kq = lane >> 4;          // 0..3: k within an instruction
     const int l16 = lane & 15;
     const int nch = (n + KC - 1) / KC;
     gload(0);
@@ -123,27 +140,29 @@ __global__ __launch_bounds__(256) void cgemm_mfma_kernel(const float2* __restric
     for (int ch = 0; ch < nch; ++ch) {
         const int buf = ch & 1;
         if (ch + 1 < nch) gload((ch + 1) * KC);
-        const float* A_ = As[buf];
-        const float2* B_ = Bs[buf];
+        const float2* A_ = As[buf] + (wm * WM + l16) * AS + kq;
+        const float2* B_ = Bs[buf] + (wn * WN + l16) * AS + kq;
 #pragma unroll
-        for (int st = 0; st < KC / 2; ++st) {
-            const int kf = 4 * st + kq;        // real k index inside the chunk
-            const int jj = kf >> 1, t = kf & 1;
-            float av[TM], bv[TN];
+        for (int kk = 0; kk < KC; kk += 4) {
+            float2 xa[TM], zb[TN];
 #pragma unroll
-            for (int a = 0; a < TM; ++a) av[a] = A_[(wm * WM + a * 16 + l16) * AP + kf];
+            for (int a = 0; a < TM; ++a) xa[a] = A_[a * 16 * AS + kk];
 #pragma unroll
-            for (int b = 0; b < TN; ++b) {
-                const int col = wn * WN + b * 16 + l16;     // real column inside the tile
-                const float2 z = B_[(col >> 1) * BP + jj];
-                const int u = col & 1;
-                bv[b] = u == 0 ? (t == 0 ? z.x : -z.y) : (t == 0 ? z.y : z.x);
-            }
+            for (int b = 0; b < TN; ++b) zb[b] = B_[b * 16 * AS + kk];
 #pragma unroll
             for (int a = 0; a < TM; ++a)
 #pragma unroll
-                for (int b = 0; b < TN; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
+                for (int b = 0; b < TN; ++b) {
+                    accr[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[a].x, zb[b].x, accr[a][b], 0, 0, 0);
+                    acci[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[a].x, zb[b].y, acci[a][b], 0, 0, 0);
+                }
+#pragma unroll
+            for (int a = 0; a < TM; ++a)
+#pragma unroll
+                for (int b = 0; b < TN; ++b) {
+                    accr[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(-xa[a].y, zb[b].y, accr[a][b], 0, 0, 0);
+                    acci[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[a].y, zb[b].x, acci[a][b], 0, 0, 0);
+                }
         }
         if (ACC64) {
 #pragma unroll
@@ -151,27 +170,33 @@ __global__ __launch_bounds__(256) void cgemm_mfma_kernel(const float2* __restric
 #pragma unroll
                 for (int b = 0; b < (ACC64 ? TN : 1); ++b) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) acc64[a][b][r] += double(acc[a][b][r]);
-                    acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    for (int r = 0; r < 4; ++r) {
+                        dr[a][b][r] += double(accr[a][b][r]);
+                        di[a][b][r] += double(acci[a][b][r]);
+                    }
+                    accr[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    acci[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
                 }
         }
         if (ch + 1 < nch) lstore(buf ^ 1);
         __syncthreads();
     }
+    // D layout of the 16x16x4 instruction: lane l holds rows 4 (l / 16) + r, column l % 16
 #pragma unroll
     for (int a = 0; a < TM; ++a)
 #pragma unroll
         for (int b = 0; b < TN; ++b) {
-            const int col = 2 * i0 + wn * WN + b * 16 + l16;
+            const int col = i0 + wn * WN + b * 16 + l16;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = s0 + wm * WM + a * 16 + 4 * kq + r;
-                if (row < M && col < 2 * n) {
+                if (row < M && col < n) {
                     if (ACC64)
-                        reinterpret_cast<double*>(Yv)[size_t(yrow[row]) * 2 * n + col] =
-                            acc64[ACC64 ? a : 0][ACC64 ? b : 0][r];
+                        reinterpret_cast<double2*>(Yv)[size_t(yrow[row]) * n + col] =
+                            make_double2(dr[ACC64 ? a : 0][ACC64 ? b : 0][r], di[ACC64 ? a : 0][ACC64 ? b : 0][r]);
                     else
-                        reinterpret_cast<float*>(Yv)[size_t(row) * 2 * n + col] = acc[a][b][r];
+                        reinterpret_cast<float2*>(Yv)[size_t(row) * n + col] =
+                            make_float2(accr[a][b][r], acci[a][b][r]);
                 }
             }
         }
@@ -180,23 +205,23 @@ __global__ __launch_bounds__(256) void cgemm_mfma_kernel(const float2* __restric
 bool cgemm_mfma_supported(int M, int n) { return M >= 1 && n >= 1; }
 
 // ------------------------------------------------------------ tile variants
-// Block tile BM (right-hand sides) x BN (real columns = BN/2 unknowns), K chunk KC.
-// The FP64-flush path needs 3x the accumulator registers, so smaller wavefront
-// tiles win there; efie_gemm_autotune measures and selects per path.
+// Block tile BM (right-hand sides) x BN (unknowns), K chunk KC.  The FP64-flush
+// path needs 3x the accumulator registers, so smaller wavefront tiles win there;
+// efie_gemm_autotune measures and selects per path.
 struct Variant {
     int bm, bn, kc;
 };
-static const Variant kVariants[] = {{128, 128, 16}, {128, 64, 16}, {64, 128, 16}, {64, 64, 16}, {64, 64, 32},
-                                    {128, 128, 32}, {64, 128, 32}, {32, 128, 16}};
+static const Variant kVariants[] = {{64, 32, 32}, {64, 64, 16}, {64, 64, 32}, {128, 32, 16},
+                                    {32, 64, 16}, {128, 64, 16}, {64, 32, 16}, {64, 128, 16}};
 static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
-static int g_variant[2] = {0, 1};   // defaults: complex64 output, FP64-flush output
+static int g_variant[2] = {1, 2};   // defaults: complex64 output, FP64-flush output
 
 template <int BM, int BN, int KC, bool A64>
 static void launch_v(const void* X, const void* Z, void* Y, const int* yrow, int M, int n, hipStream_t s) {
-    const int nbm = (M + BM - 1) / BM, nbn = (n + BN / 2 - 1) / (BN / 2);
+    const int nbm = (M + BM - 1) / BM, nbn = (n + BN - 1) / BN;
     const size_t nblk = size_t(nbm) * nbn;
     EFIE_REQUIRE(nblk < (size_t(1) << 31), EFIE_ERR_ARG, "cgemm: problem too large");
-    hipLaunchKernelGGL((cgemm_mfma_kernel<BM, BN, KC, A64>), dim3(unsigned(nblk)), dim3(256), 0, s,
+    hipLaunchKernelGGL((cgemm_planar_kernel<BM, BN, KC, A64>), dim3(unsigned(nblk)), dim3(256), 0, s,
                        static_cast<const float2*>(X), static_cast<const float2*>(Z), Y, M, n, yrow);
 }
 
@@ -204,14 +229,14 @@ template <bool A64>
 static void launch_variant(int v, const void* X, const void* Z, void* Y, const int* yrow, int M, int n,
                            hipStream_t s) {
     switch (v) {
-        case 0: launch_v<128, 128, 16, A64>(X, Z, Y, yrow, M, n, s); break;
-        case 1: launch_v<128, 64, 16, A64>(X, Z, Y, yrow, M, n, s); break;
-        case 2: launch_v<64, 128, 16, A64>(X, Z, Y, yrow, M, n, s); break;
-        case 3: launch_v<64, 64, 16, A64>(X, Z, Y, yrow, M, n, s); break;
-        case 4: launch_v<64, 64, 32, A64>(X, Z, Y, yrow, M, n, s); break;
-        case 5: launch_v<128, 128, 32, A64>(X, Z, Y, yrow, M, n, s); break;
-        case 6: launch_v<64, 128, 32, A64>(X, Z, Y, yrow, M, n, s); break;
-        default: launch_v<32, 128, 16, A64>(X, Z, Y, yrow, M, n, s); break;
+        case 0: launch_v<64, 32, 32, A64>(X, Z, Y, yrow, M, n, s); break;
+        case 1: launch_v<64, 64, 16, A64>(X, Z, Y, yrow, M, n, s); break;
+        case 2: launch_v<64, 64, 32, A64>(X, Z, Y, yrow, M, n, s); break;
+        case 3: launch_v<128, 32, 16, A64>(X, Z, Y, yrow, M, n, s); break;
+        case 4: launch_v<32, 64, 16, A64>(X, Z, Y, yrow, M, n, s); break;
+        case 5: launch_v<128, 64, 16, A64>(X, Z, Y, yrow, M, n, s); break;
+        case 6: launch_v<64, 32, 16, A64>(X, Z, Y, yrow, M, n, s); break;
+        default: launch_v<64, 128, 16, A64>(X, Z, Y, yrow, M, n, s); break;
     }
 }
 
@@ -257,6 +282,34 @@ extern "C" int efie_gemm_variant_info(int v, int* bm, int* bn, int* kc) {
         *bm = efie::kVariants[v].bm;
         *bn = efie::kVariants[v].bn;
         *kc = efie::kVariants[v].kc;
+        return int(EFIE_OK);
+    });
+}
+
+extern "C" int efie_zx_flush64_workspace_size(int64_t n, int64_t nrhs, size_t* bytes) {
+    return efie::guarded([&]() {
+        EFIE_REQUIRE(bytes && n >= 1 && n < (int64_t(1) << 31) && nrhs >= 1 && nrhs < 65536, EFIE_ERR_ARG,
+                     "zx_flush64_workspace_size: bad argument");
+        *bytes = ((size_t(n) * size_t(nrhs) * 8 + 255) & ~size_t(255)) + size_t(nrhs) * sizeof(int);
+        return int(EFIE_OK);
+    });
+}
+
+extern "C" int efie_zx_flush64(const void* Z, int64_t n, const void* X, void* Y, int64_t nrhs, void* ws,
+                               size_t ws_bytes, hipStream_t stream) {
+    return efie::guarded([&]() {
+        EFIE_REQUIRE(Z && X && Y && ws, EFIE_ERR_ARG, "zx_flush64: null argument");
+        EFIE_REQUIRE(n >= 1 && n < (int64_t(1) << 31) && nrhs >= 1 && nrhs < 65536, EFIE_ERR_ARG,
+                     "zx_flush64: bad sizes");
+        EFIE_REQUIRE((reinterpret_cast<uintptr_t>(ws) & 15) == 0, EFIE_ERR_ARG, "zx_flush64: ws not 16-byte aligned");
+        const size_t xbytes = (size_t(n) * size_t(nrhs) * 8 + 255) & ~size_t(255);
+        EFIE_REQUIRE(ws_bytes >= xbytes + size_t(nrhs) * sizeof(int), EFIE_ERR_ARG, "zx_flush64: workspace too small");
+        float2* x32 = static_cast<float2*>(ws);
+        int* idx = reinterpret_cast<int*>(static_cast<char*>(ws) + xbytes);
+        hipLaunchKernelGGL(efie::iota_rows_kernel, dim3(int((nrhs + 255) / 256)), dim3(256), 0, stream, idx, int(nrhs));
+        efie::gather_cast(static_cast<const double2*>(X), idx, int(nrhs), int(n), x32, stream);
+        efie::cgemm_mfma_acc64(x32, Z, static_cast<double2*>(Y), idx, int(nrhs), int(n), stream);
+        EFIE_HIP_CHECK(hipGetLastError());
         return int(EFIE_OK);
     });
 }

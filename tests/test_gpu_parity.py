@@ -185,6 +185,37 @@ def test_zx_random(dev, n, nrhs, dt):
     assert err <= tol, err
 
 
+@pytest.mark.parametrize("n,nrhs", [(257, 40), (480, 64), (33, 3)])
+def test_gemm_every_variant(dev, n, nrhs):
+    """Every matrix-core GEMM variant (both kernel forms, every tile shape) on both
+    paths: complex64 output with FP32 accumulation (efie_zx) and complex128 output
+    with FP64 flushes per K chunk (efie_zx_flush64, the mixed solves' product),
+    against the FP64 product of the values actually stored; ragged in rows,
+    unknowns and K for every tile."""
+    flush(f"gemm variants n={n} nrhs={nrhs}")
+    rng = np.random.default_rng(7 * n + nrhs)
+    Z = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    X = rng.standard_normal((nrhs, n)) + 1j * rng.standard_normal((nrhs, n))
+    Zt = torch.as_tensor(Z, dtype=torch.complex64, device=dev)
+    X64 = torch.as_tensor(X, dtype=torch.complex128, device=dev)
+    X32 = X64.to(torch.complex64)
+    ref = X32.cpu().numpy().astype(np.complex128) @ Zt.cpu().numpy().astype(np.complex128).T
+    nref = np.linalg.norm(ref)
+    prev32, prev64 = P.gemm_select(False, 0), P.gemm_select(True, 0)
+    try:
+        for v, t in enumerate(P.gemm_variants()):
+            P.gemm_select(False, v)
+            P.gemm_select(True, v)
+            e32 = np.linalg.norm(P.zx(Zt, X32).cpu().numpy().astype(np.complex128) - ref) / nref
+            e64 = np.linalg.norm(P.zx_flush64(Zt, X64).cpu().numpy() - ref) / nref
+            flush(f"  variant {v} {t}: fp32-acc {e32:.2e}, fp64-flush {e64:.2e}")
+            assert e32 <= 2e-6, (v, t, e32)
+            assert e64 <= 5e-7, (v, t, e64)
+    finally:
+        P.gemm_select(False, prev32)
+        P.gemm_select(True, prev64)
+
+
 @pytest.mark.parametrize("n", [480, 481])
 def test_zx_c64_unaligned_operands(dev, n):
     """Matrix-core product with X and Z starting 8 bytes past a 16-byte boundary
