@@ -16,6 +16,8 @@
 //  * G_mix by the 7-point rule on every barycentric triangle (exact: the integrand
 //    is quadratic there).
 #include <algorithm>
+#include <climits>
+#include <cstdio>
 #include <cmath>
 #include <map>
 
@@ -42,9 +44,35 @@ V3 rwg_value(const efie_mesh_s& m, int64_t t, int i, V3 r) {
 }
 }  // namespace
 
+namespace {
+uint64_t spread21(uint64_t x) {   // 21 bits -> every third bit
+    x &= 0x1fffff;
+    x = (x | x << 32) & 0x1f00000000ffffull;
+    x = (x | x << 16) & 0x1f0000ff0000ffull;
+    x = (x | x << 8) & 0x100f00f00f00f00full;
+    x = (x | x << 4) & 0x10c30c30c30c30c3ull;
+    x = (x | x << 2) & 0x1249249249249249ull;
+    return x;
+}
+// Morton code of p in the box [lo, hi] (21 bits per axis)
+uint64_t morton(const double* p, const double* lo, const double* hi) {
+    uint64_t code = 0;
+    for (int d = 0; d < 3; ++d) {
+        const double u = hi[d] > lo[d] ? (p[d] - lo[d]) / (hi[d] - lo[d]) : 0.0;
+        code |= spread21(uint64_t(std::min(2097151.0, std::max(0.0, u * 2097151.0)))) << d;
+    }
+    return code;
+}
+}  // namespace
+
 void build_calderon(efie_calderon_s& C, const efie_mesh_s& m) {
     const int64_t V = m.nv, N = m.N, T = m.T;
     // ---------------------------------------------------- barycentric refinement
+    // Refinement vertices in canonical order: the primal vertices, the edge
+    // midpoints (V + n), the triangle centroids (V + N + t).  The barycentric mesh
+    // is built on them renumbered by Morton code (vid[canonical] = internal id), so
+    // that its lexicographic edge numbering is spatially coherent: the barycentric
+    // RWGs in the support of neighbouring BC functions get neighbouring indices.
     std::vector<double> xyz(3 * size_t(V + N + T));
     for (int64_t i = 0; i < 3 * V; ++i) xyz[i] = m.xyz[i];
     for (int64_t n = 0; n < N; ++n)
@@ -64,9 +92,47 @@ void build_calderon(efie_calderon_s& C, const efie_mesh_s& m) {
         for (int k = 0; k < 6; ++k)
             for (int j = 0; j < 3; ++j) tri[18 * t + 3 * k + j] = sub6[k][j];
     }
-    build_mesh(C.bary, xyz.data(), V + N + T, tri.data(), 6 * T, m.near_factor);
+    const int64_t VB = V + N + T;
+    std::vector<int32_t> vid(static_cast<size_t>(VB));
+    {
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        for (int64_t v = 0; v < VB; ++v)
+            for (int d = 0; d < 3; ++d) {
+                lo[d] = std::min(lo[d], xyz[3 * size_t(v) + d]);
+                hi[d] = std::max(hi[d], xyz[3 * size_t(v) + d]);
+            }
+        std::vector<std::pair<uint64_t, int32_t>> key(static_cast<size_t>(VB));
+        for (int64_t v = 0; v < VB; ++v) key[size_t(v)] = {morton(&xyz[3 * size_t(v)], lo, hi), int32_t(v)};
+        std::sort(key.begin(), key.end());
+        for (int64_t i = 0; i < VB; ++i) vid[size_t(key[size_t(i)].second)] = int32_t(i);
+        std::vector<double> x2(xyz.size());
+        for (int64_t v = 0; v < VB; ++v)
+            for (int d = 0; d < 3; ++d) x2[3 * size_t(vid[size_t(v)]) + d] = xyz[3 * size_t(v) + d];
+        xyz.swap(x2);
+        for (auto& t : tri) t = vid[size_t(t)];
+    }
+    build_mesh(C.bary, xyz.data(), VB, tri.data(), 6 * T, m.near_factor);
     pack_tables(C.bary);
     const efie_mesh_s& b = C.bary;
+    // canonical index of every barycentric RWG: its rank among the edges of the
+    // refinement sorted by canonical (lower, higher) vertex id; where the internal
+    // (lower, higher) order of its vertices is the reverse of the canonical one,
+    // T+ and T- swap and the canonical RWG is the negative of the internal one
+    {
+        std::vector<int32_t> inv(static_cast<size_t>(VB));
+        for (int64_t v = 0; v < VB; ++v) inv[size_t(vid[size_t(v)])] = int32_t(v);
+        std::vector<std::pair<std::pair<int32_t, int32_t>, int32_t>> ce(static_cast<size_t>(b.N));
+        for (int64_t e = 0; e < b.N; ++e) {
+            const int32_t a = inv[size_t(b.edge_v[2 * e])], c = inv[size_t(b.edge_v[2 * e + 1])];
+            ce[size_t(e)] = {{std::min(a, c), std::max(a, c)}, int32_t(e)};
+        }
+        std::sort(ce.begin(), ce.end());
+        C.bary_canon.resize(static_cast<size_t>(b.N));
+        C.bary_flip.resize(static_cast<size_t>(b.N));
+        for (int64_t i = 0; i < b.N; ++i) C.bary_canon[size_t(ce[size_t(i)].second)] = int32_t(i);
+        for (int64_t e = 0; e < b.N; ++e)
+            C.bary_flip[size_t(e)] = inv[size_t(b.edge_v[2 * e])] > inv[size_t(b.edge_v[2 * e + 1])] ? 1 : 0;
+    }
 
     // --------------------------------------------------- Buffa-Christiansen R
     std::map<std::pair<int32_t, int32_t>, int32_t> bedge;
@@ -86,9 +152,9 @@ void build_calderon(efie_calderon_s& C, const efie_mesh_s& m) {
     auto from_plus = [&](int32_t t, int32_t e) { return b.edge_t[2 * e] == t ? 1.0 : -1.0; };
     std::vector<std::map<int32_t, double>> cols(static_cast<size_t>(N));
     for (int64_t n = 0; n < N; ++n) {
-        const int32_t mid = int32_t(V + n);
+        const int32_t mid = vid[size_t(V + n)];
         for (int side = 0; side < 2; ++side) {
-            const int32_t c = m.edge_v[2 * n + side];
+            const int32_t c = vid[size_t(m.edge_v[2 * n + side])];
             const double sigma = side == 0 ? 1.0 : -1.0;
             const auto& ring = around[size_t(c)];
             const int Nc = int(ring.size());
@@ -216,28 +282,82 @@ void build_calderon(efie_calderon_s& C, const efie_mesh_s& m) {
                 lo[d] = std::min(lo[d], m.xyz[3 * size_t(v) + d]);
                 hi[d] = std::max(hi[d], m.xyz[3 * size_t(v) + d]);
             }
-        auto spread = [](uint64_t x) {   // 21 bits -> every third bit
-            x &= 0x1fffff;
-            x = (x | x << 32) & 0x1f00000000ffffull;
-            x = (x | x << 16) & 0x1f0000ff0000ffull;
-            x = (x | x << 8) & 0x100f00f00f00f00full;
-            x = (x | x << 4) & 0x10c30c30c30c30c3ull;
-            x = (x | x << 2) & 0x1249249249249249ull;
-            return x;
-        };
         std::vector<std::pair<uint64_t, int32_t>> key(static_cast<size_t>(N));
         for (int64_t n = 0; n < N; ++n) {
-            uint64_t code = 0;
-            for (int d = 0; d < 3; ++d) {
-                const double mid = 0.5 * (m.xyz[3 * size_t(m.edge_v[2 * n]) + d] + m.xyz[3 * size_t(m.edge_v[2 * n + 1]) + d]);
-                const double u = hi[d] > lo[d] ? (mid - lo[d]) / (hi[d] - lo[d]) : 0.0;
-                code |= spread(uint64_t(std::min(2097151.0, std::max(0.0, u * 2097151.0)))) << d;
-            }
-            key[size_t(n)] = {code, int32_t(n)};
+            double mid[3];
+            for (int d = 0; d < 3; ++d)
+                mid[d] = 0.5 * (m.xyz[3 * size_t(m.edge_v[2 * n]) + d] + m.xyz[3 * size_t(m.edge_v[2 * n + 1]) + d]);
+            key[size_t(n)] = {morton(mid, lo, hi), int32_t(n)};
         }
         std::sort(key.begin(), key.end());
         C.n_order.resize(static_cast<size_t>(N));
         for (int64_t n = 0; n < N; ++n) C.n_order[size_t(n)] = key[size_t(n)].second;
+    }
+    // Runs of consecutive BC functions in n_order, each of at most BC_BLOCK functions
+    // whose supports hold at most BC_UMAX distinct barycentric RWGs (a run closes
+    // when the next function would break either bound): per run its first position
+    // in n_order (run_t0), the sorted distinct RWGs it reads (u_ptr / u_idx), and
+    // for every entry k of R's CSC the position of its RWG in the list of the run
+    // holding its BC function (r_loc).  The source-side contraction gathers each
+    // listed RWG once per run.
+    {
+        C.run_t0.assign(1, 0);
+        C.u_ptr.assign(1, 0);
+        C.u_idx.clear();
+        C.r_loc.assign(C.r_idx.size(), 0);
+        C.u_max = 0;
+        std::vector<int32_t> mark(static_cast<size_t>(b.N), -1), fs;
+        int32_t run = 0;
+        auto close_run = [&](int64_t t_end) {
+            std::sort(fs.begin(), fs.end());
+            for (int64_t t = C.run_t0.back(); t < t_end; ++t) {
+                const int32_t n = C.n_order[size_t(t)];
+                for (int32_t k = C.r_ptr[size_t(n)]; k < C.r_ptr[size_t(n) + 1]; ++k)
+                    C.r_loc[size_t(k)] =
+                        int32_t(std::lower_bound(fs.begin(), fs.end(), C.r_idx[size_t(k)]) - fs.begin());
+            }
+            C.u_idx.insert(C.u_idx.end(), fs.begin(), fs.end());
+            C.u_ptr.push_back(int32_t(C.u_idx.size()));
+            C.u_max = std::max<int64_t>(C.u_max, int64_t(fs.size()));
+            C.run_t0.push_back(int32_t(t_end));
+            fs.clear();
+            ++run;
+        };
+        for (int64_t t = 0; t < N; ++t) {
+            const int32_t n = C.n_order[size_t(t)];
+            int extra = 0;
+            for (int32_t k = C.r_ptr[size_t(n)]; k < C.r_ptr[size_t(n) + 1]; ++k)
+                extra += mark[size_t(C.r_idx[size_t(k)])] != run;   // entries of one column are distinct
+            EFIE_REQUIRE(extra <= BC_UMAX, EFIE_ERR_ARG, "calderon: a BC function with too large a support");
+            if (t > C.run_t0.back() && (t - C.run_t0.back() == BC_BLOCK || int64_t(fs.size()) + extra > BC_UMAX))
+                close_run(t);
+            for (int32_t k = C.r_ptr[size_t(n)]; k < C.r_ptr[size_t(n) + 1]; ++k) {
+                const int32_t f = C.r_idx[size_t(k)];
+                if (mark[size_t(f)] != run) {
+                    mark[size_t(f)] = run;
+                    fs.push_back(f);
+                }
+            }
+        }
+        if (N > 0) close_run(N);
+        // what the device contraction relies on: every local position names its RWG
+        for (int32_t r = 0; r < run; ++r) {
+            EFIE_REQUIRE(C.u_ptr[size_t(r) + 1] - C.u_ptr[size_t(r)] <= BC_UMAX &&
+                             C.run_t0[size_t(r) + 1] - C.run_t0[size_t(r)] <= BC_BLOCK,
+                         EFIE_ERR_STATE, "calderon: BC run out of bounds");
+            for (int32_t t = C.run_t0[size_t(r)]; t < C.run_t0[size_t(r) + 1]; ++t) {
+                const int32_t n = C.n_order[size_t(t)];
+                for (int32_t k = C.r_ptr[size_t(n)]; k < C.r_ptr[size_t(n) + 1]; ++k)
+                    EFIE_REQUIRE(C.r_loc[size_t(k)] >= 0 &&
+                                     C.r_loc[size_t(k)] < C.u_ptr[size_t(r) + 1] - C.u_ptr[size_t(r)] &&
+                                     C.u_idx[size_t(C.u_ptr[size_t(r)] + C.r_loc[size_t(k)])] == C.r_idx[size_t(k)],
+                                 EFIE_ERR_STATE, "calderon: BC run list inconsistent");
+            }
+        }
+        if (verbose())
+            std::fprintf(stderr, "[efie] calderon BC runs: %d, distinct barycentric RWGs per run mean %.0f max %lld, "
+                         "total %.2f N_bary\n", run, double(C.u_idx.size()) / double(std::max(run, 1)),
+                         (long long)C.u_max, double(C.u_idx.size()) / double(b.N));
     }
     C.N = N;
 }

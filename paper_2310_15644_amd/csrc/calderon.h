@@ -17,6 +17,14 @@ struct efie_calderon_s {
     std::vector<int32_t> g_ptr, g_idx, gt_ptr, gt_idx;
     std::vector<double> g_val, gt_val;
     std::vector<int32_t> n_order;            // primal RWGs in a spatially coherent (Morton) order
+    std::vector<int32_t> bary_canon;         // canonical index of each barycentric RWG
+    std::vector<int8_t> bary_flip;           // 1 where the canonical RWG is the internal one negated
+    // runs of at most BC_BLOCK consecutive BC functions in n_order (first position
+    // run_t0), the distinct barycentric RWGs each run reads (CSR u_ptr / u_idx,
+    // sorted, at most BC_UMAX) and, per entry of R's CSC, the local position of its
+    // RWG in the run's list
+    std::vector<int32_t> run_t0, u_ptr, u_idx, r_loc;
+    int64_t u_max = 0;
     // device copies (caller-owned blob)
     void* dev = nullptr;
     std::vector<char> host_blob;             // sparse arrays packed for upload
@@ -25,5 +33,8 @@ struct efie_calderon_s {
 };
 
 namespace efie {
+constexpr int BC_BLOCK = 256;   // BC functions per block of the source-side contraction
+constexpr int BC_UMAX = 2304;   // distinct barycentric RWGs per block (its LDS list)
+bool verbose();
 void build_calderon(efie_calderon_s& C, const efie_mesh_s& primal);
 }  // namespace efie

@@ -40,51 +40,94 @@ struct DevCald {
     const int32_t *g_ptr, *g_idx, *gt_ptr, *gt_idx;
     const double *g_val, *gt_val;
     const int32_t* n_order;         // primal RWGs in a spatially coherent order
+    const int32_t* run_t0;          // runs of BC functions: first position in n_order
+    const int32_t *u_ptr, *u_idx;   // per run: its distinct barycentric RWGs
+    const int32_t* r_loc;           // per entry of R's CSC: local position in its run's list
 };
 
 // Yw[row][n] = sum_k (W[row][f][0] + W[row][f][1]) r_val[k], f = r_idx[k], k over
 // column n of R (row = 3 (p - c0) + i; W rows hold 2 N_b elements, the two sides
-// of an RWG adjacent).  A thread takes one BC function n (in the spatial order)
-// and BC_RR rows: the column's indices are loaded once into registers and the
-// BC_RR x |column| workspace loads are independent, so they overlap.
-constexpr int BC_RR = 4;
-constexpr int BC_MAXK = 8;    // R column entries per group (24 per column on icosphere meshes)
-template <typename C2>
+// of an RWG adjacent).  A block takes one run of BC functions (blockIdx.x: the
+// positions run_t0[b] .. run_t0[b+1] of n_order, spatially coherent) and RRL
+// rows; it gathers once per row the distinct barycentric RWGs the run reads
+// (u_idx, sorted, so that runs of neighbouring indices coalesce), sums the two
+// sides of each into LDS, and then every thread contracts the column of R of one
+// BC function from LDS through the local positions r_loc.  W is read about 1.2
+// times in all, instead of once per BC function that uses an entry.
+// two sides of barycentric RWG f in row wr, summed (complex64: one 16-byte load)
+__device__ inline float2 bc_pair_sum(const float2* wr, int f) {
+    const float4 v = *reinterpret_cast<const float4*>(wr + 2 * size_t(f));
+    return make_float2(v.x + v.z, v.y + v.w);
+}
+__device__ inline double2 bc_pair_sum(const double2* wr, int f) {
+    const double2 a = wr[2 * size_t(f)], b = wr[2 * size_t(f) + 1];
+    return make_double2(a.x + b.x, a.y + b.y);
+}
+
+constexpr int BC_NQ = BC_UMAX / 256;   // list entries per thread
+constexpr int BC_KG = 8;               // column entries per group
+template <typename C2, int RRL>
 __global__ __launch_bounds__(256) void bc_src_kernel(DevCald c, const C2* __restrict__ W, double2* __restrict__ Yw,
                                                      int nrows) {
-    const int t = blockIdx.x * 256 + threadIdx.x;
-    if (t >= c.N) return;
-    const int n = c.n_order[t];   // neighbouring threads: neighbouring BC functions
-    const int r0 = blockIdx.y * BC_RR;
-    double ar[BC_RR], ai[BC_RR];
+    static_assert(BC_UMAX % 256 == 0, "list bound must be a multiple of the block");
+    __shared__ C2 lw[RRL][BC_UMAX];
+    const int b = blockIdx.x;
+    const int r0 = blockIdx.y * RRL;
+    const int u0 = c.u_ptr[b], nu = c.u_ptr[b + 1] - u0;   // 1 <= nu <= BC_UMAX by construction
+    // the run's list, once for all rows; entries past the end repeat the last one
+    // (loaded, not stored), so every load below is in bounds and unconditional
+    int fl[BC_NQ];
 #pragma unroll
-    for (int u = 0; u < BC_RR; ++u) ar[u] = ai[u] = 0.0;
-    // the column in groups of BC_MAXK entries: all index loads of a group first, then
-    // all BC_RR x BC_MAXK workspace loads
-    for (int kb = c.r_ptr[n], ke = c.r_ptr[n + 1]; kb < ke; kb += BC_MAXK) {
-        int f[BC_MAXK];
-        double v[BC_MAXK];
+    for (int q = 0; q < BC_NQ; ++q) fl[q] = c.u_idx[u0 + min(int(threadIdx.x) + 256 * q, nu - 1)];
+    // rows past the end read a valid row (result dropped); the loads of row u + 1
+    // are in flight while row u is written to LDS
+    auto wrow = [&](int u) { return W + size_t(min(r0 + u, nrows - 1)) * 2 * size_t(c.Nb); };
+    C2 x[BC_NQ], y[BC_NQ];
 #pragma unroll
-        for (int q = 0; q < BC_MAXK; ++q) {
-            const bool ok = kb + q < ke;
-            f[q] = ok ? c.r_idx[kb + q] : 0;
-            v[q] = ok ? c.r_val[kb + q] : 0.0;
+    for (int q = 0; q < BC_NQ; ++q) x[q] = bc_pair_sum(wrow(0), fl[q]);
+#pragma unroll
+    for (int u = 0; u < RRL; ++u) {
+        if (u + 1 < RRL) {
+#pragma unroll
+            for (int q = 0; q < BC_NQ; ++q) y[q] = bc_pair_sum(wrow(u + 1), fl[q]);
         }
 #pragma unroll
-        for (int q = 0; q < BC_MAXK; ++q)
+        for (int q = 0; q < BC_NQ; ++q)
+            if (int(threadIdx.x) + 256 * q < nu) lw[u][threadIdx.x + 256 * q] = x[q];
 #pragma unroll
-            for (int u = 0; u < BC_RR; ++u) {
-                const int row = min(r0 + u, nrows - 1);   // rows past the end: read a valid row, result dropped
-                const C2* w = W + size_t(row) * 2 * size_t(c.Nb) + 2 * size_t(f[q]);
-                const C2 x0 = w[0], x1 = w[1];
-                ar[u] += v[q] * (double(x0.x) + double(x1.x));
-                ai[u] += v[q] * (double(x0.y) + double(x1.y));
+        for (int q = 0; q < BC_NQ; ++q) x[q] = y[q];
+    }
+    __syncthreads();
+    const int t = c.run_t0[b] + int(threadIdx.x);
+    if (t >= c.run_t0[b + 1]) return;
+    const int n = c.n_order[t];
+    double ar[RRL], ai[RRL];
+#pragma unroll
+    for (int u = 0; u < RRL; ++u) ar[u] = ai[u] = 0.0;
+    // the column in groups: all index and coefficient loads of a group first
+    for (int kb = c.r_ptr[n], ke = c.r_ptr[n + 1]; kb < ke; kb += BC_KG) {
+        int l[BC_KG];
+        double v[BC_KG];
+#pragma unroll
+        for (int q = 0; q < BC_KG; ++q) {
+            const int k = min(kb + q, ke - 1);
+            l[q] = c.r_loc[k];
+            v[q] = kb + q < ke ? c.r_val[k] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < BC_KG; ++q)
+#pragma unroll
+            for (int u = 0; u < RRL; ++u) {
+                const C2 xx = lw[u][l[q]];
+                ar[u] += v[q] * double(xx.x);
+                ai[u] += v[q] * double(xx.y);
             }
     }
 #pragma unroll
-    for (int u = 0; u < BC_RR; ++u)
+    for (int u = 0; u < RRL; ++u)
         if (r0 + u < nrows) Yw[size_t(r0 + u) * c.N + n] = make_double2(ar[u], ai[u]);
 }
+constexpr int BC_RRL32 = 4, BC_RRL64 = 2;   // rows per block: 72 KB of LDS either way
 
 // Tbc[m][n] += sum_k coef[k] Yw[rows[k]][n] over the list of BC row m = ml[blockIdx.y]
 __global__ __launch_bounds__(256) void bc_test_kernel(const int32_t* __restrict__ ml, const int32_t* __restrict__ mptr,
@@ -374,6 +417,10 @@ DevCald dev_cald(const efie_calderon_s& C) {
     d.gt_idx = reinterpret_cast<const int32_t*>(b + o[7]);
     d.gt_val = reinterpret_cast<const double*>(b + o[8]);
     d.n_order = reinterpret_cast<const int32_t*>(b + o[9]);
+    d.run_t0 = reinterpret_cast<const int32_t*>(b + o[10]);
+    d.u_ptr = reinterpret_cast<const int32_t*>(b + o[11]);
+    d.u_idx = reinterpret_cast<const int32_t*>(b + o[12]);
+    d.r_loc = reinterpret_cast<const int32_t*>(b + o[13]);
     return d;
 }
 
@@ -411,6 +458,10 @@ int efie_calderon_create(efie_mesh mesh, efie_calderon* out) {
             efie::put(blob, offs, C->gt_idx);
             efie::put(blob, offs, C->gt_val);
             efie::put(blob, offs, C->n_order);
+            efie::put(blob, offs, C->run_t0);
+            efie::put(blob, offs, C->u_ptr);
+            efie::put(blob, offs, C->u_idx);
+            efie::put(blob, offs, C->r_loc);
             blob.resize(efie::a256(blob.size()));
             C->host_blob.swap(blob);
             C->offs.swap(offs);
@@ -463,7 +514,11 @@ int efie_calderon_host_matrices(efie_calderon c, double* R, double* G) {
         if (R) {
             std::memset(R, 0, sizeof(double) * Nb * N);
             for (size_t n = 0; n < N; ++n)
-                for (int32_t k = c->r_ptr[n]; k < c->r_ptr[n + 1]; ++k) R[size_t(c->r_idx[size_t(k)]) * N + n] = c->r_val[size_t(k)];
+                for (int32_t k = c->r_ptr[n]; k < c->r_ptr[n + 1]; ++k) {
+                    const int32_t e = c->r_idx[size_t(k)];
+                    R[size_t(c->bary_canon[size_t(e)]) * N + n] = c->bary_flip[size_t(e)] ? -c->r_val[size_t(k)]
+                                                                                          : c->r_val[size_t(k)];
+                }
         }
         if (G) {
             std::memset(G, 0, sizeof(double) * N * N);
@@ -501,15 +556,21 @@ int efie_calderon_assemble_ex(efie_calderon c, double kt_re, double kt_im, doubl
         fill_zero_bytes(w.Tbc, size_t(N) * N * 16, stream);
         const int Tb = int(c->bary.T);
         const unsigned nx = unsigned((N + 255) / 256);
+        static_assert(BC_BLOCK == 256, "one thread per BC function of a run");
+        EFIE_REQUIRE(c->u_max <= BC_UMAX, EFIE_ERR_STATE, "calderon_assemble: BC run lists too long");
+        const unsigned nruns = unsigned(c->run_t0.size() - 1);
         for (int ch = 0; ch < pl.nchunks; ++ch) {
             const int c0 = ch * pl.chunk, c1 = std::min(Tb, c0 + pl.chunk), np = c1 - c0;
             pair_rows_chunk(c->bary.dm, kt_re, kt_im, eta, bary_dtype, w.W, c0, c1, c->bary.near_p, stream);
+            const int nr = 3 * np;
             if (bary_dtype == EFIE_C64)
-                hipLaunchKernelGGL(bc_src_kernel<float2>, dim3(nx, unsigned((3 * np + BC_RR - 1) / BC_RR)), dim3(256),
-                                   0, stream, d, static_cast<const float2*>(w.W), w.Yw, 3 * np);
+                hipLaunchKernelGGL((bc_src_kernel<float2, BC_RRL32>),
+                                   dim3(nruns, unsigned((nr + BC_RRL32 - 1) / BC_RRL32)), dim3(256), 0, stream, d,
+                                   static_cast<const float2*>(w.W), w.Yw, nr);
             else
-                hipLaunchKernelGGL(bc_src_kernel<double2>, dim3(nx, unsigned((3 * np + BC_RR - 1) / BC_RR)),
-                                   dim3(256), 0, stream, d, static_cast<const double2*>(w.W), w.Yw, 3 * np);
+                hipLaunchKernelGGL((bc_src_kernel<double2, BC_RRL64>),
+                                   dim3(nruns, unsigned((nr + BC_RRL64 - 1) / BC_RRL64)), dim3(256), 0, stream, d,
+                                   static_cast<const double2*>(w.W), w.Yw, nr);
             if (L.nm[size_t(ch)] > 0)
                 hipLaunchKernelGGL(bc_test_kernel, dim3(nx, unsigned(L.nm[size_t(ch)])), dim3(256), 0, stream,
                                    w.ml + L.m0[size_t(ch)], w.mptr + L.mp0[size_t(ch)], w.rows, w.coef, w.Yw, w.Tbc, N);

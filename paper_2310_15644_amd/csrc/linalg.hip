@@ -400,34 +400,35 @@ void gemv(const void* Z, int zdt, int n, const void* x, int xdt, void* y, int yd
 // ------------------------------------------------- FP64 matrix-core product
 // C[crow[s]][i] = sum_k A[arow[s]][k] B[i][k] (complex128 A and C, complex128 or
 // complex64 B; B square n x n with K = n here) on v_mfma_f64_16x16x4f64, in the
-// real 4M form used by the complex64 kernel: A viewed as reals A[s][2k+t],
-// B built on the fly from the 2 x 2 real blocks of each complex B[i][k], so every
-// complex multiply-add is four real FP64 multiply-adds on the matrix cores.
+// planar complex form of the complex64 kernel: the K chunks of A and B sit in LDS
+// as complex rows, a lane's operand element is one complex value (one 16-byte LDS
+// read), and each 16 x 16 complex output block takes four real instructions per 4
+// complex K:  Cr += Ar Br + (-Ai) Bi,  Ci += Ar Bi + Ai Br.
 // Operand layouts of v_mfma_f64_16x16x4f64: lane l supplies A[l%16][l/16] and
 // B[l/16][l%16]; accumulator register r of lane l holds D[l/16 + 4*r][l%16]
 // (rows interleaved, unlike the FP32 16x16x4 form).
 // Tiling as the complex64 kernel: 4 wavefronts (WGM along the right-hand sides x
-// 4/WGM along the columns), a BM x BN real tile, K chunks of KC complex elements
-// double-buffered in LDS with register prefetch, XCD-aware block order.  Few
-// right-hand sides (the residual products of a handful of columns) use a 16-row
-// tile with all four wavefronts along the columns, so Z is read once.
+// 4/WGM along the columns), a BM x BNC complex tile, K chunks of KC complex
+// elements double-buffered in LDS with register prefetch, XCD-aware block order.
+// LDS rows hold KC + 1 complex values, which keeps the 16-byte reads of a
+// wavefront free of bank conflicts.  Few right-hand sides (the residual products
+// of a handful of columns) use a 16-row tile with all four wavefronts along the
+// columns, so Z is read once.
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
-template <int BM, int BN, int KC, int WGM, typename BT>
+template <int BM, int BNC, int KC, int WGM, typename BT>
 __global__ __launch_bounds__(256) void zgemm_mfma_kernel(const double2* __restrict__ A, const BT* __restrict__ B,
                                                          double2* __restrict__ C, int M, int n, int lda, int ldc,
                                                          const int* __restrict__ arow, const int* __restrict__ crow) {
-    constexpr int AP = 2 * KC + 2;     // doubles per LDS row of the A tile (16-byte rows)
-    constexpr int BNC = BN / 2;        // complex columns of C per tile
-    constexpr int BP = KC + 1;         // double2 per LDS row of the B tile
+    constexpr int AS = KC + 1;         // double2 per LDS row
     constexpr int WGN = 4 / WGM;
-    constexpr int WM = BM / WGM, WN = BN / WGN;
+    constexpr int WM = BM / WGM, WN = BNC / WGN;
     constexpr int TM = WM / 16, TN = WN / 16;
     constexpr int NA = BM * KC / 256, NB = BNC * KC / 256;
     static_assert(WGM * WGN == 4 && TM >= 1 && TN >= 1, "bad wavefront arrangement");
     static_assert(BM * KC % 256 == 0 && BNC * KC % 256 == 0, "tile not divisible by the block");
-    __shared__ double As[2][BM * AP];
-    __shared__ double2 Bs[2][BNC * BP];
+    __shared__ double2 As[2][BM * AS];
+    __shared__ double2 Bs[2][BNC * AS];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
@@ -440,11 +441,14 @@ __global__ __launch_bounds__(256) void zgemm_mfma_kernel(const double2* __restri
     const int bm = logical % nbm, bn = logical / nbm;
     const int s0 = bm * BM, i0 = bn * BNC;
 
-    doublex4 acc[TM][TN];
+    doublex4 accr[TM][TN], acci[TM][TN];
 #pragma unroll
     for (int a = 0; a < TM; ++a)
 #pragma unroll
-        for (int b = 0; b < TN; ++b) acc[a][b] = doublex4{0.0, 0.0, 0.0, 0.0};
+        for (int b = 0; b < TN; ++b) {
+            accr[a][b] = doublex4{0.0, 0.0, 0.0, 0.0};
+            acci[a][b] = doublex4{0.0, 0.0, 0.0, 0.0};
+        }
 
     double2 ra[NA];
     BT rb[NB];   // raw storage type: converted when written to LDS, so the loads stay in flight
@@ -466,12 +470,12 @@ __global__ __launch_bounds__(256) void zgemm_mfma_kernel(const double2* __restri
 #pragma unroll
         for (int q = 0; q < NA; ++q) {
             const int e = tid + 256 * q, r = e / KC, c = e % KC;
-            *reinterpret_cast<double2*>(&As[buf][r * AP + 2 * c]) = ra[q];
+            As[buf][r * AS + c] = ra[q];
         }
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
             const int e = tid + 256 * q, r = e / KC, c = e % KC;
-            Bs[buf][r * BP + c] = to_d2(rb[q]);
+            Bs[buf][r * AS + c] = to_d2(rb[q]);
         }
     };
 
@@ -483,27 +487,29 @@ __global__ __launch_bounds__(256) void zgemm_mfma_kernel(const double2* __restri
     for (int ch = 0; ch < nch; ++ch) {
         const int buf = ch & 1;
         if (ch + 1 < nch) gload((ch + 1) * KC);
-        const double* A_ = As[buf];
-        const double2* B_ = Bs[buf];
+        const double2* A_ = As[buf] + (wm * WM + l16) * AS + kq;
+        const double2* B_ = Bs[buf] + (wn * WN + l16) * AS + kq;
 #pragma unroll
-        for (int st = 0; st < KC / 2; ++st) {
-            const int kf = 4 * st + kq;
-            const int jj = kf >> 1, t = kf & 1;
-            double av[TM], bv[TN];
+        for (int kk = 0; kk < KC; kk += 4) {
+            double2 xa[TM], zb[TN];
 #pragma unroll
-            for (int a = 0; a < TM; ++a) av[a] = A_[(wm * WM + a * 16 + l16) * AP + kf];
+            for (int a = 0; a < TM; ++a) xa[a] = A_[a * 16 * AS + kk];
 #pragma unroll
-            for (int b = 0; b < TN; ++b) {
-                const int col = wn * WN + b * 16 + l16;
-                const double2 z = B_[(col >> 1) * BP + jj];
-                const int u = col & 1;
-                bv[b] = u == 0 ? (t == 0 ? z.x : -z.y) : (t == 0 ? z.y : z.x);
-            }
+            for (int b = 0; b < TN; ++b) zb[b] = B_[b * 16 * AS + kk];
 #pragma unroll
             for (int a = 0; a < TM; ++a)
 #pragma unroll
-                for (int b = 0; b < TN; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+                for (int b = 0; b < TN; ++b) {
+                    accr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[a].x, zb[b].x, accr[a][b], 0, 0, 0);
+                    acci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[a].x, zb[b].y, acci[a][b], 0, 0, 0);
+                }
+#pragma unroll
+            for (int a = 0; a < TM; ++a)
+#pragma unroll
+                for (int b = 0; b < TN; ++b) {
+                    accr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-xa[a].y, zb[b].y, accr[a][b], 0, 0, 0);
+                    acci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[a].y, zb[b].x, acci[a][b], 0, 0, 0);
+                }
         }
         if (ch + 1 < nch) lstore(buf ^ 1);
         __syncthreads();
@@ -512,32 +518,32 @@ __global__ __launch_bounds__(256) void zgemm_mfma_kernel(const double2* __restri
     for (int a = 0; a < TM; ++a)
 #pragma unroll
         for (int b = 0; b < TN; ++b) {
-            const int col = 2 * i0 + wn * WN + b * 16 + l16;
+            const int col = i0 + wn * WN + b * 16 + l16;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = s0 + wm * WM + a * 16 + kq + 4 * r;
-                if (row < M && col < 2 * n)
-                    reinterpret_cast<double*>(C)[size_t(crow ? crow[row] : row) * 2 * ldc + col] = acc[a][b][r];
+                if (row < M && col < n)
+                    C[size_t(crow ? crow[row] : row) * ldc + col] = make_double2(accr[a][b][r], acci[a][b][r]);
             }
         }
 }
 
-template <int BM, int BN, int KC, int WGM, typename BT>
+template <int BM, int BNC, int KC, int WGM, typename BT>
 static void launch_zgemm_tile(const double2* A, const BT* B, double2* C, int M, int n, int lda, int ldc,
                               const int* arow, const int* crow, hipStream_t s) {
-    const size_t nblk = size_t((M + BM - 1) / BM) * size_t((n + BN / 2 - 1) / (BN / 2));
+    const size_t nblk = size_t((M + BM - 1) / BM) * size_t((n + BNC - 1) / BNC);
     EFIE_REQUIRE(nblk < (size_t(1) << 31), EFIE_ERR_ARG, "zgemm: problem too large");
-    hipLaunchKernelGGL((zgemm_mfma_kernel<BM, BN, KC, WGM, BT>), dim3(unsigned(nblk)), dim3(256), 0, s, A, B, C, M, n,
-                       lda, ldc, arow, crow);
+    hipLaunchKernelGGL((zgemm_mfma_kernel<BM, BNC, KC, WGM, BT>), dim3(unsigned(nblk)), dim3(256), 0, s, A, B, C, M,
+                       n, lda, ldc, arow, crow);
 }
 
 template <typename BT>
 static void launch_zgemm_mfma(const double2* A, const BT* B, double2* C, int M, int n, int lda, int ldc,
                               const int* arow, const int* crow, hipStream_t s) {
     if (M <= 16)
-        launch_zgemm_tile<16, 256, 16, 1>(A, B, C, M, n, lda, ldc, arow, crow, s);
+        launch_zgemm_tile<16, 64, 16, 1>(A, B, C, M, n, lda, ldc, arow, crow, s);
     else if (M <= 64)
-        launch_zgemm_tile<32, 128, 16, 1>(A, B, C, M, n, lda, ldc, arow, crow, s);
+        launch_zgemm_tile<32, 64, 16, 1>(A, B, C, M, n, lda, ldc, arow, crow, s);
     else
         launch_zgemm_tile<64, 64, 16, 2>(A, B, C, M, n, lda, ldc, arow, crow, s);
 }
