@@ -312,7 +312,9 @@ int efie_solve(const void* Z, int dtype, int64_t n, const void* V, void* J, int6
  *   (at most 2 GiB) that are contracted with R at once.  Rows of P solve
  *   G_mix^T p = T_BC row by CGNR (batches of rows, column layout) to the relative
  *   residual tol (maxit steps); *relres (host, may be NULL) gets the worst
- *   achieved.  ws: dev workspace of ws_bytes from efie_calderon_sizes (T_BC,
+ *   achieved.  For tol >= 1e-4 the CGNR vectors are stored in complex64 (every
+ *   sum, norm and update still in FP64), which bounds the attainable residual
+ *   near 1e-6; tighter tolerances keep them in complex128.  ws: dev workspace of ws_bytes from efie_calderon_sizes (T_BC,
  *   16 N^2 bytes, plus a few GiB).  EFIE_NOT_CONVERGED if tol missed.
  * efie_calderon_assemble_ex: the same with bary_dtype EFIE_C128 (as above) or
  *   EFIE_C64: barycentric far pairs in FP32 (near pairs FP64) and complex64

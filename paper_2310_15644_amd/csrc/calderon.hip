@@ -149,28 +149,56 @@ __global__ __launch_bounds__(256) void bc_test_kernel(const int32_t* __restrict_
 }
 
 // ---------------------------------------------- CGNR in column layout X[j][s]
+// The vectors are stored as V (double2, or float2 when the requested tolerance
+// is loose: CGNR_C64_TOL); every sum, norm and update is evaluated in FP64.
+constexpr double CGNR_C64_TOL = 1e-4;
+__device__ inline double2 ld2(const double2& v) { return v; }
+__device__ inline double2 ld2(const float2& v) { return make_double2(double(v.x), double(v.y)); }
+template <typename V>
+__device__ inline V st2(double x, double y);
+template <>
+__device__ inline double2 st2<double2>(double x, double y) { return make_double2(x, y); }
+template <>
+__device__ inline float2 st2<float2>(double x, double y) { return make_float2(float(x), float(y)); }
+
 // Out[j][s] = sum_k val[k] X[idx[k]][s], k over row j of a real CSR matrix;
 // grid (N rows, column tiles of 256)
+template <typename V>
 __global__ __launch_bounds__(256) void cspmm_kernel(const int32_t* __restrict__ ptr, const int32_t* __restrict__ idx,
-                                                    const double* __restrict__ val, const double2* __restrict__ X,
-                                                    int ldx, double2* __restrict__ Out, int S,
+                                                    const double* __restrict__ val, const V* __restrict__ X,
+                                                    int ldx, V* __restrict__ Out, int S,
                                                     const int32_t* __restrict__ order) {
     const int j = order[blockIdx.x];   // rows in a spatially coherent order
     const int s = blockIdx.y * 256 + threadIdx.x;
     if (s >= S) return;
     double ar = 0, ai = 0;
-    for (int k = ptr[j]; k < ptr[j + 1]; ++k) {
-        const double2 v = X[size_t(idx[k]) * ldx + s];
-        ar += val[k] * v.x;
-        ai += val[k] * v.y;
+    // the row in groups of 8: the (block-uniform) indices first, then 8 gathers in flight
+    for (int kb = ptr[j], ke = ptr[j + 1]; kb < ke; kb += 8) {
+        int ix[8];
+        double vv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int k = min(kb + q, ke - 1);
+            ix[q] = idx[k];
+            vv[q] = kb + q < ke ? val[k] : 0.0;
+        }
+        double2 x[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) x[q] = ld2(X[size_t(ix[q]) * ldx + s]);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            ar += vv[q] * x[q].x;
+            ai += vv[q] * x[q].y;
+        }
     }
-    Out[size_t(j) * S + s] = make_double2(ar, ai);
+    Out[size_t(j) * S + s] = st2<V>(ar, ai);
 }
 
 constexpr int CJS = 32;   // row slices of the column reductions
 // part[js][s] = sum over rows j of slice js of |X[j][s]|^2; block = 64 columns x 4
 // row stripes, grid (column tiles of 64, CJS slices)
-__global__ __launch_bounds__(256) void colsq_part_kernel(const double2* __restrict__ X, int ld, int N, int S,
+template <typename V>
+__global__ __launch_bounds__(256) void colsq_part_kernel(const V* __restrict__ X, int ld, int N, int S,
                                                          double* __restrict__ part) {
     __shared__ double sh[4][64];
     const int cl = threadIdx.x & 63, st = threadIdx.x >> 6;
@@ -180,7 +208,7 @@ __global__ __launch_bounds__(256) void colsq_part_kernel(const double2* __restri
     double a = 0.0;
     if (s < S)
         for (int j = j0 + st; j < j1; j += 4) {
-            const double2 v = X[size_t(j) * ld + s];
+            const double2 v = ld2(X[size_t(j) * ld + s]);
             a += v.x * v.x + v.y * v.y;
         }
     sh[st][cl] = a;
@@ -201,13 +229,15 @@ struct CgnrCol {
 };
 
 // w = 0, r = b (b[j][s] with leading dimension ldb)
-__global__ void cgnr_init_kernel(const double2* __restrict__ b, int ldb, double2* __restrict__ w,
-                                 double2* __restrict__ r, int N, int S) {
+template <typename V>
+__global__ void cgnr_init_kernel(const double2* __restrict__ b, int ldb, V* __restrict__ w, V* __restrict__ r, int N,
+                                 int S) {
     const size_t tot = size_t(N) * S;
     for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < tot; e += size_t(gridDim.x) * blockDim.x) {
         const size_t j = e / S, s = e - j * S;
-        w[e] = make_double2(0.0, 0.0);
-        r[e] = b[j * ldb + s];
+        const double2 v = b[j * ldb + s];
+        w[e] = st2<V>(0.0, 0.0);
+        r[e] = st2<V>(v.x, v.y);
     }
 }
 __global__ void cgnr_setup_kernel(CgnrCol* cols, const double* bn2, const double* zz, double tol, int S) {
@@ -222,22 +252,19 @@ __global__ void cgnr_setup_kernel(CgnrCol* cols, const double* bn2, const double
     cols[s] = c;
 }
 // after t = G^T p, tt = ||t||^2: alpha = gamma / tt, w += alpha p, r -= alpha t
-__global__ void cgnr_upd1_kernel(double2* __restrict__ w, double2* __restrict__ r, const double2* __restrict__ p,
-                                 const double2* __restrict__ t, const CgnrCol* __restrict__ cols,
+template <typename V>
+__global__ void cgnr_upd1_kernel(V* __restrict__ w, V* __restrict__ r, const V* __restrict__ p,
+                                 const V* __restrict__ t, const CgnrCol* __restrict__ cols,
                                  const double* __restrict__ tt, int N, int S) {
     const size_t tot = size_t(N) * S;
     for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < tot; e += size_t(gridDim.x) * blockDim.x) {
         const int s = int(e % S);
         if (!cols[s].active || !(tt[s] > 0.0)) continue;
         const double al = cols[s].gamma / tt[s];
-        const double2 pp = p[e], tv = t[e];
-        double2 ww = w[e], rr = r[e];
-        ww.x += al * pp.x;
-        ww.y += al * pp.y;
-        rr.x -= al * tv.x;
-        rr.y -= al * tv.y;
-        w[e] = ww;
-        r[e] = rr;
+        const double2 pp = ld2(p[e]), tv = ld2(t[e]);
+        const double2 ww = ld2(w[e]), rr = ld2(r[e]);
+        w[e] = st2<V>(ww.x + al * pp.x, ww.y + al * pp.y);
+        r[e] = st2<V>(rr.x - al * tv.x, rr.y - al * tv.y);
     }
 }
 __global__ void cgnr_check_kernel(CgnrCol* cols, const double* rn2, const double* tt, int S, int* nactive) {
@@ -252,18 +279,16 @@ __global__ void cgnr_check_kernel(CgnrCol* cols, const double* rn2, const double
     if (c.active) atomicAdd(nactive, 1);
 }
 // after z = G r, zz = ||z||^2: p = z + (zz / gamma) p for active columns
-__global__ void cgnr_upd2_kernel(double2* __restrict__ p, const double2* __restrict__ z,
-                                 const CgnrCol* __restrict__ cols, const double* __restrict__ zz, int N, int S) {
+template <typename V>
+__global__ void cgnr_upd2_kernel(V* __restrict__ p, const V* __restrict__ z, const CgnrCol* __restrict__ cols,
+                                 const double* __restrict__ zz, int N, int S) {
     const size_t tot = size_t(N) * S;
     for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < tot; e += size_t(gridDim.x) * blockDim.x) {
         const int s = int(e % S);
         if (!cols[s].active) continue;
         const double be = zz[s] / cols[s].gamma;
-        double2 pp = p[e];
-        const double2 zv = z[e];
-        pp.x = zv.x + be * pp.x;
-        pp.y = zv.y + be * pp.y;
-        p[e] = pp;
+        const double2 pp = ld2(p[e]), zv = ld2(z[e]);
+        p[e] = st2<V>(zv.x + be * pp.x, zv.y + be * pp.y);
     }
 }
 __global__ void cgnr_gamma_kernel(CgnrCol* cols, const double* zz, int S) {
@@ -271,14 +296,15 @@ __global__ void cgnr_gamma_kernel(CgnrCol* cols, const double* zz, int S) {
     if (s < S && cols[s].active) cols[s].gamma = zz[s];
 }
 // P[s0 + s][j] = w[j][s] (32 x 32 tiles through LDS)
-__global__ __launch_bounds__(256) void transpose_kernel(const double2* __restrict__ w, int S, int N,
-                                                        double2* __restrict__ P, int s0) {
+template <typename V>
+__global__ __launch_bounds__(256) void transpose_kernel(const V* __restrict__ w, int S, int N, double2* __restrict__ P,
+                                                        int s0) {
     __shared__ double2 tile[32][33];
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
     const int sb = blockIdx.x * 32, jb = blockIdx.y * 32;
     for (int r = ty; r < 32; r += 8) {
         const int j = jb + r, s = sb + tx;
-        if (j < N && s < S) tile[r][tx] = w[size_t(j) * S + s];
+        if (j < N && s < S) tile[r][tx] = ld2(w[size_t(j) * S + s]);
     }
     __syncthreads();
     for (int r = ty; r < 32; r += 8) {
@@ -297,10 +323,12 @@ constexpr size_t CALD_CG_BUDGET = size_t(6) << 30;   // CGNR vectors of one colu
 struct CaldPlan {
     int chunk = 1, nchunks = 1, Sb = 1;
     size_t entries = 0;   // (BC row, workspace row, coefficient) list entries over all chunks
+    size_t vsz = 16;      // bytes per complex element of the CGNR vectors
 };
 
-CaldPlan cald_plan(const efie_calderon_s& C, int bary_dtype) {
+CaldPlan cald_plan(const efie_calderon_s& C, int bary_dtype, double tol) {
     CaldPlan pl;
+    pl.vsz = tol >= CGNR_C64_TOL ? 8 : 16;
     const size_t esz = bary_dtype == EFIE_C64 ? 8 : 16;
     const size_t per_tri = size_t(6) * size_t(C.bary.N) * esz;
     const size_t Tb = size_t(C.bary.T);
@@ -308,7 +336,7 @@ CaldPlan cald_plan(const efie_calderon_s& C, int bary_dtype) {
     pl.chunk = int(std::max<size_t>(1, std::min<size_t>({Tb, CALD_W_BUDGET / per_tri, 3640})));
     pl.nchunks = int((Tb + size_t(pl.chunk) - 1) / size_t(pl.chunk));
     const size_t N = size_t(C.N);
-    pl.Sb = int(std::max<size_t>(64, std::min<size_t>(N, CALD_CG_BUDGET / (5 * N * 16))));
+    pl.Sb = int(std::max<size_t>(64, std::min<size_t>(N, CALD_CG_BUDGET / (5 * N * pl.vsz))));
     pl.entries = 2 * C.re_idx.size();
     return pl;
 }
@@ -319,7 +347,7 @@ struct CaldWs {
     int32_t *ml, *mptr, *rows;
     double* coef;
     double2* Tbc;
-    double2 *w, *r, *z, *p, *t;
+    void *w, *r, *z, *p, *t;   // CGNR vectors (complex64 or complex128)
     double *part, *bn2, *tt, *rn2, *zz;
     CgnrCol* cols;
     int* counter;
@@ -342,11 +370,11 @@ size_t cald_layout(const efie_calderon_s& C, const CaldPlan& pl, int bary_dtype,
     x.rows = (int32_t*)take(4 * pl.entries);
     x.coef = (double*)take(8 * pl.entries);
     x.Tbc = (double2*)take(N * N * 16);
-    x.w = (double2*)take(N * Sb * 16);
-    x.r = (double2*)take(N * Sb * 16);
-    x.z = (double2*)take(N * Sb * 16);
-    x.p = (double2*)take(N * Sb * 16);
-    x.t = (double2*)take(N * Sb * 16);
+    x.w = take(N * Sb * pl.vsz);
+    x.r = take(N * Sb * pl.vsz);
+    x.z = take(N * Sb * pl.vsz);
+    x.p = take(N * Sb * pl.vsz);
+    x.t = take(N * Sb * pl.vsz);
     x.part = (double*)take(8 * size_t(CJS) * Sb);
     x.bn2 = (double*)take(8 * Sb);
     x.tt = (double*)take(8 * Sb);
@@ -433,6 +461,68 @@ size_t put(std::vector<char>& blob, std::vector<size_t>& offs, const std::vector
     return off;
 }
 
+// CGNR on G^T Y = T_BC for the columns of T_BC in batches of pl.Sb (vectors stored
+// as V), each batch transposed into P; returns the worst final relative residual.
+template <typename V>
+double cald_cgnr(const DevCald& d, const CaldWs& w, const CaldPlan& pl, int N, double tol, int maxit, double2* Pout,
+                 hipStream_t stream) {
+    V* const wv = static_cast<V*>(w.w);
+    V* const rv = static_cast<V*>(w.r);
+    V* const zv = static_cast<V*>(w.z);
+    V* const pv = static_cast<V*>(w.p);
+    V* const tv = static_cast<V*>(w.t);
+    double worst = 0.0;
+    auto colsq = [&](const V* X, int ld, int S, double* out) {
+        hipLaunchKernelGGL(colsq_part_kernel<V>, dim3(unsigned((S + 63) / 64), unsigned(CJS)), dim3(256), 0, stream, X,
+                           ld, N, S, w.part);
+        hipLaunchKernelGGL(colsq_final_kernel, dim3(unsigned((S + 255) / 256)), dim3(256), 0, stream, w.part, S, out);
+    };
+    for (int s0 = 0; s0 < N; s0 += pl.Sb) {
+        const int S = std::min(pl.Sb, N - s0);
+        const size_t tot = size_t(N) * S;
+        const int ge = int(std::min<size_t>((tot + 255) / 256, 16384));
+        const dim3 gs(unsigned(N), unsigned((S + 255) / 256));
+        hipLaunchKernelGGL(cgnr_init_kernel<V>, dim3(ge), dim3(256), 0, stream, w.Tbc + s0, N, wv, rv, N, S);
+        colsq(rv, S, S, w.bn2);
+        hipLaunchKernelGGL(cspmm_kernel<V>, gs, dim3(256), 0, stream, d.g_ptr, d.g_idx, d.g_val, rv, S, zv, S,
+                           d.n_order);
+        colsq(zv, S, S, w.zz);
+        EFIE_HIP_CHECK(hipMemcpyAsync(pv, zv, tot * sizeof(V), hipMemcpyDeviceToDevice, stream));
+        hipLaunchKernelGGL(cgnr_setup_kernel, dim3(unsigned((S + 255) / 256)), dim3(256), 0, stream, w.cols, w.bn2,
+                           w.zz, tol, S);
+        int h_active = S;
+        for (int it = 0; it < maxit && h_active > 0; ++it) {
+            hipLaunchKernelGGL(cspmm_kernel<V>, gs, dim3(256), 0, stream, d.gt_ptr, d.gt_idx, d.gt_val, pv, S, tv, S,
+                               d.n_order);
+            colsq(tv, S, S, w.tt);
+            hipLaunchKernelGGL(cgnr_upd1_kernel<V>, dim3(ge), dim3(256), 0, stream, wv, rv, pv, tv, w.cols, w.tt, N,
+                               S);
+            colsq(rv, S, S, w.rn2);
+            EFIE_HIP_CHECK(hipMemsetAsync(w.counter, 0, sizeof(int), stream));
+            hipLaunchKernelGGL(cgnr_check_kernel, dim3(unsigned((S + 255) / 256)), dim3(256), 0, stream, w.cols, w.rn2,
+                               w.tt, S, w.counter);
+            hipLaunchKernelGGL(cspmm_kernel<V>, gs, dim3(256), 0, stream, d.g_ptr, d.g_idx, d.g_val, rv, S, zv, S,
+                               d.n_order);
+            colsq(zv, S, S, w.zz);
+            hipLaunchKernelGGL(cgnr_upd2_kernel<V>, dim3(ge), dim3(256), 0, stream, pv, zv, w.cols, w.zz, N, S);
+            hipLaunchKernelGGL(cgnr_gamma_kernel, dim3(unsigned((S + 255) / 256)), dim3(256), 0, stream, w.cols, w.zz,
+                               S);
+            EFIE_HIP_CHECK(hipMemcpyAsync(&h_active, w.counter, sizeof(int), hipMemcpyDeviceToHost, stream));
+            EFIE_HIP_CHECK(hipStreamSynchronize(stream));
+        }
+        hipLaunchKernelGGL(transpose_kernel<V>, dim3(unsigned((S + 31) / 32), unsigned((N + 31) / 32)), dim3(256), 0,
+                           stream, wv, S, N, Pout, s0);
+        if (verbose())
+            std::fprintf(stderr, "[efie] calderon CGNR columns %d..%d done t=%.3f\n", s0, s0 + S, now_s()),
+                std::fflush(stderr);
+        std::vector<CgnrCol> cols(static_cast<size_t>(S));
+        EFIE_HIP_CHECK(hipMemcpyAsync(cols.data(), w.cols, sizeof(CgnrCol) * size_t(S), hipMemcpyDeviceToHost, stream));
+        EFIE_HIP_CHECK(hipStreamSynchronize(stream));
+        for (const auto& cc : cols) worst = std::max(worst, cc.bn2 > 0 ? std::sqrt(cc.rn2 / cc.bn2) : 0.0);
+    }
+    return worst;
+}
+
 }  // namespace
 }  // namespace efie
 
@@ -484,9 +574,13 @@ int efie_calderon_sizes(efie_calderon c, int64_t* n_bary_rwg, int64_t* n_bary_tr
         if (n_bary_rwg) *n_bary_rwg = c->bary.N;
         if (n_bary_tri) *n_bary_tri = c->bary.T;
         if (table_bytes) *table_bytes = efie::a256(c->bary_bytes) + c->host_blob.size();
-        if (ws_bytes)
-            *ws_bytes = std::max(efie::cald_layout(*c, efie::cald_plan(*c, EFIE_C128), EFIE_C128, nullptr, nullptr),
-                                 efie::cald_layout(*c, efie::cald_plan(*c, EFIE_C64), EFIE_C64, nullptr, nullptr));
+        if (ws_bytes) {
+            size_t mx = 0;
+            for (int dt : {EFIE_C128, EFIE_C64})
+                for (double tl : {1.0, 0.0})
+                    mx = std::max(mx, efie::cald_layout(*c, efie::cald_plan(*c, dt, tl), dt, nullptr, nullptr));
+            *ws_bytes = mx;
+        }
         return int(EFIE_OK);
     });
 }
@@ -540,7 +634,7 @@ int efie_calderon_assemble_ex(efie_calderon c, double kt_re, double kt_im, doubl
         EFIE_REQUIRE(kt_im <= 0.0 && (kt_re != 0.0 || kt_im != 0.0), EFIE_ERR_ARG, "calderon_assemble: bad k~");
         EFIE_REQUIRE(tol > 0.0 && maxit >= 1, EFIE_ERR_ARG, "calderon_assemble: bad tol/maxit");
         const int N = int(c->N);
-        const CaldPlan pl = cald_plan(*c, bary_dtype);
+        const CaldPlan pl = cald_plan(*c, bary_dtype, tol);
         const size_t need = cald_layout(*c, pl, bary_dtype, nullptr, nullptr);
         EFIE_REQUIRE(ws_bytes >= need, EFIE_ERR_ARG, "calderon_assemble: workspace too small");
         EFIE_REQUIRE((reinterpret_cast<uintptr_t>(ws) & 255) == 0, EFIE_ERR_ARG, "calderon_assemble: ws not aligned");
@@ -583,58 +677,8 @@ int efie_calderon_assemble_ex(efie_calderon c, double kt_re, double kt_im, doubl
         if (Tbc_out)
             EFIE_HIP_CHECK(hipMemcpyAsync(Tbc_out, w.Tbc, size_t(N) * N * 16, hipMemcpyDeviceToDevice, stream));
         // ---- P = T_BC G^{-1}: column batches of G^T Y = T_BC (column s = row s of T_BC), P = Y^T
-        double2* Pout = static_cast<double2*>(P);
-        double worst = 0.0;
-        auto colsq = [&](const double2* X, int ld, int S, double* out) {
-            hipLaunchKernelGGL(colsq_part_kernel, dim3(unsigned((S + 63) / 64), unsigned(CJS)), dim3(256), 0, stream,
-                               X, ld, N, S, w.part);
-            hipLaunchKernelGGL(colsq_final_kernel, dim3(unsigned((S + 255) / 256)), dim3(256), 0, stream, w.part, S,
-                               out);
-        };
-        for (int s0 = 0; s0 < N; s0 += pl.Sb) {
-            const int S = std::min(pl.Sb, N - s0);
-            const size_t tot = size_t(N) * S;
-            const int ge = int(std::min<size_t>((tot + 255) / 256, 16384));
-            const dim3 gs(unsigned(N), unsigned((S + 255) / 256));
-            hipLaunchKernelGGL(cgnr_init_kernel, dim3(ge), dim3(256), 0, stream, w.Tbc + s0, N, w.w, w.r, N, S);
-            colsq(w.r, S, S, w.bn2);
-            hipLaunchKernelGGL(cspmm_kernel, gs, dim3(256), 0, stream, d.g_ptr, d.g_idx, d.g_val, w.r, S, w.z, S,
-                               d.n_order);
-            colsq(w.z, S, S, w.zz);
-            EFIE_HIP_CHECK(hipMemcpyAsync(w.p, w.z, tot * 16, hipMemcpyDeviceToDevice, stream));
-            hipLaunchKernelGGL(cgnr_setup_kernel, dim3(unsigned((S + 255) / 256)), dim3(256), 0, stream, w.cols, w.bn2,
-                               w.zz, tol, S);
-            int h_active = S;
-            for (int it = 0; it < maxit && h_active > 0; ++it) {
-                hipLaunchKernelGGL(cspmm_kernel, gs, dim3(256), 0, stream, d.gt_ptr, d.gt_idx, d.gt_val, w.p, S, w.t,
-                                   S, d.n_order);
-                colsq(w.t, S, S, w.tt);
-                hipLaunchKernelGGL(cgnr_upd1_kernel, dim3(ge), dim3(256), 0, stream, w.w, w.r, w.p, w.t, w.cols, w.tt,
-                                   N, S);
-                colsq(w.r, S, S, w.rn2);
-                EFIE_HIP_CHECK(hipMemsetAsync(w.counter, 0, sizeof(int), stream));
-                hipLaunchKernelGGL(cgnr_check_kernel, dim3(unsigned((S + 255) / 256)), dim3(256), 0, stream, w.cols,
-                                   w.rn2, w.tt, S, w.counter);
-                hipLaunchKernelGGL(cspmm_kernel, gs, dim3(256), 0, stream, d.g_ptr, d.g_idx, d.g_val, w.r, S, w.z, S,
-                               d.n_order);
-                colsq(w.z, S, S, w.zz);
-                hipLaunchKernelGGL(cgnr_upd2_kernel, dim3(ge), dim3(256), 0, stream, w.p, w.z, w.cols, w.zz, N, S);
-                hipLaunchKernelGGL(cgnr_gamma_kernel, dim3(unsigned((S + 255) / 256)), dim3(256), 0, stream, w.cols,
-                                   w.zz, S);
-                EFIE_HIP_CHECK(hipMemcpyAsync(&h_active, w.counter, sizeof(int), hipMemcpyDeviceToHost, stream));
-                EFIE_HIP_CHECK(hipStreamSynchronize(stream));
-            }
-            hipLaunchKernelGGL(transpose_kernel, dim3(unsigned((S + 31) / 32), unsigned((N + 31) / 32)), dim3(256), 0,
-                               stream, w.w, S, N, Pout, s0);
-            if (verbose())
-                std::fprintf(stderr, "[efie] calderon CGNR columns %d..%d done t=%.3f\n", s0, s0 + S, now_s()),
-                    std::fflush(stderr);
-            std::vector<CgnrCol> cols(static_cast<size_t>(S));
-            EFIE_HIP_CHECK(
-                hipMemcpyAsync(cols.data(), w.cols, sizeof(CgnrCol) * size_t(S), hipMemcpyDeviceToHost, stream));
-            EFIE_HIP_CHECK(hipStreamSynchronize(stream));
-            for (const auto& cc : cols) worst = std::max(worst, cc.bn2 > 0 ? std::sqrt(cc.rn2 / cc.bn2) : 0.0);
-        }
+        const double worst = pl.vsz == 8 ? cald_cgnr<float2>(d, w, pl, N, tol, maxit, static_cast<double2*>(P), stream)
+                                         : cald_cgnr<double2>(d, w, pl, N, tol, maxit, static_cast<double2*>(P), stream);
         if (relres) *relres = worst;
         EFIE_HIP_CHECK(hipGetLastError());
         return worst <= tol ? int(EFIE_OK) : int(EFIE_NOT_CONVERGED);
