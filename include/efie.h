@@ -233,7 +233,9 @@ int efie_zx_flush64(const void* Z, int64_t n, const void* X, void* Y, int64_t nr
  * efie_gemm_autotune times every variant on the caller's Z (n x n complex64) and
  * X (M x n complex64) with HIP events (reps launches each, after one warm-up),
  * writes the mean milliseconds per launch into ms[variant] (host, count
- * entries), returns the fastest in *best, and does not change the selection.
+ * entries), returns in *best the first variant (in table order) within 2 % of
+ * the fastest, so that timing noise does not flip between near-equal tiles, and
+ * does not change the selection.
  * ws: dev scratch of at least M*n*(acc64 ? 16 : 8) bytes rounded up to 256, plus
  * 4*M bytes.  efie_gemm_select sets the variant used by later calls (process-wide).
  */

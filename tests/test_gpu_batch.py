@@ -63,10 +63,12 @@ def test_batch_solve_equals_single(dev):
     for i, m in enumerate(meshes):
         J1, st1 = P.solve(B.z_of(Zc, i).contiguous(), Vc[B.voff[i]:B.voff[i + 1]].contiguous(), tol=1e-10,
                           maxit=1000)
-        # grouped and single GEMV sum in different orders; COCG's step count to 1e-10 in
-        # finite precision follows the rounding (loss of bi-orthogonality), so the two
-        # counts agree to a few percent, not exactly
-        assert abs(int(st1.iters[0]) - int(st.iters[i])) <= max(3, int(0.05 * st1.iters[0]))
+        # grouped and single GEMV sum in different orders, and the batch matrix itself
+        # is accumulated with atomics (its rounding differs from run to run); COCG's step
+        # count to 1e-10 in finite precision follows the rounding (loss of
+        # bi-orthogonality), so the counts agree to within ten percent, not exactly;
+        # the currents are the comparison that matters
+        assert abs(int(st1.iters[0]) - int(st.iters[i])) <= max(3, int(0.10 * st1.iters[0]))
         a = J[B.voff[i]:B.voff[i + 1]].cpu().numpy()
         b = J1.cpu().numpy()[0]
         assert np.linalg.norm(a - b) <= 1e-8 * np.linalg.norm(b)
