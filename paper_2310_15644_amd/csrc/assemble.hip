@@ -76,8 +76,12 @@ struct Cplx<double> {
     using T = double2;
 };
 
-// pass 1: block = (test triangle p of the chunk, 256 source triangles)
-template <typename R, bool CK>
+// pass 1: block = (test triangle p of the chunk, 256 source triangles).  UPPER:
+// only the far pairs with source triangle q > p are written; the entries of the
+// pairs q < p are left unwritten and those of near pairs to near_rows_kernel (the
+// caller reads only the entries of triangles q >= p and restores the other half
+// from the symmetry of the operator).
+template <typename R, bool CK, bool UPPER>
 __global__ __launch_bounds__(FAR_BLOCK) void far_rows_kernel(DevMesh m, Tables<R> tb, R kphase, R ki, Scale sc,
                                                              typename Cplx<R>::T* __restrict__ W, int c0, int nqblk) {
     using C2 = typename Cplx<R>::T;
@@ -99,7 +103,9 @@ __global__ __launch_bounds__(FAR_BLOCK) void far_rows_kernel(DevMesh m, Tables<R
         const int side = tb.cf[j * T + q] > R(0) ? 0 : 1;
         rows[(size_t(i) * N + n) * 2 + side] = C2{re, im};
     };
-    if ((m.near_mask[size_t(p) * m.nqb + (q >> 6)] >> (q & 63)) & 1ull) {
+    const bool near = (m.near_mask[size_t(p) * m.nqb + (q >> 6)] >> (q & 63)) & 1ull;
+    if (UPPER && (q < p || near)) return;
+    if (near) {
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -110,23 +116,27 @@ __global__ __launch_bounds__(FAR_BLOCK) void far_rows_kernel(DevMesh m, Tables<R
 }
 
 // near pairs (p, q) with p in the chunk: their values replace the zeros pass 1
-// wrote (one thread per ordered near pair, FP64 arithmetic)
+// wrote (one thread per ordered near pair, FP64 arithmetic, all nine entries).
+// upper: pairs with q < p are not written and the diagonal blocks (q = p) are
+// halved.
 template <typename R>
 __global__ __launch_bounds__(128) void near_rows_kernel(DevMesh m, double kr, double ki, Scale sc,
                                                         typename Cplx<R>::T* __restrict__ W, int c0, int c1, int e0,
-                                                        int e1) {
+                                                        int e1, int upper) {
     using C2 = typename Cplx<R>::T;
     const int e = e0 + int(blockIdx.x * blockDim.x + threadIdx.x);
     if (e >= e1) return;
     const int p = m.near_p[e], q = m.near_q[e];
     if (p < c0 || p >= c1) return;
+    if (upper && q < p) return;
+    const double f = upper && q == p ? 0.5 : 1.0;
     const int T = m.T;
     const size_t N = size_t(m.N);
     C2* rows = W + size_t(p - c0) * 3 * 2 * N;
     auto put = [&](int i, int j, double re, double im) {
         const size_t n = size_t(m.te[j * T + q]);
         const int side = m.cf[j * T + q] > 0.0 ? 0 : 1;
-        rows[(size_t(i) * N + n) * 2 + side] = C2{R(re), R(im)};
+        rows[(size_t(i) * N + n) * 2 + side] = C2{R(f * re), R(f * im)};
     };
     near_pair_emit<false>(m, e, kr, ki, sc, put, put);
 }
@@ -242,16 +252,16 @@ void launch_far_rows(const DevMesh& m, double kr, double ki, const Scale& sc, vo
         const int c1 = std::min(m.T, c0 + chunk), np = c1 - c0;
         const dim3 g1(unsigned(size_t(np) * nqblk));
         if (ck)
-            hipLaunchKernelGGL((far_rows_kernel<R, true>), g1, dim3(FAR_BLOCK), 0, s, m, tables<R>(m), kphase, R(ki),
-                               sc, W, c0, nqblk);
+            hipLaunchKernelGGL((far_rows_kernel<R, true, false>), g1, dim3(FAR_BLOCK), 0, s, m, tables<R>(m), kphase,
+                               R(ki), sc, W, c0, nqblk);
         else
-            hipLaunchKernelGGL((far_rows_kernel<R, false>), g1, dim3(FAR_BLOCK), 0, s, m, tables<R>(m), kphase, R(ki),
-                               sc, W, c0, nqblk);
+            hipLaunchKernelGGL((far_rows_kernel<R, false, false>), g1, dim3(FAR_BLOCK), 0, s, m, tables<R>(m), kphase,
+                               R(ki), sc, W, c0, nqblk);
         const int e0 = int(std::lower_bound(near_p.begin(), near_p.end(), c0) - near_p.begin());
         const int e1 = int(std::lower_bound(near_p.begin(), near_p.end(), c1) - near_p.begin());
         if (e1 > e0)
             hipLaunchKernelGGL((near_rows_kernel<R>), dim3((e1 - e0 + 127) / 128), dim3(128), 0, s, m, kr, ki, sc, W,
-                               c0, c1, e0, e1);
+                               c0, c1, e0, e1, 0);
         hipLaunchKernelGGL((gather_rows_kernel<R>), dim3(unsigned(3 * np)), dim3(256), 0, s, m, W, c0, c1,
                            static_cast<C2*>(Z));
     }
@@ -285,9 +295,12 @@ static Scale operator_scale(double kr, double ki, double eta) {
 // value of Z = eta (j k T_A + T_Phi / (j k)) (far pairs in the storage precision,
 // near pairs in FP64) into rows W[p - c0][i][n][side] of complex64 (dtype
 // EFIE_C64) or complex128 elements.  Used by the Calderon build, which contracts
-// these rows without forming the matrix.
+// these rows without forming the matrix.  upper: only the pairs with source
+// triangle q > p, plus the halved diagonal blocks q = p (rows of U + D/2 for the
+// split Z = U + U^T + D of the symmetric operator); the entries of triangles
+// q < p are not written, and the reader must skip them.
 void pair_rows_chunk(const DevMesh& m, double kr, double ki, double eta, int dtype, void* W, int c0, int c1,
-                     const std::vector<int32_t>& near_p, hipStream_t s) {
+                     const std::vector<int32_t>& near_p, bool upper, hipStream_t s) {
     const Scale sc = operator_scale(kr, ki, eta);
     const int nqblk = (m.T + FAR_BLOCK - 1) / FAR_BLOCK;
     const int np = c1 - c0;
@@ -301,15 +314,21 @@ void pair_rows_chunk(const DevMesh& m, double kr, double ki, double eta, int dty
         using C2 = typename Cplx<R>::T;
         const R kphase = std::is_same<R, float>::value ? R(kr / (2.0 * PI)) : R(kr);
         C2* w = static_cast<C2*>(W);
-        if (ck)
-            hipLaunchKernelGGL((far_rows_kernel<R, true>), g1, dim3(FAR_BLOCK), 0, s, m, tables<R>(m), kphase, R(ki),
-                               sc, w, c0, nqblk);
+        if (ck && upper)
+            hipLaunchKernelGGL((far_rows_kernel<R, true, true>), g1, dim3(FAR_BLOCK), 0, s, m, tables<R>(m), kphase,
+                               R(ki), sc, w, c0, nqblk);
+        else if (ck)
+            hipLaunchKernelGGL((far_rows_kernel<R, true, false>), g1, dim3(FAR_BLOCK), 0, s, m, tables<R>(m), kphase,
+                               R(ki), sc, w, c0, nqblk);
+        else if (upper)
+            hipLaunchKernelGGL((far_rows_kernel<R, false, true>), g1, dim3(FAR_BLOCK), 0, s, m, tables<R>(m), kphase,
+                               R(ki), sc, w, c0, nqblk);
         else
-            hipLaunchKernelGGL((far_rows_kernel<R, false>), g1, dim3(FAR_BLOCK), 0, s, m, tables<R>(m), kphase, R(ki),
-                               sc, w, c0, nqblk);
+            hipLaunchKernelGGL((far_rows_kernel<R, false, false>), g1, dim3(FAR_BLOCK), 0, s, m, tables<R>(m), kphase,
+                               R(ki), sc, w, c0, nqblk);
         if (e1 > e0)
             hipLaunchKernelGGL((near_rows_kernel<R>), dim3((e1 - e0 + 127) / 128), dim3(128), 0, s, m, kr, ki, sc, w,
-                               c0, c1, e0, e1);
+                               c0, c1, e0, e1, int(upper));
     };
     if (dtype == EFIE_C64) run(float{});
     else run(double{});

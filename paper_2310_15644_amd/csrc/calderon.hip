@@ -29,7 +29,7 @@
 namespace efie {
 
 void pair_rows_chunk(const DevMesh& m, double kr, double ki, double eta, int dtype, void* W, int c0, int c1,
-                     const std::vector<int32_t>& near_p, hipStream_t s);
+                     const std::vector<int32_t>& near_p, bool upper, hipStream_t s);
 bool verbose();
 double now_s();
 
@@ -54,21 +54,29 @@ struct DevCald {
 // sides of each into LDS, and then every thread contracts the column of R of one
 // BC function from LDS through the local positions r_loc.  W is read about 1.2
 // times in all, instead of once per BC function that uses an entry.
-// two sides of barycentric RWG f in row wr, summed (complex64: one 16-byte load)
-__device__ inline float2 bc_pair_sum(const float2* wr, int f) {
-    const float4 v = *reinterpret_cast<const float4*>(wr + 2 * size_t(f));
-    return make_float2(v.x + v.z, v.y + v.w);
+// two sides of barycentric RWG f in row wr, summed, each only where its flag is
+// set (a select, so that unwritten entries never enter; complex64: one 16-byte load)
+// (lanes with neither side wanted issue no load)
+__device__ inline float2 bc_pair_sum(const float2* wr, int f, bool s0, bool s1) {
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (s0 || s1) v = *reinterpret_cast<const float4*>(wr + 2 * size_t(f));
+    return make_float2((s0 ? v.x : 0.f) + (s1 ? v.z : 0.f), (s0 ? v.y : 0.f) + (s1 ? v.w : 0.f));
 }
-__device__ inline double2 bc_pair_sum(const double2* wr, int f) {
-    const double2 a = wr[2 * size_t(f)], b = wr[2 * size_t(f) + 1];
-    return make_double2(a.x + b.x, a.y + b.y);
+__device__ inline double2 bc_pair_sum(const double2* wr, int f, bool s0, bool s1) {
+    double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+    if (s0) a = wr[2 * size_t(f)];
+    if (s1) b = wr[2 * size_t(f) + 1];
+    return make_double2((s0 ? a.x : 0.0) + (s1 ? b.x : 0.0), (s0 ? a.y : 0.0) + (s1 ? b.y : 0.0));
 }
 
 constexpr int BC_NQ = BC_UMAX / 256;   // list entries per thread
 constexpr int BC_KG = 8;               // column entries per group
+// The rows hold the pairs with source triangle q >= p only (p the row's test
+// triangle c0 + row / 3): side s of RWG f (triangle et[s Nb + f]) is read only
+// where that triangle is not below p.
 template <typename C2, int RRL>
 __global__ __launch_bounds__(256) void bc_src_kernel(DevCald c, const C2* __restrict__ W, double2* __restrict__ Yw,
-                                                     int nrows) {
+                                                     int nrows, const int32_t* __restrict__ et, int c0) {
     static_assert(BC_UMAX % 256 == 0, "list bound must be a multiple of the block");
     __shared__ C2 lw[RRL][BC_UMAX];
     const int b = blockIdx.x;
@@ -76,20 +84,30 @@ __global__ __launch_bounds__(256) void bc_src_kernel(DevCald c, const C2* __rest
     const int u0 = c.u_ptr[b], nu = c.u_ptr[b + 1] - u0;   // 1 <= nu <= BC_UMAX by construction
     // the run's list, once for all rows; entries past the end repeat the last one
     // (loaded, not stored), so every load below is in bounds and unconditional
-    int fl[BC_NQ];
+    int fl[BC_NQ], tp[BC_NQ], tm[BC_NQ];
 #pragma unroll
     for (int q = 0; q < BC_NQ; ++q) fl[q] = c.u_idx[u0 + min(int(threadIdx.x) + 256 * q, nu - 1)];
+#pragma unroll
+    for (int q = 0; q < BC_NQ; ++q) {
+        tp[q] = et[fl[q]];
+        tm[q] = et[size_t(c.Nb) + fl[q]];
+    }
     // rows past the end read a valid row (result dropped); the loads of row u + 1
     // are in flight while row u is written to LDS
     auto wrow = [&](int u) { return W + size_t(min(r0 + u, nrows - 1)) * 2 * size_t(c.Nb); };
+    auto ptri = [&](int u) { return c0 + min(r0 + u, nrows - 1) / 3; };
     C2 x[BC_NQ], y[BC_NQ];
+    {
+        const int p = ptri(0);
 #pragma unroll
-    for (int q = 0; q < BC_NQ; ++q) x[q] = bc_pair_sum(wrow(0), fl[q]);
+        for (int q = 0; q < BC_NQ; ++q) x[q] = bc_pair_sum(wrow(0), fl[q], tp[q] >= p, tm[q] >= p);
+    }
 #pragma unroll
     for (int u = 0; u < RRL; ++u) {
         if (u + 1 < RRL) {
+            const int p = ptri(u + 1);
 #pragma unroll
-            for (int q = 0; q < BC_NQ; ++q) y[q] = bc_pair_sum(wrow(u + 1), fl[q]);
+            for (int q = 0; q < BC_NQ; ++q) y[q] = bc_pair_sum(wrow(u + 1), fl[q], tp[q] >= p, tm[q] >= p);
         }
 #pragma unroll
         for (int q = 0; q < BC_NQ; ++q)
@@ -146,6 +164,41 @@ __global__ __launch_bounds__(256) void bc_test_kernel(const int32_t* __restrict_
         acc.y += coef[k] * y.y;
     }
     Tbc[o] = acc;
+}
+
+// T <- T + T^T in place (N x N complex128): one block per pair of mirror 32 x 32
+// tiles (bi <= bj), both read into LDS before either is written
+__global__ __launch_bounds__(256) void sym_add_kernel(double2* __restrict__ T, int N, int nt) {
+    __shared__ double2 a[32][33], b[32][33];
+    // blockIdx.x -> (bi, bj), bi <= bj, row by row of the upper triangle of tiles
+    int k = int(blockIdx.x), bi = 0;
+    while (k >= nt - bi) {
+        k -= nt - bi;
+        ++bi;
+    }
+    const int bj = bi + k;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+    for (int r = ty; r < 32; r += 8) {
+        const int i = bi * 32 + r, j = bj * 32 + tx;
+        const int i2 = bj * 32 + r, j2 = bi * 32 + tx;
+        if (i < N && j < N) a[r][tx] = T[size_t(i) * N + j];
+        if (i2 < N && j2 < N) b[r][tx] = T[size_t(i2) * N + j2];
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int i = bi * 32 + r, j = bj * 32 + tx;
+        if (i < N && j < N) {   // (i, j) += (j, i): element (r, tx) of a plus element (tx, r) of b
+            const double2 u = a[r][tx], v = b[tx][r];
+            T[size_t(i) * N + j] = make_double2(u.x + v.x, u.y + v.y);
+        }
+        if (bi != bj) {
+            const int i2 = bj * 32 + r, j2 = bi * 32 + tx;
+            if (i2 < N && j2 < N) {
+                const double2 u = b[r][tx], v = a[tx][r];
+                T[size_t(i2) * N + j2] = make_double2(u.x + v.x, u.y + v.y);
+            }
+        }
+    }
 }
 
 // ---------------------------------------------- CGNR in column layout X[j][s]
@@ -655,16 +708,16 @@ int efie_calderon_assemble_ex(efie_calderon c, double kt_re, double kt_im, doubl
         const unsigned nruns = unsigned(c->run_t0.size() - 1);
         for (int ch = 0; ch < pl.nchunks; ++ch) {
             const int c0 = ch * pl.chunk, c1 = std::min(Tb, c0 + pl.chunk), np = c1 - c0;
-            pair_rows_chunk(c->bary.dm, kt_re, kt_im, eta, bary_dtype, w.W, c0, c1, c->bary.near_p, stream);
+            pair_rows_chunk(c->bary.dm, kt_re, kt_im, eta, bary_dtype, w.W, c0, c1, c->bary.near_p, true, stream);
             const int nr = 3 * np;
             if (bary_dtype == EFIE_C64)
                 hipLaunchKernelGGL((bc_src_kernel<float2, BC_RRL32>),
                                    dim3(nruns, unsigned((nr + BC_RRL32 - 1) / BC_RRL32)), dim3(256), 0, stream, d,
-                                   static_cast<const float2*>(w.W), w.Yw, nr);
+                                   static_cast<const float2*>(w.W), w.Yw, nr, c->bary.dm.et, c0);
             else
                 hipLaunchKernelGGL((bc_src_kernel<double2, BC_RRL64>),
                                    dim3(nruns, unsigned((nr + BC_RRL64 - 1) / BC_RRL64)), dim3(256), 0, stream, d,
-                                   static_cast<const double2*>(w.W), w.Yw, nr);
+                                   static_cast<const double2*>(w.W), w.Yw, nr, c->bary.dm.et, c0);
             if (L.nm[size_t(ch)] > 0)
                 hipLaunchKernelGGL(bc_test_kernel, dim3(nx, unsigned(L.nm[size_t(ch)])), dim3(256), 0, stream,
                                    w.ml + L.m0[size_t(ch)], w.mptr + L.mp0[size_t(ch)], w.rows, w.coef, w.Yw, w.Tbc, N);
@@ -673,6 +726,14 @@ int efie_calderon_assemble_ex(efie_calderon c, double kt_re, double kt_im, doubl
                 std::fprintf(stderr, "[efie] calderon T_BC chunk %d/%d t=%.3f\n", ch + 1, pl.nchunks, now_s());
                 std::fflush(stderr);
             }
+        }
+        // the chunks held the rows of U + D/2 (pairs with source triangle above the
+        // test triangle, halved diagonal blocks): T_BC = A + A^T
+        {
+            const int nt = (N + 31) / 32;
+            const size_t npairs = size_t(nt) * size_t(nt + 1) / 2;
+            EFIE_REQUIRE(npairs < (size_t(1) << 31), EFIE_ERR_ARG, "calderon_assemble: N too large");
+            hipLaunchKernelGGL(sym_add_kernel, dim3(unsigned(npairs)), dim3(256), 0, stream, w.Tbc, N, nt);
         }
         if (Tbc_out)
             EFIE_HIP_CHECK(hipMemcpyAsync(Tbc_out, w.Tbc, size_t(N) * N * 16, hipMemcpyDeviceToDevice, stream));
