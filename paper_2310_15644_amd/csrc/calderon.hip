@@ -145,7 +145,10 @@ __global__ __launch_bounds__(256) void bc_src_kernel(DevCald c, const C2* __rest
     for (int u = 0; u < RRL; ++u)
         if (r0 + u < nrows) Yw[size_t(r0 + u) * c.N + n] = make_double2(ar[u], ai[u]);
 }
-constexpr int BC_RRL32 = 4, BC_RRL64 = 2;   // rows per block: 72 KB of LDS either way
+// rows per block: 144 KB of LDS either way (one block per CU); more rows amortize
+// the run's list and index loads (level 5, complex64: 2 / 4 / 6 / 8 rows per block
+// built P in 2.16 / 1.65 / 1.60 / 1.54 s)
+constexpr int BC_RRL32 = 8, BC_RRL64 = 4;
 
 // Tbc[m][n] += sum_k coef[k] Yw[rows[k]][n] over the list of BC row m = ml[blockIdx.y]
 __global__ __launch_bounds__(256) void bc_test_kernel(const int32_t* __restrict__ ml, const int32_t* __restrict__ mptr,
