@@ -105,30 +105,43 @@ TRAFFIC_FILES = {False: os.path.join(ROOT, "profiles", "cgemm_planar_fp32acc_l5_
 GEMM_SOURCE = os.path.join(ROOT, "paper_2310_15644_amd", "csrc", "gemm_mfma.hip")
 
 
+def gemm_code_sha256(path=None):
+    """SHA-256 of the GEMM source with its // comments and all whitespace removed:
+    the counters stay attached to the kernel code, not to the wording of its comments."""
+    import hashlib
+    import re
+
+    text = open(path or GEMM_SOURCE).read()
+    code = re.sub(r"//[^\n]*", "", text)
+    code = re.sub(r"\s+", "", code)
+    return hashlib.sha256(code.encode()).hexdigest()
+
+
 def measured_traffic(tiles, acc64, n, nrhs, solver):
     """HBM bytes per launch of the in-solve matrix-core GEMM, from the committed
     rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE per dispatch, each divided
-    by the factor the same counter reads for a plain 1 GiB copy).  None when the
-    summary is for another tile shape or workload, or the GEMM source has changed
-    since the counters were taken."""
-    import hashlib
-
+    by the factor the same counter reads for a plain 1 GiB copy).  The summary may
+    hold one entry per tile; None when no entry is for the selected tile and this
+    workload, or the GEMM code has changed since the counters were taken."""
     path = TRAFFIC_FILES[bool(acc64)]
     if tiles is None or not os.path.exists(path):
         return None, None
-    kv = {}
-    for line in open(path):
-        if line.startswith("- ") and ": " in line:
-            key, val = line[2:].split(": ", 1)
-            kv[key.strip()] = val.strip().strip("`")
-    sha = hashlib.sha256(open(GEMM_SOURCE, "rb").read()).hexdigest()
     from paper_2310_15644_amd import gemm_kernel_name
 
+    entries = []
+    for line in open(path):
+        if line.startswith("- kernel:"):
+            entries.append({})
+        if entries and line.startswith("- ") and ": " in line:
+            key, val = line[2:].split(": ", 1)
+            entries[-1][key.strip()] = val.strip().strip("`")
+    sha = gemm_code_sha256()
     want = gemm_kernel_name(tiles, acc64)
-    if (kv.get("gemm_source_sha256") != sha or kv.get("kernel") != want
-            or kv.get("workload") != f"n={n} nrhs={nrhs} solver={solver}"):
-        return None, None
-    return float(kv["hbm_bytes_per_launch"]), os.path.relpath(path, ROOT)
+    for kv in entries:
+        if (kv.get("gemm_code_sha256") == sha and kv.get("kernel") == want
+                and kv.get("workload") == f"n={n} nrhs={nrhs} solver={solver}"):
+            return float(kv["hbm_bytes_per_launch"]), os.path.relpath(path, ROOT)
+    return None, None
 
 
 def copy_calibration(torch):

@@ -8,7 +8,7 @@
 // fetched with one 8-byte LDS read, and each 16 x 16 complex output block takes
 // four real instructions per 4 complex K:
 //   Yr += Ar Br + (-Ai) Bi,   Yi += Ar Bi + Ai Br
-// (8 M n K real flops in all).  X and Y keep the ABI's interleaved complex
+// (8 M n K real flops in all); the FP64-flush path below takes three (3M).  X and Y keep the ABI's interleaved complex
 // layouts; no operand is converted or copied.
 //
 // Tiling: a block of 256 threads (4 wavefronts, 2 x 2) owns BM right-hand sides
@@ -23,8 +23,10 @@
 // without per-element bounds tests when the tile lies wholly inside the
 // matrices) are in flight while chunk c is multiplied, then written to the other
 // buffer; one barrier per chunk.  LDS rows are padded to KC + 2 complex values,
-// which keeps them 16-byte aligned and the 8-byte reads of a wavefront free of
-// bank conflicts.
+// which keeps them 16-byte aligned for the 16-byte stores.  (The 8-byte reads
+// still meet some bank conflicts; an odd pad removes them for KC = 16 and halves
+// them for KC = 32, but changes the time by under one percent: the conflicts
+// overlap with the matrix instructions.)
 // Block order: workgroups are dealt to the 8 XCDs round-robin by id, so the ids
 // are remapped to give each XCD a contiguous run of tiles, walking the
 // right-hand-side tiles of one Z row strip first: the blocks that read the
@@ -44,7 +46,7 @@ template <int BM, int BNC, int KC, bool ACC64>
 __global__ __launch_bounds__(256) void cgemm_planar_kernel(const float2* __restrict__ X, const float2* __restrict__ Z,
                                                            void* __restrict__ Yv, int M, int n,
                                                            const int* __restrict__ yrow) {
-    constexpr int AS = KC + 2;             // float2 per LDS row (16-byte rows, conflict-free 8-byte reads)
+    constexpr int AS = KC + 2;             // float2 per LDS row (16-byte aligned rows)
     constexpr int WM = BM / 2, WN = BNC / 2;
     constexpr int TM = WM / 16, TN = WN / 16;
     constexpr int KV = KC / 2;             // 16-byte groups per row of a chunk
