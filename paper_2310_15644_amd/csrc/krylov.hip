@@ -428,11 +428,12 @@ __global__ __launch_bounds__(1024) void compact_kernel(const Col* cols, int S, i
     if (threadIdx.x == 0) *count = base;
 }
 
-// out = b - y, and per-column ||out||^2 into nrm[s]
+// out = b - y, and per-column ||out||^2 into nrm[s], for the columns s = idx[block]
+// (idx == nullptr: s = block)
 __global__ __launch_bounds__(KB) void residual_kernel(const double2* b, const double2* y, double2* out, double* nrm,
-                                                      double* bnrm, int n) {
+                                                      double* bnrm, int n, const int* __restrict__ idx) {
     __shared__ double sh[KB / 64 * 4];
-    const int s = blockIdx.x;
+    const int s = idx ? idx[blockIdx.x] : int(blockIdx.x);
     const size_t o = size_t(s) * n;
     double a[4] = {0, 0, 0, 0};
     for (int k = threadIdx.x; k < n; k += KB) {
@@ -454,14 +455,6 @@ __global__ void axpy_inplace_kernel(double2* x, const double2* d, size_t n) {
         double2 a = x[i], b = d[i];
         x[i] = make_double2(a.x + b.x, a.y + b.y);
     }
-}
-
-// zero column s of r when its true residual already meets tol (||r||^2 <= tol^2 ||b||^2)
-__global__ __launch_bounds__(KB) void zero_done_kernel(double2* r, const double* nrm, const double* bnrm, double tol,
-                                                       int n) {
-    const int s = blockIdx.x;
-    if (!(nrm[s] <= tol * tol * bnrm[s])) return;
-    for (int k = threadIdx.x; k < n; k += KB) r[size_t(s) * n + k] = make_double2(0.0, 0.0);
 }
 
 // flag every active column for a replacement with restart
@@ -504,6 +497,7 @@ struct Ws {
     double *nrm, *bnrm;
     int* counters;                          // [0] active, [1] flagged for a true residual, [2] count
     int *idx_a, *idx_u, *idx_all;           // column lists: active, flagged, all
+    int* idx_ref;                           // columns still refined (preconditioned solve)
 };
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
@@ -533,6 +527,7 @@ size_t layout(int64_t n, int64_t S, int dtype, Ws* ws, char* base) {
     w.idx_a = (int*)take(sizeof(int) * size_t(S));
     w.idx_u = (int*)take(sizeof(int) * size_t(S));
     w.idx_all = (int*)take(sizeof(int) * size_t(S));
+    w.idx_ref = (int*)take(sizeof(int) * size_t(S));
     if (ws) *ws = w;
     return off;
 }
@@ -588,12 +583,14 @@ int compact(const Ws& w, int S, int which, int* idx, hipStream_t st) {
     return h;
 }
 
-// FP64-accumulated residual out = b - Z x (Z of either dtype); norms into w.nrm / w.bnrm.
-void true_residual(const void* Z, int zdt, int n, const double2* b, const double2* x, double2* out, int S,
-                   const Ws& w, hipStream_t st) {
+// FP64-accumulated residual out = b - Z x (Z of either dtype) for the m columns
+// listed in idx; their norms into w.nrm / w.bnrm (other columns untouched).
+void true_residual(const void* Z, int zdt, int n, const double2* b, const double2* x, double2* out,
+                   const int* idx, int m, const Ws& w, hipStream_t st) {
+    if (m <= 0) return;
     double2* y = w.q;   // scratch
-    product(Z, zdt, n, x, y, w.idx_all, S, true, w, st);
-    hipLaunchKernelGGL(residual_kernel, dim3(S), dim3(KB), 0, st, b, y, out, w.nrm, w.bnrm, n);
+    product(Z, zdt, n, x, y, idx, m, true, w, st);
+    hipLaunchKernelGGL(residual_kernel, dim3(m), dim3(KB), 0, st, b, y, out, w.nrm, w.bnrm, n, idx);
 }
 
 // One Krylov solve of Z x = b for S columns.  Returns per-column Col states in host memory.
@@ -704,7 +701,7 @@ extern "C" int efie_solve(const void* Z, int dtype, int64_t n, const void* V, vo
             std::vector<double> h_nrm(S), h_bn(S);
             for (int outer = 0; outer < opts->max_refine; ++outer) {
                 if (outer > 0) {
-                    true_residual(Z, dtype, nn, b, x, w.res, S, w, stream);
+                    true_residual(Z, dtype, nn, b, x, w.res, w.idx_all, S, w, stream);
                     EFIE_HIP_CHECK(hipMemcpyAsync(h_nrm.data(), w.nrm, sizeof(double) * S, hipMemcpyDeviceToHost, stream));
                     EFIE_HIP_CHECK(hipMemcpyAsync(h_bn.data(), w.bnrm, sizeof(double) * S, hipMemcpyDeviceToHost, stream));
                     EFIE_HIP_CHECK(hipStreamSynchronize(stream));
@@ -735,7 +732,7 @@ extern "C" int efie_solve(const void* Z, int dtype, int64_t n, const void* V, vo
             }
         }
         // true residual at exit (FP64 accumulation)
-        true_residual(Z, dtype, nn, b, x, nullptr, S, w, stream);
+        true_residual(Z, dtype, nn, b, x, nullptr, w.idx_all, S, w, stream);
         std::vector<double> h_nrm(S), h_bn(S);
         EFIE_HIP_CHECK(hipMemcpyAsync(h_nrm.data(), w.nrm, sizeof(double) * S, hipMemcpyDeviceToHost, stream));
         EFIE_HIP_CHECK(hipMemcpyAsync(h_bn.data(), w.bnrm, sizeof(double) * S, hipMemcpyDeviceToHost, stream));
@@ -816,15 +813,25 @@ extern "C" int efie_solve_precond_ex(const void* Z, int zdt, const void* P, int 
         // inner_tol per pass
         const double floor_tau = mixed ? std::max(opts->inner_tol, 1e-13) : 1e-13;
         double tau = std::max(0.25 * opts->tol, floor_tau);
+        // the right-hand side P r of a pass only has to be as accurate as the pass
+        // (its tolerance >= inner_tol): the solver's own product forms it; the true
+        // residual that decides convergence stays FP64-accumulated.  After the first
+        // pass only the columns still above tol (listed in idx_ref) are refined: the
+        // others keep x and their residual norms, and get a zero right-hand side.
+        std::vector<int> h_ref(S);
+        for (int s = 0; s < S; ++s) h_ref[s] = s;
+        int m_ref = S;
         for (int pass = 0; pass < passes; ++pass) {
             const double2* rhs = pass == 0 ? b : rt;
-            product(P, pdt, nn, rhs, pb, w.idx_all, S, true, w, stream);
+            const int* ref = pass == 0 ? w.idx_all : w.idx_ref;
+            if (pass > 0) fill_zero_bytes(pb, tot * sizeof(double2), stream);
+            product(P, pdt, nn, rhs, pb, ref, m_ref, false, w, stream);
             double2* dst = pass == 0 ? x : dl;
             krylov(op, nn, pb, dst, S, EFIE_CGS, tau, opts->maxit, false, w, cols, stream);
             if (pass > 0)
                 hipLaunchKernelGGL(axpy_inplace_kernel, dim3(int(std::min<size_t>((tot + 255) / 256, 16384))),
                                    dim3(256), 0, stream, x, dl, tot);
-            true_residual(Z, zdt, nn, b, x, rt, S, w, stream);
+            true_residual(Z, zdt, nn, b, x, rt, ref, m_ref, w, stream);
             EFIE_HIP_CHECK(hipMemcpyAsync(h_nrm.data(), w.nrm, sizeof(double) * S, hipMemcpyDeviceToHost, stream));
             EFIE_HIP_CHECK(hipMemcpyAsync(h_bn.data(), w.bnrm, sizeof(double) * S, hipMemcpyDeviceToHost, stream));
             EFIE_HIP_CHECK(hipStreamSynchronize(stream));
@@ -849,8 +856,10 @@ extern "C" int efie_solve_precond_ex(const void* Z, int zdt, const void* P, int 
                     std::fflush(stderr);
             if (done) break;
             tau = std::max(need, floor_tau);
-            // columns already converged get a zero right-hand side (no further work)
-            hipLaunchKernelGGL(zero_done_kernel, dim3(S), dim3(KB), 0, stream, rt, w.nrm, w.bnrm, opts->tol, nn);
+            m_ref = 0;
+            for (int s = 0; s < S; ++s)
+                if (rel[s] > opts->tol) h_ref[m_ref++] = s;
+            EFIE_HIP_CHECK(hipMemcpyAsync(w.idx_ref, h_ref.data(), sizeof(int) * m_ref, hipMemcpyHostToDevice, stream));
         }
         int ret = EFIE_OK;
         for (int s = 0; s < S; ++s) {
