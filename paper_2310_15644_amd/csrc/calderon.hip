@@ -37,7 +37,7 @@ struct DevCald {
     int N, Nb;
     const int32_t *r_ptr, *r_idx;   // CSC of R by BC function
     const double* r_val;
-    const int32_t *g_ptr, *g_idx, *gt_ptr, *gt_idx;
+    const int32_t *g_ptr, *g_idx, *gt_ptr, *gt_idx;   // G and G^T, rows stored in n_order order
     const double *g_val, *gt_val;
     const int32_t* n_order;         // primal RWGs in a spatially coherent order
     const int32_t* run_t0;          // runs of BC functions: first position in n_order
@@ -204,10 +204,17 @@ __global__ __launch_bounds__(256) void sym_add_kernel(double2* __restrict__ T, i
     }
 }
 
-// ---------------------------------------------- CGNR in column layout X[j][s]
+// ---------------------------------------------- CGNR on column tiles
 // The vectors are stored as V (double2, or float2 when the requested tolerance
 // is loose: CGNR_C64_TOL); every sum, norm and update is evaluated in FP64.
+// A batch of S columns is split into tiles of CG_W = 64 columns, each tile stored
+// row by row: element (j, s) sits at ((s / CG_W) N + j) CG_W + s % CG_W, so a
+// wave reads a row of a tile as 512 contiguous bytes (complex64).  A block takes
+// CG_R consecutive rows of one tile (a slice), a wave every fourth of them.  The
+// padding columns of the last tile stay zero.
 constexpr double CGNR_C64_TOL = 1e-4;
+constexpr int CG_W = 64;   // columns per tile: one per lane
+constexpr int CG_R = 64;   // rows per block
 __device__ inline double2 ld2(const double2& v) { return v; }
 __device__ inline double2 ld2(const float2& v) { return make_double2(double(v.x), double(v.y)); }
 template <typename V>
@@ -217,66 +224,102 @@ __device__ inline double2 st2<double2>(double x, double y) { return make_double2
 template <>
 __device__ inline float2 st2<float2>(double x, double y) { return make_float2(float(x), float(y)); }
 
-// Out[j][s] = sum_k val[k] X[idx[k]][s], k over row j of a real CSR matrix;
-// grid (N rows, column tiles of 256)
+inline int cg_pad(int S) { return (S + CG_W - 1) / CG_W * CG_W; }
+inline int cg_slices(int N) { return (N + CG_R - 1) / CG_R; }
+// blocks of a batch of S columns: every slice of every tile, the tile count
+// rounded up to a multiple of 8
+inline unsigned cg_blocks(int S, int N) { return unsigned((cg_pad(S) / CG_W + 7) / 8 * 8) * unsigned(cg_slices(N)); }
+
+// Block b runs on XCD b % 8 (round-robin dispatch).  That XCD's blocks, in
+// dispatch order, take tile b % 8, then tile b % 8 + 8, ..., every slice of one
+// tile before the next: the rows a sparse product gathers then come from the
+// XCD's own tile, and its L2 is not shared among all the columns.
+struct CgBlock {
+    int tile, c, wv, s, j0, j1, slice;
+};
+__device__ inline CgBlock cg_block(int N) {
+    const int ns = (N + CG_R - 1) / CG_R;
+    const int b = blockIdx.x, idx = b >> 3;
+    CgBlock k;
+    k.tile = (b & 7) + 8 * (idx / ns);
+    k.slice = idx % ns;
+    k.c = int(threadIdx.x) & 63;
+    k.wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+    k.s = k.tile * CG_W + k.c;
+    k.j0 = k.slice * CG_R + k.wv;   // the wave's rows: j0, j0 + 4, ... < j1
+    k.j1 = min(N, (k.slice + 1) * CG_R);
+    return k;
+}
+__device__ inline size_t cg_at(int tile, int j, int c, int N) { return (size_t(tile) * N + j) * CG_W + c; }
+
+// part[slice][s] = the block's sum over its waves of sq (a column's squared norm
+// over the slice), for s < S
+__device__ inline void cg_part(double sq, const CgBlock& k, int S, double* part) {
+    __shared__ double sh[4][CG_W];
+    sh[k.wv][k.c] = sq;
+    __syncthreads();
+    if (k.wv == 0 && k.s < S) part[size_t(k.slice) * S + k.s] = sh[0][k.c] + sh[1][k.c] + sh[2][k.c] + sh[3][k.c];
+}
+
+// Out[j] = sum_q val[q] X[idx[q]] for the rows of a real CSR matrix stored in the
+// spatially coherent order (stored row t is row j = order[t]), over the stored
+// rows of the block's slice, for the columns of the block's tile;
+// part[slice][s] = sum over those rows of |Out[j][s]|^2
 template <typename V>
 __global__ __launch_bounds__(256) void cspmm_kernel(const int32_t* __restrict__ ptr, const int32_t* __restrict__ idx,
                                                     const double* __restrict__ val, const V* __restrict__ X,
-                                                    int ldx, V* __restrict__ Out, int S,
-                                                    const int32_t* __restrict__ order) {
-    const int j = order[blockIdx.x];   // rows in a spatially coherent order
-    const int s = blockIdx.y * 256 + threadIdx.x;
-    if (s >= S) return;
-    double ar = 0, ai = 0;
-    // the row in groups of 8: the (block-uniform) indices first, then 8 gathers in flight
-    for (int kb = ptr[j], ke = ptr[j + 1]; kb < ke; kb += 8) {
-        int ix[8];
-        double vv[8];
+                                                    V* __restrict__ Out, int S, const int32_t* __restrict__ order,
+                                                    int N, double* __restrict__ part) {
+    const CgBlock k = cg_block(N);
+    if (k.tile * CG_W >= S) return;   // a whole block of the rounding tiles
+    const V* Xt = X + cg_at(k.tile, 0, k.c, N);
+    double sq = 0.0;
+    for (int t = k.j0; t < k.j1; t += 4) {
+        double ar = 0, ai = 0;
+        // the (wave-uniform) row in groups of 8: 8 gathers in flight
+        for (int kb = ptr[t], ke = ptr[t + 1]; kb < ke; kb += 8) {
+            int ix[8];
+            double vv[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int k = min(kb + q, ke - 1);
-            ix[q] = idx[k];
-            vv[q] = kb + q < ke ? val[k] : 0.0;
+            for (int q = 0; q < 8; ++q) {
+                const int e = min(kb + q, ke - 1);
+                ix[q] = idx[e];
+                vv[q] = kb + q < ke ? val[e] : 0.0;
+            }
+            double2 x[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) x[q] = ld2(Xt[size_t(ix[q]) * CG_W]);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                ar += vv[q] * x[q].x;
+                ai += vv[q] * x[q].y;
+            }
         }
-        double2 x[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) x[q] = ld2(X[size_t(ix[q]) * ldx + s]);
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            ar += vv[q] * x[q].x;
-            ai += vv[q] * x[q].y;
-        }
+        const V o = st2<V>(ar, ai);
+        Out[cg_at(k.tile, order[t], k.c, N)] = o;
+        const double2 od = ld2(o);   // the norm of the stored value
+        sq += od.x * od.x + od.y * od.y;
     }
-    Out[size_t(j) * S + s] = st2<V>(ar, ai);
+    cg_part(sq, k, S, part);
 }
 
-constexpr int CJS = 32;   // row slices of the column reductions
-// part[js][s] = sum over rows j of slice js of |X[j][s]|^2; block = 64 columns x 4
-// row stripes, grid (column tiles of 64, CJS slices)
-template <typename V>
-__global__ __launch_bounds__(256) void colsq_part_kernel(const V* __restrict__ X, int ld, int N, int S,
-                                                         double* __restrict__ part) {
-    __shared__ double sh[4][64];
-    const int cl = threadIdx.x & 63, st = threadIdx.x >> 6;
-    const int s = blockIdx.x * 64 + cl;
-    const int per = (N + CJS - 1) / CJS;
-    const int j0 = blockIdx.y * per, j1 = min(N, j0 + per);
+// out[s] = sum over the ns slices of part[slice][s]; block = 16 columns x 16
+// slice stripes, grid ceil(S / 16)
+__global__ __launch_bounds__(256) void colsq_final_kernel(const double* __restrict__ part, int S, int ns,
+                                                          double* __restrict__ out) {
+    __shared__ double sh[16][17];
+    const int c = threadIdx.x & 15, st = threadIdx.x >> 4;
+    const int s = blockIdx.x * 16 + c;
     double a = 0.0;
     if (s < S)
-        for (int j = j0 + st; j < j1; j += 4) {
-            const double2 v = ld2(X[size_t(j) * ld + s]);
-            a += v.x * v.x + v.y * v.y;
-        }
-    sh[st][cl] = a;
+        for (int js = st; js < ns; js += 16) a += part[size_t(js) * S + s];
+    sh[st][c] = a;
     __syncthreads();
-    if (st == 0 && s < S) part[size_t(blockIdx.y) * S + s] = sh[0][cl] + sh[1][cl] + sh[2][cl] + sh[3][cl];
-}
-__global__ void colsq_final_kernel(const double* __restrict__ part, int S, double* __restrict__ out) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= S) return;
-    double a = 0.0;
-    for (int js = 0; js < CJS; ++js) a += part[size_t(js) * S + s];
-    out[s] = a;
+    if (st == 0 && s < S) {
+        double t = 0.0;
+        for (int q = 0; q < 16; ++q) t += sh[q][c];
+        out[s] = t;
+    }
 }
 
 struct CgnrCol {
@@ -284,17 +327,24 @@ struct CgnrCol {
     int active, iters, pad[2];
 };
 
-// w = 0, r = b (b[j][s] with leading dimension ldb)
+// w = 0, r = b (b[j][s] with leading dimension ldb; zero in the padding columns);
+// part = slice sums of |r|^2
 template <typename V>
-__global__ void cgnr_init_kernel(const double2* __restrict__ b, int ldb, V* __restrict__ w, V* __restrict__ r, int N,
-                                 int S) {
-    const size_t tot = size_t(N) * S;
-    for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < tot; e += size_t(gridDim.x) * blockDim.x) {
-        const size_t j = e / S, s = e - j * S;
-        const double2 v = b[j * ldb + s];
+__global__ __launch_bounds__(256) void cgnr_init_kernel(const double2* __restrict__ b, int ldb, V* __restrict__ w,
+                                                        V* __restrict__ r, int N, int S, double* __restrict__ part) {
+    const CgBlock k = cg_block(N);
+    if (k.tile * CG_W >= S) return;
+    double sq = 0.0;
+    for (int j = k.j0; j < k.j1; j += 4) {
+        const double2 v = k.s < S ? b[size_t(j) * ldb + k.s] : make_double2(0.0, 0.0);
+        const size_t e = cg_at(k.tile, j, k.c, N);
         w[e] = st2<V>(0.0, 0.0);
-        r[e] = st2<V>(v.x, v.y);
+        const V rv = st2<V>(v.x, v.y);
+        r[e] = rv;
+        const double2 rd = ld2(rv);
+        sq += rd.x * rd.x + rd.y * rd.y;
     }
+    cg_part(sq, k, S, part);
 }
 __global__ void cgnr_setup_kernel(CgnrCol* cols, const double* bn2, const double* zz, double tol, int S) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -307,21 +357,31 @@ __global__ void cgnr_setup_kernel(CgnrCol* cols, const double* bn2, const double
     c.active = bn2[s] > 0.0 && zz[s] > 0.0;
     cols[s] = c;
 }
-// after t = G^T p, tt = ||t||^2: alpha = gamma / tt, w += alpha p, r -= alpha t
+// after t = G^T p, tt = ||t||^2: alpha = gamma / tt, w += alpha p, r -= alpha t for
+// the active columns; part = slice sums of |r|^2 (every column)
 template <typename V>
-__global__ void cgnr_upd1_kernel(V* __restrict__ w, V* __restrict__ r, const V* __restrict__ p,
-                                 const V* __restrict__ t, const CgnrCol* __restrict__ cols,
-                                 const double* __restrict__ tt, int N, int S) {
-    const size_t tot = size_t(N) * S;
-    for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < tot; e += size_t(gridDim.x) * blockDim.x) {
-        const int s = int(e % S);
-        if (!cols[s].active || !(tt[s] > 0.0)) continue;
-        const double al = cols[s].gamma / tt[s];
-        const double2 pp = ld2(p[e]), tv = ld2(t[e]);
-        const double2 ww = ld2(w[e]), rr = ld2(r[e]);
-        w[e] = st2<V>(ww.x + al * pp.x, ww.y + al * pp.y);
-        r[e] = st2<V>(rr.x - al * tv.x, rr.y - al * tv.y);
+__global__ __launch_bounds__(256) void cgnr_upd1_kernel(V* __restrict__ w, V* __restrict__ r, const V* __restrict__ p,
+                                                        const V* __restrict__ t, const CgnrCol* __restrict__ cols,
+                                                        const double* __restrict__ tt, int N, int S,
+                                                        double* __restrict__ part) {
+    const CgBlock k = cg_block(N);
+    if (k.tile * CG_W >= S) return;
+    const bool act = k.s < S && cols[k.s].active && tt[k.s] > 0.0;
+    const double al = act ? cols[k.s].gamma / tt[k.s] : 0.0;
+    double sq = 0.0;
+    for (int j = k.j0; j < k.j1; j += 4) {
+        const size_t e = cg_at(k.tile, j, k.c, N);
+        double2 rr = ld2(r[e]);
+        if (act) {
+            const double2 pp = ld2(p[e]), tv = ld2(t[e]), ww = ld2(w[e]);
+            w[e] = st2<V>(ww.x + al * pp.x, ww.y + al * pp.y);
+            const V rn = st2<V>(rr.x - al * tv.x, rr.y - al * tv.y);
+            r[e] = rn;
+            rr = ld2(rn);
+        }
+        sq += rr.x * rr.x + rr.y * rr.y;
     }
+    cg_part(sq, k, S, part);
 }
 __global__ void cgnr_check_kernel(CgnrCol* cols, const double* rn2, const double* tt, int S, int* nactive) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -334,15 +394,16 @@ __global__ void cgnr_check_kernel(CgnrCol* cols, const double* rn2, const double
     cols[s] = c;
     if (c.active) atomicAdd(nactive, 1);
 }
-// after z = G r, zz = ||z||^2: p = z + (zz / gamma) p for active columns
+// after z = G r, zz = ||z||^2: p = z + (zz / gamma) p for the active columns
 template <typename V>
-__global__ void cgnr_upd2_kernel(V* __restrict__ p, const V* __restrict__ z, const CgnrCol* __restrict__ cols,
-                                 const double* __restrict__ zz, int N, int S) {
-    const size_t tot = size_t(N) * S;
-    for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < tot; e += size_t(gridDim.x) * blockDim.x) {
-        const int s = int(e % S);
-        if (!cols[s].active) continue;
-        const double be = zz[s] / cols[s].gamma;
+__global__ __launch_bounds__(256) void cgnr_upd2_kernel(V* __restrict__ p, const V* __restrict__ z,
+                                                        const CgnrCol* __restrict__ cols,
+                                                        const double* __restrict__ zz, int N, int S) {
+    const CgBlock k = cg_block(N);
+    if (k.s >= S || !cols[k.s].active) return;
+    const double be = zz[k.s] / cols[k.s].gamma;
+    for (int j = k.j0; j < k.j1; j += 4) {
+        const size_t e = cg_at(k.tile, j, k.c, N);
         const double2 pp = ld2(p[e]), zv = ld2(z[e]);
         p[e] = st2<V>(zv.x + be * pp.x, zv.y + be * pp.y);
     }
@@ -351,21 +412,22 @@ __global__ void cgnr_gamma_kernel(CgnrCol* cols, const double* zz, int S) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s < S && cols[s].active) cols[s].gamma = zz[s];
 }
-// P[s0 + s][j] = w[j][s] (32 x 32 tiles through LDS)
+// P[s0 + s][j] = w[j][s] for s < S, 32 x 32 tiles through LDS; grid (ceil(N / 32),
+// padded columns / 32)
 template <typename V>
-__global__ __launch_bounds__(256) void transpose_kernel(const V* __restrict__ w, int S, int N, double2* __restrict__ P,
-                                                        int s0) {
-    __shared__ double2 tile[32][33];
+__global__ __launch_bounds__(256) void tile_out_kernel(const V* __restrict__ w, int S, int N, double2* __restrict__ P,
+                                                       int s0) {
+    __shared__ double2 tl[32][33];
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
-    const int sb = blockIdx.x * 32, jb = blockIdx.y * 32;
+    const int jb = blockIdx.x * 32, cb = blockIdx.y * 32;
     for (int r = ty; r < 32; r += 8) {
-        const int j = jb + r, s = sb + tx;
-        if (j < N && s < S) tile[r][tx] = ld2(w[size_t(j) * S + s]);
+        const int j = jb + r, sc = cb + tx;
+        if (j < N) tl[r][tx] = ld2(w[cg_at(sc / CG_W, j, sc % CG_W, N)]);
     }
     __syncthreads();
     for (int r = ty; r < 32; r += 8) {
-        const int s = sb + r, j = jb + tx;
-        if (s < S && j < N) P[size_t(s0 + s) * N + j] = tile[tx][r];
+        const int sc = cb + r, j = jb + tx;
+        if (sc < S && j < N) P[size_t(s0 + sc) * N + j] = tl[tx][r];
     }
 }
 
@@ -426,12 +488,12 @@ size_t cald_layout(const efie_calderon_s& C, const CaldPlan& pl, int bary_dtype,
     x.rows = (int32_t*)take(4 * pl.entries);
     x.coef = (double*)take(8 * pl.entries);
     x.Tbc = (double2*)take(N * N * 16);
-    x.w = take(N * Sb * pl.vsz);
-    x.r = take(N * Sb * pl.vsz);
-    x.z = take(N * Sb * pl.vsz);
-    x.p = take(N * Sb * pl.vsz);
-    x.t = take(N * Sb * pl.vsz);
-    x.part = (double*)take(8 * size_t(CJS) * Sb);
+    x.w = take(N * size_t(cg_pad(pl.Sb)) * pl.vsz);
+    x.r = take(N * size_t(cg_pad(pl.Sb)) * pl.vsz);
+    x.z = take(N * size_t(cg_pad(pl.Sb)) * pl.vsz);
+    x.p = take(N * size_t(cg_pad(pl.Sb)) * pl.vsz);
+    x.t = take(N * size_t(cg_pad(pl.Sb)) * pl.vsz);
+    x.part = (double*)take(8 * size_t(cg_slices(int(N))) * Sb);
     x.bn2 = (double*)take(8 * Sb);
     x.tt = (double*)take(8 * Sb);
     x.rn2 = (double*)take(8 * Sb);
@@ -528,45 +590,41 @@ double cald_cgnr(const DevCald& d, const CaldWs& w, const CaldPlan& pl, int N, d
     V* const pv = static_cast<V*>(w.p);
     V* const tv = static_cast<V*>(w.t);
     double worst = 0.0;
-    auto colsq = [&](const V* X, int ld, int S, double* out) {
-        hipLaunchKernelGGL(colsq_part_kernel<V>, dim3(unsigned((S + 63) / 64), unsigned(CJS)), dim3(256), 0, stream, X,
-                           ld, N, S, w.part);
-        hipLaunchKernelGGL(colsq_final_kernel, dim3(unsigned((S + 255) / 256)), dim3(256), 0, stream, w.part, S, out);
-    };
     for (int s0 = 0; s0 < N; s0 += pl.Sb) {
         const int S = std::min(pl.Sb, N - s0);
-        const size_t tot = size_t(N) * S;
-        const int ge = int(std::min<size_t>((tot + 255) / 256, 16384));
-        const dim3 gs(unsigned(N), unsigned((S + 255) / 256));
-        hipLaunchKernelGGL(cgnr_init_kernel<V>, dim3(ge), dim3(256), 0, stream, w.Tbc + s0, N, wv, rv, N, S);
-        colsq(rv, S, S, w.bn2);
-        hipLaunchKernelGGL(cspmm_kernel<V>, gs, dim3(256), 0, stream, d.g_ptr, d.g_idx, d.g_val, rv, S, zv, S,
-                           d.n_order);
-        colsq(zv, S, S, w.zz);
+        const size_t tot = size_t(N) * size_t(cg_pad(S));
+        const dim3 gs(cg_blocks(S, N)), gc(unsigned((S + 255) / 256));
+        const int ns = cg_slices(N);
+        auto finish = [&](double* out) {   // slice sums -> per-column squared norms
+            hipLaunchKernelGGL(colsq_final_kernel, dim3(unsigned((S + 15) / 16)), dim3(256), 0, stream, w.part, S, ns,
+                               out);
+        };
+        hipLaunchKernelGGL(cgnr_init_kernel<V>, gs, dim3(256), 0, stream, w.Tbc + s0, N, wv, rv, N, S, w.part);
+        finish(w.bn2);
+        hipLaunchKernelGGL(cspmm_kernel<V>, gs, dim3(256), 0, stream, d.g_ptr, d.g_idx, d.g_val, rv, zv, S, d.n_order,
+                           N, w.part);
+        finish(w.zz);
         EFIE_HIP_CHECK(hipMemcpyAsync(pv, zv, tot * sizeof(V), hipMemcpyDeviceToDevice, stream));
-        hipLaunchKernelGGL(cgnr_setup_kernel, dim3(unsigned((S + 255) / 256)), dim3(256), 0, stream, w.cols, w.bn2,
-                           w.zz, tol, S);
+        hipLaunchKernelGGL(cgnr_setup_kernel, gc, dim3(256), 0, stream, w.cols, w.bn2, w.zz, tol, S);
         int h_active = S;
         for (int it = 0; it < maxit && h_active > 0; ++it) {
-            hipLaunchKernelGGL(cspmm_kernel<V>, gs, dim3(256), 0, stream, d.gt_ptr, d.gt_idx, d.gt_val, pv, S, tv, S,
-                               d.n_order);
-            colsq(tv, S, S, w.tt);
-            hipLaunchKernelGGL(cgnr_upd1_kernel<V>, dim3(ge), dim3(256), 0, stream, wv, rv, pv, tv, w.cols, w.tt, N,
-                               S);
-            colsq(rv, S, S, w.rn2);
+            hipLaunchKernelGGL(cspmm_kernel<V>, gs, dim3(256), 0, stream, d.gt_ptr, d.gt_idx, d.gt_val, pv, tv, S,
+                               d.n_order, N, w.part);
+            finish(w.tt);
+            hipLaunchKernelGGL(cgnr_upd1_kernel<V>, gs, dim3(256), 0, stream, wv, rv, pv, tv, w.cols, w.tt, N, S,
+                               w.part);
+            finish(w.rn2);
             EFIE_HIP_CHECK(hipMemsetAsync(w.counter, 0, sizeof(int), stream));
-            hipLaunchKernelGGL(cgnr_check_kernel, dim3(unsigned((S + 255) / 256)), dim3(256), 0, stream, w.cols, w.rn2,
-                               w.tt, S, w.counter);
-            hipLaunchKernelGGL(cspmm_kernel<V>, gs, dim3(256), 0, stream, d.g_ptr, d.g_idx, d.g_val, rv, S, zv, S,
-                               d.n_order);
-            colsq(zv, S, S, w.zz);
-            hipLaunchKernelGGL(cgnr_upd2_kernel<V>, dim3(ge), dim3(256), 0, stream, pv, zv, w.cols, w.zz, N, S);
-            hipLaunchKernelGGL(cgnr_gamma_kernel, dim3(unsigned((S + 255) / 256)), dim3(256), 0, stream, w.cols, w.zz,
-                               S);
+            hipLaunchKernelGGL(cgnr_check_kernel, gc, dim3(256), 0, stream, w.cols, w.rn2, w.tt, S, w.counter);
+            hipLaunchKernelGGL(cspmm_kernel<V>, gs, dim3(256), 0, stream, d.g_ptr, d.g_idx, d.g_val, rv, zv, S,
+                               d.n_order, N, w.part);
+            finish(w.zz);
+            hipLaunchKernelGGL(cgnr_upd2_kernel<V>, gs, dim3(256), 0, stream, pv, zv, w.cols, w.zz, N, S);
+            hipLaunchKernelGGL(cgnr_gamma_kernel, gc, dim3(256), 0, stream, w.cols, w.zz, S);
             EFIE_HIP_CHECK(hipMemcpyAsync(&h_active, w.counter, sizeof(int), hipMemcpyDeviceToHost, stream));
             EFIE_HIP_CHECK(hipStreamSynchronize(stream));
         }
-        hipLaunchKernelGGL(transpose_kernel<V>, dim3(unsigned((S + 31) / 32), unsigned((N + 31) / 32)), dim3(256), 0,
+        hipLaunchKernelGGL(tile_out_kernel<V>, dim3(unsigned((N + 31) / 32), unsigned(cg_pad(S) / 32)), dim3(256), 0,
                            stream, wv, S, N, Pout, s0);
         if (verbose())
             std::fprintf(stderr, "[efie] calderon CGNR columns %d..%d done t=%.3f\n", s0, s0 + S, now_s()),
@@ -577,6 +635,23 @@ double cald_cgnr(const DevCald& d, const CaldWs& w, const CaldPlan& pl, int N, d
         for (const auto& cc : cols) worst = std::max(worst, cc.bn2 > 0 ? std::sqrt(cc.rn2 / cc.bn2) : 0.0);
     }
     return worst;
+}
+
+// CSR rows in the order ord: stored row t is row ord[t]
+void permute_rows(const std::vector<int32_t>& ptr, const std::vector<int32_t>& idx, const std::vector<double>& val,
+                  const std::vector<int32_t>& ord, std::vector<int32_t>& pp, std::vector<int32_t>& pi,
+                  std::vector<double>& pv) {
+    pp.assign(ord.size() + 1, 0);
+    pi.clear();
+    pv.clear();
+    for (size_t t = 0; t < ord.size(); ++t) {
+        const size_t j = size_t(ord[t]);
+        for (int32_t q = ptr[j]; q < ptr[j + 1]; ++q) {
+            pi.push_back(idx[size_t(q)]);
+            pv.push_back(val[size_t(q)]);
+        }
+        pp[t + 1] = int32_t(pi.size());
+    }
 }
 
 }  // namespace
@@ -597,12 +672,17 @@ int efie_calderon_create(efie_mesh mesh, efie_calderon* out) {
             efie::put(blob, offs, C->r_ptr);
             efie::put(blob, offs, C->r_idx);
             efie::put(blob, offs, C->r_val);
-            efie::put(blob, offs, C->g_ptr);
-            efie::put(blob, offs, C->g_idx);
-            efie::put(blob, offs, C->g_val);
-            efie::put(blob, offs, C->gt_ptr);
-            efie::put(blob, offs, C->gt_idx);
-            efie::put(blob, offs, C->gt_val);
+            // the device copies of G and G^T store their rows in n_order order
+            std::vector<int32_t> pp, pi;
+            std::vector<double> pv;
+            efie::permute_rows(C->g_ptr, C->g_idx, C->g_val, C->n_order, pp, pi, pv);
+            efie::put(blob, offs, pp);
+            efie::put(blob, offs, pi);
+            efie::put(blob, offs, pv);
+            efie::permute_rows(C->gt_ptr, C->gt_idx, C->gt_val, C->n_order, pp, pi, pv);
+            efie::put(blob, offs, pp);
+            efie::put(blob, offs, pi);
+            efie::put(blob, offs, pv);
             efie::put(blob, offs, C->n_order);
             efie::put(blob, offs, C->run_t0);
             efie::put(blob, offs, C->u_ptr);
