@@ -265,6 +265,29 @@ __device__ inline void cg_part(double sq, const CgBlock& k, int S, double* part)
 // spatially coherent order (stored row t is row j = order[t]), over the stored
 // rows of the block's slice, for the columns of the block's tile;
 // part[slice][s] = sum over those rows of |Out[j][s]|^2
+// ar + j ai += sum of val[e] Xt[idx[e] CG_W] over e = kb .. min(kb + G, ke) - 1
+// (indices past ke repeat the last entry with weight 0)
+template <int G, typename V>
+__device__ inline void csp_group(const int32_t* __restrict__ idx, const double* __restrict__ val,
+                                 const V* __restrict__ Xt, int kb, int ke, double& ar, double& ai) {
+    int ix[G];
+    double vv[G];
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+        const int e = min(kb + q, ke - 1);
+        ix[q] = idx[e];
+        vv[q] = kb + q < ke ? val[e] : 0.0;
+    }
+    double2 x[G];
+#pragma unroll
+    for (int q = 0; q < G; ++q) x[q] = ld2(Xt[size_t(ix[q]) * CG_W]);
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+        ar += vv[q] * x[q].x;
+        ai += vv[q] * x[q].y;
+    }
+}
+
 template <typename V>
 __global__ __launch_bounds__(256) void cspmm_kernel(const int32_t* __restrict__ ptr, const int32_t* __restrict__ idx,
                                                     const double* __restrict__ val, const V* __restrict__ X,
@@ -276,25 +299,11 @@ __global__ __launch_bounds__(256) void cspmm_kernel(const int32_t* __restrict__ 
     double sq = 0.0;
     for (int t = k.j0; t < k.j1; t += 4) {
         double ar = 0, ai = 0;
-        // the (wave-uniform) row in groups of 8: 8 gathers in flight
-        for (int kb = ptr[t], ke = ptr[t + 1]; kb < ke; kb += 8) {
-            int ix[8];
-            double vv[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int e = min(kb + q, ke - 1);
-                ix[q] = idx[e];
-                vv[q] = kb + q < ke ? val[e] : 0.0;
-            }
-            double2 x[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) x[q] = ld2(Xt[size_t(ix[q]) * CG_W]);
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                ar += vv[q] * x[q].x;
-                ai += vv[q] * x[q].y;
-            }
-        }
+        // the (wave-uniform) row in groups of 8 gathers in flight, the rest in groups of 4
+        int kb = ptr[t];
+        const int ke = ptr[t + 1];
+        for (; kb + 8 <= ke; kb += 8) csp_group<8>(idx, val, Xt, kb, ke, ar, ai);
+        for (; kb < ke; kb += 4) csp_group<4>(idx, val, Xt, kb, ke, ar, ai);
         const V o = st2<V>(ar, ai);
         Out[cg_at(k.tile, order[t], k.c, N)] = o;
         const double2 od = ld2(o);   // the norm of the stored value

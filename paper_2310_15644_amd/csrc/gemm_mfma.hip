@@ -18,15 +18,17 @@
 // (the Krylov vectors); this bounds the FP32 accumulation error to short partial
 // sums.  Otherwise complex64 is written to Y[r].
 //
-// Pipeline: two LDS buffers; the global loads of chunk c+1 (16-byte loads into
-// registers when n is even and the operands 16-byte aligned, 8-byte otherwise;
+// Pipeline: two LDS buffers and two register sets of staged global loads (16-byte
+// loads when n is even and the operands 16-byte aligned, 8-byte otherwise;
 // without per-element bounds tests when the tile lies wholly inside the
-// matrices) are in flight while chunk c is multiplied, then written to the other
-// buffer; one barrier per chunk.  LDS rows are padded to KC + 2 complex values,
-// which keeps them 16-byte aligned for the 16-byte stores.  (The 8-byte reads
-// still meet some bank conflicts; an odd pad removes them for KC = 16 and halves
-// them for KC = 32, but changes the time by under one percent: the conflicts
-// overlap with the matrix instructions.)
+// matrices).  While chunk c is multiplied from LDS, chunk c+1 waits in registers
+// and the loads of chunk c+2 are in flight: the global latency is hidden behind
+// two chunks of matrix work instead of one.  After the multiply, chunk c+1 goes
+// to the other LDS buffer; one barrier per chunk.  LDS rows are padded to KC + 2
+// complex values, which keeps them 16-byte aligned for the 16-byte stores.  (The
+// 8-byte reads still meet some bank conflicts; an odd pad removes them for
+// KC = 16 and halves them for KC = 32, but changes the time by under one
+// percent: the conflicts overlap with the matrix instructions.)
 // Block order: workgroups are dealt to the 8 XCDs round-robin by id, so the ids
 // are remapped to give each XCD a contiguous run of tiles, walking the
 // right-hand-side tiles of one Z row strip first: the blocks that read the
@@ -34,6 +36,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "efie_internal.h"
 #include "linalg.h"
@@ -93,7 +96,8 @@ __global__ __launch_bounds__(256) void cgemm_planar_kernel(const float2* __restr
             }
     }
 
-    float4 ra[NA], rb[NB];
+    // two register sets of staged global loads: chunk c goes to set c % 2
+    float4 ra[2][NA], rb[2][NB];
     auto load2 = [&](const float2* base, int row, int nrows, int j) -> float4 {
         // complex elements j and j+1 of row `row` (zero outside the matrix)
         if (row >= nrows || j >= n) return make_float4(0.f, 0.f, 0.f, 0.f);
@@ -103,53 +107,54 @@ __global__ __launch_bounds__(256) void cgemm_planar_kernel(const float2* __restr
         const float2 v = j + 1 < n ? p[1] : make_float2(0.f, 0.f);
         return make_float4(u.x, u.y, v.x, v.y);
     };
-    auto gload = [&](int j0) {
+    auto gload = [&](int j0, float4* ga, float4* gb) {
         if (inside && j0 + KC <= n) {
 #pragma unroll
             for (int q = 0; q < NA; ++q) {
                 const int e = tid + 256 * q, r = e / KV, c = e % KV;
-                ra[q] = *reinterpret_cast<const float4*>(X + size_t(s0 + r) * n + j0 + 2 * c);
+                ga[q] = *reinterpret_cast<const float4*>(X + size_t(s0 + r) * n + j0 + 2 * c);
             }
 #pragma unroll
             for (int q = 0; q < NB; ++q) {
                 const int e = tid + 256 * q, r = e / KV, c = e % KV;
-                rb[q] = *reinterpret_cast<const float4*>(Z + size_t(i0 + r) * n + j0 + 2 * c);
+                gb[q] = *reinterpret_cast<const float4*>(Z + size_t(i0 + r) * n + j0 + 2 * c);
             }
         } else {
 #pragma unroll
             for (int q = 0; q < NA; ++q) {
                 const int e = tid + 256 * q, r = e / KV, c = e % KV;
-                ra[q] = load2(X, s0 + r, M, j0 + 2 * c);
+                ga[q] = load2(X, s0 + r, M, j0 + 2 * c);
             }
 #pragma unroll
             for (int q = 0; q < NB; ++q) {
                 const int e = tid + 256 * q, r = e / KV, c = e % KV;
-                rb[q] = load2(Z, i0 + r, n, j0 + 2 * c);
+                gb[q] = load2(Z, i0 + r, n, j0 + 2 * c);
             }
         }
     };
-    auto lstore = [&](int buf) {
+    auto lstore = [&](int buf, const float4* ga, const float4* gb) {
 #pragma unroll
         for (int q = 0; q < NA; ++q) {
             const int e = tid + 256 * q, r = e / KV, c = e % KV;
-            *reinterpret_cast<float4*>(&As[buf][r * AS + 2 * c]) = ra[q];
+            *reinterpret_cast<float4*>(&As[buf][r * AS + 2 * c]) = ga[q];
         }
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
             const int e = tid + 256 * q, r = e / KV, c = e % KV;
-            *reinterpret_cast<float4*>(&Bs[buf][r * AS + 2 * c]) = rb[q];
+            *reinterpret_cast<float4*>(&Bs[buf][r * AS + 2 * c]) = gb[q];
         }
     };
 
     const int kq = lane >> 4;          // 0..3: k within an instruction
     const int l16 = lane & 15;
     const int nch = (n + KC - 1) / KC;
-    gload(0);
-    lstore(0);
-    __syncthreads();
-    for (int ch = 0; ch < nch; ++ch) {
+    // one chunk: multiply LDS buffer ch % 2, flush (ACC64), store the staged chunk
+    // ch + 1 (set SN) into the other buffer; the loads of chunk ch + 2 (set SP,
+    // free since its chunk went to LDS) are issued first, two chunks ahead
+    auto step = [&](int ch, auto sp, auto sn) {
+        constexpr int SP = decltype(sp)::value, SN = decltype(sn)::value;
         const int buf = ch & 1;
-        if (ch + 1 < nch) gload((ch + 1) * KC);
+        if (ch + 2 < nch) gload((ch + 2) * KC, ra[SP], rb[SP]);
         const float2* A_ = As[buf] + (wm * WM + l16) * AS + kq;
         const float2* B_ = Bs[buf] + (wn * WN + l16) * AS + kq;
 #pragma unroll
@@ -206,8 +211,18 @@ __global__ __launch_bounds__(256) void cgemm_planar_kernel(const float2* __restr
                     acc3[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
                 }
         }
-        if (ch + 1 < nch) lstore(buf ^ 1);
+        if (ch + 1 < nch) lstore(buf ^ 1, ra[SN], rb[SN]);
         __syncthreads();
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    gload(0, ra[0], rb[0]);
+    lstore(0, ra[0], rb[0]);
+    if (nch > 1) gload(KC, ra[1], rb[1]);
+    __syncthreads();
+    for (int ch = 0; ch < nch; ch += 2) {
+        step(ch, I0{}, I1{});   // chunk ch is even: ch + 2 goes to set 0, ch + 1 comes from set 1
+        if (ch + 1 < nch) step(ch + 1, I1{}, I0{});
     }
     // D layout of the 16x16x4 instruction: lane l holds rows 4 (l / 16) + r, column l % 16
 #pragma unroll
