@@ -8,7 +8,11 @@ definition of Sec. III):
 with G_k(R) = exp(-j k R) / (4 pi R); k may be complex (Im k < 0 decays).
 
 Integration: the 7-point rule on each triangle, the 7x7 product rule on each
-triangle pair.  Near pairs (sharing a vertex, or centroid distance below
+triangle pair.  Optional distance-adaptive far rule (not in the paper): with
+far3 = r, a far pair whose centroid distance D satisfies D^2 >= (r h)^2, h the
+larger longest edge of the two triangles, takes the 3x3 product of the interior
+3-point degree-2 rule instead (the squares compared in FP64, summed in x, y, z
+order).  Near pairs (sharing a vertex, or centroid distance below
 near_factor times the larger longest edge) split G_k = G_smooth + 1/(4 pi R):
   G_smooth(R) = (exp(-j k R) - 1)/(4 pi R), limit -j k / (4 pi) at R = 0,
   integrated by the same 7x7 rule; 1/(4 pi R) by the 7-point rule on the test
@@ -40,6 +44,18 @@ def near_row(mesh, p, near_factor=2.0):
     d2 = ((mesh.centroid - mesh.centroid[p]) ** 2).sum(-1)
     hm = np.maximum(mesh.hmax, mesh.hmax[p])
     return share | (d2 < (near_factor * hm) ** 2)
+
+
+def far3_row(mesh, p, far3):
+    """Pairs (p, q) that take the 3x3 rule under the adaptive far rule with ratio
+    far3 (before the near test, which takes precedence): (T,) bool."""
+    if far3 is None:
+        return np.zeros(mesh.t, dtype=bool)
+    d = mesh.centroid - mesh.centroid[p]
+    d2 = d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1] + d[:, 2] * d[:, 2]
+    hm = np.maximum(mesh.hmax, mesh.hmax[p])
+    lim = far3 * hm
+    return d2 >= lim * lim
 
 
 def green(k, R):
@@ -103,27 +119,46 @@ def singular_blocks(geo, ps, qs):
     return TA, TP
 
 
-def pair_blocks(geo, k, p, qs, near_factor=2.0):
-    """T_A and T_Phi local 3x3 blocks for test triangle p against source triangles qs.
-    Returns TA (len(qs), 3, 3) and TP (len(qs), 3, 3) complex."""
+def _regular_blocks(geo, k, p, qs, near):
+    """T_A, T_Phi blocks of test triangle p against sources qs by the product rule of
+    geo: G_k on the far pairs, G_smooth on the near ones (flags `near`)."""
     mesh = geo.mesh
-    qs = np.atleast_1d(np.asarray(qs))
-    near = near_row(mesh, p, near_factor)[qs]
-    rp = geo.qp[p]                                   # (7, 3)
-    rq = geo.qp[qs]                                  # (Q, 7, 3)
-    R = np.linalg.norm(rp[None, :, None, :] - rq[:, None, :, :], axis=-1)   # (Q, 7a, 7b)
+    rp = geo.qp[p]                                   # (a, 3)
+    rq = geo.qp[qs]                                  # (Q, b, 3)
+    R = np.linalg.norm(rp[None, :, None, :] - rq[:, None, :, :], axis=-1)   # (Q, a, b)
     G = np.empty(R.shape, dtype=np.complex128)
     far = ~near
     G[far] = green(k, R[far])
     r_zero = 1e-14 * mesh.hmax[p]
     G[near] = green_smooth(k, R[near], r_zero)
-    WW = geo.W[p][None, :, None] * geo.W[qs][:, None, :]                   # (Q, 7a, 7b)
-    fp = geo.basis(p)                                # (3i, 7a, 3)
-    fq = geo.basis(qs)                               # (Q, 3j, 7b, 3)
-    dot = np.einsum("iax,qjbx->qijab", fp, fq)       # (Q, 3, 3, 7, 7)
+    WW = geo.W[p][None, :, None] * geo.W[qs][:, None, :]                   # (Q, a, b)
+    fp = geo.basis(p)                                # (3i, a, 3)
+    fq = geo.basis(qs)                               # (Q, 3j, b, 3)
+    dot = np.einsum("iax,qjbx->qijab", fp, fq)       # (Q, 3, 3, a, b)
     TA = np.einsum("qab,qijab->qij", WW * G, dot)
     S = np.einsum("qab->q", WW * G)
     TP = geo.div[p][None, :, None] * geo.div[qs][:, None, :] * S[:, None, None]
+    return TA, TP
+
+
+def pair_blocks(geo, k, p, qs, near_factor=2.0, far3=None, geo3=None):
+    """T_A and T_Phi local 3x3 blocks for test triangle p against source triangles qs.
+    Returns TA (len(qs), 3, 3) and TP (len(qs), 3, 3) complex.  far3: ratio of the
+    distance-adaptive far rule (None: the 7x7 rule on every pair); geo3 the
+    Geometry of the 3-point rule (built when not given)."""
+    mesh = geo.mesh
+    qs = np.atleast_1d(np.asarray(qs))
+    near = near_row(mesh, p, near_factor)[qs]
+    use3 = far3_row(mesh, p, far3)[qs] & ~near
+    TA = np.empty((len(qs), 3, 3), dtype=np.complex128)
+    TP = np.empty((len(qs), 3, 3), dtype=np.complex128)
+    i7 = np.nonzero(~use3)[0]
+    if len(i7):
+        TA[i7], TP[i7] = _regular_blocks(geo, k, p, qs[i7], near[i7])
+    i3 = np.nonzero(use3)[0]
+    if len(i3):
+        geo3 = geo3 or Geometry(mesh, quadrature.strang_fix3())
+        TA[i3], TP[i3] = _regular_blocks(geo3, k, p, qs[i3], np.zeros(len(i3), dtype=bool))
     idx = np.nonzero(near)[0]
     if len(idx):
         qn = qs[idx]
@@ -139,17 +174,19 @@ def z_from_blocks(k, TA, TP, eta=ETA0):
     return eta * (1j * k * TA + TP / (1j * k))
 
 
-def assemble(mesh, k, near_factor=2.0, eta=ETA0, parts=False, rule=None):
+def assemble(mesh, k, near_factor=2.0, eta=ETA0, parts=False, rule=None, far3=None):
     """Full N x N matrix Z (complex128); with parts=True also T_A and T_Phi
-    (Z is None when k == 0).  `rule` replaces the 7-point rule (convergence pins)."""
+    (Z is None when k == 0).  `rule` replaces the 7-point rule (convergence pins);
+    far3: ratio of the distance-adaptive far rule (None: off)."""
     geo = Geometry(mesh, rule)
+    geo3 = Geometry(mesh, quadrature.strang_fix3()) if far3 is not None else None
     N, T = mesh.n, mesh.t
     TAm = np.zeros((N, N), dtype=np.complex128)
     TPm = np.zeros((N, N), dtype=np.complex128)
     allq = np.arange(T)
     rows_of = mesh.tri_edge                                    # (T, 3)
     for p in range(T):
-        TA, TP = pair_blocks(geo, k, p, allq, near_factor)
+        TA, TP = pair_blocks(geo, k, p, allq, near_factor, far3, geo3)
         for i in range(3):
             m = rows_of[p, i]
             for j in range(3):
@@ -159,25 +196,27 @@ def assemble(mesh, k, near_factor=2.0, eta=ETA0, parts=False, rule=None):
     return (Z, TAm, TPm) if parts else Z
 
 
-def z_rows(mesh, k, rows, near_factor=2.0, eta=ETA0, geo=None):
+def z_rows(mesh, k, rows, near_factor=2.0, eta=ETA0, geo=None, far3=None):
     """Selected rows of Z: (len(rows), N).  Each row m sums its two test triangles."""
     geo = geo or Geometry(mesh)
+    geo3 = Geometry(mesh, quadrature.strang_fix3()) if far3 is not None else None
     N, T = mesh.n, mesh.t
     out = np.zeros((len(rows), N), dtype=np.complex128)
     allq = np.arange(T)
     for r, m in enumerate(rows):
         for p in mesh.edge_tri[m]:
             i = int(np.nonzero(mesh.tri_edge[p] == m)[0][0])
-            TA, TP = pair_blocks(geo, k, p, allq, near_factor)
+            TA, TP = pair_blocks(geo, k, p, allq, near_factor, far3, geo3)
             zb = z_from_blocks(k, TA[:, i, :], TP[:, i, :], eta)  # (T, 3)
             for j in range(3):
                 np.add.at(out[r], mesh.tri_edge[:, j], zb[:, j])
     return out
 
 
-def z_entries(mesh, k, pairs, near_factor=2.0, eta=ETA0, geo=None):
+def z_entries(mesh, k, pairs, near_factor=2.0, eta=ETA0, geo=None, far3=None):
     """Individual entries Z_mn for (m, n) pairs, each from its four triangle pairs."""
     geo = geo or Geometry(mesh)
+    geo3 = Geometry(mesh, quadrature.strang_fix3()) if far3 is not None else None
     out = np.zeros(len(pairs), dtype=np.complex128)
     for e, (m, n) in enumerate(pairs):
         acc = 0.0 + 0.0j
@@ -185,7 +224,7 @@ def z_entries(mesh, k, pairs, near_factor=2.0, eta=ETA0, geo=None):
             i = int(np.nonzero(mesh.tri_edge[p] == m)[0][0])
             for q in mesh.edge_tri[n]:
                 j = int(np.nonzero(mesh.tri_edge[q] == n)[0][0])
-                TA, TP = pair_blocks(geo, k, p, [q], near_factor)
+                TA, TP = pair_blocks(geo, k, p, [q], near_factor, far3, geo3)
                 acc += z_from_blocks(k, TA[0, i, j], TP[0, i, j], eta)
         out[e] = acc
     return out

@@ -34,6 +34,16 @@ def radon7():
     return bary, w
 
 
+def strang_fix3():
+    """Barycentric coordinates (3, 3) and weights (3,) of the interior 3-point rule
+    of degree 2 (points (2/3, 1/6, 1/6) and permutations, equal weights; Strang and
+    Fix 1973, Table 4.1).  Used for well-separated triangle pairs by the
+    distance-adaptive far rule, which the paper does not have."""
+    a, b = 2.0 / 3.0, 1.0 / 6.0
+    bary = np.array([[a, b, b], [b, a, b], [b, b, a]], dtype=np.float64)
+    return bary, np.full(3, 1.0 / 3.0)
+
+
 def points(tri_xyz, bary):
     """Cartesian quadrature points: tri_xyz (..., 3 vertices, 3) -> (..., npts, 3)."""
     return np.einsum("pk,...kx->...px", bary, tri_xyz)
