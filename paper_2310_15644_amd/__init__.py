@@ -37,7 +37,7 @@ library_path = os.environ.get("EFIE_LIBRARY") or os.path.join(HERE, "libefie.so"
 # symbols declared in include/efie.h (checked by the CPU tests)
 EXPORTED = [
     "efie_abi_version", "efie_last_error", "efie_mesh_create", "efie_mesh_destroy", "efie_mesh_sizes",
-    "efie_mesh_rwg_table", "efie_mesh_upload", "efie_assemble", "efie_excite_planewave",
+    "efie_mesh_rwg_table", "efie_mesh_upload", "efie_mesh_set_far_rule", "efie_assemble", "efie_excite_planewave",
     "efie_farfield_workspace_size", "efie_farfield", "efie_zx", "efie_solve_workspace_size", "efie_solve",
     "efie_prof_enable", "efie_prof_reset", "efie_prof_read",
     "efie_gemm_variants", "efie_gemm_variant_info", "efie_gemm_autotune", "efie_gemm_select",
@@ -90,6 +90,7 @@ def lib():
                              ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "efie_mesh_rwg_table": ([P, P, P], ctypes.c_int),
         "efie_mesh_upload": ([P, P, ctypes.c_size_t, P], ctypes.c_int),
+        "efie_mesh_set_far_rule": ([P, D], ctypes.c_int),
         "efie_assemble": ([P, D, D, D, ctypes.c_int, P, P, ctypes.c_int, P], ctypes.c_int),
         "efie_excite_planewave": ([P, D, P, P, I64, D, P, P], ctypes.c_int),
         "efie_farfield_workspace_size": ([P, I64, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
@@ -204,8 +205,18 @@ class Mesh:
         self.vertices = v
         self.triangles = t
         self.near_factor = near_factor
+        self.far3 = 0.0
         self._dev = None
         self._device = device
+
+    def set_far_rule(self, ratio: float = 0.0):
+        """Distance-adaptive far rule: pairs with centroid distance >= ratio times the
+        larger longest edge take the 3x3 product of the interior 3-point rule
+        (0: the 7x7 rule everywhere).  Applies to later assemblies of this mesh and
+        to the barycentric operator of a Calderon built from it."""
+        _check(lib().efie_mesh_set_far_rule(self._h, float(ratio)))
+        self.far3 = float(ratio)
+        return self
 
     def rwg_table(self):
         ev = np.zeros((self.n, 2), dtype=np.int32)

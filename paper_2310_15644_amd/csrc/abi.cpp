@@ -1,4 +1,5 @@
 // C ABI entry points for mesh handles, errors and versioning.
+#include <cmath>
 #include <cstring>
 
 #include "efie_internal.h"
@@ -37,6 +38,16 @@ int efie_mesh_create(const double* xyz, int64_t nv, const int32_t* tri, int64_t 
 }
 
 void efie_mesh_destroy(efie_mesh mesh) { delete mesh; }
+
+int efie_mesh_set_far_rule(efie_mesh mesh, double ratio) {
+    return guarded([&]() {
+        EFIE_REQUIRE(mesh != nullptr, EFIE_ERR_ARG, "mesh_set_far_rule: null mesh");
+        EFIE_REQUIRE(std::isfinite(ratio) && ratio >= 0.0, EFIE_ERR_ARG, "mesh_set_far_rule: ratio must be >= 0");
+        mesh->far3 = ratio;
+        mesh->dm.far3 = ratio;   // the device view (taken by value at each launch)
+        return int(EFIE_OK);
+    });
+}
 
 int efie_mesh_sizes(efie_mesh mesh, int64_t* n_rwg, int64_t* n_tri, int64_t* n_near, size_t* table_bytes) {
     return guarded([&]() {

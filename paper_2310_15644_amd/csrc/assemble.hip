@@ -208,11 +208,12 @@ template <typename R>
 Tables<R> tables(const DevMesh& m);
 template <>
 Tables<double> tables<double>(const DevMesh& m) {
-    return {m.qx, m.qy, m.qz, m.qw, m.vx, m.vy, m.vz, m.cf, m.dv};
+    return {m.qx, m.qy, m.qz, m.qw, m.vx, m.vy, m.vz, m.cf, m.dv, m.q3x, m.q3y, m.q3z, m.q3w};
 }
 template <>
 Tables<float> tables<float>(const DevMesh& m) {
-    return {m.qx32, m.qy32, m.qz32, m.qw32, m.vx32, m.vy32, m.vz32, m.cf32, m.dv32};
+    return {m.qx32, m.qy32, m.qz32, m.qw32, m.vx32, m.vy32, m.vz32, m.cf32, m.dv32,
+            m.q3x32, m.q3y32, m.q3z32, m.q3w32};
 }
 
 template <typename R, bool PARTS>

@@ -351,6 +351,10 @@ extern "C" int efie_batch_create(const efie_mesh* meshes, int32_t nmesh, efie_ba
                 delete B;
                 throw Error{EFIE_ERR_STATE, "batch_create: every mesh must exist and be uploaded"};
             }
+            if (meshes[i]->far3 != 0.0) {
+                delete B;
+                throw Error{EFIE_ERR_ARG, "batch_create: the batch takes the 7x7 rule only (a mesh has the far rule on)"};
+            }
             B->meshes.push_back(meshes[i]);
         }
         batch_prepare(*B);

@@ -798,6 +798,9 @@ int efie_calderon_assemble_ex(efie_calderon c, double kt_re, double kt_im, doubl
         static_assert(BC_BLOCK == 256, "one thread per BC function of a run");
         EFIE_REQUIRE(c->u_max <= BC_UMAX, EFIE_ERR_STATE, "calderon_assemble: BC run lists too long");
         const unsigned nruns = unsigned(c->run_t0.size() - 1);
+        // the barycentric operator follows the primal mesh's far rule
+        c->bary.far3 = c->primal->far3;
+        c->bary.dm.far3 = c->primal->far3;
         for (int ch = 0; ch < pl.nchunks; ++ch) {
             const int c0 = ch * pl.chunk, c1 = std::min(Tb, c0 + pl.chunk), np = c1 - c0;
             pair_rows_chunk(c->bary.dm, kt_re, kt_im, eta, bary_dtype, w.W, c0, c1, c->bary.near_p, true, stream);

@@ -76,6 +76,11 @@ struct DevMesh {
     const int32_t *near_p, *near_q;      // ordered near pairs (incl. p == q)
     const int32_t *et;                   // RWG -> (T+, T-) [2][N]
     const int32_t *el;                   // RWG -> local edge index in T+ / T- [2][N]
+    // distance-adaptive far rule: pairs with centroid distance D >= far3 * (larger
+    // longest edge) take the 3x3 product of the interior 3-point rule (far3 = 0: off)
+    const double *q3x, *q3y, *q3z, *q3w;       // its point offsets and weights*area [3][T]
+    const float *q3x32, *q3y32, *q3z32, *q3w32;
+    double far3;
 };
 
 }  // namespace efie
@@ -83,6 +88,7 @@ struct DevMesh {
 struct efie_mesh_s {
     int64_t nv = 0, T = 0, N = 0;
     double near_factor = 2.0;
+    double far3 = 0.0;                       // ratio of the distance-adaptive far rule (0: off)
     std::vector<double> xyz;                 // nv*3
     std::vector<int32_t> tri;                // T*3
     std::vector<int32_t> edge_v, edge_t, edge_l;  // N*2 each (edge_l: local index in T+/T-)

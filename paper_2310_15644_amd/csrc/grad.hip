@@ -643,6 +643,7 @@ extern "C" int efie_vertex_grad(efie_mesh mesh, double k, double eta, const void
         EFIE_REQUIRE(mesh && J && lambda && W && dirs && khat && pol && dxyz && ws, EFIE_ERR_ARG,
                      "vertex_grad: null argument");
         EFIE_REQUIRE(mesh->dev != nullptr, EFIE_ERR_STATE, "vertex_grad: mesh tables not uploaded");
+        EFIE_REQUIRE(mesh->far3 == 0.0, EFIE_ERR_ARG, "vertex_grad: differentiates the 7x7 rule only (far rule on)");
         EFIE_REQUIRE(k > 0.0 && std::isfinite(k) && ndir >= 1 && ndir < (int64_t(1) << 20), EFIE_ERR_ARG,
                      "vertex_grad: bad k or ndir");
         EFIE_REQUIRE(ws_bytes >= size_t(mesh->T) * 9 * sizeof(double), EFIE_ERR_ARG, "vertex_grad: ws too small");

@@ -216,6 +216,11 @@ void pack_tables(efie_mesh_s& m) {
     std::vector<double> cx(T), cy(T), cz(T), qx(7 * T), qy(7 * T), qz(7 * T), qw(7 * T);
     std::vector<double> vx(3 * T), vy(3 * T), vz(3 * T), cf(3 * T), dv(3 * T), nx(T), ny(T), nz(T), hm(T);
     std::vector<int32_t> te(3 * T), tv(3 * T), et(2 * N), el(2 * N);
+    // interior 3-point rule of degree 2 (the distance-adaptive far rule):
+    // barycentric (2/3, 1/6, 1/6) and permutations, weights 1/3
+    const double b3[3][3] = {{2.0 / 3.0, 1.0 / 6.0, 1.0 / 6.0}, {1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0},
+                             {1.0 / 6.0, 1.0 / 6.0, 2.0 / 3.0}};
+    std::vector<double> q3x(3 * T), q3y(3 * T), q3z(3 * T), q3w(3 * T);
     for (int64_t t = 0; t < T; ++t) {
         // vertex offsets from the centroid; points r = sum_k lambda_k p_k become
         // sum_k lambda_k (p_k - c) since the barycentric weights sum to one
@@ -231,6 +236,12 @@ void pack_tables(efie_mesh_s& m) {
             qy[a * T + t] = bary[a][0] * X[0][1] + bary[a][1] * X[1][1] + bary[a][2] * X[2][1];
             qz[a * T + t] = bary[a][0] * X[0][2] + bary[a][1] * X[1][2] + bary[a][2] * X[2][2];
             qw[a * T + t] = w[a] * m.area[t];
+        }
+        for (int a = 0; a < 3; ++a) {
+            q3x[a * T + t] = b3[a][0] * X[0][0] + b3[a][1] * X[1][0] + b3[a][2] * X[2][0];
+            q3y[a * T + t] = b3[a][0] * X[0][1] + b3[a][1] * X[1][1] + b3[a][2] * X[2][1];
+            q3z[a * T + t] = b3[a][0] * X[0][2] + b3[a][1] * X[1][2] + b3[a][2] * X[2][2];
+            q3w[a * T + t] = m.area[t] / 3.0;
         }
         for (int i = 0; i < 3; ++i) {
             vx[i * T + t] = X[i][0];
@@ -270,6 +281,8 @@ void pack_tables(efie_mesh_s& m) {
     pk.add(m.near_mask);
     pk.add(m.near_p); pk.add(m.near_q);
     pk.add(et); pk.add(el);
+    pk.add(q3x); pk.add(q3y); pk.add(q3z); pk.add(q3w);
+    pk.add(f32(q3x)); pk.add(f32(q3y)); pk.add(f32(q3z)); pk.add(f32(q3w));
     pk.blob.resize((pk.blob.size() + 255) & ~size_t(255));
     m.host_blob.swap(pk.blob);
     m.offs.swap(pk.offs);
@@ -298,6 +311,9 @@ void bind_tables(efie_mesh_s& m, void* dev) {
     d.near_mask = reinterpret_cast<const uint64_t*>(b + o[i++]);
     d.near_p = I(); d.near_q = I();
     d.et = I(); d.el = I();
+    d.q3x = D(); d.q3y = D(); d.q3z = D(); d.q3w = D();
+    d.q3x32 = F(); d.q3y32 = F(); d.q3z32 = F(); d.q3w32 = F();
+    d.far3 = m.far3;
     m.dev = dev;
 }
 

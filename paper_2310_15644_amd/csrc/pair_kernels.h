@@ -22,7 +22,20 @@ struct Scale {          // Z contribution = A * T_A + P * T_Phi (complex), or pa
 template <typename R>
 struct Tables {
     const R *qx, *qy, *qz, *qw, *vx, *vy, *vz, *cf, *dv;
+    const R *q3x, *q3y, *q3z, *q3w;   // 3-point rule of the adaptive far rule (null: not used)
 };
+
+// Whether the far pair (p, q) takes the 3x3 rule: D^2 >= (far3 h)^2 with h the
+// larger longest edge of the two triangles, all in FP64 without contraction (the
+// same decision as the oracle's)
+__device__ __forceinline__ bool far3_pair(const DevMesh& m, int p, int q) {
+    const double dx = __dsub_rn(m.cx[q], m.cx[p]);
+    const double dy = __dsub_rn(m.cy[q], m.cy[p]);
+    const double dz = __dsub_rn(m.cz[q], m.cz[p]);
+    const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+    const double lim = __dmul_rn(m.far3, fmax(m.hm[p], m.hm[q]));
+    return d2 >= __dmul_rn(lim, lim);
+}
 
 // ------------------------------------------------------------------ helpers
 template <typename R>
@@ -69,32 +82,36 @@ __device__ __forceinline__ void green_far(float krev, float ki, bool ck, float R
 // the nine half-function products.  emit(i, j, zr, zi) receives the Z
 // contribution of test edge i of p and source edge j of q (PARTS: zr, zi are the
 // T_A part and emit2 gets the T_Phi part).
-template <typename R, bool CK, bool PARTS, typename Emit, typename Emit2>
-__device__ __forceinline__ void far_pair_emit(const DevMesh& m, const Tables<R>& tb, int p, int q, R kphase, R ki,
+// The product rule of NP points per triangle, point offsets and weights from the
+// tables (qx, qy, qz, qw), [NP][T].
+template <int NP, typename R, bool CK, bool PARTS, typename Emit, typename Emit2>
+__device__ __forceinline__ void far_pair_rule(const DevMesh& m, const Tables<R>& tb, const R* __restrict__ qx,
+                                              const R* __restrict__ qy, const R* __restrict__ qz,
+                                              const R* __restrict__ qw, int p, int q, R kphase, R ki,
                                               const Scale& sc, Emit emit, Emit2 emit2) {
     const int T = m.T;
     const R Dx = R(m.cx[p] - m.cx[q]);
     const R Dy = R(m.cy[p] - m.cy[q]);
     const R Dz = R(m.cz[p] - m.cz[q]);
-    R sx[NQ], sy[NQ], sz[NQ], sw[NQ];
+    R sx[NP], sy[NP], sz[NP], sw[NP];
 #pragma unroll
-    for (int b = 0; b < NQ; ++b) {
-        sx[b] = tb.qx[b * T + q];
-        sy[b] = tb.qy[b * T + q];
-        sz[b] = tb.qz[b * T + q];
-        sw[b] = tb.qw[b * T + q];
+    for (int b = 0; b < NP; ++b) {
+        sx[b] = qx[b * T + q];
+        sy[b] = qy[b * T + q];
+        sz[b] = qz[b * T + q];
+        sw[b] = qw[b * T + q];
     }
     R m0r = 0, m0i = 0;
     R mdr[3] = {0, 0, 0}, mdi[3] = {0, 0, 0};     // sum W W G d_a
     R mpr[3] = {0, 0, 0}, mpi[3] = {0, 0, 0};     // sum W W G d'_b
     R mmr = 0, mmi = 0;                             // sum W W G d_a . d'_b
 #pragma unroll 1
-    for (int a = 0; a < NQ; ++a) {
-        const R ax = tb.qx[a * T + p], ay = tb.qy[a * T + p], az = tb.qz[a * T + p], wa = tb.qw[a * T + p];
+    for (int a = 0; a < NP; ++a) {
+        const R ax = qx[a * T + p], ay = qy[a * T + p], az = qz[a * T + p], wa = qw[a * T + p];
         const R ox = Dx + ax, oy = Dy + ay, oz = Dz + az;
         R s0r = 0, s0i = 0, s1r[3] = {0, 0, 0}, s1i[3] = {0, 0, 0};
 #pragma unroll
-        for (int b = 0; b < NQ; ++b) {
+        for (int b = 0; b < NP; ++b) {
             const R dx = ox - sx[b], dy = oy - sy[b], dz = oz - sz[b];
             const R R2 = dx * dx + dy * dy + dz * dz;
             R gr, gi;
@@ -156,6 +173,17 @@ __device__ __forceinline__ void far_pair_emit(const DevMesh& m, const Tables<R>&
             }
         }
     }
+}
+
+// The far pair (p, q) by the 7x7 rule, or by the 3x3 rule where the adaptive far
+// rule is on (m.far3 > 0) and the pair is far enough.
+template <typename R, bool CK, bool PARTS, typename Emit, typename Emit2>
+__device__ __forceinline__ void far_pair_emit(const DevMesh& m, const Tables<R>& tb, int p, int q, R kphase, R ki,
+                                              const Scale& sc, Emit emit, Emit2 emit2) {
+    if (m.far3 > 0.0 && far3_pair(m, p, q))
+        far_pair_rule<3, R, CK, PARTS>(m, tb, tb.q3x, tb.q3y, tb.q3z, tb.q3w, p, q, kphase, ki, sc, emit, emit2);
+    else
+        far_pair_rule<NQ, R, CK, PARTS>(m, tb, tb.qx, tb.qy, tb.qz, tb.qw, p, q, kphase, ki, sc, emit, emit2);
 }
 
 // The pair (p, q) added to Z (and Z2 in parts mode) with atomics; near pairs skipped.

@@ -91,6 +91,18 @@ def test_mesh_errors():
         P.Mesh(v, f, near_factor=0.0)
 
 
+def test_far_rule_setter():
+    v, f = synth.icosphere(1)
+    m = P.Mesh(v, f)
+    for bad in (-1.0, float("nan"), float("inf")):
+        with pytest.raises(P.EfieError) as ei:
+            m.set_far_rule(bad)
+        assert ei.value.code == -1
+    assert m.set_far_rule(4.0).far3 == 4.0
+    assert m.set_far_rule(0.0).far3 == 0.0
+    assert P.lib().efie_mesh_set_far_rule(None, 1.0) == -1
+
+
 def test_calls_before_upload_fail_cleanly():
     L = P.lib()
     v, f = synth.icosphere(1)
