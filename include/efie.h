@@ -232,8 +232,9 @@ int efie_zx(const void* Z, int dtype, int64_t n, const void* X, void* Y, int64_t
 /*
  * The mixed solves' product as a call of its own: Y = Z X with Z complex64
  * (n x n) and X, Y complex128 (nrhs, n).  X is rounded to complex64 and
- * multiplied on the FP32 matrix cores with the partial sums of every K chunk
- * flushed into FP64 accumulators; Y is written in complex128.  Any nrhs >= 1
+ * multiplied on the FP32 matrix cores with the partial sums of every two K
+ * chunks (at most 64 complex terms) flushed into FP64 accumulators; Y is
+ * written in complex128.  Any nrhs >= 1
  * takes the matrix cores here.  ws: dev scratch of at least
  * efie_zx_flush64_workspace_size bytes, 16-byte aligned.  Y must not overlap X.
  */
@@ -272,8 +273,8 @@ typedef struct {
     int32_t max_refine;   /* EFIE_C64 only: outer refinement steps (>= 1)            */
     double inner_tol;     /* EFIE_C64 only: relative tolerance of each inner solve   */
     int32_t fp32_acc;     /* EFIE_C64 only: 0 (default) = flush the FP32 matrix-core */
-                          /* partial sums into FP64 every K chunk; 1 = accumulate in */
-                          /* FP32 (faster products, more Krylov iterations)          */
+                          /* partial sums into FP64 every two K chunks; 1 = accumu-  */
+                          /* late in FP32 (more Krylov iterations)                   */
 } efie_solve_opts;
 
 typedef struct {

@@ -14,9 +14,9 @@
 // Tiling: a block of 256 threads (4 wavefronts, 2 x 2) owns BM right-hand sides
 // x BNC unknowns; K is walked in chunks of KC complex elements.
 // ACC64: the FP32 matrix-core partial sums are flushed into FP64 accumulators after
-// every K chunk, and the result is written as complex128 to the rows Y[yrow[r]]
-// (the Krylov vectors); this bounds the FP32 accumulation error to short partial
-// sums.  Otherwise complex64 is written to Y[r].
+// every two K chunks (2 KC terms), and the result is written as complex128 to the
+// rows Y[yrow[r]] (the Krylov vectors); this bounds the FP32 accumulation error to
+// short partial sums.  Otherwise complex64 is written to Y[r].
 //
 // Pipeline: two LDS buffers and two register sets of staged global loads (16-byte
 // loads when n is even and the operands 16-byte aligned, 8-byte otherwise;
@@ -45,8 +45,17 @@ namespace efie {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
+// Minimum wavefronts per SIMD asked of the register allocator: three for the
+// FP64-flush tile with 32-row chunks, whose two-chunk flush interval would
+// otherwise take it to 178 registers and two wavefronts.
 template <int BM, int BNC, int KC, bool ACC64>
-__global__ __launch_bounds__(256) void cgemm_planar_kernel(const float2* __restrict__ X, const float2* __restrict__ Z,
+constexpr int gemm_min_waves() {
+    return (ACC64 && BM == 64 && BNC == 32 && KC == 32) ? 3 : 1;
+}
+
+template <int BM, int BNC, int KC, bool ACC64>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_min_waves<BM, BNC, KC, ACC64>())))
+void cgemm_planar_kernel(const float2* __restrict__ X, const float2* __restrict__ Z,
                                                            void* __restrict__ Yv, int M, int n,
                                                            const int* __restrict__ yrow) {
     constexpr int AS = KC + 2;             // float2 per LDS row (16-byte aligned rows)
@@ -148,10 +157,29 @@ __global__ __launch_bounds__(256) void cgemm_planar_kernel(const float2* __restr
     const int kq = lane >> 4;          // 0..3: k within an instruction
     const int l16 = lane & 15;
     const int nch = (n + KC - 1) / KC;
-    // one chunk: multiply LDS buffer ch % 2, flush (ACC64), store the staged chunk
-    // ch + 1 (set SN) into the other buffer; the loads of chunk ch + 2 (set SP,
-    // free since its chunk went to LDS) are issued first, two chunks ahead
-    auto step = [&](int ch, auto sp, auto sn) {
+    // one chunk: multiply LDS buffer ch % 2, flush when fl is set (ACC64; odd chunks), store
+    // the staged chunk ch + 1 (set SN) into the other buffer; the loads of chunk
+    // ch + 2 (set SP, free since its chunk went to LDS) are issued first, two chunks
+    // ahead
+    auto flush = [&]() {
+        if constexpr (ACC64) {
+#pragma unroll
+            for (int a = 0; a < TM; ++a)
+#pragma unroll
+                for (int b = 0; b < TN; ++b) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const double p1 = accr[a][b][r], p2 = acci[a][b][r], p3 = acc3[a][b][r];
+                        dr[a][b][r] += p1 - p2;
+                        di[a][b][r] += p3 - p1 - p2;
+                    }
+                    accr[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    acci[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    acc3[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+                }
+        }
+    };
+    auto step = [&](int ch, auto sp, auto sn, auto fl) {
         constexpr int SP = decltype(sp)::value, SN = decltype(sn)::value;
         const int buf = ch & 1;
         if (ch + 2 < nch) gload((ch + 2) * KC, ra[SP], rb[SP]);
@@ -196,20 +224,7 @@ __global__ __launch_bounds__(256) void cgemm_planar_kernel(const float2* __restr
             }
         }
         if constexpr (ACC64) {
-#pragma unroll
-            for (int a = 0; a < TM; ++a)
-#pragma unroll
-                for (int b = 0; b < TN; ++b) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const double p1 = accr[a][b][r], p2 = acci[a][b][r], p3 = acc3[a][b][r];
-                        dr[a][b][r] += p1 - p2;
-                        di[a][b][r] += p3 - p1 - p2;
-                    }
-                    accr[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
-                    acci[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
-                    acc3[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
-                }
+            if constexpr (decltype(fl)::value) flush();
         }
         if (ch + 1 < nch) lstore(buf ^ 1, ra[SN], rb[SN]);
         __syncthreads();
@@ -220,10 +235,13 @@ __global__ __launch_bounds__(256) void cgemm_planar_kernel(const float2* __restr
     lstore(0, ra[0], rb[0]);
     if (nch > 1) gload(KC, ra[1], rb[1]);
     __syncthreads();
+    using F0 = std::integral_constant<bool, false>;
+    using F1 = std::integral_constant<bool, true>;
     for (int ch = 0; ch < nch; ch += 2) {
-        step(ch, I0{}, I1{});   // chunk ch is even: ch + 2 goes to set 0, ch + 1 comes from set 1
-        if (ch + 1 < nch) step(ch + 1, I1{}, I0{});
+        step(ch, I0{}, I1{}, F0{});   // chunk ch is even: ch + 2 goes to set 0, ch + 1 comes from set 1
+        if (ch + 1 < nch) step(ch + 1, I1{}, I0{}, F1{});
     }
+    if (nch & 1) flush();
     // D layout of the 16x16x4 instruction: lane l holds rows 4 (l / 16) + r, column l % 16
 #pragma unroll
     for (int a = 0; a < TM; ++a)
