@@ -470,6 +470,10 @@ def main():
                          "calderon: level-4 Calderon vs plain CGS; mixed-fp64: level-5 mixed vs FP64 path; "
                          "gradient: level-4 adjoint vertex gradient; far-rule: level-5 assembly, P build and "
                          "accuracy with the distance-adaptive far rule against the 7x7 rule")
+    ap.add_argument("--cal-far-rule", type=float, default=4.0,
+                    help="far rule of the Calderon preconditioner's barycentric operator alone: its pairs with "
+                         "centroid distance >= this times the larger longest edge take the 3x3 rule (default 4; "
+                         "< 0: follow --far-rule).  P only preconditions: Z and the true residual keep their rule")
     ap.add_argument("--far-rule", type=float, default=0.0,
                     help="distance-adaptive far rule: far pairs with centroid distance >= this times the larger "
                          "longest edge take the 3x3 rule (0: the 7x7 rule everywhere, the default)")
@@ -539,6 +543,7 @@ def main():
     cal = None
     if args.solver == "calderon":
         cal = P.Calderon(m).upload(dev)        # host refinement and BC tables: mesh preprocessing
+        cal.set_far_rule(args.cal_far_rule)
         log(f"bench: Calderon tables: {cal.n_bary} barycentric RWGs")
 
     def step(rec):
@@ -621,10 +626,13 @@ def main():
                         + ((f"mixed precision (complex64 Z, FP32 MFMA with "
                             f"{'FP32 accumulation' if args.fp32_acc else 'FP64 flushes'}, FP64 refinement)")
                            if dt == P.C64 else "FP64") + "; "
-                        + ("Calderon-preconditioned CGS (P = T_BC(k~) G_mix^-1 built in the step)"
+                        + ("Calderon-preconditioned CGS (P = T_BC(k~) G_mix^-1 built in the step"
+                           + (f", its barycentric far pairs beyond {args.cal_far_rule} h by the 3x3 rule)"
+                              if args.cal_far_rule >= 0 else ")")
                            if args.solver == "calderon" else "unpreconditioned COCG"),
             "solver": args.solver,
             "far_rule": args.far_rule if args.far_rule > 0 else None,
+            "calderon_far_rule": args.cal_far_rule if args.cal_far_rule >= 0 else None,
             "accumulation": ("fp32" if args.fp32_acc else "fp64-flush") if dt == P.C64 else "fp64",
             "n_unknowns": N,
             "nrhs": S,

@@ -100,7 +100,8 @@ void efie_mesh_destroy(efie_mesh mesh);
  * evaluations instead of 49.  ratio = 0 restores the 7x7 rule everywhere.
  * Applies to every later assembly of this mesh (efie_assemble, efie_assemble_ws,
  * and the barycentric operator of an efie_calderon created from it, whose pairs
- * are measured in their own triangles' edges); efie_batch_* and
+ * are measured in their own triangles' edges, unless efie_calderon_set_far_rule
+ * gives that operator a rule of its own); efie_batch_* and
  * efie_vertex_grad reject a mesh with the rule on (EFIE_ERR_ARG).  Accuracy: the
  * 3x3 rule's error on a pair falls as (h / D)^3 and (k h)^3; on a level-2
  * sphere (ratio 3, k = 1) Z moves by 2e-5 (Frobenius, relative) and the RCS by
@@ -356,6 +357,13 @@ int efie_solve(const void* Z, int dtype, int64_t n, const void* V, void* J, int6
 typedef struct efie_calderon_s* efie_calderon;
 int efie_calderon_create(efie_mesh mesh, efie_calderon* out);
 void efie_calderon_destroy(efie_calderon c);
+/* The far rule of the barycentric operator T_bary(k~) alone (see
+ * efie_mesh_set_far_rule): ratio >= 0 sets it for later efie_calderon_assemble
+ * calls, independently of the primal mesh; ratio < 0 (the default) makes it
+ * follow the primal mesh's rule.  P only has to be a fixed approximation of
+ * T_BC G_mix^-1, so a coarser rule here leaves the solution of P Z J = P V to
+ * the accuracy of Z.  Errors: EFIE_ERR_ARG (null handle, ratio not finite). */
+int efie_calderon_set_far_rule(efie_calderon c, double ratio);
 int efie_calderon_sizes(efie_calderon c, int64_t* n_bary_rwg, int64_t* n_bary_tri, size_t* table_bytes,
                         size_t* ws_bytes);
 int efie_calderon_upload(efie_calderon c, void* dev, size_t bytes, hipStream_t stream);

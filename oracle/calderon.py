@@ -136,16 +136,18 @@ def bc_charge(mesh, bary, R):
 class Calderon:
     """Dense oracle of the Calderon-preconditioned EFIE for one mesh and wavenumber."""
 
-    def __init__(self, mesh, k, ktilde, near_factor=2.0, eta=efie.ETA0, far3=None):
-        """far3: ratio of the distance-adaptive far rule, for both operators (the
-        barycentric one measured in its own triangles' edges); None: off."""
+    def __init__(self, mesh, k, ktilde, near_factor=2.0, eta=efie.ETA0, far3=None, far3_bary="primal"):
+        """far3: ratio of the distance-adaptive far rule of the primal operator (None:
+        off); far3_bary: that of the barycentric operator, measured in its own
+        triangles' edges ("primal": the same as far3)."""
         self.mesh = mesh
         xyz, tri = barycentric_refinement(mesh)
         self.bary = rwg.build(xyz, tri)
         self.R = bc_coefficients(mesh, self.bary)
         self.G = mixed_gram(mesh, self.bary, self.R)
         self.Z = efie.assemble(mesh, k, near_factor=near_factor, eta=eta, far3=far3)
-        self.Zb = efie.assemble(self.bary, ktilde, near_factor=near_factor, eta=eta, far3=far3)
+        fb = far3 if isinstance(far3_bary, str) else far3_bary
+        self.Zb = efie.assemble(self.bary, ktilde, near_factor=near_factor, eta=eta, far3=fb)
         self.Tbc = self.R.T @ self.Zb @ self.R
         self.P = self.Tbc @ np.linalg.inv(self.G)      # second operator times the Gram inverse
         self.M = self.P @ self.Z

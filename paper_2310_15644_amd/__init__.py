@@ -43,7 +43,7 @@ EXPORTED = [
     "efie_gemm_variants", "efie_gemm_variant_info", "efie_gemm_autotune", "efie_gemm_select",
     "efie_zx_flush64_workspace_size", "efie_zx_flush64",
     "efie_calderon_create", "efie_calderon_destroy", "efie_calderon_sizes", "efie_calderon_upload",
-    "efie_calderon_host_matrices", "efie_calderon_assemble", "efie_solve_precond_workspace_size", "efie_solve_precond",
+    "efie_calderon_host_matrices", "efie_calderon_assemble", "efie_calderon_set_far_rule", "efie_solve_precond_workspace_size", "efie_solve_precond",
     "efie_batch_create", "efie_batch_destroy", "efie_batch_sizes", "efie_batch_upload", "efie_batch_assemble",
     "efie_batch_solve", "efie_farfield_adjoint", "efie_vertex_grad_workspace_size", "efie_vertex_grad",
     "efie_assemble_workspace_size", "efie_assemble_ws", "efie_calderon_assemble_ex", "efie_solve_precond_ex",
@@ -116,6 +116,7 @@ def lib():
                                  ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "efie_calderon_upload": ([P, P, ctypes.c_size_t, P], ctypes.c_int),
         "efie_calderon_host_matrices": ([P, P, P], ctypes.c_int),
+        "efie_calderon_set_far_rule": ([P, D], ctypes.c_int),
         "efie_calderon_assemble": ([P, D, D, D, P, P, D, I32, ctypes.POINTER(D), P, ctypes.c_size_t, P], ctypes.c_int),
         "efie_calderon_assemble_ex": ([P, D, D, D, ctypes.c_int, P, P, D, I32, ctypes.POINTER(D), P, ctypes.c_size_t,
                                        P], ctypes.c_int),
@@ -581,6 +582,12 @@ class Calderon:
         _check(L.efie_calderon_sizes(h, ctypes.byref(nb), ctypes.byref(tb), ctypes.byref(tbytes), ctypes.byref(wbytes)))
         self.n_bary, self.t_bary, self.table_bytes, self.ws_bytes = nb.value, tb.value, tbytes.value, wbytes.value
         self._dev = None
+
+    def set_far_rule(self, ratio: float = -1.0):
+        """Far rule of the barycentric operator alone (ratio >= 0; see Mesh.set_far_rule);
+        ratio < 0: follow the primal mesh's rule (the default)."""
+        _check(lib().efie_calderon_set_far_rule(self._h, float(ratio)))
+        return self
 
     def host_matrices(self):
         """Dense (R: N_bary x N, G_mix: N x N) host copies (small meshes)."""

@@ -6,6 +6,7 @@
 struct efie_calderon_s {
     const efie_mesh_s* primal = nullptr;
     efie_mesh_s bary;                        // barycentric refinement (its own device tables)
+    double far3 = -1.0;                      // far rule of the barycentric operator (< 0: the primal's)
     int64_t N = 0;
     // R: Buffa-Christiansen coefficients, CSC by BC function n (rows: barycentric RWGs)
     std::vector<int32_t> r_ptr, r_idx;

@@ -712,6 +712,14 @@ int efie_calderon_create(efie_mesh mesh, efie_calderon* out) {
 
 void efie_calderon_destroy(efie_calderon c) { delete c; }
 
+int efie_calderon_set_far_rule(efie_calderon c, double ratio) {
+    return efie::guarded([&]() {
+        EFIE_REQUIRE(c != nullptr && std::isfinite(ratio), EFIE_ERR_ARG, "calderon_set_far_rule: bad argument");
+        c->far3 = ratio < 0.0 ? -1.0 : ratio;
+        return int(EFIE_OK);
+    });
+}
+
 int efie_calderon_sizes(efie_calderon c, int64_t* n_bary_rwg, int64_t* n_bary_tri, size_t* table_bytes,
                         size_t* ws_bytes) {
     return efie::guarded([&]() {
@@ -798,9 +806,10 @@ int efie_calderon_assemble_ex(efie_calderon c, double kt_re, double kt_im, doubl
         static_assert(BC_BLOCK == 256, "one thread per BC function of a run");
         EFIE_REQUIRE(c->u_max <= BC_UMAX, EFIE_ERR_STATE, "calderon_assemble: BC run lists too long");
         const unsigned nruns = unsigned(c->run_t0.size() - 1);
-        // the barycentric operator follows the primal mesh's far rule
-        c->bary.far3 = c->primal->far3;
-        c->bary.dm.far3 = c->primal->far3;
+        // the barycentric operator's far rule: its own, else the primal mesh's
+        const double f3 = c->far3 >= 0.0 ? c->far3 : c->primal->far3;
+        c->bary.far3 = f3;
+        c->bary.dm.far3 = f3;
         for (int ch = 0; ch < pl.nchunks; ++ch) {
             const int c0 = ch * pl.chunk, c1 = std::min(Tb, c0 + pl.chunk), np = c1 - c0;
             pair_rows_chunk(c->bary.dm, kt_re, kt_im, eta, bary_dtype, w.W, c0, c1, c->bary.near_p, true, stream);

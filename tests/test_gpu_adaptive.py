@@ -112,6 +112,27 @@ def test_far_rule_calderon_l1(dev):
     assert rel_max(Pm.cpu().numpy(), C.P) <= 1e-10
 
 
+def test_calderon_own_far_rule_l1(dev):
+    """A rule for the barycentric operator alone: T_BC and P follow it, Z does not."""
+    flush("calderon own far rule L1")
+    k = 1.0
+    kt = P.ktilde(k)
+    v, f = icosphere(1)
+    m = P.Mesh(v, f).upload(dev)
+    cal = P.Calderon(m).upload(dev).set_far_rule(2.5)
+    Pm, Tbc = cal.assemble(kt, with_tbc=True)
+    C = ocal.Calderon(oracle_mesh(1), k, kt, far3=None, far3_bary=2.5)
+    assert rel_max(Tbc.cpu().numpy(), C.Tbc) <= 1e-11
+    assert rel_max(Pm.cpu().numpy(), C.P) <= 1e-10
+    assert rel_max(P.assemble(m, k).cpu().numpy(), oefie.assemble(oracle_mesh(1), k)) <= 1e-11
+    # back to following the primal mesh (7x7 here)
+    cal.set_far_rule(-1.0)
+    _, Tbc7 = cal.assemble(kt, with_tbc=True)
+    assert rel_max(Tbc7.cpu().numpy(), ocal.Calderon(oracle_mesh(1), k, kt).Tbc) <= 1e-11
+    with pytest.raises(P.EfieError):
+        cal.set_far_rule(float("nan"))
+
+
 def test_far_rule_rejected_by_gradient_and_batch(dev):
     m = far_mesh(1, 3.0, dev)
     n = m.n
