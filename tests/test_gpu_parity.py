@@ -142,6 +142,26 @@ def test_assemble_l4_sampled_rows(dev, k):
     assert np.abs(blk - blk.T).max() <= 1e-14 * np.abs(blk).max()
 
 
+def test_assemble_l5_sampled_entries_c64(dev):
+    """Full size (level 5, N = 30720, k = 10), complex64 two-pass assembly as the
+    bench runs it: sampled entries, the diagonal and a near pair among them,
+    against the oracle's, one by one."""
+    flush("assemble L5 c64 sampled entries")
+    v, f = icosphere(5)
+    m = gmesh(v, f, dev)
+    Zg = P.assemble(m, 10.0, dtype=P.C64)
+    zmax = float(Zg.abs().max())
+    rng = np.random.default_rng(23)
+    pairs = [(int(a), int(b)) for a, b in rng.integers(0, m.n, size=(12, 2))] + [(7, 7), (30719, 30719), (200, 201)]
+    ref = oefie.z_entries(oracle_mesh(5), 10.0, pairs)
+    got = np.array([complex(Zg[a, b]) for a, b in pairs])
+    err = np.abs(got - ref).max() / zmax
+    flush(f"  max err / max|Z| {err:.3e}")
+    assert err <= 2e-5
+    assert abs(complex(Zg[5, 9000]) - complex(Zg[9000, 5])) <= 1e-7 * zmax
+    del Zg
+
+
 # ------------------------------------------------------- excitation / far field
 def test_excitation_l2(dev):
     v, f = icosphere(2)
