@@ -1,0 +1,57 @@
+"""Host logic of bench.py (no GPU): the one-GPU guard, the comment-insensitive hash
+that ties the committed HBM-traffic counters to the GEMM code, the lookup of those
+counters, and the far-rule pair fraction against the oracle's classification."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+import synth
+from oracle import efie, rwg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_gemm_hash_ignores_comments_and_whitespace(tmp_path):
+    src = open(bench.GEMM_SOURCE).read()
+    a = tmp_path / "a.hip"
+    b = tmp_path / "b.hip"
+    a.write_text(src)
+    b.write_text("// a new comment line\n" + src.replace("\n", "\n  "))
+    assert bench.gemm_code_sha256(str(a)) == bench.gemm_code_sha256(str(b)) == bench.gemm_code_sha256()
+    c = tmp_path / "c.hip"
+    c.write_text(src.replace("constexpr int AS = KC + 2;", "constexpr int AS = KC + 3;", 1))
+    assert bench.gemm_code_sha256(str(c)) != bench.gemm_code_sha256()
+
+
+def test_committed_traffic_matches_the_current_gemm():
+    """The committed counters belong to the current GEMM code (else the bench line
+    would report traffic null): one entry for the FP64-flush tile the tuner picks."""
+    t, src = bench.measured_traffic([64, 32, 32], True, 30720, 512, "calderon")
+    assert src is not None and 7.9e9 < t < 1e12
+    assert bench.measured_traffic([64, 128, 16], True, 30720, 512, "calderon") == (None, None)
+    assert bench.measured_traffic([64, 32, 32], True, 7680, 512, "calderon") == (None, None)
+
+
+def test_far3_fraction_matches_oracle_classification():
+    v, f = synth.icosphere(2)
+    m = rwg.build(v, f)
+    n3 = nfar = 0
+    for p in range(m.t):
+        d = m.centroid - m.centroid[p]
+        d2 = (d * d).sum(-1)
+        hm = np.maximum(m.hmax, m.hmax[p])
+        n3 += int(efie.far3_row(m, p, 3.0).sum())
+        nfar += int(np.count_nonzero(d2 >= (2.0 * hm) ** 2))
+    got = bench.far3_fraction(np.asarray(v, dtype=np.float64), np.asarray(f), 3.0)
+    assert abs(got - n3 / nfar) < 1e-12
