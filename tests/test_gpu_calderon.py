@@ -139,3 +139,34 @@ def test_calderon_c64_bary_and_mixed_solve(dev, fp32_acc):
     err = float((torch.linalg.norm(J32 - J64, dim=1) / torch.linalg.norm(J64, dim=1)).max())
     flush(f"  mixed vs FP64 currents: {err:.2e}")
     assert err <= 1e-4
+
+
+def test_calderon_l5_gram_solve_as_benched(dev):
+    """Level 5 (N = 30720) in the bench's configuration: FP32 barycentric pairs with
+    the far rule at ratio 4, Gram solve to 1e-3 with complex64 vectors in six column
+    batches (the last ragged: 4510 columns).  Property at full size: sampled rows of
+    P G_mix reproduce T_BC within the solve's tolerance (P = T_BC G_mix^-1, so row s
+    of P G_mix is row s of T_BC; G_mix from the host tables, independent of the
+    device Gram products), and the reported worst residual bounds them."""
+    flush("calderon L5 Gram solve as benched")
+    import ctypes
+    k = 10.0
+    v, f = icosphere(5)
+    m = P.Mesh(v, f).upload(dev)
+    cal = P.Calderon(m).upload(dev).set_far_rule(4.0)
+    Pm, Tbc = cal.assemble(P.ktilde(k), tol=1e-3, bary_dtype=P.C64, with_tbc=True)
+    flush(f"  gram relres {cal.gram_relres:.2e}")
+    assert 0.0 < cal.gram_relres <= 1e-3
+    n = m.n
+    G = np.zeros((n, n))
+    assert P.lib().efie_calderon_host_matrices(cal._h, None, ctypes.c_void_p(G.ctypes.data)) == 0
+    rng = np.random.default_rng(3)
+    rows = sorted(set(rng.integers(0, n, 10).tolist()) | {0, 26209, 26210, n - 1})   # batch edges and the tail
+    Gd = torch.from_numpy(G).to(dev)
+    del G
+    got = Pm[rows] @ Gd.to(torch.complex128)
+    ref = Tbc[rows]
+    rel = ((got - ref).norm(dim=1) / ref.norm(dim=1)).cpu().numpy()
+    flush(f"  sampled rows: max ||(P G - T_BC)_s|| / ||T_BC_s|| = {rel.max():.2e}")
+    assert rel.max() <= 1.2e-3
+    del Gd, Pm, Tbc, got
