@@ -35,7 +35,9 @@ struct efie_calderon_s {
 
 namespace efie {
 constexpr int BC_BLOCK = 256;   // BC functions per block of the source-side contraction
-constexpr int BC_UMAX = 2304;   // distinct barycentric RWGs per block (its LDS list)
+// distinct barycentric RWGs per block (its LDS list): a run closes when its next
+// BC function would exceed it, so at level 5 runs hold about 140 functions
+constexpr int BC_UMAX = 1024;
 bool verbose();
 void build_calderon(efie_calderon_s& C, const efie_mesh_s& primal);
 }  // namespace efie

@@ -145,10 +145,12 @@ __global__ __launch_bounds__(256) void bc_src_kernel(DevCald c, const C2* __rest
     for (int u = 0; u < RRL; ++u)
         if (r0 + u < nrows) Yw[size_t(r0 + u) * c.N + n] = make_double2(ar[u], ai[u]);
 }
-// rows per block: 144 KB of LDS either way (one block per CU); more rows amortize
-// the run's list and index loads (level 5, complex64: 2 / 4 / 6 / 8 rows per block
-// built P in 2.16 / 1.65 / 1.60 / 1.54 s)
-constexpr int BC_RRL32 = 8, BC_RRL64 = 4;
+// rows per block x list bound: 10 x 1024 complex64 (80 KB of LDS) lets two blocks
+// share a CU, one computing while the other loads, and still amortizes the run's
+// list and index loads over 10 rows (level 5, source-side contraction per P
+// build: 429 ms with 8 x 2304 and one block per CU; 387 / 392 / 406 / 455 / 470 ms
+// with 10 x 1024, 8 x 768, 12 x 768, 6 x 1024, 16 x 512)
+constexpr int BC_RRL32 = 10, BC_RRL64 = 4;
 
 // Tbc[m][n] += sum_k coef[k] Yw[rows[k]][n] over the list of BC row m = ml[blockIdx.y]
 __global__ __launch_bounds__(256) void bc_test_kernel(const int32_t* __restrict__ ml, const int32_t* __restrict__ mptr,
