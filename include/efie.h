@@ -143,9 +143,11 @@ int efie_assemble(efie_mesh mesh, double k_re, double k_im, double eta, int dtyp
                   void* Z, void* Z2, int parts, hipStream_t stream);
 
 /*
- * The same Z as efie_assemble (parts = 0) without atomics: the far-pair values are
- * written per chunk of test triangles into the caller's workspace and then added
- * row by row, so the result is deterministic (bit-identical between runs).  Any
+ * The same Z as efie_assemble (parts = 0) without atomics: the pair values of the
+ * triangle pairs with source triangle q >= p (q = p halved) are written per chunk
+ * of test triangles into the caller's workspace and added row by row into U, and
+ * Z = U + U^T by mirror tiles, so the result is deterministic (bit-identical
+ * between runs) and exactly symmetric.  Any
  * ws_bytes >= min_bytes works (chunks of ws_bytes / min_bytes test triangles);
  * full_bytes (= T x min_bytes) holds all triangles in one chunk.
  *   min_bytes = 6 N x (16 for EFIE_C128, 8 for EFIE_C64);  ws dev, 16-byte aligned.

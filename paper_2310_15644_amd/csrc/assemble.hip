@@ -17,19 +17,22 @@
 // The test triangle is uniform over a block (scalar loads), the source triangle
 // varies across lanes (coalesced structure-of-arrays loads).
 //
-// Without atomics (efie_assemble_ws): the nine values of every pair are first
-// written, per chunk of test triangles p, to a caller workspace laid out as
+// Without atomics (efie_assemble_ws): the operator is symmetric, so only the
+// pairs with source triangle q >= p are evaluated (the pair q = p halved): their
+// nine values go, per chunk of test triangles p, to a caller workspace laid out as
 //   W[p][i][n][side]   (test edge i of p, source RWG n, side 0/1: the source
 //                       triangle is n's T+ / T-),
-// each entry written exactly once (far pairs by far_rows_kernel, which writes zeros
-// for near pairs, then near pairs in FP64 by near_rows_kernel), with the blocks of
-// one test triangle kept on one XCD so that its rows are completed in one L2; then one
-// block per RWG row m adds the rows of its triangles in the chunk,
-//   Z[m][n] += sum_{p in {T+(m), T-(m)} in chunk} (W[p][i_p][n][0] + W[p][i_p][n][1]),
-// with coalesced reads and writes.  No atomics anywhere and a fixed sum order, so
-// the result is deterministic; the atomic path's scattered read-modify-writes of
-// Z, which cost ten times the arithmetic of the complex64 kernel, are gone
-// (level 5, complex64: 160 ms -> 33 ms).
+// (far pairs q > p by far_rows_kernel<UPPER>, near pairs q >= p in FP64 by
+// near_rows_kernel; entries of triangles q < p are never written), with the blocks
+// of one test triangle kept on one XCD so that its rows are completed in one L2;
+// then one block per RWG row m adds the written entries of its triangles' rows,
+//   U[m][n] += sum_{p in {T+(m), T-(m)} in chunk} sum_{t: T_t(n) >= p} W[p][i_p][n][t],
+// with coalesced reads and writes, and at the end Z = U + U^T by pairs of mirror
+// 32 x 32 tiles.  No atomics anywhere and a fixed sum order, so the result is
+// deterministic and exactly symmetric; the atomic path's scattered
+// read-modify-writes of Z, which cost ten times the arithmetic of the complex64
+// kernel, are gone (level 5, complex64: 160 ms -> 33 ms with every pair, 24 ms
+// with the pairs q >= p and the mirror).
 //
 // Near pairs (near mask bit set) are skipped by the far kernel and handled by
 // near_pairs_kernel in FP64: the smooth part (exp(-jkR)-1)/(4 pi R) with the same
@@ -143,8 +146,11 @@ __global__ __launch_bounds__(128) void near_rows_kernel(DevMesh m, double kr, do
 
 // pass 2: block = (test triangle p of the chunk, local edge i) -> RWG row mm; the
 // block of mm's T+ adds both triangles' rows when both are in the chunk, so every
-// row is updated by one block per chunk
-template <typename R>
+// row is updated by one block per chunk.  UPPER: the rows hold the pairs with
+// source triangle q >= p only (q = p halved); side t of RWG n enters the row of
+// test triangle p only where its triangle et[t N + n] >= p, and the result is the
+// U of Z = U + U^T
+template <typename R, bool UPPER>
 __global__ __launch_bounds__(256) void gather_rows_kernel(DevMesh m, const typename Cplx<R>::T* __restrict__ W,
                                                           int c0, int c1, typename Cplx<R>::T* __restrict__ Z) {
     using C2 = typename Cplx<R>::T;
@@ -172,8 +178,17 @@ __global__ __launch_bounds__(256) void gather_rows_kernel(DevMesh m, const typen
             const int n = n0 + u * int(blockDim.x);
             if (n < N) {
                 acc[u] = first ? C2{0, 0} : zr[n];
-                if (wp) { a[u] = wp[2 * n]; b[u] = wp[2 * n + 1]; }
-                if (wm) { c[u] = wm[2 * n]; d[u] = wm[2 * n + 1]; }
+                if (UPPER) {
+                    const int s0 = m.et[n], s1 = m.et[N + n];   // source triangles of the two sides
+                    a[u] = b[u] = c[u] = d[u] = C2{0, 0};
+                    if (wp && s0 >= tp) a[u] = wp[2 * n];
+                    if (wp && s1 >= tp) b[u] = wp[2 * n + 1];
+                    if (wm && s0 >= tm) c[u] = wm[2 * n];
+                    if (wm && s1 >= tm) d[u] = wm[2 * n + 1];
+                } else {
+                    if (wp) { a[u] = wp[2 * n]; b[u] = wp[2 * n + 1]; }
+                    if (wm) { c[u] = wm[2 * n]; d[u] = wm[2 * n + 1]; }
+                }
             }
         }
 #pragma unroll
@@ -183,6 +198,46 @@ __global__ __launch_bounds__(256) void gather_rows_kernel(DevMesh m, const typen
                 if (wp) { acc[u].x += a[u].x + b[u].x; acc[u].y += a[u].y + b[u].y; }
                 if (wm) { acc[u].x += c[u].x + d[u].x; acc[u].y += c[u].y + d[u].y; }
                 zr[n] = acc[u];
+            }
+        }
+    }
+}
+
+// Z <- Z + Z^T in place (N x N): one block per pair of mirror 32 x 32 tiles
+// (bi <= bj, numbered row by row of the upper triangle of tiles), both read into
+// LDS before either is written
+template <typename C2>
+__global__ __launch_bounds__(256) void mirror_add_kernel(C2* __restrict__ Z, int N, int nt) {
+    __shared__ C2 a[32][33], b[32][33];
+    // tile row bi starts at S(bi) = bi nt - bi (bi - 1) / 2: the root of S(r) = k,
+    // corrected for its rounding
+    const long long k = blockIdx.x;
+    auto S = [&](long long r) { return r * nt - r * (r - 1) / 2; };
+    const double b2 = 2.0 * nt + 1.0;
+    long long bi = (long long)((b2 - sqrt(b2 * b2 - 8.0 * double(k))) * 0.5);
+    bi = bi < 0 ? 0 : (bi > nt - 1 ? nt - 1 : bi);
+    while (bi > 0 && S(bi) > k) --bi;
+    while (bi + 1 < nt && S(bi + 1) <= k) ++bi;
+    const int bj = int(bi + (k - S(bi)));
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+    for (int r = ty; r < 32; r += 8) {
+        const int i = int(bi) * 32 + r, j = bj * 32 + tx;
+        const int i2 = bj * 32 + r, j2 = int(bi) * 32 + tx;
+        if (i < N && j < N) a[r][tx] = Z[size_t(i) * N + j];
+        if (i2 < N && j2 < N) b[r][tx] = Z[size_t(i2) * N + j2];
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int i = int(bi) * 32 + r, j = bj * 32 + tx;
+        if (i < N && j < N) {   // (i, j) += (j, i): element (r, tx) of a plus element (tx, r) of b
+            const C2 u = a[r][tx], v = b[tx][r];
+            Z[size_t(i) * N + j] = C2{u.x + v.x, u.y + v.y};
+        }
+        if (bi != bj) {
+            const int i2 = bj * 32 + r, j2 = int(bi) * 32 + tx;
+            if (i2 < N && j2 < N) {
+                const C2 u = b[r][tx], v = a[tx][r];
+                Z[size_t(i2) * N + j2] = C2{u.x + v.x, u.y + v.y};
             }
         }
     }
@@ -252,19 +307,28 @@ void launch_far_rows(const DevMesh& m, double kr, double ki, const Scale& sc, vo
     for (int c0 = 0; c0 < m.T; c0 += chunk) {
         const int c1 = std::min(m.T, c0 + chunk), np = c1 - c0;
         const dim3 g1(unsigned(size_t(np) * nqblk));
+        // pairs with source triangle q >= p only (the operator is symmetric): the
+        // chunks build U with Z = U + U^T
         if (ck)
-            hipLaunchKernelGGL((far_rows_kernel<R, true, false>), g1, dim3(FAR_BLOCK), 0, s, m, tables<R>(m), kphase,
+            hipLaunchKernelGGL((far_rows_kernel<R, true, true>), g1, dim3(FAR_BLOCK), 0, s, m, tables<R>(m), kphase,
                                R(ki), sc, W, c0, nqblk);
         else
-            hipLaunchKernelGGL((far_rows_kernel<R, false, false>), g1, dim3(FAR_BLOCK), 0, s, m, tables<R>(m), kphase,
+            hipLaunchKernelGGL((far_rows_kernel<R, false, true>), g1, dim3(FAR_BLOCK), 0, s, m, tables<R>(m), kphase,
                                R(ki), sc, W, c0, nqblk);
         const int e0 = int(std::lower_bound(near_p.begin(), near_p.end(), c0) - near_p.begin());
         const int e1 = int(std::lower_bound(near_p.begin(), near_p.end(), c1) - near_p.begin());
         if (e1 > e0)
             hipLaunchKernelGGL((near_rows_kernel<R>), dim3((e1 - e0 + 127) / 128), dim3(128), 0, s, m, kr, ki, sc, W,
-                               c0, c1, e0, e1, 0);
-        hipLaunchKernelGGL((gather_rows_kernel<R>), dim3(unsigned(3 * np)), dim3(256), 0, s, m, W, c0, c1,
+                               c0, c1, e0, e1, 1);
+        hipLaunchKernelGGL((gather_rows_kernel<R, true>), dim3(unsigned(3 * np)), dim3(256), 0, s, m, W, c0, c1,
                            static_cast<C2*>(Z));
+    }
+    {
+        const int nt = (m.N + 31) / 32;
+        const size_t npairs = size_t(nt) * size_t(nt + 1) / 2;
+        EFIE_REQUIRE(npairs < (size_t(1) << 31), EFIE_ERR_ARG, "assemble_ws: N too large");
+        hipLaunchKernelGGL((mirror_add_kernel<C2>), dim3(unsigned(npairs)), dim3(256), 0, s, static_cast<C2*>(Z),
+                           m.N, nt);
     }
     prof_end(PROF_FAR, s);
 }
