@@ -86,36 +86,43 @@ struct Cplx<double> {
 // from the symmetry of the operator).
 template <typename R, bool CK, bool UPPER>
 __global__ __launch_bounds__(FAR_BLOCK) void far_rows_kernel(DevMesh m, Tables<R> tb, R kphase, R ki, Scale sc,
-                                                             typename Cplx<R>::T* __restrict__ W, int c0, int nqblk) {
+                                                             typename Cplx<R>::T* __restrict__ W, int c0, int np,
+                                                             int nqblk) {
     using C2 = typename Cplx<R>::T;
     // blocks are dealt to the 8 XCDs round-robin: remap so that each XCD runs the
-    // blocks of consecutive test triangles, all blocks of one triangle together
+    // blocks of consecutive test triangles, all blocks of one group together.  A
+    // block takes FAR_PB test triangles against its FAR_BLOCK source triangles: the
+    // source triangles' tables, read for the first, are cache hits for the others
+    // (one triangle per block re-read them from memory for every test triangle)
     const int nblk = int(gridDim.x);
     const int xcd = int(blockIdx.x) & 7, idx = int(blockIdx.x) >> 3;
     const int per = nblk >> 3, rem = nblk & 7;
     const int logical = xcd * per + min(xcd, rem) + idx;
-    const int pl = logical / nqblk, qb = logical - pl * nqblk;
-    const int p = c0 + pl;
+    const int pg = logical / nqblk, qb = logical - pg * nqblk;
     const int q = qb * FAR_BLOCK + threadIdx.x;
     const int T = m.T;
     if (q >= T) return;
     const size_t N = size_t(m.N);
-    C2* rows = W + size_t(pl) * 3 * 2 * N;
-    auto put = [&](int i, int j, R re, R im) {
-        const size_t n = size_t(m.te[j * T + q]);
-        const int side = tb.cf[j * T + q] > R(0) ? 0 : 1;
-        rows[(size_t(i) * N + n) * 2 + side] = C2{re, im};
-    };
-    const bool near = (m.near_mask[size_t(p) * m.nqb + (q >> 6)] >> (q & 63)) & 1ull;
-    if (UPPER && (q < p || near)) return;
-    if (near) {
+    const int pl1 = min(np, (pg + 1) * FAR_PB);
+    for (int pl = pg * FAR_PB; pl < pl1; ++pl) {
+        const int p = c0 + pl;
+        C2* rows = W + size_t(pl) * 3 * 2 * N;
+        auto put = [&](int i, int j, R re, R im) {
+            const size_t n = size_t(m.te[j * T + q]);
+            const int side = tb.cf[j * T + q] > R(0) ? 0 : 1;
+            rows[(size_t(i) * N + n) * 2 + side] = C2{re, im};
+        };
+        const bool near = (m.near_mask[size_t(p) * m.nqb + (q >> 6)] >> (q & 63)) & 1ull;
+        if (UPPER && (q < p || near)) continue;
+        if (near) {
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
+            for (int i = 0; i < 3; ++i)
 #pragma unroll
-            for (int j = 0; j < 3; ++j) put(i, j, R(0), R(0));
-        return;
+                for (int j = 0; j < 3; ++j) put(i, j, R(0), R(0));
+            continue;
+        }
+        far_pair_emit<R, CK, false>(m, tb, p, q, kphase, ki, sc, put, put);
     }
-    far_pair_emit<R, CK, false>(m, tb, p, q, kphase, ki, sc, put, put);
 }
 
 // near pairs (p, q) with p in the chunk: their values replace the zeros pass 1
@@ -306,15 +313,15 @@ void launch_far_rows(const DevMesh& m, double kr, double ki, const Scale& sc, vo
     prof_begin(PROF_FAR, s);
     for (int c0 = 0; c0 < m.T; c0 += chunk) {
         const int c1 = std::min(m.T, c0 + chunk), np = c1 - c0;
-        const dim3 g1(unsigned(size_t(np) * nqblk));
+        const dim3 g1(unsigned(size_t((np + FAR_PB - 1) / FAR_PB) * nqblk));
         // pairs with source triangle q >= p only (the operator is symmetric): the
         // chunks build U with Z = U + U^T
         if (ck)
             hipLaunchKernelGGL((far_rows_kernel<R, true, true>), g1, dim3(FAR_BLOCK), 0, s, m, tables<R>(m), kphase,
-                               R(ki), sc, W, c0, nqblk);
+                               R(ki), sc, W, c0, np, nqblk);
         else
             hipLaunchKernelGGL((far_rows_kernel<R, false, true>), g1, dim3(FAR_BLOCK), 0, s, m, tables<R>(m), kphase,
-                               R(ki), sc, W, c0, nqblk);
+                               R(ki), sc, W, c0, np, nqblk);
         const int e0 = int(std::lower_bound(near_p.begin(), near_p.end(), c0) - near_p.begin());
         const int e1 = int(std::lower_bound(near_p.begin(), near_p.end(), c1) - near_p.begin());
         if (e1 > e0)
@@ -371,7 +378,7 @@ void pair_rows_chunk(const DevMesh& m, double kr, double ki, double eta, int dty
     const int np = c1 - c0;
     EFIE_REQUIRE(np >= 1 && size_t(np) * nqblk < (size_t(1) << 31), EFIE_ERR_ARG, "pair_rows_chunk: bad chunk");
     const bool ck = ki != 0.0;
-    const dim3 g1(unsigned(size_t(np) * nqblk));
+    const dim3 g1(unsigned(size_t((np + FAR_PB - 1) / FAR_PB) * nqblk));
     const int e0 = int(std::lower_bound(near_p.begin(), near_p.end(), c0) - near_p.begin());
     const int e1 = int(std::lower_bound(near_p.begin(), near_p.end(), c1) - near_p.begin());
     auto run = [&](auto tag) {
@@ -381,16 +388,16 @@ void pair_rows_chunk(const DevMesh& m, double kr, double ki, double eta, int dty
         C2* w = static_cast<C2*>(W);
         if (ck && upper)
             hipLaunchKernelGGL((far_rows_kernel<R, true, true>), g1, dim3(FAR_BLOCK), 0, s, m, tables<R>(m), kphase,
-                               R(ki), sc, w, c0, nqblk);
+                               R(ki), sc, w, c0, np, nqblk);
         else if (ck)
             hipLaunchKernelGGL((far_rows_kernel<R, true, false>), g1, dim3(FAR_BLOCK), 0, s, m, tables<R>(m), kphase,
-                               R(ki), sc, w, c0, nqblk);
+                               R(ki), sc, w, c0, np, nqblk);
         else if (upper)
             hipLaunchKernelGGL((far_rows_kernel<R, false, true>), g1, dim3(FAR_BLOCK), 0, s, m, tables<R>(m), kphase,
-                               R(ki), sc, w, c0, nqblk);
+                               R(ki), sc, w, c0, np, nqblk);
         else
             hipLaunchKernelGGL((far_rows_kernel<R, false, false>), g1, dim3(FAR_BLOCK), 0, s, m, tables<R>(m), kphase,
-                               R(ki), sc, w, c0, nqblk);
+                               R(ki), sc, w, c0, np, nqblk);
         if (e1 > e0)
             hipLaunchKernelGGL((near_rows_kernel<R>), dim3((e1 - e0 + 127) / 128), dim3(128), 0, s, m, kr, ki, sc, w,
                                c0, c1, e0, e1, int(upper));

@@ -14,6 +14,7 @@ namespace efie {
 
 constexpr double PI = 3.14159265358979323846;
 constexpr int FAR_BLOCK = 256;
+constexpr int FAR_PB = 4;   // test triangles per block of the row-building far kernel
 
 struct Scale {          // Z contribution = A * T_A + P * T_Phi (complex), or parts mode
     double ar, ai, pr, pi;
