@@ -93,18 +93,21 @@ def test_assemble_near_factor(dev, nf):
     assert rel_max(Zg, oefie.assemble(oracle_mesh(1), 2.0, near_factor=nf)) <= 1e-11
 
 
+@pytest.mark.parametrize("per", [7, 1])
 @pytest.mark.parametrize("dt", ["c128", "c64"])
-def test_assemble_two_pass_vs_atomic(dev, dt):
-    """The atomic-free path in many chunks (7 test triangles each, ragged last chunk)
-    against the atomic path, and bit-identical when repeated."""
-    flush(f"assemble two-pass vs atomic {dt}")
+def test_assemble_two_pass_vs_atomic(dev, dt, per):
+    """The atomic-free path in many chunks (`per` test triangles each, ragged last
+    chunk; the far kernel takes test triangles four to a block, so 7 leaves a group
+    of three and 1 a group of one) against the atomic path, and bit-identical when
+    repeated."""
+    flush(f"assemble two-pass vs atomic {dt} per={per}")
     v, f = icosphere(2)
     m = gmesh(v, f, dev)
     code = P.C128 if dt == "c128" else P.C64
     lo, full = ctypes.c_size_t(), ctypes.c_size_t()
     assert P.lib().efie_assemble_workspace_size(m._h, code, ctypes.byref(lo), ctypes.byref(full)) == 0
     assert lo.value == 6 * m.n * (16 if dt == "c128" else 8) and full.value == m.t * lo.value
-    wsb = 7 * lo.value + lo.value // 2
+    wsb = per * lo.value + lo.value // 2
     Za = P.assemble(m, 2.0, dtype=code, atomic=True).cpu().numpy()
     Z1 = P.assemble(m, 2.0, dtype=code, workspace_bytes=wsb).cpu().numpy()
     Z2 = P.assemble(m, 2.0, dtype=code, workspace_bytes=wsb).cpu().numpy()
