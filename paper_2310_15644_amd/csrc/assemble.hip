@@ -295,6 +295,45 @@ void launch_far(const DevMesh& m, double kr, double ki, const Scale& sc, void* Z
     prof_end(PROF_FAR, s);
 }
 
+// With the pairs q >= p only, the far kernel leaves the entries of near pairs
+// alone, so a chunk's near pairs (few, long-running threads) run beside its far
+// pairs on a second stream: forked from the caller's stream before the far kernel,
+// so that they follow whatever read the workspace before, and joined before
+// anything reads the chunk's rows.  One side stream and event pair per host thread
+// and device, created on first use and kept until the process ends.
+struct SideStream {
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+
+static SideStream& side_stream() {
+    constexpr int MAXDEV = 64;
+    thread_local SideStream ss[MAXDEV];
+    int dev = 0;
+    EFIE_HIP_CHECK(hipGetDevice(&dev));
+    EFIE_REQUIRE(dev >= 0 && dev < MAXDEV, EFIE_ERR_STATE, "side stream: device index out of range");
+    SideStream& x = ss[dev];
+    if (!x.s) {
+        EFIE_HIP_CHECK(hipStreamCreateWithFlags(&x.s, hipStreamNonBlocking));
+        EFIE_HIP_CHECK(hipEventCreateWithFlags(&x.fork, hipEventDisableTiming));
+        EFIE_HIP_CHECK(hipEventCreateWithFlags(&x.join, hipEventDisableTiming));
+    }
+    return x;
+}
+
+// launch near(stream) beside far(stream) as above; returns after both are enqueued,
+// with the caller's stream s waiting for the near pairs
+template <typename NearF, typename FarF>
+static void near_beside_far(hipStream_t s, NearF near, FarF far) {
+    SideStream& x = side_stream();
+    EFIE_HIP_CHECK(hipEventRecord(x.fork, s));
+    EFIE_HIP_CHECK(hipStreamWaitEvent(x.s, x.fork, 0));
+    near(x.s);
+    EFIE_HIP_CHECK(hipEventRecord(x.join, x.s));
+    far(s);
+    EFIE_HIP_CHECK(hipStreamWaitEvent(s, x.join, 0));
+}
+
 // far pairs without atomics, in chunks of test triangles that fit the workspace
 // near_p: host copy of the ordered near list's test triangles (sorted), to launch
 // only the chunk's near pairs
@@ -316,17 +355,26 @@ void launch_far_rows(const DevMesh& m, double kr, double ki, const Scale& sc, vo
         const dim3 g1(unsigned(size_t((np + FAR_PB - 1) / FAR_PB) * nqblk));
         // pairs with source triangle q >= p only (the operator is symmetric): the
         // chunks build U with Z = U + U^T
-        if (ck)
-            hipLaunchKernelGGL((far_rows_kernel<R, true, true>), g1, dim3(FAR_BLOCK), 0, s, m, tables<R>(m), kphase,
-                               R(ki), sc, W, c0, np, nqblk);
-        else
-            hipLaunchKernelGGL((far_rows_kernel<R, false, true>), g1, dim3(FAR_BLOCK), 0, s, m, tables<R>(m), kphase,
-                               R(ki), sc, W, c0, np, nqblk);
+        auto far = [&](hipStream_t st) {
+            if (ck)
+                hipLaunchKernelGGL((far_rows_kernel<R, true, true>), g1, dim3(FAR_BLOCK), 0, st, m, tables<R>(m),
+                                   kphase, R(ki), sc, W, c0, np, nqblk);
+            else
+                hipLaunchKernelGGL((far_rows_kernel<R, false, true>), g1, dim3(FAR_BLOCK), 0, st, m, tables<R>(m),
+                                   kphase, R(ki), sc, W, c0, np, nqblk);
+        };
         const int e0 = int(std::lower_bound(near_p.begin(), near_p.end(), c0) - near_p.begin());
         const int e1 = int(std::lower_bound(near_p.begin(), near_p.end(), c1) - near_p.begin());
         if (e1 > e0)
-            hipLaunchKernelGGL((near_rows_kernel<R>), dim3((e1 - e0 + 127) / 128), dim3(128), 0, s, m, kr, ki, sc, W,
-                               c0, c1, e0, e1, 1);
+            near_beside_far(
+                s,
+                [&](hipStream_t st) {
+                    hipLaunchKernelGGL((near_rows_kernel<R>), dim3((e1 - e0 + 127) / 128), dim3(128), 0, st, m, kr,
+                                       ki, sc, W, c0, c1, e0, e1, 1);
+                },
+                far);
+        else
+            far(s);
         hipLaunchKernelGGL((gather_rows_kernel<R, true>), dim3(unsigned(3 * np)), dim3(256), 0, s, m, W, c0, c1,
                            static_cast<C2*>(Z));
     }
@@ -386,21 +434,32 @@ void pair_rows_chunk(const DevMesh& m, double kr, double ki, double eta, int dty
         using C2 = typename Cplx<R>::T;
         const R kphase = std::is_same<R, float>::value ? R(kr / (2.0 * PI)) : R(kr);
         C2* w = static_cast<C2*>(W);
-        if (ck && upper)
-            hipLaunchKernelGGL((far_rows_kernel<R, true, true>), g1, dim3(FAR_BLOCK), 0, s, m, tables<R>(m), kphase,
-                               R(ki), sc, w, c0, np, nqblk);
-        else if (ck)
-            hipLaunchKernelGGL((far_rows_kernel<R, true, false>), g1, dim3(FAR_BLOCK), 0, s, m, tables<R>(m), kphase,
-                               R(ki), sc, w, c0, np, nqblk);
-        else if (upper)
-            hipLaunchKernelGGL((far_rows_kernel<R, false, true>), g1, dim3(FAR_BLOCK), 0, s, m, tables<R>(m), kphase,
-                               R(ki), sc, w, c0, np, nqblk);
-        else
-            hipLaunchKernelGGL((far_rows_kernel<R, false, false>), g1, dim3(FAR_BLOCK), 0, s, m, tables<R>(m), kphase,
-                               R(ki), sc, w, c0, np, nqblk);
-        if (e1 > e0)
-            hipLaunchKernelGGL((near_rows_kernel<R>), dim3((e1 - e0 + 127) / 128), dim3(128), 0, s, m, kr, ki, sc, w,
-                               c0, c1, e0, e1, int(upper));
+        auto far = [&](hipStream_t st) {
+            if (ck && upper)
+                hipLaunchKernelGGL((far_rows_kernel<R, true, true>), g1, dim3(FAR_BLOCK), 0, st, m, tables<R>(m),
+                                   kphase, R(ki), sc, w, c0, np, nqblk);
+            else if (ck)
+                hipLaunchKernelGGL((far_rows_kernel<R, true, false>), g1, dim3(FAR_BLOCK), 0, st, m, tables<R>(m),
+                                   kphase, R(ki), sc, w, c0, np, nqblk);
+            else if (upper)
+                hipLaunchKernelGGL((far_rows_kernel<R, false, true>), g1, dim3(FAR_BLOCK), 0, st, m, tables<R>(m),
+                                   kphase, R(ki), sc, w, c0, np, nqblk);
+            else
+                hipLaunchKernelGGL((far_rows_kernel<R, false, false>), g1, dim3(FAR_BLOCK), 0, st, m, tables<R>(m),
+                                   kphase, R(ki), sc, w, c0, np, nqblk);
+        };
+        auto near = [&](hipStream_t st) {
+            hipLaunchKernelGGL((near_rows_kernel<R>), dim3((e1 - e0 + 127) / 128), dim3(128), 0, st, m, kr, ki, sc,
+                               w, c0, c1, e0, e1, int(upper));
+        };
+        if (e1 <= e0) {
+            far(s);
+        } else if (upper) {
+            near_beside_far(s, near, far);   // disjoint entries: see near_beside_far
+        } else {
+            far(s);                          // the far kernel zeroes the near entries first
+            near(s);
+        }
     };
     if (dtype == EFIE_C64) run(float{});
     else run(double{});
