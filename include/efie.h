@@ -29,7 +29,11 @@
  *   - Z is N x N row-major; it is symmetric (Z = Z^T), so rows and columns
  *     may be exchanged freely.
  *   - Device work is enqueued on the given stream; calls that return host
- *     values synchronise that stream before returning.
+ *     values synchronise that stream before returning.  The workspace
+ *     assemblies (efie_assemble_ws, the Calderon build) also run the near
+ *     pairs of each chunk on a library-owned side stream of the current device
+ *     (default priority, one per host thread), forked from and joined back to
+ *     the given stream by events, so the call stays ordered on that stream.
  *   - Calls on one mesh handle are not thread-safe.
  */
 #ifndef EFIE_H
