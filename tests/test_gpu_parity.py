@@ -118,6 +118,41 @@ def test_assemble_two_pass_vs_atomic(dev, dt, per):
     assert np.abs(Z1 - Z1.T).max() <= tol * np.abs(Z1).max()
 
 
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_assemble_two_host_threads(dev, dt):
+    """Two host threads assemble at once, each on its own stream: the near pairs
+    run on a side stream per host thread, and both results equal the serial one
+    bit for bit."""
+    import threading
+    flush(f"assemble from two host threads {dt}")
+    v, f = icosphere(2)
+    m = gmesh(v, f, dev)
+    code = P.C128 if dt == "c128" else P.C64
+    lo, full = ctypes.c_size_t(), ctypes.c_size_t()
+    assert P.lib().efie_assemble_workspace_size(m._h, code, ctypes.byref(lo), ctypes.byref(full)) == 0
+    wsb = 7 * lo.value
+    ref = P.assemble(m, 2.0, dtype=code, workspace_bytes=wsb).cpu().numpy()
+    out, errs = [None, None], []
+
+    def work(i):
+        try:
+            st = torch.cuda.Stream(device=dev)
+            with torch.cuda.stream(st):
+                Z = P.assemble(m, 2.0, dtype=code, workspace_bytes=wsb)
+            st.synchronize()
+            out[i] = Z.cpu().numpy()
+        except Exception as e:  # reported by the main thread
+            errs.append(e)
+
+    ths = [threading.Thread(target=work, args=(i,)) for i in range(2)]
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    assert not errs, errs
+    assert np.array_equal(out[0], ref) and np.array_equal(out[1], ref)
+
+
 def test_assemble_ws_too_small(dev):
     v, f = icosphere(1)
     m = gmesh(v, f, dev)
