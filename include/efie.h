@@ -113,6 +113,18 @@ void efie_mesh_destroy(efie_mesh mesh);
  */
 int efie_mesh_set_far_rule(efie_mesh mesh, double ratio);
 
+/*
+ * Largest |Re k| accepted by the complex64 assemblies of this mesh (efie_assemble
+ * and efie_assemble_ws with EFIE_C64, the complex64 barycentric pairs of
+ * efie_calderon_assemble_ex, efie_batch_assemble with EFIE_C64).  Their FP32
+ * far-pair kernels hand the phase Re(k) R, in revolutions, to the hardware sine
+ * and cosine, whose argument must stay below 256 revolutions; R never exceeds the
+ * bounding-box diagonal D of the vertices, so the limit is 512 pi / D.  Those
+ * calls return EFIE_ERR_ARG at or beyond it, before any device work (EFIE_C128
+ * has no such limit).  Host only.  Errors: EFIE_ERR_ARG (null argument).
+ */
+int efie_mesh_fp32_kmax(efie_mesh mesh, double* kmax);
+
 /* Sizes: RWG count N, triangle count T, ordered near pairs (incl. self pairs),
  * and the byte size of the device tables required by efie_mesh_upload. */
 int efie_mesh_sizes(efie_mesh mesh, int64_t* n_rwg, int64_t* n_tri, int64_t* n_near,
@@ -271,6 +283,29 @@ int efie_gemm_autotune(const void* Z, int64_t n, const void* X, int64_t M, int a
                        size_t ws_bytes, int reps, double* ms, int* best, hipStream_t stream);
 int efie_gemm_select(int acc64, int variant, int* previous);
 
+/*
+ * The autotuner with a persistent cache of its choices.  For a Z of order n
+ * (complex64, dev) times M right-hand sides on the current device, the cache
+ * file cache_path (plain text, one line per entry: a key naming the device, n, M
+ * and the tile table, the chosen variants of the complex64-output and the
+ * FP64-flush paths, and the mean milliseconds of every variant on each path) is
+ * read; an entry with the same key is reused unless force != 0.  Otherwise both
+ * paths are timed as by efie_gemm_autotune (reps launches after a warm-up) on a
+ * seeded block X generated on the device, and the entry is added (the file is
+ * rewritten through a temporary file and a rename; an unwritable file leaves the
+ * result valid).  Either way both variants are selected as by efie_gemm_select.
+ * cache_path may be NULL (always time, keep nothing).  Outputs (host):
+ * variant_acc32, variant_acc64; ms_acc32 / ms_acc64 (efie_gemm_variants entries
+ * each, may be NULL); from_cache (may be NULL) = 1 when the entry was reused.
+ * ws: dev, 256-byte aligned, efie_gemm_autotune_cached_workspace_size bytes.
+ * Synchronises the stream when it times.  Malformed cache lines are ignored and
+ * dropped when the file is rewritten.
+ */
+int efie_gemm_autotune_cached_workspace_size(int64_t n, int64_t M, size_t* bytes);
+int efie_gemm_autotune_cached(const char* cache_path, const void* Z, int64_t n, int64_t M, int reps, int force,
+                              void* ws, size_t ws_bytes, int* variant_acc32, int* variant_acc64, double* ms_acc32,
+                              double* ms_acc64, int* from_cache, hipStream_t stream);
+
 /* ------------------------------------------------------------------ solve */
 
 typedef struct {
@@ -360,6 +395,16 @@ int efie_solve(const void* Z, int dtype, int64_t n, const void* V, void* J, int6
  *   A column is EFIE_OK when ||V - Z J|| <= tol ||V||; stats report that residual
  *   and the CGS iterations summed over the passes.
  */
+/*
+ * The complex wavenumber of the Calderon second operator (Sec. III, the
+ * definition that follows the preconditioned operator of eq. 16):
+ *   k~ = k - 0.4 j k^(1/3) a^(-2/3),
+ * a an average radius of curvature of the scatterer (a = 1 for the unit
+ * sphere).  Host only.  Errors: EFIE_ERR_ARG (null output, k or a not finite
+ * and > 0).
+ */
+int efie_ktilde(double k, double a, double* kt_re, double* kt_im);
+
 typedef struct efie_calderon_s* efie_calderon;
 int efie_calderon_create(efie_mesh mesh, efie_calderon* out);
 void efie_calderon_destroy(efie_calderon c);

@@ -35,6 +35,14 @@ import numpy as np
 from . import efie, quadrature, rwg
 
 
+def ktilde(k, a=1.0):
+    """The complex wavenumber at which the paper evaluates the second operator of
+    its Calderon product (Sec. III, the definition that follows eq. 16):
+    k~ = k - 0.4 j k^(1/3) a^(-2/3), a an average radius of curvature of the
+    scatterer (a = 1 for the unit sphere)."""
+    return complex(k, -0.4 * np.cbrt(k) / np.cbrt(a) ** 2)
+
+
 def barycentric_refinement(mesh):
     """(vertices, triangles) of the barycentric refinement: vertex ids
     0..V-1 original, V..V+N-1 edge midpoints (RWG order), V+N..V+N+T-1 centroids.

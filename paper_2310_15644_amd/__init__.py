@@ -47,7 +47,8 @@ EXPORTED = [
     "efie_batch_create", "efie_batch_destroy", "efie_batch_sizes", "efie_batch_upload", "efie_batch_assemble",
     "efie_batch_solve", "efie_farfield_adjoint", "efie_vertex_grad_workspace_size", "efie_vertex_grad",
     "efie_assemble_workspace_size", "efie_assemble_ws", "efie_calderon_assemble_ex", "efie_solve_precond_ex",
-    "efie_convert",
+    "efie_convert", "efie_ktilde", "efie_mesh_fp32_kmax",
+    "efie_gemm_autotune_cached_workspace_size", "efie_gemm_autotune_cached",
 ]
 PROF_IDS = {"far": 0, "near": 1, "mfma": 2, "gemv": 3, "zgemm": 4, "krylov": 5, "excite": 6, "farfield": 7, "grad_far": 8,
             "grad_near": 9, "grad_tri": 10}
@@ -121,6 +122,12 @@ def lib():
         "efie_calderon_assemble_ex": ([P, D, D, D, ctypes.c_int, P, P, D, I32, ctypes.POINTER(D), P, ctypes.c_size_t,
                                        P], ctypes.c_int),
         "efie_convert": ([P, ctypes.c_int, P, ctypes.c_int, I64, P], ctypes.c_int),
+        "efie_ktilde": ([D, D, ctypes.POINTER(D), ctypes.POINTER(D)], ctypes.c_int),
+        "efie_mesh_fp32_kmax": ([P, ctypes.POINTER(D)], ctypes.c_int),
+        "efie_gemm_autotune_cached_workspace_size": ([I64, I64, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "efie_gemm_autotune_cached": ([ctypes.c_char_p, P, I64, I64, ctypes.c_int, ctypes.c_int, P, ctypes.c_size_t,
+                                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), ctypes.POINTER(D),
+                                       ctypes.POINTER(D), ctypes.POINTER(ctypes.c_int), P], ctypes.c_int),
         "efie_solve_precond_ex": ([P, ctypes.c_int, P, ctypes.c_int, I64, P, P, I64, ctypes.POINTER(_SolveOpts),
                                    ctypes.POINTER(_RhsStats), P, ctypes.c_size_t, P], ctypes.c_int),
         "efie_solve_precond_workspace_size": ([I64, I64, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
@@ -184,9 +191,12 @@ def _require_cuda(t, name):
 
 
 def ktilde(k: float, a: float = 1.0) -> complex:
-    """Complex wavenumber of the Calderon preconditioner (paper, Sec. III):
-    k~ = k - 0.4 j k^(1/3) a^(-2/3), a an average radius of curvature."""
-    return complex(k, -0.4 * k ** (1.0 / 3.0) * a ** (-2.0 / 3.0))
+    """Complex wavenumber of the Calderon preconditioner (paper, Sec. III),
+    k~ = k - 0.4 j k^(1/3) a^(-2/3) with a an average radius of curvature, as the
+    library computes it (efie_ktilde)."""
+    re, im = ctypes.c_double(), ctypes.c_double()
+    _check(lib().efie_ktilde(float(k), float(a), ctypes.byref(re), ctypes.byref(im)))
+    return complex(re.value, im.value)
 
 
 class Mesh:
@@ -218,6 +228,13 @@ class Mesh:
         _check(lib().efie_mesh_set_far_rule(self._h, float(ratio)))
         self.far3 = float(ratio)
         return self
+
+    def fp32_kmax(self) -> float:
+        """Largest |Re k| that complex64 assembly of this mesh accepts (the FP32
+        phase range of its far-pair kernels)."""
+        v = ctypes.c_double()
+        _check(lib().efie_mesh_fp32_kmax(self._h, ctypes.byref(v)))
+        return v.value
 
     def rwg_table(self):
         ev = np.zeros((self.n, 2), dtype=np.int32)
@@ -512,58 +529,38 @@ def gemm_select(acc64: bool, variant: int) -> int:
 
 
 def default_tuning_cache():
-    return os.path.join(os.path.expanduser("~"), ".cache", "efie", "gemm_tiles.json")
+    return os.path.join(os.path.expanduser("~"), ".cache", "efie", "gemm_tiles.txt")
 
 
 def gemm_autotune(Z, M: int, reps: int = 3, cache: str | None = None, force: bool = False):
-    """Pick the fastest matrix-core tile shape for Z (n x n complex64) times M
-    right-hand sides, for both GEMM paths, and select it.  Results are kept in a
-    JSON cache keyed by device name, n and M; a cached entry is reused unless force.
-    Returns {"acc32": variant, "acc64": variant, "ms": {...}, "tiles": [...]}."""
-    import json
-
+    """Pick and select the matrix-core tile shape of both GEMM paths for Z (n x n
+    complex64) times M right-hand sides (efie_gemm_autotune_cached: the library
+    times the tiles and keeps its choice in the cache file, reused unless force).
+    Returns {"acc32": variant, "acc64": variant, "ms": {...}, "tiles": [...],
+    "from_cache": bool}."""
     torch = _torch()
     if Z.dtype != torch.complex64:
         raise ValueError("autotuning is for the complex64 matrix-core GEMM")
+    _require_cuda(Z, "Z")
     n = Z.shape[0]
     cache = cache or default_tuning_cache()
-    key = f"{torch.cuda.get_device_name(Z.device)}|n={n}|M={M}"
-    db = {}
-    if os.path.exists(cache):
-        try:
-            db = json.load(open(cache))
-        except (OSError, ValueError):
-            db = {}
+    try:
+        os.makedirs(os.path.dirname(cache), exist_ok=True)
+    except OSError:
+        pass
+    nb = ctypes.c_size_t()
+    _check(lib().efie_gemm_autotune_cached_workspace_size(n, int(M), ctypes.byref(nb)))
+    ws = torch.empty(nb.value + 256, dtype=torch.uint8, device=Z.device)
+    off = (-ws.data_ptr()) % 256
     tiles = gemm_variants()
-    if key in db and not force and [list(t) for t in db[key].get("tiles", [])] == [list(t) for t in tiles]:
-        ent = db[key]
-    else:
-        g = torch.Generator(device=Z.device).manual_seed(0)
-        X = torch.randn((M, n), dtype=torch.complex64, device=Z.device, generator=g)
-        ws_bytes = ((M * n * 16 + 255) // 256) * 256 + 4 * M
-        ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=Z.device)
-        off = (-ws.data_ptr()) % 256
-        ent = {"tiles": tiles, "ms": {}}
-        for acc64 in (0, 1):
-            ms = (ctypes.c_double * len(tiles))()
-            best = ctypes.c_int()
-            _check(lib().efie_gemm_autotune(_ptr(Z), n, _ptr(X), M, acc64, ctypes.c_void_p(ws.data_ptr() + off),
-                                            ws_bytes, int(reps), ms, ctypes.byref(best), _stream(Z.device)))
-            name = "acc64" if acc64 else "acc32"
-            ent[name] = best.value
-            ent["ms"][name] = [round(x, 4) for x in ms]
-        del X, ws
-        db[key] = ent
-        try:
-            os.makedirs(os.path.dirname(cache), exist_ok=True)
-            tmp = cache + ".tmp"
-            json.dump(db, open(tmp, "w"), indent=1)
-            os.replace(tmp, cache)
-        except OSError:
-            pass
-    gemm_select(False, ent["acc32"])
-    gemm_select(True, ent["acc64"])
-    return ent
+    v32, v64, hit = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    ms32, ms64 = (ctypes.c_double * len(tiles))(), (ctypes.c_double * len(tiles))()
+    _check(lib().efie_gemm_autotune_cached(cache.encode(), _ptr(Z), n, int(M), int(reps), int(bool(force)),
+                                           ctypes.c_void_p(ws.data_ptr() + off), nb.value, ctypes.byref(v32),
+                                           ctypes.byref(v64), ms32, ms64, ctypes.byref(hit), _stream(Z.device)))
+    del ws
+    return {"acc32": v32.value, "acc64": v64.value, "tiles": tiles, "from_cache": bool(hit.value),
+            "ms": {"acc32": [round(x, 4) for x in ms32], "acc64": [round(x, 4) for x in ms64]}}
 
 
 # ------------------------------------------------------------------ Calderon

@@ -49,6 +49,25 @@ int efie_mesh_set_far_rule(efie_mesh mesh, double ratio) {
     });
 }
 
+int efie_mesh_fp32_kmax(efie_mesh mesh, double* kmax) {
+    return guarded([&]() {
+        EFIE_REQUIRE(mesh != nullptr && kmax != nullptr, EFIE_ERR_ARG, "mesh_fp32_kmax: null argument");
+        *kmax = efie::fp32_kmax(mesh->diam);
+        return int(EFIE_OK);
+    });
+}
+
+int efie_ktilde(double k, double a, double* kt_re, double* kt_im) {
+    return guarded([&]() {
+        EFIE_REQUIRE(kt_re != nullptr && kt_im != nullptr, EFIE_ERR_ARG, "ktilde: null output");
+        EFIE_REQUIRE(std::isfinite(k) && k > 0.0 && std::isfinite(a) && a > 0.0, EFIE_ERR_ARG,
+                     "ktilde: need finite k > 0 and a > 0");
+        *kt_re = k;
+        *kt_im = -0.4 * std::cbrt(k) / std::cbrt(a * a);
+        return int(EFIE_OK);
+    });
+}
+
 int efie_mesh_sizes(efie_mesh mesh, int64_t* n_rwg, int64_t* n_tri, int64_t* n_near, size_t* table_bytes) {
     return guarded([&]() {
         EFIE_REQUIRE(mesh != nullptr, EFIE_ERR_ARG, "mesh_sizes: null mesh");

@@ -112,8 +112,9 @@ __global__ __launch_bounds__(FAR_BLOCK) void far_rows_kernel(DevMesh m, Tables<R
             const int side = tb.cf[j * T + q] > R(0) ? 0 : 1;
             rows[(size_t(i) * N + n) * 2 + side] = C2{re, im};
         };
-        const bool near = (m.near_mask[size_t(p) * m.nqb + (q >> 6)] >> (q & 63)) & 1ull;
-        if (UPPER && (q < p || near)) continue;
+        if (UPPER && q < p) continue;
+        const bool near = is_near(m, p, q);
+        if (UPPER && near) continue;
         if (near) {
 #pragma unroll
             for (int i = 0; i < 3; ++i)
@@ -422,6 +423,7 @@ static Scale operator_scale(double kr, double ki, double eta) {
 void pair_rows_chunk(const DevMesh& m, double kr, double ki, double eta, int dtype, void* W, int c0, int c1,
                      const std::vector<int32_t>& near_p, bool upper, hipStream_t s) {
     const Scale sc = operator_scale(kr, ki, eta);
+    if (dtype == EFIE_C64) require_fp32_phase(m.diam, kr, "pair rows");
     const int nqblk = (m.T + FAR_BLOCK - 1) / FAR_BLOCK;
     const int np = c1 - c0;
     EFIE_REQUIRE(np >= 1 && size_t(np) * nqblk < (size_t(1) << 31), EFIE_ERR_ARG, "pair_rows_chunk: bad chunk");
@@ -470,6 +472,7 @@ static void assemble_impl(const DevMesh& m, double kr, double ki, double eta, in
                           hipStream_t s, void* ws, size_t ws_bytes, const std::vector<int32_t>* near_p) {
     const size_t N = size_t(m.N);
     const size_t esz = dtype == EFIE_C128 ? 16 : 8;
+    if (dtype == EFIE_C64) require_fp32_phase(m.diam, kr, "assemble");
     if (!ws || parts) fill_zero_bytes(Z, N * N * esz, s);   // the two-pass path writes every entry
     if (parts) fill_zero_bytes(Z2, N * N * esz, s);
     Scale sc{};

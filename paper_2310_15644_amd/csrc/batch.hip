@@ -430,6 +430,7 @@ extern "C" int efie_batch_assemble(efie_batch b, const double* k, double eta, in
         for (size_t r = 0; r < nm; ++r) {
             const double kr = k[b->order[r]];
             EFIE_REQUIRE(std::isfinite(kr) && kr > 0.0, EFIE_ERR_ARG, "batch_assemble: k must be real and > 0");
+            if (dtype == EFIE_C64) require_fp32_phase(b->meshes[size_t(b->order[r])]->diam, kr, "batch_assemble");
             const double f = eta / (4.0 * 3.14159265358979323846);
             BatchParam p{};
             p.sc.ar = 0.0;

@@ -788,6 +788,7 @@ int efie_calderon_assemble_ex(efie_calderon c, double kt_re, double kt_im, doubl
         EFIE_REQUIRE(bary_dtype == EFIE_C128 || bary_dtype == EFIE_C64, EFIE_ERR_ARG, "calderon_assemble: bad dtype");
         EFIE_REQUIRE(kt_im <= 0.0 && (kt_re != 0.0 || kt_im != 0.0), EFIE_ERR_ARG, "calderon_assemble: bad k~");
         EFIE_REQUIRE(tol > 0.0 && maxit >= 1, EFIE_ERR_ARG, "calderon_assemble: bad tol/maxit");
+        if (bary_dtype == EFIE_C64) require_fp32_phase(c->bary.diam, kt_re, "calderon_assemble");
         const int N = int(c->N);
         const CaldPlan pl = cald_plan(*c, bary_dtype, tol);
         const size_t need = cald_layout(*c, pl, bary_dtype, nullptr, nullptr);

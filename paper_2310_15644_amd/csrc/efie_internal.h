@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -56,8 +57,10 @@ constexpr int NQ = 7;   // points of the triangle rule
 // Local edge i of a triangle is the edge opposite its local vertex i, so that
 // vertex i is the free vertex of the RWG half-function carried by that edge.
 struct DevMesh {
-    int32_t T, N, nqb;          // triangles, RWGs, 64-wide source blocks per row of the near mask
+    int32_t T, N;               // triangles, RWGs
     int32_t n_near;             // ordered near pairs
+    double nf;                  // near factor: distance rule of near_by_distance
+    double diam;                // bounding-box diagonal of the vertices (host use: FP32 phase range)
     // FP64.  Positions are stored relative to the triangle centroid (cx, cy, cz):
     // offsets are O(h), so products of offsets keep their relative precision.
     const double *cx, *cy, *cz;          // centroids [T]
@@ -72,7 +75,6 @@ struct DevMesh {
     // topology
     const int32_t* te;                   // RWG index of local edge i [3][T]
     const int32_t* tv;                   // vertex id of local vertex i [3][T]
-    const uint64_t* near_mask;           // [T][nqb], bit q%64 of word q/64: pair (p,q) is near
     const int32_t *near_p, *near_q;      // ordered near pairs (incl. p == q)
     const int32_t *et;                   // RWG -> (T+, T-) [2][N]
     const int32_t *el;                   // RWG -> local edge index in T+ / T- [2][N]
@@ -89,6 +91,7 @@ struct efie_mesh_s {
     int64_t nv = 0, T = 0, N = 0;
     double near_factor = 2.0;
     double far3 = 0.0;                       // ratio of the distance-adaptive far rule (0: off)
+    double diam = 0.0;                       // bounding-box diagonal of the vertices
     std::vector<double> xyz;                 // nv*3
     std::vector<int32_t> tri;                // T*3
     std::vector<int32_t> edge_v, edge_t, edge_l;  // N*2 each (edge_l: local index in T+/T-)
@@ -96,8 +99,6 @@ struct efie_mesh_s {
     std::vector<int32_t> tri_edge, tri_sign; // T*3
     std::vector<double> area, normal, centroid, hmax;
     std::vector<int32_t> near_p, near_q;     // ordered near pairs, sorted by p then q
-    int32_t nqb = 0;
-    std::vector<uint64_t> near_mask;         // T * nqb
     // device tables (caller-owned blob)
     void* dev = nullptr;
     size_t dev_bytes = 0;
@@ -107,6 +108,37 @@ struct efie_mesh_s {
 };
 
 namespace efie {
+// The distance part of the near-pair rule: |c_p - c_q|^2 < (nf max(h_p, h_q))^2,
+// every operation rounded on its own (no fused multiply-add), in the order
+// ((dx dx + dy dy) + dz dz), so that the host list and the device test decide
+// every pair alike.  A pair is near if this holds or the triangles share a vertex.
+__host__ __device__ inline bool near_by_distance(double cpx, double cpy, double cpz, double cqx, double cqy,
+                                                 double cqz, double hp, double hq, double nf) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const double dx = __dsub_rn(cpx, cqx), dy = __dsub_rn(cpy, cqy), dz = __dsub_rn(cpz, cqz);
+    const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+    const double thr = __dmul_rn(nf, hp > hq ? hp : hq);
+    return d2 < __dmul_rn(thr, thr);
+#else
+#pragma clang fp contract(off)
+    const double dx = cpx - cqx, dy = cpy - cqy, dz = cpz - cqz;
+    const double d2 = (dx * dx + dy * dy) + dz * dz;
+    const double thr = nf * (hp > hq ? hp : hq);
+    return d2 < thr * thr;
+#endif
+}
+
+// The FP32 far-pair kernels take the phase Re(k) R in revolutions to the hardware
+// sine and cosine, whose argument must stay below 256 revolutions in magnitude.
+// Every distance between two points of a mesh is at most its bounding-box
+// diagonal, so complex64 assembly is accepted for |Re k| < fp32_kmax(diam).
+inline double fp32_kmax(double diam) { return 256.0 * 2.0 * 3.14159265358979323846 / diam; }
+inline void require_fp32_phase(double diam, double kr, const char* who) {
+    if (!(std::fabs(kr) < fp32_kmax(diam)))
+        throw Error{EFIE_ERR_ARG, std::string(who) + ": |Re k| * (mesh diameter) / 2 pi reaches 256 revolutions, "
+                                                     "beyond the FP32 phase range of complex64 assembly; use EFIE_C128"};
+}
+
 // mesh.cpp
 void build_mesh(efie_mesh_s& m, const double* xyz, int64_t nv, const int32_t* tri, int64_t nt,
                 double near_factor);

@@ -283,7 +283,7 @@ __global__ __launch_bounds__(256) void grad_far_kernel(DevMesh m, double kr, Sca
     double out[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) out[k] = 0.0;
-    const bool live = q < T && !((m.near_mask[size_t(t) * m.nqb + (q >> 6)] >> (q & 63)) & 1ull);
+    const bool live = q < T && !is_near(m, t, q);
     if (live) {
         // test triangle (uniform): vertex offsets u, point offsets d, coefficients
         double ut[3][3], e[3][3], lt[3];

@@ -61,6 +61,15 @@ void build_mesh(efie_mesh_s& m, const double* xyz, int64_t nv, const int32_t* tr
         EFIE_REQUIRE(std::isfinite(xyz[i]), EFIE_ERR_ARG, "mesh: non-finite vertex coordinate");
 
     auto P = [&](int64_t v) { return V3{xyz[3 * v], xyz[3 * v + 1], xyz[3 * v + 2]}; };
+    {
+        double blo[3] = {xyz[0], xyz[1], xyz[2]}, bhi[3] = {xyz[0], xyz[1], xyz[2]};
+        for (int64_t v = 0; v < nv; ++v)
+            for (int d = 0; d < 3; ++d) {
+                blo[d] = std::min(blo[d], xyz[3 * v + d]);
+                bhi[d] = std::max(bhi[d], xyz[3 * v + d]);
+            }
+        m.diam = norm(V3{bhi[0] - blo[0], bhi[1] - blo[1], bhi[2] - blo[2]});
+    }
     const int64_t T = nt;
     m.area.resize(T);
     m.normal.resize(3 * T);
@@ -164,23 +173,21 @@ void build_mesh(efie_mesh_s& m, const double* xyz, int64_t nv, const int32_t* tr
     for (int64_t t = 0; t < T; ++t)
         for (int i = 0; i < 3; ++i) vtri[size_t(tri[3 * t + i])].push_back(int32_t(t));
 
-    m.nqb = int32_t((T + 63) / 64);
-    m.near_mask.assign(size_t(T) * size_t(m.nqb), 0ull);
     m.near_p.clear();
     m.near_q.clear();
     std::vector<int32_t> cand;
     for (int64_t p = 0; p < T; ++p) {
         cand.clear();
         int64_t c0 = cell_of(p, 0), c1 = cell_of(p, 1), c2 = cell_of(p, 2);
+        const double* cp = &m.centroid[3 * p];
         for (int64_t i = std::max<int64_t>(c0 - 1, 0); i <= std::min(c0 + 1, dim[0] - 1); ++i)
             for (int64_t j = std::max<int64_t>(c1 - 1, 0); j <= std::min(c1 + 1, dim[1] - 1); ++j)
                 for (int64_t k = std::max<int64_t>(c2 - 1, 0); k <= std::min(c2 + 1, dim[2] - 1); ++k)
                     for (int32_t q : grid[size_t((i * dim[1] + j) * dim[2] + k)]) {
-                        double dx = m.centroid[3 * p] - m.centroid[3 * q];
-                        double dy = m.centroid[3 * p + 1] - m.centroid[3 * q + 1];
-                        double dz = m.centroid[3 * p + 2] - m.centroid[3 * q + 2];
-                        double thr = near_factor * std::max(m.hmax[p], m.hmax[q]);
-                        if (dx * dx + dy * dy + dz * dz < thr * thr) cand.push_back(q);
+                        const double* cq = &m.centroid[3 * size_t(q)];
+                        if (near_by_distance(cp[0], cp[1], cp[2], cq[0], cq[1], cq[2], m.hmax[p], m.hmax[q],
+                                             near_factor))
+                            cand.push_back(q);
                     }
         for (int i = 0; i < 3; ++i)
             for (int32_t q : vtri[size_t(tri[3 * p + i])]) cand.push_back(q);
@@ -189,7 +196,6 @@ void build_mesh(efie_mesh_s& m, const double* xyz, int64_t nv, const int32_t* tr
         for (int32_t q : cand) {
             m.near_p.push_back(int32_t(p));
             m.near_q.push_back(q);
-            m.near_mask[size_t(p) * m.nqb + size_t(q / 64)] |= (1ull << (q % 64));
         }
     }
 }
@@ -278,7 +284,6 @@ void pack_tables(efie_mesh_s& m) {
     pk.add(f32(vx)); pk.add(f32(vy)); pk.add(f32(vz)); pk.add(f32(cf)); pk.add(f32(dv));
     pk.add(te);
     pk.add(tv);
-    pk.add(m.near_mask);
     pk.add(m.near_p); pk.add(m.near_q);
     pk.add(et); pk.add(el);
     pk.add(q3x); pk.add(q3y); pk.add(q3z); pk.add(q3w);
@@ -294,7 +299,8 @@ void bind_tables(efie_mesh_s& m, void* dev) {
     DevMesh& d = m.dm;
     d.T = int32_t(m.T);
     d.N = int32_t(m.N);
-    d.nqb = m.nqb;
+    d.nf = m.near_factor;
+    d.diam = m.diam;
     d.n_near = int32_t(m.near_p.size());
     int i = 0;
     auto D = [&]() { return reinterpret_cast<const double*>(b + o[i++]); };
@@ -308,7 +314,6 @@ void bind_tables(efie_mesh_s& m, void* dev) {
     d.vx32 = F(); d.vy32 = F(); d.vz32 = F(); d.cf32 = F(); d.dv32 = F();
     d.te = I();
     d.tv = I();
-    d.near_mask = reinterpret_cast<const uint64_t*>(b + o[i++]);
     d.near_p = I(); d.near_q = I();
     d.et = I(); d.el = I();
     d.q3x = D(); d.q3y = D(); d.q3z = D(); d.q3w = D();

@@ -38,6 +38,18 @@ __device__ __forceinline__ bool far3_pair(const DevMesh& m, int p, int q) {
     return d2 >= __dmul_rn(lim, lim);
 }
 
+// Whether the pair (p, q) is near: the triangles share a vertex, or their
+// centroids are closer than near_factor times the larger longest edge (decided
+// as on the host, so that the device agrees with the ordered near-pair list).
+__device__ __forceinline__ bool is_near(const DevMesh& m, int p, int q) {
+    const int T = m.T;
+    const int a0 = m.tv[p], a1 = m.tv[T + p], a2 = m.tv[2 * T + p];
+    const int b0 = m.tv[q], b1 = m.tv[T + q], b2 = m.tv[2 * T + q];
+    const bool share = (a0 == b0) | (a0 == b1) | (a0 == b2) | (a1 == b0) | (a1 == b1) | (a1 == b2) | (a2 == b0) |
+                       (a2 == b1) | (a2 == b2);
+    return share || near_by_distance(m.cx[p], m.cy[p], m.cz[p], m.cx[q], m.cy[q], m.cz[q], m.hm[p], m.hm[q], m.nf);
+}
+
 // ------------------------------------------------------------------ helpers
 template <typename R>
 __device__ __forceinline__ void atomic_add_c(void* Z, size_t idx, R re, R im);
@@ -192,7 +204,7 @@ template <typename R, bool CK, bool PARTS>
 __device__ __forceinline__ void far_pair(const DevMesh& m, const Tables<R>& tb, int p, int q, R kphase, R ki,
                                          const Scale& sc, void* Z, void* Z2) {
     const int T = m.T;
-    if ((m.near_mask[size_t(p) * m.nqb + (q >> 6)] >> (q & 63)) & 1ull) return;
+    if (is_near(m, p, q)) return;
     const size_t N = size_t(m.N);
     auto at = [&](void* dst) {
         return [=, &m](int i, int j, R re, R im) {

@@ -121,3 +121,20 @@ def test_workspace_sizes():
     assert L.efie_solve_workspace_size(480, 8, 1, ctypes.byref(nb)) == 0
     assert nb.value > b1 > 7 * 480 * 16
     assert L.efie_solve_workspace_size(0, 1, 0, ctypes.byref(nb)) == -1
+
+
+def test_ktilde_library_errors():
+    with pytest.raises(P.EfieError):
+        P.ktilde(0.0)
+    with pytest.raises(P.EfieError):
+        P.ktilde(1.0, -1.0)
+
+
+def test_fp32_kmax_from_bounding_box():
+    """The complex64 assemblies accept |Re k| below 512 pi / (bounding-box diagonal)."""
+    v, f = synth.icosphere(2)
+    m = P.Mesh(v, f)
+    diag = np.linalg.norm(v.max(axis=0) - v.min(axis=0))
+    assert abs(m.fp32_kmax() - 512.0 * np.pi / diag) <= 1e-12 * m.fp32_kmax()
+    m2 = P.Mesh(v * 10.0, f)
+    assert abs(m2.fp32_kmax() * 10.0 - m.fp32_kmax()) <= 1e-12 * m.fp32_kmax()

@@ -34,7 +34,7 @@ def test_calderon_l1_parity(dev, k):
     kt = P.ktilde(k)
     Pm, Tbc = cal.assemble(kt, with_tbc=True)
     assert cal.gram_relres <= 1e-13
-    C = ocal.Calderon(oracle_mesh(1), k, kt)
+    C = ocal.Calderon(oracle_mesh(1), k, ocal.ktilde(k))
     assert rel_max(Tbc.cpu().numpy(), C.Tbc) <= 1e-11
     assert rel_max(Pm.cpu().numpy(), C.P) <= 1e-10
     Z = P.assemble(m, k)
@@ -71,7 +71,7 @@ def test_calderon_l4_sampled_row(dev):
     xyz, tri = ocal.barycentric_refinement(om)
     ob = rwg.build(xyz, tri)
     es = np.nonzero(R[:, row])[0]
-    Zb_rows = oefie.z_rows(ob, kt, list(es))            # (|es|, N_bary)
+    Zb_rows = oefie.z_rows(ob, ocal.ktilde(k), list(es))            # (|es|, N_bary)
     ref = R[es, row] @ Zb_rows @ R
     assert rel_max(got, ref) <= 1e-11
     # T_BC symmetric (T_bary symmetric, R real)
@@ -138,7 +138,7 @@ def test_calderon_c64_bary_and_mixed_solve(dev, fp32_acc):
     assert st64.relres_true.max() <= 1e-6 and st32.relres_true.max() <= 1e-6
     err = float((torch.linalg.norm(J32 - J64, dim=1) / torch.linalg.norm(J64, dim=1)).max())
     flush(f"  mixed vs FP64 currents: {err:.2e}")
-    assert err <= 1e-4
+    assert err <= 1e-5     # the precision form's bound on the currents (measured 1.9e-6)
 
 
 def test_calderon_l5_gram_solve_as_benched(dev):

@@ -56,7 +56,7 @@ def test_calderon_bounded_spectrum_l1():
     kh, pol = synth.planewave_x_along_minus_z()
     # (k, bound on kappa(M), minimum kappa(Z)/kappa(M), iteration cap); measured 2.3 / 7.1
     for k, cmax, ratio, itmax in ((1.0, 3.0, 10.0, 15), (0.1, 10.0, 300.0, 25)):
-        C = calderon.Calderon(m, k, P.ktilde(k))
+        C = calderon.Calderon(m, k, calderon.ktilde(k))
         cm, cz = np.linalg.cond(C.M), np.linalg.cond(C.Z)
         assert cm < cmax and cz > ratio * cm, (k, cm, cz)
         V = efie.excitation(m, k, kh, pol)[0]
@@ -76,3 +76,18 @@ def test_host_library_matches_oracle_bc_and_gram():
         assert np.abs(R - Ro).max() <= 1e-14 * np.abs(Ro).max()
         Go = calderon.mixed_gram(m, b, Ro)
         assert np.abs(G - Go).max() <= 1e-14 * np.abs(Go).max()
+
+
+def test_ktilde_golden():
+    """k~ of the paper's Sec. III against values evaluated by hand at exact cube roots."""
+    import os
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "ktilde.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    assert len(rows) == 5
+    for k, a, re_, im in rows:
+        kt = calderon.ktilde(float(k), float(a))
+        assert abs(kt - complex(float(re_), float(im))) <= 1e-15 * float(k), (k, a, kt)
+    # the damping grows as k^(1/3) and falls as a^(-2/3): exact ratios between rows
+    assert calderon.ktilde(8.0).imag == 2.0 * calderon.ktilde(1.0).imag
+    assert calderon.ktilde(1.0, 8.0).imag == 0.25 * calderon.ktilde(1.0).imag

@@ -284,3 +284,52 @@ def test_mom_converges_to_mie():
             e = max(e, np.max(np.abs(10 * np.log10(s / sm))))
         errs.append(e)
     assert errs[1] < 0.5 and errs[1] < errs[0] / 3
+
+
+# ------------------------------------------------------------ near-pair rule
+def _two_tetrahedra(shift, scale_b):
+    """A regular tetrahedron A (edge 1) and a copy B scaled by scale_b and moved
+    so that the centroid of B's face 0 lies `shift` from that of A's face 0."""
+    a = np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], dtype=float) / (2.0 * math.sqrt(2.0))
+    f = np.array([[0, 1, 2], [0, 3, 1], [0, 2, 3], [1, 3, 2]])
+    b = a * scale_b
+    cA = a[f[0]].mean(axis=0)
+    cB = b[f[0]].mean(axis=0)
+    b = b + (cA - cB) + np.asarray(shift, dtype=float)
+    return rwg.build(np.concatenate([a, b]), np.concatenate([f, f + 4]))
+
+
+@pytest.mark.parametrize("factor,expect", [(1.99, True), (2.01, False)])
+def test_near_rule_distance_threshold(factor, expect):
+    """Centroid distance just below / above 2 h_max (the default near factor): the
+    pair is near / far, whichever triangle is the test triangle, with h_max the
+    longest edge of the larger triangle (edge 1 of A, 1/2 of B)."""
+    m = _two_tetrahedra([factor, 0.0, 0.0], 0.5)
+    assert abs(m.hmax[0] - 1.0) < 1e-15 and abs(m.hmax[4] - 0.5) < 1e-15
+    assert abs(np.linalg.norm(m.centroid[4] - m.centroid[0]) - factor) < 1e-14
+    assert bool(efie.near_row(m, 0)[4]) is expect
+    assert bool(efie.near_row(m, 4)[0]) is expect        # symmetric: max of the two edges
+
+
+def test_near_rule_uses_larger_edge():
+    """At 1.5 h_max(A) the pair is near from both sides; a rule taking the test
+    triangle's own edge would call it far from B's side (2 h_B = 1 < 1.5)."""
+    m = _two_tetrahedra([0.0, 1.5, 0.0], 0.5)
+    assert efie.near_row(m, 4)[0] and efie.near_row(m, 0)[4]
+    # scaled by the near factor: 1.5 h < 1.6 h but not < 1.4 h
+    assert efie.near_row(m, 0, 1.6)[4] and not efie.near_row(m, 0, 1.4)[4]
+
+
+def test_near_rule_vertex_sharing():
+    """Icosahedron with a vanishing distance factor: the near triangles of a face
+    are the ten faces that share at least one vertex with it (itself, three across
+    its edges, six touching one corner only), whatever their distance."""
+    m = rwg.build(*synth.icosphere(0))
+    far_edge = m.hmax.max()
+    for p in range(m.t):
+        row = efie.near_row(m, p, 1e-6)
+        assert row.sum() == 10
+        corner_only = [q for q in range(m.t) if len(set(m.tri[q]) & set(m.tri[p])) == 1]
+        assert len(corner_only) == 6 and all(row[q] for q in corner_only)
+        # a corner-only neighbour lies farther than its own longest edge times 1e-6
+        assert all(np.linalg.norm(m.centroid[q] - m.centroid[p]) > 1e-6 * far_edge for q in corner_only)
