@@ -142,7 +142,7 @@ extern "C" int efie_gemm_autotune_cached(const char* cache_path, const void* Z, 
             if (cache_path) {
                 std::ostringstream l;
                 l << key << " " << ent.v32 << " " << ent.v64;
-                l.precision(6);
+                l.precision(17);   // round trip: a reused entry returns the same doubles
                 for (double x : ent.ms32) l << " " << x;
                 for (double x : ent.ms64) l << " " << x;
                 lines.push_back(l.str());
