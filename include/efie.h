@@ -261,6 +261,25 @@ int efie_zx_flush64_workspace_size(int64_t n, int64_t nrhs, size_t* bytes);
 int efie_zx_flush64(const void* Z, int64_t n, const void* X, void* Y, int64_t nrhs, void* ws,
                     size_t ws_bytes, hipStream_t stream);
 
+/*
+ * efie_zx_flush64 for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * product and the same kernels, with the complex64 copy of X and the row list
+ * kept in a library-owned scratch array of 64 MiB per GPU (a static device
+ * array, one copy on each device the library runs on, held until the process
+ * ends) instead of a caller workspace.  Allocates nothing and calls no allocating
+ * routine.  Limit: n * nrhs * 8 bytes, rounded up to a multiple of 256, plus
+ * 4 * nrhs bytes must not exceed the scratch (efie_zx_flush64_noalloc_max gives
+ * its size; e.g. n = 30720 with nrhs <= 273); larger products return EFIE_ERR_ARG.
+ * Every call on one GPU shares that GPU's scratch: calls that overlap on one GPU
+ * (two streams, or two host threads without ordering) race and give wrong
+ * results; calls ordered on one stream are safe.  Every scratch element a call
+ * reads is written earlier in the same call.  Z, X, Y, n, nrhs as for
+ * efie_zx_flush64; asynchronous on stream.
+ */
+int efie_zx_flush64_noalloc_max(int64_t* max_bytes);
+int efie_zx_flush64_noalloc(const void* Z, int64_t n, const void* X, void* Y, int64_t nrhs, hipStream_t stream);
+
 /* ------------------------------------------------------- GEMM autotuning */
 
 /*

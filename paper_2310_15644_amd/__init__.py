@@ -47,7 +47,7 @@ EXPORTED = [
     "efie_batch_create", "efie_batch_destroy", "efie_batch_sizes", "efie_batch_upload", "efie_batch_assemble",
     "efie_batch_solve", "efie_farfield_adjoint", "efie_vertex_grad_workspace_size", "efie_vertex_grad",
     "efie_assemble_workspace_size", "efie_assemble_ws", "efie_calderon_assemble_ex", "efie_solve_precond_ex",
-    "efie_convert", "efie_ktilde", "efie_mesh_fp32_kmax",
+    "efie_convert", "efie_ktilde", "efie_mesh_fp32_kmax", "efie_zx_flush64_noalloc_max", "efie_zx_flush64_noalloc",
     "efie_gemm_autotune_cached_workspace_size", "efie_gemm_autotune_cached",
 ]
 PROF_IDS = {"far": 0, "near": 1, "mfma": 2, "gemv": 3, "zgemm": 4, "krylov": 5, "excite": 6, "farfield": 7, "grad_far": 8,
@@ -124,6 +124,8 @@ def lib():
         "efie_convert": ([P, ctypes.c_int, P, ctypes.c_int, I64, P], ctypes.c_int),
         "efie_ktilde": ([D, D, ctypes.POINTER(D), ctypes.POINTER(D)], ctypes.c_int),
         "efie_mesh_fp32_kmax": ([P, ctypes.POINTER(D)], ctypes.c_int),
+        "efie_zx_flush64_noalloc_max": ([ctypes.POINTER(I64)], ctypes.c_int),
+        "efie_zx_flush64_noalloc": ([P, I64, P, P, I64, P], ctypes.c_int),
         "efie_gemm_autotune_cached_workspace_size": ([I64, I64, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "efie_gemm_autotune_cached": ([ctypes.c_char_p, P, I64, I64, ctypes.c_int, ctypes.c_int, P, ctypes.c_size_t,
                                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), ctypes.POINTER(D),
