@@ -91,10 +91,14 @@ def cpu_baseline(level, n_sample_rows, nrhs, k, seconds):
         if time.perf_counter() - t1 > seconds * 0.4:
             break
     ta = time.perf_counter() - t1
+    phases = oracle_phases(np, k, nrhs)
     return {
         "value": round(gflops, 3),
         "unit": "GFLOP/s",
         "cores": int(threads),
+        "cpu_model": cpu_model(),
+        "cores_available": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count(),
+        "phases": phases,
         "kind": "oracle",
         "sample": (f"oracle Z.X (numpy complex128) of a {rows} x {N} row block of Z times {N} x {nrhs}, "
                    f"{reps} repetitions; oracle assembly of {nrow} rows of the level-{level} Z at k={k}: "
@@ -145,6 +149,44 @@ def measured_traffic(tiles, acc64, n, nrhs, solver):
                 and kv.get("workload") == f"n={n} nrhs={nrhs} solver={solver}"):
             return float(kv["hbm_bytes_per_launch"]), os.path.relpath(path, ROOT)
     return None, None
+
+
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or None."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def oracle_phases(np, k, nrhs):
+    """Per-phase timings of the oracle on the level-3 sphere (N = 1920) on the host
+    cores: its LU solve of the dense system for nrhs right-hand sides (numpy/LAPACK,
+    all BLAS threads; the values of Z do not change the LU's cost, so a seeded
+    matrix of the same shape stands in for the assembled one) and its far field of
+    nrhs currents in nrhs directions (numpy, one thread's loops)."""
+    import synth
+    from oracle import efie, krylov, rwg
+
+    v, f = synth.icosphere(3)
+    om = rwg.build(v, f)
+    N = om.n
+    rng = np.random.default_rng(1)
+    A = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N)) + N * np.eye(N)
+    B = rng.standard_normal((N, nrhs)) + 1j * rng.standard_normal((N, nrhs))
+    t0 = time.perf_counter()
+    krylov.lu_solve(A, B)
+    t_lu = time.perf_counter() - t0
+    rhat, _, _, _, _ = synth.monostatic_grid(16, 32)
+    J = (rng.standard_normal((nrhs, N)) + 1j * rng.standard_normal((nrhs, N)))[:nrhs]
+    t0 = time.perf_counter()
+    efie.farfield(om, k, J, rhat[:nrhs])
+    t_ff = time.perf_counter() - t0
+    return {"mesh": f"icosphere level 3 (N={N})", "lu_solve_s": round(t_lu, 3),
+            "lu_rhs": nrhs, "farfield_s": round(t_ff, 3), "farfield_currents_x_dirs": [nrhs, min(nrhs, len(rhat))]}
 
 
 def copy_calibration(torch):
@@ -451,6 +493,31 @@ def bench_far_rule(args, P, synth, torch, np, dev):
     print(json.dumps(out), flush=True)
 
 
+def fp64_leg(args, P, torch, np, m, kh_d, po_d, V, J, cal):
+    """The plain FP64 path on the same inputs, timed like a step (after the mixed
+    steps, --fp64-steps of them, no warm-up): complex128 Z, complex128 P (the same
+    build), CGS on P Z J = P V with FP64 products to the same true residual."""
+    log(f"bench: FP64 path, {args.fp64_steps} step(s)")
+    Z = torch.empty((m.n, m.n), dtype=torch.complex128, device=V.device)
+    times, st = [], None
+    for _ in range(args.fp64_steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P.assemble(m, args.k, dtype=P.C128, out=Z)
+        P.excite_planewave(m, args.k, kh_d, po_d, out=V)
+        Pm = cal.assemble(P.ktilde(args.k), tol=1e-3, bary_dtype=P.C64)
+        _, st = P.solve_precond(Z, Pm, V, tol=args.tol, maxit=args.maxit, out=J)
+        del Pm
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    del Z
+    torch.cuda.empty_cache()
+    return {"time_to_solve_s": round(float(np.mean(times)), 3), "steps": args.fp64_steps,
+            "iters_max": int(np.max(st.iters)), "iters_mean": round(float(np.mean(st.iters)), 1),
+            "relres_true_max": float(np.max(st.relres_true)), "all_converged": bool(np.all(st.status == 0)),
+            "dtype": "c128"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -483,6 +550,9 @@ def main():
     ap.add_argument("--fp32-acc", action="store_true",
                     help="mixed solve: accumulate the matrix-core products in FP32 instead of flushing "
                          "the partial sums into FP64 every K chunk")
+    ap.add_argument("--fp64-steps", type=int, default=1,
+                    help="after the timed mixed steps, time this many steps of the plain FP64 path "
+                         "(complex128 Z and P, FP64 products; Calderon solver only; 0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -544,10 +614,14 @@ def main():
         torch.cuda.synchronize()
 
     cal = None
+    cal_host_s = None
     if args.solver == "calderon":
+        t_c = time.perf_counter()
         cal = P.Calderon(m).upload(dev)        # host refinement and BC tables: mesh preprocessing
         cal.set_far_rule(args.cal_far_rule)
-        log(f"bench: Calderon tables: {cal.n_bary} barycentric RWGs")
+        sync()
+        cal_host_s = time.perf_counter() - t_c
+        log(f"bench: Calderon tables: {cal.n_bary} barycentric RWGs, host setup and upload {cal_host_s:.2f} s")
 
     def step(rec):
         t0 = time.perf_counter()
@@ -593,6 +667,9 @@ def main():
     P.prof_enable(False)
 
     ms_step = 1e3 * wall / args.steps
+    fp64 = None
+    if args.fp64_steps > 0 and dt == P.C64 and args.solver == "calderon":
+        fp64 = fp64_leg(args, P, torch, np, m, kh_d, po_d, V, J, cal)
     gemm_key = "mfma" if dt == P.C64 else "zgemm"
     n_mm, ms_mm, fl_mm = prof[gemm_key]
     # Z.X launches inside the solve run over the active (unconverged) columns only:
@@ -650,6 +727,10 @@ def main():
         "time_to_solve_s": round(tts, 3),
         "calderon_build_s": round(float(np.mean([r["build_s"] for r in rec])), 3) if args.solver == "calderon"
         else None,
+        "calderon_host_s": None if cal_host_s is None else round(cal_host_s, 3),
+        "time_to_solve_fp64_s": None if fp64 is None else fp64["time_to_solve_s"],
+        "fp64_path": fp64,
+        "mixed_speedup_vs_fp64": None if fp64 is None else round(fp64["time_to_solve_s"] / tts, 3),
         "iters_max": int(np.max(last["iters"])),
         "iters_mean": round(float(np.mean(last["iters"])), 1),
         "relres_true_max": float(np.max(last["relres"])),

@@ -21,4 +21,10 @@ Modules
   mie         Mie series for a PEC sphere
   calderon    barycentric refinement, Buffa-Christiansen functions, the mixed
               Gram matrix and the Calderon-preconditioned operator
+  bie2d       the paper's own 2-D method: single, adjoint double and hypersingular
+              layer operators with the Hankel kernel on a closed polygon, the TM
+              CFIE of a PEC cylinder, its Calderon-stabilized form C_p (eq. 16),
+              the circular counterpart, the randomized skeleton of their
+              difference and the Woodbury inverse (eqs. 17-18); the PEC-cylinder
+              series solution
 """

@@ -14,6 +14,10 @@ Workloads (all in metres, free space):
   * Vertex-perturbed spheres: radius 1 + delta(theta, phi), delta a seeded real
     spherical-harmonic series of degree <= lmax scaled to max |delta| = amp.
   * Plane-wave grids and seeded observation directions.
+  * 2-D contours (the paper's Sec. IV geometries): an ellipse of aspect ratio
+    1.5 and perimeter 2 pi, a Joukowsky airfoil of perimeter 2 pi and the circle
+    of the same perimeter, as nodes equally spaced in arc length; seeded complex
+    Gaussian test matrices for the randomized range finder.
 
 Every triangle is listed counter-clockwise seen from outside (outward normal).
 """
@@ -33,6 +37,10 @@ __all__ = [
     "monostatic_grid",
     "planewave_x_along_minus_z",
     "ellipsoid_batch",
+    "contour_ellipse",
+    "contour_joukowsky",
+    "contour_circle",
+    "gaussian_block",
 ]
 
 
@@ -212,3 +220,88 @@ def monostatic_grid(ntheta: int = 16, nphi: int = 32):
 def planewave_x_along_minus_z():
     """The single plane wave of the small sphere case: propagation -z, polarisation +x."""
     return np.array([[0.0, 0.0, -1.0]]), np.array([[1.0, 0.0, 0.0]])
+
+
+# ------------------------------------------------------------- 2-D contours
+def _equal_arclength(curve, n: int, samples: int = 1 << 16):
+    """n points of the closed parametric curve z(t), t in [0, 1), equally spaced in
+    arc length, counter-clockwise, the first at t = 0; and the curve's perimeter.
+    Arc length from composite 5-point Gauss-Legendre on `samples` intervals, the
+    inverse by interpolation refined with Newton steps on |z'(t)|."""
+    x, w = np.polynomial.legendre.leggauss(5)
+    t0 = np.arange(samples) / samples
+    h = 1.0 / samples
+    tq = t0[:, None] + 0.5 * h * (x[None, :] + 1.0)
+    _, dz = curve(tq)
+    seg = 0.5 * h * (np.abs(dz) * w[None, :]).sum(axis=1)
+    cum = np.concatenate([[0.0], np.cumsum(seg)])
+    per = cum[-1]
+    target = per * np.arange(n) / n
+    t = np.interp(target, cum, np.concatenate([t0, [1.0]]))
+    for _ in range(3):   # Newton on s(t) = target with the local 5-point arc length
+        i = np.minimum((t * samples).astype(np.int64), samples - 1)
+        a = t0[i]
+        tl = a[:, None] + 0.5 * (t - a)[:, None] * (x[None, :] + 1.0)
+        _, dzl = curve(tl)
+        s = cum[i] + 0.5 * (t - a) * (np.abs(dzl) * w[None, :]).sum(axis=1)
+        _, dzt = curve(t)
+        t = t - (s - target) / np.abs(dzt)
+    z, _ = curve(t)
+    return np.stack([z.real, z.imag], axis=1), per
+
+
+def contour_ellipse(n: int, aspect: float = 1.5, perimeter: float = 2.0 * math.pi):
+    """n nodes of the ellipse x^2/a^2 + y^2/b^2 = 1 with a = aspect * b and the given
+    perimeter, equally spaced in arc length, counter-clockwise from (a, 0)."""
+    from scipy.special import ellipe
+
+    e2 = 1.0 - 1.0 / aspect ** 2
+    b = perimeter / (4.0 * aspect * ellipe(e2))          # perimeter = 4 a E(e)
+    a = aspect * b
+
+    def curve(t):
+        th = 2.0 * math.pi * t
+        return a * np.cos(th) + 1j * b * np.sin(th), 2.0 * math.pi * (-a * np.sin(th) + 1j * b * np.cos(th))
+
+    nodes, _ = _equal_arclength(curve, n)
+    return nodes
+
+
+def contour_joukowsky(n: int, center=(-0.08, 0.08), round_te: float = 1.02, perimeter: float = 2.0 * math.pi):
+    """n nodes of a Joukowsky airfoil w = z + 1/z, the image of the circle through
+    z = 1 about `center` with its radius enlarged by round_te (a rounded trailing
+    edge instead of the cusp), scaled to the given perimeter; equally spaced in arc
+    length, counter-clockwise, the first node at the trailing edge."""
+    c = complex(*center)
+    r0 = round_te * abs(1.0 - c)
+
+    def raw(t):
+        th = 2.0 * math.pi * t
+        z = c + r0 * np.exp(1j * th)
+        dz = 2.0j * math.pi * r0 * np.exp(1j * th)
+        return z + 1.0 / z, dz * (1.0 - 1.0 / z ** 2)
+
+    _, per = _equal_arclength(raw, 8, samples=1 << 16)
+    s = perimeter / per
+
+    def curve(t):
+        w, dw = raw(t)
+        return s * w, s * dw
+
+    nodes, _ = _equal_arclength(curve, n)
+    return nodes
+
+
+def contour_circle(n: int, perimeter: float = 2.0 * math.pi):
+    """n nodes of the circle of the given perimeter, node i at angle 2 pi i / n."""
+    r = perimeter / (2.0 * math.pi)
+    th = 2.0 * math.pi * np.arange(n) / n
+    return np.stack([r * np.cos(th), r * np.sin(th)], axis=1)
+
+
+def gaussian_block(n: int, cols: int, seed: int = 0):
+    """Seeded complex Gaussian test matrix (n, cols): real and imaginary parts
+    N(0, 1/2), so that each entry has unit variance (the random draws of a
+    randomized range finder, passed to it as an input)."""
+    rng = np.random.default_rng(seed)
+    return (rng.standard_normal((n, cols)) + 1j * rng.standard_normal((n, cols))) / math.sqrt(2.0)

@@ -1,0 +1,167 @@
+"""Pins of the 2-D oracle (oracle/bie2d.py) against closed forms, separation of
+variables on the circle and invariants -- none re-types the oracle's formulas:
+
+  * the closed-form log moments of the self-segment rule against adaptive
+    numerical integration;
+  * the Gram matrix: its entries sum to the perimeter;
+  * S and N complex symmetric; every matrix circulant on the regular polygon;
+  * on the circle, the discrete eigenvalues of G^-1 S, G^-1 D* and G^-1 N tend to
+    the continuous ones -(j pi/2) J_n H_n, -(j pi k/2) J_n' H_n - 1/2 and
+    (j pi k^2/2) J_n' H_n' (addition theorem), and N S + D*^2 = 1/4 (Calderon);
+  * the PEC-cylinder current and echo width of the separated-variables series,
+    with O(h^2) convergence of the CFIE and C_p solutions;
+  * the resonances: at k a = 2.4048 (J_0 = 0, where S is singular) and at
+    k a = 1.2558 (J_0 = k a J_1, where the unit-coupled C = S + G/2 + D* is),
+    C_p stays well conditioned while S or C degrade as the mesh is refined;
+  * the fast direct solver: Q orthonormal, Halko's a-posteriori bound, rank 0 for
+    the circle against itself, the Woodbury identity exact for C_c + U V^T, the
+    solution within the skeleton tolerance of a dense solve.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, special
+
+import synth
+from oracle import bie2d as b2
+
+
+def _system(nodes, k, kt=None):
+    return b2.System(b2.Contour(nodes), k, kt)
+
+
+def test_log_moments_closed_form():
+    for a in range(2):
+        for b in range(2):
+            fa = (lambda x: 1.0 - x) if a == 0 else (lambda x: x)
+            fb = (lambda y: 1.0 - y) if b == 0 else (lambda y: y)
+            lo = integrate.dblquad(lambda y, x: fa(x) * fb(y) * math.log(x - y), 0, 1, 0, lambda x: x,
+                                   epsabs=1e-13, epsrel=1e-13)[0]
+            hi = integrate.dblquad(lambda y, x: fa(x) * fb(y) * math.log(y - x), 0, 1, lambda x: x, 1,
+                                   epsabs=1e-13, epsrel=1e-13)[0]
+            assert abs(lo + hi - b2._LOGMOM[a, b]) < 1e-9
+
+
+def test_gram_sum_is_perimeter():
+    c = b2.Contour(synth.contour_ellipse(97))
+    G = b2.gram(c)
+    assert abs(G.sum() - c.perimeter) < 1e-13
+    assert np.allclose(G, G.T)
+
+
+def test_symmetry_and_circulant():
+    s = _system(synth.contour_ellipse(60), 7.0)
+    assert np.abs(s.S - s.S.T).max() <= 1e-14 * np.abs(s.S).max()
+    assert np.abs(s.Nt - s.Nt.T).max() <= 1e-13 * np.abs(s.Nt).max()
+    sc = _system(synth.contour_circle(60), 7.0)
+    for M in (sc.S, sc.D, sc.Nt, sc.Dt, sc.calderon()):
+        rolled = np.roll(np.roll(M, 1, axis=0), 1, axis=1)
+        assert np.abs(M - rolled).max() <= 1e-12 * np.abs(M).max()
+
+
+def test_circle_eigenvalues_and_calderon_identity():
+    k = 5.0
+    errs = {}
+    for N in (100, 200):
+        s = _system(synth.contour_circle(N), k, kt=k)     # k~ = k: the Calderon identity holds
+        ph = 2.0 * math.pi * np.arange(N) / N
+        e = []
+        for n in (0, 1, 3, 6):
+            v = np.exp(1j * n * ph)
+            g = (s.G @ v)[0]
+            lS, lD, lN = (s.S @ v)[0] / g, (s.D @ v)[0] / g, (s.Nt @ v)[0] / g
+            J, Jp, H, Hp = special.jv(n, k), special.jvp(n, k), special.hankel2(n, k), special.h2vp(n, k)
+            e.append(max(abs(lS + 0.5j * math.pi * J * H) / abs(J * H),
+                         abs(lD - (-0.5j * math.pi * k * Jp * H - 0.5)),
+                         abs(lN - 0.5j * math.pi * k * k * Jp * Hp) / abs(k * k * Jp * Hp),
+                         abs(lN * lS + lD * lD - 0.25)))
+        errs[N] = max(e)
+    assert errs[200] <= 2e-3
+    assert errs[100] / errs[200] > 3.0          # second order in the mesh size
+
+
+@pytest.mark.parametrize("k", [5.0, 10.0])
+def test_cylinder_current_and_echo_width(k):
+    errs = []
+    for N in (100, 200):
+        nodes = synth.contour_circle(N)
+        s = _system(nodes, k)
+        c = s.c
+        e, h = b2.excitation(c, k, [0.3])
+        phi = np.arctan2(nodes[:, 1], nodes[:, 0])
+        ja = b2.cylinder_current(k, 1.0, phi, 0.3)
+        j1 = np.linalg.solve(s.cfie(), s.cfie_rhs(e, h)[0])
+        j2 = np.linalg.solve(s.calderon(), s.calderon_rhs(e, h)[0])
+        e1 = np.linalg.norm(j1 - ja) / np.linalg.norm(ja)
+        e2 = np.linalg.norm(j2 - ja) / np.linalg.norm(ja)
+        errs.append(max(e1, e2))
+        obs = np.linspace(0.0, 2.0 * math.pi, 73)
+        sw = b2.echo_width(k, b2.farfield(c, k, j2, obs)[0])
+        sa = b2.cylinder_echo_width(k, 1.0, obs, 0.3)
+        db = np.abs(10 * np.log10(sw / sa))
+        keep = 10 * np.log10(sa / sa.max()) > -30
+        errs.append(0.0)
+        if N == 200:
+            assert db[keep].max() < 0.05
+    assert errs[2] < (2e-3 if k == 5.0 else 8e-3)
+    assert errs[0] / errs[2] > 3.0
+
+
+@pytest.mark.parametrize("k", [2.404825557695773, 1.2557837117948])
+def test_calderon_resonance_free(k):
+    conds = []
+    for N in (50, 100, 200):
+        s = _system(synth.contour_circle(N), k)
+        conds.append((np.linalg.cond(s.S), np.linalg.cond(s.cfie()), np.linalg.cond(s.calderon())))
+    cS, cC, cP = np.array(conds).T
+    assert cP.max() < 8.0 and cP.max() / cP.min() < 1.05
+    worst = cS if k > 2 else cC                   # the operator that resonates at this k
+    assert worst[2] / worst[0] > 3.5 and worst[2] > 50 * cP[2]
+
+
+def test_fast_direct_solver():
+    k, N = 10.0, 180
+    kt = b2.ktilde(k, a=1.0)
+    s = _system(synth.contour_ellipse(N), k, kt)
+    sc = _system(synth.contour_circle(N), k, kt)
+    Cp, Cc = s.calderon(), sc.calderon()
+    om = synth.gaussian_block(N, N, seed=0)
+    tol = 1e-4
+    fd = b2.FastDirect(Cp, Cc, om, 16, tol)
+    Q = fd.Q
+    assert 0 < fd.rank < N and fd.rank % 16 == 0
+    assert np.abs(Q.conj().T @ Q - np.eye(fd.rank)).max() < 1e-12
+    A = Cp - Cc
+    err = np.linalg.norm(A - Q @ fd.Vt, 2)
+    # Halko et al. (2011, Lemma 4.1): ||(I - Q Q^H) A|| <= 10 sqrt(2/pi) max_i ||(I - Q Q^H) A w_i||
+    # with probability 1 - 10^-block, for Gaussian w_i of unit variance
+    assert err <= 10 * math.sqrt(2 / math.pi) * fd.est
+    e, h = b2.excitation(s.c, k, [0.0, 1.2])
+    bp = s.calderon_rhs(e, h).T
+    x = fd.solve(bp)
+    # the Woodbury formula inverts C_c + U V^T exactly
+    lhs = Cc @ x + Q @ (fd.Vt @ x)
+    assert np.linalg.norm(lhs - bp) <= 1e-11 * np.linalg.norm(bp)
+    xd = np.linalg.solve(Cp, bp)
+    rel = np.linalg.norm(x - xd) / np.linalg.norm(xd)
+    assert rel <= 10 * tol * np.linalg.cond(Cp)
+    # the circle against its own counterpart: nothing to compress
+    fc = b2.FastDirect(Cc, Cc, om, 16, tol)
+    assert fc.rank == 0
+    xc = fc.solve(bp)
+    assert np.linalg.norm(Cc @ xc - bp) <= 1e-12 * np.linalg.norm(bp)
+
+
+def test_ktilde_mean_curvature_radius():
+    """a = P / 2 pi, the reciprocal of the arc-length mean of the curvature (the
+    total curvature of a closed curve is 2 pi): 1 for the perimeter-2 pi contours,
+    which their polygons approach as they are refined."""
+    assert b2.ktilde(8.0, a=1.0) == complex(8.0, -0.8)
+    assert b2.ktilde(1.0, a=8.0) == complex(1.0, -0.1)
+    for make in (synth.contour_ellipse, synth.contour_circle):
+        d = [abs(b2.Contour(make(n)).perimeter / (2.0 * math.pi) - 1.0) for n in (200, 400)]
+        assert d[1] < 2e-5 and d[0] / d[1] > 3.5            # the polygon perimeter converges as h^2
+    # the airfoil's rounded trailing edge (radius of curvature below the node spacing
+    # here) keeps its polygon 0.14 % short at 400 nodes
+    assert abs(b2.Contour(synth.contour_joukowsky(400)).perimeter / (2.0 * math.pi) - 1.0) < 2e-3
