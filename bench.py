@@ -493,6 +493,110 @@ def bench_far_rule(args, P, synth, torch, np, dev):
     print(json.dumps(out), flush=True)
 
 
+# the paper's Table I: skeleton compression time of the ellipse (aspect ratio 1.5,
+# perimeter 2 pi) on 25 parallel processes (hardware not stated)
+PAPER_TABLE1 = {15011: (833.91, 59.33), 30021: (1667.8, 129.6), 45032: (2501.7, 210.2)}
+
+
+def bench_bie2d(args, P, synth, torch, np, dev):
+    """The paper's 2-D fast direct solver (Sec. III-IV): for each ellipse of the
+    paper's Table I (or --bie2d-n / --bie2d-k), assemble S_k, D*_k, N_k~, D*_k~ and
+    the circular counterpart, compress C_p - C_p,c by the randomized skeleton to
+    --bie2d-tol, factor the Woodbury inverse, and solve for --bie2d-nrhs plane waves;
+    the stabilized system's residual ||C_p x - b_p|| / ||b_p|| checks the solve.
+    Times are wall clock around each phase (device synchronised)."""
+    import math
+
+    cases = [(n, kk) for n, (kk, _) in sorted(PAPER_TABLE1.items())]
+    if args.bie2d_n:
+        cases = [(int(n), float(kk)) for n, kk in zip(args.bie2d_n, args.bie2d_k)]
+    geom = {"ellipse": synth.contour_ellipse, "airfoil": synth.contour_joukowsky}[args.bie2d_geom]
+    rows = []
+    for n, k in cases:
+        nodes, circ = geom(n), synth.contour_circle(n)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = P.Bie2d(nodes, circ, device=dev)
+        rmax = min(n, args.bie2d_rmax)
+        h.setup(k, rmax=rmax, block=64, nvec=max(64, args.bie2d_nrhs))
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t0
+        g = torch.Generator(device=dev).manual_seed(0)
+        om = torch.randn((rmax + 64, n), dtype=torch.complex128, device=dev, generator=g)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rank, est, ref = h.skeleton(om, args.bie2d_tol)
+        torch.cuda.synchronize()
+        t_skel = time.perf_counter() - t0
+        del om
+        phis = 2.0 * math.pi * np.arange(args.bie2d_nrhs) / args.bie2d_nrhs
+        e, hv, bp = h.rhs(phis)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x = h.solve(bp)
+        torch.cuda.synchronize()
+        t_solve = time.perf_counter() - t0
+        res = (h.apply("cp", x) - bp).norm(dim=1) / bp.norm(dim=1)
+        paper = PAPER_TABLE1.get(n)
+        row = {"n": n, "k0": k, "nodes_per_wavelength": round(n * 2.0 * math.pi / (k * h.perimeter()), 2),
+               "rank": rank, "tol": args.bie2d_tol, "est_rel": est / ref if ref else 0.0,
+               "setup_s": round(t_setup, 3), "skeleton_s": round(t_skel, 3), "solve_s": round(t_solve, 4),
+               "nrhs": args.bie2d_nrhs, "residual_max": float(res.max()),
+               "paper_skeleton_s": None if paper is None or abs(paper[0] - k) > 1e-6 else paper[1]}
+        log(f"bench: bie2d {row}")
+        rows.append(row)
+        del h, e, hv, bp, x
+        torch.cuda.empty_cache()
+    main = rows[-1]
+    out = {
+        "metric": "skeleton compression time of C_p - C_p,c (paper Table I)",
+        "value": main["skeleton_s"],
+        "unit": "s",
+        "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": round(1e3 * (main["setup_s"] + main["skeleton_s"]), 1),
+        "higher_is_better": False, "scaling": "strong",
+        "vs_baseline": None if main["paper_skeleton_s"] is None else round(main["skeleton_s"] / main["paper_skeleton_s"], 5),
+        "dtype": "c128", "data": "synthetic",
+        "config": {"workload": f"2-D PEC {args.bie2d_geom} (aspect 1.5, perimeter 2 pi), TM, Calderon-stabilized CFIE "
+                               f"C_p (eq. 16), randomized skeleton of C_p - C_p,c to {args.bie2d_tol:g} and Woodbury "
+                               f"inverse (eqs. 17-18); N and k0 of the paper's Table I",
+                   "cases": [[r["n"], r["k0"]] for r in rows]},
+        "cases": rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_bie2d_rank(args, P, synth, torch, np, dev):
+    """Skeleton rank of C_p - C_p,c against k0 (the paper's Figs. 1-2, whose data
+    are not in the text) for the ellipse and the airfoil at a fixed number of nodes
+    per wavelength."""
+    import math
+
+    out = {"metric": "skeleton rank of C_p - C_p,c vs k0", "unit": "rank", "tol": args.bie2d_tol,
+           "nodes_per_wavelength": args.bie2d_ppw, "curves": {}}
+    for geom, make in (("ellipse", synth.contour_ellipse), ("airfoil", synth.contour_joukowsky)):
+        pts = []
+        for k in args.bie2d_ks:
+            n = int(round(args.bie2d_ppw * k))          # perimeter 2 pi: k0 wavelengths
+            h = P.Bie2d(make(n), synth.contour_circle(n), device=dev)
+            rmax = min(n, args.bie2d_rmax)
+            h.setup(k, rmax=rmax, block=32, nvec=32)
+            g = torch.Generator(device=dev).manual_seed(0)
+            om = torch.randn((rmax + 32, n), dtype=torch.complex128, device=dev, generator=g)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rank, est, ref = h.skeleton(om, args.bie2d_tol)
+            torch.cuda.synchronize()
+            pts.append({"k0": k, "n": n, "rank": rank, "skeleton_s": round(time.perf_counter() - t0, 3)})
+            log(f"bench: bie2d rank {geom} {pts[-1]}")
+            del h, om
+            torch.cuda.empty_cache()
+        ks = np.array([p["k0"] for p in pts])
+        rk = np.array([max(p["rank"], 1) for p in pts], dtype=float)
+        slope = np.polyfit(np.log(ks[-3:]), np.log(rk[-3:]), 1)[0] if len(ks) >= 3 else None
+        out["curves"][geom] = {"points": pts, "loglog_slope_last3": None if slope is None else round(float(slope), 3)}
+    print(json.dumps(out), flush=True)
+
+
 def fp64_leg(args, P, torch, np, m, kh_d, po_d, V, J, cal):
     """The plain FP64 path on the same inputs, timed like a step (after the mixed
     steps, --fp64-steps of them, no warm-up): complex128 Z, complex128 P (the same
@@ -534,7 +638,7 @@ def main():
                     help="calderon: CGS on P Z J = P V with P = T_BC(k~) G_mix^-1 built in the step (default); "
                          "cocg: unpreconditioned COCG")
     ap.add_argument("--workload", choices=["sphere", "ellipsoids", "calderon", "mixed-fp64", "gradient",
-                                           "far-rule"],
+                                           "far-rule", "bie2d", "bie2d-rank"],
                     default="sphere",
                     help="sphere: the 512-RHS level-5 sphere (default); ellipsoids: 64 uneven ellipsoids; "
                          "calderon: level-4 Calderon vs plain CGS; mixed-fp64: level-5 mixed vs FP64 path; "
@@ -553,6 +657,14 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=1,
                     help="after the timed mixed steps, time this many steps of the plain FP64 path "
                          "(complex128 Z and P, FP64 products; Calderon solver only; 0: skip)")
+    ap.add_argument("--bie2d-n", type=int, nargs="*", help="2-D workload: node counts (default: the paper's Table I)")
+    ap.add_argument("--bie2d-k", type=float, nargs="*", help="2-D workload: wavenumbers, one per --bie2d-n")
+    ap.add_argument("--bie2d-geom", choices=["ellipse", "airfoil"], default="ellipse")
+    ap.add_argument("--bie2d-tol", type=float, default=1e-4)
+    ap.add_argument("--bie2d-rmax", type=int, default=4096)
+    ap.add_argument("--bie2d-nrhs", type=int, default=64)
+    ap.add_argument("--bie2d-ks", type=float, nargs="*", default=[25, 50, 100, 200, 400, 834])
+    ap.add_argument("--bie2d-ppw", type=float, default=18.0, help="bie2d-rank: nodes per wavelength")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -586,6 +698,12 @@ def main():
         return
     if args.workload == "far-rule":
         bench_far_rule(args, P, synth, torch, np, dev)
+        return
+    if args.workload == "bie2d":
+        bench_bie2d(args, P, synth, torch, np, dev)
+        return
+    if args.workload == "bie2d-rank":
+        bench_bie2d_rank(args, P, synth, torch, np, dev)
         return
     v, f = synth.icosphere(args.level)
     m = P.Mesh(v, f).upload(dev)

@@ -485,6 +485,84 @@ int efie_batch_solve(efie_batch b, const void* Zcat, int dtype, const void* Vcat
                      const efie_solve_opts* opts, efie_rhs_stats* stats, void* ws, size_t ws_bytes,
                      hipStream_t stream);
 
+/* ------------------------------------------------ the paper's 2-D method */
+
+/*
+ * The paper's own method on a closed curve (Sec. II-III): the boundary integral
+ * operators of eqs. 1-5 with G_k(R) = -(j/4) H0^(2)(k R), discretized by
+ * Galerkin with piecewise-linear functions on the polygon through the nodes, the
+ * TM CFIE of a PEC cylinder (eq. 7, first row), its Calderon-stabilized form
+ *   C_p = N_k~ G^-1 S_k + (G/2 - D*_k~) G^-1 (G/2 + D*_k)            (eq. 16)
+ * and the fast direct solver: C_p = C_p,c + C_p,ext with C_p,c the circular
+ * counterpart (C_p on a circle with the same node count, circulant), a skeleton
+ * C_p,ext ~ U V^T from an adaptive randomized range finder, and
+ *   C_p^-1 = C_c^-1 - C_c^-1 U (I + V^T C_c^-1 U)^-1 V^T C_c^-1      (eqs. 17-18).
+ * Readings (the paper names none of them): Maue's form of N,
+ *   (lambda_i, N lambda_j) = int int G [lambda_i' lambda_j' - k^2 (n.n') lambda_i lambda_j];
+ * q x q Gauss-Legendre on segment pairs that share no node, a graded Duffy rule
+ * (8 x 8 per triangle) on adjacent pairs, the self pair's log part in closed form;
+ * TM excitation E_z = exp(-j k khat . r), khat = (cos phi, sin phi),
+ * e_i = (lambda_i, E_z), h_i = (lambda_i, H_t) with H_t = -(khat . n) E_z / eta, and
+ *   b_p = N_k~ G^-1 e/(j k eta) + (G/2 - D*_k~) G^-1 h;
+ * the range finder samples blocks of a caller-given test matrix, projects each
+ * twice against the basis so far and stops when its largest column norm is at
+ * most tol times that of C_p Omega_0 (the first block applied to C_p).
+ * Vectors are rows: (count, n) complex128, row-major.  All arithmetic FP64, the
+ * dense products on FP64 matrix cores.
+ *
+ * efie_bie2d_create: nodes and circle_nodes host (n x 2), counter-clockwise (node
+ *   i of the circle is the counterpart of node i of the curve); q = 2..6 or 8
+ *   Gauss points per segment.  Errors: EFIE_ERR_ARG, EFIE_ERR_DEGENERATE (zero-length
+ *   segment), EFIE_ERR_MESH_ORIENT (clockwise contour).
+ * efie_bie2d_sizes: table_bytes for efie_bie2d_upload; ws_bytes of the workspace of
+ *   efie_bie2d_setup for a skeleton of rank <= rmax, blocks of `block` columns
+ *   (<= 64) and up to nvec vectors per call (nvec >= block).  The workspace holds
+ *   S_k, D*_k, N_k~, D*_k~ (4 n^2 complex128) and the skeleton's factors.
+ * efie_bie2d_assemble: a window [row0, row0 + nrows) x [col0, col0 + ncols) of
+ *   S_k, D*_k and N_k of contour `which` (0 the curve, 1 the circle) into the
+ *   non-null outputs (dev, row-major with leading dimension ld).
+ * efie_bie2d_setup: assembles the four operators of C_p at k and k~ and the
+ *   counterpart's first column (and its inverse's) from the spectra of its
+ *   factors on the circle; the workspace must stay alive for the later calls.
+ * efie_bie2d_apply: Y = op X for nvec rows, op 0: C_p, 1: C_p^T, 2: C_c, 3: C_c^-1,
+ *   4: G^-1, 5: C_p - C_c.
+ * efie_bie2d_rhs: e, h (and b_p if bp is not null) for plane waves of incidence
+ *   angles phis (host, nrhs); synchronises.
+ * efie_bie2d_skeleton: the range finder on A = C_p - C_p,c with the test matrix
+ *   omega (dev, ncols x n rows, ncols >= block; the last block may be partial): *rank, the last projected block's
+ *   largest column norm *est and the reference scale *ref (host); then
+ *   V^T = U^H A, W = C_c^-1 U and the LU factors of I + V^T W.  Synchronises.
+ *   EFIE_ERR_ARG if rank would exceed rmax or omega runs out; EFIE_ERR_BREAKDOWN
+ *   if a factorization fails.
+ * efie_bie2d_solve: X = C_p^-1 B by the Woodbury formula (nrhs rows, <= nvec).
+ * efie_bie2d_factors: copies U (rank x n rows) and V^T (rank x n) into dev buffers.
+ * efie_bie2d_counterpart: the first columns of C_p,c and of its inverse (dev, n).
+ * efie_bie2d_farfield: F[s][d] = int J_s exp(j k rhat_d . r) dS (2-D far-field
+ *   amplitude; echo width (k eta^2 / 4) |F|^2), phis dev (nphi), F dev (nrhs x nphi).
+ * efie_bie2d_perimeter: the polygon perimeter of contour `which` (host).
+ */
+typedef struct efie_bie2d_s* efie_bie2d;
+int efie_bie2d_create(const double* nodes, const double* circle_nodes, int64_t n, int q, efie_bie2d* out);
+void efie_bie2d_destroy(efie_bie2d h);
+int efie_bie2d_sizes(efie_bie2d h, int64_t rmax, int64_t block, int64_t nvec, size_t* table_bytes,
+                     size_t* ws_bytes);
+int efie_bie2d_upload(efie_bie2d h, void* dev, size_t bytes, hipStream_t stream);
+int efie_bie2d_perimeter(efie_bie2d h, int which, double* perimeter);
+int efie_bie2d_assemble(efie_bie2d h, int which, double k_re, double k_im, void* S, void* Dstar, void* Nm,
+                        int64_t row0, int64_t nrows, int64_t col0, int64_t ncols, int64_t ld, hipStream_t stream);
+int efie_bie2d_setup(efie_bie2d h, double k, double kt_re, double kt_im, int64_t rmax, int64_t block, int64_t nvec,
+                     void* ws, size_t ws_bytes, hipStream_t stream);
+int efie_bie2d_apply(efie_bie2d h, int op, const void* X, void* Y, int64_t nvec, hipStream_t stream);
+int efie_bie2d_rhs(efie_bie2d h, const double* phis, int64_t nrhs, double eta, void* e, void* hv, void* bp,
+                   hipStream_t stream);
+int efie_bie2d_skeleton(efie_bie2d h, const void* omega, int64_t ncols, double tol, int64_t* rank, double* est,
+                        double* ref, hipStream_t stream);
+int efie_bie2d_solve(efie_bie2d h, const void* B, void* X, int64_t nrhs, hipStream_t stream);
+int efie_bie2d_factors(efie_bie2d h, void* U, void* Vt, hipStream_t stream);
+int efie_bie2d_counterpart(efie_bie2d h, void* col, void* col_inv, hipStream_t stream);
+int efie_bie2d_farfield(efie_bie2d h, double k, const void* J, int64_t nrhs, const double* phis, int64_t nphi,
+                        void* F, hipStream_t stream);
+
 /* -------------------------------------------------------------- utilities */
 
 /*

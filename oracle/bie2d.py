@@ -242,6 +242,30 @@ def assemble(c, k, q=4):
     return S, D, Nm
 
 
+def assemble_rows(c, k, rows, q=4):
+    """Selected rows of (S_k, D*_k, N_k): each (len(rows), N), from the segment pairs
+    of the two segments around each row's node (the same blocks as assemble)."""
+    n = c.n
+    rows = list(rows)
+    out = [np.zeros((len(rows), n), dtype=complex) for _ in range(3)]
+    sig = np.array([-1.0, 1.0])
+    nn = c.nrm @ c.nrm.T
+    cols = (np.arange(n), (np.arange(n) + 1) % n)
+    for r, i in enumerate(rows):
+        for a, al in (((i - 1) % n, 1), (i, 0)):
+            mS, mD, m0 = _regular_row(c, k, a, q)
+            sb = c.L[a] * c.L[:, None, None] * mS
+            db = c.L[a] * c.L[:, None, None] * mD
+            nb = np.outer(sig, sig)[None] * m0[:, None, None] - k * k * nn[a][:, None, None] * sb
+            for b in {(a - 1) % n, a, (a + 1) % n}:
+                sb[b], db[b], nb[b] = pair_blocks(c, k, a, b, q)
+            for be in range(2):
+                np.add.at(out[0][r], cols[be], sb[:, al, be])
+                np.add.at(out[1][r], cols[be], db[:, al, be])
+                np.add.at(out[2][r], cols[be], nb[:, al, be])
+    return tuple(out)
+
+
 def gram(c):
     """(lambda_i, lambda_j): L/3 + L/3 on the diagonal, L/6 beside it (cyclic)."""
     n = c.n

@@ -49,6 +49,9 @@ EXPORTED = [
     "efie_assemble_workspace_size", "efie_assemble_ws", "efie_calderon_assemble_ex", "efie_solve_precond_ex",
     "efie_convert", "efie_ktilde", "efie_mesh_fp32_kmax", "efie_zx_flush64_noalloc_max", "efie_zx_flush64_noalloc",
     "efie_gemm_autotune_cached_workspace_size", "efie_gemm_autotune_cached",
+    "efie_bie2d_create", "efie_bie2d_destroy", "efie_bie2d_sizes", "efie_bie2d_upload", "efie_bie2d_perimeter",
+    "efie_bie2d_assemble", "efie_bie2d_setup", "efie_bie2d_apply", "efie_bie2d_rhs", "efie_bie2d_skeleton",
+    "efie_bie2d_solve", "efie_bie2d_factors", "efie_bie2d_counterpart", "efie_bie2d_farfield",
 ]
 PROF_IDS = {"far": 0, "near": 1, "mfma": 2, "gemv": 3, "zgemm": 4, "krylov": 5, "excite": 6, "farfield": 7, "grad_far": 8,
             "grad_near": 9, "grad_tri": 10}
@@ -125,6 +128,22 @@ def lib():
         "efie_ktilde": ([D, D, ctypes.POINTER(D), ctypes.POINTER(D)], ctypes.c_int),
         "efie_mesh_fp32_kmax": ([P, ctypes.POINTER(D)], ctypes.c_int),
         "efie_zx_flush64_noalloc_max": ([ctypes.POINTER(I64)], ctypes.c_int),
+        "efie_bie2d_create": ([P, P, I64, ctypes.c_int, ctypes.POINTER(P)], ctypes.c_int),
+        "efie_bie2d_destroy": ([P], None),
+        "efie_bie2d_sizes": ([P, I64, I64, I64, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)],
+                             ctypes.c_int),
+        "efie_bie2d_upload": ([P, P, ctypes.c_size_t, P], ctypes.c_int),
+        "efie_bie2d_perimeter": ([P, ctypes.c_int, ctypes.POINTER(D)], ctypes.c_int),
+        "efie_bie2d_assemble": ([P, ctypes.c_int, D, D, P, P, P, I64, I64, I64, I64, I64, P], ctypes.c_int),
+        "efie_bie2d_setup": ([P, D, D, D, I64, I64, I64, P, ctypes.c_size_t, P], ctypes.c_int),
+        "efie_bie2d_apply": ([P, ctypes.c_int, P, P, I64, P], ctypes.c_int),
+        "efie_bie2d_rhs": ([P, P, I64, D, P, P, P, P], ctypes.c_int),
+        "efie_bie2d_skeleton": ([P, P, I64, D, ctypes.POINTER(I64), ctypes.POINTER(D), ctypes.POINTER(D), P],
+                                ctypes.c_int),
+        "efie_bie2d_solve": ([P, P, P, I64, P], ctypes.c_int),
+        "efie_bie2d_factors": ([P, P, P, P], ctypes.c_int),
+        "efie_bie2d_counterpart": ([P, P, P, P], ctypes.c_int),
+        "efie_bie2d_farfield": ([P, D, P, I64, P, I64, P, P], ctypes.c_int),
         "efie_zx_flush64_noalloc": ([P, I64, P, P, I64, P], ctypes.c_int),
         "efie_gemm_autotune_cached_workspace_size": ([I64, I64, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "efie_gemm_autotune_cached": ([ctypes.c_char_p, P, I64, I64, ctypes.c_int, ctypes.c_int, P, ctypes.c_size_t,
@@ -734,4 +753,150 @@ class Batch:
         h = getattr(self, "_h", None)
         if h is not None and _lib is not None:
             _lib.efie_batch_destroy(h)
+            self._h = None
+
+
+# ------------------------------------------------------ the paper's 2-D method
+class Bie2d:
+    """The paper's 2-D fast direct solver on a closed curve (Sec. II-III): TM CFIE
+    of a PEC cylinder, its Calderon-stabilized operator C_p (eq. 16), the circular
+    counterpart C_p,c, a randomized skeleton of C_p - C_p,c and the Woodbury
+    inverse (eqs. 17-18).  Vectors are rows: (count, n) complex128 device tensors.
+
+    nodes, circle_nodes: (n, 2) counter-clockwise; q: Gauss points per segment."""
+
+    APPLY = {"cp": 0, "cpt": 1, "cc": 2, "ccinv": 3, "ginv": 4, "a": 5}
+
+    def __init__(self, nodes, circle_nodes, q: int = 4, device=None):
+        torch = _torch()
+        L = lib()
+        v = np.ascontiguousarray(nodes, dtype=np.float64)
+        c = np.ascontiguousarray(circle_nodes, dtype=np.float64)
+        if v.shape != c.shape or v.ndim != 2 or v.shape[1] != 2:
+            raise ValueError("nodes and circle_nodes must both be (n, 2)")
+        h = ctypes.c_void_p()
+        _check(L.efie_bie2d_create(v.ctypes.data, c.ctypes.data, len(v), int(q), ctypes.byref(h)))
+        self._h = h
+        self.n = len(v)
+        self.q = q
+        tb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(L.efie_bie2d_sizes(h, 0, 1, 1, ctypes.byref(tb), ctypes.byref(wb)))
+        self.device = torch.device(device or "cuda")
+        self._tab = torch.empty(tb.value + 256, dtype=torch.uint8, device=self.device)
+        off = (-self._tab.data_ptr()) % 256
+        _check(L.efie_bie2d_upload(h, ctypes.c_void_p(self._tab.data_ptr() + off), tb.value, _stream(self.device)))
+        self._ws = None
+        self.nvec = 0
+
+    def perimeter(self, which: int = 0) -> float:
+        p = ctypes.c_double()
+        _check(lib().efie_bie2d_perimeter(self._h, int(which), ctypes.byref(p)))
+        return p.value
+
+    def assemble(self, k, which: int = 0, rows=None, cols=None):
+        """(S, D*, N) at complex k on the curve (which = 0) or the circle (1), for the
+        window rows x cols (slices; default the whole matrix)."""
+        torch = _torch()
+        r0, r1 = (0, self.n) if rows is None else (rows.start or 0, rows.stop)
+        c0, c1 = (0, self.n) if cols is None else (cols.start or 0, cols.stop)
+        k = complex(k)
+        out = [torch.empty((r1 - r0, c1 - c0), dtype=torch.complex128, device=self.device) for _ in range(3)]
+        _check(lib().efie_bie2d_assemble(self._h, int(which), k.real, k.imag, *[_ptr(t) for t in out], r0, r1 - r0,
+                                          c0, c1 - c0, c1 - c0, _stream(self.device)))
+        return tuple(out)
+
+    def setup(self, k: float, kt=None, rmax: int | None = None, block: int = 64, nvec: int = 64, a: float = 1.0):
+        """Assemble S_k, D*_k, N_k~, D*_k~ and the counterpart (k~ = the paper's
+        complex wavenumber with radius a unless given); workspace for a skeleton of
+        rank <= rmax (default n) in blocks of `block` and calls of <= nvec vectors."""
+        torch = _torch()
+        kt = ktilde(k, a) if kt is None else complex(kt)
+        rmax = self.n if rmax is None else int(rmax)
+        nvec = max(int(nvec), int(block))
+        tb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(lib().efie_bie2d_sizes(self._h, rmax, int(block), nvec, ctypes.byref(tb), ctypes.byref(wb)))
+        self._ws = None
+        self._ws = torch.empty(wb.value + 256, dtype=torch.uint8, device=self.device)
+        off = (-self._ws.data_ptr()) % 256
+        _check(lib().efie_bie2d_setup(self._h, float(k), kt.real, kt.imag, rmax, int(block), nvec,
+                                      ctypes.c_void_p(self._ws.data_ptr() + off), wb.value, _stream(self.device)))
+        self.k, self.kt, self.rmax, self.block, self.nvec = float(k), kt, rmax, int(block), nvec
+        return self
+
+    def _vec(self, X, name):
+        torch = _torch()
+        X = X.reshape(-1, self.n)
+        _require_cuda(X, name)
+        if X.dtype != torch.complex128:
+            raise ValueError(f"{name} must be complex128")
+        return X
+
+    def apply(self, op: str, X):
+        """op X for rows X: "cp" C_p, "cpt" C_p^T, "cc" C_c, "ccinv" C_c^-1, "ginv" G^-1,
+        "a" C_p - C_c."""
+        torch = _torch()
+        X = self._vec(X, "X")
+        Y = torch.empty_like(X)
+        _check(lib().efie_bie2d_apply(self._h, self.APPLY[op], _ptr(X), _ptr(Y), X.shape[0], _stream(self.device)))
+        return Y
+
+    def rhs(self, phis, eta: float = ETA0, stabilized: bool = True):
+        """(e, h, b_p) for plane waves of incidence angles phis (b_p None unless stabilized)."""
+        torch = _torch()
+        ph = np.ascontiguousarray(np.atleast_1d(phis), dtype=np.float64)
+        e = torch.empty((len(ph), self.n), dtype=torch.complex128, device=self.device)
+        hv = torch.empty_like(e)
+        bp = torch.empty_like(e) if stabilized else None
+        _check(lib().efie_bie2d_rhs(self._h, ph.ctypes.data, len(ph), float(eta), _ptr(e), _ptr(hv),
+                                    _ptr(bp) if bp is not None else None, _stream(self.device)))
+        return e, hv, bp
+
+    def skeleton(self, omega, tol: float = 1e-4):
+        """Randomized skeleton of C_p - C_p,c with the test matrix omega (rows:
+        (ncols, n) complex128 device tensor); returns (rank, est, ref)."""
+        omega = self._vec(omega, "omega")
+        r, est, ref = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+        _check(lib().efie_bie2d_skeleton(self._h, _ptr(omega), omega.shape[0], float(tol), ctypes.byref(r),
+                                         ctypes.byref(est), ctypes.byref(ref), _stream(self.device)))
+        self.rank = r.value
+        return r.value, est.value, ref.value
+
+    def solve(self, B):
+        """X = C_p^-1 B (rows) by the Woodbury formula around the counterpart."""
+        torch = _torch()
+        B = self._vec(B, "B")
+        X = torch.empty_like(B)
+        _check(lib().efie_bie2d_solve(self._h, _ptr(B), _ptr(X), B.shape[0], _stream(self.device)))
+        return X
+
+    def factors(self):
+        """(U, V^T): rank x n rows each."""
+        torch = _torch()
+        U = torch.empty((self.rank, self.n), dtype=torch.complex128, device=self.device)
+        Vt = torch.empty_like(U)
+        _check(lib().efie_bie2d_factors(self._h, _ptr(U), _ptr(Vt), _stream(self.device)))
+        return U, Vt
+
+    def counterpart(self):
+        """First columns of C_p,c and of its inverse."""
+        torch = _torch()
+        c = torch.empty(self.n, dtype=torch.complex128, device=self.device)
+        ci = torch.empty_like(c)
+        _check(lib().efie_bie2d_counterpart(self._h, _ptr(c), _ptr(ci), _stream(self.device)))
+        return c, ci
+
+    def farfield(self, k: float, J, phis):
+        """F (nrhs, nphi): int J exp(j k rhat . r) dS at observation angles phis."""
+        torch = _torch()
+        J = self._vec(J, "J")
+        ph = torch.as_tensor(np.atleast_1d(phis), dtype=torch.float64, device=self.device).contiguous()
+        F = torch.empty((J.shape[0], ph.numel()), dtype=torch.complex128, device=self.device)
+        _check(lib().efie_bie2d_farfield(self._h, float(k), _ptr(J), J.shape[0], _ptr(ph), ph.numel(), _ptr(F),
+                                         _stream(self.device)))
+        return F
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.efie_bie2d_destroy(h)
             self._h = None

@@ -20,7 +20,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libefie.so")
 BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
 
-SOURCES = ["abi.cpp", "mesh.cpp", "prof.cpp", "assemble.hip", "linalg.hip", "gemm_mfma.hip", "krylov.hip", "excite.hip", "calderon.cpp", "calderon.hip", "batch.hip", "grad.hip", "gemm_tune.hip", "noalloc.hip"]
+SOURCES = ["abi.cpp", "mesh.cpp", "prof.cpp", "assemble.hip", "linalg.hip", "gemm_mfma.hip", "krylov.hip", "excite.hip", "calderon.cpp", "calderon.hip", "batch.hip", "grad.hip", "gemm_tune.hip", "noalloc.hip", "bie2d.hip", "bie2d_gemm.hip"]
 
 ARCH = "gfx950"
 

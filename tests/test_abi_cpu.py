@@ -138,3 +138,26 @@ def test_fp32_kmax_from_bounding_box():
     assert abs(m.fp32_kmax() - 512.0 * np.pi / diag) <= 1e-12 * m.fp32_kmax()
     m2 = P.Mesh(v * 10.0, f)
     assert abs(m2.fp32_kmax() * 10.0 - m.fp32_kmax()) <= 1e-12 * m.fp32_kmax()
+
+
+def test_bie2d_create_checks_the_contour():
+    """Host-side checks of the 2-D path's contour: orientation, degenerate segments,
+    the Gauss rule; the polygon perimeter (no GPU needed)."""
+    import ctypes
+
+    L = P.lib()
+    nodes = synth.contour_ellipse(64)
+    circ = synth.contour_circle(64)
+    h = ctypes.c_void_p()
+    rev = np.ascontiguousarray(nodes[::-1])
+    assert L.efie_bie2d_create(rev.ctypes.data, circ.ctypes.data, 64, 4, ctypes.byref(h)) == -4
+    dup = np.ascontiguousarray(nodes.copy())
+    dup[5] = dup[4]
+    assert L.efie_bie2d_create(dup.ctypes.data, circ.ctypes.data, 64, 4, ctypes.byref(h)) == -5
+    assert L.efie_bie2d_create(nodes.ctypes.data, circ.ctypes.data, 64, 7, ctypes.byref(h)) == -1
+    assert L.efie_bie2d_create(nodes.ctypes.data, circ.ctypes.data, 64, 4, ctypes.byref(h)) == 0
+    per = ctypes.c_double()
+    assert L.efie_bie2d_perimeter(h, 0, ctypes.byref(per)) == 0
+    d = np.linalg.norm(np.roll(nodes, -1, axis=0) - nodes, axis=1).sum()
+    assert abs(per.value - d) < 1e-13
+    L.efie_bie2d_destroy(h)
