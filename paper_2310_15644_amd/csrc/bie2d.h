@@ -31,7 +31,11 @@ enum Gemm2dOp { G2D_NT = 0, G2D_NN = 1, G2D_CIRC = 2 };
 //   NN:   B is K x Nc (ldb):  C[s][i] = sum_k A[s][k] B[k][i]
 //   CIRC: B is a vector c of length K = Nc: C[s][i] = sum_k A[s][k] c[(i - k) mod K]
 //   B conjugated if conjb.
+// With scratch (scratch_elems complex values), products with few output tiles and
+// a long contraction are split along K into partial products reduced in a second
+// pass (deterministic; no atomics).
 void gemm2d(int op, const double2* A, int lda, bool conja, const double2* B, int ldb, bool conjb, double2* C,
-            int ldc, int M, int Nc, int K, double2 alpha, bool accumulate, hipStream_t s);
+            int ldc, int M, int Nc, int K, double2 alpha, bool accumulate, hipStream_t s, double2* scratch = nullptr,
+            size_t scratch_elems = 0);
 
 }  // namespace efie

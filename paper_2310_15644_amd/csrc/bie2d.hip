@@ -621,18 +621,25 @@ __global__ __launch_bounds__(256) void chol_inv_kernel(const double2* __restrict
     if (tid == 0) *info = bad;
 }
 
-// LU with partial pivoting of the r x r matrix M (row-major, in place), one block
-__global__ __launch_bounds__(1024) void lu_kernel(double2* __restrict__ M, int r, int* __restrict__ piv,
-                                                  int* __restrict__ info) {
+// Blocked right-looking LU with partial pivoting of the r x r matrix M (row-major,
+// in place; the same factors and pivot order as the unblocked elimination): for
+// each panel of LU_NB columns, the panel is factored in one workgroup (pivot search
+// over its column below the diagonal, row swap within the panel, scaling, rank-1
+// update of the panel), its row swaps are applied to the columns outside the panel,
+// the block row to its right is solved against the panel's unit lower triangle, and
+// the trailing matrix takes the update A22 -= L21 U12 on the matrix cores.
+constexpr int LU_NB = 64;
+
+__global__ __launch_bounds__(1024) void lu_panel_kernel(double2* __restrict__ M, int r, int k0, int kb,
+                                                        int* __restrict__ piv, int* __restrict__ info) {
     __shared__ double vmax[1024];
     __shared__ int imax[1024];
     const int tid = threadIdx.x;
-    if (tid == 0) *info = 0;
-    for (int k = 0; k < r; ++k) {
+    for (int j = k0; j < k0 + kb; ++j) {
         double best = -1.0;
-        int bi = k;
-        for (int i = k + tid; i < r; i += 1024) {
-            const double v = cabs_(M[size_t(i) * r + k]);
+        int bi = j;
+        for (int i = j + tid; i < r; i += 1024) {
+            const double v = cabs_(M[size_t(i) * r + j]);
             if (v > best) {
                 best = v;
                 bi = i;
@@ -652,51 +659,99 @@ __global__ __launch_bounds__(1024) void lu_kernel(double2* __restrict__ M, int r
         const double pv = vmax[0];
         __syncthreads();
         if (tid == 0) {
-            piv[k] = p;
-            if (!(pv > 0.0) && *info == 0) *info = k + 1;
+            piv[j] = p;
+            if (!(pv > 0.0) && *info == 0) *info = j + 1;
         }
-        if (p != k)
-            for (int c = tid; c < r; c += 1024) {
-                const double2 t = M[size_t(k) * r + c];
-                M[size_t(k) * r + c] = M[size_t(p) * r + c];
+        if (p != j)
+            for (int c = k0 + tid; c < k0 + kb; c += 1024) {
+                const double2 t = M[size_t(j) * r + c];
+                M[size_t(j) * r + c] = M[size_t(p) * r + c];
                 M[size_t(p) * r + c] = t;
             }
         __syncthreads();
-        const double2 inv = pv > 0.0 ? crcp(M[size_t(k) * r + k]) : make_double2(0.0, 0.0);
-        for (int i = k + 1 + tid; i < r; i += 1024) M[size_t(i) * r + k] = cmul(M[size_t(i) * r + k], inv);
+        const double2 inv = pv > 0.0 ? crcp(M[size_t(j) * r + j]) : make_double2(0.0, 0.0);
+        for (int i = j + 1 + tid; i < r; i += 1024) M[size_t(i) * r + j] = cmul(M[size_t(i) * r + j], inv);
         __syncthreads();
-        const int w = r - k - 1;
-        for (size_t e = tid; e < size_t(w) * w; e += 1024) {
-            const int i = k + 1 + int(e / w), c = k + 1 + int(e % w);
-            M[size_t(i) * r + c] = csub(M[size_t(i) * r + c], cmul(M[size_t(i) * r + k], M[size_t(k) * r + c]));
-        }
+        const int w = k0 + kb - j - 1;
+        if (w > 0)
+            for (size_t e = tid; e < size_t(r - j - 1) * w; e += 1024) {
+                const int i = j + 1 + int(e / w), c = j + 1 + int(e % w);
+                M[size_t(i) * r + c] = csub(M[size_t(i) * r + c], cmul(M[size_t(i) * r + j], M[size_t(j) * r + c]));
+            }
         __syncthreads();
     }
 }
 
-// rows X[s] (r values each) overwritten by M^-1 X[s] from the LU factors: a thread per row
-__global__ void lu_solve_kernel(const double2* __restrict__ LU, const int* __restrict__ piv, int r,
-                                double2* __restrict__ X, int nrhs) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= nrhs) return;
-    double2* x = X + size_t(s) * r;
-    for (int k = 0; k < r; ++k) {
-        const int p = piv[k];
-        if (p != k) {
-            const double2 t = x[k];
-            x[k] = x[p];
-            x[p] = t;
+// the panel's row swaps (in pivot order) on the columns outside [k0, k0 + kb): a thread per column
+__global__ void lu_swap_kernel(double2* __restrict__ M, int r, int k0, int kb, const int* __restrict__ piv) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = t < k0 ? t : t + kb;          // skip the panel's columns
+    if (t >= r - kb) return;
+    for (int j = k0; j < k0 + kb; ++j) {
+        const int p = piv[j];
+        if (p != j) {
+            const double2 x = M[size_t(j) * r + c];
+            M[size_t(j) * r + c] = M[size_t(p) * r + c];
+            M[size_t(p) * r + c] = x;
         }
     }
-    for (int i = 0; i < r; ++i) {
-        double2 acc = x[i];
-        for (int m = 0; m < i; ++m) acc = csub(acc, cmul(LU[size_t(i) * r + m], x[m]));
-        x[i] = acc;
+}
+
+// U12 = L11^-1 A12 for the block row [k0, k0 + kb) right of the panel: a thread per column
+__global__ void lu_trsm_kernel(double2* __restrict__ M, int r, int k0, int kb) {
+    const int c = k0 + kb + blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= r) return;
+    for (int i = 1; i < kb; ++i) {
+        double2 acc = M[size_t(k0 + i) * r + c];
+        for (int t = 0; t < i; ++t) acc = csub(acc, cmul(M[size_t(k0 + i) * r + k0 + t], M[size_t(k0 + t) * r + c]));
+        M[size_t(k0 + i) * r + c] = acc;
     }
-    for (int i = r - 1; i >= 0; --i) {
-        double2 acc = x[i];
-        for (int m = i + 1; m < r; ++m) acc = csub(acc, cmul(LU[size_t(i) * r + m], x[m]));
-        x[i] = cdiv(acc, LU[size_t(i) * r + i]);
+}
+
+// sum over the block of 256 threads (four wavefronts)
+__device__ double2 block_sum(double2 v, double2* red) {
+    for (int o = 32; o > 0; o >>= 1) {
+        v.x += __shfl_down(v.x, o);
+        v.y += __shfl_down(v.y, o);
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    return cadd(cadd(red[0], red[1]), cadd(red[2], red[3]));
+}
+
+// row s of X (r values) overwritten by M^-1 X[s] from the LU factors: a block per
+// row, the substitutions row by row, each row's dot product over the block
+__global__ __launch_bounds__(256) void lu_solve_kernel(const double2* __restrict__ LU, const int* __restrict__ piv,
+                                                       int r, double2* __restrict__ X, int nrhs) {
+    __shared__ double2 red[4];
+    const int s = blockIdx.x;
+    if (s >= nrhs) return;
+    double2* x = X + size_t(s) * r;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < r; ++k) {
+            const int p = piv[k];
+            if (p != k) {
+                const double2 t = x[k];
+                x[k] = x[p];
+                x[p] = t;
+            }
+        }
+    __syncthreads();
+    for (int i = 1; i < r; ++i) {           // L (unit diagonal)
+        double2 acc = make_double2(0.0, 0.0);
+        for (int m = threadIdx.x; m < i; m += 256) acc = cadd(acc, cmul(LU[size_t(i) * r + m], x[m]));
+        const double2 t = block_sum(acc, red);
+        if (threadIdx.x == 0) x[i] = csub(x[i], t);
+        __syncthreads();
+    }
+    for (int i = r - 1; i >= 0; --i) {      // U
+        double2 acc = make_double2(0.0, 0.0);
+        for (int m = i + 1 + threadIdx.x; m < r; m += 256) acc = cadd(acc, cmul(LU[size_t(i) * r + m], x[m]));
+        const double2 t = block_sum(acc, red);
+        if (threadIdx.x == 0) x[i] = cdiv(csub(x[i], t), LU[size_t(i) * r + i]);
+        __syncthreads();
     }
 }
 
@@ -804,6 +859,8 @@ struct efie_bie2d_s {
     double2 *T1 = nullptr, *T2 = nullptr, *T3 = nullptr;                       // nvec x n temporaries
     double2 *Qm = nullptr, *Bm = nullptr, *Wm = nullptr, *Mm = nullptr;        // skeleton and Woodbury factors
     double2 *Gb = nullptr, *Tb = nullptr;                                      // block x block
+    double2* split = nullptr;                                                  // split-K partial products
+    size_t split_n = 0;
     double* nrm = nullptr;
     int* piv = nullptr;
     int* info = nullptr;
@@ -816,8 +873,12 @@ namespace {
 using efie::gemm2d;
 
 struct Layout {
-    size_t S, Dst, Nt, Dtt, cC, cCT, cI, cIT, eig, T1, T2, T3, Qm, Bm, Wm, Mm, Gb, Tb, nrm, piv, info, total;
+    size_t S, Dst, Nt, Dtt, cC, cCT, cI, cIT, eig, T1, T2, T3, Qm, Bm, Wm, Mm, Gb, Tb, nrm, piv, info, split, total;
 };
+
+// scratch of the split-K products (the range finder's projections onto the basis
+// and its Gram matrices): up to 64 partial products of 64 x max(rmax, 64)
+size_t split_elems(int64_t rmax) { return size_t(64) * 64 * size_t(std::max<int64_t>(rmax, 64)); }
 
 Layout layout(int64_t n, int64_t rmax, int64_t block, int64_t nvec) {
     Layout L{};
@@ -838,6 +899,7 @@ Layout layout(int64_t n, int64_t rmax, int64_t block, int64_t nvec) {
     L.nrm = take(size_t(std::max(nvec, block)) * 8);
     L.piv = take(size_t(rmax) * 4);
     L.info = take(64);
+    L.split = take(split_elems(rmax) * 16);
     L.total = o;
     return L;
 }
@@ -1042,6 +1104,8 @@ int efie_bie2d_setup(efie_bie2d h, double k, double kt_re, double kt_im, int64_t
         h->nrm = reinterpret_cast<double*>(w + L.nrm);
         h->piv = reinterpret_cast<int*>(w + L.piv);
         h->info = reinterpret_cast<int*>(w + L.info);
+        h->split = P(L.split);
+        h->split_n = split_elems(rmax);
         h->rank = -1;
         const int n = int(h->n);
         // the four operators of C_p on the scatterer
@@ -1149,7 +1213,8 @@ int efie_bie2d_skeleton(efie_bie2d h, const void* omega, int64_t ncols, double t
             apply_cp(*h, om + size_t(c0) * n, h->T3, mb, false, true, stream);
             for (int pass = 0; pass < 2 && r > 0; ++pass) {
                 // P (mb x r) = Y Q^H rows: P[s][t] = sum_k Y[s][k] conj(Q[t][k]); Y -= P Q
-                gemm2d(efie::G2D_NT, h->T3, n, false, h->Qm, n, true, h->T1, r, mb, r, n, ONE, false, stream);
+                gemm2d(efie::G2D_NT, h->T3, n, false, h->Qm, n, true, h->T1, r, mb, r, n, ONE, false, stream,
+                       h->split, h->split_n);
                 gemm2d(efie::G2D_NN, h->T1, r, false, h->Qm, n, false, h->T3, n, mb, n, r, MONE, true, stream);
             }
             hipLaunchKernelGGL(efie::row_norm_kernel, dim3(mb), dim3(256), 0, stream, h->T3, n, h->nrm);
@@ -1165,7 +1230,8 @@ int efie_bie2d_skeleton(efie_bie2d h, const void* omega, int64_t ncols, double t
                          "bie2d_skeleton: the rank exceeds rmax of the setup (raise rmax or tol)");
             // orthonormal basis of the block: shifted Cholesky QR, then two plain passes
             for (int pass = 0; pass < 3; ++pass) {
-                gemm2d(efie::G2D_NT, h->T3, n, true, h->T3, n, false, h->Gb, mb, mb, mb, n, ONE, false, stream);
+                gemm2d(efie::G2D_NT, h->T3, n, true, h->T3, n, false, h->Gb, mb, mb, mb, n, ONE, false, stream,
+                       h->split, h->split_n);
                 double shift = 0.0;
                 if (pass == 0) {
                     double mx = 0.0;
@@ -1183,7 +1249,8 @@ int efie_bie2d_skeleton(efie_bie2d h, const void* omega, int64_t ncols, double t
                 EFIE_REQUIRE(info == 0, EFIE_ERR_BREAKDOWN, "bie2d_skeleton: Cholesky QR broke down");
                 if (pass == 0 && r > 0) {
                     // the projection again after the shifted pass (round-off of the first)
-                    gemm2d(efie::G2D_NT, h->T3, n, false, h->Qm, n, true, h->T1, r, mb, r, n, ONE, false, stream);
+                    gemm2d(efie::G2D_NT, h->T3, n, false, h->Qm, n, true, h->T1, r, mb, r, n, ONE, false, stream,
+                           h->split, h->split_n);
                     gemm2d(efie::G2D_NN, h->T1, r, false, h->Qm, n, false, h->T3, n, mb, n, r, MONE, true, stream);
                 }
             }
@@ -1209,7 +1276,23 @@ int efie_bie2d_skeleton(efie_bie2d h, const void* omega, int64_t ncols, double t
             gemm2d(efie::G2D_CIRC, h->Qm, n, false, h->cI, 0, false, h->Wm, n, r, n, n, ONE, false, stream);
             gemm2d(efie::G2D_NT, h->Bm, n, false, h->Wm, n, false, h->Mm, r, r, r, n, ONE, false, stream);
             hipLaunchKernelGGL(efie::identity_add_kernel, dim3(efie::grid_of(r)), dim3(256), 0, stream, h->Mm, r);
-            hipLaunchKernelGGL(efie::lu_kernel, dim3(1), dim3(1024), 0, stream, h->Mm, r, h->piv, h->info);
+            efie::fill_zero_bytes(h->info, 8, stream);   // the failure flag (a fill kernel, no memset node)
+            for (int k0 = 0; k0 < r; k0 += efie::LU_NB) {
+                const int kb = std::min(efie::LU_NB, r - k0);
+                hipLaunchKernelGGL(efie::lu_panel_kernel, dim3(1), dim3(1024), 0, stream, h->Mm, r, k0, kb, h->piv,
+                                   h->info);
+                if (r - kb > 0)
+                    hipLaunchKernelGGL(efie::lu_swap_kernel, dim3(efie::grid_of(r - kb)), dim3(256), 0, stream, h->Mm, r,
+                                       k0, kb, h->piv);
+                const int rest = r - k0 - kb;
+                if (rest > 0) {
+                    hipLaunchKernelGGL(efie::lu_trsm_kernel, dim3(efie::grid_of(rest)), dim3(256), 0, stream, h->Mm, r,
+                                       k0, kb);
+                    // A22 -= L21 U12
+                    gemm2d(efie::G2D_NN, h->Mm + size_t(k0 + kb) * r + k0, r, false, h->Mm + size_t(k0) * r + k0 + kb, r,
+                           false, h->Mm + size_t(k0 + kb) * r + k0 + kb, r, rest, rest, kb, MONE, true, stream);
+                }
+            }
             int info = 0;
             EFIE_HIP_CHECK(hipMemcpyAsync(&info, h->info, 4, hipMemcpyDeviceToHost, stream));
             EFIE_HIP_CHECK(hipStreamSynchronize(stream));
@@ -1237,9 +1320,9 @@ int efie_bie2d_solve(efie_bie2d h, const void* B, void* X, int64_t nrhs, hipStre
                stream);
         if (r > 0) {
             EFIE_REQUIRE(size_t(nr) * r <= size_t(h->nvec) * n, EFIE_ERR_ARG, "bie2d_solve: too many right-hand sides");
-            gemm2d(efie::G2D_NT, x, n, false, h->Bm, n, false, h->T1, r, nr, r, n, ONE, false, stream);
-            hipLaunchKernelGGL(efie::lu_solve_kernel, dim3((nr + 63) / 64), dim3(64), 0, stream, h->Mm, h->piv, r,
-                               h->T1, nr);
+            gemm2d(efie::G2D_NT, x, n, false, h->Bm, n, false, h->T1, r, nr, r, n, ONE, false, stream, h->split,
+                   h->split_n);
+            hipLaunchKernelGGL(efie::lu_solve_kernel, dim3(nr), dim3(256), 0, stream, h->Mm, h->piv, r, h->T1, nr);
             gemm2d(efie::G2D_NN, h->T1, r, false, h->Wm, n, false, x, n, nr, n, r, MONE, true, stream);
         }
         EFIE_HIP_CHECK(hipGetLastError());
