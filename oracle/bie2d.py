@@ -44,6 +44,13 @@ with e_i = (lambda_i, E_z^inc), h_i = (lambda_i, H_t^inc) (q-point rule per
 segment).  The Calderon-stabilized operator (eq. 16) and its right-hand side:
   C_p = N_k~ G^-1 S_k + (G/2 - D*_k~) G^-1 (G/2 + D*_k),
   b_p = N_k~ G^-1 e/(j k eta) + (G/2 - D*_k~) G^-1 h,
+TE incidence H_z^inc = exp(-j k khat . r) (the paper's "other polarization", whose
+formulas it does not print; the readings follow by the same Calderon structure),
+unknown the tangential current j_t along t = z x n:
+  EFIE part  N j = (j k / eta) (lambda, E_t^inc),  E_t = eta (khat . n) H_z^inc,
+  MFIE part  (1/2 - D) j = -(lambda, H_z^inc),   D = D*^T the double layer,
+  C_p^TE = S_k~ G^-1 N_k + (G/2 + D_k~) G^-1 (G/2 - D_k)   (S N = 1/4 - D^2),
+  b_p^TE = S_k~ G^-1 (j k / eta) e_t - (G/2 + D_k~) G^-1 h_z.
 k~ = k - 0.4 j k^(1/3) a^(-2/3) with a = P / 2 pi, P the curve's perimeter (the
 reciprocal of the arc-length mean of the curvature of a closed curve, whose
 total curvature is 2 pi: a reading of the paper's "suitable average"; a = 1 for
@@ -303,15 +310,45 @@ def excitation(c, k, phis, q=4, eta=ETA0):
     return e, h
 
 
-class System:
-    """The operators of one contour at k (and k~): S_k, D*_k, N_k~, D*_k~, G."""
+def excitation_te(c, k, phis, q=4, eta=ETA0):
+    """(e_t, h_z): e_t,i = (lambda_i, E_t^inc), h_z,i = (lambda_i, H_z^inc) for TE plane
+    waves H_z^inc = exp(-j k khat . r): E = (eta / (j k)) grad(H_z) x z, so that
+    E_t = E . (z x n) = eta (khat . n) H_z.  Returns two (S, N) arrays."""
+    phis = np.atleast_1d(phis)
+    xg, wg = gauss01(q)
+    n = c.n
+    et = np.zeros((len(phis), n), dtype=complex)
+    hz = np.zeros((len(phis), n), dtype=complex)
+    pts = c.point(np.arange(n)[:, None], xg[None, :])
+    ph = _phi(xg)
+    for s, p in enumerate(phis):
+        kh = np.array([math.cos(p), math.sin(p)])
+        H = np.exp(-1j * k * (pts @ kh))
+        Et = eta * (c.nrm @ kh)[:, None] * H
+        for al in range(2):
+            idx = (np.arange(n) + al) % n
+            np.add.at(et[s], idx, c.L * np.sum(wg * ph[al] * Et, axis=1))
+            np.add.at(hz[s], idx, c.L * np.sum(wg * ph[al] * H, axis=1))
+    return et, hz
 
-    def __init__(self, c, k, kt=None, q=4):
+
+class System:
+    """The operators of one contour for one polarization: TM (S_k, D*_k, N_k~, D*_k~)
+    or TE (N_k, D*_k, S_k~, D*_k~), and G."""
+
+    def __init__(self, c, k, kt=None, q=4, pol="TM"):
         self.c = c
         self.k = complex(k)
         self.kt = ktilde(k) if kt is None else complex(kt)
-        self.S, self.D, _ = assemble(c, self.k, q)
-        _, self.Dt, self.Nt = assemble(c, self.kt, q)
+        self.pol = pol
+        if pol == "TM":
+            self.S, self.D, _ = assemble(c, self.k, q)
+            _, self.Dt, self.Nt = assemble(c, self.kt, q)
+        elif pol == "TE":
+            _, self.D, self.N = assemble(c, self.k, q)
+            self.St, self.Dt, _ = assemble(c, self.kt, q)
+        else:
+            raise ValueError("pol must be TM or TE")
         self.G = gram(c)
         self.q = q
 
@@ -322,13 +359,21 @@ class System:
         return e / (1j * self.k * eta) + h
 
     def calderon(self):
-        """C_p = N_k~ G^-1 S_k + (G/2 - D*_k~) G^-1 (G/2 + D*_k) (paper eq. 16)."""
+        """TM: C_p = N_k~ G^-1 S_k + (G/2 - D*_k~) G^-1 (G/2 + D*_k) (paper eq. 16);
+        TE: C_p = S_k~ G^-1 N_k + (G/2 + D_k~) G^-1 (G/2 - D_k), D = D*^T."""
         Gi = np.linalg.inv(self.G)
+        if self.pol == "TE":
+            return self.St @ Gi @ self.N + (0.5 * self.G + self.Dt.T) @ Gi @ (0.5 * self.G - self.D.T)
         return self.Nt @ Gi @ self.S + (0.5 * self.G - self.Dt) @ Gi @ (0.5 * self.G + self.D)
 
     def calderon_rhs(self, e, h, eta=ETA0):
-        """b_p = N_k~ G^-1 e/(j k eta) + (G/2 - D*_k~) G^-1 h, for (S, N) stacks of e, h."""
+        """TM: b_p = N_k~ G^-1 e/(j k eta) + (G/2 - D*_k~) G^-1 h for e = (lambda, E_z),
+        h = (lambda, H_t); TE: b_p = S_k~ G^-1 (j k/eta) e - (G/2 + D_k~) G^-1 h for
+        e = (lambda, E_t), h = (lambda, H_z).  (S, N) stacks in and out."""
         Gi = np.linalg.inv(self.G)
+        if self.pol == "TE":
+            ee = (1j * self.k / eta * e).T
+            return (self.St @ (Gi @ ee) - (0.5 * self.G + self.Dt.T) @ (Gi @ h.T)).T
         ee = (e / (1j * self.k * eta)).T
         return (self.Nt @ (Gi @ ee) + (0.5 * self.G - self.Dt) @ (Gi @ h.T)).T
 
@@ -443,3 +488,17 @@ def cylinder_echo_width(k, a, phi, phi_inc=0.0, nmax=None):
     c = special.jv(ns, x) / special.hankel2(ns, x)
     s = (c[None, :] * np.exp(1j * ns[None, :] * (phi[:, None] - phi_inc))).sum(axis=1)
     return 4.0 / k * np.abs(s) ** 2
+
+
+def cylinder_current_te(k, a, phi, phi_inc=0.0, nmax=None):
+    """Tangential current j_t (along z x n) of a PEC circular cylinder of radius a under
+    the TE plane wave H_z = exp(-j k khat . r): j_t = -H_z^tot on the surface,
+    j_t = (2j / (pi k a)) sum_n j^-n exp(j n (phi - phi_inc)) / H_n^(2)'(k a)."""
+    x = k * a
+    if nmax is None:
+        nmax = int(x + 4.0 * x ** (1.0 / 3.0) + 15)
+    ns = np.arange(-nmax, nmax + 1)
+    phi = np.atleast_1d(phi)
+    terms = (1j ** (-ns.astype(float)))[None, :] * np.exp(1j * ns[None, :] * (phi[:, None] - phi_inc)) \
+        / special.h2vp(ns, x)[None, :]
+    return 2j / (math.pi * x) * terms.sum(axis=1)

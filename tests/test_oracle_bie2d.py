@@ -15,7 +15,10 @@ variables on the circle and invariants -- none re-types the oracle's formulas:
     C_p stays well conditioned while S or C degrade as the mesh is refined;
   * the fast direct solver: Q orthonormal, Halko's a-posteriori bound, rank 0 for
     the circle against itself, the Woodbury identity exact for C_c + U V^T, the
-    solution within the skeleton tolerance of a dense solve.
+    solution within the skeleton tolerance of a dense solve;
+  * TE: the stabilized solution converges at second order to the series current
+    (-H_z^tot on the cylinder, built on H_n^(2)'), and C_p^TE stays well
+    conditioned at the zeros of J_1' (TE EFIE) and J_0 (TE MFIE).
 """
 import math
 
@@ -165,3 +168,31 @@ def test_ktilde_mean_curvature_radius():
     # the airfoil's rounded trailing edge (radius of curvature below the node spacing
     # here) keeps its polygon 0.14 % short at 400 nodes
     assert abs(b2.Contour(synth.contour_joukowsky(400)).perimeter / (2.0 * math.pi) - 1.0) < 2e-3
+
+
+@pytest.mark.parametrize("k", [5.0, 1.8411837813406593, 2.404825557695773])
+def test_te_calderon_cylinder_and_resonances(k):
+    """TE: the stabilized solution converges to the series current at second order,
+    and C_p^TE stays well conditioned at x = 1.8412 (J_1' = 0, where the TE EFIE's N
+    is singular) and at x = 2.4048 (J_0 = 0, where the TE MFIE's G/2 - D is)."""
+    errs, conds = [], []
+    for N in (100, 200):
+        nodes = synth.contour_circle(N)
+        s = _system_pol(nodes, k, "TE")
+        et, hz = b2.excitation_te(s.c, k, [0.3])
+        Cp = s.calderon()
+        j = np.linalg.solve(Cp, s.calderon_rhs(et, hz)[0])
+        ja = b2.cylinder_current_te(k, 1.0, np.arctan2(nodes[:, 1], nodes[:, 0]), 0.3)
+        errs.append(np.linalg.norm(j - ja) / np.linalg.norm(ja))
+        conds.append((np.linalg.cond(Cp), np.linalg.cond(s.N), np.linalg.cond(0.5 * s.G - s.D.T)))
+    assert errs[1] < 2e-3 and errs[0] / errs[1] > 3.5
+    cP = [c[0] for c in conds]
+    assert max(cP) < 5.0 and abs(cP[1] / cP[0] - 1.0) < 0.02
+    if k < 2.0:
+        assert conds[1][1] > 1e3 * cP[1]            # N (TE EFIE) near-singular here
+    elif k < 3.0:
+        assert conds[1][2] > 1e3 * cP[1]            # G/2 - D (TE MFIE) near-singular here
+
+
+def _system_pol(nodes, k, pol):
+    return b2.System(b2.Contour(nodes), k, pol=pol)
