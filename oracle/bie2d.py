@@ -378,8 +378,14 @@ class System:
         return (self.Nt @ (Gi @ ee) + (0.5 * self.G - self.Dt) @ (Gi @ h.T)).T
 
 
-def farfield(c, k, J, phis, q=4):
-    """F(phi) = int J(r') exp(j k rhat . r') dS' for currents J (S, N): (S, len(phis))."""
+def farfield(c, k, J, phis, q=4, pol="TM"):
+    """Far-field pattern of currents J (S, N): (S, len(phis)).
+    TM: F(phi) = int J(r') exp(j k rhat . r') dS' (E_z ~ -j k eta G F);
+    TE: F(phi) = int (rhat . n(r')) J(r') exp(j k rhat . r') dS' (the tangential
+    current along z x n radiates H_z = curl(A)_z ~ -j k (rhat x t)_z G F, and
+    rhat x (z x n) = z (rhat . n))."""
+    if pol not in ("TM", "TE"):
+        raise ValueError("pol must be TM or TE")
     phis = np.atleast_1d(phis)
     xg, wg = gauss01(q)
     n = c.n
@@ -392,14 +398,19 @@ def farfield(c, k, J, phis, q=4):
         ex = np.exp(1j * k * (pts @ rh))                         # (N seg, q)
         for al in range(2):
             col = c.L * np.sum(wg * ph[al] * ex, axis=1)           # contribution of node a+al per segment a
+            if pol == "TE":
+                col = col * (c.nrm @ rh)
             idx = (np.arange(n) + al) % n
             out[:, d] += J[:, idx] @ col
     return out
 
 
-def echo_width(k, F, eta=ETA0):
-    """2-D scattering width sigma = (k eta^2 / 4) |F|^2 (unit incident amplitude)."""
-    return 0.25 * k * eta * eta * np.abs(F) ** 2
+def echo_width(k, F, eta=ETA0, pol="TM"):
+    """2-D scattering width for unit incident amplitude: sigma = lim 2 pi rho |u_s|^2
+    with u_s ~ c G F and |G|^2 ~ 1/(8 pi k rho): TM (u = E_z, c = -j k eta)
+    sigma = (k eta^2 / 4) |F|^2; TE (u = H_z, c = -j k) sigma = (k / 4) |F|^2."""
+    f = eta * eta if pol == "TM" else 1.0
+    return 0.25 * k * f * np.abs(F) ** 2
 
 
 # ------------------------------------------------------------ fast direct solver
@@ -486,6 +497,18 @@ def cylinder_echo_width(k, a, phi, phi_inc=0.0, nmax=None):
     ns = np.arange(-nmax, nmax + 1)
     phi = np.atleast_1d(phi)
     c = special.jv(ns, x) / special.hankel2(ns, x)
+    s = (c[None, :] * np.exp(1j * ns[None, :] * (phi[:, None] - phi_inc))).sum(axis=1)
+    return 4.0 / k * np.abs(s) ** 2
+
+
+def cylinder_echo_width_te(k, a, phi, phi_inc=0.0, nmax=None):
+    """sigma(phi) = (4/k) |sum_n J_n'(ka)/H_n^(2)'(ka) exp(j n (phi - phi_inc))|^2, TE, PEC."""
+    x = k * a
+    if nmax is None:
+        nmax = int(x + 4.0 * x ** (1.0 / 3.0) + 15)
+    ns = np.arange(-nmax, nmax + 1)
+    phi = np.atleast_1d(phi)
+    c = special.jvp(ns, x) / special.h2vp(ns, x)
     s = (c[None, :] * np.exp(1j * ns[None, :] * (phi[:, None] - phi_inc))).sum(axis=1)
     return 4.0 / k * np.abs(s) ** 2
 

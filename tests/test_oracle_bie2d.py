@@ -17,7 +17,8 @@ variables on the circle and invariants -- none re-types the oracle's formulas:
     the circle against itself, the Woodbury identity exact for C_c + U V^T, the
     solution within the skeleton tolerance of a dense solve;
   * TE: the stabilized solution converges at second order to the series current
-    (-H_z^tot on the cylinder, built on H_n^(2)'), and C_p^TE stays well
+    (-H_z^tot on the cylinder, built on H_n^(2)'), its echo width matches the
+    series (J_n'/H_n^(2)') within 0.05 dB, and C_p^TE stays well
     conditioned at the zeros of J_1' (TE EFIE) and J_0 (TE MFIE).
 """
 import math
@@ -184,6 +185,12 @@ def test_te_calderon_cylinder_and_resonances(k):
         j = np.linalg.solve(Cp, s.calderon_rhs(et, hz)[0])
         ja = b2.cylinder_current_te(k, 1.0, np.arctan2(nodes[:, 1], nodes[:, 0]), 0.3)
         errs.append(np.linalg.norm(j - ja) / np.linalg.norm(ja))
+        if N == 200:
+            obs = np.linspace(0.0, 2.0 * math.pi, 73)
+            sw = b2.echo_width(k, b2.farfield(s.c, k, j, obs, pol="TE")[0], pol="TE")
+            sa = b2.cylinder_echo_width_te(k, 1.0, obs, 0.3)
+            keep = 10 * np.log10(sa / sa.max()) > -30
+            assert np.abs(10 * np.log10(sw / sa))[keep].max() < 0.05
         conds.append((np.linalg.cond(Cp), np.linalg.cond(s.N), np.linalg.cond(0.5 * s.G - s.D.T)))
     assert errs[1] < 2e-3 and errs[0] / errs[1] > 3.5
     cP = [c[0] for c in conds]
