@@ -511,14 +511,15 @@ def bench_bie2d(args, P, synth, torch, np, dev):
     if args.bie2d_n:
         cases = [(int(n), float(kk)) for n, kk in zip(args.bie2d_n, args.bie2d_k)]
     geom = {"ellipse": synth.contour_ellipse, "airfoil": synth.contour_joukowsky}[args.bie2d_geom]
+    pols = args.bie2d_pol or ["TM"]
     rows = []
-    for n, k in cases:
+    for (n, k), pol in [(c, p) for c in cases for p in pols]:
         nodes, circ = geom(n), synth.contour_circle(n)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         h = P.Bie2d(nodes, circ, device=dev)
         rmax = min(n, args.bie2d_rmax)
-        h.setup(k, rmax=rmax, block=64, nvec=max(64, args.bie2d_nrhs))
+        h.setup(k, rmax=rmax, block=64, nvec=max(64, args.bie2d_nrhs), pol=pol)
         torch.cuda.synchronize()
         t_setup = time.perf_counter() - t0
         g = torch.Generator(device=dev).manual_seed(0)
@@ -538,7 +539,7 @@ def bench_bie2d(args, P, synth, torch, np, dev):
         t_solve = time.perf_counter() - t0
         res = (h.apply("cp", x) - bp).norm(dim=1) / bp.norm(dim=1)
         paper = PAPER_TABLE1.get(n)
-        row = {"n": n, "k0": k, "nodes_per_wavelength": round(n * 2.0 * math.pi / (k * h.perimeter()), 2),
+        row = {"n": n, "k0": k, "pol": pol, "nodes_per_wavelength": round(n * 2.0 * math.pi / (k * h.perimeter()), 2),
                "rank": rank, "tol": args.bie2d_tol, "est_rel": est / ref if ref else 0.0,
                "setup_s": round(t_setup, 3), "skeleton_s": round(t_skel, 3), "solve_s": round(t_solve, 4),
                "nrhs": args.bie2d_nrhs, "residual_max": float(res.max()),
@@ -556,10 +557,11 @@ def bench_bie2d(args, P, synth, torch, np, dev):
         "higher_is_better": False, "scaling": "strong",
         "vs_baseline": None if main["paper_skeleton_s"] is None else round(main["skeleton_s"] / main["paper_skeleton_s"], 5),
         "dtype": "c128", "data": "synthetic",
-        "config": {"workload": f"2-D PEC {args.bie2d_geom} (aspect 1.5, perimeter 2 pi), TM, Calderon-stabilized CFIE "
+        "config": {"workload": f"2-D PEC {args.bie2d_geom} (aspect 1.5, perimeter 2 pi), {main['pol']}, "
+                               f"Calderon-stabilized CFIE "
                                f"C_p (eq. 16), randomized skeleton of C_p - C_p,c to {args.bie2d_tol:g} and Woodbury "
                                f"inverse (eqs. 17-18); N and k0 of the paper's Table I",
-                   "cases": [[r["n"], r["k0"]] for r in rows]},
+                   "cases": [[r["n"], r["k0"], r["pol"]] for r in rows]},
         "cases": rows,
     }
     print(json.dumps(out), flush=True)
@@ -573,13 +575,15 @@ def bench_bie2d_rank(args, P, synth, torch, np, dev):
 
     out = {"metric": "skeleton rank of C_p - C_p,c vs k0", "unit": "rank", "tol": args.bie2d_tol,
            "nodes_per_wavelength": args.bie2d_ppw, "curves": {}}
-    for geom, make in (("ellipse", synth.contour_ellipse), ("airfoil", synth.contour_joukowsky)):
+    curves = [(g, m, p) for g, m in (("ellipse", synth.contour_ellipse), ("airfoil", synth.contour_joukowsky))
+              for p in (args.bie2d_pol or ["TM", "TE"])]
+    for geom, make, pol in curves:
         pts = []
         for k in args.bie2d_ks:
             n = int(round(args.bie2d_ppw * k))          # perimeter 2 pi: k0 wavelengths
             h = P.Bie2d(make(n), synth.contour_circle(n), device=dev)
             rmax = min(n, args.bie2d_rmax)
-            h.setup(k, rmax=rmax, block=32, nvec=32)
+            h.setup(k, rmax=rmax, block=32, nvec=32, pol=pol)
             g = torch.Generator(device=dev).manual_seed(0)
             om = torch.randn((rmax + 32, n), dtype=torch.complex128, device=dev, generator=g)
             torch.cuda.synchronize()
@@ -587,13 +591,13 @@ def bench_bie2d_rank(args, P, synth, torch, np, dev):
             rank, est, ref = h.skeleton(om, args.bie2d_tol)
             torch.cuda.synchronize()
             pts.append({"k0": k, "n": n, "rank": rank, "skeleton_s": round(time.perf_counter() - t0, 3)})
-            log(f"bench: bie2d rank {geom} {pts[-1]}")
+            log(f"bench: bie2d rank {geom} {pol} {pts[-1]}")
             del h, om
             torch.cuda.empty_cache()
         ks = np.array([p["k0"] for p in pts])
         rk = np.array([max(p["rank"], 1) for p in pts], dtype=float)
         slope = np.polyfit(np.log(ks[-3:]), np.log(rk[-3:]), 1)[0] if len(ks) >= 3 else None
-        out["curves"][geom] = {"points": pts, "loglog_slope_last3": None if slope is None else round(float(slope), 3)}
+        out["curves"][f"{geom}_{pol}"] = {"points": pts, "loglog_slope_last3": None if slope is None else round(float(slope), 3)}
     print(json.dumps(out), flush=True)
 
 
@@ -665,6 +669,8 @@ def main():
     ap.add_argument("--bie2d-nrhs", type=int, default=64)
     ap.add_argument("--bie2d-ks", type=float, nargs="*", default=[25, 50, 100, 200, 400, 834])
     ap.add_argument("--bie2d-ppw", type=float, default=18.0, help="bie2d-rank: nodes per wavelength")
+    ap.add_argument("--bie2d-pol", choices=["TM", "TE"], nargs="*",
+                    help="2-D polarizations (default: TM for bie2d, TM and TE for bie2d-rank)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--copy-calibration", action="store_true",

@@ -521,13 +521,19 @@ int efie_batch_solve(efie_batch b, const void* Zcat, int dtype, const void* Vcat
  * efie_bie2d_assemble: a window [row0, row0 + nrows) x [col0, col0 + ncols) of
  *   S_k, D*_k and N_k of contour `which` (0 the curve, 1 the circle) into the
  *   non-null outputs (dev, row-major with leading dimension ld).
- * efie_bie2d_setup: assembles the four operators of C_p at k and k~ and the
- *   counterpart's first column (and its inverse's) from the spectra of its
- *   factors on the circle; the workspace must stay alive for the later calls.
+ * efie_bie2d_setup: pol 0 (TM, the paper's eq. 7 and 16) or 1 (TE, the other
+ *   polarization, by the same Calderon structure: incident H_z, unknown the
+ *   tangential current along z x n, N j = (j k/eta)(lambda, E_t), (G/2 - D) j =
+ *   -(lambda, H_z), C_p = S_k~ G^-1 N_k + (G/2 + D_k~) G^-1 (G/2 - D_k) with
+ *   D = D*^T, b_p = S_k~ G^-1 (j k/eta) e_t - (G/2 + D_k~) G^-1 h_z); assembles the
+ *   four operators of C_p at k and k~ and the counterpart's first column (and its
+ *   inverse's) from the spectra of its factors on the circle; the workspace must
+ *   stay alive for the later calls.
  * efie_bie2d_apply: Y = op X for nvec rows, op 0: C_p, 1: C_p^T, 2: C_c, 3: C_c^-1,
  *   4: G^-1, 5: C_p - C_c.
  * efie_bie2d_rhs: e, h (and b_p if bp is not null) for plane waves of incidence
- *   angles phis (host, nrhs); synchronises.
+ *   angles phis (host, nrhs); TM: e = (lambda, E_z), h = (lambda, H_t); TE:
+ *   e = (lambda, E_t), h = (lambda, H_z); synchronises.
  * efie_bie2d_skeleton: the range finder on A = C_p - C_p,c with the test matrix
  *   omega (dev, ncols x n rows, ncols >= block; the last block may be partial): *rank, the last projected block's
  *   largest column norm *est and the reference scale *ref (host); then
@@ -537,8 +543,10 @@ int efie_batch_solve(efie_batch b, const void* Zcat, int dtype, const void* Vcat
  * efie_bie2d_solve: X = C_p^-1 B by the Woodbury formula (nrhs rows, <= nvec).
  * efie_bie2d_factors: copies U (rank x n rows) and V^T (rank x n) into dev buffers.
  * efie_bie2d_counterpart: the first columns of C_p,c and of its inverse (dev, n).
- * efie_bie2d_farfield: F[s][d] = int J_s exp(j k rhat_d . r) dS (2-D far-field
- *   amplitude; echo width (k eta^2 / 4) |F|^2), phis dev (nphi), F dev (nrhs x nphi).
+ * efie_bie2d_farfield: 2-D far-field amplitude, phis dev (nphi), F dev (nrhs x
+ *   nphi); pol 0 (TM): F[s][d] = int J_s exp(j k rhat_d . r) dS, echo width
+ *   (k eta^2 / 4) |F|^2; pol 1 (TE): F[s][d] = int (rhat_d . n) J_s exp(j k rhat_d . r) dS,
+ *   echo width (k / 4) |F|^2.
  * efie_bie2d_perimeter: the polygon perimeter of contour `which` (host).
  */
 typedef struct efie_bie2d_s* efie_bie2d;
@@ -550,8 +558,8 @@ int efie_bie2d_upload(efie_bie2d h, void* dev, size_t bytes, hipStream_t stream)
 int efie_bie2d_perimeter(efie_bie2d h, int which, double* perimeter);
 int efie_bie2d_assemble(efie_bie2d h, int which, double k_re, double k_im, void* S, void* Dstar, void* Nm,
                         int64_t row0, int64_t nrows, int64_t col0, int64_t ncols, int64_t ld, hipStream_t stream);
-int efie_bie2d_setup(efie_bie2d h, double k, double kt_re, double kt_im, int64_t rmax, int64_t block, int64_t nvec,
-                     void* ws, size_t ws_bytes, hipStream_t stream);
+int efie_bie2d_setup(efie_bie2d h, int pol, double k, double kt_re, double kt_im, int64_t rmax, int64_t block,
+                     int64_t nvec, void* ws, size_t ws_bytes, hipStream_t stream);
 int efie_bie2d_apply(efie_bie2d h, int op, const void* X, void* Y, int64_t nvec, hipStream_t stream);
 int efie_bie2d_rhs(efie_bie2d h, const double* phis, int64_t nrhs, double eta, void* e, void* hv, void* bp,
                    hipStream_t stream);
@@ -560,8 +568,8 @@ int efie_bie2d_skeleton(efie_bie2d h, const void* omega, int64_t ncols, double t
 int efie_bie2d_solve(efie_bie2d h, const void* B, void* X, int64_t nrhs, hipStream_t stream);
 int efie_bie2d_factors(efie_bie2d h, void* U, void* Vt, hipStream_t stream);
 int efie_bie2d_counterpart(efie_bie2d h, void* col, void* col_inv, hipStream_t stream);
-int efie_bie2d_farfield(efie_bie2d h, double k, const void* J, int64_t nrhs, const double* phis, int64_t nphi,
-                        void* F, hipStream_t stream);
+int efie_bie2d_farfield(efie_bie2d h, int pol, double k, const void* J, int64_t nrhs, const double* phis,
+                        int64_t nphi, void* F, hipStream_t stream);
 
 /* -------------------------------------------------------------- utilities */
 

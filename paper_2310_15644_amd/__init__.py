@@ -135,7 +135,7 @@ def lib():
         "efie_bie2d_upload": ([P, P, ctypes.c_size_t, P], ctypes.c_int),
         "efie_bie2d_perimeter": ([P, ctypes.c_int, ctypes.POINTER(D)], ctypes.c_int),
         "efie_bie2d_assemble": ([P, ctypes.c_int, D, D, P, P, P, I64, I64, I64, I64, I64, P], ctypes.c_int),
-        "efie_bie2d_setup": ([P, D, D, D, I64, I64, I64, P, ctypes.c_size_t, P], ctypes.c_int),
+        "efie_bie2d_setup": ([P, ctypes.c_int, D, D, D, I64, I64, I64, P, ctypes.c_size_t, P], ctypes.c_int),
         "efie_bie2d_apply": ([P, ctypes.c_int, P, P, I64, P], ctypes.c_int),
         "efie_bie2d_rhs": ([P, P, I64, D, P, P, P, P], ctypes.c_int),
         "efie_bie2d_skeleton": ([P, P, I64, D, ctypes.POINTER(I64), ctypes.POINTER(D), ctypes.POINTER(D), P],
@@ -143,7 +143,7 @@ def lib():
         "efie_bie2d_solve": ([P, P, P, I64, P], ctypes.c_int),
         "efie_bie2d_factors": ([P, P, P, P], ctypes.c_int),
         "efie_bie2d_counterpart": ([P, P, P, P], ctypes.c_int),
-        "efie_bie2d_farfield": ([P, D, P, I64, P, I64, P, P], ctypes.c_int),
+        "efie_bie2d_farfield": ([P, ctypes.c_int, D, P, I64, P, I64, P, P], ctypes.c_int),
         "efie_zx_flush64_noalloc": ([P, I64, P, P, I64, P], ctypes.c_int),
         "efie_gemm_autotune_cached_workspace_size": ([I64, I64, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "efie_gemm_autotune_cached": ([ctypes.c_char_p, P, I64, I64, ctypes.c_int, ctypes.c_int, P, ctypes.c_size_t,
@@ -805,10 +805,13 @@ class Bie2d:
                                           c0, c1 - c0, c1 - c0, _stream(self.device)))
         return tuple(out)
 
-    def setup(self, k: float, kt=None, rmax: int | None = None, block: int = 64, nvec: int = 64, a: float = 1.0):
-        """Assemble S_k, D*_k, N_k~, D*_k~ and the counterpart (k~ = the paper's
-        complex wavenumber with radius a unless given); workspace for a skeleton of
-        rank <= rmax (default n) in blocks of `block` and calls of <= nvec vectors."""
+    def setup(self, k: float, kt=None, rmax: int | None = None, block: int = 64, nvec: int = 64, a: float = 1.0,
+              pol: str = "TM"):
+        """Assemble the four operators of C_p for polarization pol ("TM": S_k, D*_k,
+        N_k~, D*_k~; "TE": N_k, D*_k, S_k~, D*_k~) and the counterpart (k~ = the
+        paper's complex wavenumber with radius a unless given); workspace for a
+        skeleton of rank <= rmax (default n) in blocks of `block` and calls of <=
+        nvec vectors."""
         torch = _torch()
         kt = ktilde(k, a) if kt is None else complex(kt)
         rmax = self.n if rmax is None else int(rmax)
@@ -818,9 +821,12 @@ class Bie2d:
         self._ws = None
         self._ws = torch.empty(wb.value + 256, dtype=torch.uint8, device=self.device)
         off = (-self._ws.data_ptr()) % 256
-        _check(lib().efie_bie2d_setup(self._h, float(k), kt.real, kt.imag, rmax, int(block), nvec,
+        if pol not in ("TM", "TE"):
+            raise ValueError("pol must be TM or TE")
+        _check(lib().efie_bie2d_setup(self._h, 0 if pol == "TM" else 1, float(k), kt.real, kt.imag, rmax, int(block),
+                                      nvec,
                                       ctypes.c_void_p(self._ws.data_ptr() + off), wb.value, _stream(self.device)))
-        self.k, self.kt, self.rmax, self.block, self.nvec = float(k), kt, rmax, int(block), nvec
+        self.k, self.kt, self.rmax, self.block, self.nvec, self.pol = float(k), kt, rmax, int(block), nvec, pol
         return self
 
     def _vec(self, X, name):
@@ -841,7 +847,9 @@ class Bie2d:
         return Y
 
     def rhs(self, phis, eta: float = ETA0, stabilized: bool = True):
-        """(e, h, b_p) for plane waves of incidence angles phis (b_p None unless stabilized)."""
+        """(e, h, b_p) for plane waves of incidence angles phis (b_p None unless
+        stabilized); TM: e = (lambda, E_z), h = (lambda, H_t); TE: e = (lambda, E_t),
+        h = (lambda, H_z)."""
         torch = _torch()
         ph = np.ascontiguousarray(np.atleast_1d(phis), dtype=np.float64)
         e = torch.empty((len(ph), self.n), dtype=torch.complex128, device=self.device)
@@ -885,14 +893,18 @@ class Bie2d:
         _check(lib().efie_bie2d_counterpart(self._h, _ptr(c), _ptr(ci), _stream(self.device)))
         return c, ci
 
-    def farfield(self, k: float, J, phis):
-        """F (nrhs, nphi): int J exp(j k rhat . r) dS at observation angles phis."""
+    def farfield(self, k: float, J, phis, pol: str | None = None):
+        """F (nrhs, nphi) at observation angles phis: TM int J exp(j k rhat . r) dS,
+        TE int (rhat . n) J exp(j k rhat . r) dS (pol defaults to the setup's, else TM)."""
         torch = _torch()
+        pol = pol or getattr(self, "pol", "TM")
+        if pol not in ("TM", "TE"):
+            raise ValueError("pol must be TM or TE")
         J = self._vec(J, "J")
         ph = torch.as_tensor(np.atleast_1d(phis), dtype=torch.float64, device=self.device).contiguous()
         F = torch.empty((J.shape[0], ph.numel()), dtype=torch.complex128, device=self.device)
-        _check(lib().efie_bie2d_farfield(self._h, float(k), _ptr(J), J.shape[0], _ptr(ph), ph.numel(), _ptr(F),
-                                         _stream(self.device)))
+        _check(lib().efie_bie2d_farfield(self._h, 0 if pol == "TM" else 1, float(k), _ptr(J), J.shape[0], _ptr(ph),
+                                         ph.numel(), _ptr(F), _stream(self.device)))
         return F
 
     def __del__(self):

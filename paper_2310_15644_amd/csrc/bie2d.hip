@@ -356,8 +356,11 @@ __global__ __launch_bounds__(256) void assemble2d_kernel(DevContour c, double kr
 
 // e (and h) for plane waves exp(-j k khat . r), khat = (cos phi, sin phi): one
 // thread per (right-hand side, node)
+// TM (te = 0): e = (lambda, E_z), h = (lambda, H_t), H_t = -(khat . n) E_z / eta;
+// TE (te = 1): e = (lambda, E_t), E_t = eta (khat . n) H_z, h = (lambda, H_z);
+// the incident field exp(-j k khat . r) is E_z (TM) or H_z (TE)
 __global__ void excite2d_kernel(DevContour c, double k, double eta, const double* __restrict__ phis, int nrhs,
-                                double2* __restrict__ e, double2* __restrict__ h) {
+                                double2* __restrict__ e, double2* __restrict__ h, int te) {
     const int n = c.n;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= n * nrhs) return;
@@ -376,19 +379,27 @@ __global__ void excite2d_kernel(DevContour c, double k, double eta, const double
             double s_, c_;
             sincos(-k * (cp * rx + sp * ry), &s_, &c_);
             const double wphi = L * c.gw[p] * (al == 0 ? 1.0 - x : x);
-            ev.x += wphi * c_;
-            ev.y += wphi * s_;
-            hv.x -= wphi * kn * c_ / eta;
-            hv.y -= wphi * kn * s_ / eta;
+            if (te) {
+                ev.x += wphi * eta * kn * c_;
+                ev.y += wphi * eta * kn * s_;
+                hv.x += wphi * c_;
+                hv.y += wphi * s_;
+            } else {
+                ev.x += wphi * c_;
+                ev.y += wphi * s_;
+                hv.x -= wphi * kn * c_ / eta;
+                hv.y -= wphi * kn * s_ / eta;
+            }
         }
     }
     e[idx] = ev;
     if (h) h[idx] = hv;
 }
 
-// F[s][d] = sum_i J[s][i] int lambda_i exp(j k rhat_d . r) dS: one thread per (s, d)
+// F[s][d] = sum_i J[s][i] int w lambda_i exp(j k rhat_d . r) dS: one thread per (s, d);
+// w = 1 (TM) or rhat_d . n (TE, constant on each segment)
 __global__ void farfield2d_kernel(DevContour c, double k, const double2* __restrict__ J, int nrhs,
-                                  const double* __restrict__ phis, int nphi, double2* __restrict__ F) {
+                                  const double* __restrict__ phis, int nphi, double2* __restrict__ F, int te) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= nrhs * nphi) return;
     const int s = idx / nphi, d = idx - s * nphi;
@@ -404,7 +415,7 @@ __global__ void farfield2d_kernel(DevContour c, double k, const double2* __restr
             const double rx = c.ax[a] + x * (c.bx[a] - c.ax[a]), ry = c.ay[a] + x * (c.by[a] - c.ay[a]);
             double s_, c_;
             sincos(k * (cp * rx + sp * ry), &s_, &c_);
-            const double w = c.len[a] * c.gw[p];
+            const double w = c.len[a] * c.gw[p] * (te ? cp * c.nx[a] + sp * c.ny[a] : 1.0);
             m0.x += w * (1.0 - x) * c_;
             m0.y += w * (1.0 - x) * s_;
             m1.x += w * x * c_;
@@ -500,16 +511,20 @@ __global__ void dft_kernel(const double2* __restrict__ x, double2* __restrict__ 
 }
 
 // eigenvalues of the counterpart C_c and of its inverse from those of its factors
+// TM: lC = lN lS / lG + (lG/2 - lDt)(lG/2 + lD) / lG  (lN at k~, lS at k, lD at k, lDt at k~);
+// TE: lC = lS lN / lG + (lG/2 + lDt)(lG/2 - lD) / lG  (lS at k~, lN at k, lD, lDt the
+//     spectra of the double layer D = D*^T at k and k~)
 __global__ void circ_combine_kernel(const double2* __restrict__ lS, const double2* __restrict__ lD,
                                     const double2* __restrict__ lN, const double2* __restrict__ lDt,
                                     const double2* __restrict__ lG, double2* __restrict__ lC, double2* __restrict__ lCi,
-                                    int n) {
+                                    int n, int te) {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= n) return;
     const double2 g = lG[m], ig = crcp(g);
     const double2 hg = cscale(g, 0.5);
     const double2 t1 = cmul(cmul(lN[m], lS[m]), ig);
-    const double2 t2 = cmul(cmul(csub(hg, lDt[m]), cadd(hg, lD[m])), ig);
+    const double2 t2 = te ? cmul(cmul(cadd(hg, lDt[m]), csub(hg, lD[m])), ig)
+                          : cmul(cmul(csub(hg, lDt[m]), cadd(hg, lD[m])), ig);
     const double2 v = cadd(t1, t2);
     lC[m] = v;
     lCi[m] = crcp(v);
@@ -851,10 +866,12 @@ struct efie_bie2d_s {
     DevContour dc[2]{};
     // state of the last setup (device pointers into the caller's workspace)
     double k = 0.0, kt_re = 0.0, kt_im = 0.0;
+    int pol = 0;                   // 0 TM, 1 TE
     char* ws = nullptr;
     size_t ws_bytes = 0;
     int64_t rmax = 0, block = 0, nvec = 0;
-    double2 *S = nullptr, *Dst = nullptr, *Nt = nullptr, *Dtt = nullptr;      // S_k, D*_k, N_k~, D*_k~
+    // TM: S_k, D*_k, N_k~, D*_k~;  TE: S_k~, D*_k, N_k, D*_k~ (S / N at the wavenumber their term uses)
+    double2 *S = nullptr, *Dst = nullptr, *Nt = nullptr, *Dtt = nullptr;
     double2 *cC = nullptr, *cCT = nullptr, *cI = nullptr, *cIT = nullptr;    // counterpart, inverse (+ transposes)
     double2 *T1 = nullptr, *T2 = nullptr, *T3 = nullptr;                       // nvec x n temporaries
     double2 *Qm = nullptr, *Bm = nullptr, *Wm = nullptr, *Mm = nullptr;        // skeleton and Woodbury factors
@@ -942,6 +959,32 @@ const double2 ONE = {1.0, 0.0}, MONE = {-1.0, 0.0};
 // M x, and sum_k X[s][k] M[k][i] (NN) for M^T x.
 void apply_cp(efie_bie2d_s& h, const double2* X, double2* Y, int nvec, bool trans, bool sub_c, hipStream_t s) {
     const int n = int(h.n);
+    if (h.pol == 1) {
+        // TE: C_p = S~ G^-1 N + (G/2 + D~) G^-1 (G/2 - D), D = D*^T;
+        //     C_p^T = N G^-1 S~ + (G/2 - D*) G^-1 (G/2 + D*~)
+        if (!trans) {
+            gemm2d(efie::G2D_NT, X, n, false, h.Nt, n, false, h.T1, n, nvec, n, n, ONE, false, s);
+            gram_solve(h, 0, h.T1, h.T2, nvec, s);
+            gemm2d(efie::G2D_NT, h.T2, n, false, h.S, n, false, Y, n, nvec, n, n, ONE, false, s);
+            gemm2d(efie::G2D_NN, X, n, false, h.Dst, n, false, h.T1, n, nvec, n, n, MONE, false, s);
+            gram_apply(h, 0, X, h.T1, nvec, 0.5, 1.0, s);
+            gram_solve(h, 0, h.T1, h.T2, nvec, s);
+            gemm2d(efie::G2D_NN, h.T2, n, false, h.Dtt, n, false, Y, n, nvec, n, n, ONE, true, s);
+            gram_apply(h, 0, h.T2, Y, nvec, 0.5, 1.0, s);
+            if (sub_c) gemm2d(efie::G2D_CIRC, X, n, false, h.cC, 0, false, Y, n, nvec, n, n, MONE, true, s);
+        } else {
+            gemm2d(efie::G2D_NT, X, n, false, h.S, n, false, h.T1, n, nvec, n, n, ONE, false, s);
+            gram_solve(h, 0, h.T1, h.T2, nvec, s);
+            gemm2d(efie::G2D_NT, h.T2, n, false, h.Nt, n, false, Y, n, nvec, n, n, ONE, false, s);
+            gemm2d(efie::G2D_NT, X, n, false, h.Dtt, n, false, h.T1, n, nvec, n, n, ONE, false, s);
+            gram_apply(h, 0, X, h.T1, nvec, 0.5, 1.0, s);
+            gram_solve(h, 0, h.T1, h.T2, nvec, s);
+            gemm2d(efie::G2D_NT, h.T2, n, false, h.Dst, n, false, Y, n, nvec, n, n, MONE, true, s);
+            gram_apply(h, 0, h.T2, Y, nvec, 0.5, 1.0, s);
+            if (sub_c) gemm2d(efie::G2D_CIRC, X, n, false, h.cCT, 0, false, Y, n, nvec, n, n, MONE, true, s);
+        }
+        return;
+    }
     if (!trans) {
         // first term: N~ G^-1 S X
         gemm2d(efie::G2D_NT, X, n, false, h.S, n, false, h.T1, n, nvec, n, n, ONE, false, s);
@@ -1074,8 +1117,8 @@ int efie_bie2d_assemble(efie_bie2d h, int which, double k_re, double k_im, void*
     });
 }
 
-int efie_bie2d_setup(efie_bie2d h, double k, double kt_re, double kt_im, int64_t rmax, int64_t block, int64_t nvec,
-                     void* ws, size_t ws_bytes, hipStream_t stream) {
+int efie_bie2d_setup(efie_bie2d h, int pol, double k, double kt_re, double kt_im, int64_t rmax, int64_t block,
+                     int64_t nvec, void* ws, size_t ws_bytes, hipStream_t stream) {
     return efie::guarded([&]() {
         EFIE_REQUIRE(h && ws, EFIE_ERR_ARG, "bie2d_setup: null argument");
         EFIE_REQUIRE(h->dev != nullptr, EFIE_ERR_STATE, "bie2d_setup: tables not uploaded");
@@ -1083,6 +1126,7 @@ int efie_bie2d_setup(efie_bie2d h, double k, double kt_re, double kt_im, int64_t
                      EFIE_ERR_ARG, "bie2d_setup: need k > 0, Re k~ > 0, Im k~ <= 0");
         EFIE_REQUIRE(block >= 1 && block <= 64 && rmax >= 0 && rmax <= h->n && nvec >= block, EFIE_ERR_ARG,
                      "bie2d_setup: need 1 <= block <= 64, 0 <= rmax <= n, nvec >= block");
+        EFIE_REQUIRE(pol == 0 || pol == 1, EFIE_ERR_ARG, "bie2d_setup: pol must be 0 (TM) or 1 (TE)");
         const Layout L = layout(h->n, rmax, block, nvec);
         EFIE_REQUIRE(ws_bytes >= L.total, EFIE_ERR_ARG, "bie2d_setup: workspace too small");
         EFIE_REQUIRE((reinterpret_cast<uintptr_t>(ws) & 255) == 0, EFIE_ERR_ARG, "bie2d_setup: ws not 256-aligned");
@@ -1096,6 +1140,7 @@ int efie_bie2d_setup(efie_bie2d h, double k, double kt_re, double kt_im, int64_t
         h->k = k;
         h->kt_re = kt_re;
         h->kt_im = kt_im;
+        h->pol = pol;
         h->S = P(L.S); h->Dst = P(L.Dst); h->Nt = P(L.Nt); h->Dtt = P(L.Dtt);
         h->cC = P(L.cC); h->cCT = P(L.cCT); h->cI = P(L.cI); h->cIT = P(L.cIT);
         h->T1 = P(L.T1); h->T2 = P(L.T2); h->T3 = P(L.T3);
@@ -1108,24 +1153,35 @@ int efie_bie2d_setup(efie_bie2d h, double k, double kt_re, double kt_im, int64_t
         h->split_n = split_elems(rmax);
         h->rank = -1;
         const int n = int(h->n);
-        // the four operators of C_p on the scatterer
-        launch_assemble(h->dc[0], k, 0.0, 0, n, 0, n, n, h->S, h->Dst, nullptr, h->q, stream);
-        launch_assemble(h->dc[0], kt_re, kt_im, 0, n, 0, n, n, nullptr, h->Dtt, h->Nt, h->q, stream);
+        // the four operators of C_p on the scatterer (TM: S and D* at k, N and D* at k~;
+        // TE: N and D* at k, S and D* at k~)
+        const bool te = pol == 1;
+        launch_assemble(h->dc[0], k, 0.0, 0, n, 0, n, n, te ? nullptr : h->S, h->Dst, te ? h->Nt : nullptr, h->q,
+                        stream);
+        launch_assemble(h->dc[0], kt_re, kt_im, 0, n, 0, n, n, te ? h->S : nullptr, h->Dtt, te ? nullptr : h->Nt, h->q,
+                        stream);
         // the counterpart: first columns of its factors on the circle, their spectra
         // (direct DFT), the spectrum of C_c and of its inverse, back to first columns
         double2* e = P(L.eig);
         double2 *cS = e, *cD = e + n, *cN = e + 2 * n, *cDt = e + 3 * n, *cG = e + 4 * n, *l1 = e + 5 * n,
                 *l2 = e + 6 * n;
-        launch_assemble(h->dc[1], k, 0.0, 0, n, 0, 1, 1, cS, cD, nullptr, h->q, stream);
-        launch_assemble(h->dc[1], kt_re, kt_im, 0, n, 0, 1, 1, nullptr, cDt, cN, h->q, stream);
+        launch_assemble(h->dc[1], k, 0.0, 0, n, 0, 1, 1, te ? nullptr : cS, cD, te ? cN : nullptr, h->q, stream);
+        launch_assemble(h->dc[1], kt_re, kt_im, 0, n, 0, 1, 1, te ? cS : nullptr, cDt, te ? nullptr : cN, h->q, stream);
         hipLaunchKernelGGL(efie::gram_column_kernel, dim3(efie::grid_of(n)), dim3(256), 0, stream, h->dc[1], cG);
         double2* lam[5] = {e + 7 * n, e + 8 * n, e + 9 * n, e + 10 * n, e + 11 * n};
         const double2* cols[5] = {cS, cD, cN, cDt, cG};
+        if (te) {
+            // the double layer D = D*^T: first columns of the transposes (scratch l1, l2)
+            hipLaunchKernelGGL(efie::circ_transpose_kernel, dim3(efie::grid_of(n)), dim3(256), 0, stream, cD, l1, n);
+            hipLaunchKernelGGL(efie::circ_transpose_kernel, dim3(efie::grid_of(n)), dim3(256), 0, stream, cDt, l2, n);
+            cols[1] = l1;
+            cols[3] = l2;
+        }
         for (int i = 0; i < 5; ++i)
             hipLaunchKernelGGL(efie::dft_kernel, dim3(efie::grid_of(n)), dim3(256), 0, stream, cols[i], lam[i], n, -1.0,
                                1.0);
         hipLaunchKernelGGL(efie::circ_combine_kernel, dim3(efie::grid_of(n)), dim3(256), 0, stream, lam[0], lam[1],
-                           lam[2], lam[3], lam[4], l1, l2, n);
+                           lam[2], lam[3], lam[4], l1, l2, n, int(te));
         hipLaunchKernelGGL(efie::dft_kernel, dim3(efie::grid_of(n)), dim3(256), 0, stream, l1, h->cC, n, 1.0, 1.0 / n);
         hipLaunchKernelGGL(efie::dft_kernel, dim3(efie::grid_of(n)), dim3(256), 0, stream, l2, h->cI, n, 1.0, 1.0 / n);
         hipLaunchKernelGGL(efie::circ_transpose_kernel, dim3(efie::grid_of(n)), dim3(256), 0, stream, h->cC, h->cCT, n);
@@ -1172,8 +1228,17 @@ int efie_bie2d_rhs(efie_bie2d h, const double* phis, int64_t nrhs, double eta, v
         auto* ed = static_cast<double2*>(e);
         auto* hd = static_cast<double2*>(hv);
         hipLaunchKernelGGL(efie::excite2d_kernel, dim3(efie::grid_of(size_t(n) * nr)), dim3(256), 0, stream,
-                           h->dc[0], h->k, eta, dphi, nr, ed, hd);
-        if (bp) {
+                           h->dc[0], h->k, eta, dphi, nr, ed, hd, h->pol);
+        if (bp && h->pol == 1) {
+            // TE: b_p = S~ G^-1 (j k/eta) e_t - (G/2 + D~) G^-1 h_z, D~ = D*~^T
+            auto* b = static_cast<double2*>(bp);
+            const double2 f = {0.0, h->k / eta};
+            gram_solve(*h, 0, ed, h->T1, nr, stream);
+            gemm2d(efie::G2D_NT, h->T1, n, false, h->S, n, false, b, n, nr, n, n, f, false, stream);
+            gram_solve(*h, 0, hd, h->T2, nr, stream);
+            gemm2d(efie::G2D_NN, h->T2, n, false, h->Dtt, n, false, b, n, nr, n, n, MONE, true, stream);
+            gram_apply(*h, 0, h->T2, b, nr, -0.5, 1.0, stream);
+        } else if (bp) {
             // b_p = N~ G^-1 e/(j k eta) + (G/2 - D*~) G^-1 h
             auto* b = static_cast<double2*>(bp);
             const double2 f = {0.0, -1.0 / (h->k * eta)};              // 1/(j k eta)
@@ -1351,15 +1416,16 @@ int efie_bie2d_counterpart(efie_bie2d h, void* col, void* col_inv, hipStream_t s
     });
 }
 
-int efie_bie2d_farfield(efie_bie2d h, double k, const void* J, int64_t nrhs, const double* phis, int64_t nphi,
-                        void* F, hipStream_t stream) {
+int efie_bie2d_farfield(efie_bie2d h, int pol, double k, const void* J, int64_t nrhs, const double* phis,
+                        int64_t nphi, void* F, hipStream_t stream) {
     return efie::guarded([&]() {
         EFIE_REQUIRE(h && J && phis && F && nrhs >= 1 && nphi >= 1, EFIE_ERR_ARG, "bie2d_farfield: bad argument");
+        EFIE_REQUIRE(pol == 0 || pol == 1, EFIE_ERR_ARG, "bie2d_farfield: pol must be 0 (TM) or 1 (TE)");
         EFIE_REQUIRE(h->dev != nullptr, EFIE_ERR_STATE, "bie2d_farfield: tables not uploaded");
         EFIE_REQUIRE(std::isfinite(k) && k > 0.0, EFIE_ERR_ARG, "bie2d_farfield: need k > 0");
         hipLaunchKernelGGL(efie::farfield2d_kernel, dim3(efie::grid_of(size_t(nrhs) * nphi)), dim3(256), 0, stream,
                            h->dc[0], k, static_cast<const double2*>(J), int(nrhs), phis, int(nphi),
-                           static_cast<double2*>(F));
+                           static_cast<double2*>(F), pol);
         EFIE_HIP_CHECK(hipGetLastError());
         return int(EFIE_OK);
     });

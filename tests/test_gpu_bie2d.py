@@ -8,7 +8,10 @@ the oracle (oracle/bie2d.py) on the same seeded contours and test matrices:
     right-hand sides e, h, b_p and the far field;
   * the fast direct solver with the oracle's test matrix: the same rank, the same
     projector U V^T and the same solution; the Woodbury identity; rank 0 for the
-    circle against itself; the PEC-cylinder current of the series solution.
+    circle against itself; the PEC-cylinder current of the series solution;
+  * TE incidence: C_p^TE X, (C_p^TE)^T X, the TE counterpart, e_t, h_z, b_p and the
+    TE far field against the oracle's System(pol="TE"); the same rank and solution
+    as the oracle's fast direct solver; the TE cylinder current and echo width.
 """
 import math
 
@@ -171,7 +174,86 @@ def test_bie2d_errors(dev):
         h.apply("cp", torch.zeros((1, 40), dtype=torch.complex128, device=dev))   # no setup yet
     with pytest.raises(P.EfieError):
         h.setup(5.0, rmax=16, block=65, nvec=65)             # blocks of at most 64 columns
+    with pytest.raises(ValueError):
+        h.setup(5.0, rmax=16, block=16, nvec=16, pol="TEM")
     h.setup(5.0, rmax=16, block=16, nvec=16)
     om = synth.gaussian_block(40, 40, seed=0)
     with pytest.raises(P.EfieError):
         h.skeleton(torch.as_tensor(om.T.copy(), device=dev), 1e-12)   # rank would exceed rmax
+
+
+@pytest.fixture(scope="module")
+def airfoil_te(dev):
+    N, k = 160, 8.0
+    nodes, circ = _pair(N, "airfoil")
+    kt = ob.ktilde(k)
+    so = ob.System(ob.Contour(nodes), k, kt, pol="TE")
+    sc = ob.System(ob.Contour(circ), k, kt, pol="TE")
+    h = P.Bie2d(nodes, circ, device=dev).setup(k, kt, rmax=N, block=16, nvec=64, pol="TE")
+    return N, k, kt, h, so, sc
+
+
+def test_te_apply_rhs_farfield(dev, airfoil_te):
+    N, k, kt, h, so, sc = airfoil_te
+    flush("bie2d TE: C_p, C_p^T, counterpart, rhs, far field")
+    Cp, Cc = so.calderon(), sc.calderon()
+    g = torch.Generator(device=dev).manual_seed(5)
+    X = torch.randn((5, N), dtype=torch.complex128, device=dev, generator=g)
+    Xn = X.cpu().numpy()
+    e = (rel(h.apply("cp", X).cpu().numpy(), (Cp @ Xn.T).T), rel(h.apply("cpt", X).cpu().numpy(), (Cp.T @ Xn.T).T),
+         rel(h.apply("a", X).cpu().numpy(), ((Cp - Cc) @ Xn.T).T))
+    flush(f"  rel err C_p {e[0]:.2e} C_p^T {e[1]:.2e} C_p - C_c {e[2]:.2e}")
+    assert e[0] <= 1e-11 and e[1] <= 1e-11 and e[2] <= 1e-10
+    col, coli = (t.cpu().numpy() for t in h.counterpart())
+    assert rel(col, Cc[:, 0]) <= 1e-11 and rel(coli, np.linalg.inv(Cc)[:, 0]) <= 1e-10
+    phis = np.array([0.2, 1.9, 4.0])
+    et, hz, bp = (t.cpu().numpy() for t in h.rhs(phis))
+    eo, ho = ob.excitation_te(so.c, k, phis)
+    assert rel(et, eo) <= 1e-13 and rel(hz, ho) <= 1e-13
+    assert rel(bp, so.calderon_rhs(eo, ho)) <= 1e-11
+    J = np.linalg.solve(Cp, so.calderon_rhs(eo, ho).T).T
+    obs = np.linspace(0.0, 2.0 * math.pi, 41)
+    F = h.farfield(k, torch.as_tensor(J, device=dev).contiguous(), obs).cpu().numpy()
+    assert rel(F, ob.farfield(so.c, k, J, obs, pol="TE")) <= 1e-12
+    F_tm = h.farfield(k, torch.as_tensor(J, device=dev).contiguous(), obs, pol="TM").cpu().numpy()
+    assert rel(F_tm, ob.farfield(so.c, k, J, obs)) <= 1e-12
+
+
+def test_te_fast_direct_solver_matches_oracle(dev, airfoil_te):
+    N, k, kt, h, so, sc = airfoil_te
+    Cp, Cc = so.calderon(), sc.calderon()
+    om = synth.gaussian_block(N, N, seed=2)
+    tol = 1e-5
+    flush(f"bie2d TE skeleton N={N} k={k} tol={tol}")
+    fo = ob.FastDirect(Cp, Cc, om, 16, tol)
+    r, est, ref = h.skeleton(torch.as_tensor(om.T.copy(), device=dev), tol)
+    flush(f"  rank gpu {r} oracle {fo.rank}")
+    assert r == fo.rank
+    U, Vt = (t.cpu().numpy() for t in h.factors())
+    assert rel(U.T @ Vt, fo.Q @ fo.Vt) <= 1e-9
+    e, hv, bp = h.rhs([0.0, 2.2])
+    X = h.solve(bp).cpu().numpy()
+    assert rel(X, fo.solve(bp.cpu().numpy().T).T) <= 1e-9
+    xd = np.linalg.solve(Cp, bp.cpu().numpy().T).T
+    assert rel(X, xd) <= 10 * tol * np.linalg.cond(Cp)
+
+
+def test_te_cylinder_current_and_echo_width(dev):
+    """TE on the circle (rank 0 against itself) at x = 1.8412, the first zero of J_1'
+    where the TE EFIE alone is singular: the series current and echo width."""
+    N, k = 400, 1.8411837813406593
+    circ = synth.contour_circle(N)
+    h = P.Bie2d(circ, circ, device=dev).setup(k, rmax=64, block=16, nvec=16, pol="TE")
+    r, est, ref = h.skeleton(torch.as_tensor(synth.gaussian_block(N, 32, seed=3).T.copy(), device=dev), 1e-6)
+    assert r == 0
+    e, hv, bp = h.rhs([0.4])
+    J = h.solve(bp)
+    ja = ob.cylinder_current_te(k, 1.0, 2.0 * math.pi * np.arange(N) / N, 0.4)
+    err = np.linalg.norm(J.cpu().numpy()[0] - ja) / np.linalg.norm(ja)
+    obs = np.linspace(0.0, 2.0 * math.pi, 73)
+    sw = ob.echo_width(k, h.farfield(k, J, obs).cpu().numpy()[0], pol="TE")
+    sa = ob.cylinder_echo_width_te(k, 1.0, obs, 0.4)
+    keep = 10 * np.log10(sa / sa.max()) > -30
+    db = np.abs(10 * np.log10(sw / sa))[keep].max()
+    flush(f"bie2d TE circle N={N} k={k}: current vs series {err:.2e}, echo width {db:.3f} dB")
+    assert err <= 1e-3 and db < 0.02
