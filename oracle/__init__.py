@@ -21,6 +21,9 @@ Modules
   mie         Mie series for a PEC sphere
   calderon    barycentric refinement, Buffa-Christiansen functions, the mixed
               Gram matrix and the Calderon-preconditioned operator
+  cfie        the 3-D Calderon-stabilized CFIE: the magnetic (MFIE) operator K
+              tested with rotated BC functions, its Calderon product and the
+              combination with the EFIE product (the 3-D reading of eq. 16)
   bie2d       the paper's own 2-D method: single, adjoint double and hypersingular
               layer operators with the Hankel kernel on a closed polygon, the TM
               CFIE of a PEC cylinder, its Calderon-stabilized form C_p (eq. 16),
