@@ -452,6 +452,54 @@ int efie_solve_precond_ex(const void* Z, int zdt, const void* P, int pdt, int64_
                           int64_t nrhs, const efie_solve_opts* opts, efie_rhs_stats* stats, void* ws,
                           size_t ws_bytes, hipStream_t stream);
 
+/* --------------------------------------- Calderon-stabilized CFIE (3-D) */
+
+/*
+ * The paper's stabilized operator (Sec. III, eq. 16) adds to the Calderon product
+ * of the electric operator that of the magnetic one (the MFIE part of the CFIE of
+ * eq. 7), each second factor at k~.  In 3-D, with f RWG and g BC functions:
+ *   K J = n x p.v. int grad G_k(r, r') x J(r') dS'   (MFIE: (1/2 - K) J = n x H^inc),
+ *   K_BC(k)[m][n] = (g_m, p.v. int grad G_k x f_n dS')  (the MFIE tested with n x g_m),
+ *   M  = eta (-G_mix^T / 2 - K_BC(k))     = eta (n x g_m, (1/2 - K_k) f_n),
+ *   M~ = eta (-G_mix^T / 2 + K_BC(k~))    = eta (n x g_m, (1/2 + K_k~) f_n),
+ *   Q  = M~ G_mix^-T,
+ *   eta^2 C_p = P Z + Q M,   eta^2 b_p = P V + Q H,
+ *   H[s][m] = (g_m, (khat_s x pol_s) exp(-j k khat_s . r)) = eta (g_m, H^inc_s)
+ * with P = T_BC(k~) G_mix^-1 (efie_calderon_assemble) and Z, V the EFIE matrix and
+ * right-hand side.  C_p is a second-kind operator (near -1/2 + 2 K~ K), free of the
+ * interior resonances of the EFIE and of the MFIE.  The sign of the combination
+ * follows from the Calderon identity (n x T/eta)^2 = -1/4 + K^2.
+ * K_BC is built as R^T K_mix, K_mix[e][n] = (f_e, p.v. int grad G x f_n) over the
+ * barycentric RWGs f_e (test triangle b inside primal triangle b / 6): zero on
+ * the coplanar pair (b / 6, b / 6); singularity extraction (7-point smooth part
+ * plus the closed-form int (r - r')/R^3 dS') on the primal pairs the EFIE near
+ * rule calls near; the 7 x 7 product rule elsewhere.  FP64 throughout.
+ *
+ * efie_calderon_cfie_assemble: M and Q into dev buffers (N x N complex128 each),
+ *   optionally K_BC(k) and K_BC(k~) (raw, N x N complex128) into K_out, Kt_out;
+ *   k > 0 real, kt_im <= 0; Q by CGNR on G_mix to tol (maxit sweeps; complex64
+ *   vectors when tol >= 1e-4), its worst relative residual in *relres.  Needs the
+ *   mesh and the Calderon tables uploaded; ws as for efie_calderon_assemble
+ *   (ws_bytes from efie_calderon_sizes).  Returns EFIE_NOT_CONVERGED if Q missed tol.
+ * efie_calderon_mfie_rhs: H (dev, nrhs x N complex128) for the plane waves khat_s,
+ *   pol_s (dev, nrhs x 3 doubles each); ws (256-aligned) of the size from
+ *   efie_calderon_mfie_rhs_workspace_size.
+ * efie_solve_cfie: CGS (opts->solver EFIE_CGS) on (P Z + Q M) J = P V + Q H, every
+ *   matrix complex128 (n x n), V, H, J (nrhs x n); FP64 products; stats report the
+ *   FP64 true residual of the stabilized system; ws from
+ *   efie_solve_cfie_workspace_size.
+ */
+int efie_calderon_cfie_assemble(efie_calderon c, double k, double kt_re, double kt_im, double eta, void* M, void* Q,
+                                void* K_out, void* Kt_out, double tol, int32_t maxit, double* relres, void* ws,
+                                size_t ws_bytes, hipStream_t stream);
+int efie_calderon_mfie_rhs_workspace_size(efie_calderon c, int64_t nrhs, size_t* bytes);
+int efie_calderon_mfie_rhs(efie_calderon c, double k, const double* khat, const double* pol, int64_t nrhs, void* H,
+                           void* ws, size_t ws_bytes, hipStream_t stream);
+int efie_solve_cfie_workspace_size(int64_t n, int64_t nrhs, size_t* bytes);
+int efie_solve_cfie(const void* Z, const void* P, const void* M, const void* Q, int64_t n, const void* V,
+                    const void* H, void* J, int64_t nrhs, const efie_solve_opts* opts, efie_rhs_stats* stats,
+                    void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* ---------------------------------------------------------- many meshes */
 
 /*

@@ -52,6 +52,8 @@ EXPORTED = [
     "efie_bie2d_create", "efie_bie2d_destroy", "efie_bie2d_sizes", "efie_bie2d_upload", "efie_bie2d_perimeter",
     "efie_bie2d_assemble", "efie_bie2d_setup", "efie_bie2d_apply", "efie_bie2d_rhs", "efie_bie2d_skeleton",
     "efie_bie2d_solve", "efie_bie2d_factors", "efie_bie2d_counterpart", "efie_bie2d_farfield",
+    "efie_calderon_cfie_assemble", "efie_calderon_mfie_rhs_workspace_size", "efie_calderon_mfie_rhs",
+    "efie_solve_cfie_workspace_size", "efie_solve_cfie",
 ]
 PROF_IDS = {"far": 0, "near": 1, "mfma": 2, "gemv": 3, "zgemm": 4, "krylov": 5, "excite": 6, "farfield": 7, "grad_far": 8,
             "grad_near": 9, "grad_tri": 10}
@@ -152,6 +154,13 @@ def lib():
         "efie_solve_precond_ex": ([P, ctypes.c_int, P, ctypes.c_int, I64, P, P, I64, ctypes.POINTER(_SolveOpts),
                                    ctypes.POINTER(_RhsStats), P, ctypes.c_size_t, P], ctypes.c_int),
         "efie_solve_precond_workspace_size": ([I64, I64, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "efie_calderon_cfie_assemble": ([P, D, D, D, D, P, P, P, P, D, I32, ctypes.POINTER(D), P, ctypes.c_size_t, P],
+                                        ctypes.c_int),
+        "efie_calderon_mfie_rhs_workspace_size": ([P, I64, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "efie_calderon_mfie_rhs": ([P, D, P, P, I64, P, P, ctypes.c_size_t, P], ctypes.c_int),
+        "efie_solve_cfie_workspace_size": ([I64, I64, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "efie_solve_cfie": ([P, P, P, P, I64, P, P, P, I64, ctypes.POINTER(_SolveOpts), ctypes.POINTER(_RhsStats), P,
+                             ctypes.c_size_t, P], ctypes.c_int),
         "efie_solve_precond": ([P, P, I64, P, P, I64, ctypes.POINTER(_SolveOpts), ctypes.POINTER(_RhsStats), P,
                                 ctypes.c_size_t, P], ctypes.c_int),
         "efie_batch_create": ([P, I32, ctypes.POINTER(P)], ctypes.c_int),
@@ -649,6 +658,53 @@ class Calderon:
         self.gram_relres = rel.value
         return (Pm, T) if with_tbc else Pm
 
+    def cfie(self, k: float, kt=None, eta: float = ETA0, tol: float = 1e-13, maxit: int = 500, with_k=False,
+             a: float = 1.0):
+        """The MFIE factors of the Calderon-stabilized CFIE on the device: M =
+        eta (-G_mix^T/2 - K_BC(k)) and Q = eta (-G_mix^T/2 + K_BC(k~)) G_mix^-T (N x N
+        complex128 each), with eta^2 C_p = P Z + Q M; k~ the paper's complex
+        wavenumber of radius a unless given.  with_k also returns K_BC(k), K_BC(k~)."""
+        torch = _torch()
+        if self._dev is None:
+            self.upload()
+        dev = self.mesh.device
+        n = self.mesh.n
+        kt = ktilde(k, a) if kt is None else complex(kt)
+        M = torch.empty((n, n), dtype=torch.complex128, device=dev)
+        Q = torch.empty((n, n), dtype=torch.complex128, device=dev)
+        K1 = torch.empty((n, n), dtype=torch.complex128, device=dev) if with_k else None
+        K2 = torch.empty((n, n), dtype=torch.complex128, device=dev) if with_k else None
+        ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=dev)
+        off = (-ws.data_ptr()) % 256
+        rel = ctypes.c_double()
+        code = lib().efie_calderon_cfie_assemble(self._h, float(k), kt.real, kt.imag, float(eta), _ptr(M), _ptr(Q),
+                                                 _ptr(K1) if with_k else None, _ptr(K2) if with_k else None,
+                                                 float(tol), int(maxit), ctypes.byref(rel),
+                                                 ctypes.c_void_p(ws.data_ptr() + off), self.ws_bytes, _stream(dev))
+        _check(code, allow_not_converged=True)
+        del ws
+        self.cfie_gram_relres = rel.value
+        return (M, Q, K1, K2) if with_k else (M, Q)
+
+    def mfie_rhs(self, k: float, khat, pol):
+        """H (nrhs, N) complex128: H[s][m] = (g_m, (khat_s x pol_s) exp(-j k khat_s . r)),
+        eta times the BC-tested incident magnetic field of E = pol exp(-j k khat . r)."""
+        torch = _torch()
+        if self._dev is None:
+            self.upload()
+        dev = self.mesh.device
+        kh = _dev_vectors(khat, dev)
+        po = _dev_vectors(pol, dev)
+        S = kh.shape[0]
+        nb = ctypes.c_size_t()
+        _check(lib().efie_calderon_mfie_rhs_workspace_size(self._h, S, ctypes.byref(nb)))
+        ws = torch.empty(nb.value + 256, dtype=torch.uint8, device=dev)
+        off = (-ws.data_ptr()) % 256
+        H = torch.empty((S, self.mesh.n), dtype=torch.complex128, device=dev)
+        _check(lib().efie_calderon_mfie_rhs(self._h, float(k), _ptr(kh), _ptr(po), S, _ptr(H),
+                                            ctypes.c_void_p(ws.data_ptr() + off), nb.value, _stream(dev)))
+        return H
+
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and _lib is not None:
@@ -680,6 +736,40 @@ def solve_precond(Z, Pm, V, tol=1e-8, maxit=1000, max_refine=6, inner_tol=1e-4, 
     st = (_RhsStats * S)()
     code = lib().efie_solve_precond_ex(_ptr(Z), zdt, _ptr(Pm), pdt, n, _ptr(V), _ptr(J), S, ctypes.byref(opts), st,
                                        ctypes.c_void_p(ws.data_ptr() + off), nb.value, _stream(Z.device))
+    _check(code, allow_not_converged=True)
+    return J, SolveStats(
+        iters=np.array([s.iters for s in st]), status=np.array([s.status for s in st]),
+        relres_recur=np.array([s.relres_recur for s in st]), relres_true=np.array([s.relres_true for s in st]),
+        code=code,
+    )
+
+
+def solve_cfie(Z, Pm, M, Q, V, H, tol=1e-8, maxit=1000, out=None):
+    """CGS on the Calderon-stabilized CFIE (P Z + Q M) J = P V + Q H (every matrix
+    complex128, FP64 products); stats report the FP64 true residual of that system."""
+    torch = _torch()
+    for t, nm in ((Z, "Z"), (Pm, "P"), (M, "M"), (Q, "Q")):
+        _require_cuda(t, nm)
+        if t.dtype != torch.complex128:
+            raise ValueError(f"{nm} must be complex128")
+    n = Z.shape[0]
+    V = V.reshape(-1, n)
+    H = H.reshape(-1, n)
+    _require_cuda(V, "V")
+    _require_cuda(H, "H")
+    if V.shape != H.shape:
+        raise ValueError("V and H must have the same shape")
+    S = V.shape[0]
+    J = out if out is not None else torch.empty_like(V)
+    nb = ctypes.c_size_t()
+    _check(lib().efie_solve_cfie_workspace_size(n, S, ctypes.byref(nb)))
+    ws = torch.empty(nb.value + 256, dtype=torch.uint8, device=Z.device)
+    off = (-ws.data_ptr()) % 256
+    opts = _SolveOpts(CGS, int(maxit), float(tol), 1, 1e-4, 0)
+    st = (_RhsStats * S)()
+    code = lib().efie_solve_cfie(_ptr(Z), _ptr(Pm), _ptr(M), _ptr(Q), n, _ptr(V), _ptr(H), _ptr(J), S,
+                                 ctypes.byref(opts), st, ctypes.c_void_p(ws.data_ptr() + off), nb.value,
+                                 _stream(Z.device))
     _check(code, allow_not_converged=True)
     return J, SolveStats(
         iters=np.array([s.iters for s in st]), status=np.array([s.status for s in st]),

@@ -25,6 +25,7 @@
 
 #include "calderon.h"
 #include "linalg.h"
+#include "mfie_pair.h"
 
 namespace efie {
 
@@ -442,6 +443,149 @@ __global__ __launch_bounds__(256) void tile_out_kernel(const V* __restrict__ w, 
     }
 }
 
+// ------------------------------------------ the MFIE operator of the 3-D CFIE
+// K_BC(k) = R^T K_mix(k) without forming K_mix (N_b x N): per chunk of
+// barycentric test triangles p, every pair value into W[p][i][n][side] (source
+// RWG n primal, side 0 where the source triangle is T+(n)), then the test-side
+// contraction K_BC[m][n] += sum R[e(p, i)][m] (W[p][i][n][0] + W[p][i][n][1]) by
+// the BC-row lists of the T_BC build (no atomics; chunks in order).
+constexpr int K_PB = 4;   // barycentric test triangles per block of k_rows_kernel
+
+// block = (K_PB test triangles of the chunk, 256 primal source triangles), the
+// blocks of consecutive test triangles kept on one XCD (as in the far-row kernel);
+// every slot of a row is written: the three local edges of the source triangles
+// cover each (n, side) once
+__global__ __launch_bounds__(256) void k_rows_kernel(DevMesh mb, DevMesh m, double kr, double ki,
+                                                     double2* __restrict__ W, int c0, int np, int nqblk) {
+    const int nblk = int(gridDim.x);
+    const int xcd = int(blockIdx.x) & 7, idx = int(blockIdx.x) >> 3;
+    const int per = nblk >> 3, rem = nblk & 7;
+    const int logical = xcd * per + min(xcd, rem) + idx;
+    const int pg = logical / nqblk, qb = logical - pg * nqblk;
+    const int q = qb * 256 + int(threadIdx.x);
+    const int T = m.T;
+    if (q >= T) return;
+    const size_t N = size_t(m.N);
+    const int pl1 = min(np, (pg + 1) * K_PB);
+    for (int pl = pg * K_PB; pl < pl1; ++pl) {
+        const int p = c0 + pl, t = p / 6;   // the refinement's triangle p lies in primal triangle p / 6
+        double2* rows = W + size_t(pl) * 6 * N;
+        auto put = [&](int i, int j, double re, double im) {
+            const size_t n = size_t(m.te[j * T + q]);
+            const int side = m.cf[j * T + q] > 0.0 ? 0 : 1;
+            rows[(size_t(i) * N + n) * 2 + side] = make_double2(re, im);
+        };
+        if (q == t) {   // coplanar: the principal value vanishes
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) put(i, j, 0.0, 0.0);
+            continue;
+        }
+        mfie_pair(mb, m, p, q, kr, ki, is_near(m, t, q), put);
+    }
+}
+
+// K[m][n] += sum_k coef[k] (W[rows[k]][n][0] + W[rows[k]][n][1]) over the list of
+// BC row m = ml[blockIdx.y]
+__global__ __launch_bounds__(256) void kbc_test_kernel(const int32_t* __restrict__ ml,
+                                                       const int32_t* __restrict__ mptr,
+                                                       const int32_t* __restrict__ rows,
+                                                       const double* __restrict__ coef,
+                                                       const double2* __restrict__ W, double2* __restrict__ K, int N) {
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    const int mi = blockIdx.y;
+    if (n >= N) return;
+    const size_t o = size_t(ml[mi]) * N + n;
+    double2 acc = K[o];
+    for (int k = mptr[mi]; k < mptr[mi + 1]; ++k) {
+        const double2* w = W + size_t(rows[k]) * 2 * size_t(N) + 2 * size_t(n);
+        const double2 a = w[0], b = w[1];
+        acc.x += coef[k] * (a.x + b.x);
+        acc.y += coef[k] * (a.y + b.y);
+    }
+    K[o] = acc;
+}
+
+// Y = a X (n complex elements; Y may be X)
+__global__ void scale_c_kernel(const double2* X, double2* Y, double a, size_t n) {
+    size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const size_t stride = size_t(gridDim.x) * blockDim.x;
+    for (; i < n; i += stride) {
+        const double2 v = X[i];
+        Y[i] = make_double2(a * v.x, a * v.y);
+    }
+}
+
+// Y[order[t]][idx[e]] += a val[e] over the stored rows t of a real CSR matrix whose
+// rows are stored in the order `order` (one thread per row: no two threads touch
+// one element)
+__global__ void add_csr_kernel(const int32_t* __restrict__ ptr, const int32_t* __restrict__ idx,
+                               const double* __restrict__ val, const int32_t* __restrict__ order, int N, double a,
+                               double2* __restrict__ Y) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N) return;
+    double2* row = Y + size_t(order[t]) * N;
+    for (int e = ptr[t]; e < ptr[t + 1]; ++e) row[idx[e]].x += a * val[e];
+}
+
+// T <- T^T in place (N x N complex128): one block per pair of mirror 32 x 32
+// tiles (bi <= bj), both read into LDS before either is written
+__global__ __launch_bounds__(256) void transpose_inplace_kernel(double2* __restrict__ T, int N, int nt) {
+    __shared__ double2 a[32][33], b[32][33];
+    int k = int(blockIdx.x), bi = 0;
+    while (k >= nt - bi) {
+        k -= nt - bi;
+        ++bi;
+    }
+    const int bj = bi + k;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+    for (int r = ty; r < 32; r += 8) {
+        const int i = bi * 32 + r, j = bj * 32 + tx;
+        const int i2 = bj * 32 + r, j2 = bi * 32 + tx;
+        if (i < N && j < N) a[r][tx] = T[size_t(i) * N + j];
+        if (i2 < N && j2 < N) b[r][tx] = T[size_t(i2) * N + j2];
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        // (bi*32 + r, bj*32 + tx) <- old (bj*32 + tx, bi*32 + r) = b[tx][r]
+        const int i = bi * 32 + r, j = bj * 32 + tx;
+        if (i < N && j < N) T[size_t(i) * N + j] = b[tx][r];
+        if (bi != bj) {   // (bj*32 + r, bi*32 + tx) <- old (bi*32 + tx, bj*32 + r) = a[tx][r]
+            const int i2 = bj * 32 + r, j2 = bi * 32 + tx;
+            if (i2 < N && j2 < N) T[size_t(i2) * N + j2] = a[tx][r];
+        }
+    }
+}
+
+// out[s] = khat_s x pol_s
+__global__ void cross3_kernel(const double* __restrict__ kh, const double* __restrict__ po, double* __restrict__ out,
+                              int nrhs) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nrhs) return;
+    const double* a = kh + 3 * s;
+    const double* b = po + 3 * s;
+    out[3 * s] = a[1] * b[2] - a[2] * b[1];
+    out[3 * s + 1] = a[2] * b[0] - a[0] * b[2];
+    out[3 * s + 2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// H[s][n] = sum over column n of R of r_val[k] Vb[s][r_idx[k]]: BC-tested values
+// from barycentric-RWG-tested ones
+__global__ void bc_contract_kernel(DevCald c, const double2* __restrict__ Vb, int nrhs, double2* __restrict__ H) {
+    const size_t idx = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= size_t(c.N) * nrhs) return;
+    const int s = int(idx / c.N), n = int(idx - size_t(s) * c.N);
+    const double2* v = Vb + size_t(s) * c.Nb;
+    double ar = 0.0, ai = 0.0;
+    for (int k = c.r_ptr[n]; k < c.r_ptr[n + 1]; ++k) {
+        const double2 x = v[c.r_idx[k]];
+        ar += c.r_val[k] * x.x;
+        ai += c.r_val[k] * x.y;
+    }
+    H[idx] = make_double2(ar, ai);
+}
+
 namespace {
 
 size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
@@ -590,11 +734,17 @@ size_t put(std::vector<char>& blob, std::vector<size_t>& offs, const std::vector
     return off;
 }
 
-// CGNR on G^T Y = T_BC for the columns of T_BC in batches of pl.Sb (vectors stored
-// as V), each batch transposed into P; returns the worst final relative residual.
+// CGNR on A Y = B for the columns of B (N x N, row-major) in batches of pl.Sb
+// (vectors stored as V), each batch transposed into the rows of Pout; A = G^T
+// (opG false) or G (opG true).  Returns the worst final relative residual.
 template <typename V>
 double cald_cgnr(const DevCald& d, const CaldWs& w, const CaldPlan& pl, int N, double tol, int maxit, double2* Pout,
-                 hipStream_t stream) {
+                 const double2* B, bool opG, hipStream_t stream) {
+    // A p with the CSR of A, A^T r with the CSR of A^T
+    const int32_t *a_ptr = opG ? d.g_ptr : d.gt_ptr, *a_idx = opG ? d.g_idx : d.gt_idx;
+    const double* a_val = opG ? d.g_val : d.gt_val;
+    const int32_t *at_ptr = opG ? d.gt_ptr : d.g_ptr, *at_idx = opG ? d.gt_idx : d.g_idx;
+    const double* at_val = opG ? d.gt_val : d.g_val;
     V* const wv = static_cast<V*>(w.w);
     V* const rv = static_cast<V*>(w.r);
     V* const zv = static_cast<V*>(w.z);
@@ -610,16 +760,16 @@ double cald_cgnr(const DevCald& d, const CaldWs& w, const CaldPlan& pl, int N, d
             hipLaunchKernelGGL(colsq_final_kernel, dim3(unsigned((S + 15) / 16)), dim3(256), 0, stream, w.part, S, ns,
                                out);
         };
-        hipLaunchKernelGGL(cgnr_init_kernel<V>, gs, dim3(256), 0, stream, w.Tbc + s0, N, wv, rv, N, S, w.part);
+        hipLaunchKernelGGL(cgnr_init_kernel<V>, gs, dim3(256), 0, stream, B + s0, N, wv, rv, N, S, w.part);
         finish(w.bn2);
-        hipLaunchKernelGGL(cspmm_kernel<V>, gs, dim3(256), 0, stream, d.g_ptr, d.g_idx, d.g_val, rv, zv, S, d.n_order,
+        hipLaunchKernelGGL(cspmm_kernel<V>, gs, dim3(256), 0, stream, at_ptr, at_idx, at_val, rv, zv, S, d.n_order,
                            N, w.part);
         finish(w.zz);
         EFIE_HIP_CHECK(hipMemcpyAsync(pv, zv, tot * sizeof(V), hipMemcpyDeviceToDevice, stream));
         hipLaunchKernelGGL(cgnr_setup_kernel, gc, dim3(256), 0, stream, w.cols, w.bn2, w.zz, tol, S);
         int h_active = S;
         for (int it = 0; it < maxit && h_active > 0; ++it) {
-            hipLaunchKernelGGL(cspmm_kernel<V>, gs, dim3(256), 0, stream, d.gt_ptr, d.gt_idx, d.gt_val, pv, tv, S,
+            hipLaunchKernelGGL(cspmm_kernel<V>, gs, dim3(256), 0, stream, a_ptr, a_idx, a_val, pv, tv, S,
                                d.n_order, N, w.part);
             finish(w.tt);
             hipLaunchKernelGGL(cgnr_upd1_kernel<V>, gs, dim3(256), 0, stream, wv, rv, pv, tv, w.cols, w.tt, N, S,
@@ -627,7 +777,7 @@ double cald_cgnr(const DevCald& d, const CaldWs& w, const CaldPlan& pl, int N, d
             finish(w.rn2);
             EFIE_HIP_CHECK(hipMemsetAsync(w.counter, 0, sizeof(int), stream));
             hipLaunchKernelGGL(cgnr_check_kernel, gc, dim3(256), 0, stream, w.cols, w.rn2, w.tt, S, w.counter);
-            hipLaunchKernelGGL(cspmm_kernel<V>, gs, dim3(256), 0, stream, d.g_ptr, d.g_idx, d.g_val, rv, zv, S,
+            hipLaunchKernelGGL(cspmm_kernel<V>, gs, dim3(256), 0, stream, at_ptr, at_idx, at_val, rv, zv, S,
                                d.n_order, N, w.part);
             finish(w.zz);
             hipLaunchKernelGGL(cgnr_upd2_kernel<V>, gs, dim3(256), 0, stream, pv, zv, w.cols, w.zz, N, S);
@@ -845,8 +995,9 @@ int efie_calderon_assemble_ex(efie_calderon c, double kt_re, double kt_im, doubl
         if (Tbc_out)
             EFIE_HIP_CHECK(hipMemcpyAsync(Tbc_out, w.Tbc, size_t(N) * N * 16, hipMemcpyDeviceToDevice, stream));
         // ---- P = T_BC G^{-1}: column batches of G^T Y = T_BC (column s = row s of T_BC), P = Y^T
-        const double worst = pl.vsz == 8 ? cald_cgnr<float2>(d, w, pl, N, tol, maxit, static_cast<double2*>(P), stream)
-                                         : cald_cgnr<double2>(d, w, pl, N, tol, maxit, static_cast<double2*>(P), stream);
+        const double worst =
+            pl.vsz == 8 ? cald_cgnr<float2>(d, w, pl, N, tol, maxit, static_cast<double2*>(P), w.Tbc, false, stream)
+                        : cald_cgnr<double2>(d, w, pl, N, tol, maxit, static_cast<double2*>(P), w.Tbc, false, stream);
         if (relres) *relres = worst;
         EFIE_HIP_CHECK(hipGetLastError());
         return worst <= tol ? int(EFIE_OK) : int(EFIE_NOT_CONVERGED);
@@ -857,6 +1008,124 @@ int efie_calderon_assemble(efie_calderon c, double kt_re, double kt_im, double e
                            double tol, int32_t maxit, double* relres, void* ws, size_t ws_bytes, hipStream_t stream) {
     return efie_calderon_assemble_ex(c, kt_re, kt_im, eta, EFIE_C128, P, Tbc_out, tol, maxit, relres, ws, ws_bytes,
                                      stream);
+}
+
+int efie_calderon_cfie_assemble(efie_calderon c, double k, double kt_re, double kt_im, double eta, void* M, void* Q,
+                                void* K_out, void* Kt_out, double tol, int32_t maxit, double* relres, void* ws,
+                                size_t ws_bytes, hipStream_t stream) {
+    using namespace efie;
+    return guarded([&]() {
+        EFIE_REQUIRE(c && M && Q && ws, EFIE_ERR_ARG, "calderon_cfie_assemble: null argument");
+        EFIE_REQUIRE(c->dev != nullptr && c->primal->dev != nullptr, EFIE_ERR_STATE,
+                     "calderon_cfie_assemble: tables not uploaded (mesh and Calderon)");
+        EFIE_REQUIRE(std::isfinite(k) && k > 0.0, EFIE_ERR_ARG, "calderon_cfie_assemble: need k > 0");
+        EFIE_REQUIRE(std::isfinite(kt_re) && std::isfinite(kt_im) && kt_im <= 0.0 && (kt_re != 0.0 || kt_im != 0.0),
+                     EFIE_ERR_ARG, "calderon_cfie_assemble: bad k~");
+        EFIE_REQUIRE(std::isfinite(eta) && eta > 0.0, EFIE_ERR_ARG, "calderon_cfie_assemble: need eta > 0");
+        EFIE_REQUIRE(tol > 0.0 && maxit >= 1, EFIE_ERR_ARG, "calderon_cfie_assemble: bad tol/maxit");
+        const int N = int(c->N);
+        const CaldPlan pl = cald_plan(*c, EFIE_C128, tol);
+        const size_t need = cald_layout(*c, pl, EFIE_C128, nullptr, nullptr);
+        EFIE_REQUIRE(ws_bytes >= need, EFIE_ERR_ARG, "calderon_cfie_assemble: workspace too small");
+        EFIE_REQUIRE((reinterpret_cast<uintptr_t>(ws) & 255) == 0, EFIE_ERR_ARG,
+                     "calderon_cfie_assemble: ws not aligned");
+        CaldWs w;
+        cald_layout(*c, pl, EFIE_C128, &w, static_cast<char*>(ws));
+        const DevCald d = dev_cald(*c);
+        const CaldLists L = cald_lists(*c, pl);
+        EFIE_HIP_CHECK(hipMemcpyAsync(w.ml, L.ml.data(), 4 * L.ml.size(), hipMemcpyHostToDevice, stream));
+        EFIE_HIP_CHECK(hipMemcpyAsync(w.mptr, L.mptr.data(), 4 * L.mptr.size(), hipMemcpyHostToDevice, stream));
+        EFIE_HIP_CHECK(hipMemcpyAsync(w.rows, L.rows.data(), 4 * L.rows.size(), hipMemcpyHostToDevice, stream));
+        EFIE_HIP_CHECK(hipMemcpyAsync(w.coef, L.coef.data(), 8 * L.coef.size(), hipMemcpyHostToDevice, stream));
+        const DevMesh& mb = c->bary.dm;
+        const DevMesh& m = c->primal->dm;
+        const int Tb = int(c->bary.T);
+        const int nqblk = (m.T + 255) / 256;
+        const unsigned nx = unsigned((N + 255) / 256);
+        const size_t nn = size_t(N) * size_t(N);
+        const unsigned gsc = unsigned(std::min<size_t>((nn + 255) / 256, 65536));
+        auto build_k = [&](double kr, double ki) {   // K_BC(kr + j ki) into w.Tbc
+            fill_zero_bytes(w.Tbc, nn * 16, stream);
+            for (int ch = 0; ch < pl.nchunks; ++ch) {
+                const int c0 = ch * pl.chunk, c1 = std::min(Tb, c0 + pl.chunk), np = c1 - c0;
+                const size_t nblk = size_t((np + K_PB - 1) / K_PB) * size_t(nqblk);
+                EFIE_REQUIRE(nblk < (size_t(1) << 31), EFIE_ERR_ARG, "calderon_cfie_assemble: chunk too large");
+                hipLaunchKernelGGL(k_rows_kernel, dim3(unsigned(nblk)), dim3(256), 0, stream, mb, m, kr, ki,
+                                   static_cast<double2*>(w.W), c0, np, nqblk);
+                if (L.nm[size_t(ch)] > 0)
+                    hipLaunchKernelGGL(kbc_test_kernel, dim3(nx, unsigned(L.nm[size_t(ch)])), dim3(256), 0, stream,
+                                       w.ml + L.m0[size_t(ch)], w.mptr + L.mp0[size_t(ch)], w.rows, w.coef,
+                                       static_cast<const double2*>(w.W), w.Tbc, N);
+            }
+            if (verbose()) {
+                EFIE_HIP_CHECK(hipStreamSynchronize(stream));
+                std::fprintf(stderr, "[efie] cfie K_BC(%g%+gj) t=%.3f\n", kr, ki, now_s());
+                std::fflush(stderr);
+            }
+        };
+        const unsigned gr = unsigned((N + 255) / 256);
+        // M = eta (-G^T / 2 - K_BC(k))
+        build_k(k, 0.0);
+        if (K_out) EFIE_HIP_CHECK(hipMemcpyAsync(K_out, w.Tbc, nn * 16, hipMemcpyDeviceToDevice, stream));
+        hipLaunchKernelGGL(scale_c_kernel, dim3(gsc), dim3(256), 0, stream, w.Tbc, static_cast<double2*>(M), -eta, nn);
+        hipLaunchKernelGGL(add_csr_kernel, dim3(gr), dim3(256), 0, stream, d.gt_ptr, d.gt_idx, d.gt_val, d.n_order, N,
+                           -0.5 * eta, static_cast<double2*>(M));
+        // M~ = eta (-G^T / 2 + K_BC(k~)), transposed in place: its rows are the
+        // right-hand sides of G Q^T = M~^T
+        build_k(kt_re, kt_im);
+        if (Kt_out) EFIE_HIP_CHECK(hipMemcpyAsync(Kt_out, w.Tbc, nn * 16, hipMemcpyDeviceToDevice, stream));
+        hipLaunchKernelGGL(scale_c_kernel, dim3(gsc), dim3(256), 0, stream, w.Tbc, w.Tbc, eta, nn);
+        hipLaunchKernelGGL(add_csr_kernel, dim3(gr), dim3(256), 0, stream, d.gt_ptr, d.gt_idx, d.gt_val, d.n_order, N,
+                           -0.5 * eta, w.Tbc);
+        {
+            const int nt = (N + 31) / 32;
+            const size_t npairs = size_t(nt) * size_t(nt + 1) / 2;
+            EFIE_REQUIRE(npairs < (size_t(1) << 31), EFIE_ERR_ARG, "calderon_cfie_assemble: N too large");
+            hipLaunchKernelGGL(transpose_inplace_kernel, dim3(unsigned(npairs)), dim3(256), 0, stream, w.Tbc, N, nt);
+        }
+        // Q = M~ G^-T: row s of Q solves G y = row s of M~
+        const double worst =
+            pl.vsz == 8 ? cald_cgnr<float2>(d, w, pl, N, tol, maxit, static_cast<double2*>(Q), w.Tbc, true, stream)
+                        : cald_cgnr<double2>(d, w, pl, N, tol, maxit, static_cast<double2*>(Q), w.Tbc, true, stream);
+        if (relres) *relres = worst;
+        EFIE_HIP_CHECK(hipGetLastError());
+        return worst <= tol ? int(EFIE_OK) : int(EFIE_NOT_CONVERGED);
+    });
+}
+
+int efie_calderon_mfie_rhs_workspace_size(efie_calderon c, int64_t nrhs, size_t* bytes) {
+    return efie::guarded([&]() {
+        EFIE_REQUIRE(c && bytes && nrhs >= 1, EFIE_ERR_ARG, "calderon_mfie_rhs_workspace_size: bad argument");
+        *bytes = efie::a256(size_t(24) * size_t(nrhs)) + size_t(nrhs) * size_t(c->bary.N) * 16;
+        return int(EFIE_OK);
+    });
+}
+
+int efie_calderon_mfie_rhs(efie_calderon c, double k, const double* khat, const double* pol, int64_t nrhs, void* H,
+                           void* ws, size_t ws_bytes, hipStream_t stream) {
+    using namespace efie;
+    return guarded([&]() {
+        EFIE_REQUIRE(c && khat && pol && H && ws, EFIE_ERR_ARG, "calderon_mfie_rhs: null argument");
+        EFIE_REQUIRE(c->dev != nullptr, EFIE_ERR_STATE, "calderon_mfie_rhs: tables not uploaded");
+        EFIE_REQUIRE(std::isfinite(k) && k > 0.0, EFIE_ERR_ARG, "calderon_mfie_rhs: need k > 0");
+        EFIE_REQUIRE(nrhs >= 1 && nrhs * c->bary.N < (int64_t(1) << 31), EFIE_ERR_ARG, "calderon_mfie_rhs: bad nrhs");
+        const size_t off = a256(size_t(24) * size_t(nrhs));
+        EFIE_REQUIRE(ws_bytes >= off + size_t(nrhs) * size_t(c->bary.N) * 16, EFIE_ERR_ARG,
+                     "calderon_mfie_rhs: workspace too small");
+        EFIE_REQUIRE((reinterpret_cast<uintptr_t>(ws) & 255) == 0, EFIE_ERR_ARG, "calderon_mfie_rhs: ws not aligned");
+        double* kxp = static_cast<double*>(ws);
+        auto* Vb = reinterpret_cast<double2*>(static_cast<char*>(ws) + off);
+        const int S = int(nrhs);
+        hipLaunchKernelGGL(cross3_kernel, dim3((S + 255) / 256), dim3(256), 0, stream, khat, pol, kxp, S);
+        const int code = efie_excite_planewave(&c->bary, k, khat, kxp, nrhs, 1.0, Vb, stream);
+        if (code != EFIE_OK) return code;
+        const DevCald d = dev_cald(*c);
+        const size_t tot = size_t(c->N) * size_t(S);
+        hipLaunchKernelGGL(bc_contract_kernel, dim3(unsigned((tot + 255) / 256)), dim3(256), 0, stream, d, Vb, S,
+                           static_cast<double2*>(H));
+        EFIE_HIP_CHECK(hipGetLastError());
+        return int(EFIE_OK);
+    });
 }
 
 }  // extern "C"

@@ -467,6 +467,16 @@ __global__ void force_replace_kernel(Col* cols, int S, int* counters) {
         }
 }
 
+// Y[idx[c]] += X[idx[c]] for the m listed rows (n elements each)
+__global__ void add_rows_kernel(double2* __restrict__ Y, const double2* __restrict__ X, const int* __restrict__ idx,
+                                int n) {
+    const size_t o = size_t(idx[blockIdx.y]) * n;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+        const double2 a = Y[o + k], b = X[o + k];
+        Y[o + k] = make_double2(a.x + b.x, a.y + b.y);
+    }
+}
+
 __global__ void iota_kernel(int* idx, int S) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < S; i += gridDim.x * blockDim.x) idx[i] = i;
 }
@@ -556,13 +566,18 @@ void product(const void* Z, int zdt, int n, const double2* X, double2* Y, const 
 }
 
 // The operator of a solve: Z, or P Z with a dense FP64 left factor P (the
-// Calderon product); tmp holds Z X for the rows in flight.
+// Calderon product), or P Z + Q M (the Calderon-stabilized CFIE, every factor
+// complex128); tmp holds Z X for the rows in flight, tmp2 and tmp3 M X and Q M X.
 struct Op {
     const void* Z;
     int zdt;
     const void* P;   // optional left factor (dtype pdt)
     double2* tmp;
     int pdt = EFIE_C128;
+    const void* M = nullptr;   // optional second term Q M (complex128)
+    const void* Q = nullptr;
+    double2* tmp2 = nullptr;
+    double2* tmp3 = nullptr;
 };
 
 void op_product(const Op& op, int n, const double2* X, double2* Y, const int* idx, int m, bool exact64, const Ws& w,
@@ -573,6 +588,12 @@ void op_product(const Op& op, int n, const double2* X, double2* Y, const int* id
     }
     product(op.Z, op.zdt, n, X, op.tmp, idx, m, exact64, w, st);
     product(op.P, op.pdt, n, op.tmp, Y, idx, m, exact64 || op.pdt == EFIE_C128, w, st);
+    if (op.M && m > 0) {
+        product(op.M, EFIE_C128, n, X, op.tmp2, idx, m, true, w, st);
+        product(op.Q, EFIE_C128, n, op.tmp2, op.tmp3, idx, m, true, w, st);
+        hipLaunchKernelGGL(add_rows_kernel, dim3(unsigned(std::min(64, (n + 255) / 256)), unsigned(m)), dim3(256), 0,
+                           st, Y, op.tmp3, idx, n);
+    }
 }
 
 int compact(const Ws& w, int S, int which, int* idx, hipStream_t st) {
@@ -882,4 +903,73 @@ extern "C" int efie_solve_precond(const void* Z, const void* P, int64_t n, const
                                   const efie_solve_opts* opts, efie_rhs_stats* stats, void* ws, size_t ws_bytes,
                                   hipStream_t stream) {
     return efie_solve_precond_ex(Z, EFIE_C128, P, EFIE_C128, n, V, J, nrhs, opts, stats, ws, ws_bytes, stream);
+}
+
+extern "C" int efie_solve_cfie_workspace_size(int64_t n, int64_t nrhs, size_t* bytes) {
+    return efie::guarded([&]() {
+        EFIE_REQUIRE(bytes && n >= 1 && nrhs >= 1, EFIE_ERR_ARG, "solve_cfie_workspace_size: bad argument");
+        const size_t vec = efie::align256(size_t(n) * size_t(nrhs) * 16);
+        *bytes = efie::layout(n, nrhs, EFIE_C128, nullptr, nullptr) + 5 * vec;
+        return int(EFIE_OK);
+    });
+}
+
+extern "C" int efie_solve_cfie(const void* Z, const void* P, const void* M, const void* Q, int64_t n, const void* V,
+                               const void* H, void* J, int64_t nrhs, const efie_solve_opts* opts,
+                               efie_rhs_stats* stats, void* ws, size_t ws_bytes, hipStream_t stream) {
+    using namespace efie;
+    return guarded([&]() {
+        EFIE_REQUIRE(Z && P && M && Q && V && H && J && opts && ws, EFIE_ERR_ARG, "solve_cfie: null argument");
+        EFIE_REQUIRE(n >= 1 && n < (int64_t(1) << 31) && nrhs >= 1 && nrhs <= 65535, EFIE_ERR_ARG,
+                     "solve_cfie: bad sizes");
+        EFIE_REQUIRE(opts->solver == EFIE_CGS, EFIE_ERR_ARG, "solve_cfie: the operator is not symmetric; use EFIE_CGS");
+        EFIE_REQUIRE(opts->maxit >= 1 && opts->tol > 0.0, EFIE_ERR_ARG, "solve_cfie: need maxit >= 1 and tol > 0");
+        const size_t base = layout(n, nrhs, EFIE_C128, nullptr, nullptr);
+        const size_t vec = align256(size_t(n) * size_t(nrhs) * 16);
+        EFIE_REQUIRE(ws_bytes >= base + 5 * vec, EFIE_ERR_ARG, "solve_cfie: workspace too small");
+        EFIE_REQUIRE((reinterpret_cast<uintptr_t>(ws) & 255) == 0, EFIE_ERR_ARG, "solve_cfie: ws not aligned");
+        Ws w;
+        layout(n, nrhs, EFIE_C128, &w, static_cast<char*>(ws));
+        w.acc64 = true;
+        char* b0 = static_cast<char*>(ws) + base;
+        Op op{Z, EFIE_C128, P, reinterpret_cast<double2*>(b0), EFIE_C128};
+        op.M = M;
+        op.Q = Q;
+        op.tmp2 = reinterpret_cast<double2*>(b0 + vec);
+        op.tmp3 = reinterpret_cast<double2*>(b0 + 2 * vec);
+        double2* pb = reinterpret_cast<double2*>(b0 + 3 * vec);   // b = P V + Q H
+        double2* y = reinterpret_cast<double2*>(b0 + 4 * vec);    // C x for the true residual
+        const int S = int(nrhs), nn = int(n);
+        hipLaunchKernelGGL(iota_kernel, dim3((S + 255) / 256), dim3(256), 0, stream, w.idx_all, S);
+        product(P, EFIE_C128, nn, static_cast<const double2*>(V), pb, w.idx_all, S, true, w, stream);
+        product(Q, EFIE_C128, nn, static_cast<const double2*>(H), op.tmp3, w.idx_all, S, true, w, stream);
+        hipLaunchKernelGGL(add_rows_kernel, dim3(unsigned(std::min(64, (nn + 255) / 256)), unsigned(S)), dim3(256), 0,
+                           stream, pb, op.tmp3, w.idx_all, nn);
+        double2* x = static_cast<double2*>(J);
+        std::vector<Col> cols;
+        krylov(op, nn, pb, x, S, EFIE_CGS, opts->tol, opts->maxit, false, w, cols, stream);
+        // FP64 true residual of the stabilized system
+        op_product(op, nn, x, y, w.idx_all, S, true, w, stream);
+        hipLaunchKernelGGL(residual_kernel, dim3(S), dim3(KB), 0, stream, pb, y, nullptr, w.nrm, w.bnrm, nn,
+                           w.idx_all);
+        std::vector<double> h_nrm(S), h_bn(S);
+        EFIE_HIP_CHECK(hipMemcpyAsync(h_nrm.data(), w.nrm, sizeof(double) * S, hipMemcpyDeviceToHost, stream));
+        EFIE_HIP_CHECK(hipMemcpyAsync(h_bn.data(), w.bnrm, sizeof(double) * S, hipMemcpyDeviceToHost, stream));
+        EFIE_HIP_CHECK(hipStreamSynchronize(stream));
+        int ret = EFIE_OK;
+        for (int s = 0; s < S; ++s) {
+            const double rel = h_bn[s] > 0 ? std::sqrt(h_nrm[s] / h_bn[s]) : 0.0;
+            int st = cols[s].status;
+            if (st >= 0) st = rel <= opts->tol ? EFIE_OK : EFIE_NOT_CONVERGED;
+            if (!(rel == rel)) st = EFIE_ERR_NAN;
+            if (stats) {
+                stats[s].iters = cols[s].iters;
+                stats[s].status = st;
+                stats[s].relres_recur = cols[s].bn2 > 0 ? std::sqrt(cols[s].rn2 / cols[s].bn2) : 0.0;
+                stats[s].relres_true = rel;
+            }
+            if (st != EFIE_OK) ret = EFIE_NOT_CONVERGED;
+        }
+        return ret;
+    });
 }
