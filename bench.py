@@ -305,6 +305,60 @@ def bench_calderon(args, P, synth, torch, np, dev):
     print(json.dumps(out), flush=True)
 
 
+def bench_cfie(args, P, synth, torch, np, dev):
+    """The 3-D Calderon-stabilized CFIE against the Calderon-EFIE on the sphere of
+    --cfie-level (default 4, N = 7680) at wavenumbers --cfie-ks (default: 4.9734
+    and 9.9675, zeros of (x j_3(x))' and of (x j_7(x))' where the EFIE has interior
+    resonances, and 5 and 10 beside them), --cfie-nrhs plane waves along the
+    monostatic grid: build times (Z, P, M and Q), CGS iterations and time to 1e-6,
+    and the RCS difference between the two solutions.  Everything FP64."""
+    v, f = synth.icosphere(args.cfie_level)
+    m = P.Mesh(v, f).upload(dev)
+    cal = P.Calderon(m).upload(dev)
+    rhat, khat, pol, _, _ = synth.monostatic_grid(4, 8)
+    S = min(args.cfie_nrhs, len(khat))
+    kh, po = khat[:S], pol[:S]
+    res = {}
+    for k in args.cfie_ks:
+        kt = P.ktilde(k)
+        Z, t_z = _timed(torch, lambda: P.assemble(m, k))
+        Pm, t_p = _timed(torch, lambda: cal.assemble(kt, tol=1e-10))
+        (M, Q), t_mq = _timed(torch, lambda: cal.cfie(k, kt, tol=1e-10))
+        V = P.excite_planewave(m, k, kh, po)
+        H = cal.mfie_rhs(k, kh, po)
+        (J, st), t_c = _timed(torch, lambda: P.solve_cfie(Z, Pm, M, Q, V, H, tol=1e-6, maxit=1000))
+        (Je, se), t_e = _timed(torch, lambda: P.solve_precond(Z, Pm, V, tol=1e-6, maxit=3000))
+        Fc = P.farfield(m, k, J, rhat[:S]).cpu().numpy()
+        Fe = P.farfield(m, k, Je, rhat[:S]).cpu().numpy()
+        sc = np.sum(np.abs(Fc) ** 2, axis=-1)          # (rhs, direction) bistatic
+        sv = np.sum(np.abs(Fe) ** 2, axis=-1)
+        db = np.abs(10 * np.log10(sc / sv))
+        db30 = db[sv >= 1e-3 * sv.max(axis=1, keepdims=True)]
+        row = {"ktilde": [kt.real, kt.imag], "Z_s": round(t_z, 3), "P_s": round(t_p, 3), "M_Q_s": round(t_mq, 3),
+               "cfie_iters_max": int(st.iters.max()), "cfie_iters_mean": round(float(st.iters.mean()), 1),
+               "cfie_solve_s": round(t_c, 3), "cfie_relres_true_max": float(st.relres_true.max()),
+               "efie_iters_max": int(se.iters.max()), "efie_iters_mean": round(float(se.iters.mean()), 1),
+               "efie_solve_s": round(t_e, 3), "efie_relres_true_max": float(se.relres_true.max()),
+               "bistatic_rcs_db_diff_max": float(db.max()), "bistatic_rcs_db_diff_max_within_30db": float(db30.max()),
+               "q_gram_relres": cal.cfie_gram_relres}
+        log(f"bench: cfie k={k} {row}")
+        res[str(k)] = row
+        del Z, Pm, M, Q
+        torch.cuda.empty_cache()
+    key = str(args.cfie_ks[0])
+    tot = res[key]["M_Q_s"] + res[key]["cfie_solve_s"]
+    out = {
+        "metric": "Calderon-stabilized CFIE vs Calderon-EFIE: CGS iterations and time-to-solve @ 1e-6",
+        "value": round(tot, 3), "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": round(1e3 * tot, 1),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "c128", "data": "synthetic",
+        "config": {"workload": f"PEC unit sphere icosphere level {args.cfie_level} (N={m.n} RWG), {S} plane waves, "
+                               f"k in {list(args.cfie_ks)}, FP64; value = M, Q build + CFIE solve at k={key}",
+                   "n_unknowns": m.n, "nrhs": S},
+        "results": res,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def bench_gradient(args, P, synth, torch, np, dev):
     """Adjoint vertex gradient of J = sum_d |F(rhat_d)|^2 (32 seeded directions) on the
     level-4 perturbed sphere (N = 7680), k = 3, x-polarised plane wave along -z:
@@ -642,7 +696,7 @@ def main():
                     help="calderon: CGS on P Z J = P V with P = T_BC(k~) G_mix^-1 built in the step (default); "
                          "cocg: unpreconditioned COCG")
     ap.add_argument("--workload", choices=["sphere", "ellipsoids", "calderon", "mixed-fp64", "gradient",
-                                           "far-rule", "bie2d", "bie2d-rank"],
+                                           "far-rule", "bie2d", "bie2d-rank", "cfie"],
                     default="sphere",
                     help="sphere: the 512-RHS level-5 sphere (default); ellipsoids: 64 uneven ellipsoids; "
                          "calderon: level-4 Calderon vs plain CGS; mixed-fp64: level-5 mixed vs FP64 path; "
@@ -671,6 +725,9 @@ def main():
     ap.add_argument("--bie2d-ppw", type=float, default=18.0, help="bie2d-rank: nodes per wavelength")
     ap.add_argument("--bie2d-pol", choices=["TM", "TE"], nargs="*",
                     help="2-D polarizations (default: TM for bie2d, TM and TE for bie2d-rank)")
+    ap.add_argument("--cfie-level", type=int, default=4)
+    ap.add_argument("--cfie-ks", type=float, nargs="*", default=[4.9734, 5.0, 9.9675, 10.0])
+    ap.add_argument("--cfie-nrhs", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -710,6 +767,9 @@ def main():
         return
     if args.workload == "bie2d-rank":
         bench_bie2d_rank(args, P, synth, torch, np, dev)
+        return
+    if args.workload == "cfie":
+        bench_cfie(args, P, synth, torch, np, dev)
         return
     v, f = synth.icosphere(args.level)
     m = P.Mesh(v, f).upload(dev)
