@@ -455,6 +455,7 @@ constexpr int K_PB = 4;   // barycentric test triangles per block of k_rows_kern
 // blocks of consecutive test triangles kept on one XCD (as in the far-row kernel);
 // every slot of a row is written: the three local edges of the source triangles
 // cover each (n, side) once
+template <bool CK>
 __global__ __launch_bounds__(256) void k_rows_kernel(DevMesh mb, DevMesh m, double kr, double ki,
                                                      double2* __restrict__ W, int c0, int np, int nqblk) {
     const int nblk = int(gridDim.x);
@@ -482,7 +483,7 @@ __global__ __launch_bounds__(256) void k_rows_kernel(DevMesh mb, DevMesh m, doub
                 for (int j = 0; j < 3; ++j) put(i, j, 0.0, 0.0);
             continue;
         }
-        mfie_pair(mb, m, p, q, kr, ki, is_near(m, t, q), put);
+        mfie_pair<CK>(mb, m, p, q, kr, ki, is_near(m, t, q), put);
     }
 }
 
@@ -1050,8 +1051,12 @@ int efie_calderon_cfie_assemble(efie_calderon c, double k, double kt_re, double 
                 const int c0 = ch * pl.chunk, c1 = std::min(Tb, c0 + pl.chunk), np = c1 - c0;
                 const size_t nblk = size_t((np + K_PB - 1) / K_PB) * size_t(nqblk);
                 EFIE_REQUIRE(nblk < (size_t(1) << 31), EFIE_ERR_ARG, "calderon_cfie_assemble: chunk too large");
-                hipLaunchKernelGGL(k_rows_kernel, dim3(unsigned(nblk)), dim3(256), 0, stream, mb, m, kr, ki,
-                                   static_cast<double2*>(w.W), c0, np, nqblk);
+                if (ki != 0.0)
+                    hipLaunchKernelGGL(k_rows_kernel<true>, dim3(unsigned(nblk)), dim3(256), 0, stream, mb, m, kr, ki,
+                                       static_cast<double2*>(w.W), c0, np, nqblk);
+                else
+                    hipLaunchKernelGGL(k_rows_kernel<false>, dim3(unsigned(nblk)), dim3(256), 0, stream, mb, m, kr,
+                                       ki, static_cast<double2*>(w.W), c0, np, nqblk);
                 if (L.nm[size_t(ch)] > 0)
                     hipLaunchKernelGGL(kbc_test_kernel, dim3(nx, unsigned(L.nm[size_t(ch)])), dim3(256), 0, stream,
                                        w.ml + L.m0[size_t(ch)], w.mptr + L.mp0[size_t(ch)], w.rows, w.coef,

@@ -41,32 +41,36 @@ struct Cx {
 };
 __device__ __forceinline__ Cx cxmul(Cx a, Cx b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
 
-// (1 + x) exp(-x) - 1 and, with full = true, (1 + x) exp(-x), for x = j k R,
-// k = kr + j ki
-__device__ inline Cx mfie_num(double kr, double ki, double R, bool full) {
+// (1 + x) exp(-x) for x = j k R, k = kr + j ki (CK: ki != 0)
+template <bool CK>
+__device__ __forceinline__ Cx mfie_full(double kr, double ki, double R) {
+    double s, c;
+    sincos(kr * R, &s, &c);
+    const double e = CK ? exp(ki * R) : 1.0;
+    // (1 - ki R + j kr R) e^{ki R} (cos(kr R) - j sin(kr R))
+    const double ar = 1.0 - ki * R, ai = kr * R;
+    return {e * (ar * c + ai * s), e * (ai * c - ar * s)};
+}
+
+// (1 + x) exp(-x) - 1, x = j k R: the Taylor series for |x| < 1/2
+__device__ inline Cx mfie_num(double kr, double ki, double R) {
     const Cx x = {-ki * R, kr * R};
-    const double ax2 = x.r * x.r + x.i * x.i;
-    if (!full && ax2 < 0.25) {
-        // Taylor series: term_m = x^m / m!, sum (-1)^(m+1) (m - 1) term_m
+    if (x.r * x.r + x.i * x.i < 0.25) {
+        // term_m = x^m / m!, sum (-1)^(m+1) (m - 1) term_m
         Cx term = x, acc = {0.0, 0.0};
-#pragma unroll 1
+#pragma unroll
         for (int m = 2; m < 24; ++m) {
             term = cxmul(term, x);
-            term.r /= double(m);
-            term.i /= double(m);
+            term.r *= 1.0 / double(m);
+            term.i *= 1.0 / double(m);
             const double c = (m & 1) ? double(m - 1) : -double(m - 1);
             acc.r += c * term.r;
             acc.i += c * term.i;
         }
         return acc;
     }
-    double s, c;
-    sincos(kr * R, &s, &c);
-    const double e = exp(ki * R);
-    // (1 - ki R + j kr R) e^{ki R} (cos(kr R) - j sin(kr R))
-    const double ar = 1.0 - ki * R, ai = kr * R;
-    Cx v = {e * (ar * c + ai * s), e * (ai * c - ar * s)};
-    if (!full) v.r -= 1.0;
+    Cx v = mfie_full<true>(kr, ki, R);
+    v.r -= 1.0;
     return v;
 }
 
@@ -112,7 +116,7 @@ __device__ inline void grad_potential(double px, double py, double pz, const dou
 
 // The nine K_mix values of test triangle p of the refinement mb against source
 // triangle q of the primal mesh m: emit(i, j, re, im)
-template <typename Emit>
+template <bool CK, typename Emit>
 __device__ inline void mfie_pair(const DevMesh& mb, const DevMesh& m, int p, int q, double kr, double ki, bool near,
                                  Emit emit) {
     const int Tb = mb.T, T = m.T;
@@ -140,18 +144,31 @@ __device__ inline void mfie_pair(const DevMesh& mb, const DevMesh& m, int p, int
         const double ax = mb.qx[a * Tb + p], ay = mb.qy[a * Tb + p], az = mb.qz[a * Tb + p], wa = mb.qw[a * Tb + p];
         const double X[3] = {Dx + ax, Dy + ay, Dz + az};
         Cx A[3] = {};
+        if (!near) {
 #pragma unroll
-        for (int c = 0; c < NQ; ++c) {
-            const double dx = X[0] - sx[c], dy = X[1] - sy[c], dz = X[2] - sz[c];
-            const double R = sqrt(dx * dx + dy * dy + dz * dz);
-            const Cx num = mfie_num(kr, ki, R, !near);
-            const double s = -sw[c] * F / (R * R * R);
-            const double gr = s * num.r, gi = s * num.i;
-            A[0].r += gr * dx; A[0].i += gi * dx;
-            A[1].r += gr * dy; A[1].i += gi * dy;
-            A[2].r += gr * dz; A[2].i += gi * dz;
-        }
-        if (near) {
+            for (int c = 0; c < NQ; ++c) {
+                const double dx = X[0] - sx[c], dy = X[1] - sy[c], dz = X[2] - sz[c];
+                const double R2 = dx * dx + dy * dy + dz * dz;
+                const double rinv = rsqrt(R2);
+                const Cx num = mfie_full<CK>(kr, ki, R2 * rinv);
+                const double s = -sw[c] * F * (rinv * rinv * rinv);
+                const double gr = s * num.r, gi = s * num.i;
+                A[0].r += gr * dx; A[0].i += gi * dx;
+                A[1].r += gr * dy; A[1].i += gi * dy;
+                A[2].r += gr * dz; A[2].i += gi * dz;
+            }
+        } else {
+#pragma unroll 1
+            for (int c = 0; c < NQ; ++c) {
+                const double dx = X[0] - sx[c], dy = X[1] - sy[c], dz = X[2] - sz[c];
+                const double R = sqrt(dx * dx + dy * dy + dz * dz);
+                const Cx num = mfie_num(kr, ki, R);
+                const double s = -sw[c] * F / (R * R * R);
+                const double gr = s * num.r, gi = s * num.i;
+                A[0].r += gr * dx; A[0].i += gi * dx;
+                A[1].r += gr * dy; A[1].i += gi * dy;
+                A[2].r += gr * dz; A[2].i += gi * dz;
+            }
             double J[3];
             grad_potential(X[0], X[1], X[2], vq, nq, hq, J);
             A[0].r -= F * J[0];
