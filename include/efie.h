@@ -503,20 +503,26 @@ int efie_solve_cfie(const void* Z, const void* P, const void* M, const void* Q, 
 /* ---------------------------------------------------------- many meshes */
 
 /*
- * A batch of uploaded meshes (uneven sizes) assembled in ONE persistent launch
- * and solved together (one right-hand side per mesh).
+ * A batch of uploaded meshes (uneven sizes) assembled by persistent work-queue
+ * launches and solved together (one right-hand side per mesh).
  * Layout: the Z of mesh i (caller order) occupies N_i^2 consecutive complex
  * elements of Zcat starting at sum_{j<i} N_j^2 (row-major, as efie_assemble);
  * vectors occupy N_i consecutive complex128 elements of Vcat / Jcat starting at
  * sum_{j<i} N_j.
- * efie_batch_create: meshes must stay alive and uploaded.  efie_batch_sizes:
- *   table_bytes for efie_batch_upload, ws_bytes for assemble/solve, total Z and
- *   vector elements, and the number of work items of the persistent launch.
- * efie_batch_assemble: k host array (nmesh, real, > 0); far pairs in FP32
- *   (EFIE_C64) or FP64 (EFIE_C128), near pairs in FP64, same formulas as
- *   efie_assemble; work items (one test triangle x 256 source triangles, or 256
- *   near pairs) are taken from one atomic queue, largest meshes first.
- *   Synchronises.
+ * efie_batch_create: meshes must stay alive and uploaded (and not be uploaded
+ *   again after efie_batch_upload: efie_batch_assemble then fails with
+ *   EFIE_ERR_STATE; upload the batch again).  efie_batch_sizes: table_bytes for
+ *   efie_batch_upload, ws_bytes for assemble/solve (with the row workspace of the
+ *   assembly, at most 2 GiB), total Z and vector elements, and the number of
+ *   pass-1 work items (complex64).
+ * efie_batch_assemble: k host array (nmesh, real, > 0); the atomic-free two-pass
+ *   assembly of efie_assemble_ws (far pairs in FP32 for EFIE_C64 or FP64 for
+ *   EFIE_C128, near pairs in FP64) run as work items of persistent launches, largest
+ *   meshes first: per group of meshes (or chunks of test triangles) whose rows fit
+ *   the row workspace, a rows launch (pass-1 blocks and near pairs), a gather
+ *   launch and a mirror launch, each taking items from its own atomic counter.
+ *   Every Z is bit-identical to efie_assemble_ws of its mesh (any workspace); no
+ *   atomics touch Z.  Meshes with the far rule on are rejected.  Synchronises.
  * efie_batch_solve: COCG per mesh (FP64 vectors), one grouped GEMV launch (FP64
  *   accumulation) and one grouped update launch per iteration; stats host nmesh.
  *   Per-mesh failures give EFIE_NOT_CONVERGED with the status in stats.

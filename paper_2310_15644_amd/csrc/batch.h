@@ -15,12 +15,12 @@ struct BatchCol {           // COCG state of one mesh (one right-hand side)
 
 struct efie_batch_s {
     std::vector<efie_mesh_s*> meshes;   // caller order
-    std::vector<int> order;             // processing order (decreasing item count)
+    std::vector<int> order;             // processing order (decreasing cost)
     std::vector<int64_t> zoff, voff;    // caller order: Z element offsets; vector offsets (n + 1)
-    std::vector<int64_t> prefix;        // processing order: first item of each mesh (n + 1)
-    int64_t z_total = 0, v_total = 0, total_items = 0;
+    int64_t z_total = 0, v_total = 0;
     void* dev = nullptr;                // caller-owned device blob
-    size_t off_prefix = 0, off_zoff = 0, off_voff = 0;
+    std::vector<void*> mesh_dev;        // caller order: each mesh's tables when the batch was uploaded
+    size_t off_zoff = 0, off_voff = 0;
 };
 
 namespace efie {

@@ -1,13 +1,19 @@
-// Many uneven meshes at once: one persistent assembly launch and a grouped
+// Many uneven meshes at once: persistent work-queue assembly and a grouped
 // Krylov solve.
 //
-// Assembly.  The work of every mesh is cut into items: a far item is one test
-// triangle against 256 source triangles (256 triangle pairs), a near item is 256
-// ordered near pairs.  Meshes are ordered by decreasing item count (largest
-// first) and their items numbered consecutively; a persistent grid of blocks
-// takes items from one global atomic counter until all are done (every block
-// leaves when the counter passes the total).  Each item runs the same pair code
-// as the single-mesh kernels.
+// Assembly.  The atomic-free two-pass scheme of the single-mesh assembly
+// (assemble.hip), run as work items of persistent launches: the meshes, ordered
+// by decreasing cost, are cut into segments (chunks of test triangles) whose rows
+// W[p][i][n][side] fit one workspace; per group of segments three launches take
+// items from their own atomic counter until all are done (every block leaves when
+// the counter passes the total):
+//   A  rows: a far item is one block of the single-mesh pass-1 kernel (FAR_PB test
+//      triangles against 256 source triangles), a near item 256 ordered near pairs;
+//   B  gather: a block per (test triangle, local edge) row of a segment;
+//   C  mirror: the mirror tile pairs of every mesh whose last segment is in the group.
+// Each item runs the same device code as the single-mesh kernels (rows_kernels.h),
+// with the same scale factors, so every batched matrix is bit-identical to its
+// single-mesh assembly; no atomics touch Z.
 //
 // Solve.  One right-hand side per mesh; Z of the meshes concatenated
 // (Z_i at element offset sum_{j<i} N_j^2), vectors concatenated (offset
@@ -25,65 +31,110 @@
 
 #include "batch.h"
 #include "linalg.h"
+#include "rows_kernels.h"
 
 namespace efie {
 
 struct BatchMeshDev {
     DevMesh m;
     int64_t zoff;     // element offset of this mesh's Z
-    int64_t nfar;     // far items
-    int64_t nitems;   // far + near items
-    int nqblk;        // 256-wide source blocks per test triangle
-    int pad;
+    int64_t pad[2];
 };
 
 struct BatchParam {
-    Scale sc;
+    Scale sc;         // operator_scale(k, 0, eta), as the single-mesh assembly
     double kr;
-    float kphase32;
+    float kphase32;   // k / 2 pi in FP32 (the complex64 pass 1)
     float pad;
 };
 
-template <typename ZT>
-__global__ __launch_bounds__(256, 4) void batch_assemble_kernel(const BatchMeshDev* __restrict__ bm,
-                                                                const BatchParam* __restrict__ prm, int nmesh,
-                                                                const int64_t* __restrict__ prefix, int64_t total,
-                                                                unsigned long long* counter, void* Zcat) {
+// a chunk [c0, c0 + np) of the test triangles of mesh r (processing order)
+struct BatchSeg {
+    int r, c0, np, nqblk;
+    int e0, e1;       // its ordered near pairs
+    int64_t woff;     // element offset of its rows in the workspace
+    int64_t nfar;     // pass-1 far items: ceil(np / FAR_PB) nqblk
+};
+
+// the item of a block: one shared load, uniform over the block
+__device__ inline long long next_item(unsigned long long* counter) {
     __shared__ long long item_s;
+    if (threadIdx.x == 0) item_s = (long long)atomicAdd(counter, 1ull);
+    __syncthreads();
+    const long long item = item_s;
+    __syncthreads();
+    return item;
+}
+
+// pref[lo] <= item < pref[lo + 1]
+__device__ inline int find_seg(const int64_t* __restrict__ pref, int n, long long item) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pref[mid] <= item) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// phase A: pass-1 far blocks and near pairs of every segment of the group
+template <typename ZT>
+__global__ __launch_bounds__(256) void batch_rows_kernel(const BatchMeshDev* __restrict__ bm,
+                                                         const BatchParam* __restrict__ prm,
+                                                         const BatchSeg* __restrict__ seg,
+                                                         const int64_t* __restrict__ pref, int nseg, int64_t total,
+                                                         unsigned long long* counter, ZT* __restrict__ W) {
+    using R = typename std::conditional<sizeof(ZT) == 8, float, double>::type;
     for (;;) {
-        if (threadIdx.x == 0) item_s = (long long)atomicAdd(counter, 1ull);
-        __syncthreads();
-        const long long item = item_s;
-        __syncthreads();
+        const long long item = next_item(counter);
         if (item >= total) return;
-        int lo = 0, hi = nmesh;   // prefix[lo] <= item < prefix[lo + 1]
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (prefix[mid] <= item) lo = mid;
-            else hi = mid;
-        }
-        const BatchMeshDev& B = bm[lo];
-        const BatchParam& Pm = prm[lo];
-        const long long li = item - prefix[lo];
-        ZT* Z = static_cast<ZT*>(Zcat) + B.zoff;
-        if (li < B.nfar) {
-            const int p = int(li / B.nqblk);
-            const int q = int(li - (long long)p * B.nqblk) * 256 + threadIdx.x;
-            if (q < B.m.T) {
-                if (sizeof(ZT) == 8) {
-                    const Tables<float> tb{B.m.qx32, B.m.qy32, B.m.qz32, B.m.qw32, B.m.vx32, B.m.vy32, B.m.vz32,
-                                           B.m.cf32, B.m.dv32};
-                    far_pair<float, false, false>(B.m, tb, p, q, Pm.kphase32, 0.f, Pm.sc, Z, nullptr);
-                } else {
-                    const Tables<double> tb{B.m.qx, B.m.qy, B.m.qz, B.m.qw, B.m.vx, B.m.vy, B.m.vz, B.m.cf, B.m.dv};
-                    far_pair<double, false, false>(B.m, tb, p, q, Pm.kr, 0.0, Pm.sc, Z, nullptr);
-                }
-            }
+        const int s = find_seg(pref, nseg, item);
+        const BatchSeg& g = seg[s];
+        const DevMesh& m = bm[g.r].m;
+        const BatchParam& pm = prm[g.r];
+        const long long li = item - pref[s];
+        ZT* w = W + g.woff;
+        if (li < g.nfar) {
+            const R kphase = sizeof(ZT) == 8 ? R(pm.kphase32) : R(pm.kr);
+            far_rows_block<R, false, true>(m, tables_of<R>(m), kphase, R(0), pm.sc, w, g.c0, g.np, g.nqblk, int(li));
         } else {
-            const long long e = (li - B.nfar) * 256 + threadIdx.x;
-            if (e < B.m.n_near) near_pair<typename std::conditional<sizeof(ZT) == 8, float, double>::type, false>(
-                B.m, int(e), Pm.kr, 0.0, Pm.sc, Z, nullptr);
+            const long long e = g.e0 + (li - g.nfar) * 256 + threadIdx.x;
+            if (e < g.e1) near_rows_one<R>(m, pm.kr, 0.0, pm.sc, w, g.c0, g.c0 + g.np, int(e), 1);
         }
+    }
+}
+
+// phase B: the gather blocks of every segment (3 np per segment)
+template <typename ZT>
+__global__ __launch_bounds__(256) void batch_gather_kernel(const BatchMeshDev* __restrict__ bm,
+                                                           const BatchSeg* __restrict__ seg,
+                                                           const int64_t* __restrict__ pref, int nseg, int64_t total,
+                                                           unsigned long long* counter, const ZT* __restrict__ W,
+                                                           ZT* __restrict__ Zcat) {
+    using R = typename std::conditional<sizeof(ZT) == 8, float, double>::type;
+    for (;;) {
+        const long long item = next_item(counter);
+        if (item >= total) return;
+        const int s = find_seg(pref, nseg, item);
+        const BatchSeg& g = seg[s];
+        const BatchMeshDev& b = bm[g.r];
+        gather_rows_block<R, true>(b.m, W + g.woff, g.c0, g.c0 + g.np, Zcat + b.zoff, int(item - pref[s]));
+    }
+}
+
+// phase C: the mirror tile pairs of the meshes completed by the group (mesh ranks mr[])
+template <typename ZT>
+__global__ __launch_bounds__(256) void batch_mirror_kernel(const BatchMeshDev* __restrict__ bm,
+                                                           const int* __restrict__ mr,
+                                                           const int64_t* __restrict__ pref, int nmr, int64_t total,
+                                                           unsigned long long* counter, ZT* __restrict__ Zcat) {
+    for (;;) {
+        const long long item = next_item(counter);
+        if (item >= total) return;
+        const int s = find_seg(pref, nmr, item);
+        const BatchMeshDev& b = bm[mr[s]];
+        const int N = b.m.N;
+        mirror_add_block<ZT>(Zcat + b.zoff, N, (N + 31) / 32, item - pref[s]);
     }
 }
 
@@ -278,14 +329,127 @@ void batch_residual_norms(const double2* b, const double2* y, const int64_t* vof
 namespace {
 size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
 
+// rows of one group of segments: at most this many bytes (a chunk of one test
+// triangle is the minimum)
+constexpr size_t BATCH_W_BUDGET = size_t(2) << 30;
+
+// The assembly plan for one storage type: segments in processing order, cut into
+// groups whose rows fit BATCH_W_BUDGET; per group the item prefixes of the three
+// phases (concatenated, nseg + 1 / nmr + 1 entries per group).
+struct BatchPlan {
+    struct Group {
+        int s0, ns, m0, nmr;         // its segments and mirror meshes
+        size_t a0, c0;               // first entry of its prefixes in apref / bpref, cpref
+        int64_t atot, btot, ctot;    // item totals of the three phases
+    };
+    std::vector<BatchSeg> segs;
+    std::vector<int64_t> apref, bpref, cpref;
+    std::vector<int> mr;
+    std::vector<Group> groups;
+    size_t w_bytes = 0;
+    int64_t pass1_items = 0;
+};
+
+BatchPlan batch_plan(const efie_batch_s& B, size_t esz) {
+    BatchPlan P;
+    const int nm = int(B.meshes.size());
+    std::vector<BatchSeg> cur;
+    std::vector<int> cur_mr;
+    size_t gbytes = 0;
+    auto close = [&]() {
+        if (cur.empty() && cur_mr.empty()) return;
+        BatchPlan::Group g{};
+        g.s0 = int(P.segs.size());
+        g.ns = int(cur.size());
+        g.m0 = int(P.mr.size());
+        g.nmr = int(cur_mr.size());
+        g.a0 = P.apref.size();
+        g.c0 = P.cpref.size();
+        int64_t a = 0, b = 0, c = 0;
+        for (const BatchSeg& x : cur) {
+            P.apref.push_back(a);
+            P.bpref.push_back(b);
+            a += x.nfar + (x.e1 - x.e0 + 255) / 256;
+            b += 3 * int64_t(x.np);
+            P.segs.push_back(x);
+        }
+        P.apref.push_back(a);
+        P.bpref.push_back(b);
+        for (int r : cur_mr) {
+            P.cpref.push_back(c);
+            const int64_t nt = (B.meshes[size_t(B.order[size_t(r)])]->N + 31) / 32;
+            c += nt * (nt + 1) / 2;
+            P.mr.push_back(r);
+        }
+        P.cpref.push_back(c);
+        g.atot = a;
+        g.btot = b;
+        g.ctot = c;
+        P.pass1_items += a;
+        P.groups.push_back(g);
+        P.w_bytes = std::max(P.w_bytes, gbytes);
+        cur.clear();
+        cur_mr.clear();
+        gbytes = 0;
+    };
+    for (int r = 0; r < nm; ++r) {
+        const efie_mesh_s& m = *B.meshes[size_t(B.order[size_t(r)])];
+        const size_t per_tri = size_t(6) * size_t(m.N) * esz;
+        EFIE_REQUIRE(per_tri <= BATCH_W_BUDGET, EFIE_ERR_ARG, "batch: a mesh too large for the row workspace");
+        const int T = int(m.T);
+        const int chunk = int(std::max<size_t>(1, std::min<size_t>(size_t(T), BATCH_W_BUDGET / per_tri)));
+        const int nqblk = (T + FAR_BLOCK - 1) / FAR_BLOCK;
+        for (int c0 = 0; c0 < T; c0 += chunk) {
+            const int np = std::min(chunk, T - c0);
+            const size_t bytes = a256(size_t(np) * per_tri);
+            if (!cur.empty() && gbytes + bytes > BATCH_W_BUDGET) close();
+            BatchSeg x{};
+            x.r = r;
+            x.c0 = c0;
+            x.np = np;
+            x.nqblk = nqblk;
+            x.e0 = int(std::lower_bound(m.near_p.begin(), m.near_p.end(), c0) - m.near_p.begin());
+            x.e1 = int(std::lower_bound(m.near_p.begin(), m.near_p.end(), c0 + np) - m.near_p.begin());
+            x.woff = int64_t(gbytes / esz);
+            x.nfar = int64_t((np + FAR_PB - 1) / FAR_PB) * nqblk;
+            cur.push_back(x);
+            gbytes += bytes;
+        }
+        cur_mr.push_back(r);   // the mesh's last segment is in the current group
+    }
+    close();
+    return P;
+}
+
 struct BatchWs {
     BatchParam* prm;
-    unsigned long long* counter;
+    unsigned long long* counter;   // [0] rows, [1] gather, [2] mirror
+    BatchSeg* segs;
+    int64_t *apref, *bpref, *cpref;
+    int* mr;
+    void* W;
     double2 *r, *p, *q, *y;
     BatchCol* cols;
     int* active;
     int* nact;
 };
+
+// sizes of the plan arrays and rows: the larger of the two storage types
+struct BatchPlanMax {
+    size_t nseg = 0, npref = 0, ncpref = 0, nmr = 0, w_bytes = 0;
+};
+BatchPlanMax batch_plan_max(const efie_batch_s& B) {
+    BatchPlanMax x;
+    for (size_t esz : {size_t(8), size_t(16)}) {
+        const BatchPlan P = batch_plan(B, esz);
+        x.nseg = std::max(x.nseg, P.segs.size());
+        x.npref = std::max(x.npref, P.apref.size());
+        x.ncpref = std::max(x.ncpref, P.cpref.size());
+        x.nmr = std::max(x.nmr, P.mr.size());
+        x.w_bytes = std::max(x.w_bytes, P.w_bytes);
+    }
+    return x;
+}
 
 size_t batch_ws_layout(const efie_batch_s& B, BatchWs* w, char* base) {
     size_t off = 0;
@@ -294,11 +458,18 @@ size_t batch_ws_layout(const efie_batch_s& B, BatchWs* w, char* base) {
         off += a256(bytes);
         return p;
     };
+    const BatchPlanMax pm = batch_plan_max(B);
     BatchWs x{};
     const size_t nm = B.meshes.size();
     const size_t vec = size_t(B.v_total) * 16;
     x.prm = (BatchParam*)take(sizeof(BatchParam) * nm);
     x.counter = (unsigned long long*)take(64);
+    x.segs = (BatchSeg*)take(sizeof(BatchSeg) * pm.nseg);
+    x.apref = (int64_t*)take(8 * pm.npref);
+    x.bpref = (int64_t*)take(8 * pm.npref);
+    x.cpref = (int64_t*)take(8 * pm.ncpref);
+    x.mr = (int*)take(4 * pm.nmr);
+    x.W = take(pm.w_bytes);
     x.r = (double2*)take(vec);
     x.p = (double2*)take(vec);
     x.q = (double2*)take(vec);
@@ -323,7 +494,7 @@ void batch_prepare(efie_batch_s& B) {
     }
     B.z_total = z;
     B.v_total = B.voff[size_t(nm)];
-    // processing order: decreasing number of items
+    // processing order: decreasing cost (pass-1 blocks and near pairs)
     std::vector<int64_t> items(static_cast<size_t>(nm));
     for (int i = 0; i < nm; ++i) {
         const efie_mesh_s& m = *B.meshes[size_t(i)];
@@ -333,9 +504,6 @@ void batch_prepare(efie_batch_s& B) {
     B.order.resize(size_t(nm));
     std::iota(B.order.begin(), B.order.end(), 0);
     std::stable_sort(B.order.begin(), B.order.end(), [&](int a, int b) { return items[size_t(a)] > items[size_t(b)]; });
-    B.prefix.assign(size_t(nm) + 1, 0);
-    for (int r = 0; r < nm; ++r) B.prefix[size_t(r) + 1] = B.prefix[size_t(r)] + items[size_t(B.order[size_t(r)])];
-    B.total_items = B.prefix[size_t(nm)];
 }
 
 }  // namespace efie
@@ -370,12 +538,11 @@ extern "C" int efie_batch_sizes(efie_batch b, size_t* table_bytes, size_t* ws_by
     return guarded([&]() {
         EFIE_REQUIRE(b != nullptr, EFIE_ERR_ARG, "batch_sizes: null");
         const size_t nm = b->meshes.size();
-        if (table_bytes)
-            *table_bytes = a256(sizeof(BatchMeshDev) * nm) + a256(8 * (nm + 1)) + a256(8 * nm) + a256(8 * (nm + 1));
+        if (table_bytes) *table_bytes = a256(sizeof(BatchMeshDev) * nm) + a256(8 * nm) + a256(8 * (nm + 1));
         if (ws_bytes) *ws_bytes = batch_ws_layout(*b, nullptr, nullptr);
         if (z_elems) *z_elems = b->z_total;
         if (v_elems) *v_elems = b->v_total;
-        if (items) *items = b->total_items;
+        if (items) *items = batch_plan(*b, 8).pass1_items;
         return int(EFIE_OK);
     });
 }
@@ -384,26 +551,25 @@ extern "C" int efie_batch_upload(efie_batch b, void* dev, size_t bytes, hipStrea
     return guarded([&]() {
         EFIE_REQUIRE(b && dev, EFIE_ERR_ARG, "batch_upload: null argument");
         const size_t nm = b->meshes.size();
-        const size_t need = a256(sizeof(BatchMeshDev) * nm) + a256(8 * (nm + 1)) + a256(8 * nm) + a256(8 * (nm + 1));
+        const size_t need = a256(sizeof(BatchMeshDev) * nm) + a256(8 * nm) + a256(8 * (nm + 1));
         EFIE_REQUIRE(bytes >= need, EFIE_ERR_ARG, "batch_upload: buffer too small");
         EFIE_REQUIRE((reinterpret_cast<uintptr_t>(dev) & 255) == 0, EFIE_ERR_ARG, "batch_upload: not 256-aligned");
         std::vector<char> blob(need, 0);
         auto* bmd = reinterpret_cast<BatchMeshDev*>(blob.data());
+        b->mesh_dev.assign(nm, nullptr);
         for (size_t r = 0; r < nm; ++r) {
             const int i = b->order[r];
             const efie_mesh_s& m = *b->meshes[size_t(i)];
+            EFIE_REQUIRE(m.dev != nullptr, EFIE_ERR_STATE, "batch_upload: a mesh is not uploaded");
+            EFIE_REQUIRE(m.far3 == 0.0, EFIE_ERR_ARG, "batch_upload: the batch takes the 7x7 rule only (a mesh has "
+                                                      "the far rule on)");
             BatchMeshDev d{};
             d.m = m.dm;
             d.zoff = b->zoff[size_t(i)];
-            d.nqblk = int((m.T + 255) / 256);
-            d.nfar = m.T * int64_t(d.nqblk);
-            d.nitems = b->prefix[r + 1] - b->prefix[r];
             bmd[r] = d;
+            b->mesh_dev[size_t(i)] = m.dev;
         }
         size_t off = a256(sizeof(BatchMeshDev) * nm);
-        std::memcpy(blob.data() + off, b->prefix.data(), 8 * (nm + 1));
-        b->off_prefix = off;
-        off += a256(8 * (nm + 1));
         std::memcpy(blob.data() + off, b->zoff.data(), 8 * nm);
         b->off_zoff = off;
         off += a256(8 * nm);
@@ -426,45 +592,69 @@ extern "C" int efie_batch_assemble(efie_batch b, const double* k, double eta, in
         BatchWs w;
         batch_ws_layout(*b, &w, static_cast<char*>(ws));
         const size_t nm = b->meshes.size();
+        for (size_t i = 0; i < nm; ++i) {
+            const efie_mesh_s& m = *b->meshes[i];
+            EFIE_REQUIRE(m.far3 == 0.0, EFIE_ERR_ARG, "batch_assemble: the batch takes the 7x7 rule only (a mesh "
+                                                      "has the far rule on)");
+            EFIE_REQUIRE(m.dev != nullptr && m.dev == b->mesh_dev[i], EFIE_ERR_STATE,
+                         "batch_assemble: a mesh was uploaded again after the batch; upload the batch again");
+        }
         std::vector<BatchParam> prm(nm);
         for (size_t r = 0; r < nm; ++r) {
             const double kr = k[b->order[r]];
             EFIE_REQUIRE(std::isfinite(kr) && kr > 0.0, EFIE_ERR_ARG, "batch_assemble: k must be real and > 0");
             if (dtype == EFIE_C64) require_fp32_phase(b->meshes[size_t(b->order[r])]->diam, kr, "batch_assemble");
-            const double f = eta / (4.0 * 3.14159265358979323846);
             BatchParam p{};
-            p.sc.ar = 0.0;
-            p.sc.ai = f * kr;
-            p.sc.pr = 0.0;
-            p.sc.pi = -f / kr;
+            p.sc = operator_scale(kr, 0.0, eta);   // the single-mesh assembly's factors, bit for bit
             p.kr = kr;
-            p.kphase32 = float(kr / (2.0 * 3.14159265358979323846));
+            p.kphase32 = float(kr / (2.0 * PI));
             prm[r] = p;
         }
+        const size_t esz = dtype == EFIE_C128 ? 16 : 8;
+        const BatchPlan plan = batch_plan(*b, esz);
         EFIE_HIP_CHECK(hipMemcpyAsync(w.prm, prm.data(), sizeof(BatchParam) * nm, hipMemcpyHostToDevice, stream));
-        fill_zero_bytes(w.counter, 64, stream);
-        fill_zero_bytes(Zcat, size_t(b->z_total) * (dtype == EFIE_C128 ? 16 : 8), stream);
-        int dev_id = 0, ncu = 0, per_cu = 0;
+        EFIE_HIP_CHECK(hipMemcpyAsync(w.segs, plan.segs.data(), sizeof(BatchSeg) * plan.segs.size(),
+                                      hipMemcpyHostToDevice, stream));
+        EFIE_HIP_CHECK(hipMemcpyAsync(w.apref, plan.apref.data(), 8 * plan.apref.size(), hipMemcpyHostToDevice, stream));
+        EFIE_HIP_CHECK(hipMemcpyAsync(w.bpref, plan.bpref.data(), 8 * plan.bpref.size(), hipMemcpyHostToDevice, stream));
+        EFIE_HIP_CHECK(hipMemcpyAsync(w.cpref, plan.cpref.data(), 8 * plan.cpref.size(), hipMemcpyHostToDevice, stream));
+        if (!plan.mr.empty())
+            EFIE_HIP_CHECK(hipMemcpyAsync(w.mr, plan.mr.data(), 4 * plan.mr.size(), hipMemcpyHostToDevice, stream));
+        int dev_id = 0, ncu = 0;
         EFIE_HIP_CHECK(hipGetDevice(&dev_id));
         EFIE_HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev_id));
-        const char* base = static_cast<const char*>(b->dev);
-        const auto* bmd = reinterpret_cast<const BatchMeshDev*>(base);
-        const auto* prefix = reinterpret_cast<const int64_t*>(base + b->off_prefix);
+        const auto* bmd = static_cast<const BatchMeshDev*>(b->dev);
+        auto grid_of = [&](const void* fn) {   // persistent grid: every CU full
+            int per_cu = 0;
+            EFIE_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0));
+            return dim3(unsigned(std::max(1, ncu * std::max(1, per_cu))));
+        };
+        auto run = [&](auto tag) {
+            using ZT = decltype(tag);
+            ZT* W = static_cast<ZT*>(w.W);
+            ZT* Z = static_cast<ZT*>(Zcat);
+            const dim3 ga = grid_of(reinterpret_cast<const void*>(batch_rows_kernel<ZT>));
+            const dim3 gb = grid_of(reinterpret_cast<const void*>(batch_gather_kernel<ZT>));
+            const dim3 gc = grid_of(reinterpret_cast<const void*>(batch_mirror_kernel<ZT>));
+            for (const BatchPlan::Group& g : plan.groups) {
+                fill_zero_bytes(w.counter, 64, stream);
+                if (g.atot > 0)
+                    hipLaunchKernelGGL(batch_rows_kernel<ZT>, ga, dim3(256), 0, stream, bmd, w.prm, w.segs + g.s0,
+                                       w.apref + g.a0, g.ns, g.atot, w.counter, W);
+                if (g.btot > 0)
+                    hipLaunchKernelGGL(batch_gather_kernel<ZT>, gb, dim3(256), 0, stream, bmd, w.segs + g.s0,
+                                       w.bpref + g.a0, g.ns, g.btot, w.counter + 1, W, Z);
+                if (g.ctot > 0)
+                    hipLaunchKernelGGL(batch_mirror_kernel<ZT>, gc, dim3(256), 0, stream, bmd, w.mr + g.m0,
+                                       w.cpref + g.c0, g.nmr, g.ctot, w.counter + 2, Z);
+            }
+        };
         prof_begin(PROF_FAR, stream);
-        if (dtype == EFIE_C64) {
-            EFIE_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_assemble_kernel<float2>, 256, 0));
-            const int grid = std::max(1, ncu * std::max(1, per_cu));
-            hipLaunchKernelGGL(batch_assemble_kernel<float2>, dim3(grid), dim3(256), 0, stream, bmd, w.prm, int(nm),
-                               prefix, b->total_items, w.counter, Zcat);
-        } else {
-            EFIE_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_assemble_kernel<double2>, 256, 0));
-            const int grid = std::max(1, ncu * std::max(1, per_cu));
-            hipLaunchKernelGGL(batch_assemble_kernel<double2>, dim3(grid), dim3(256), 0, stream, bmd, w.prm, int(nm),
-                               prefix, b->total_items, w.counter, Zcat);
-        }
+        if (dtype == EFIE_C64) run(float2{});
+        else run(double2{});
         prof_end(PROF_FAR, stream);
         EFIE_HIP_CHECK(hipGetLastError());
-        EFIE_HIP_CHECK(hipStreamSynchronize(stream));   // prm staging lives on this stack frame
+        EFIE_HIP_CHECK(hipStreamSynchronize(stream));   // the host staging lives on this stack frame
         return int(EFIE_OK);
     });
 }
