@@ -240,7 +240,7 @@ def bench_ellipsoids(args, P, synth, torch, np, dev):
     asm_ms = prof["far"][1] / args.steps
     st = rec[-1]["st"]
     out = {
-        "metric": "assembly Mentries/s (one persistent launch, 64 uneven meshes); time-to-solve @ rel.res 1e-6",
+        "metric": "assembly Mentries/s (persistent work-queue launches, 64 uneven meshes); time-to-solve @ rel.res 1e-6",
         "value": round(float((ns ** 2).sum()) / (asm_ms * 1e-3) / 1e6, 1),
         "unit": "Mentries/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * wall / args.steps, 3),

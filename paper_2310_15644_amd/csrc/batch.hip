@@ -4,11 +4,13 @@
 // Assembly.  The atomic-free two-pass scheme of the single-mesh assembly
 // (assemble.hip), run as work items of persistent launches: the meshes, ordered
 // by decreasing cost, are cut into segments (chunks of test triangles) whose rows
-// W[p][i][n][side] fit one workspace; per group of segments three launches take
+// W[p][i][n][side] fit one workspace; per group of segments four launches take
 // items from their own atomic counter until all are done (every block leaves when
 // the counter passes the total):
 //   A  rows: a far item is one block of the single-mesh pass-1 kernel (FAR_PB test
-//      triangles against 256 source triangles), a near item 256 ordered near pairs;
+//      triangles against 256 source triangles); a near item 256 ordered near pairs
+//      (their own launch, whose FP64 code would otherwise take the far items'
+//      registers);
 //   B  gather: a block per (test triangle, local edge) row of a segment;
 //   C  mirror: the mirror tile pairs of every mesh whose last segment is in the group.
 // Each item runs the same device code as the single-mesh kernels (rows_kernels.h),
@@ -77,8 +79,10 @@ __device__ inline int find_seg(const int64_t* __restrict__ pref, int n, long lon
     return lo;
 }
 
-// phase A: pass-1 far blocks and near pairs of every segment of the group
-template <typename ZT>
+// phase A: pass-1 far blocks (NEAR false) or the near pairs, 256 per item (NEAR
+// true), of every segment of the group (two launches: the FP64 near-pair code
+// would take the far blocks' registers)
+template <typename ZT, bool NEAR>
 __global__ __launch_bounds__(256) void batch_rows_kernel(const BatchMeshDev* __restrict__ bm,
                                                          const BatchParam* __restrict__ prm,
                                                          const BatchSeg* __restrict__ seg,
@@ -94,11 +98,11 @@ __global__ __launch_bounds__(256) void batch_rows_kernel(const BatchMeshDev* __r
         const BatchParam& pm = prm[g.r];
         const long long li = item - pref[s];
         ZT* w = W + g.woff;
-        if (li < g.nfar) {
+        if (!NEAR) {
             const R kphase = sizeof(ZT) == 8 ? R(pm.kphase32) : R(pm.kr);
             far_rows_block<R, false, true>(m, tables_of<R>(m), kphase, R(0), pm.sc, w, g.c0, g.np, g.nqblk, int(li));
         } else {
-            const long long e = g.e0 + (li - g.nfar) * 256 + threadIdx.x;
+            const long long e = g.e0 + li * 256 + threadIdx.x;
             if (e < g.e1) near_rows_one<R>(m, pm.kr, 0.0, pm.sc, w, g.c0, g.c0 + g.np, int(e), 1);
         }
     }
@@ -340,10 +344,10 @@ struct BatchPlan {
     struct Group {
         int s0, ns, m0, nmr;         // its segments and mirror meshes
         size_t a0, c0;               // first entry of its prefixes in apref / bpref, cpref
-        int64_t atot, btot, ctot;    // item totals of the three phases
+        int64_t atot, ntot, btot, ctot;   // item totals: far rows, near rows, gather, mirror
     };
     std::vector<BatchSeg> segs;
-    std::vector<int64_t> apref, bpref, cpref;
+    std::vector<int64_t> apref, npref, bpref, cpref;
     std::vector<int> mr;
     std::vector<Group> groups;
     size_t w_bytes = 0;
@@ -365,15 +369,18 @@ BatchPlan batch_plan(const efie_batch_s& B, size_t esz) {
         g.nmr = int(cur_mr.size());
         g.a0 = P.apref.size();
         g.c0 = P.cpref.size();
-        int64_t a = 0, b = 0, c = 0;
+        int64_t a = 0, nn = 0, b = 0, c = 0;
         for (const BatchSeg& x : cur) {
             P.apref.push_back(a);
+            P.npref.push_back(nn);
             P.bpref.push_back(b);
-            a += x.nfar + (x.e1 - x.e0 + 255) / 256;
+            a += x.nfar;
+            nn += (x.e1 - x.e0 + 255) / 256;
             b += 3 * int64_t(x.np);
             P.segs.push_back(x);
         }
         P.apref.push_back(a);
+        P.npref.push_back(nn);
         P.bpref.push_back(b);
         for (int r : cur_mr) {
             P.cpref.push_back(c);
@@ -383,9 +390,10 @@ BatchPlan batch_plan(const efie_batch_s& B, size_t esz) {
         }
         P.cpref.push_back(c);
         g.atot = a;
+        g.ntot = nn;
         g.btot = b;
         g.ctot = c;
-        P.pass1_items += a;
+        P.pass1_items += a + nn;
         P.groups.push_back(g);
         P.w_bytes = std::max(P.w_bytes, gbytes);
         cur.clear();
@@ -423,9 +431,9 @@ BatchPlan batch_plan(const efie_batch_s& B, size_t esz) {
 
 struct BatchWs {
     BatchParam* prm;
-    unsigned long long* counter;   // [0] rows, [1] gather, [2] mirror
+    unsigned long long* counter;   // [0] far rows, [1] near rows, [2] gather, [3] mirror
     BatchSeg* segs;
-    int64_t *apref, *bpref, *cpref;
+    int64_t *apref, *npref, *bpref, *cpref;
     int* mr;
     void* W;
     double2 *r, *p, *q, *y;
@@ -466,6 +474,7 @@ size_t batch_ws_layout(const efie_batch_s& B, BatchWs* w, char* base) {
     x.counter = (unsigned long long*)take(64);
     x.segs = (BatchSeg*)take(sizeof(BatchSeg) * pm.nseg);
     x.apref = (int64_t*)take(8 * pm.npref);
+    x.npref = (int64_t*)take(8 * pm.npref);
     x.bpref = (int64_t*)take(8 * pm.npref);
     x.cpref = (int64_t*)take(8 * pm.ncpref);
     x.mr = (int*)take(4 * pm.nmr);
@@ -616,6 +625,7 @@ extern "C" int efie_batch_assemble(efie_batch b, const double* k, double eta, in
         EFIE_HIP_CHECK(hipMemcpyAsync(w.segs, plan.segs.data(), sizeof(BatchSeg) * plan.segs.size(),
                                       hipMemcpyHostToDevice, stream));
         EFIE_HIP_CHECK(hipMemcpyAsync(w.apref, plan.apref.data(), 8 * plan.apref.size(), hipMemcpyHostToDevice, stream));
+        EFIE_HIP_CHECK(hipMemcpyAsync(w.npref, plan.npref.data(), 8 * plan.npref.size(), hipMemcpyHostToDevice, stream));
         EFIE_HIP_CHECK(hipMemcpyAsync(w.bpref, plan.bpref.data(), 8 * plan.bpref.size(), hipMemcpyHostToDevice, stream));
         EFIE_HIP_CHECK(hipMemcpyAsync(w.cpref, plan.cpref.data(), 8 * plan.cpref.size(), hipMemcpyHostToDevice, stream));
         if (!plan.mr.empty())
@@ -633,20 +643,24 @@ extern "C" int efie_batch_assemble(efie_batch b, const double* k, double eta, in
             using ZT = decltype(tag);
             ZT* W = static_cast<ZT*>(w.W);
             ZT* Z = static_cast<ZT*>(Zcat);
-            const dim3 ga = grid_of(reinterpret_cast<const void*>(batch_rows_kernel<ZT>));
+            const dim3 ga = grid_of(reinterpret_cast<const void*>(batch_rows_kernel<ZT, false>));
+            const dim3 gn = grid_of(reinterpret_cast<const void*>(batch_rows_kernel<ZT, true>));
             const dim3 gb = grid_of(reinterpret_cast<const void*>(batch_gather_kernel<ZT>));
             const dim3 gc = grid_of(reinterpret_cast<const void*>(batch_mirror_kernel<ZT>));
             for (const BatchPlan::Group& g : plan.groups) {
                 fill_zero_bytes(w.counter, 64, stream);
                 if (g.atot > 0)
-                    hipLaunchKernelGGL(batch_rows_kernel<ZT>, ga, dim3(256), 0, stream, bmd, w.prm, w.segs + g.s0,
-                                       w.apref + g.a0, g.ns, g.atot, w.counter, W);
+                    hipLaunchKernelGGL((batch_rows_kernel<ZT, false>), ga, dim3(256), 0, stream, bmd, w.prm,
+                                       w.segs + g.s0, w.apref + g.a0, g.ns, g.atot, w.counter, W);
+                if (g.ntot > 0)
+                    hipLaunchKernelGGL((batch_rows_kernel<ZT, true>), gn, dim3(256), 0, stream, bmd, w.prm,
+                                       w.segs + g.s0, w.npref + g.a0, g.ns, g.ntot, w.counter + 1, W);
                 if (g.btot > 0)
                     hipLaunchKernelGGL(batch_gather_kernel<ZT>, gb, dim3(256), 0, stream, bmd, w.segs + g.s0,
-                                       w.bpref + g.a0, g.ns, g.btot, w.counter + 1, W, Z);
+                                       w.bpref + g.a0, g.ns, g.btot, w.counter + 2, W, Z);
                 if (g.ctot > 0)
                     hipLaunchKernelGGL(batch_mirror_kernel<ZT>, gc, dim3(256), 0, stream, bmd, w.mr + g.m0,
-                                       w.cpref + g.c0, g.nmr, g.ctot, w.counter + 2, Z);
+                                       w.cpref + g.c0, g.nmr, g.ctot, w.counter + 3, Z);
             }
         };
         prof_begin(PROF_FAR, stream);
