@@ -34,8 +34,9 @@
 // kernel, are gone (level 5, complex64: 160 ms -> 33 ms with every pair, 24 ms
 // with the pairs q >= p and the mirror).
 //
-// Near pairs (near mask bit set) are skipped by the far kernel and handled by
-// near_pairs_kernel in FP64: the smooth part (exp(-jkR)-1)/(4 pi R) with the same
+// Near pairs (a shared vertex, or centroids closer than the near factor times the
+// larger longest edge; decided on the device as on the host) are skipped by the
+// far kernels and handled by the near kernels in FP64: the smooth part (exp(-jkR)-1)/(4 pi R) with the same
 // 7 x 7 rule, and the 1/(4 pi R) part with closed-form inner integrals over the
 // source triangle (Wilton et al., IEEE TAP 32(3) 1984; Graglia, IEEE TAP 41(10)
 // 1993) and the 7-point rule over the test triangle, averaged with the
@@ -44,6 +45,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "efie_internal.h"
@@ -141,20 +143,24 @@ void launch_far(const DevMesh& m, double kr, double ki, const Scale& sc, void* Z
 // alone, so a chunk's near pairs (few, long-running threads) run beside its far
 // pairs on a second stream: forked from the caller's stream before the far kernel,
 // so that they follow whatever read the workspace before, and joined before
-// anything reads the chunk's rows.  One side stream and event pair per host thread
-// and device, created on first use and kept until the process ends.
+// anything reads the chunk's rows.  One side stream and event pair per device,
+// created on first use and kept until the process ends; host threads that
+// assemble at once take turns enqueueing (the pair of events is shared).
 struct SideStream {
     hipStream_t s = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
+    std::mutex mu;
 };
 
 static SideStream& side_stream() {
     constexpr int MAXDEV = 64;
-    thread_local SideStream ss[MAXDEV];
+    static SideStream ss[MAXDEV];
+    static std::mutex create_mu;
     int dev = 0;
     EFIE_HIP_CHECK(hipGetDevice(&dev));
     EFIE_REQUIRE(dev >= 0 && dev < MAXDEV, EFIE_ERR_STATE, "side stream: device index out of range");
     SideStream& x = ss[dev];
+    std::lock_guard<std::mutex> g(create_mu);
     if (!x.s) {
         EFIE_HIP_CHECK(hipStreamCreateWithFlags(&x.s, hipStreamNonBlocking));
         EFIE_HIP_CHECK(hipEventCreateWithFlags(&x.fork, hipEventDisableTiming));
@@ -164,13 +170,17 @@ static SideStream& side_stream() {
 }
 
 // launch near(stream) beside far(stream) as above; returns after both are enqueued,
-// with the caller's stream s waiting for the near pairs
+// with the caller's stream s waiting for the near pairs (timed as PROF_NEAR on the
+// side stream)
 template <typename NearF, typename FarF>
 static void near_beside_far(hipStream_t s, NearF near, FarF far) {
     SideStream& x = side_stream();
+    std::lock_guard<std::mutex> g(x.mu);
     EFIE_HIP_CHECK(hipEventRecord(x.fork, s));
     EFIE_HIP_CHECK(hipStreamWaitEvent(x.s, x.fork, 0));
+    prof_begin(PROF_NEAR, x.s);
     near(x.s);
+    prof_end(PROF_NEAR, x.s);
     EFIE_HIP_CHECK(hipEventRecord(x.join, x.s));
     far(s);
     EFIE_HIP_CHECK(hipStreamWaitEvent(s, x.join, 0));
