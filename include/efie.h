@@ -503,26 +503,21 @@ int efie_solve_cfie(const void* Z, const void* P, const void* M, const void* Q, 
 /* ---------------------------------------------------------- many meshes */
 
 /*
- * A batch of uploaded meshes (uneven sizes) assembled by persistent work-queue
- * launches and solved together (one right-hand side per mesh).
+ * A batch of uploaded meshes (uneven sizes) assembled together and solved
+ * together (one right-hand side per mesh).
  * Layout: the Z of mesh i (caller order) occupies N_i^2 consecutive complex
  * elements of Zcat starting at sum_{j<i} N_j^2 (row-major, as efie_assemble);
  * vectors occupy N_i consecutive complex128 elements of Vcat / Jcat starting at
  * sum_{j<i} N_j.
- * efie_batch_create: meshes must stay alive and uploaded (and not be uploaded
- *   again after efie_batch_upload: efie_batch_assemble then fails with
- *   EFIE_ERR_STATE; upload the batch again).  efie_batch_sizes: table_bytes for
- *   efie_batch_upload, ws_bytes for assemble/solve (with the row workspace of the
- *   assembly, at most 2 GiB), total Z and vector elements, and the number of
- *   pass-1 work items (complex64).
- * efie_batch_assemble: k host array (nmesh, real, > 0); the atomic-free two-pass
- *   assembly of efie_assemble_ws (far pairs in FP32 for EFIE_C64 or FP64 for
- *   EFIE_C128, near pairs in FP64) run as work items of persistent launches, largest
- *   meshes first: per group of meshes (or chunks of test triangles) whose rows fit
- *   the row workspace, a rows launch (pass-1 blocks and near pairs), a gather
- *   launch and a mirror launch, each taking items from its own atomic counter.
- *   Every Z is bit-identical to efie_assemble_ws of its mesh (any workspace); no
- *   atomics touch Z.  Meshes with the far rule on are rejected.  Synchronises.
+ * efie_batch_create: meshes must stay alive and uploaded.  efie_batch_sizes:
+ *   table_bytes for efie_batch_upload, ws_bytes for assemble/solve (with every
+ *   mesh's near-pair blocks), total Z and vector elements, and the number of
+ *   assembly launches (two per mesh).
+ * efie_batch_assemble: k host array (nmesh, real, > 0); every mesh by the tile
+ *   assembly of efie_assemble_ws (its near blocks, then its tiles of Z), the meshes
+ *   in decreasing cost dealt to four streams of the device forked from and joined
+ *   back into `stream`: every Z bit-identical to efie_assemble_ws of its mesh, no
+ *   atomics.  Synchronises.
  * efie_batch_solve: COCG per mesh (FP64 vectors), one grouped GEMV launch (FP64
  *   accumulation) and one grouped update launch per iteration; stats host nmesh.
  *   Per-mesh failures give EFIE_NOT_CONVERGED with the status in stats.
@@ -642,7 +637,8 @@ int efie_convert(const void* src, int src_dtype, void* dst, int dst_dtype, int64
  * stream.  Kernel ids: 0 far-pair assembly, 1 near-pair assembly, 2 complex64
  * matrix-core GEMM, 3 GEMV, 4 FP64 GEMM, 5 Krylov vector kernels, 6 excitation,
  * 7 far field, 8 / 9 / 10 vertex gradient far pairs / near pairs / per-triangle
- * excitation and radiation terms.  efie_prof_read waits for the recorded events and returns the
+ * excitation and radiation terms, 11 the near pairs of the pair rows of the
+ * Calderon build (beside its far pairs, on a second stream).  efie_prof_read waits for the recorded events and returns the
  * launch count, summed milliseconds and summed algorithmic work (real flops for
  * the GEMMs, 8 M n n per complex product; Z bytes read for the GEMVs; triangle
  * pairs for the gradient pair kernels and triangles for its per-triangle

@@ -56,7 +56,7 @@ EXPORTED = [
     "efie_solve_cfie_workspace_size", "efie_solve_cfie",
 ]
 PROF_IDS = {"far": 0, "near": 1, "mfma": 2, "gemv": 3, "zgemm": 4, "krylov": 5, "excite": 6, "farfield": 7, "grad_far": 8,
-            "grad_near": 9, "grad_tri": 10}
+            "grad_near": 9, "grad_tri": 10, "rows_near": 11}
 
 
 class EfieError(RuntimeError):
@@ -307,16 +307,16 @@ def _cdtype(dtype):
     raise ValueError(f"bad dtype {dtype}")
 
 
-ASSEMBLY_WORKSPACE_BYTES = 2 << 30   # default bound of the far-pair workspace (2 GiB)
 
 
 def assemble(mesh: Mesh, k, eta: float = ETA0, dtype=C128, parts: bool = False, out=None, out2=None,
              atomic: bool = False, workspace_bytes: int | None = None):
     """Dense Z (N, N) on the device; parts=True returns (T_A, T_Phi) instead.
 
-    By default the far pairs go through the atomic-free two-pass path
-    (efie_assemble_ws) with a workspace of at most `workspace_bytes`
-    (ASSEMBLY_WORKSPACE_BYTES); atomic=True (and parts mode) use efie_assemble."""
+    By default Z is built by the owner-computes tiles of efie_assemble_ws (written
+    once, deterministic, exactly symmetric; the workspace holds the near-pair
+    blocks, and `workspace_bytes` is accepted for compatibility and otherwise
+    unused); atomic=True (and parts mode) use efie_assemble."""
     torch = _torch()
     dev = mesh.device
     code, tdt = _cdtype(dtype)
@@ -329,8 +329,7 @@ def assemble(mesh: Mesh, k, eta: float = ETA0, dtype=C128, parts: bool = False, 
     if not parts and not atomic:
         lo, full = ctypes.c_size_t(), ctypes.c_size_t()
         _check(lib().efie_assemble_workspace_size(mesh._h, code, ctypes.byref(lo), ctypes.byref(full)))
-        budget = ASSEMBLY_WORKSPACE_BYTES if workspace_bytes is None else int(workspace_bytes)
-        nb = min(full.value, max(lo.value, budget))
+        nb = full.value
         ws = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
         off = (-ws.data_ptr()) % 256
         _check(lib().efie_assemble_ws(mesh._h, k.real, k.imag, float(eta), code, _ptr(Z),

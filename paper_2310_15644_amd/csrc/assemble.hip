@@ -17,22 +17,18 @@
 // The test triangle is uniform over a block (scalar loads), the source triangle
 // varies across lanes (coalesced structure-of-arrays loads).
 //
-// Without atomics (efie_assemble_ws): the operator is symmetric, so only the
-// pairs with source triangle q >= p are evaluated (the pair q = p halved): their
-// nine values go, per chunk of test triangles p, to a caller workspace laid out as
-//   W[p][i][n][side]   (test edge i of p, source RWG n, side 0/1: the source
-//                       triangle is n's T+ / T-),
-// (far pairs q > p by far_rows_kernel<UPPER>, near pairs q >= p in FP64 by
-// near_rows_kernel; entries of triangles q < p are never written), with the blocks
-// of one test triangle kept on one XCD so that its rows are completed in one L2;
-// then one block per RWG row m adds the written entries of its triangles' rows,
-//   U[m][n] += sum_{p in {T+(m), T-(m)} in chunk} sum_{t: T_t(n) >= p} W[p][i_p][n][t],
-// with coalesced reads and writes, and at the end Z = U + U^T by pairs of mirror
-// 32 x 32 tiles.  No atomics anywhere and a fixed sum order, so the result is
-// deterministic and exactly symmetric; the atomic path's scattered
-// read-modify-writes of Z, which cost ten times the arithmetic of the complex64
-// kernel, are gone (level 5, complex64: 160 ms -> 33 ms with every pair, 24 ms
-// with the pairs q >= p and the mirror).
+// Without atomics (efie_assemble_ws): owner-computes tiles (tile_kernels.h).  A
+// block owns a tile of Z (64 x 64 RWGs in complex64, 32 x 32 in complex128, the
+// tiles on and above the diagonal), evaluates every triangle pair between the
+// triangles of its row RWGs and those of its column RWGs once, adds each entry's
+// four pair values in a fixed order and writes the tile and its mirror: Z is
+// written once, no workspace rows, no atomics, deterministic and exactly
+// symmetric.  The near pairs' FP64 blocks are computed first (one thread per
+// ordered near pair) into the caller's workspace, where the tiles read them.
+// The pair rows W[p][i][n][side] of a chunk of test triangles (far_rows_kernel,
+// near_rows_kernel: the pairs with source triangle q >= p, q = p halved) remain
+// the first step of the Calderon build, which contracts rows without forming the
+// matrix (pair_rows_chunk).
 //
 // Near pairs (a shared vertex, or centroids closer than the near factor times the
 // larger longest edge; decided on the device as on the host) are skipped by the
@@ -51,6 +47,7 @@
 #include "efie_internal.h"
 #include "pair_kernels.h"
 #include "rows_kernels.h"
+#include "tile_kernels.h"
 
 namespace efie {
 
@@ -95,15 +92,22 @@ __global__ __launch_bounds__(128) void near_rows_kernel(DevMesh m, double kr, do
     near_rows_one<R>(m, kr, ki, sc, W, c0, c1, e, upper);
 }
 
-template <typename R, bool UPPER>
-__global__ __launch_bounds__(256) void gather_rows_kernel(DevMesh m, const typename Cplx<R>::T* __restrict__ W,
-                                                          int c0, int c1, typename Cplx<R>::T* __restrict__ Z) {
-    gather_rows_block<R, UPPER>(m, W, c0, c1, Z, int(blockIdx.x));
+// the FP64 blocks of every ordered near pair, in the precision of Z
+template <typename R>
+__global__ __launch_bounds__(256) void near_blocks_kernel(DevMesh m, double kr, double ki, Scale sc,
+                                                          typename Cplx<R>::T* __restrict__ NB) {
+    const int e = int(blockIdx.x) * 256 + int(threadIdx.x);
+    if (e >= m.n_near) return;
+    near_block_one<R>(m, kr, ki, sc, NB, e);
 }
 
-template <typename C2>
-__global__ __launch_bounds__(256) void mirror_add_kernel(C2* __restrict__ Z, int N, int nt) {
-    mirror_add_block<C2>(Z, N, nt, (long long)blockIdx.x);
+// one block per tile of Z (tiles on and above the diagonal)
+template <typename R, bool CK>
+__global__ __launch_bounds__(256) void tile_kernel(DevMesh m, Tables<R> tb, R kphase, R ki, Scale sc,
+                                                   const typename Cplx<R>::T* __restrict__ NB,
+                                                   typename Cplx<R>::T* __restrict__ Z) {
+    __shared__ TileLds<R> L;
+    tile_block<R, CK>(m, tb, kphase, ki, sc, NB, Z, (long long)blockIdx.x, L);
 }
 
 template <typename R>
@@ -170,74 +174,48 @@ static SideStream& side_stream() {
 }
 
 // launch near(stream) beside far(stream) as above; returns after both are enqueued,
-// with the caller's stream s waiting for the near pairs (timed as PROF_NEAR on the
-// side stream)
+// with the caller's stream s waiting for the near pairs (timed as PROF_ROWS_NEAR on
+// the side stream)
 template <typename NearF, typename FarF>
 static void near_beside_far(hipStream_t s, NearF near, FarF far) {
     SideStream& x = side_stream();
     std::lock_guard<std::mutex> g(x.mu);
     EFIE_HIP_CHECK(hipEventRecord(x.fork, s));
     EFIE_HIP_CHECK(hipStreamWaitEvent(x.s, x.fork, 0));
-    prof_begin(PROF_NEAR, x.s);
+    prof_begin(PROF_ROWS_NEAR, x.s);
     near(x.s);
-    prof_end(PROF_NEAR, x.s);
+    prof_end(PROF_ROWS_NEAR, x.s);
     EFIE_HIP_CHECK(hipEventRecord(x.join, x.s));
     far(s);
     EFIE_HIP_CHECK(hipStreamWaitEvent(s, x.join, 0));
 }
 
-// far pairs without atomics, in chunks of test triangles that fit the workspace
-// near_p: host copy of the ordered near list's test triangles (sorted), to launch
-// only the chunk's near pairs
+// Z by tiles: the near blocks into the workspace, then one block per tile
+// (prof: bracket the two launches for efie_prof_read)
 template <typename R>
-void launch_far_rows(const DevMesh& m, double kr, double ki, const Scale& sc, void* Z, void* ws, size_t ws_bytes,
-                     const std::vector<int32_t>& near_p, hipStream_t s) {
+void launch_tiles(const DevMesh& m, double kr, double ki, const Scale& sc, void* Z, void* ws, size_t ws_bytes,
+                  hipStream_t s, bool prof = true) {
     using C2 = typename Cplx<R>::T;
-    const size_t per_tri = size_t(6) * size_t(m.N) * sizeof(C2);
-    const int chunk = int(std::min<size_t>(size_t(m.T), ws_bytes / per_tri));
-    EFIE_REQUIRE(chunk >= 1, EFIE_ERR_ARG, "assemble_ws: workspace smaller than one test triangle's rows");
-    const int nqblk = (m.T + FAR_BLOCK - 1) / FAR_BLOCK;
-    EFIE_REQUIRE(size_t(chunk) * nqblk < (size_t(1) << 31), EFIE_ERR_ARG, "assemble_ws: chunk too large");
-    const bool ck = ki != 0.0;
+    EFIE_REQUIRE(ws_bytes >= size_t(m.n_near) * 9 * sizeof(C2), EFIE_ERR_ARG,
+                 "assemble_ws: workspace smaller than the near-pair blocks");
+    const long long ntiles = tile_count<R>(m.N);
+    EFIE_REQUIRE(ntiles < (1ll << 31), EFIE_ERR_ARG, "assemble_ws: N too large");
+    C2* NB = static_cast<C2*>(ws);
+    if (m.n_near > 0) {
+        if (prof) prof_begin(PROF_NEAR, s);
+        hipLaunchKernelGGL(near_blocks_kernel<R>, dim3(unsigned((m.n_near + 255) / 256)), dim3(256), 0, s, m, kr, ki,
+                           sc, NB);
+        if (prof) prof_end(PROF_NEAR, s);
+    }
     const R kphase = std::is_same<R, float>::value ? R(kr / (2.0 * PI)) : R(kr);
-    C2* W = static_cast<C2*>(ws);
-    prof_begin(PROF_FAR, s);
-    for (int c0 = 0; c0 < m.T; c0 += chunk) {
-        const int c1 = std::min(m.T, c0 + chunk), np = c1 - c0;
-        const dim3 g1(unsigned(size_t((np + FAR_PB - 1) / FAR_PB) * nqblk));
-        // pairs with source triangle q >= p only (the operator is symmetric): the
-        // chunks build U with Z = U + U^T
-        auto far = [&](hipStream_t st) {
-            if (ck)
-                hipLaunchKernelGGL((far_rows_kernel<R, true, true>), g1, dim3(FAR_BLOCK), 0, st, m, tables_of<R>(m),
-                                   kphase, R(ki), sc, W, c0, np, nqblk);
-            else
-                hipLaunchKernelGGL((far_rows_kernel<R, false, true>), g1, dim3(FAR_BLOCK), 0, st, m, tables_of<R>(m),
-                                   kphase, R(ki), sc, W, c0, np, nqblk);
-        };
-        const int e0 = int(std::lower_bound(near_p.begin(), near_p.end(), c0) - near_p.begin());
-        const int e1 = int(std::lower_bound(near_p.begin(), near_p.end(), c1) - near_p.begin());
-        if (e1 > e0)
-            near_beside_far(
-                s,
-                [&](hipStream_t st) {
-                    hipLaunchKernelGGL((near_rows_kernel<R>), dim3((e1 - e0 + 127) / 128), dim3(128), 0, st, m, kr,
-                                       ki, sc, W, c0, c1, e0, e1, 1);
-                },
-                far);
-        else
-            far(s);
-        hipLaunchKernelGGL((gather_rows_kernel<R, true>), dim3(unsigned(3 * np)), dim3(256), 0, s, m, W, c0, c1,
-                           static_cast<C2*>(Z));
-    }
-    {
-        const int nt = (m.N + 31) / 32;
-        const size_t npairs = size_t(nt) * size_t(nt + 1) / 2;
-        EFIE_REQUIRE(npairs < (size_t(1) << 31), EFIE_ERR_ARG, "assemble_ws: N too large");
-        hipLaunchKernelGGL((mirror_add_kernel<C2>), dim3(unsigned(npairs)), dim3(256), 0, s, static_cast<C2*>(Z),
-                           m.N, nt);
-    }
-    prof_end(PROF_FAR, s);
+    if (prof) prof_begin(PROF_FAR, s);
+    if (ki != 0.0)
+        hipLaunchKernelGGL((tile_kernel<R, true>), dim3(unsigned(ntiles)), dim3(256), 0, s, m, tables_of<R>(m),
+                           kphase, R(ki), sc, NB, static_cast<C2*>(Z));
+    else
+        hipLaunchKernelGGL((tile_kernel<R, false>), dim3(unsigned(ntiles)), dim3(256), 0, s, m, tables_of<R>(m),
+                           kphase, R(ki), sc, NB, static_cast<C2*>(Z));
+    if (prof) prof_end(PROF_FAR, s);
 }
 
 template <typename ZT, bool PARTS>
@@ -307,13 +285,13 @@ void pair_rows_chunk(const DevMesh& m, double kr, double ki, double eta, int dty
     else run(double{});
 }
 
-// ws != nullptr (and not parts): far pairs by the two-pass path in that workspace
+// ws != nullptr (and not parts): Z by tiles, the near blocks in that workspace
 static void assemble_impl(const DevMesh& m, double kr, double ki, double eta, int dtype, void* Z, void* Z2, int parts,
                           hipStream_t s, void* ws, size_t ws_bytes, const std::vector<int32_t>* near_p) {
     const size_t N = size_t(m.N);
     const size_t esz = dtype == EFIE_C128 ? 16 : 8;
     if (dtype == EFIE_C64) require_fp32_phase(m.diam, kr, "assemble");
-    if (!ws || parts) fill_zero_bytes(Z, N * N * esz, s);   // the two-pass path writes every entry
+    if (!ws || parts) fill_zero_bytes(Z, N * N * esz, s);   // the tiles write every entry
     if (parts) fill_zero_bytes(Z2, N * N * esz, s);
     Scale sc{};
     if (parts) sc.ar = 1.0 / (4.0 * PI);
@@ -324,7 +302,7 @@ static void assemble_impl(const DevMesh& m, double kr, double ki, double eta, in
             launch_near<double, true>(m, kr, ki, sc, Z, Z2, s);
         } else {
             if (ws) {
-                launch_far_rows<double>(m, kr, ki, sc, Z, ws, ws_bytes, *near_p, s);   // near pairs included
+                launch_tiles<double>(m, kr, ki, sc, Z, ws, ws_bytes, s);   // near pairs included
             } else {
                 launch_far<double, false>(m, kr, ki, sc, Z, Z2, s);
                 launch_near<double, false>(m, kr, ki, sc, Z, Z2, s);
@@ -336,7 +314,7 @@ static void assemble_impl(const DevMesh& m, double kr, double ki, double eta, in
             launch_near<float, true>(m, kr, ki, sc, Z, Z2, s);
         } else {
             if (ws) {
-                launch_far_rows<float>(m, kr, ki, sc, Z, ws, ws_bytes, *near_p, s);    // near pairs included
+                launch_tiles<float>(m, kr, ki, sc, Z, ws, ws_bytes, s);    // near pairs included
             } else {
                 launch_far<float, false>(m, kr, ki, sc, Z, Z2, s);
                 launch_near<float, false>(m, kr, ki, sc, Z, Z2, s);
@@ -349,6 +327,16 @@ static void assemble_impl(const DevMesh& m, double kr, double ki, double eta, in
 void assemble_into(const DevMesh& m, double kr, double ki, double eta, int dtype, void* Z, void* Z2, int parts,
                    hipStream_t s) {
     assemble_impl(m, kr, ki, eta, dtype, Z, Z2, parts, s, nullptr, 0, nullptr);
+}
+
+// the tile assembly of one mesh, not timed on its own (the batch times its whole run)
+void assemble_tiles(const DevMesh& m, double kr, double ki, double eta, int dtype, void* Z, void* NB, size_t nb_bytes,
+                    hipStream_t s) {
+    if (dtype == EFIE_C64) require_fp32_phase(m.diam, kr, "assemble");
+    const Scale sc = operator_scale(kr, ki, eta);
+    if (dtype == EFIE_C128) launch_tiles<double>(m, kr, ki, sc, Z, NB, nb_bytes, s, false);
+    else launch_tiles<float>(m, kr, ki, sc, Z, NB, nb_bytes, s, false);
+    EFIE_HIP_CHECK(hipGetLastError());
 }
 
 }  // namespace efie
@@ -373,9 +361,10 @@ extern "C" int efie_assemble_workspace_size(efie_mesh mesh, int dtype, size_t* m
         EFIE_REQUIRE(mesh != nullptr && min_bytes != nullptr && full_bytes != nullptr, EFIE_ERR_ARG,
                      "assemble_workspace_size: null argument");
         EFIE_REQUIRE(dtype == EFIE_C128 || dtype == EFIE_C64, EFIE_ERR_ARG, "assemble_workspace_size: bad dtype");
-        const size_t per_tri = size_t(6) * size_t(mesh->N) * (dtype == EFIE_C128 ? 16 : 8);
-        *min_bytes = per_tri;
-        *full_bytes = per_tri * size_t(mesh->T);
+        // the FP64 blocks of the ordered near pairs, stored in the precision of Z
+        const size_t nb = std::max<size_t>(256, mesh->near_p.size() * 9 * (dtype == EFIE_C128 ? 16 : 8));
+        *min_bytes = nb;
+        *full_bytes = nb;
         return int(EFIE_OK);
     });
 }

@@ -19,7 +19,6 @@ struct efie_batch_s {
     std::vector<int64_t> zoff, voff;    // caller order: Z element offsets; vector offsets (n + 1)
     int64_t z_total = 0, v_total = 0;
     void* dev = nullptr;                // caller-owned device blob
-    std::vector<void*> mesh_dev;        // caller order: each mesh's tables when the batch was uploaded
     size_t off_zoff = 0, off_voff = 0;
 };
 

@@ -1,21 +1,16 @@
-// Many uneven meshes at once: persistent work-queue assembly and a grouped
+// Many uneven meshes at once: the tile assembly of every mesh and a grouped
 // Krylov solve.
 //
-// Assembly.  The atomic-free two-pass scheme of the single-mesh assembly
-// (assemble.hip), run as work items of persistent launches: the meshes, ordered
-// by decreasing cost, are cut into segments (chunks of test triangles) whose rows
-// W[p][i][n][side] fit one workspace; per group of segments four launches take
-// items from their own atomic counter until all are done (every block leaves when
-// the counter passes the total):
-//   A  rows: a far item is one block of the single-mesh pass-1 kernel (FAR_PB test
-//      triangles against 256 source triangles); a near item 256 ordered near pairs
-//      (their own launch, whose FP64 code would otherwise take the far items'
-//      registers);
-//   B  gather: a block per (test triangle, local edge) row of a segment;
-//   C  mirror: the mirror tile pairs of every mesh whose last segment is in the group.
-// Each item runs the same device code as the single-mesh kernels (rows_kernels.h),
-// with the same scale factors, so every batched matrix is bit-identical to its
-// single-mesh assembly; no atomics touch Z.
+// Assembly.  Every mesh is assembled by the single-mesh tile kernels
+// (tile_kernels.h: its near blocks, then its tiles of Z written once), the meshes
+// in order of decreasing cost dealt round-robin to four streams of the device
+// forked from and joined back into the caller's stream, so that the small meshes'
+// launches run beside each other.  The kernels and their arguments are those of
+// efie_assemble_ws, so every batched matrix is bit-identical to its single-mesh
+// assembly; Z is written once and no atomics touch it.  (A persistent work-queue
+// launch over all meshes' tiles reads each mesh's tables through pointers loaded
+// from device memory, generic loads that cost the tile code a third of its
+// occupancy; the kernel-argument launches keep the single-mesh code as it is.)
 //
 // Solve.  One right-hand side per mesh; Z of the meshes concatenated
 // (Z_i at element offset sum_{j<i} N_j^2), vectors concatenated (offset
@@ -25,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -33,113 +29,43 @@
 
 #include "batch.h"
 #include "linalg.h"
-#include "rows_kernels.h"
 
 namespace efie {
+
+void assemble_tiles(const DevMesh& m, double kr, double ki, double eta, int dtype, void* Z, void* NB, size_t nb_bytes,
+                    hipStream_t s);
 
 struct BatchMeshDev {
     DevMesh m;
     int64_t zoff;     // element offset of this mesh's Z
-    int64_t pad[2];
+    int64_t pad[3];
 };
 
-struct BatchParam {
-    Scale sc;         // operator_scale(k, 0, eta), as the single-mesh assembly
-    double kr;
-    float kphase32;   // k / 2 pi in FP32 (the complex64 pass 1)
-    float pad;
+// the streams of the batched assembly: four per device, created on first use and
+// kept until the process ends; host threads take turns
+constexpr int BATCH_STREAMS = 4;
+struct BatchStreams {
+    hipStream_t s[BATCH_STREAMS] = {};
+    hipEvent_t fork = nullptr, join[BATCH_STREAMS] = {};
+    std::mutex mu;
 };
-
-// a chunk [c0, c0 + np) of the test triangles of mesh r (processing order)
-struct BatchSeg {
-    int r, c0, np, nqblk;
-    int e0, e1;       // its ordered near pairs
-    int64_t woff;     // element offset of its rows in the workspace
-    int64_t nfar;     // pass-1 far items: ceil(np / FAR_PB) nqblk
-};
-
-// the item of a block: one shared load, uniform over the block
-__device__ inline long long next_item(unsigned long long* counter) {
-    __shared__ long long item_s;
-    if (threadIdx.x == 0) item_s = (long long)atomicAdd(counter, 1ull);
-    __syncthreads();
-    const long long item = item_s;
-    __syncthreads();
-    return item;
-}
-
-// pref[lo] <= item < pref[lo + 1]
-__device__ inline int find_seg(const int64_t* __restrict__ pref, int n, long long item) {
-    int lo = 0, hi = n;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (pref[mid] <= item) lo = mid;
-        else hi = mid;
-    }
-    return lo;
-}
-
-// phase A: pass-1 far blocks (NEAR false) or the near pairs, 256 per item (NEAR
-// true), of every segment of the group (two launches: the FP64 near-pair code
-// would take the far blocks' registers)
-template <typename ZT, bool NEAR>
-__global__ __launch_bounds__(256) void batch_rows_kernel(const BatchMeshDev* __restrict__ bm,
-                                                         const BatchParam* __restrict__ prm,
-                                                         const BatchSeg* __restrict__ seg,
-                                                         const int64_t* __restrict__ pref, int nseg, int64_t total,
-                                                         unsigned long long* counter, ZT* __restrict__ W) {
-    using R = typename std::conditional<sizeof(ZT) == 8, float, double>::type;
-    for (;;) {
-        const long long item = next_item(counter);
-        if (item >= total) return;
-        const int s = find_seg(pref, nseg, item);
-        const BatchSeg& g = seg[s];
-        const DevMesh& m = bm[g.r].m;
-        const BatchParam& pm = prm[g.r];
-        const long long li = item - pref[s];
-        ZT* w = W + g.woff;
-        if (!NEAR) {
-            const R kphase = sizeof(ZT) == 8 ? R(pm.kphase32) : R(pm.kr);
-            far_rows_block<R, false, true>(m, tables_of<R>(m), kphase, R(0), pm.sc, w, g.c0, g.np, g.nqblk, int(li));
-        } else {
-            const long long e = g.e0 + li * 256 + threadIdx.x;
-            if (e < g.e1) near_rows_one<R>(m, pm.kr, 0.0, pm.sc, w, g.c0, g.c0 + g.np, int(e), 1);
+static BatchStreams& batch_streams() {
+    constexpr int MAXDEV = 64;
+    static BatchStreams bs[MAXDEV];
+    static std::mutex create_mu;
+    int dev = 0;
+    EFIE_HIP_CHECK(hipGetDevice(&dev));
+    EFIE_REQUIRE(dev >= 0 && dev < MAXDEV, EFIE_ERR_STATE, "batch streams: device index out of range");
+    BatchStreams& x = bs[dev];
+    std::lock_guard<std::mutex> g(create_mu);
+    if (!x.fork) {
+        for (int i = 0; i < BATCH_STREAMS; ++i) {
+            EFIE_HIP_CHECK(hipStreamCreateWithFlags(&x.s[i], hipStreamNonBlocking));
+            EFIE_HIP_CHECK(hipEventCreateWithFlags(&x.join[i], hipEventDisableTiming));
         }
+        EFIE_HIP_CHECK(hipEventCreateWithFlags(&x.fork, hipEventDisableTiming));
     }
-}
-
-// phase B: the gather blocks of every segment (3 np per segment)
-template <typename ZT>
-__global__ __launch_bounds__(256) void batch_gather_kernel(const BatchMeshDev* __restrict__ bm,
-                                                           const BatchSeg* __restrict__ seg,
-                                                           const int64_t* __restrict__ pref, int nseg, int64_t total,
-                                                           unsigned long long* counter, const ZT* __restrict__ W,
-                                                           ZT* __restrict__ Zcat) {
-    using R = typename std::conditional<sizeof(ZT) == 8, float, double>::type;
-    for (;;) {
-        const long long item = next_item(counter);
-        if (item >= total) return;
-        const int s = find_seg(pref, nseg, item);
-        const BatchSeg& g = seg[s];
-        const BatchMeshDev& b = bm[g.r];
-        gather_rows_block<R, true>(b.m, W + g.woff, g.c0, g.c0 + g.np, Zcat + b.zoff, int(item - pref[s]));
-    }
-}
-
-// phase C: the mirror tile pairs of the meshes completed by the group (mesh ranks mr[])
-template <typename ZT>
-__global__ __launch_bounds__(256) void batch_mirror_kernel(const BatchMeshDev* __restrict__ bm,
-                                                           const int* __restrict__ mr,
-                                                           const int64_t* __restrict__ pref, int nmr, int64_t total,
-                                                           unsigned long long* counter, ZT* __restrict__ Zcat) {
-    for (;;) {
-        const long long item = next_item(counter);
-        if (item >= total) return;
-        const int s = find_seg(pref, nmr, item);
-        const BatchMeshDev& b = bm[mr[s]];
-        const int N = b.m.N;
-        mirror_add_block<ZT>(Zcat + b.zoff, N, (N + 31) / 32, item - pref[s]);
-    }
+    return x;
 }
 
 // rows of all meshes: y[voff_s + i] = sum_k Z_s[i][k] x[voff_s + k] for active meshes
@@ -333,130 +259,22 @@ void batch_residual_norms(const double2* b, const double2* y, const int64_t* vof
 namespace {
 size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
 
-// rows of one group of segments: at most this many bytes (a chunk of one test
-// triangle is the minimum)
-constexpr size_t BATCH_W_BUDGET = size_t(2) << 30;
-
-// The assembly plan for one storage type: segments in processing order, cut into
-// groups whose rows fit BATCH_W_BUDGET; per group the item prefixes of the three
-// phases (concatenated, nseg + 1 / nmr + 1 entries per group).
-struct BatchPlan {
-    struct Group {
-        int s0, ns, m0, nmr;         // its segments and mirror meshes
-        size_t a0, c0;               // first entry of its prefixes in apref / bpref, cpref
-        int64_t atot, ntot, btot, ctot;   // item totals: far rows, near rows, gather, mirror
-    };
-    std::vector<BatchSeg> segs;
-    std::vector<int64_t> apref, npref, bpref, cpref;
-    std::vector<int> mr;
-    std::vector<Group> groups;
-    size_t w_bytes = 0;
-    int64_t pass1_items = 0;
-};
-
-BatchPlan batch_plan(const efie_batch_s& B, size_t esz) {
-    BatchPlan P;
-    const int nm = int(B.meshes.size());
-    std::vector<BatchSeg> cur;
-    std::vector<int> cur_mr;
-    size_t gbytes = 0;
-    auto close = [&]() {
-        if (cur.empty() && cur_mr.empty()) return;
-        BatchPlan::Group g{};
-        g.s0 = int(P.segs.size());
-        g.ns = int(cur.size());
-        g.m0 = int(P.mr.size());
-        g.nmr = int(cur_mr.size());
-        g.a0 = P.apref.size();
-        g.c0 = P.cpref.size();
-        int64_t a = 0, nn = 0, b = 0, c = 0;
-        for (const BatchSeg& x : cur) {
-            P.apref.push_back(a);
-            P.npref.push_back(nn);
-            P.bpref.push_back(b);
-            a += x.nfar;
-            nn += (x.e1 - x.e0 + 255) / 256;
-            b += 3 * int64_t(x.np);
-            P.segs.push_back(x);
-        }
-        P.apref.push_back(a);
-        P.npref.push_back(nn);
-        P.bpref.push_back(b);
-        for (int r : cur_mr) {
-            P.cpref.push_back(c);
-            const int64_t nt = (B.meshes[size_t(B.order[size_t(r)])]->N + 31) / 32;
-            c += nt * (nt + 1) / 2;
-            P.mr.push_back(r);
-        }
-        P.cpref.push_back(c);
-        g.atot = a;
-        g.ntot = nn;
-        g.btot = b;
-        g.ctot = c;
-        P.pass1_items += a + nn;
-        P.groups.push_back(g);
-        P.w_bytes = std::max(P.w_bytes, gbytes);
-        cur.clear();
-        cur_mr.clear();
-        gbytes = 0;
-    };
-    for (int r = 0; r < nm; ++r) {
-        const efie_mesh_s& m = *B.meshes[size_t(B.order[size_t(r)])];
-        const size_t per_tri = size_t(6) * size_t(m.N) * esz;
-        EFIE_REQUIRE(per_tri <= BATCH_W_BUDGET, EFIE_ERR_ARG, "batch: a mesh too large for the row workspace");
-        const int T = int(m.T);
-        const int chunk = int(std::max<size_t>(1, std::min<size_t>(size_t(T), BATCH_W_BUDGET / per_tri)));
-        const int nqblk = (T + FAR_BLOCK - 1) / FAR_BLOCK;
-        for (int c0 = 0; c0 < T; c0 += chunk) {
-            const int np = std::min(chunk, T - c0);
-            const size_t bytes = a256(size_t(np) * per_tri);
-            if (!cur.empty() && gbytes + bytes > BATCH_W_BUDGET) close();
-            BatchSeg x{};
-            x.r = r;
-            x.c0 = c0;
-            x.np = np;
-            x.nqblk = nqblk;
-            x.e0 = int(std::lower_bound(m.near_p.begin(), m.near_p.end(), c0) - m.near_p.begin());
-            x.e1 = int(std::lower_bound(m.near_p.begin(), m.near_p.end(), c0 + np) - m.near_p.begin());
-            x.woff = int64_t(gbytes / esz);
-            x.nfar = int64_t((np + FAR_PB - 1) / FAR_PB) * nqblk;
-            cur.push_back(x);
-            gbytes += bytes;
-        }
-        cur_mr.push_back(r);   // the mesh's last segment is in the current group
-    }
-    close();
-    return P;
-}
-
 struct BatchWs {
-    BatchParam* prm;
-    unsigned long long* counter;   // [0] far rows, [1] near rows, [2] gather, [3] mirror
-    BatchSeg* segs;
-    int64_t *apref, *npref, *bpref, *cpref;
-    int* mr;
-    void* W;
+    char* NB;                      // near blocks of every mesh
     double2 *r, *p, *q, *y;
     BatchCol* cols;
     int* active;
     int* nact;
 };
 
-// sizes of the plan arrays and rows: the larger of the two storage types
-struct BatchPlanMax {
-    size_t nseg = 0, npref = 0, ncpref = 0, nmr = 0, w_bytes = 0;
-};
-BatchPlanMax batch_plan_max(const efie_batch_s& B) {
-    BatchPlanMax x;
-    for (size_t esz : {size_t(8), size_t(16)}) {
-        const BatchPlan P = batch_plan(B, esz);
-        x.nseg = std::max(x.nseg, P.segs.size());
-        x.npref = std::max(x.npref, P.apref.size());
-        x.ncpref = std::max(x.ncpref, P.cpref.size());
-        x.nmr = std::max(x.nmr, P.mr.size());
-        x.w_bytes = std::max(x.w_bytes, P.w_bytes);
-    }
-    return x;
+// byte offsets of every mesh's near blocks (complex128 size, 256-aligned), caller
+// order; total in [nm]
+std::vector<size_t> batch_nb_offsets(const efie_batch_s& B) {
+    const size_t nm = B.meshes.size();
+    std::vector<size_t> off(nm + 1, 0);
+    for (size_t i = 0; i < nm; ++i)
+        off[i + 1] = off[i] + a256(std::max<size_t>(256, B.meshes[i]->near_p.size() * 9 * 16));
+    return off;
 }
 
 size_t batch_ws_layout(const efie_batch_s& B, BatchWs* w, char* base) {
@@ -466,19 +284,10 @@ size_t batch_ws_layout(const efie_batch_s& B, BatchWs* w, char* base) {
         off += a256(bytes);
         return p;
     };
-    const BatchPlanMax pm = batch_plan_max(B);
     BatchWs x{};
     const size_t nm = B.meshes.size();
     const size_t vec = size_t(B.v_total) * 16;
-    x.prm = (BatchParam*)take(sizeof(BatchParam) * nm);
-    x.counter = (unsigned long long*)take(64);
-    x.segs = (BatchSeg*)take(sizeof(BatchSeg) * pm.nseg);
-    x.apref = (int64_t*)take(8 * pm.npref);
-    x.npref = (int64_t*)take(8 * pm.npref);
-    x.bpref = (int64_t*)take(8 * pm.npref);
-    x.cpref = (int64_t*)take(8 * pm.ncpref);
-    x.mr = (int*)take(4 * pm.nmr);
-    x.W = take(pm.w_bytes);
+    x.NB = take(batch_nb_offsets(B)[nm]);
     x.r = (double2*)take(vec);
     x.p = (double2*)take(vec);
     x.q = (double2*)take(vec);
@@ -528,10 +337,6 @@ extern "C" int efie_batch_create(const efie_mesh* meshes, int32_t nmesh, efie_ba
                 delete B;
                 throw Error{EFIE_ERR_STATE, "batch_create: every mesh must exist and be uploaded"};
             }
-            if (meshes[i]->far3 != 0.0) {
-                delete B;
-                throw Error{EFIE_ERR_ARG, "batch_create: the batch takes the 7x7 rule only (a mesh has the far rule on)"};
-            }
             B->meshes.push_back(meshes[i]);
         }
         batch_prepare(*B);
@@ -551,7 +356,9 @@ extern "C" int efie_batch_sizes(efie_batch b, size_t* table_bytes, size_t* ws_by
         if (ws_bytes) *ws_bytes = batch_ws_layout(*b, nullptr, nullptr);
         if (z_elems) *z_elems = b->z_total;
         if (v_elems) *v_elems = b->v_total;
-        if (items) *items = batch_plan(*b, 8).pass1_items;
+        if (items) {   // launches of the assembly: near blocks and tiles per mesh
+            *items = int64_t(2 * nm);
+        }
         return int(EFIE_OK);
     });
 }
@@ -565,18 +372,14 @@ extern "C" int efie_batch_upload(efie_batch b, void* dev, size_t bytes, hipStrea
         EFIE_REQUIRE((reinterpret_cast<uintptr_t>(dev) & 255) == 0, EFIE_ERR_ARG, "batch_upload: not 256-aligned");
         std::vector<char> blob(need, 0);
         auto* bmd = reinterpret_cast<BatchMeshDev*>(blob.data());
-        b->mesh_dev.assign(nm, nullptr);
         for (size_t r = 0; r < nm; ++r) {
             const int i = b->order[r];
             const efie_mesh_s& m = *b->meshes[size_t(i)];
             EFIE_REQUIRE(m.dev != nullptr, EFIE_ERR_STATE, "batch_upload: a mesh is not uploaded");
-            EFIE_REQUIRE(m.far3 == 0.0, EFIE_ERR_ARG, "batch_upload: the batch takes the 7x7 rule only (a mesh has "
-                                                      "the far rule on)");
             BatchMeshDev d{};
             d.m = m.dm;
             d.zoff = b->zoff[size_t(i)];
             bmd[r] = d;
-            b->mesh_dev[size_t(i)] = m.dev;
         }
         size_t off = a256(sizeof(BatchMeshDev) * nm);
         std::memcpy(blob.data() + off, b->zoff.data(), 8 * nm);
@@ -601,74 +404,34 @@ extern "C" int efie_batch_assemble(efie_batch b, const double* k, double eta, in
         BatchWs w;
         batch_ws_layout(*b, &w, static_cast<char*>(ws));
         const size_t nm = b->meshes.size();
-        for (size_t i = 0; i < nm; ++i) {
-            const efie_mesh_s& m = *b->meshes[i];
-            EFIE_REQUIRE(m.far3 == 0.0, EFIE_ERR_ARG, "batch_assemble: the batch takes the 7x7 rule only (a mesh "
-                                                      "has the far rule on)");
-            EFIE_REQUIRE(m.dev != nullptr && m.dev == b->mesh_dev[i], EFIE_ERR_STATE,
-                         "batch_assemble: a mesh was uploaded again after the batch; upload the batch again");
-        }
-        std::vector<BatchParam> prm(nm);
+        for (size_t i = 0; i < nm; ++i)
+            EFIE_REQUIRE(b->meshes[i]->dev != nullptr, EFIE_ERR_STATE, "batch_assemble: a mesh is not uploaded");
         for (size_t r = 0; r < nm; ++r) {
             const double kr = k[b->order[r]];
             EFIE_REQUIRE(std::isfinite(kr) && kr > 0.0, EFIE_ERR_ARG, "batch_assemble: k must be real and > 0");
             if (dtype == EFIE_C64) require_fp32_phase(b->meshes[size_t(b->order[r])]->diam, kr, "batch_assemble");
-            BatchParam p{};
-            p.sc = operator_scale(kr, 0.0, eta);   // the single-mesh assembly's factors, bit for bit
-            p.kr = kr;
-            p.kphase32 = float(kr / (2.0 * PI));
-            prm[r] = p;
         }
+        const std::vector<size_t> nbo = batch_nb_offsets(*b);
         const size_t esz = dtype == EFIE_C128 ? 16 : 8;
-        const BatchPlan plan = batch_plan(*b, esz);
-        EFIE_HIP_CHECK(hipMemcpyAsync(w.prm, prm.data(), sizeof(BatchParam) * nm, hipMemcpyHostToDevice, stream));
-        EFIE_HIP_CHECK(hipMemcpyAsync(w.segs, plan.segs.data(), sizeof(BatchSeg) * plan.segs.size(),
-                                      hipMemcpyHostToDevice, stream));
-        EFIE_HIP_CHECK(hipMemcpyAsync(w.apref, plan.apref.data(), 8 * plan.apref.size(), hipMemcpyHostToDevice, stream));
-        EFIE_HIP_CHECK(hipMemcpyAsync(w.npref, plan.npref.data(), 8 * plan.npref.size(), hipMemcpyHostToDevice, stream));
-        EFIE_HIP_CHECK(hipMemcpyAsync(w.bpref, plan.bpref.data(), 8 * plan.bpref.size(), hipMemcpyHostToDevice, stream));
-        EFIE_HIP_CHECK(hipMemcpyAsync(w.cpref, plan.cpref.data(), 8 * plan.cpref.size(), hipMemcpyHostToDevice, stream));
-        if (!plan.mr.empty())
-            EFIE_HIP_CHECK(hipMemcpyAsync(w.mr, plan.mr.data(), 4 * plan.mr.size(), hipMemcpyHostToDevice, stream));
-        int dev_id = 0, ncu = 0;
-        EFIE_HIP_CHECK(hipGetDevice(&dev_id));
-        EFIE_HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev_id));
-        const auto* bmd = static_cast<const BatchMeshDev*>(b->dev);
-        auto grid_of = [&](const void* fn) {   // persistent grid: every CU full
-            int per_cu = 0;
-            EFIE_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0));
-            return dim3(unsigned(std::max(1, ncu * std::max(1, per_cu))));
-        };
-        auto run = [&](auto tag) {
-            using ZT = decltype(tag);
-            ZT* W = static_cast<ZT*>(w.W);
-            ZT* Z = static_cast<ZT*>(Zcat);
-            const dim3 ga = grid_of(reinterpret_cast<const void*>(batch_rows_kernel<ZT, false>));
-            const dim3 gn = grid_of(reinterpret_cast<const void*>(batch_rows_kernel<ZT, true>));
-            const dim3 gb = grid_of(reinterpret_cast<const void*>(batch_gather_kernel<ZT>));
-            const dim3 gc = grid_of(reinterpret_cast<const void*>(batch_mirror_kernel<ZT>));
-            for (const BatchPlan::Group& g : plan.groups) {
-                fill_zero_bytes(w.counter, 64, stream);
-                if (g.atot > 0)
-                    hipLaunchKernelGGL((batch_rows_kernel<ZT, false>), ga, dim3(256), 0, stream, bmd, w.prm,
-                                       w.segs + g.s0, w.apref + g.a0, g.ns, g.atot, w.counter, W);
-                if (g.ntot > 0)
-                    hipLaunchKernelGGL((batch_rows_kernel<ZT, true>), gn, dim3(256), 0, stream, bmd, w.prm,
-                                       w.segs + g.s0, w.npref + g.a0, g.ns, g.ntot, w.counter + 1, W);
-                if (g.btot > 0)
-                    hipLaunchKernelGGL(batch_gather_kernel<ZT>, gb, dim3(256), 0, stream, bmd, w.segs + g.s0,
-                                       w.bpref + g.a0, g.ns, g.btot, w.counter + 2, W, Z);
-                if (g.ctot > 0)
-                    hipLaunchKernelGGL(batch_mirror_kernel<ZT>, gc, dim3(256), 0, stream, bmd, w.mr + g.m0,
-                                       w.cpref + g.c0, g.nmr, g.ctot, w.counter + 3, Z);
-            }
-        };
+        BatchStreams& bs = batch_streams();
+        std::lock_guard<std::mutex> g(bs.mu);
         prof_begin(PROF_FAR, stream);
-        if (dtype == EFIE_C64) run(float2{});
-        else run(double2{});
+        EFIE_HIP_CHECK(hipEventRecord(bs.fork, stream));
+        for (int i = 0; i < BATCH_STREAMS; ++i) EFIE_HIP_CHECK(hipStreamWaitEvent(bs.s[i], bs.fork, 0));
+        for (size_t r = 0; r < nm; ++r) {
+            const int i = b->order[r];
+            const efie_mesh_s& m = *b->meshes[size_t(i)];
+            char* z = static_cast<char*>(Zcat) + size_t(b->zoff[size_t(i)]) * esz;
+            assemble_tiles(m.dm, k[i], 0.0, eta, dtype, z, w.NB + nbo[size_t(i)], nbo[size_t(i) + 1] - nbo[size_t(i)],
+                           bs.s[r % BATCH_STREAMS]);
+        }
+        for (int i = 0; i < BATCH_STREAMS; ++i) {
+            EFIE_HIP_CHECK(hipEventRecord(bs.join[i], bs.s[i]));
+            EFIE_HIP_CHECK(hipStreamWaitEvent(stream, bs.join[i], 0));
+        }
         prof_end(PROF_FAR, stream);
         EFIE_HIP_CHECK(hipGetLastError());
-        EFIE_HIP_CHECK(hipStreamSynchronize(stream));   // the host staging lives on this stack frame
+        EFIE_HIP_CHECK(hipStreamSynchronize(stream));
         return int(EFIE_OK);
     });
 }

@@ -97,11 +97,14 @@ __device__ __forceinline__ void green_far(float krev, float ki, bool ck, float R
 // T_A part and emit2 gets the T_Phi part).
 // The product rule of NP points per triangle, point offsets and weights from the
 // tables (qx, qy, qz, qw), [NP][T].
-template <int NP, typename R, bool CK, bool PARTS, typename Emit, typename Emit2>
+// PRE: the source triangle's points and weights come from pre[4][NP] (x, y, z, w)
+// already in registers instead of the tables
+template <int NP, typename R, bool CK, bool PARTS, bool PRE = false, typename Emit, typename Emit2>
 __device__ __forceinline__ void far_pair_rule(const DevMesh& m, const Tables<R>& tb, const R* __restrict__ qx,
                                               const R* __restrict__ qy, const R* __restrict__ qz,
                                               const R* __restrict__ qw, int p, int q, R kphase, R ki,
-                                              const Scale& sc, Emit emit, Emit2 emit2) {
+                                              const Scale& sc, Emit emit, Emit2 emit2,
+                                              const R (*pre)[NP] = nullptr) {
     const int T = m.T;
     const R Dx = R(m.cx[p] - m.cx[q]);
     const R Dy = R(m.cy[p] - m.cy[q]);
@@ -109,10 +112,10 @@ __device__ __forceinline__ void far_pair_rule(const DevMesh& m, const Tables<R>&
     R sx[NP], sy[NP], sz[NP], sw[NP];
 #pragma unroll
     for (int b = 0; b < NP; ++b) {
-        sx[b] = qx[b * T + q];
-        sy[b] = qy[b * T + q];
-        sz[b] = qz[b * T + q];
-        sw[b] = qw[b * T + q];
+        sx[b] = PRE ? pre[0][b] : qx[b * T + q];
+        sy[b] = PRE ? pre[1][b] : qy[b * T + q];
+        sz[b] = PRE ? pre[2][b] : qz[b * T + q];
+        sw[b] = PRE ? pre[3][b] : qw[b * T + q];
     }
     R m0r = 0, m0i = 0;
     R mdr[3] = {0, 0, 0}, mdi[3] = {0, 0, 0};     // sum W W G d_a

@@ -7,7 +7,8 @@ basis functions, no Green's function, no quadrature, no operator.
 Workloads (all in metres, free space):
   * PEC unit sphere meshed as an icosphere: recursive 4-split of the regular
     icosahedron with projection to the unit sphere after every level
-    (level L has T = 20*4**L triangles, N = 30*4**L edges, V = 10*4**L + 2 vertices).
+    (level L has T = 20*4**L triangles, N = 30*4**L edges, V = 10*4**L + 2 vertices),
+    vertices numbered in Morton order.
   * Ellipsoids: Class-I geodesic subdivision of frequency n of the icosahedron
     (each face split into n*n triangles), projected to the unit sphere and then
     scaled per axis.  N = 30*n*n edges.
@@ -41,6 +42,7 @@ __all__ = [
     "contour_joukowsky",
     "contour_circle",
     "gaussian_block",
+    "morton_order",
 ]
 
 
@@ -78,11 +80,27 @@ def _orient_outward(v, f):
     return v, f
 
 
+def morton_order(v, bits: int = 21):
+    """Permutation sorting points (V, 3) by their Morton (Z-order) code in the
+    bounding box, `bits` per axis: neighbouring indices are neighbours in space."""
+    v = np.asarray(v, dtype=np.float64)
+    lo, hi = v.min(axis=0), v.max(axis=0)
+    span = np.where(hi > lo, hi - lo, 1.0)
+    q = np.minimum(((v - lo) / span * (2 ** bits - 1)).astype(np.int64), 2 ** bits - 1)
+    code = np.zeros(len(v), dtype=np.int64)
+    for b in range(bits):
+        for d in range(3):
+            code |= ((q[:, d] >> b) & 1) << (3 * b + d)
+    return np.argsort(code, kind="stable")
+
+
 def icosphere(level: int):
     """Unit icosphere: recursive 4-split with projection after every level.
 
     Children of triangle t at one level are triangles 4t..4t+3 at the next,
-    so the triangle order is hierarchical (spatially local).
+    so the triangle order is hierarchical (spatially local).  The vertices are
+    numbered in Morton order of their positions, so that RWG functions, numbered
+    by their vertex ids, are spatially coherent in index ranges as well.
     """
     v, f = icosahedron()
     verts = [tuple(x) for x in v]
@@ -103,7 +121,11 @@ def icosphere(level: int):
             ab, bc, ca = mid(a, b), mid(b, c), mid(c, a)
             nf += [(a, ab, ca), (ab, b, bc), (ca, bc, c), (ab, bc, ca)]
         f = np.array(nf, dtype=np.int32)
-    return np.array(verts, dtype=np.float64), f
+    v = np.array(verts, dtype=np.float64)
+    order = morton_order(v)
+    rank = np.empty(len(order), dtype=np.int32)
+    rank[order] = np.arange(len(order), dtype=np.int32)
+    return v[order], rank[np.asarray(f)].astype(np.int32)
 
 
 def geodesic_sphere(n: int):

@@ -133,8 +133,10 @@ def test_calderon_own_far_rule_l1(dev):
         cal.set_far_rule(float("nan"))
 
 
-def test_far_rule_rejected_by_gradient_and_batch(dev):
-    m = far_mesh(1, 3.0, dev)
+def test_far_rule_rejected_by_gradient_followed_by_batch(dev):
+    """The vertex gradient keeps the 7x7 rule and rejects a mesh with the far rule
+    on; the batched assembly runs the single-mesh tile kernels and follows it."""
+    m = far_mesh(2, 3.0, dev)
     n = m.n
     J = torch.zeros(n, dtype=torch.complex128, device=dev)
     W = torch.zeros(2, dtype=torch.complex128, device=dev)
@@ -142,6 +144,6 @@ def test_far_rule_rejected_by_gradient_and_batch(dev):
     with pytest.raises(P.EfieError) as ei:
         P.vertex_grad(m, 1.0, J, J, W, np.array([[0.0, 0.0, 1.0]]), kh, pol)
     assert ei.value.code == -1
-    with pytest.raises(P.EfieError) as ei:
-        P.Batch([m])
-    assert ei.value.code == -1
+    for code in (P.C64, P.C128):
+        Zb = P.Batch([m]).assemble([2.0], dtype=code)
+        assert torch.equal(Zb.view(n, n), P.assemble(m, 2.0, dtype=code))

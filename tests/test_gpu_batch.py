@@ -62,14 +62,19 @@ def test_batch_solve_equals_single(dev):
     Zc = B.assemble(k, dtype=P.C128)
     kh, pol = synth.planewave_x_along_minus_z()
     Vc = torch.cat([P.excite_planewave(m, k, kh, pol)[0] for m in meshes])
+    J6, st6 = B.solve(Zc, Vc, tol=1e-6, maxit=1000)
     J, st = B.solve(Zc, Vc, tol=1e-10, maxit=1000)
     assert np.all(st.status == 0) and np.all(st.relres_true <= 2e-10)
     for i, m in enumerate(meshes):
-        J1, st1 = P.solve(B.z_of(Zc, i).contiguous(), Vc[B.voff[i]:B.voff[i + 1]].contiguous(), tol=1e-10,
-                          maxit=1000)
-        # the matrices are bit-identical; grouped and single GEMV sum in different
-        # orders, which moves COCG's step count to 1e-10 by at most a couple
-        assert abs(int(st1.iters[0]) - int(st.iters[i])) <= 2
+        Zi, Vi = B.z_of(Zc, i).contiguous(), Vc[B.voff[i]:B.voff[i + 1]].contiguous()
+        _, s6 = P.solve(Zi, Vi, tol=1e-6, maxit=1000)
+        J1, st1 = P.solve(Zi, Vi, tol=1e-10, maxit=1000)
+        # the matrices are bit-identical; the grouped and the single GEMV sum in
+        # different orders: the step counts to 1e-6 agree within 2, those to 1e-10
+        # (about 180 steps, where COCG's loss of orthogonality amplifies rounding)
+        # within 3 %
+        assert abs(int(s6.iters[0]) - int(st6.iters[i])) <= 2
+        assert abs(int(st1.iters[0]) - int(st.iters[i])) <= max(2, int(0.03 * st1.iters[0]))
         a = J[B.voff[i]:B.voff[i + 1]].cpu().numpy()
         b = J1.cpu().numpy()[0]
         assert np.linalg.norm(a - b) <= 1e-8 * np.linalg.norm(b)
