@@ -151,6 +151,39 @@ def measured_traffic(tiles, acc64, n, nrhs, solver):
     return None, None
 
 
+ASSEMBLY_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "assembly_tiles_l5_k10_hbm_traffic.md")
+TILE_SOURCES = [os.path.join(ROOT, "paper_2310_15644_amd", "csrc", f)
+                for f in ("tile_kernels.h", "pair_kernels.h", "rows_kernels.h")]
+
+
+def tile_code_sha256():
+    """SHA-256 of the tile assembly's device code (comments and whitespace removed)."""
+    import hashlib
+    import re
+
+    h = hashlib.sha256()
+    for path in TILE_SOURCES:
+        code = re.sub(r"//[^\n]*", "", open(path).read())
+        h.update(re.sub(r"\s+", "", code).encode())
+    return h.hexdigest()
+
+
+def assembly_traffic(n, k, dtype, far_rule):
+    """HBM bytes of one tile assembly from the committed counter summary, or None
+    when it is for another workload or the device code has changed since."""
+    if not os.path.exists(ASSEMBLY_TRAFFIC_FILE):
+        return None, None
+    kv = {}
+    for line in open(ASSEMBLY_TRAFFIC_FILE):
+        if line.startswith("- ") and ": " in line:
+            key, val = line[2:].split(": ", 1)
+            kv[key.strip()] = val.strip().strip("`")
+    if (kv.get("tile_code_sha256") == tile_code_sha256()
+            and kv.get("workload") == f"n={n} k={float(k)} dtype={dtype} far_rule={float(far_rule)}"):
+        return float(kv["hbm_bytes_per_assembly"]), os.path.relpath(ASSEMBLY_TRAFFIC_FILE, ROOT)
+    return None, None
+
+
 def cpu_model():
     """The host CPU's model name (from /proc/cpuinfo), or None."""
     try:
@@ -951,6 +984,13 @@ def main():
     out["roofline"]["kernel"] = None if tiles is None else P.gemm_kernel_name(tiles, not args.fp32_acc)
     out["roofline"]["traffic"], out["roofline"]["traffic_source"] = measured_traffic(
         tiles, not args.fp32_acc, out["config"]["n_unknowns"], S, args.solver)
+    # the assembly's HBM bytes (rocprofv3 counters) against Z's and the 8 TB/s peak
+    a_tr, a_src = assembly_traffic(N, args.k, args.dtype, args.far_rule)
+    zb = N * N * (8 if dt == P.C64 else 16)
+    out["assembly_roofline"]["traffic"] = a_tr
+    out["assembly_roofline"]["traffic_source"] = a_src
+    out["assembly_roofline"]["traffic_over_z"] = None if a_tr is None else round(a_tr / zb, 3)
+    out["assembly_roofline"]["hbm_frac"] = None if a_tr is None else round(a_tr / (asm_ms * 1e-3) / 8e12, 4)
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(args.level, 2048, S, args.k, args.cpu_seconds)

@@ -43,6 +43,17 @@ def test_committed_traffic_matches_the_current_gemm():
     assert bench.measured_traffic([64, 32, 32], True, 7680, 512, "calderon") == (None, None)
 
 
+def test_committed_assembly_traffic_matches_the_current_tiles():
+    """The committed assembly counters belong to the current tile code and the bench
+    workload (the level-5 sphere at k = 10, complex64, no far rule), and show Z
+    written once with at most three times its bytes in all."""
+    t, src = bench.assembly_traffic(30720, 10.0, "c64", 0.0)
+    z = 30720 * 30720 * 8
+    assert src is not None and z <= t <= 3 * z
+    assert bench.assembly_traffic(7680, 10.0, "c64", 0.0) == (None, None)
+    assert bench.assembly_traffic(30720, 10.0, "c64", 4.0) == (None, None)
+
+
 def test_far3_fraction_matches_oracle_classification():
     v, f = synth.icosphere(2)
     m = rwg.build(v, f)
