@@ -39,13 +39,18 @@ PEAK_FP32_MFMA = 157.3      # TFLOP/s, MI355X dense FP32 matrix
 PEAK_HBM = 8000.0           # GB/s
 PEAK_FP32_VALU = 78.6       # TFLOP/s with FMA = 2 flops, packed FP32 disabled (256 CU x 64 lanes x 2.4 GHz x 2)
 VALU_LANE_SLOTS = 256 * 64 * 2.4e9   # vector-ALU lane-instructions per second
-# VALU instructions per far triangle pair in the compiled complex64 far-pair kernel
-# (far_rows_kernel<float>): 7 x 190 in the 7 x 7 quadrature loop (21 of them
-# transcendental) plus 371 outside it.
-FAR_PAIR_VALU_C64 = 7 * 190 + 371
-# triangle pairs evaluated per Z entry: the two-pass assembly evaluates the pairs with
-# source triangle q >= p only (T^2 / 2 of them; Z = U + U^T), and T^2 / N^2 = 4 / 9
-PAIRS_PER_ENTRY = 0.5 * 4.0 / 9.0
+# Algorithmic cost model of the assembly (vector ALU): 7 x 7 Green's-function
+# evaluations per triangle pair, every ordered pair counted, i.e. 49 T^2 / N^2 per Z
+# entry (21.8 on a closed surface, T = 2N/3); one evaluation costs about 46 FP32
+# issue slots (4 transcendentals at quarter rate, about 30 FMA-class operations for
+# R^2, the kernel and the moment sums) or about 110 in FP64 (no hardware sine and
+# cosine).  The bound does not credit the symmetry Z = Z^T that the kernels use.
+EVAL_SLOTS = {"c64": 46.0, "c128": 110.0}
+
+
+def assembly_alu_peak(n, t, dtype):
+    """Mentries/s at which the vector ALUs would finish the model's work."""
+    return VALU_LANE_SLOTS / (49.0 * t * t / (n * n) * EVAL_SLOTS[dtype]) / 1e6
 
 
 def log(msg):
@@ -153,7 +158,7 @@ def measured_traffic(tiles, acc64, n, nrhs, solver):
 
 ASSEMBLY_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "assembly_tiles_l5_k10_hbm_traffic.md")
 TILE_SOURCES = [os.path.join(ROOT, "paper_2310_15644_amd", "csrc", f)
-                for f in ("tile_kernels.h", "pair_kernels.h", "rows_kernels.h")]
+                for f in ("tile_kernels.h", "pair_kernels.h", "rows_kernels.h", "assemble.hip")]
 
 
 def tile_code_sha256():
@@ -168,11 +173,11 @@ def tile_code_sha256():
     return h.hexdigest()
 
 
-def assembly_traffic(n, k, dtype, far_rule):
-    """HBM bytes of one tile assembly from the committed counter summary, or None
-    when it is for another workload or the device code has changed since."""
+def _assembly_entry(n, k, dtype, far_rule):
+    """The entry of the committed assembly counter summary, or None when it is for
+    another workload or the device code has changed since."""
     if not os.path.exists(ASSEMBLY_TRAFFIC_FILE):
-        return None, None
+        return None
     kv = {}
     for line in open(ASSEMBLY_TRAFFIC_FILE):
         if line.startswith("- ") and ": " in line:
@@ -180,8 +185,23 @@ def assembly_traffic(n, k, dtype, far_rule):
             kv[key.strip()] = val.strip().strip("`")
     if (kv.get("tile_code_sha256") == tile_code_sha256()
             and kv.get("workload") == f"n={n} k={float(k)} dtype={dtype} far_rule={float(far_rule)}"):
-        return float(kv["hbm_bytes_per_assembly"]), os.path.relpath(ASSEMBLY_TRAFFIC_FILE, ROOT)
-    return None, None
+        return kv
+    return None
+
+
+def assembly_traffic(n, k, dtype, far_rule):
+    """HBM bytes of one tile assembly from the committed counter summary (and that
+    file), or (None, None)."""
+    kv = _assembly_entry(n, k, dtype, far_rule)
+    if kv is None:
+        return None, None
+    return float(kv["hbm_bytes_per_assembly"]), os.path.relpath(ASSEMBLY_TRAFFIC_FILE, ROOT)
+
+
+def assembly_valu_issue(n, k, dtype, far_rule):
+    """Fraction of the VALU issue rate the tile kernel used (SQ counters), or None."""
+    kv = _assembly_entry(n, k, dtype, far_rule)
+    return None if kv is None or "valu_issue_frac" not in kv else float(kv["valu_issue_frac"])
 
 
 def cpu_model():
@@ -898,6 +918,7 @@ def main():
     n_near, ms_near, _ = prof["near"]
     asm_ms = (ms_far + ms_near) / args.steps
     mentries = N * N / (asm_ms * 1e-3) / 1e6
+    alu_peak = assembly_alu_peak(N, m.t, args.dtype) if args.far_rule <= 0 else None
     last = rec[-1]
     F = last["F"]
     # reciprocity of the bistatic matrix S_ij = theta_j . F_i(rhat_j)
@@ -968,12 +989,11 @@ def main():
             "bound": "alu",
             "kernel": "near_blocks_kernel + tile_kernel (owner-computes tiles, Z written once)",
             "achieved": round(mentries, 1),
-            # the VALU bound is that of the 7x7 pair kernel; with the far rule on it does not apply
-            "peak": round(VALU_LANE_SLOTS / (FAR_PAIR_VALU_C64 * PAIRS_PER_ENTRY) / 1e6, 1)
-            if dt == P.C64 and args.far_rule <= 0 else None,
+            # the cost model of the 7x7 rule; with the far rule on it does not apply
+            "peak": round(alu_peak, 1) if alu_peak else None,
             "unit": "Mentries/s",
-            "frac": round(mentries / (VALU_LANE_SLOTS / (FAR_PAIR_VALU_C64 * PAIRS_PER_ENTRY) / 1e6), 4)
-            if dt == P.C64 and args.far_rule <= 0 else None,
+            "frac": round(mentries / alu_peak, 4) if alu_peak else None,
+            "model": "49 T^2/N^2 Green's-function evaluations per entry x %g issue slots" % EVAL_SLOTS[args.dtype],
             "z_write_gbs": round(N * N * (8 if dt == P.C64 else 16) / (asm_ms * 1e-3) / 1e9, 1),
         },
         "kernel_ms": {kname: [n, round(ms, 3)] for kname, (n, ms, _) in prof.items()},
@@ -991,6 +1011,7 @@ def main():
     out["assembly_roofline"]["traffic_source"] = a_src
     out["assembly_roofline"]["traffic_over_z"] = None if a_tr is None else round(a_tr / zb, 3)
     out["assembly_roofline"]["hbm_frac"] = None if a_tr is None else round(a_tr / (asm_ms * 1e-3) / 8e12, 4)
+    out["assembly_roofline"]["valu_issue_frac"] = assembly_valu_issue(N, args.k, args.dtype, args.far_rule)
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(args.level, 2048, S, args.k, args.cpu_seconds)

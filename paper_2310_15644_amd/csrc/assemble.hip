@@ -68,8 +68,8 @@ __global__ __launch_bounds__(128) void near_pairs_kernel(DevMesh m, double kr, d
     near_pair<ZT, PARTS>(m, e, kr, ki, sc, Z, Z2);
 }
 
-// pass 1, pass 2 and the mirror: the bodies live in rows_kernels.h (shared with
-// the batched assembly, which runs the same code per work item)
+// the pair rows of a chunk of test triangles (the first step of the Calderon
+// build): the bodies live in rows_kernels.h
 template <typename R, bool CK, bool UPPER>
 __global__ __launch_bounds__(FAR_BLOCK) void far_rows_kernel(DevMesh m, Tables<R> tb, R kphase, R ki, Scale sc,
                                                              typename Cplx<R>::T* __restrict__ W, int c0, int np,
@@ -101,9 +101,10 @@ __global__ __launch_bounds__(256) void near_blocks_kernel(DevMesh m, double kr, 
     near_block_one<R>(m, kr, ki, sc, NB, e);
 }
 
-// one block per tile of Z (tiles on and above the diagonal)
+// one block per tile of Z (tiles on and above the diagonal); complex64: three
+// blocks per CU (the LDS allows three), so at most 168 VGPRs
 template <typename R, bool CK>
-__global__ __launch_bounds__(256) void tile_kernel(DevMesh m, Tables<R> tb, R kphase, R ki, Scale sc,
+__global__ __launch_bounds__(256, sizeof(R) == 4 ? 3 : 1) void tile_kernel(DevMesh m, Tables<R> tb, R kphase, R ki, Scale sc,
                                                    const typename Cplx<R>::T* __restrict__ NB,
                                                    typename Cplx<R>::T* __restrict__ Z) {
     __shared__ TileLds<R> L;

@@ -181,6 +181,27 @@ __device__ __forceinline__ void tile_block(const DevMesh& m, const Tables<R>& tb
     C2 acc[NE];
 #pragma unroll
     for (int u = 0; u < NE; ++u) acc[u] = C2{R(0), R(0)};
+    // 64-wide tiles: the rows of a thread's entries (r = w + 4 u) are wave-uniform,
+    // so where their row triangles come up is read once, packed as
+    // 16 loc + 3 el (loc = 4 step + slot; -16: row past the end), and tested with
+    // scalar branches; the column side (c = lane) is per lane, read once too
+    constexpr bool UNIFORM_ROWS = TS == 64;
+    int rinfo[UNIFORM_ROWS ? NE : 1][2];
+    int cidx[2] = {0, 0};   // element of the lane's column side sb in one slot of L.val
+    if (UNIFORM_ROWS) {
+#pragma unroll
+        for (int u = 0; u < (UNIFORM_ROWS ? NE : 1); ++u) {
+            const int r = w + 4 * u;
+#pragma unroll
+            for (int sa = 0; sa < 2; ++sa)
+                rinfo[u][sa] = __builtin_amdgcn_readfirstlane(
+                    r < nr ? 16 * L.loc[0][2 * r + sa] + 3 * L.el[0][2 * r + sa] : -16);
+        }
+        // columns past the end read element 0 (valid LDS) into entries never written
+#pragma unroll
+        for (int sb = 0; sb < 2; ++sb)
+            cidx[sb] = lane < nc ? 9 * L.loc[1][2 * lane + sb] + L.el[1][2 * lane + sb] : 0;
+    }
     for (int s = 0; 4 * s < nP; ++s) {
         const int pi = 4 * s + w;
         if (pi < nP) {
@@ -209,6 +230,26 @@ __device__ __forceinline__ void tile_block(const DevMesh& m, const Tables<R>& tb
             }
         }
         __syncthreads();
+        if (UNIFORM_ROWS) {
+#pragma unroll
+            for (int u = 0; u < (UNIFORM_ROWS ? NE : 1); ++u)
+#pragma unroll
+                for (int sa = 0; sa < 2; ++sa) {
+                    const int info = rinfo[u][sa];
+                    if ((info >> 6) != s) continue;
+                    // slot (info >> 4) - 4 s: written with s so that the addresses
+                    // are formed here, not kept for every (u, sa) across the steps
+                    const int so = ((info >> 4) - 4 * s) * (NC * 9) + (info & 15);
+#pragma unroll
+                    for (int sb = 0; sb < 2; ++sb) {
+                        const C2 v = (&L.val[0][0][0])[so + cidx[sb]];
+                        acc[u].x += v.x;
+                        acc[u].y += v.y;
+                    }
+                }
+            __syncthreads();
+            continue;
+        }
 #pragma unroll
         for (int u = 0; u < NE; ++u) {
             const int e = tid + 256 * u;

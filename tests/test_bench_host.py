@@ -52,6 +52,9 @@ def test_committed_assembly_traffic_matches_the_current_tiles():
     assert src is not None and z <= t <= 3 * z
     assert bench.assembly_traffic(7680, 10.0, "c64", 0.0) == (None, None)
     assert bench.assembly_traffic(30720, 10.0, "c64", 4.0) == (None, None)
+    # the same entry's shader counters: the kernel issues VALU instructions most of its time
+    assert 0.5 < bench.assembly_valu_issue(30720, 10.0, "c64", 0.0) <= 1.0
+    assert bench.assembly_valu_issue(30720, 10.0, "c128", 0.0) is None
 
 
 def test_far3_fraction_matches_oracle_classification():
@@ -66,3 +69,14 @@ def test_far3_fraction_matches_oracle_classification():
         nfar += int(np.count_nonzero(d2 >= (2.0 * hm) ** 2))
     got = bench.far3_fraction(np.asarray(v, dtype=np.float64), np.asarray(f), 3.0)
     assert abs(got - n3 / nfar) < 1e-12
+
+
+def test_assembly_alu_bound_is_the_cost_model():
+    """The assembly's ALU bound is the algorithmic model (49 T^2/N^2 evaluations per
+    entry, 46 FP32 or 110 FP64 issue slots each, no credit for the symmetry), not a
+    count taken from the compiled kernel: about 39 Gentries/s (complex64) and 16
+    Gentries/s (complex128) at 256 CUs x 64 lanes x 2.4 GHz on the level-5 sphere."""
+    n, t = 30720, 20480
+    assert abs(bench.assembly_alu_peak(n, t, "c64") - 3.93216e13 / (49 * 4 / 9 * 46) / 1e6) < 1e-6
+    assert 39000 < bench.assembly_alu_peak(n, t, "c64") < 39500
+    assert 16000 < bench.assembly_alu_peak(n, t, "c128") < 16500
