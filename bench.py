@@ -158,7 +158,8 @@ def measured_traffic(tiles, acc64, n, nrhs, solver):
 
 ASSEMBLY_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "assembly_tiles_l5_k10_hbm_traffic.md")
 TILE_SOURCES = [os.path.join(ROOT, "paper_2310_15644_amd", "csrc", f)
-                for f in ("tile_kernels.h", "pair_kernels.h", "rows_kernels.h", "assemble.hip")]
+                for f in ("tile_kernels.h", "pair_kernels.h", "rows_kernels.h")]
+TILE_WRAPPER = os.path.join(ROOT, "paper_2310_15644_amd", "csrc", "assemble.hip")
 
 
 def tile_code_sha256():
@@ -167,8 +168,13 @@ def tile_code_sha256():
     import re
 
     h = hashlib.sha256()
-    for path in TILE_SOURCES:
-        code = re.sub(r"//[^\n]*", "", open(path).read())
+    codes = [open(path).read() for path in TILE_SOURCES]
+    # the tile kernel's own definition (its launch bounds) in assemble.hip
+    src = open(TILE_WRAPPER).read()
+    i = src.index("void tile_kernel(")
+    codes.append(src[src.rindex("template", 0, i):src.index("\n}\n", i) + 3])
+    for code in codes:
+        code = re.sub(r"//[^\n]*", "", code)
         h.update(re.sub(r"\s+", "", code).encode())
     return h.hexdigest()
 
@@ -256,8 +262,9 @@ def copy_calibration(torch):
 
 def bench_ellipsoids(args, P, synth, torch, np, dev):
     """64 seeded ellipsoids (geodesic frequency 6..16, semi-axes U[0.5, 1.5]), k = 2,
-    x-polarised plane wave along -z: one persistent assembly launch (complex64, FP32
-    far pairs) and one grouped COCG solve to rel.res 1e-6 per step."""
+    x-polarised plane wave along -z: the near-pair blocks of all meshes in one launch,
+    their tiles of Z in one persistent launch (complex64, FP32 far pairs), and one
+    grouped COCG solve to rel.res 1e-6 per step."""
     batch = synth.ellipsoid_batch(64, seed=0)
     meshes = [P.Mesh(v, f).upload(dev) for v, f, _, _ in batch]
     ns = np.array([m.n for m in meshes])
@@ -293,7 +300,7 @@ def bench_ellipsoids(args, P, synth, torch, np, dev):
     asm_ms = (prof["far"][1] + prof["near"][1]) / args.steps   # tiles + near blocks
     st = rec[-1]["st"]
     out = {
-        "metric": "assembly Mentries/s (persistent work-queue launches, 64 uneven meshes); time-to-solve @ rel.res 1e-6",
+        "metric": "assembly Mentries/s (one persistent tile launch over 64 uneven meshes); time-to-solve @ rel.res 1e-6",
         "value": round(float((ns ** 2).sum()) / (asm_ms * 1e-3) / 1e6, 1),
         "unit": "Mentries/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * wall / args.steps, 3),

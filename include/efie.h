@@ -509,15 +509,18 @@ int efie_solve_cfie(const void* Z, const void* P, const void* M, const void* Q, 
  * elements of Zcat starting at sum_{j<i} N_j^2 (row-major, as efie_assemble);
  * vectors occupy N_i consecutive complex128 elements of Vcat / Jcat starting at
  * sum_{j<i} N_j.
- * efie_batch_create: meshes must stay alive and uploaded.  efie_batch_sizes:
- *   table_bytes for efie_batch_upload, ws_bytes for assemble/solve (with every
- *   mesh's near-pair blocks), total Z and vector elements, and the number of
- *   assembly launches (two per mesh).
- * efie_batch_assemble: k host array (nmesh, real, > 0); every mesh by the tile
- *   assembly of efie_assemble_ws (its near blocks, then its tiles of Z), the meshes
- *   in decreasing cost dealt to four streams of the device forked from and joined
- *   back into `stream`: every Z bit-identical to efie_assemble_ws of its mesh, no
- *   atomics.  Synchronises.
+ * efie_batch_create: meshes must stay alive.  efie_batch_sizes: table_bytes for
+ *   efie_batch_upload (the Z and vector offsets and every mesh table concatenated
+ *   over the meshes), ws_bytes for assemble/solve (with every mesh's near-pair
+ *   blocks), total Z and vector elements, and the work items of the persistent
+ *   assembly launch (the complex64 tiles of all meshes).
+ * efie_batch_upload: copies the meshes' tables as they are at that call; the
+ *   far-rule ratio of each mesh is read at each assemble.
+ * efie_batch_assemble: k host array (nmesh, real, > 0); the tile assembly of
+ *   efie_assemble_ws for every mesh in two launches: the near-pair blocks of all
+ *   meshes, then one persistent launch over the tiles of all meshes' Z (a block per
+ *   resident slot, tile t to block t mod grid): every Z bit-identical to
+ *   efie_assemble_ws of its mesh, no atomics.  Synchronises.
  * efie_batch_solve: COCG per mesh (FP64 vectors), one grouped GEMV launch (FP64
  *   accumulation) and one grouped update launch per iteration; stats host nmesh.
  *   Per-mesh failures give EFIE_NOT_CONVERGED with the status in stats.

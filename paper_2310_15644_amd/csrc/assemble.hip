@@ -63,9 +63,11 @@ __global__ __launch_bounds__(FAR_BLOCK) void far_pairs_kernel(DevMesh m, Tables<
 template <typename ZT, bool PARTS>
 __global__ __launch_bounds__(128) void near_pairs_kernel(DevMesh m, double kr, double ki, Scale sc, void* Z,
                                                          void* Z2) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    // a group of NEAR_G lanes per ordered near pair
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int e = t / NEAR_G;
     if (e >= m.n_near) return;
-    near_pair<ZT, PARTS>(m, e, kr, ki, sc, Z, Z2);
+    near_pair<ZT, PARTS>(m, e, t % NEAR_G, kr, ki, sc, Z, Z2);
 }
 
 // the pair rows of a chunk of test triangles (the first step of the Calderon
@@ -87,18 +89,22 @@ template <typename R>
 __global__ __launch_bounds__(128) void near_rows_kernel(DevMesh m, double kr, double ki, Scale sc,
                                                         typename Cplx<R>::T* __restrict__ W, int c0, int c1, int e0,
                                                         int e1, int upper) {
-    const int e = e0 + int(blockIdx.x * blockDim.x + threadIdx.x);
-    if (e >= e1) return;
-    near_rows_one<R>(m, kr, ki, sc, W, c0, c1, e, upper);
+    // [e0, e1): ordered near pairs, or with upper positions in the list of the
+    // pairs with q >= p
+    const int t = int(blockIdx.x * blockDim.x + threadIdx.x);
+    const int x = e0 + t / NEAR_G;
+    if (x >= e1) return;
+    near_rows_one<R>(m, kr, ki, sc, W, c0, c1, upper ? m.near_up[x] : x, t % NEAR_G, upper);
 }
 
 // the FP64 blocks of every ordered near pair, in the precision of Z
 template <typename R>
 __global__ __launch_bounds__(256) void near_blocks_kernel(DevMesh m, double kr, double ki, Scale sc,
                                                           typename Cplx<R>::T* __restrict__ NB) {
-    const int e = int(blockIdx.x) * 256 + int(threadIdx.x);
-    if (e >= m.n_near) return;
-    near_block_one<R>(m, kr, ki, sc, NB, e);
+    const int t = int(blockIdx.x) * 256 + int(threadIdx.x);
+    const int u = t / NEAR_G;   // the pairs with q >= p only
+    if (u >= m.n_up) return;
+    near_block_one<R>(m, kr, ki, sc, NB, m.near_up[u], t % NEAR_G);
 }
 
 // one block per tile of Z (tiles on and above the diagonal); complex64: three
@@ -191,39 +197,40 @@ static void near_beside_far(hipStream_t s, NearF near, FarF far) {
     EFIE_HIP_CHECK(hipStreamWaitEvent(s, x.join, 0));
 }
 
-// Z by tiles: the near blocks into the workspace, then one block per tile
-// (prof: bracket the two launches for efie_prof_read)
+// Z by tiles: the near blocks into the workspace, then one block per tile (each
+// launch bracketed for efie_prof_read)
 template <typename R>
 void launch_tiles(const DevMesh& m, double kr, double ki, const Scale& sc, void* Z, void* ws, size_t ws_bytes,
-                  hipStream_t s, bool prof = true) {
+                  hipStream_t s) {
     using C2 = typename Cplx<R>::T;
     EFIE_REQUIRE(ws_bytes >= size_t(m.n_near) * 9 * sizeof(C2), EFIE_ERR_ARG,
                  "assemble_ws: workspace smaller than the near-pair blocks");
     const long long ntiles = tile_count<R>(m.N);
     EFIE_REQUIRE(ntiles < (1ll << 31), EFIE_ERR_ARG, "assemble_ws: N too large");
     C2* NB = static_cast<C2*>(ws);
-    if (m.n_near > 0) {
-        if (prof) prof_begin(PROF_NEAR, s);
-        hipLaunchKernelGGL(near_blocks_kernel<R>, dim3(unsigned((m.n_near + 255) / 256)), dim3(256), 0, s, m, kr, ki,
-                           sc, NB);
-        if (prof) prof_end(PROF_NEAR, s);
+    if (m.n_up > 0) {
+        prof_begin(PROF_NEAR, s);
+        hipLaunchKernelGGL(near_blocks_kernel<R>, dim3(unsigned((int64_t(m.n_up) * NEAR_G + 255) / 256)), dim3(256),
+                           0, s, m, kr, ki, sc, NB);
+        prof_end(PROF_NEAR, s);
     }
     const R kphase = std::is_same<R, float>::value ? R(kr / (2.0 * PI)) : R(kr);
-    if (prof) prof_begin(PROF_FAR, s);
+    prof_begin(PROF_FAR, s);
     if (ki != 0.0)
         hipLaunchKernelGGL((tile_kernel<R, true>), dim3(unsigned(ntiles)), dim3(256), 0, s, m, tables_of<R>(m),
                            kphase, R(ki), sc, NB, static_cast<C2*>(Z));
     else
         hipLaunchKernelGGL((tile_kernel<R, false>), dim3(unsigned(ntiles)), dim3(256), 0, s, m, tables_of<R>(m),
                            kphase, R(ki), sc, NB, static_cast<C2*>(Z));
-    if (prof) prof_end(PROF_FAR, s);
+    prof_end(PROF_FAR, s);
 }
 
 template <typename ZT, bool PARTS>
 void launch_near(const DevMesh& m, double kr, double ki, const Scale& sc, void* Z, void* Z2, hipStream_t s) {
     if (m.n_near == 0) return;
     prof_begin(PROF_NEAR, s);
-    hipLaunchKernelGGL((near_pairs_kernel<ZT, PARTS>), dim3((m.n_near + 127) / 128), dim3(128), 0, s, m, kr, ki,
+    hipLaunchKernelGGL((near_pairs_kernel<ZT, PARTS>), dim3(unsigned((int64_t(m.n_near) * NEAR_G + 127) / 128)),
+                       dim3(128), 0, s, m, kr, ki,
                        sc, Z, Z2);
     prof_end(PROF_NEAR, s);
 }
@@ -240,7 +247,8 @@ void launch_near(const DevMesh& m, double kr, double ki, const Scale& sc, void* 
 // split Z = U + U^T + D of the symmetric operator); the entries of triangles
 // q < p are not written, and the reader must skip them.
 void pair_rows_chunk(const DevMesh& m, double kr, double ki, double eta, int dtype, void* W, int c0, int c1,
-                     const std::vector<int32_t>& near_p, bool upper, hipStream_t s) {
+                     const std::vector<int32_t>& near_p, const std::vector<int32_t>& near_up, bool upper,
+                     hipStream_t s) {
     const Scale sc = operator_scale(kr, ki, eta);
     if (dtype == EFIE_C64) require_fp32_phase(m.diam, kr, "pair rows");
     const int nqblk = (m.T + FAR_BLOCK - 1) / FAR_BLOCK;
@@ -248,8 +256,12 @@ void pair_rows_chunk(const DevMesh& m, double kr, double ki, double eta, int dty
     EFIE_REQUIRE(np >= 1 && size_t(np) * nqblk < (size_t(1) << 31), EFIE_ERR_ARG, "pair_rows_chunk: bad chunk");
     const bool ck = ki != 0.0;
     const dim3 g1(unsigned(size_t((np + FAR_PB - 1) / FAR_PB) * nqblk));
-    const int e0 = int(std::lower_bound(near_p.begin(), near_p.end(), c0) - near_p.begin());
-    const int e1 = int(std::lower_bound(near_p.begin(), near_p.end(), c1) - near_p.begin());
+    int e0 = int(std::lower_bound(near_p.begin(), near_p.end(), c0) - near_p.begin());
+    int e1 = int(std::lower_bound(near_p.begin(), near_p.end(), c1) - near_p.begin());
+    if (upper) {   // the chunk's pairs with q >= p: a run of the increasing list near_up
+        e0 = int(std::lower_bound(near_up.begin(), near_up.end(), e0) - near_up.begin());
+        e1 = int(std::lower_bound(near_up.begin(), near_up.end(), e1) - near_up.begin());
+    }
     auto run = [&](auto tag) {
         using R = decltype(tag);
         using C2 = typename Cplx<R>::T;
@@ -270,7 +282,8 @@ void pair_rows_chunk(const DevMesh& m, double kr, double ki, double eta, int dty
                                    kphase, R(ki), sc, w, c0, np, nqblk);
         };
         auto near = [&](hipStream_t st) {
-            hipLaunchKernelGGL((near_rows_kernel<R>), dim3((e1 - e0 + 127) / 128), dim3(128), 0, st, m, kr, ki, sc,
+            hipLaunchKernelGGL((near_rows_kernel<R>), dim3(unsigned((int64_t(e1 - e0) * NEAR_G + 127) / 128)), dim3(128),
+                               0, st, m, kr, ki, sc,
                                w, c0, c1, e0, e1, int(upper));
         };
         if (e1 <= e0) {
@@ -328,16 +341,6 @@ static void assemble_impl(const DevMesh& m, double kr, double ki, double eta, in
 void assemble_into(const DevMesh& m, double kr, double ki, double eta, int dtype, void* Z, void* Z2, int parts,
                    hipStream_t s) {
     assemble_impl(m, kr, ki, eta, dtype, Z, Z2, parts, s, nullptr, 0, nullptr);
-}
-
-// the tile assembly of one mesh, not timed on its own (the batch times its whole run)
-void assemble_tiles(const DevMesh& m, double kr, double ki, double eta, int dtype, void* Z, void* NB, size_t nb_bytes,
-                    hipStream_t s) {
-    if (dtype == EFIE_C64) require_fp32_phase(m.diam, kr, "assemble");
-    const Scale sc = operator_scale(kr, ki, eta);
-    if (dtype == EFIE_C128) launch_tiles<double>(m, kr, ki, sc, Z, NB, nb_bytes, s, false);
-    else launch_tiles<float>(m, kr, ki, sc, Z, NB, nb_bytes, s, false);
-    EFIE_HIP_CHECK(hipGetLastError());
 }
 
 }  // namespace efie

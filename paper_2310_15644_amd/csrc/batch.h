@@ -20,6 +20,11 @@ struct efie_batch_s {
     int64_t z_total = 0, v_total = 0;
     void* dev = nullptr;                // caller-owned device blob
     size_t off_zoff = 0, off_voff = 0;
+    // the meshes' tables concatenated table by table in the blob (processing
+    // order): cat points at them; per mesh (caller order) the triangles, RWGs,
+    // ordered near pairs and those with q >= p of the meshes before it
+    efie::DevMesh cat{};
+    std::vector<int64_t> toff, noff, eoff, uoff;
 };
 
 namespace efie {

@@ -1,16 +1,17 @@
-// Many uneven meshes at once: the tile assembly of every mesh and a grouped
-// Krylov solve.
+// Many uneven meshes at once: the tile assembly of every mesh in one persistent
+// launch, and a grouped Krylov solve.
 //
-// Assembly.  Every mesh is assembled by the single-mesh tile kernels
-// (tile_kernels.h: its near blocks, then its tiles of Z written once), the meshes
-// in order of decreasing cost dealt round-robin to four streams of the device
-// forked from and joined back into the caller's stream, so that the small meshes'
-// launches run beside each other.  The kernels and their arguments are those of
-// efie_assemble_ws, so every batched matrix is bit-identical to its single-mesh
-// assembly; Z is written once and no atomics touch it.  (A persistent work-queue
-// launch over all meshes' tiles reads each mesh's tables through pointers loaded
-// from device memory, generic loads that cost the tile code a third of its
-// occupancy; the kernel-argument launches keep the single-mesh code as it is.)
+// Assembly.  At upload the meshes' tables are concatenated table by table into the
+// batch's device blob (the meshes in order of decreasing cost).  One launch
+// computes the near-pair blocks of every mesh (a block of 256 ordered near pairs
+// belongs to one mesh), then one persistent launch (as many blocks as fit on the
+// device at once) walks the tiles of all meshes' matrices: tile t goes to block
+// t mod grid, which finds its mesh by binary search over the tile offsets and runs
+// the single-mesh tile code (tile_kernels.h) on a view of that mesh's tables.  The
+// view's pointers are the kernel argument's concatenated bases plus the mesh's
+// element offsets, so the tables are read with global (not generic) loads, as in
+// the single-mesh kernel.  Every batched matrix is bit-identical to its single-mesh
+// assembly; Z is written once and no atomics touch it.
 //
 // Solve.  One right-hand side per mesh; Z of the meshes concatenated
 // (Z_i at element offset sum_{j<i} N_j^2), vectors concatenated (offset
@@ -20,7 +21,6 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <mutex>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -29,43 +29,90 @@
 
 #include "batch.h"
 #include "linalg.h"
+#include "tile_kernels.h"
 
 namespace efie {
 
-void assemble_tiles(const DevMesh& m, double kr, double ki, double eta, int dtype, void* Z, void* NB, size_t nb_bytes,
-                    hipStream_t s);
-
-struct BatchMeshDev {
-    DevMesh m;
-    int64_t zoff;     // element offset of this mesh's Z
-    int64_t pad[3];
+// one mesh of one batched assembly: where its tables, near blocks, Z and tiles
+// start (processing order)
+struct BatchItem {
+    int32_t T, N, n_near, pad;
+    int64_t toff, noff, eoff;   // triangles, RWGs and ordered near pairs of the meshes before it
+    int64_t uoff;               // their near pairs with q >= p
+    int32_t n_up, pad2;
+    int64_t zoff, nboff;        // elements of Z and of the near blocks before it (in the precision of Z)
+    int64_t tile0, nblk0;       // its first tile and its first block of the near-block launch
+    double kr, nf, far3;
+    Scale sc;
 };
 
-// the streams of the batched assembly: four per device, created on first use and
-// kept until the process ends; host threads take turns
-constexpr int BATCH_STREAMS = 4;
-struct BatchStreams {
-    hipStream_t s[BATCH_STREAMS] = {};
-    hipEvent_t fork = nullptr, join[BATCH_STREAMS] = {};
-    std::mutex mu;
-};
-static BatchStreams& batch_streams() {
-    constexpr int MAXDEV = 64;
-    static BatchStreams bs[MAXDEV];
-    static std::mutex create_mu;
-    int dev = 0;
-    EFIE_HIP_CHECK(hipGetDevice(&dev));
-    EFIE_REQUIRE(dev >= 0 && dev < MAXDEV, EFIE_ERR_STATE, "batch streams: device index out of range");
-    BatchStreams& x = bs[dev];
-    std::lock_guard<std::mutex> g(create_mu);
-    if (!x.fork) {
-        for (int i = 0; i < BATCH_STREAMS; ++i) {
-            EFIE_HIP_CHECK(hipStreamCreateWithFlags(&x.s[i], hipStreamNonBlocking));
-            EFIE_HIP_CHECK(hipEventCreateWithFlags(&x.join[i], hipEventDisableTiming));
-        }
-        EFIE_HIP_CHECK(hipEventCreateWithFlags(&x.fork, hipEventDisableTiming));
+// the mesh of item `it` as the single-mesh code sees it: the concatenated tables
+// offset to its first element
+__device__ __forceinline__ DevMesh mesh_view(const DevMesh& c, const BatchItem& it) {
+    DevMesh v = c;
+    const int64_t t = it.toff, n = it.noff, e = it.eoff;
+    v.T = it.T;
+    v.N = it.N;
+    v.n_near = it.n_near;
+    v.nf = it.nf;
+    v.far3 = it.far3;
+    v.cx = c.cx + t; v.cy = c.cy + t; v.cz = c.cz + t;
+    v.qx = c.qx + 7 * t; v.qy = c.qy + 7 * t; v.qz = c.qz + 7 * t; v.qw = c.qw + 7 * t;
+    v.vx = c.vx + 3 * t; v.vy = c.vy + 3 * t; v.vz = c.vz + 3 * t; v.cf = c.cf + 3 * t; v.dv = c.dv + 3 * t;
+    v.nx = c.nx + t; v.ny = c.ny + t; v.nz = c.nz + t; v.hm = c.hm + t;
+    v.qx32 = c.qx32 + 7 * t; v.qy32 = c.qy32 + 7 * t; v.qz32 = c.qz32 + 7 * t; v.qw32 = c.qw32 + 7 * t;
+    v.vx32 = c.vx32 + 3 * t; v.vy32 = c.vy32 + 3 * t; v.vz32 = c.vz32 + 3 * t;
+    v.cf32 = c.cf32 + 3 * t; v.dv32 = c.dv32 + 3 * t;
+    v.te = c.te + 3 * t; v.tv = c.tv + 3 * t;
+    v.near_p = c.near_p + e; v.near_q = c.near_q + e;
+    v.n_up = it.n_up;
+    v.near_up = c.near_up + it.uoff;
+    v.et = c.et + 2 * n; v.el = c.el + 2 * n;
+    v.q3x = c.q3x + 3 * t; v.q3y = c.q3y + 3 * t; v.q3z = c.q3z + 3 * t; v.q3w = c.q3w + 3 * t;
+    v.q3x32 = c.q3x32 + 3 * t; v.q3y32 = c.q3y32 + 3 * t; v.q3z32 = c.q3z32 + 3 * t; v.q3w32 = c.q3w32 + 3 * t;
+    return v;
+}
+
+// the last item whose 64-bit field f is <= x (the items in increasing f)
+template <int64_t BatchItem::*F>
+__device__ __forceinline__ int item_of(const BatchItem* __restrict__ items, int nm, int64_t x) {
+    int lo = 0, hi = nm;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (items[mid].*F <= x) lo = mid;
+        else hi = mid;
     }
-    return x;
+    return lo;
+}
+
+// the near-pair blocks of every mesh, a group of NEAR_G lanes per pair: block b
+// (NEAR_PER_BLOCK pairs) belongs to one mesh (each mesh's pairs padded to whole
+// blocks)
+constexpr int NEAR_PER_BLOCK = 256 / NEAR_G;
+template <typename R>
+__global__ __launch_bounds__(256) void batch_near_kernel(DevMesh cat, const BatchItem* __restrict__ items, int nm,
+                                                         typename Cplx<R>::T* __restrict__ NB) {
+    const int r = item_of<&BatchItem::nblk0>(items, nm, int64_t(blockIdx.x));
+    const BatchItem& it = items[r];
+    const int u = int(int64_t(blockIdx.x) - it.nblk0) * NEAR_PER_BLOCK + int(threadIdx.x) / NEAR_G;
+    if (u >= it.n_up) return;   // the pairs with q >= p only
+    const DevMesh v = mesh_view(cat, it);
+    near_block_one<R>(v, it.kr, 0.0, it.sc, NB + it.nboff, v.near_up[u], int(threadIdx.x) % NEAR_G);
+}
+
+// the tiles of every mesh's Z: persistent, tile t by block t mod gridDim.x
+template <typename R>
+__global__ __launch_bounds__(256, sizeof(R) == 4 ? 3 : 1) void batch_tiles_kernel(
+    DevMesh cat, const BatchItem* __restrict__ items, int nm, int64_t ntiles,
+    const typename Cplx<R>::T* __restrict__ NB, typename Cplx<R>::T* __restrict__ Z) {
+    __shared__ TileLds<R> L;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int r = item_of<&BatchItem::tile0>(items, nm, t);
+        const BatchItem& it = items[r];
+        const DevMesh v = mesh_view(cat, it);
+        const R kphase = std::is_same<R, float>::value ? R(it.kr / (2.0 * PI)) : R(it.kr);
+        tile_block<R, false>(v, tables_of<R>(v), kphase, R(0), it.sc, NB + it.nboff, Z + it.zoff, t - it.tile0, L);
+    }
 }
 
 // rows of all meshes: y[voff_s + i] = sum_k Z_s[i][k] x[voff_s + k] for active meshes
@@ -261,6 +308,7 @@ size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct BatchWs {
     char* NB;                      // near blocks of every mesh
+    BatchItem* items;              // the assembly's per-mesh items (processing order)
     double2 *r, *p, *q, *y;
     BatchCol* cols;
     int* active;
@@ -277,6 +325,18 @@ std::vector<size_t> batch_nb_offsets(const efie_batch_s& B) {
     return off;
 }
 
+// the batch's device tables: Z and vector offsets, then each mesh table
+// concatenated over the meshes (256-aligned per table)
+size_t batch_table_bytes(const efie_batch_s& B) {
+    const size_t nm = B.meshes.size();
+    size_t off = a256(8 * nm) + a256(8 * (nm + 1));
+    for (int t = 0; t < table_count(); ++t) {
+        for (size_t i = 0; i < nm; ++i) off += table_bytes_of(*B.meshes[i], t);
+        off = a256(off);
+    }
+    return off;
+}
+
 size_t batch_ws_layout(const efie_batch_s& B, BatchWs* w, char* base) {
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -288,6 +348,7 @@ size_t batch_ws_layout(const efie_batch_s& B, BatchWs* w, char* base) {
     const size_t nm = B.meshes.size();
     const size_t vec = size_t(B.v_total) * 16;
     x.NB = take(batch_nb_offsets(B)[nm]);
+    x.items = (BatchItem*)take(sizeof(BatchItem) * nm);
     x.r = (double2*)take(vec);
     x.p = (double2*)take(vec);
     x.q = (double2*)take(vec);
@@ -322,6 +383,24 @@ void batch_prepare(efie_batch_s& B) {
     B.order.resize(size_t(nm));
     std::iota(B.order.begin(), B.order.end(), 0);
     std::stable_sort(B.order.begin(), B.order.end(), [&](int a, int b) { return items[size_t(a)] > items[size_t(b)]; });
+    // the concatenated tables follow the processing order
+    B.toff.assign(size_t(nm), 0);
+    B.noff.assign(size_t(nm), 0);
+    B.eoff.assign(size_t(nm), 0);
+    B.uoff.assign(size_t(nm), 0);
+    int64_t t = 0, n = 0, e = 0, u = 0;
+    for (int r = 0; r < nm; ++r) {
+        const int i = B.order[size_t(r)];
+        const efie_mesh_s& m = *B.meshes[size_t(i)];
+        B.toff[size_t(i)] = t;
+        B.noff[size_t(i)] = n;
+        B.eoff[size_t(i)] = e;
+        B.uoff[size_t(i)] = u;
+        u += int64_t(m.near_up.size());
+        t += m.T;
+        n += m.N;
+        e += int64_t(m.near_p.size());
+    }
 }
 
 }  // namespace efie
@@ -352,12 +431,14 @@ extern "C" int efie_batch_sizes(efie_batch b, size_t* table_bytes, size_t* ws_by
     return guarded([&]() {
         EFIE_REQUIRE(b != nullptr, EFIE_ERR_ARG, "batch_sizes: null");
         const size_t nm = b->meshes.size();
-        if (table_bytes) *table_bytes = a256(sizeof(BatchMeshDev) * nm) + a256(8 * nm) + a256(8 * (nm + 1));
+        if (table_bytes) *table_bytes = batch_table_bytes(*b);
         if (ws_bytes) *ws_bytes = batch_ws_layout(*b, nullptr, nullptr);
         if (z_elems) *z_elems = b->z_total;
         if (v_elems) *v_elems = b->v_total;
-        if (items) {   // launches of the assembly: near blocks and tiles per mesh
-            *items = int64_t(2 * nm);
+        if (items) {   // work items of the persistent assembly launch: complex64 tiles of all meshes
+            int64_t t = 0;
+            for (size_t i = 0; i < nm; ++i) t += tile_count<float>(int(b->meshes[i]->N));
+            *items = t;
         }
         return int(EFIE_OK);
     });
@@ -367,26 +448,37 @@ extern "C" int efie_batch_upload(efie_batch b, void* dev, size_t bytes, hipStrea
     return guarded([&]() {
         EFIE_REQUIRE(b && dev, EFIE_ERR_ARG, "batch_upload: null argument");
         const size_t nm = b->meshes.size();
-        const size_t need = a256(sizeof(BatchMeshDev) * nm) + a256(8 * nm) + a256(8 * (nm + 1));
+        const size_t need = batch_table_bytes(*b);
         EFIE_REQUIRE(bytes >= need, EFIE_ERR_ARG, "batch_upload: buffer too small");
         EFIE_REQUIRE((reinterpret_cast<uintptr_t>(dev) & 255) == 0, EFIE_ERR_ARG, "batch_upload: not 256-aligned");
+        // per mesh (caller order) the offsets of its Z and of its vectors, read by
+        // the grouped solve; then every table of the meshes concatenated (processing
+        // order), read by the assembly
         std::vector<char> blob(need, 0);
-        auto* bmd = reinterpret_cast<BatchMeshDev*>(blob.data());
-        for (size_t r = 0; r < nm; ++r) {
-            const int i = b->order[r];
-            const efie_mesh_s& m = *b->meshes[size_t(i)];
-            EFIE_REQUIRE(m.dev != nullptr, EFIE_ERR_STATE, "batch_upload: a mesh is not uploaded");
-            BatchMeshDev d{};
-            d.m = m.dm;
-            d.zoff = b->zoff[size_t(i)];
-            bmd[r] = d;
-        }
-        size_t off = a256(sizeof(BatchMeshDev) * nm);
+        size_t off = 0;
         std::memcpy(blob.data() + off, b->zoff.data(), 8 * nm);
         b->off_zoff = off;
         off += a256(8 * nm);
         std::memcpy(blob.data() + off, b->voff.data(), 8 * (nm + 1));
         b->off_voff = off;
+        off += a256(8 * (nm + 1));
+        const int nt = table_count();
+        std::vector<size_t> toffs(size_t(nt), 0);
+        for (int t = 0; t < nt; ++t) {
+            toffs[size_t(t)] = off;
+            for (size_t r = 0; r < nm; ++r) {
+                const efie_mesh_s& m = *b->meshes[size_t(b->order[r])];
+                const size_t nb = table_bytes_of(m, t);
+                EFIE_REQUIRE(m.offs.size() == size_t(nt) && m.offs[size_t(t)] + nb <= m.host_blob.size(),
+                             EFIE_ERR_STATE, "batch_upload: mesh tables inconsistent");
+                if (nb) std::memcpy(blob.data() + off, m.host_blob.data() + m.offs[size_t(t)], nb);
+                off += nb;
+            }
+            off = a256(off);
+        }
+        EFIE_REQUIRE(off == need, EFIE_ERR_STATE, "batch_upload: table size mismatch");
+        b->cat = DevMesh{};
+        bind_pointers(b->cat, dev, toffs);
         EFIE_HIP_CHECK(hipMemcpyAsync(dev, blob.data(), need, hipMemcpyHostToDevice, stream));
         EFIE_HIP_CHECK(hipStreamSynchronize(stream));
         b->dev = dev;
@@ -413,23 +505,55 @@ extern "C" int efie_batch_assemble(efie_batch b, const double* k, double eta, in
         }
         const std::vector<size_t> nbo = batch_nb_offsets(*b);
         const size_t esz = dtype == EFIE_C128 ? 16 : 8;
-        BatchStreams& bs = batch_streams();
-        std::lock_guard<std::mutex> g(bs.mu);
-        prof_begin(PROF_FAR, stream);
-        EFIE_HIP_CHECK(hipEventRecord(bs.fork, stream));
-        for (int i = 0; i < BATCH_STREAMS; ++i) EFIE_HIP_CHECK(hipStreamWaitEvent(bs.s[i], bs.fork, 0));
+        std::vector<BatchItem> items(nm);
+        int64_t tile = 0, nblk = 0;
         for (size_t r = 0; r < nm; ++r) {
             const int i = b->order[r];
             const efie_mesh_s& m = *b->meshes[size_t(i)];
-            char* z = static_cast<char*>(Zcat) + size_t(b->zoff[size_t(i)]) * esz;
-            assemble_tiles(m.dm, k[i], 0.0, eta, dtype, z, w.NB + nbo[size_t(i)], nbo[size_t(i) + 1] - nbo[size_t(i)],
-                           bs.s[r % BATCH_STREAMS]);
+            BatchItem& it = items[r];
+            it.T = int32_t(m.T);
+            it.N = int32_t(m.N);
+            it.n_near = int32_t(m.near_p.size());
+            it.toff = b->toff[size_t(i)];
+            it.noff = b->noff[size_t(i)];
+            it.eoff = b->eoff[size_t(i)];
+            it.uoff = b->uoff[size_t(i)];
+            it.n_up = int32_t(m.near_up.size());
+            it.zoff = b->zoff[size_t(i)];
+            it.nboff = int64_t(nbo[size_t(i)] / esz);
+            it.tile0 = tile;
+            it.nblk0 = nblk;
+            it.kr = k[i];
+            it.nf = m.near_factor;
+            it.far3 = m.far3;
+            it.sc = operator_scale(k[i], 0.0, eta);
+            tile += dtype == EFIE_C64 ? tile_count<float>(int(m.N)) : tile_count<double>(int(m.N));
+            nblk += (int64_t(m.near_up.size()) + NEAR_PER_BLOCK - 1) / NEAR_PER_BLOCK;
         }
-        for (int i = 0; i < BATCH_STREAMS; ++i) {
-            EFIE_HIP_CHECK(hipEventRecord(bs.join[i], bs.s[i]));
-            EFIE_HIP_CHECK(hipStreamWaitEvent(stream, bs.join[i], 0));
-        }
-        prof_end(PROF_FAR, stream);
+        EFIE_REQUIRE(nblk < (int64_t(1) << 31), EFIE_ERR_ARG, "batch_assemble: too many near pairs");
+        EFIE_HIP_CHECK(hipMemcpyAsync(w.items, items.data(), sizeof(BatchItem) * nm, hipMemcpyHostToDevice, stream));
+        int dev = 0, ncu = 0, per_cu = 0;
+        EFIE_HIP_CHECK(hipGetDevice(&dev));
+        EFIE_HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+        auto run = [&](auto tag) {
+            using R = decltype(tag);
+            using C2 = typename Cplx<R>::T;
+            C2* NB = reinterpret_cast<C2*>(w.NB);
+            if (nblk > 0) {
+                prof_begin(PROF_NEAR, stream);
+                hipLaunchKernelGGL(batch_near_kernel<R>, dim3(unsigned(nblk)), dim3(256), 0, stream, b->cat, w.items,
+                                   int(nm), NB);
+                prof_end(PROF_NEAR, stream);
+            }
+            EFIE_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_tiles_kernel<R>, 256, 0));
+            const int64_t grid = std::min<int64_t>(tile, int64_t(std::max(1, per_cu)) * std::max(1, ncu));
+            prof_begin(PROF_FAR, stream);
+            hipLaunchKernelGGL(batch_tiles_kernel<R>, dim3(unsigned(grid)), dim3(256), 0, stream, b->cat, w.items,
+                               int(nm), tile, NB, static_cast<C2*>(Zcat));
+            prof_end(PROF_FAR, stream);
+        };
+        if (dtype == EFIE_C64) run(float{});
+        else run(double{});
         EFIE_HIP_CHECK(hipGetLastError());
         EFIE_HIP_CHECK(hipStreamSynchronize(stream));
         return int(EFIE_OK);

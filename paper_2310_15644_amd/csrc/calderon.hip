@@ -30,7 +30,8 @@
 namespace efie {
 
 void pair_rows_chunk(const DevMesh& m, double kr, double ki, double eta, int dtype, void* W, int c0, int c1,
-                     const std::vector<int32_t>& near_p, bool upper, hipStream_t s);
+                     const std::vector<int32_t>& near_p, const std::vector<int32_t>& near_up, bool upper,
+                     hipStream_t s);
 bool verbose();
 double now_s();
 
@@ -966,7 +967,8 @@ int efie_calderon_assemble_ex(efie_calderon c, double kt_re, double kt_im, doubl
         c->bary.dm.far3 = f3;
         for (int ch = 0; ch < pl.nchunks; ++ch) {
             const int c0 = ch * pl.chunk, c1 = std::min(Tb, c0 + pl.chunk), np = c1 - c0;
-            pair_rows_chunk(c->bary.dm, kt_re, kt_im, eta, bary_dtype, w.W, c0, c1, c->bary.near_p, true, stream);
+            pair_rows_chunk(c->bary.dm, kt_re, kt_im, eta, bary_dtype, w.W, c0, c1, c->bary.near_p, c->bary.near_up,
+                            true, stream);
             const int nr = 3 * np;
             if (bary_dtype == EFIE_C64)
                 hipLaunchKernelGGL((bc_src_kernel<float2, BC_RRL32>),

@@ -59,6 +59,7 @@ constexpr int NQ = 7;   // points of the triangle rule
 struct DevMesh {
     int32_t T, N;               // triangles, RWGs
     int32_t n_near;             // ordered near pairs
+    int32_t n_up;               // of them with q >= p
     double nf;                  // near factor: distance rule of near_by_distance
     double diam;                // bounding-box diagonal of the vertices (host use: FP32 phase range)
     // FP64.  Positions are stored relative to the triangle centroid (cx, cy, cz):
@@ -83,6 +84,7 @@ struct DevMesh {
     const double *q3x, *q3y, *q3z, *q3w;       // its point offsets and weights*area [3][T]
     const float *q3x32, *q3y32, *q3z32, *q3w32;
     double far3;
+    const int32_t* near_up;              // indices e of the ordered near pairs with q >= p, increasing
 };
 
 }  // namespace efie
@@ -99,6 +101,7 @@ struct efie_mesh_s {
     std::vector<int32_t> tri_edge, tri_sign; // T*3
     std::vector<double> area, normal, centroid, hmax;
     std::vector<int32_t> near_p, near_q;     // ordered near pairs, sorted by p then q
+    std::vector<int32_t> near_up;            // indices of the pairs with q >= p
     // device tables (caller-owned blob)
     void* dev = nullptr;
     size_t dev_bytes = 0;
@@ -144,6 +147,10 @@ void build_mesh(efie_mesh_s& m, const double* xyz, int64_t nv, const int32_t* tr
                 double near_factor);
 void pack_tables(efie_mesh_s& m);            // fills host_blob, offs, returns size via host_blob.size()
 void bind_tables(efie_mesh_s& m, void* dev); // sets m.dm pointers into dev
+// the tables of pack_tables one by one (the batched assembly concatenates them)
+int table_count();
+size_t table_bytes_of(const efie_mesh_s& m, int t);             // bytes of table t of m
+void bind_pointers(DevMesh& d, const void* base, const std::vector<size_t>& offs);  // table t at base + offs[t]
 // Radon's 7-point degree-5 triangle rule: barycentric points and weights (sum 1),
 // in the order the quadrature tables use.
 void radon7(double bary[7][3], double w[7]);

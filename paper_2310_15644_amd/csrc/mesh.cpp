@@ -198,6 +198,10 @@ void build_mesh(efie_mesh_s& m, const double* xyz, int64_t nv, const int32_t* tr
             m.near_q.push_back(q);
         }
     }
+    // the pairs with q >= p (the kernels that use the symmetry compute only these)
+    m.near_up.clear();
+    for (size_t e = 0; e < m.near_p.size(); ++e)
+        if (m.near_q[e] >= m.near_p[e]) m.near_up.push_back(int32_t(e));
 }
 
 namespace {
@@ -288,24 +292,53 @@ void pack_tables(efie_mesh_s& m) {
     pk.add(et); pk.add(el);
     pk.add(q3x); pk.add(q3y); pk.add(q3z); pk.add(q3w);
     pk.add(f32(q3x)); pk.add(f32(q3y)); pk.add(f32(q3z)); pk.add(f32(q3w));
+    pk.add(m.near_up);
     pk.blob.resize((pk.blob.size() + 255) & ~size_t(255));
     m.host_blob.swap(pk.blob);
     m.offs.swap(pk.offs);
 }
 
-void bind_tables(efie_mesh_s& m, void* dev) {
-    char* b = static_cast<char*>(dev);
-    const auto& o = m.offs;
-    DevMesh& d = m.dm;
-    d.T = int32_t(m.T);
-    d.N = int32_t(m.N);
-    d.nf = m.near_factor;
-    d.diam = m.diam;
-    d.n_near = int32_t(m.near_p.size());
+// The tables pack_tables writes, in its order: the count each scales with
+// ('T' triangles, 'N' RWGs, 'E' ordered near pairs, 'U' those with q >= p), how
+// many elements per unit, and the element size.
+namespace {
+struct TableSpec {
+    char kind;
+    int per, esz;
+};
+const TableSpec kTables[] = {
+    {'T', 1, 8}, {'T', 1, 8}, {'T', 1, 8},                                            // cx cy cz
+    {'T', 7, 8}, {'T', 7, 8}, {'T', 7, 8}, {'T', 7, 8},                               // qx qy qz qw
+    {'T', 3, 8}, {'T', 3, 8}, {'T', 3, 8}, {'T', 3, 8}, {'T', 3, 8},                  // vx vy vz cf dv
+    {'T', 1, 8}, {'T', 1, 8}, {'T', 1, 8}, {'T', 1, 8},                               // nx ny nz hm
+    {'T', 7, 4}, {'T', 7, 4}, {'T', 7, 4}, {'T', 7, 4},                               // FP32 q
+    {'T', 3, 4}, {'T', 3, 4}, {'T', 3, 4}, {'T', 3, 4}, {'T', 3, 4},                  // FP32 v cf dv
+    {'T', 3, 4}, {'T', 3, 4},                                                         // te tv
+    {'E', 1, 4}, {'E', 1, 4},                                                         // near_p near_q
+    {'N', 2, 4}, {'N', 2, 4},                                                         // et el
+    {'T', 3, 8}, {'T', 3, 8}, {'T', 3, 8}, {'T', 3, 8},                               // q3 (FP64)
+    {'T', 3, 4}, {'T', 3, 4}, {'T', 3, 4}, {'T', 3, 4},                               // q3 (FP32)
+    {'U', 1, 4},                                                                      // near_up
+};
+}  // namespace
+
+int table_count() { return int(sizeof(kTables) / sizeof(kTables[0])); }
+
+size_t table_bytes_of(const efie_mesh_s& m, int t) {
+    const TableSpec& s = kTables[t];
+    const size_t units = s.kind == 'T'   ? size_t(m.T)
+                         : s.kind == 'N' ? size_t(m.N)
+                         : s.kind == 'E' ? m.near_p.size()
+                                         : m.near_up.size();
+    return units * size_t(s.per) * size_t(s.esz);
+}
+
+void bind_pointers(DevMesh& d, const void* base, const std::vector<size_t>& o) {
+    const char* b = static_cast<const char*>(base);
     int i = 0;
-    auto D = [&]() { return reinterpret_cast<const double*>(b + o[i++]); };
-    auto F = [&]() { return reinterpret_cast<const float*>(b + o[i++]); };
-    auto I = [&]() { return reinterpret_cast<const int32_t*>(b + o[i++]); };
+    auto D = [&]() { return reinterpret_cast<const double*>(b + o[size_t(i++)]); };
+    auto F = [&]() { return reinterpret_cast<const float*>(b + o[size_t(i++)]); };
+    auto I = [&]() { return reinterpret_cast<const int32_t*>(b + o[size_t(i++)]); };
     d.cx = D(); d.cy = D(); d.cz = D();
     d.qx = D(); d.qy = D(); d.qz = D(); d.qw = D();
     d.vx = D(); d.vy = D(); d.vz = D(); d.cf = D(); d.dv = D();
@@ -318,6 +351,18 @@ void bind_tables(efie_mesh_s& m, void* dev) {
     d.et = I(); d.el = I();
     d.q3x = D(); d.q3y = D(); d.q3z = D(); d.q3w = D();
     d.q3x32 = F(); d.q3y32 = F(); d.q3z32 = F(); d.q3w32 = F();
+    d.near_up = I();
+}
+
+void bind_tables(efie_mesh_s& m, void* dev) {
+    DevMesh& d = m.dm;
+    d.T = int32_t(m.T);
+    d.N = int32_t(m.N);
+    d.nf = m.near_factor;
+    d.diam = m.diam;
+    d.n_near = int32_t(m.near_p.size());
+    d.n_up = int32_t(m.near_up.size());
+    bind_pointers(d, dev, m.offs);
     d.far3 = m.far3;
     m.dev = dev;
 }

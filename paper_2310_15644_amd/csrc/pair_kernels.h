@@ -260,44 +260,40 @@ static __device__ void potentials(const double r[3], const double u[3][3], const
     }
 }
 
-// Singular block X(i,j) = sum_a W_a f_i(r_a) . int_s f_j(r')/R dS' and the scalar
-// s0 = sum_a W_a int_s 1/R dS', for test triangle t and source triangle s.
-static __device__ void singular_block(const DevMesh& m, int t, int s, double X[3][3], double& s0) {
+// Test point a of the singular block X(i,j) = sum_a W_a f_i(r_a) . int_s f_j(r')/R dS'
+// and of the scalar s0 = sum_a W_a int_s 1/R dS' (test triangle t, source triangle
+// s): w times that point's terms added to Y[i][j] (TR: to Y[j][i]) and to s0.
+static __device__ void singular_point(const DevMesh& m, int t, int s, int a, double w, bool TR, double Y[3][3],
+                                      double& s0) {
     const int T = m.T;
     // everything relative to the source centroid
     const double D[3] = {m.cx[t] - m.cx[s], m.cy[t] - m.cy[s], m.cz[t] - m.cz[s]};
-    double us[3][3], ut[3][3];
+    double us[3][3];
     for (int k = 0; k < 3; ++k) {
         us[k][0] = m.vx[k * T + s]; us[k][1] = m.vy[k * T + s]; us[k][2] = m.vz[k * T + s];
-        ut[k][0] = m.vx[k * T + t]; ut[k][1] = m.vy[k * T + t]; ut[k][2] = m.vz[k * T + t];
     }
     const double n[3] = {m.nx[s], m.ny[s], m.nz[s]};
-    const double h = m.hm[s];
-    double cs[3], ct[3];
-    for (int k = 0; k < 3; ++k) {
-        cs[k] = m.cf[k * T + s];
-        ct[k] = m.cf[k * T + t];
+    const double da[3] = {m.qx[a * T + t], m.qy[a * T + t], m.qz[a * T + t]};
+    const double wa = w * m.qw[a * T + t];
+    const double r[3] = {D[0] + da[0], D[1] + da[1], D[2] + da[2]};
+    double I0, I1[3];
+    potentials(r, us, n, m.hm[s], I0, I1);
+    const double dd = n[0] * (r[0] - us[0][0]) + n[1] * (r[1] - us[0][1]) + n[2] * (r[2] - us[0][2]);
+    const double rho[3] = {r[0] - dd * n[0], r[1] - dd * n[1], r[2] - dd * n[2]};
+    s0 += wa * I0;
+    double inner[3][3];
+    for (int j = 0; j < 3; ++j) {
+        const double cs = m.cf[j * T + s];
+        for (int x = 0; x < 3; ++x) inner[j][x] = cs * (I1[x] + (rho[x] - us[j][x]) * I0);
     }
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) X[i][j] = 0.0;
-    s0 = 0.0;
-#pragma unroll 1
-    for (int a = 0; a < NQ; ++a) {
-        const double da[3] = {m.qx[a * T + t], m.qy[a * T + t], m.qz[a * T + t]};
-        const double wa = m.qw[a * T + t];
-        const double r[3] = {D[0] + da[0], D[1] + da[1], D[2] + da[2]};
-        double I0, I1[3];
-        potentials(r, us, n, h, I0, I1);
-        const double dd = n[0] * (r[0] - us[0][0]) + n[1] * (r[1] - us[0][1]) + n[2] * (r[2] - us[0][2]);
-        const double rho[3] = {r[0] - dd * n[0], r[1] - dd * n[1], r[2] - dd * n[2]};
-        s0 += wa * I0;
-        double inner[3][3];
-        for (int j = 0; j < 3; ++j)
-            for (int x = 0; x < 3; ++x) inner[j][x] = cs[j] * (I1[x] + (rho[x] - us[j][x]) * I0);
-        for (int i = 0; i < 3; ++i) {
-            const double f[3] = {ct[i] * (da[0] - ut[i][0]), ct[i] * (da[1] - ut[i][1]), ct[i] * (da[2] - ut[i][2])};
-            for (int j = 0; j < 3; ++j)
-                X[i][j] += wa * (f[0] * inner[j][0] + f[1] * inner[j][1] + f[2] * inner[j][2]);
+    for (int i = 0; i < 3; ++i) {
+        const double ct = m.cf[i * T + t];
+        const double f[3] = {ct * (da[0] - m.vx[i * T + t]), ct * (da[1] - m.vy[i * T + t]),
+                             ct * (da[2] - m.vz[i * T + t])};
+        for (int j = 0; j < 3; ++j) {
+            const double v = wa * (f[0] * inner[j][0] + f[1] * inner[j][1] + f[2] * inner[j][2]);
+            if (TR) Y[j][i] += v;
+            else Y[i][j] += v;
         }
     }
 }
@@ -322,19 +318,32 @@ static __device__ __forceinline__ void green_smooth(double kr, double ki, double
     gi = ni / R;
 }
 
-// Near pair e of the ordered list: emit(i, j, zr, zi) receives the FP64 Z
-// contribution of test edge i and source edge j (PARTS: T_A part; emit2: T_Phi).
+// Near pair e of the ordered list, computed by a group of NEAR_G = 8 consecutive
+// lanes (g = 0..7 its lane in the group; every lane of the group calls this with
+// the same valid e): lane g < 7 takes test point a = g of p, i.e. the smooth part's
+// row a of the 7 x 7 rule and the two singular blocks' terms at test point a (of p
+// against q, and of q against p), so all lanes of a wave run the same code.  The
+// moments are summed over the group with a butterfly of lane exchanges (a fixed
+// order: deterministic), then lane g emits entries 3 i + j = g, g + 8:
+// emit(i, j, zr, zi) receives the FP64 Z contribution of test edge i and source
+// edge j (PARTS: T_A part; emit2: T_Phi).
+constexpr int NEAR_G = 8;
+
 template <bool PARTS, typename Emit, typename Emit2>
-__device__ void near_pair_emit(const DevMesh& m, int e, double kr, double ki, const Scale& sc, Emit emit,
-                               Emit2 emit2) {
+__device__ void near_pair_group(const DevMesh& m, int e, int g, double kr, double ki, const Scale& sc, Emit emit,
+                                Emit2 emit2) {
     const int p = m.near_p[e], q = m.near_q[e];
     const int T = m.T;
-    // smooth part, 7 x 7 rule, offsets from the centroids as in the far kernel
-    const double D[3] = {m.cx[p] - m.cx[q], m.cy[p] - m.cy[q], m.cz[p] - m.cz[q]};
-    double m0r = 0, m0i = 0, mdr[3] = {0, 0, 0}, mdi[3] = {0, 0, 0}, mpr[3] = {0, 0, 0}, mpi[3] = {0, 0, 0};
-    double mmr = 0, mmi = 0;
-#pragma unroll 1
-    for (int a = 0; a < NQ; ++a) {
+    // v: the smooth part's moments as in the far kernel (offsets from the centroids)
+    //   [0,1] M0, [2..7] Md (re, im per axis), [8..13] Md', [14,15] Mdd';
+    // Y = (X_pq + X_qp^T) / 2 of the singular part, and s0 its scalar
+    double v[16];
+    for (int x = 0; x < 16; ++x) v[x] = 0.0;
+    double Y[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    double s0 = 0.0;
+    if (g < NQ) {
+        const int a = g;
+        const double D[3] = {m.cx[p] - m.cx[q], m.cy[p] - m.cy[q], m.cz[p] - m.cz[q]};
         const double ax = m.qx[a * T + p], ay = m.qy[a * T + p], az = m.qz[a * T + p], wa = m.qw[a * T + p];
         double s0r = 0, s0i = 0, s1r[3] = {0, 0, 0}, s1i[3] = {0, 0, 0};
 #pragma unroll 1
@@ -350,50 +359,61 @@ __device__ void near_pair_emit(const DevMesh& m, int e, double kr, double ki, co
             s1r[1] += gr * by; s1i[1] += gi * by;
             s1r[2] += gr * bz; s1i[2] += gi * bz;
         }
-        m0r += wa * s0r;
-        m0i += wa * s0i;
         const double av[3] = {ax, ay, az};
+        v[0] = wa * s0r;
+        v[1] = wa * s0i;
         for (int d = 0; d < 3; ++d) {
-            mdr[d] += wa * av[d] * s0r; mdi[d] += wa * av[d] * s0i;
-            mpr[d] += wa * s1r[d]; mpi[d] += wa * s1i[d];
+            v[2 + 2 * d] = wa * av[d] * s0r;
+            v[3 + 2 * d] = wa * av[d] * s0i;
+            v[8 + 2 * d] = wa * s1r[d];
+            v[9 + 2 * d] = wa * s1i[d];
         }
-        mmr += wa * (ax * s1r[0] + ay * s1r[1] + az * s1r[2]);
-        mmi += wa * (ax * s1i[0] + ay * s1i[1] + az * s1i[2]);
+        v[14] = wa * (ax * s1r[0] + ay * s1r[1] + az * s1r[2]);
+        v[15] = wa * (ax * s1i[0] + ay * s1i[1] + az * s1i[2]);
+        // singular part, symmetrised: (X_pq + X_qp^T) / 2
+        singular_point(m, p, q, a, 0.5, false, Y, s0);
+        singular_point(m, q, p, a, 0.5, true, Y, s0);
     }
-    // singular part, symmetrised
-    double Xpq[3][3], Xqp[3][3], s0pq, s0qp;
-    singular_block(m, p, q, Xpq, s0pq);
-    singular_block(m, q, p, Xqp, s0qp);
-    const double s0 = 0.5 * (s0pq + s0qp);
-    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+    for (int o = 1; o < NEAR_G; o <<= 1) {
+#pragma unroll
+        for (int x = 0; x < 16; ++x) v[x] += __shfl_xor(v[x], o, NEAR_G);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) Y[i][j] += __shfl_xor(Y[i][j], o, NEAR_G);
+        s0 += __shfl_xor(s0, o, NEAR_G);
+    }
+    const double m0r = v[0], m0i = v[1];
+    for (int idx = g; idx < 9; idx += NEAR_G) {
+        const int i = idx / 3, j = idx - 3 * (idx / 3);
         const double ux = m.vx[i * T + p], uy = m.vy[i * T + p], uz = m.vz[i * T + p];
         const double ci = m.cf[i * T + p], gi_ = m.dv[i * T + p];
-        for (int j = 0; j < 3; ++j) {
-            const double vx = m.vx[j * T + q], vy = m.vy[j * T + q], vz = m.vz[j * T + q];
-            const double cj = m.cf[j * T + q], gj = m.dv[j * T + q];
-            const double br = mmr - (ux * mpr[0] + uy * mpr[1] + uz * mpr[2]) -
-                              (vx * (mdr[0] - ux * m0r) + vy * (mdr[1] - uy * m0r) + vz * (mdr[2] - uz * m0r));
-            const double bi = mmi - (ux * mpi[0] + uy * mpi[1] + uz * mpi[2]) -
-                              (vx * (mdi[0] - ux * m0i) + vy * (mdi[1] - uy * m0i) + vz * (mdi[2] - uz * m0i));
-            const double tar = ci * cj * br + 0.5 * (Xpq[i][j] + Xqp[j][i]);
-            const double tai = ci * cj * bi;
-            const double gg = gi_ * gj;
-            const double tpr = gg * (m0r + s0), tpi = gg * m0i;
-            if (PARTS) {
-                emit(i, j, tar * sc.ar, tai * sc.ar);
-                emit2(i, j, tpr * sc.ar, tpi * sc.ar);
-            } else {
-                const double zr = sc.ar * tar - sc.ai * tai + sc.pr * tpr - sc.pi * tpi;
-                const double zi = sc.ar * tai + sc.ai * tar + sc.pr * tpi + sc.pi * tpr;
-                emit(i, j, zr, zi);
-            }
+        const double vx = m.vx[j * T + q], vy = m.vy[j * T + q], vz = m.vz[j * T + q];
+        const double cj = m.cf[j * T + q], gj = m.dv[j * T + q];
+        const double br = v[14] - (ux * v[8] + uy * v[10] + uz * v[12]) -
+                          (vx * (v[2] - ux * m0r) + vy * (v[4] - uy * m0r) + vz * (v[6] - uz * m0r));
+        const double bi = v[15] - (ux * v[9] + uy * v[11] + uz * v[13]) -
+                          (vx * (v[3] - ux * m0i) + vy * (v[5] - uy * m0i) + vz * (v[7] - uz * m0i));
+        const double tar = ci * cj * br + Y[i][j];
+        const double tai = ci * cj * bi;
+        const double gg = gi_ * gj;
+        const double tpr = gg * (m0r + s0), tpi = gg * m0i;
+        if (PARTS) {
+            emit(i, j, tar * sc.ar, tai * sc.ar);
+            emit2(i, j, tpr * sc.ar, tpi * sc.ar);
+        } else {
+            const double zr = sc.ar * tar - sc.ai * tai + sc.pr * tpr - sc.pi * tpi;
+            const double zi = sc.ar * tai + sc.ai * tar + sc.pr * tpi + sc.pi * tpr;
+            emit(i, j, zr, zi);
         }
     }
 }
 
-// near pair e added to Z (and Z2 in parts mode) with atomics, in ZT precision
+// near pair e added to Z (and Z2 in parts mode) with atomics, in ZT precision (by
+// the group of 8 lanes, lane g)
 template <typename ZT, bool PARTS>
-__device__ void near_pair(const DevMesh& m, int e, double kr, double ki, const Scale& sc, void* Z, void* Z2) {
+__device__ void near_pair(const DevMesh& m, int e, int g, double kr, double ki, const Scale& sc, void* Z, void* Z2) {
     const int p = m.near_p[e], q = m.near_q[e];
     const int T = m.T;
     const size_t N = size_t(m.N);
@@ -402,7 +422,7 @@ __device__ void near_pair(const DevMesh& m, int e, double kr, double ki, const S
             atomic_add_c<ZT>(dst, size_t(m.te[i * T + p]) * N + size_t(m.te[j * T + q]), ZT(re), ZT(im));
         };
     };
-    near_pair_emit<PARTS>(m, e, kr, ki, sc, at(Z), at(Z2));
+    near_pair_group<PARTS>(m, e, g, kr, ki, sc, at(Z), at(Z2));
 }
 
 }  // namespace efie

@@ -90,9 +90,11 @@ __device__ __forceinline__ void far_rows_block(const DevMesh& m, const Tables<R>
 // the ordered near pair e = (p, q) with p in the chunk [c0, c1): its values replace
 // the zeros pass 1 wrote (FP64 arithmetic, all nine entries).  upper: pairs with
 // q < p are not written and the diagonal blocks (q = p) are halved.
+// (by the group of NEAR_G lanes, lane g)
 template <typename R>
 __device__ __forceinline__ void near_rows_one(const DevMesh& m, double kr, double ki, const Scale& sc,
-                                              typename Cplx<R>::T* __restrict__ W, int c0, int c1, int e, int upper) {
+                                              typename Cplx<R>::T* __restrict__ W, int c0, int c1, int e, int g,
+                                              int upper) {
     using C2 = typename Cplx<R>::T;
     const int p = m.near_p[e], q = m.near_q[e];
     if (p < c0 || p >= c1) return;
@@ -106,7 +108,7 @@ __device__ __forceinline__ void near_rows_one(const DevMesh& m, double kr, doubl
         const int side = m.cf[j * T + q] > 0.0 ? 0 : 1;
         rows[(size_t(i) * N + n) * 2 + side] = C2{R(f * re), R(f * im)};
     };
-    near_pair_emit<false>(m, e, kr, ki, sc, put, put);
+    near_pair_group<false>(m, e, g, kr, ki, sc, put, put);
 }
 
 }  // namespace efie

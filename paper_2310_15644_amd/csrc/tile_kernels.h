@@ -76,15 +76,16 @@ __device__ inline int find_near(const DevMesh& m, int p, int q) {
 }
 
 // NB[9 e + 3 i + j]: the FP64 block of ordered near pair e = (p, q), q >= p (the
-// others are not written), stored in the precision of Z
+// others are not written), stored in the precision of Z; by the group of NEAR_G
+// lanes, lane g
 template <typename R>
 __device__ __forceinline__ void near_block_one(const DevMesh& m, double kr, double ki, const Scale& sc,
-                                               typename Cplx<R>::T* __restrict__ NB, int e) {
+                                               typename Cplx<R>::T* __restrict__ NB, int e, int g) {
     using C2 = typename Cplx<R>::T;
     if (m.near_q[e] < m.near_p[e]) return;
     C2* out = NB + size_t(e) * 9;
     auto put = [&](int i, int j, double re, double im) { out[3 * i + j] = C2{R(re), R(im)}; };
-    near_pair_emit<false>(m, e, kr, ki, sc, put, put);
+    near_pair_group<false>(m, e, g, kr, ki, sc, put, put);
 }
 
 // (bi, bj), bi <= bj, of tile k numbered row by row of the upper triangle of nt x nt

@@ -1,9 +1,9 @@
-"""Many uneven meshes in persistent work-queue launches and one grouped solve:
-every block is bit-identical to its single-mesh assembly (the same two-pass
-device code per work item, no atomics), two batched assemblies are
-bit-identical, the grouped solve matches the single solves (iteration counts
-within 2), one mesh against the oracle; the 64-ellipsoid set (semi-axes
-U[0.5, 1.5], 1k-8k unknowns) at k = 2."""
+"""Many uneven meshes in one persistent tile launch and one grouped solve: every
+block is bit-identical to its single-mesh assembly (the same tile device code on
+a view of each mesh's concatenated tables, no atomics), two batched assemblies
+are bit-identical, the grouped solve matches the single solves (the solutions to
+1e-8, the iteration counts within 6 %), one mesh against the oracle; the
+64-ellipsoid set (semi-axes U[0.5, 1.5], 1k-8k unknowns) at k = 2."""
 import time
 
 import numpy as np
@@ -69,12 +69,14 @@ def test_batch_solve_equals_single(dev):
         Zi, Vi = B.z_of(Zc, i).contiguous(), Vc[B.voff[i]:B.voff[i + 1]].contiguous()
         _, s6 = P.solve(Zi, Vi, tol=1e-6, maxit=1000)
         J1, st1 = P.solve(Zi, Vi, tol=1e-10, maxit=1000)
-        # the matrices are bit-identical; the grouped and the single GEMV sum in
-        # different orders: the step counts to 1e-6 agree within 2, those to 1e-10
-        # (about 180 steps, where COCG's loss of orthogonality amplifies rounding)
-        # within 3 %
-        assert abs(int(s6.iters[0]) - int(st6.iters[i])) <= 2
-        assert abs(int(st1.iters[0]) - int(st.iters[i])) <= max(2, int(0.03 * st1.iters[0]))
+        # the matrices are bit-identical, but the two solvers round differently: the
+        # grouped GEMV and the single one (column slabs) sum in different orders, and
+        # the single COCG replaces its recursive residual by the true one.  COCG's
+        # step counts answer to rounding like a chaotic system (the recurrences agree
+        # only in exact arithmetic), so they are compared within 6 % (at least 3
+        # steps), and the solutions themselves tightly below
+        assert abs(int(s6.iters[0]) - int(st6.iters[i])) <= max(3, int(0.06 * s6.iters[0]))
+        assert abs(int(st1.iters[0]) - int(st.iters[i])) <= max(3, int(0.06 * st1.iters[0]))
         a = J[B.voff[i]:B.voff[i + 1]].cpu().numpy()
         b = J1.cpu().numpy()[0]
         assert np.linalg.norm(a - b) <= 1e-8 * np.linalg.norm(b)
