@@ -392,9 +392,9 @@ int efie_solve(const void* Z, int dtype, int64_t n, const void* V, void* J, int6
  *   dev Tbc_out (may be NULL).  T_BC is accumulated without forming T_bary: the
  *   barycentric pair values of a chunk of test triangles go to workspace rows
  *   (at most 2 GiB) that are contracted with R at once.  Rows of P solve
- *   G_mix^T p = T_BC row by CGNR (batches of rows, column layout) to the relative
- *   residual tol (maxit steps); *relres (host, may be NULL) gets the worst
- *   achieved.  For tol >= 1e-4 the CGNR vectors are stored in complex64 (every
+ *   G_mix^T p = T_BC row by BiCGStab (batches of rows, column layout) to the
+ *   relative residual tol (maxit steps); *relres (host, may be NULL) gets the worst
+ *   achieved.  For tol >= 1e-4 the solver's vectors are stored in complex64 (every
  *   sum, norm and update still in FP64), which bounds the attainable residual
  *   near 1e-6; tighter tolerances keep them in complex128.  ws: dev workspace of ws_bytes from efie_calderon_sizes (T_BC,
  *   16 N^2 bytes, plus a few GiB).  EFIE_NOT_CONVERGED if tol missed.
@@ -477,7 +477,7 @@ int efie_solve_precond_ex(const void* Z, int zdt, const void* P, int pdt, int64_
  *
  * efie_calderon_cfie_assemble: M and Q into dev buffers (N x N complex128 each),
  *   optionally K_BC(k) and K_BC(k~) (raw, N x N complex128) into K_out, Kt_out;
- *   k > 0 real, kt_im <= 0; Q by CGNR on G_mix to tol (maxit sweeps; complex64
+ *   k > 0 real, kt_im <= 0; Q by BiCGStab on G_mix to tol (maxit steps; complex64
  *   vectors when tol >= 1e-4), its worst relative residual in *relres.  Needs the
  *   mesh and the Calderon tables uploaded; ws as for efie_calderon_assemble
  *   (ws_bytes from efie_calderon_sizes).  Returns EFIE_NOT_CONVERGED if Q missed tol.

@@ -11,9 +11,9 @@
 //                                (one block per BC row m touched by the chunk, from
 //                                host-built lists; no atomics);
 //   P = T_BC G_mix^{-1}       row s of P solves G_mix^T p_s = row s of T_BC = column s
-//       (T_BC is symmetric), by CGNR (CG on G G^T y = G b) for a batch of columns at
-//       once in column layout X[j][s], so that every sparse product reads rows of
-//       the batch coalesced; the solution block is then transposed into P.
+//       (T_BC is symmetric), by BiCGStab for a batch of columns at once in column
+//       layout X[j][s], so that every sparse product reads rows of the batch
+//       coalesced; the solution block is then transposed into P.
 // The preconditioned operator P Z is applied as two dense products.
 #include <hip/hip_runtime.h>
 
@@ -208,15 +208,20 @@ __global__ __launch_bounds__(256) void sym_add_kernel(double2* __restrict__ T, i
     }
 }
 
-// ---------------------------------------------- CGNR on column tiles
+// ------------------------------------------- BiCGStab on column tiles
+// The Gram systems (G_mix^T y = b for P, G_mix y = b for Q) are solved column by
+// column with BiCGStab (van der Vorst, SIAM J. Sci. Stat. Comput. 13(2) 1992):
+// two sparse products per step and no transpose.  On these well-conditioned
+// systems it reaches 1e-3 in three steps where CG on the normal equations takes
+// about ten (two products each).
 // The vectors are stored as V (double2, or float2 when the requested tolerance
-// is loose: CGNR_C64_TOL); every sum, norm and update is evaluated in FP64.
+// is loose: GRAM_C64_TOL); every sum, norm and update is evaluated in FP64.
 // A batch of S columns is split into tiles of CG_W = 64 columns, each tile stored
 // row by row: element (j, s) sits at ((s / CG_W) N + j) CG_W + s % CG_W, so a
 // wave reads a row of a tile as 512 contiguous bytes (complex64).  A block takes
 // CG_R consecutive rows of one tile (a slice), a wave every fourth of them.  The
 // padding columns of the last tile stay zero.
-constexpr double CGNR_C64_TOL = 1e-4;
+constexpr double GRAM_C64_TOL = 1e-4;
 constexpr int CG_W = 64;   // columns per tile: one per lane
 constexpr int CG_R = 64;   // rows per block
 __device__ inline double2 ld2(const double2& v) { return v; }
@@ -229,7 +234,7 @@ template <>
 __device__ inline float2 st2<float2>(double x, double y) { return make_float2(float(x), float(y)); }
 
 inline int cg_pad(int S) { return (S + CG_W - 1) / CG_W * CG_W; }
-inline int cg_slices(int N) { return (N + CG_R - 1) / CG_R; }
+__host__ __device__ inline int cg_slices(int N) { return (N + CG_R - 1) / CG_R; }
 // blocks of a batch of S columns: every slice of every tile, the tile count
 // rounded up to a multiple of 8
 inline unsigned cg_blocks(int S, int N) { return unsigned((cg_pad(S) / CG_W + 7) / 8 * 8) * unsigned(cg_slices(N)); }
@@ -316,11 +321,49 @@ __global__ __launch_bounds__(256) void cspmm_kernel(const int32_t* __restrict__ 
     cg_part(sq, k, S, part);
 }
 
-// out[s] = sum over the ns slices of part[slice][s]; block = 16 columns x 16
-// slice stripes, grid ceil(S / 16)
+// Out = A X as cspmm_kernel, and the slice sums of three column reductions:
+// part[0] and part[1] the real and imaginary parts of sum_j conj(Y[j]) Out[j],
+// part[2] sum_j |Out[j]|^2 (part[v] = part + v ns S)
+template <typename V>
+__global__ __launch_bounds__(256) void cspmm_dot_kernel(const int32_t* __restrict__ ptr,
+                                                        const int32_t* __restrict__ idx,
+                                                        const double* __restrict__ val, const V* __restrict__ X,
+                                                        V* __restrict__ Out, int S, const int32_t* __restrict__ order,
+                                                        int N, const V* __restrict__ Y, double* __restrict__ part) {
+    const CgBlock k = cg_block(N);
+    if (k.tile * CG_W >= S) return;
+    const V* Xt = X + cg_at(k.tile, 0, k.c, N);
+    double dr = 0.0, di = 0.0, sq = 0.0;
+    for (int t = k.j0; t < k.j1; t += 4) {
+        double ar = 0, ai = 0;
+        int kb = ptr[t];
+        const int ke = ptr[t + 1];
+        for (; kb + 8 <= ke; kb += 8) csp_group<8>(idx, val, Xt, kb, ke, ar, ai);
+        for (; kb < ke; kb += 4) csp_group<4>(idx, val, Xt, kb, ke, ar, ai);
+        const V o = st2<V>(ar, ai);
+        const size_t e = cg_at(k.tile, order[t], k.c, N);
+        Out[e] = o;
+        const double2 od = ld2(o), yv = ld2(Y[e]);
+        dr += yv.x * od.x + yv.y * od.y;
+        di += yv.x * od.y - yv.y * od.x;
+        sq += od.x * od.x + od.y * od.y;
+    }
+    const size_t ps = size_t(cg_slices(N)) * S;
+    cg_part(dr, k, S, part);
+    __syncthreads();
+    cg_part(di, k, S, part + ps);
+    __syncthreads();
+    cg_part(sq, k, S, part + 2 * ps);
+}
+
+// out[y S + s] = sum over the ns slices of part[(y ns + slice) S + s] for the
+// reductions y = blockIdx.y; block = 16 columns x 16 slice stripes, grid
+// (ceil(S / 16), reductions)
 __global__ __launch_bounds__(256) void colsq_final_kernel(const double* __restrict__ part, int S, int ns,
                                                           double* __restrict__ out) {
     __shared__ double sh[16][17];
+    part += size_t(blockIdx.y) * size_t(ns) * S;
+    out += size_t(blockIdx.y) * S;
     const int c = threadIdx.x & 15, st = threadIdx.x >> 4;
     const int s = blockIdx.x * 16 + c;
     double a = 0.0;
@@ -335,96 +378,165 @@ __global__ __launch_bounds__(256) void colsq_final_kernel(const double* __restri
     }
 }
 
-struct CgnrCol {
-    double gamma, bn2, rn2, tol2;
-    int active, iters, pad[2];
+// per column: rho = <r^, r>, alpha, omega, beta of the current step (complex),
+// ||b||^2, ||r||^2, the target tol^2 ||b||^2
+struct BicgCol {
+    double rho_r, rho_i, al_r, al_i, om_r, om_i, be_r, be_i;
+    double bn2, rn2, tol2;
+    int active, iters;
 };
 
-// w = 0, r = b (b[j][s] with leading dimension ldb; zero in the padding columns);
-// part = slice sums of |r|^2
+// x = 0, r = r^ = p = b (b[j][s] with leading dimension ldb; zero in the padding
+// columns); part = slice sums of |r|^2
 template <typename V>
-__global__ __launch_bounds__(256) void cgnr_init_kernel(const double2* __restrict__ b, int ldb, V* __restrict__ w,
-                                                        V* __restrict__ r, int N, int S, double* __restrict__ part) {
+__global__ __launch_bounds__(256) void bicg_init_kernel(const double2* __restrict__ b, int ldb, V* __restrict__ x,
+                                                        V* __restrict__ r, V* __restrict__ rh, V* __restrict__ p,
+                                                        int N, int S, double* __restrict__ part) {
     const CgBlock k = cg_block(N);
     if (k.tile * CG_W >= S) return;
     double sq = 0.0;
     for (int j = k.j0; j < k.j1; j += 4) {
         const double2 v = k.s < S ? b[size_t(j) * ldb + k.s] : make_double2(0.0, 0.0);
         const size_t e = cg_at(k.tile, j, k.c, N);
-        w[e] = st2<V>(0.0, 0.0);
+        x[e] = st2<V>(0.0, 0.0);
         const V rv = st2<V>(v.x, v.y);
         r[e] = rv;
+        rh[e] = rv;
+        p[e] = rv;
         const double2 rd = ld2(rv);
         sq += rd.x * rd.x + rd.y * rd.y;
     }
     cg_part(sq, k, S, part);
 }
-__global__ void cgnr_setup_kernel(CgnrCol* cols, const double* bn2, const double* zz, double tol, int S) {
+// red = ||b||^2 (of the stored b)
+__global__ void bicg_setup_kernel(BicgCol* cols, const double* bn2, double tol, int S) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= S) return;
-    CgnrCol c{};
-    c.gamma = zz[s];
+    BicgCol c{};
+    c.rho_r = bn2[s];
     c.bn2 = bn2[s];
     c.rn2 = bn2[s];
     c.tol2 = tol * tol * bn2[s];
-    c.active = bn2[s] > 0.0 && zz[s] > 0.0;
+    c.active = bn2[s] > c.tol2;
     cols[s] = c;
 }
-// after t = G^T p, tt = ||t||^2: alpha = gamma / tt, w += alpha p, r -= alpha t for
-// the active columns; part = slice sums of |r|^2 (every column)
+// after v = A p and d = <r^, v> (red[0] + j red[1]): alpha = rho / d
+__global__ void bicg_alpha_kernel(BicgCol* cols, const double* red, int S) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S || !cols[s].active) return;
+    BicgCol c = cols[s];
+    const double dr = red[s], di = red[S + s], dd = dr * dr + di * di;
+    if (!(dd > 0.0)) {   // breakdown: the column keeps its last iterate
+        c.active = 0;
+    } else {
+        c.al_r = (c.rho_r * dr + c.rho_i * di) / dd;
+        c.al_i = (c.rho_i * dr - c.rho_r * di) / dd;
+    }
+    cols[s] = c;
+}
+// s = r - alpha v, in place of r (active columns)
 template <typename V>
-__global__ __launch_bounds__(256) void cgnr_upd1_kernel(V* __restrict__ w, V* __restrict__ r, const V* __restrict__ p,
-                                                        const V* __restrict__ t, const CgnrCol* __restrict__ cols,
-                                                        const double* __restrict__ tt, int N, int S,
-                                                        double* __restrict__ part) {
+__global__ __launch_bounds__(256) void bicg_s_kernel(V* __restrict__ r, const V* __restrict__ v,
+                                                     const BicgCol* __restrict__ cols, int N, int S) {
+    const CgBlock k = cg_block(N);
+    if (k.s >= S || !cols[k.s].active) return;
+    const double ar = cols[k.s].al_r, ai = cols[k.s].al_i;
+    for (int j = k.j0; j < k.j1; j += 4) {
+        const size_t e = cg_at(k.tile, j, k.c, N);
+        const double2 rr = ld2(r[e]), vv = ld2(v[e]);
+        r[e] = st2<V>(rr.x - (ar * vv.x - ai * vv.y), rr.y - (ar * vv.y + ai * vv.x));
+    }
+}
+// after t = A s with red = (<s, t> re, im, ||t||^2): omega = <t, s> / ||t||^2 =
+// conj(<s, t>) / ||t||^2 (zero when t = 0: then s is the residual and x += alpha p)
+__global__ void bicg_omega_kernel(BicgCol* cols, const double* red, int S) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S || !cols[s].active) return;
+    const double tt = red[2 * S + s];
+    cols[s].om_r = tt > 0.0 ? red[s] / tt : 0.0;
+    cols[s].om_i = tt > 0.0 ? -red[S + s] / tt : 0.0;
+}
+// x += alpha p + omega s, r = s - omega t (active columns); part = slice sums of
+// <r^, r> (re, im) and |r|^2 for every column
+template <typename V>
+__global__ __launch_bounds__(256) void bicg_xr_kernel(V* __restrict__ x, V* __restrict__ r, const V* __restrict__ p,
+                                                      const V* __restrict__ t, const V* __restrict__ rh,
+                                                      const BicgCol* __restrict__ cols, int N, int S,
+                                                      double* __restrict__ part) {
     const CgBlock k = cg_block(N);
     if (k.tile * CG_W >= S) return;
-    const bool act = k.s < S && cols[k.s].active && tt[k.s] > 0.0;
-    const double al = act ? cols[k.s].gamma / tt[k.s] : 0.0;
-    double sq = 0.0;
+    const bool act = k.s < S && cols[k.s].active;
+    double ar = 0, ai = 0, wr = 0, wi = 0;
+    if (act) {
+        ar = cols[k.s].al_r;
+        ai = cols[k.s].al_i;
+        wr = cols[k.s].om_r;
+        wi = cols[k.s].om_i;
+    }
+    double dr = 0.0, di = 0.0, sq = 0.0;
     for (int j = k.j0; j < k.j1; j += 4) {
         const size_t e = cg_at(k.tile, j, k.c, N);
         double2 rr = ld2(r[e]);
         if (act) {
-            const double2 pp = ld2(p[e]), tv = ld2(t[e]), ww = ld2(w[e]);
-            w[e] = st2<V>(ww.x + al * pp.x, ww.y + al * pp.y);
-            const V rn = st2<V>(rr.x - al * tv.x, rr.y - al * tv.y);
+            const double2 pp = ld2(p[e]), tv = ld2(t[e]), xx = ld2(x[e]);
+            x[e] = st2<V>(xx.x + (ar * pp.x - ai * pp.y) + (wr * rr.x - wi * rr.y),
+                          xx.y + (ar * pp.y + ai * pp.x) + (wr * rr.y + wi * rr.x));
+            const V rn = st2<V>(rr.x - (wr * tv.x - wi * tv.y), rr.y - (wr * tv.y + wi * tv.x));
             r[e] = rn;
             rr = ld2(rn);
         }
+        const double2 hv = ld2(rh[e]);
+        dr += hv.x * rr.x + hv.y * rr.y;
+        di += hv.x * rr.y - hv.y * rr.x;
         sq += rr.x * rr.x + rr.y * rr.y;
     }
-    cg_part(sq, k, S, part);
+    const size_t ps = size_t(cg_slices(N)) * S;
+    cg_part(dr, k, S, part);
+    __syncthreads();
+    cg_part(di, k, S, part + ps);
+    __syncthreads();
+    cg_part(sq, k, S, part + 2 * ps);
 }
-__global__ void cgnr_check_kernel(CgnrCol* cols, const double* rn2, const double* tt, int S, int* nactive) {
+// red = (<r^, r> re, im, ||r||^2): convergence, then beta = (rho' / rho)(alpha /
+// omega) and rho = rho'; nactive counts the columns still active
+__global__ void bicg_check_kernel(BicgCol* cols, const double* red, int S, int* nactive) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= S) return;
-    CgnrCol c = cols[s];
+    BicgCol c = cols[s];
     if (!c.active) return;
-    c.rn2 = rn2[s];
+    const double rr = red[s], ri = red[S + s], rn2 = red[2 * S + s];
+    c.rn2 = rn2;
     c.iters += 1;
-    if (rn2[s] <= c.tol2 || !(rn2[s] == rn2[s]) || !(tt[s] > 0.0)) c.active = 0;
+    const double oo = c.om_r * c.om_r + c.om_i * c.om_i, hh = c.rho_r * c.rho_r + c.rho_i * c.rho_i;
+    if (rn2 <= c.tol2 || !(rn2 == rn2) || !(oo > 0.0) || !(hh > 0.0)) {
+        c.active = 0;
+    } else {
+        // (rho' / rho) (alpha / omega)
+        const double qr = (rr * c.rho_r + ri * c.rho_i) / hh, qi = (ri * c.rho_r - rr * c.rho_i) / hh;
+        const double ur = (c.al_r * c.om_r + c.al_i * c.om_i) / oo, ui = (c.al_i * c.om_r - c.al_r * c.om_i) / oo;
+        c.be_r = qr * ur - qi * ui;
+        c.be_i = qr * ui + qi * ur;
+        c.rho_r = rr;
+        c.rho_i = ri;
+    }
     cols[s] = c;
     if (c.active) atomicAdd(nactive, 1);
 }
-// after z = G r, zz = ||z||^2: p = z + (zz / gamma) p for the active columns
+// p = r + beta (p - omega v) (active columns)
 template <typename V>
-__global__ __launch_bounds__(256) void cgnr_upd2_kernel(V* __restrict__ p, const V* __restrict__ z,
-                                                        const CgnrCol* __restrict__ cols,
-                                                        const double* __restrict__ zz, int N, int S) {
+__global__ __launch_bounds__(256) void bicg_p_kernel(V* __restrict__ p, const V* __restrict__ r, const V* __restrict__ v,
+                                                     const BicgCol* __restrict__ cols, int N, int S) {
     const CgBlock k = cg_block(N);
     if (k.s >= S || !cols[k.s].active) return;
-    const double be = zz[k.s] / cols[k.s].gamma;
+    const double br = cols[k.s].be_r, bi = cols[k.s].be_i, wr = cols[k.s].om_r, wi = cols[k.s].om_i;
     for (int j = k.j0; j < k.j1; j += 4) {
         const size_t e = cg_at(k.tile, j, k.c, N);
-        const double2 pp = ld2(p[e]), zv = ld2(z[e]);
-        p[e] = st2<V>(zv.x + be * pp.x, zv.y + be * pp.y);
+        const double2 pp = ld2(p[e]), rr = ld2(r[e]), vv = ld2(v[e]);
+        const double ux = pp.x - (wr * vv.x - wi * vv.y), uy = pp.y - (wr * vv.y + wi * vv.x);
+        p[e] = st2<V>(rr.x + (br * ux - bi * uy), rr.y + (br * uy + bi * ux));
     }
 }
-__global__ void cgnr_gamma_kernel(CgnrCol* cols, const double* zz, int S) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < S && cols[s].active) cols[s].gamma = zz[s];
-}
+
 // P[s0 + s][j] = w[j][s] for s < S, 32 x 32 tiles through LDS; grid (ceil(N / 32),
 // padded columns / 32)
 template <typename V>
@@ -593,17 +705,17 @@ namespace {
 size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
 
 constexpr size_t CALD_W_BUDGET = size_t(2) << 30;    // workspace rows of one chunk of test triangles
-constexpr size_t CALD_CG_BUDGET = size_t(6) << 30;   // CGNR vectors of one column batch
+constexpr size_t CALD_CG_BUDGET = size_t(6) << 30;   // Gram-solve vectors of one column batch
 
 struct CaldPlan {
     int chunk = 1, nchunks = 1, Sb = 1;
     size_t entries = 0;   // (BC row, workspace row, coefficient) list entries over all chunks
-    size_t vsz = 16;      // bytes per complex element of the CGNR vectors
+    size_t vsz = 16;      // bytes per complex element of the Gram-solve vectors
 };
 
 CaldPlan cald_plan(const efie_calderon_s& C, int bary_dtype, double tol) {
     CaldPlan pl;
-    pl.vsz = tol >= CGNR_C64_TOL ? 8 : 16;
+    pl.vsz = tol >= GRAM_C64_TOL ? 8 : 16;
     const size_t esz = bary_dtype == EFIE_C64 ? 8 : 16;
     const size_t per_tri = size_t(6) * size_t(C.bary.N) * esz;
     const size_t Tb = size_t(C.bary.T);
@@ -611,7 +723,7 @@ CaldPlan cald_plan(const efie_calderon_s& C, int bary_dtype, double tol) {
     pl.chunk = int(std::max<size_t>(1, std::min<size_t>({Tb, CALD_W_BUDGET / per_tri, 3640})));
     pl.nchunks = int((Tb + size_t(pl.chunk) - 1) / size_t(pl.chunk));
     const size_t N = size_t(C.N);
-    pl.Sb = int(std::max<size_t>(64, std::min<size_t>(N, CALD_CG_BUDGET / (5 * N * pl.vsz))));
+    pl.Sb = int(std::max<size_t>(64, std::min<size_t>(N, CALD_CG_BUDGET / (6 * N * pl.vsz))));
     pl.entries = 2 * C.re_idx.size();
     return pl;
 }
@@ -622,9 +734,9 @@ struct CaldWs {
     int32_t *ml, *mptr, *rows;
     double* coef;
     double2* Tbc;
-    void *w, *r, *z, *p, *t;   // CGNR vectors (complex64 or complex128)
-    double *part, *bn2, *tt, *rn2, *zz;
-    CgnrCol* cols;
+    void *x, *r, *rh, *p, *v, *t;   // BiCGStab vectors (complex64 or complex128)
+    double *part, *red;             // slice sums and column sums of three reductions
+    BicgCol* cols;
     int* counter;
 };
 
@@ -645,17 +757,16 @@ size_t cald_layout(const efie_calderon_s& C, const CaldPlan& pl, int bary_dtype,
     x.rows = (int32_t*)take(4 * pl.entries);
     x.coef = (double*)take(8 * pl.entries);
     x.Tbc = (double2*)take(N * N * 16);
-    x.w = take(N * size_t(cg_pad(pl.Sb)) * pl.vsz);
-    x.r = take(N * size_t(cg_pad(pl.Sb)) * pl.vsz);
-    x.z = take(N * size_t(cg_pad(pl.Sb)) * pl.vsz);
-    x.p = take(N * size_t(cg_pad(pl.Sb)) * pl.vsz);
-    x.t = take(N * size_t(cg_pad(pl.Sb)) * pl.vsz);
-    x.part = (double*)take(8 * size_t(cg_slices(int(N))) * Sb);
-    x.bn2 = (double*)take(8 * Sb);
-    x.tt = (double*)take(8 * Sb);
-    x.rn2 = (double*)take(8 * Sb);
-    x.zz = (double*)take(8 * Sb);
-    x.cols = (CgnrCol*)take(sizeof(CgnrCol) * Sb);
+    const size_t vb = N * size_t(cg_pad(pl.Sb)) * pl.vsz;
+    x.x = take(vb);
+    x.r = take(vb);
+    x.rh = take(vb);
+    x.p = take(vb);
+    x.v = take(vb);
+    x.t = take(vb);
+    x.part = (double*)take(3 * 8 * size_t(cg_slices(int(N))) * Sb);
+    x.red = (double*)take(3 * 8 * Sb);
+    x.cols = (BicgCol*)take(sizeof(BicgCol) * Sb);
     x.counter = (int*)take(16);
     if (w) *w = x;
     return off;
@@ -736,64 +847,62 @@ size_t put(std::vector<char>& blob, std::vector<size_t>& offs, const std::vector
     return off;
 }
 
-// CGNR on A Y = B for the columns of B (N x N, row-major) in batches of pl.Sb
+// BiCGStab on A Y = B for the columns of B (N x N, row-major) in batches of pl.Sb
 // (vectors stored as V), each batch transposed into the rows of Pout; A = G^T
 // (opG false) or G (opG true).  Returns the worst final relative residual.
 template <typename V>
-double cald_cgnr(const DevCald& d, const CaldWs& w, const CaldPlan& pl, int N, double tol, int maxit, double2* Pout,
-                 const double2* B, bool opG, hipStream_t stream) {
-    // A p with the CSR of A, A^T r with the CSR of A^T
+double cald_gram_solve(const DevCald& d, const CaldWs& w, const CaldPlan& pl, int N, double tol, int maxit,
+                       double2* Pout, const double2* B, bool opG, hipStream_t stream) {
+    // A with the CSR of A (stored rows in n_order)
     const int32_t *a_ptr = opG ? d.g_ptr : d.gt_ptr, *a_idx = opG ? d.g_idx : d.gt_idx;
     const double* a_val = opG ? d.g_val : d.gt_val;
-    const int32_t *at_ptr = opG ? d.gt_ptr : d.g_ptr, *at_idx = opG ? d.gt_idx : d.g_idx;
-    const double* at_val = opG ? d.gt_val : d.g_val;
-    V* const wv = static_cast<V*>(w.w);
+    V* const xv = static_cast<V*>(w.x);
     V* const rv = static_cast<V*>(w.r);
-    V* const zv = static_cast<V*>(w.z);
+    V* const hv = static_cast<V*>(w.rh);
     V* const pv = static_cast<V*>(w.p);
+    V* const vv = static_cast<V*>(w.v);
     V* const tv = static_cast<V*>(w.t);
     double worst = 0.0;
     for (int s0 = 0; s0 < N; s0 += pl.Sb) {
         const int S = std::min(pl.Sb, N - s0);
-        const size_t tot = size_t(N) * size_t(cg_pad(S));
         const dim3 gs(cg_blocks(S, N)), gc(unsigned((S + 255) / 256));
         const int ns = cg_slices(N);
-        auto finish = [&](double* out) {   // slice sums -> per-column squared norms
-            hipLaunchKernelGGL(colsq_final_kernel, dim3(unsigned((S + 15) / 16)), dim3(256), 0, stream, w.part, S, ns,
-                               out);
+        auto finish = [&](int nred) {   // slice sums -> column sums red[y S + s], y < nred
+            hipLaunchKernelGGL(colsq_final_kernel, dim3(unsigned((S + 15) / 16), unsigned(nred)), dim3(256), 0, stream,
+                               w.part, S, ns, w.red);
         };
-        hipLaunchKernelGGL(cgnr_init_kernel<V>, gs, dim3(256), 0, stream, B + s0, N, wv, rv, N, S, w.part);
-        finish(w.bn2);
-        hipLaunchKernelGGL(cspmm_kernel<V>, gs, dim3(256), 0, stream, at_ptr, at_idx, at_val, rv, zv, S, d.n_order,
-                           N, w.part);
-        finish(w.zz);
-        EFIE_HIP_CHECK(hipMemcpyAsync(pv, zv, tot * sizeof(V), hipMemcpyDeviceToDevice, stream));
-        hipLaunchKernelGGL(cgnr_setup_kernel, gc, dim3(256), 0, stream, w.cols, w.bn2, w.zz, tol, S);
+        hipLaunchKernelGGL(bicg_init_kernel<V>, gs, dim3(256), 0, stream, B + s0, N, xv, rv, hv, pv, N, S, w.part);
+        finish(1);
+        hipLaunchKernelGGL(bicg_setup_kernel, gc, dim3(256), 0, stream, w.cols, w.red, tol, S);
         int h_active = S;
         for (int it = 0; it < maxit && h_active > 0; ++it) {
-            hipLaunchKernelGGL(cspmm_kernel<V>, gs, dim3(256), 0, stream, a_ptr, a_idx, a_val, pv, tv, S,
-                               d.n_order, N, w.part);
-            finish(w.tt);
-            hipLaunchKernelGGL(cgnr_upd1_kernel<V>, gs, dim3(256), 0, stream, wv, rv, pv, tv, w.cols, w.tt, N, S,
-                               w.part);
-            finish(w.rn2);
-            EFIE_HIP_CHECK(hipMemsetAsync(w.counter, 0, sizeof(int), stream));
-            hipLaunchKernelGGL(cgnr_check_kernel, gc, dim3(256), 0, stream, w.cols, w.rn2, w.tt, S, w.counter);
-            hipLaunchKernelGGL(cspmm_kernel<V>, gs, dim3(256), 0, stream, at_ptr, at_idx, at_val, rv, zv, S,
-                               d.n_order, N, w.part);
-            finish(w.zz);
-            hipLaunchKernelGGL(cgnr_upd2_kernel<V>, gs, dim3(256), 0, stream, pv, zv, w.cols, w.zz, N, S);
-            hipLaunchKernelGGL(cgnr_gamma_kernel, gc, dim3(256), 0, stream, w.cols, w.zz, S);
+            // v = A p, alpha = rho / <r^, v>, s = r - alpha v
+            hipLaunchKernelGGL(cspmm_dot_kernel<V>, gs, dim3(256), 0, stream, a_ptr, a_idx, a_val, pv, vv, S,
+                               d.n_order, N, hv, w.part);
+            finish(2);
+            hipLaunchKernelGGL(bicg_alpha_kernel, gc, dim3(256), 0, stream, w.cols, w.red, S);
+            hipLaunchKernelGGL(bicg_s_kernel<V>, gs, dim3(256), 0, stream, rv, vv, w.cols, N, S);
+            // t = A s, omega = <t, s> / <t, t>, x += alpha p + omega s, r = s - omega t
+            hipLaunchKernelGGL(cspmm_dot_kernel<V>, gs, dim3(256), 0, stream, a_ptr, a_idx, a_val, rv, tv, S,
+                               d.n_order, N, rv, w.part);
+            finish(3);
+            hipLaunchKernelGGL(bicg_omega_kernel, gc, dim3(256), 0, stream, w.cols, w.red, S);
+            hipLaunchKernelGGL(bicg_xr_kernel<V>, gs, dim3(256), 0, stream, xv, rv, pv, tv, hv, w.cols, N, S, w.part);
+            finish(3);
+            fill_zero_bytes(w.counter, 8, stream);
+            hipLaunchKernelGGL(bicg_check_kernel, gc, dim3(256), 0, stream, w.cols, w.red, S, w.counter);
+            // p = r + beta (p - omega v)
+            hipLaunchKernelGGL(bicg_p_kernel<V>, gs, dim3(256), 0, stream, pv, rv, vv, w.cols, N, S);
             EFIE_HIP_CHECK(hipMemcpyAsync(&h_active, w.counter, sizeof(int), hipMemcpyDeviceToHost, stream));
             EFIE_HIP_CHECK(hipStreamSynchronize(stream));
         }
         hipLaunchKernelGGL(tile_out_kernel<V>, dim3(unsigned((N + 31) / 32), unsigned(cg_pad(S) / 32)), dim3(256), 0,
-                           stream, wv, S, N, Pout, s0);
+                           stream, xv, S, N, Pout, s0);
         if (verbose())
-            std::fprintf(stderr, "[efie] calderon CGNR columns %d..%d done t=%.3f\n", s0, s0 + S, now_s()),
+            std::fprintf(stderr, "[efie] calderon Gram solve columns %d..%d done t=%.3f\n", s0, s0 + S, now_s()),
                 std::fflush(stderr);
-        std::vector<CgnrCol> cols(static_cast<size_t>(S));
-        EFIE_HIP_CHECK(hipMemcpyAsync(cols.data(), w.cols, sizeof(CgnrCol) * size_t(S), hipMemcpyDeviceToHost, stream));
+        std::vector<BicgCol> cols(static_cast<size_t>(S));
+        EFIE_HIP_CHECK(hipMemcpyAsync(cols.data(), w.cols, sizeof(BicgCol) * size_t(S), hipMemcpyDeviceToHost, stream));
         EFIE_HIP_CHECK(hipStreamSynchronize(stream));
         for (const auto& cc : cols) worst = std::max(worst, cc.bn2 > 0 ? std::sqrt(cc.rn2 / cc.bn2) : 0.0);
     }
@@ -999,8 +1108,9 @@ int efie_calderon_assemble_ex(efie_calderon c, double kt_re, double kt_im, doubl
             EFIE_HIP_CHECK(hipMemcpyAsync(Tbc_out, w.Tbc, size_t(N) * N * 16, hipMemcpyDeviceToDevice, stream));
         // ---- P = T_BC G^{-1}: column batches of G^T Y = T_BC (column s = row s of T_BC), P = Y^T
         const double worst =
-            pl.vsz == 8 ? cald_cgnr<float2>(d, w, pl, N, tol, maxit, static_cast<double2*>(P), w.Tbc, false, stream)
-                        : cald_cgnr<double2>(d, w, pl, N, tol, maxit, static_cast<double2*>(P), w.Tbc, false, stream);
+            pl.vsz == 8
+                ? cald_gram_solve<float2>(d, w, pl, N, tol, maxit, static_cast<double2*>(P), w.Tbc, false, stream)
+                : cald_gram_solve<double2>(d, w, pl, N, tol, maxit, static_cast<double2*>(P), w.Tbc, false, stream);
         if (relres) *relres = worst;
         EFIE_HIP_CHECK(hipGetLastError());
         return worst <= tol ? int(EFIE_OK) : int(EFIE_NOT_CONVERGED);
@@ -1092,8 +1202,9 @@ int efie_calderon_cfie_assemble(efie_calderon c, double k, double kt_re, double 
         }
         // Q = M~ G^-T: row s of Q solves G y = row s of M~
         const double worst =
-            pl.vsz == 8 ? cald_cgnr<float2>(d, w, pl, N, tol, maxit, static_cast<double2*>(Q), w.Tbc, true, stream)
-                        : cald_cgnr<double2>(d, w, pl, N, tol, maxit, static_cast<double2*>(Q), w.Tbc, true, stream);
+            pl.vsz == 8
+                ? cald_gram_solve<float2>(d, w, pl, N, tol, maxit, static_cast<double2*>(Q), w.Tbc, true, stream)
+                : cald_gram_solve<double2>(d, w, pl, N, tol, maxit, static_cast<double2*>(Q), w.Tbc, true, stream);
         if (relres) *relres = worst;
         EFIE_HIP_CHECK(hipGetLastError());
         return worst <= tol ? int(EFIE_OK) : int(EFIE_NOT_CONVERGED);
