@@ -56,7 +56,7 @@ constexpr int gemm_min_waves() {
 template <int BM, int BNC, int KC, bool ACC64>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_min_waves<BM, BNC, KC, ACC64>())))
 void cgemm_planar_kernel(const float2* __restrict__ X, const float2* __restrict__ Z,
-                                                           void* __restrict__ Yv, int M, int n,
+                                                           void* __restrict__ Yv, int M, int mrows, int n,
                                                            const int* __restrict__ yrow) {
     constexpr int AS = KC + 2;             // float2 per LDS row (16-byte aligned rows)
     constexpr int WM = BM / 2, WN = BNC / 2;
@@ -79,7 +79,9 @@ void cgemm_planar_kernel(const float2* __restrict__ X, const float2* __restrict_
     const int bm = logical % nbm, bn = logical / nbm;
     const int s0 = bm * BM, i0 = bn * BNC;
     const bool vec = (n & 1) == 0 && ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Z)) & 15) == 0;
-    const bool inside = vec && s0 + BM <= M && i0 + BNC <= n;
+    // X has mrows >= M readable rows (rows M.. are computed and not written): a tile
+    // within them takes the unchecked loads
+    const bool inside = vec && s0 + BM <= mrows && i0 + BNC <= n;
 
     // FP32 path: accr, acci = Yr, Yi (four real products per complex block).
     // ACC64 path, 3M form: accr = sum xr zr, acci = sum xi zi, acc3 = sum (xr + xi)(zr + zi)
@@ -132,7 +134,7 @@ void cgemm_planar_kernel(const float2* __restrict__ X, const float2* __restrict_
 #pragma unroll
             for (int q = 0; q < NA; ++q) {
                 const int e = tid + 256 * q, r = e / KV, c = e % KV;
-                ga[q] = load2(X, s0 + r, M, j0 + 2 * c);
+                ga[q] = load2(X, s0 + r, mrows, j0 + 2 * c);
             }
 #pragma unroll
             for (int q = 0; q < NB; ++q) {
@@ -272,44 +274,54 @@ bool cgemm_mfma_supported(int M, int n) { return M >= 1 && n >= 1; }
 struct Variant {
     int bm, bn, kc;
 };
-static const Variant kVariants[] = {{64, 32, 32}, {64, 64, 16}, {64, 64, 32}, {128, 32, 16},
+static constexpr Variant kVariants[] = {{64, 32, 32}, {64, 64, 16}, {64, 64, 32}, {128, 32, 16},
                                     {32, 64, 16}, {128, 64, 16}, {64, 32, 16}, {64, 128, 16}};
 static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 static int g_variant[2] = {1, 2};   // defaults: complex64 output, FP64-flush output
 
+// X rows readable: mcap >= M; the kernel reads up to the tile's multiple of M
+// within them, so that a ragged last tile still takes the unchecked loads
 template <int BM, int BN, int KC, bool A64>
-static void launch_v(const void* X, const void* Z, void* Y, const int* yrow, int M, int n, hipStream_t s) {
+static void launch_v(const void* X, const void* Z, void* Y, const int* yrow, int M, int mcap, int n, hipStream_t s) {
     const int nbm = (M + BM - 1) / BM, nbn = (n + BN - 1) / BN;
     const size_t nblk = size_t(nbm) * nbn;
     EFIE_REQUIRE(nblk < (size_t(1) << 31), EFIE_ERR_ARG, "cgemm: problem too large");
+    const int mrows = std::max(M, std::min(nbm * BM, mcap));
     hipLaunchKernelGGL((cgemm_planar_kernel<BM, BN, KC, A64>), dim3(unsigned(nblk)), dim3(256), 0, s,
-                       static_cast<const float2*>(X), static_cast<const float2*>(Z), Y, M, n, yrow);
+                       static_cast<const float2*>(X), static_cast<const float2*>(Z), Y, M, mrows, n, yrow);
 }
 
 template <bool A64>
-static void launch_variant(int v, const void* X, const void* Z, void* Y, const int* yrow, int M, int n,
+static void launch_variant(int v, const void* X, const void* Z, void* Y, const int* yrow, int M, int mcap, int n,
                            hipStream_t s) {
     switch (v) {
-        case 0: launch_v<64, 32, 32, A64>(X, Z, Y, yrow, M, n, s); break;
-        case 1: launch_v<64, 64, 16, A64>(X, Z, Y, yrow, M, n, s); break;
-        case 2: launch_v<64, 64, 32, A64>(X, Z, Y, yrow, M, n, s); break;
-        case 3: launch_v<128, 32, 16, A64>(X, Z, Y, yrow, M, n, s); break;
-        case 4: launch_v<32, 64, 16, A64>(X, Z, Y, yrow, M, n, s); break;
-        case 5: launch_v<128, 64, 16, A64>(X, Z, Y, yrow, M, n, s); break;
-        case 6: launch_v<64, 32, 16, A64>(X, Z, Y, yrow, M, n, s); break;
-        default: launch_v<64, 128, 16, A64>(X, Z, Y, yrow, M, n, s); break;
+        case 0: launch_v<64, 32, 32, A64>(X, Z, Y, yrow, M, mcap, n, s); break;
+        case 1: launch_v<64, 64, 16, A64>(X, Z, Y, yrow, M, mcap, n, s); break;
+        case 2: launch_v<64, 64, 32, A64>(X, Z, Y, yrow, M, mcap, n, s); break;
+        case 3: launch_v<128, 32, 16, A64>(X, Z, Y, yrow, M, mcap, n, s); break;
+        case 4: launch_v<32, 64, 16, A64>(X, Z, Y, yrow, M, mcap, n, s); break;
+        case 5: launch_v<128, 64, 16, A64>(X, Z, Y, yrow, M, mcap, n, s); break;
+        case 6: launch_v<64, 32, 16, A64>(X, Z, Y, yrow, M, mcap, n, s); break;
+        default: launch_v<64, 128, 16, A64>(X, Z, Y, yrow, M, mcap, n, s); break;
     }
 }
 
-void cgemm_mfma(const void* X, const void* Z, void* Y, int M, int n, hipStream_t s) {
+// the tile of 32 right-hand sides: for few columns it leaves half the matrix-core
+// work of the 64-row tiles undone (about 2.5 ms against 4.1 ms at 32 columns, level 5)
+constexpr int kSmallVariant = 4;
+static_assert(kVariants[kSmallVariant].bm == 32, "the small-M tile has 32 rows");
+
+void cgemm_mfma(const void* X, const void* Z, void* Y, int M, int n, hipStream_t s, int mcap) {
     prof_begin(PROF_MFMA, s);
-    launch_variant<false>(g_variant[0], X, Z, Y, nullptr, M, n, s);
+    launch_variant<false>(g_variant[0], X, Z, Y, nullptr, M, std::max(M, mcap), n, s);
     prof_end(PROF_MFMA, s, 8.0 * M * double(n) * n);
 }
 
-void cgemm_mfma_acc64(const void* X, const void* Z, double2* Y, const int* yrow, int M, int n, hipStream_t s) {
+void cgemm_mfma_acc64(const void* X, const void* Z, double2* Y, const int* yrow, int M, int n, hipStream_t s,
+                      int mcap, bool small_tile) {
     prof_begin(PROF_MFMA, s);
-    launch_variant<true>(g_variant[1], X, Z, Y, yrow, M, n, s);
+    const int v = small_tile && M <= kVariants[kSmallVariant].bm ? kSmallVariant : g_variant[1];
+    launch_variant<true>(v, X, Z, Y, yrow, M, std::max(M, mcap), n, s);
     prof_end(PROF_MFMA, s, 8.0 * M * double(n) * n);
 }
 
@@ -404,9 +416,9 @@ extern "C" int efie_gemm_autotune(const void* Z, int64_t n, const void* X, int64
         for (int v = 0; v < efie::kNumVariants; ++v) {
             auto run = [&]() {
                 if (acc64)
-                    efie::launch_variant<true>(v, X, Z, Y, idx, int(M), int(n), stream);
+                    efie::launch_variant<true>(v, X, Z, Y, idx, int(M), int(M), int(n), stream);
                 else
-                    efie::launch_variant<false>(v, X, Z, Y, nullptr, int(M), int(n), stream);
+                    efie::launch_variant<false>(v, X, Z, Y, nullptr, int(M), int(M), int(n), stream);
             };
             run();   // warm-up
             EFIE_HIP_CHECK(hipEventRecord(e0, stream));

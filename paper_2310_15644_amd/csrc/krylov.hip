@@ -500,6 +500,7 @@ struct Ws {
     double2 *r, *rt, *u, *p, *q, *v, *w;   // Krylov vectors (S x n each)
     double2 *res, *dlt;                     // outer refinement (CGS, mixed): residual and correction
     float2* x32;                            // complex64 staging of the product input
+    int x32_rows;                           // its rows (S rounded up to 128)
     float2* y32;                            // complex64 product output (FP32 accumulation)
     bool acc64;                             // FP64 flush of the matrix-core partial sums
     double2* part;                          // partial sums of the K-split product of <= 8 columns
@@ -511,11 +512,15 @@ struct Ws {
 };
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+int64_t x32_rows(int64_t S) { return (S + 127) / 128 * 128; }
 
 
 size_t layout(int64_t n, int64_t S, int dtype, Ws* ws, char* base) {
     const size_t vec = align256(size_t(n) * size_t(S) * 16);
-    const size_t vec32 = dtype == EFIE_C64 && S > 1 ? align256(size_t(n) * size_t(S) * 8) : 0;
+    // the complex64 staging of the product input holds S rounded up to 128 rows, so
+    // that every tile of the matrix-core product reads whole tiles (the rows past
+    // the active columns are computed and dropped)
+    const size_t vec32 = dtype == EFIE_C64 && S > 1 ? align256(size_t(n) * size_t(x32_rows(S)) * 8) : 0;
     const size_t outer = dtype == EFIE_C64 ? vec : 0;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -524,6 +529,7 @@ size_t layout(int64_t n, int64_t S, int dtype, Ws* ws, char* base) {
         return p;
     };
     Ws w{};
+    w.x32_rows = int(x32_rows(S));
     w.r = (double2*)take(vec); w.rt = (double2*)take(vec); w.u = (double2*)take(vec); w.p = (double2*)take(vec);
     w.q = (double2*)take(vec); w.v = (double2*)take(vec); w.w = (double2*)take(vec);
     w.res = (double2*)take(outer); w.dlt = (double2*)take(outer);
@@ -555,9 +561,9 @@ void product(const void* Z, int zdt, int n, const double2* X, double2* Y, const 
     } else if (zdt == EFIE_C64 && !exact64) {
         gather_cast(X, idx, m, n, w.x32, st);
         if (w.acc64) {
-            cgemm_mfma_acc64(w.x32, Z, Y, idx, m, n, st);
+            cgemm_mfma_acc64(w.x32, Z, Y, idx, m, n, st, w.x32_rows, true);
         } else {
-            cgemm_mfma(w.x32, Z, w.y32, m, n, st);
+            cgemm_mfma(w.x32, Z, w.y32, m, n, st, w.x32_rows);
             scatter_cast(w.y32, idx, m, n, Y, st);
         }
     } else {

@@ -26,11 +26,15 @@ void gather_cast(const double2* X, const int* idx, int m, int n, float2* out, hi
 void scatter_cast(const float2* in, const int* idx, int m, int n, double2* Y, hipStream_t s);
 
 // Y (M x n, complex64) = X (M x n, complex64) * Z^T (Z n x n complex64) on FP32 matrix cores.
-void cgemm_mfma(const void* X, const void* Z, void* Y, int M, int n, hipStream_t s);
+// mcap: rows of X that may be read (>= M; the rows past M are computed and dropped).
+void cgemm_mfma(const void* X, const void* Z, void* Y, int M, int n, hipStream_t s, int mcap = 0);
 bool cgemm_mfma_supported(int M, int n);
 // Y[yrow[r]] (complex128) = sum_j X[r][j] Z[i][j]: same product with the FP32 matrix-core
-// partial sums flushed into FP64 accumulators every 16 complex elements of K.
-void cgemm_mfma_acc64(const void* X, const void* Z, double2* Y, const int* yrow, int M, int n, hipStream_t s);
+// partial sums flushed into FP64 accumulators every two K chunks.  mcap: rows of X
+// that may be read (>= M; the rows past M are computed and dropped); small_tile:
+// M <= 32 takes the 32-row tile instead of the selected one.
+void cgemm_mfma_acc64(const void* X, const void* Z, double2* Y, const int* yrow, int M, int n, hipStream_t s,
+                      int mcap = 0, bool small_tile = false);
 
 void cast_c128_to_c64(const void* a, void* b, size_t n, hipStream_t s);
 void cast_c64_to_c128(const void* a, void* b, size_t n, hipStream_t s);
