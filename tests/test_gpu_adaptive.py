@@ -37,7 +37,7 @@ def test_far_rule_l2_c128_every_path(dev, k):
     Zo = oefie.assemble(oracle_mesh(2), k, far3=3.0)
     Z7 = oefie.assemble(oracle_mesh(2), k)
     assert rel_max(Zo, Z7) > 1e-8                       # the rule changed the operator
-    Zw = P.assemble(m, k).cpu().numpy()                 # two-pass (workspace) path
+    Zw = P.assemble(m, k).cpu().numpy()                 # tile (workspace) path
     Za = P.assemble(m, k, atomic=True).cpu().numpy()    # atomic path
     assert rel_max(Zw, Zo) <= 1e-11 and rel_max(Za, Zo) <= 1e-11
     assert np.abs(Zw - Zw.T).max() <= 1e-14 * np.abs(Zw).max()
@@ -81,7 +81,7 @@ def test_far_rule_l4_sampled_rows(dev):
 
 
 def test_far_rule_l5_sampled_entries_c64(dev):
-    """Full size (level 5, N = 30720, k = 10), complex64 two-pass assembly as the
+    """Full size (level 5, N = 30720, k = 10), complex64 tile assembly as the
     bench runs it: sampled entries against the oracle's, one by one."""
     flush("far rule L5 c64 sampled entries")
     m = far_mesh(5, 4.0, dev)

@@ -179,7 +179,7 @@ def test_assemble_l4_sampled_rows(dev, k):
 
 
 def test_assemble_l5_sampled_entries_c64(dev):
-    """Full size (level 5, N = 30720, k = 10), complex64 two-pass assembly as the
+    """Full size (level 5, N = 30720, k = 10), complex64 tile assembly as the
     bench runs it: sampled entries, the diagonal and a near pair among them,
     against the oracle's, one by one."""
     flush("assemble L5 c64 sampled entries")
