@@ -238,8 +238,7 @@ void launch_near(const DevMesh& m, double kr, double ki, const Scale& sc, void* 
 }  // namespace
 
 
-// First pass of the atomic-free assembly for test triangles [c0, c1): every pair
-// value of Z = eta (j k T_A + T_Phi / (j k)) (far pairs in the storage precision,
+// The pair rows of test triangles [c0, c1): every pair value of Z = eta (j k T_A + T_Phi / (j k)) (far pairs in the storage precision,
 // near pairs in FP64) into rows W[p - c0][i][n][side] of complex64 (dtype
 // EFIE_C64) or complex128 elements.  Used by the Calderon build, which contracts
 // these rows without forming the matrix.  upper: only the pairs with source

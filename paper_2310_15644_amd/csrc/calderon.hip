@@ -3,8 +3,8 @@
 //
 //   T_BC = R^T T_bary(k~) R   without forming T_bary (N_b x N_b, 543 GB in complex128
 //       for the level-5 sphere): per chunk of barycentric test triangles p,
-//         W[p][i][f][side]       every pair value (the first pass of the atomic-free
-//                                assembly, complex k~),
+//         W[p][i][f][side]       every pair value (the pair rows of rows_kernels.h,
+//                                complex k~),
 //         Yw[(p,i)][n] = sum_f (W[p][i][f][0] + W[p][i][f][1]) R[f][n]
 //                                (R by BC function n, CSC: a gather along the row),
 //         T_BC[m][:] += sum R[e(p,i)][m] Yw[(p,i)][:]
@@ -270,10 +270,6 @@ __device__ inline void cg_part(double sq, const CgBlock& k, int S, double* part)
     if (k.wv == 0 && k.s < S) part[size_t(k.slice) * S + k.s] = sh[0][k.c] + sh[1][k.c] + sh[2][k.c] + sh[3][k.c];
 }
 
-// Out[j] = sum_q val[q] X[idx[q]] for the rows of a real CSR matrix stored in the
-// spatially coherent order (stored row t is row j = order[t]), over the stored
-// rows of the block's slice, for the columns of the block's tile;
-// part[slice][s] = sum over those rows of |Out[j][s]|^2
 // ar + j ai += sum of val[e] Xt[idx[e] CG_W] over e = kb .. min(kb + G, ke) - 1
 // (indices past ke repeat the last entry with weight 0)
 template <int G, typename V>
@@ -297,33 +293,12 @@ __device__ inline void csp_group(const int32_t* __restrict__ idx, const double* 
     }
 }
 
-template <typename V>
-__global__ __launch_bounds__(256) void cspmm_kernel(const int32_t* __restrict__ ptr, const int32_t* __restrict__ idx,
-                                                    const double* __restrict__ val, const V* __restrict__ X,
-                                                    V* __restrict__ Out, int S, const int32_t* __restrict__ order,
-                                                    int N, double* __restrict__ part) {
-    const CgBlock k = cg_block(N);
-    if (k.tile * CG_W >= S) return;   // a whole block of the rounding tiles
-    const V* Xt = X + cg_at(k.tile, 0, k.c, N);
-    double sq = 0.0;
-    for (int t = k.j0; t < k.j1; t += 4) {
-        double ar = 0, ai = 0;
-        // the (wave-uniform) row in groups of 8 gathers in flight, the rest in groups of 4
-        int kb = ptr[t];
-        const int ke = ptr[t + 1];
-        for (; kb + 8 <= ke; kb += 8) csp_group<8>(idx, val, Xt, kb, ke, ar, ai);
-        for (; kb < ke; kb += 4) csp_group<4>(idx, val, Xt, kb, ke, ar, ai);
-        const V o = st2<V>(ar, ai);
-        Out[cg_at(k.tile, order[t], k.c, N)] = o;
-        const double2 od = ld2(o);   // the norm of the stored value
-        sq += od.x * od.x + od.y * od.y;
-    }
-    cg_part(sq, k, S, part);
-}
-
-// Out = A X as cspmm_kernel, and the slice sums of three column reductions:
-// part[0] and part[1] the real and imaginary parts of sum_j conj(Y[j]) Out[j],
-// part[2] sum_j |Out[j]|^2 (part[v] = part + v ns S)
+// Out[j] = sum_q val[q] X[idx[q]] for the rows of a real CSR matrix A stored in
+// the spatially coherent order (stored row t is row j = order[t]), over the stored
+// rows of the block's slice, for the columns of the block's tile; and the slice
+// sums of three column reductions over those rows: part[0] and part[1] the real
+// and imaginary parts of sum_j conj(Y[j]) Out[j], part[2] sum_j |Out[j]|^2
+// (part[v] = part + v ns S)
 template <typename V>
 __global__ __launch_bounds__(256) void cspmm_dot_kernel(const int32_t* __restrict__ ptr,
                                                         const int32_t* __restrict__ idx,

@@ -46,7 +46,7 @@ __host__ __device__ inline Tables<float> tables_of<float>(const DevMesh& m) {
             m.q3x32, m.q3y32, m.q3z32, m.q3w32};
 }
 
-// pass 1, one block (FAR_BLOCK threads) of logical index `logical` = (group of
+// the far pair rows, one block (FAR_BLOCK threads) of logical index `logical` = (group of
 // FAR_PB test triangles of the chunk, 256 source triangles).  A block takes FAR_PB
 // test triangles against its source triangles: the source triangles' tables, read
 // for the first, are cache hits for the others.  UPPER: only the far pairs with
@@ -87,10 +87,10 @@ __device__ __forceinline__ void far_rows_block(const DevMesh& m, const Tables<R>
     }
 }
 
-// the ordered near pair e = (p, q) with p in the chunk [c0, c1): its values replace
-// the zeros pass 1 wrote (FP64 arithmetic, all nine entries).  upper: pairs with
-// q < p are not written and the diagonal blocks (q = p) are halved.
-// (by the group of NEAR_G lanes, lane g)
+// the ordered near pair e = (p, q) with p in the chunk [c0, c1), by the group of
+// NEAR_G lanes (lane g): its values replace the zeros the far rows wrote (FP64
+// arithmetic, all nine entries).  upper: pairs with q < p are not written and the
+// diagonal blocks (q = p) are halved.
 template <typename R>
 __device__ __forceinline__ void near_rows_one(const DevMesh& m, double kr, double ki, const Scale& sc,
                                               typename Cplx<R>::T* __restrict__ W, int c0, int c1, int e, int g,
