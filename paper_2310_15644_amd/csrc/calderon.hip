@@ -80,7 +80,10 @@ template <typename C2, int RRL>
 __global__ __launch_bounds__(256) void bc_src_kernel(DevCald c, const C2* __restrict__ W, double2* __restrict__ Yw,
                                                      int nrows, const int32_t* __restrict__ et, int c0) {
     static_assert(BC_UMAX % 256 == 0, "list bound must be a multiple of the block");
-    __shared__ C2 lw[RRL][BC_UMAX];
+    // the RRL rows of one list entry adjacent, so that a thread reads them with a
+    // few wide LDS loads (random entries meet bank conflicts once per load, not once
+    // per row)
+    __shared__ C2 lw[BC_UMAX][RRL];
     const int b = blockIdx.x;
     const int r0 = blockIdx.y * RRL;
     const int u0 = c.u_ptr[b], nu = c.u_ptr[b + 1] - u0;   // 1 <= nu <= BC_UMAX by construction
@@ -113,7 +116,7 @@ __global__ __launch_bounds__(256) void bc_src_kernel(DevCald c, const C2* __rest
         }
 #pragma unroll
         for (int q = 0; q < BC_NQ; ++q)
-            if (int(threadIdx.x) + 256 * q < nu) lw[u][threadIdx.x + 256 * q] = x[q];
+            if (int(threadIdx.x) + 256 * q < nu) lw[threadIdx.x + 256 * q][u] = x[q];
 #pragma unroll
         for (int q = 0; q < BC_NQ; ++q) x[q] = y[q];
     }
@@ -135,13 +138,15 @@ __global__ __launch_bounds__(256) void bc_src_kernel(DevCald c, const C2* __rest
             v[q] = kb + q < ke ? c.r_val[k] : 0.0;
         }
 #pragma unroll
-        for (int q = 0; q < BC_KG; ++q)
+        for (int q = 0; q < BC_KG; ++q) {
+            const C2* e = lw[l[q]];
 #pragma unroll
             for (int u = 0; u < RRL; ++u) {
-                const C2 xx = lw[u][l[q]];
+                const C2 xx = e[u];
                 ar[u] += v[q] * double(xx.x);
                 ai[u] += v[q] * double(xx.y);
             }
+        }
     }
 #pragma unroll
     for (int u = 0; u < RRL; ++u)
