@@ -915,12 +915,15 @@ def main():
     if args.fp64_steps > 0 and dt == P.C64 and args.solver == "calderon":
         fp64 = fp64_leg(args, P, torch, np, m, kh_d, po_d, V, J, cal)
     gemm_key = "mfma" if dt == P.C64 else "zgemm"
-    n_mm, ms_mm, fl_mm = prof[gemm_key]
     # Z.X launches inside the solve run over the active (unconverged) columns only:
-    # the algorithmic flops 8 M N N are summed per launch with its own M.
+    # the algorithmic flops 8 M N N are summed per launch with its own M.  The
+    # roofline is that of the selected tile ("mfma"); the metric's value counts
+    # every matrix-core launch, those of <= 32 columns on the 32-row tile too.
+    n_mm, ms_mm, fl_mm = prof[gemm_key]
+    n_sm, ms_sm, fl_sm = prof["mfma_small"] if dt == P.C64 else (0, 0.0, 0.0)
     avg_mm = ms_mm / max(n_mm, 1)
     flops = fl_mm / max(n_mm, 1)                 # mean algorithmic flops per launch
-    zx_gflops = fl_mm / (ms_mm * 1e-3) / 1e9 if n_mm else float("nan")
+    zx_gflops = (fl_mm + fl_sm) / ((ms_mm + ms_sm) * 1e-3) / 1e9 if n_mm + n_sm else float("nan")
     n_far, ms_far, _ = prof["far"]
     n_near, ms_near, _ = prof["near"]
     asm_ms = (ms_far + ms_near) / args.steps
@@ -967,6 +970,8 @@ def main():
         "zx_gflops": round(zx_gflops, 2),
         "zx_launches": n_mm,
         "zx_ms_per_launch": round(avg_mm, 4),
+        "zx_small_launches": n_sm,
+        "zx_small_ms_per_launch": round(ms_sm / n_sm, 4) if n_sm else None,
         "assembly_mentries_per_s": round(mentries, 1),
         "assembly_ms": round(asm_ms, 3),
         "time_to_solve_s": round(tts, 3),

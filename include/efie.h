@@ -641,7 +641,9 @@ int efie_convert(const void* src, int src_dtype, void* dst, int dst_dtype, int64
  * matrix-core GEMM, 3 GEMV, 4 FP64 GEMM, 5 Krylov vector kernels, 6 excitation,
  * 7 far field, 8 / 9 / 10 vertex gradient far pairs / near pairs / per-triangle
  * excitation and radiation terms, 11 the near pairs of the pair rows of the
- * Calderon build (beside its far pairs, on a second stream).  efie_prof_read waits for the recorded events and returns the
+ * Calderon build (beside its far pairs, on a second stream), 12 the mixed
+ * solves' complex64 matrix-core products of at most 32 columns (the 32-row tile;
+ * id 2 holds the others).  efie_prof_read waits for the recorded events and returns the
  * launch count, summed milliseconds and summed algorithmic work (real flops for
  * the GEMMs, 8 M n n per complex product; Z bytes read for the GEMVs; triangle
  * pairs for the gradient pair kernels and triangles for its per-triangle

@@ -56,7 +56,7 @@ EXPORTED = [
     "efie_solve_cfie_workspace_size", "efie_solve_cfie",
 ]
 PROF_IDS = {"far": 0, "near": 1, "mfma": 2, "gemv": 3, "zgemm": 4, "krylov": 5, "excite": 6, "farfield": 7, "grad_far": 8,
-            "grad_near": 9, "grad_tri": 10, "rows_near": 11}
+            "grad_near": 9, "grad_tri": 10, "rows_near": 11, "mfma_small": 12}
 
 
 class EfieError(RuntimeError):

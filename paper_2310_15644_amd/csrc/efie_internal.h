@@ -163,7 +163,7 @@ namespace efie {
 // on the launch stream.
 enum ProfId { PROF_FAR = 0, PROF_NEAR = 1, PROF_MFMA = 2, PROF_GEMV = 3, PROF_ZGEMM = 4, PROF_KRYLOV = 5,
               PROF_EXCITE = 6, PROF_FARFIELD = 7, PROF_GRAD_FAR = 8, PROF_GRAD_NEAR = 9, PROF_GRAD_TRI = 10,
-              PROF_ROWS_NEAR = 11, PROF_COUNT = 12 };
+              PROF_ROWS_NEAR = 11, PROF_MFMA_SMALL = 12, PROF_COUNT = 13 };
 void prof_begin(int id, hipStream_t s);
 void prof_end(int id, hipStream_t s, double work = 0.0);   // work: algorithmic flops or bytes of the launch
 }  // namespace efie

@@ -319,10 +319,11 @@ void cgemm_mfma(const void* X, const void* Z, void* Y, int M, int n, hipStream_t
 
 void cgemm_mfma_acc64(const void* X, const void* Z, double2* Y, const int* yrow, int M, int n, hipStream_t s,
                       int mcap, bool small_tile) {
-    prof_begin(PROF_MFMA, s);
-    const int v = small_tile && M <= kVariants[kSmallVariant].bm ? kSmallVariant : g_variant[1];
-    launch_variant<true>(v, X, Z, Y, yrow, M, std::max(M, mcap), n, s);
-    prof_end(PROF_MFMA, s, 8.0 * M * double(n) * n);
+    const bool small = small_tile && M <= kVariants[kSmallVariant].bm;
+    const ProfId id = small ? PROF_MFMA_SMALL : PROF_MFMA;   // timed apart from the selected tile
+    prof_begin(id, s);
+    launch_variant<true>(small ? kSmallVariant : g_variant[1], X, Z, Y, yrow, M, std::max(M, mcap), n, s);
+    prof_end(id, s, 8.0 * M * double(n) * n);
 }
 
 __global__ void iota_rows_kernel(int* idx, int M) {
