@@ -143,8 +143,9 @@ def test_calderon_c64_bary_and_mixed_solve(dev, fp32_acc):
 
 def test_calderon_l5_gram_solve_as_benched(dev):
     """Level 5 (N = 30720) in the bench's configuration: FP32 barycentric pairs with
-    the far rule at ratio 4, Gram solve to 1e-3 with complex64 vectors in six column
-    batches (the last ragged: 4510 columns).  Property at full size: sampled rows of
+    the far rule at ratio 4, Gram solve (BiCGStab) to 1e-3 with complex64 vectors in
+    eight column batches of 4369 (the last ragged: 137 columns).  Property at full
+    size: sampled rows of
     P G_mix reproduce T_BC within the solve's tolerance (P = T_BC G_mix^-1, so row s
     of P G_mix is row s of T_BC; G_mix from the host tables, independent of the
     device Gram products), and the reported worst residual bounds them."""
@@ -161,7 +162,8 @@ def test_calderon_l5_gram_solve_as_benched(dev):
     G = np.zeros((n, n))
     assert P.lib().efie_calderon_host_matrices(cal._h, None, ctypes.c_void_p(G.ctypes.data)) == 0
     rng = np.random.default_rng(3)
-    rows = sorted(set(rng.integers(0, n, 10).tolist()) | {0, 26209, 26210, n - 1})   # batch edges and the tail
+    edges = {0, 4368, 4369, 26213, 26214, 30582, 30583, n - 1}                    # batch edges and the tail
+    rows = sorted(set(rng.integers(0, n, 10).tolist()) | edges)
     Gd = torch.from_numpy(G).to(dev)
     del G
     got = Pm[rows] @ Gd.to(torch.complex128)
