@@ -49,13 +49,16 @@ struct DevCald {
 
 // Yw[row][n] = sum_k (W[row][f][0] + W[row][f][1]) r_val[k], f = r_idx[k], k over
 // column n of R (row = 3 (p - c0) + i; W rows hold 2 N_b elements, the two sides
-// of an RWG adjacent).  A block takes one run of BC functions (blockIdx.x: the
+// of an RWG adjacent).  A block takes one run of BC functions (blockIdx.y: the
 // positions run_t0[b] .. run_t0[b+1] of n_order, spatially coherent) and RRL
 // rows; it gathers once per row the distinct barycentric RWGs the run reads
 // (u_idx, sorted, so that runs of neighbouring indices coalesce), sums the two
 // sides of each into LDS, and then every thread contracts the column of R of one
-// BC function from LDS through the local positions r_loc.  W is read about 1.2
-// times in all, instead of once per BC function that uses an entry.
+// BC function from LDS through the local positions r_loc.  The row groups of a
+// run are neighbouring blocks, so that the run's list and columns of R stay in L2
+// while its rows stream past.  L2 fetches about 1.7 times the bytes of W written
+// (lines shared by neighbouring runs, lists that overlap), instead of once per BC
+// function that uses an entry.
 // two sides of barycentric RWG f in row wr, summed, each only where its flag is
 // set (a select, so that unwritten entries never enter; complex64: one 16-byte load)
 // (lanes with neither side wanted issue no load)
@@ -84,8 +87,8 @@ __global__ __launch_bounds__(256) void bc_src_kernel(DevCald c, const C2* __rest
     // few wide LDS loads (random entries meet bank conflicts once per load, not once
     // per row)
     __shared__ C2 lw[BC_UMAX][RRL];
-    const int b = blockIdx.x;
-    const int r0 = blockIdx.y * RRL;
+    const int b = blockIdx.y;
+    const int r0 = blockIdx.x * RRL;
     const int u0 = c.u_ptr[b], nu = c.u_ptr[b + 1] - u0;   // 1 <= nu <= BC_UMAX by construction
     // the run's list, once for all rows; entries past the end repeat the last one
     // (loaded, not stored), so every load below is in bounds and unconditional
@@ -1050,6 +1053,7 @@ int efie_calderon_assemble_ex(efie_calderon c, double kt_re, double kt_im, doubl
         static_assert(BC_BLOCK == 256, "one thread per BC function of a run");
         EFIE_REQUIRE(c->u_max <= BC_UMAX, EFIE_ERR_STATE, "calderon_assemble: BC run lists too long");
         const unsigned nruns = unsigned(c->run_t0.size() - 1);
+        EFIE_REQUIRE(nruns <= 65535, EFIE_ERR_STATE, "calderon_assemble: too many BC runs for one launch");
         // the barycentric operator's far rule: its own, else the primal mesh's
         const double f3 = c->far3 >= 0.0 ? c->far3 : c->primal->far3;
         c->bary.far3 = f3;
@@ -1061,11 +1065,11 @@ int efie_calderon_assemble_ex(efie_calderon c, double kt_re, double kt_im, doubl
             const int nr = 3 * np;
             if (bary_dtype == EFIE_C64)
                 hipLaunchKernelGGL((bc_src_kernel<float2, BC_RRL32>),
-                                   dim3(nruns, unsigned((nr + BC_RRL32 - 1) / BC_RRL32)), dim3(256), 0, stream, d,
+                                   dim3(unsigned((nr + BC_RRL32 - 1) / BC_RRL32), nruns), dim3(256), 0, stream, d,
                                    static_cast<const float2*>(w.W), w.Yw, nr, c->bary.dm.et, c0);
             else
                 hipLaunchKernelGGL((bc_src_kernel<double2, BC_RRL64>),
-                                   dim3(nruns, unsigned((nr + BC_RRL64 - 1) / BC_RRL64)), dim3(256), 0, stream, d,
+                                   dim3(unsigned((nr + BC_RRL64 - 1) / BC_RRL64), nruns), dim3(256), 0, stream, d,
                                    static_cast<const double2*>(w.W), w.Yw, nr, c->bary.dm.et, c0);
             if (L.nm[size_t(ch)] > 0)
                 hipLaunchKernelGGL(bc_test_kernel, dim3(nx, unsigned(L.nm[size_t(ch)])), dim3(256), 0, stream,

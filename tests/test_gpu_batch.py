@@ -1,8 +1,10 @@
 """Many uneven meshes in one persistent tile launch and one grouped solve: every
 block is bit-identical to its single-mesh assembly (the same tile device code on
 a view of each mesh's concatenated tables, no atomics), two batched assemblies
-are bit-identical, the grouped solve matches the single solves (the solutions to
-1e-8, the iteration counts within 6 %), one mesh against the oracle; the
+are bit-identical, the grouped solve of a mesh is bit-identical to the same mesh
+solved alone by the grouped solver (equal step counts) and matches the general
+single-mesh solver (the solutions to 1e-8, the step counts within 6 %), one mesh
+against the oracle; the
 64-ellipsoid set (semi-axes U[0.5, 1.5], 1k-8k unknowns) at k = 2."""
 import time
 
@@ -80,6 +82,15 @@ def test_batch_solve_equals_single(dev):
         a = J[B.voff[i]:B.voff[i + 1]].cpu().numpy()
         b = J1.cpu().numpy()[0]
         assert np.linalg.norm(a - b) <= 1e-8 * np.linalg.norm(b)
+        # the same mesh alone in a batch: the grouped solver's arithmetic for a mesh
+        # (its rows' products, its block's reductions) does not depend on the other
+        # meshes of the group, so solution and step counts are exactly those
+        B1 = P.Batch([m])
+        Z1 = B1.assemble(k, dtype=P.C128)
+        assert torch.equal(Z1, B.z_of(Zc, i).reshape(-1))
+        J1b, st1b = B1.solve(Z1, Vi, tol=1e-10, maxit=1000)
+        assert int(st1b.iters[0]) == int(st.iters[i])
+        assert torch.equal(J1b, J[B.voff[i]:B.voff[i + 1]])
 
 
 def test_batch_64_ellipsoids(dev):
