@@ -634,7 +634,7 @@ void krylov(const Op& op, int n, const double2* b, double2* x, int S, int solver
         bool exact_regime = !reliable || m <= 8;
         for (int it = 0; it < maxit && m > 0; ++it) {
             op_product(op, n, w.p, w.q, w.idx_a, m, false, w, st);
-            EFIE_HIP_CHECK(hipMemsetAsync(w.counters, 0, 2 * sizeof(int), st));
+            fill_zero_bytes(w.counters, 2 * sizeof(int), st);
             hipLaunchKernelGGL(cocg_step, dim3(S), dim3(KB), 0, st, x, w.r, w.p, w.q, w.cols, n, w.counters,
                                int(reliable));
             if (!exact_regime && m <= 8) {
@@ -663,7 +663,7 @@ void krylov(const Op& op, int n, const double2* b, double2* x, int S, int solver
             op_product(op, n, w.p, w.v, w.idx_a, m, false, w, st);
             hipLaunchKernelGGL(cgs_step1, dim3(S), dim3(KB), 0, st, x, w.rt, w.u, w.v, w.q, w.w, w.cols, n);
             op_product(op, n, w.w, w.v, w.idx_a, m, false, w, st);
-            EFIE_HIP_CHECK(hipMemsetAsync(w.counters, 0, 2 * sizeof(int), st));
+            fill_zero_bytes(w.counters, 2 * sizeof(int), st);
             hipLaunchKernelGGL(cgs_step2, dim3(S), dim3(KB), 0, st, w.r, w.rt, w.u, w.p, w.q, w.v, w.cols, n,
                                w.counters);
             m = compact(w, S, 0, w.idx_a, st);
