@@ -548,17 +548,6 @@ __global__ void gram_column_kernel(DevContour c, double2* __restrict__ g) {
     g[i] = make_double2(v, 0.0);
 }
 
-// Y = alpha X + beta Y
-__global__ void axpby_kernel(const double2* __restrict__ X, double2* __restrict__ Y, size_t count, double2 alpha,
-                             double beta) {
-    for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < count; e += size_t(gridDim.x) * blockDim.x) {
-        const double2 x = X[e];
-        double2 v = make_double2(alpha.x * x.x - alpha.y * x.y, alpha.x * x.y + alpha.y * x.x);
-        if (beta != 0.0) v = cadd(v, cscale(Y[e], beta));
-        Y[e] = v;
-    }
-}
-
 // Y = conj(X)
 __global__ void conj_kernel(const double2* __restrict__ X, double2* __restrict__ Y, size_t count) {
     for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < count; e += size_t(gridDim.x) * blockDim.x)

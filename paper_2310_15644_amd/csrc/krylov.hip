@@ -623,8 +623,6 @@ void true_residual(const void* Z, int zdt, int n, const double2* b, const double
 // One Krylov solve of Z x = b for S columns.  Returns per-column Col states in host memory.
 void krylov(const Op& op, int n, const double2* b, double2* x, int S, int solver, double tol, int maxit,
             bool reliable, const Ws& w, std::vector<Col>& out, hipStream_t st) {
-    const void* Z = op.Z;
-    const int zdt = op.zdt;
     int h[2] = {0, 0};
     if (solver == EFIE_COCG) {
         hipLaunchKernelGGL(cocg_init, dim3(S), dim3(KB), 0, st, b, x, w.r, w.p, w.cols, n, tol);
