@@ -795,8 +795,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the sharded path is a design, "
-              "not built; see the multi-GPU section of DESIGN.md", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the library drives one GPU per "
+              "process and has no sharded path (rows of Z split by test RWG across GPUs is the intended "
+              "extension, not built)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
