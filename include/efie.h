@@ -211,6 +211,18 @@ int efie_farfield_adjoint(efie_mesh mesh, double k, double eta, const void* W, i
                           const double* dirs, int64_t ndir, void* G, void* ws, size_t ws_bytes,
                           hipStream_t stream);
 
+/*
+ * The far-field objective of the differentiation form and its adjoint weight:
+ * J = sum_i |F_i|^2 over the count complex far-field values F (e.g. the
+ * (nrhs, ndir, 2) output of efie_farfield), and W = conj(F), the derivative of J
+ * with respect to F that efie_farfield_adjoint and efie_vertex_grad take.
+ *   F dev complex128 (count);  J dev, one double (written);  W dev complex128
+ *   (count, written) or NULL;  W must not alias F.  The sum runs in a fixed order
+ *   (the same value on every call).  Errors: EFIE_ERR_ARG (null F or J,
+ *   count < 1, W == F).
+ */
+int efie_farfield_objective(const void* F, int64_t count, void* J, void* W, hipStream_t stream);
+
 /* -------------------------------------------------------- vertex gradient */
 
 /*

@@ -53,7 +53,7 @@ EXPORTED = [
     "efie_bie2d_assemble", "efie_bie2d_setup", "efie_bie2d_apply", "efie_bie2d_rhs", "efie_bie2d_skeleton",
     "efie_bie2d_solve", "efie_bie2d_factors", "efie_bie2d_counterpart", "efie_bie2d_farfield",
     "efie_calderon_cfie_assemble", "efie_calderon_mfie_rhs_workspace_size", "efie_calderon_mfie_rhs",
-    "efie_solve_cfie_workspace_size", "efie_solve_cfie",
+    "efie_solve_cfie_workspace_size", "efie_solve_cfie", "efie_farfield_objective",
 ]
 PROF_IDS = {"far": 0, "near": 1, "mfma": 2, "gemv": 3, "zgemm": 4, "krylov": 5, "excite": 6, "farfield": 7, "grad_far": 8,
             "grad_near": 9, "grad_tri": 10, "rows_near": 11, "mfma_small": 12}
@@ -172,6 +172,7 @@ def lib():
         "efie_batch_solve": ([P, P, ctypes.c_int, P, P, ctypes.POINTER(_SolveOpts), ctypes.POINTER(_RhsStats), P,
                               ctypes.c_size_t, P], ctypes.c_int),
         "efie_farfield_adjoint": ([P, D, D, P, I64, P, I64, P, P, ctypes.c_size_t, P], ctypes.c_int),
+        "efie_farfield_objective": ([P, I64, P, P, P], ctypes.c_int),
         "efie_assemble_workspace_size": ([P, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t),
                                           ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "efie_assemble_ws": ([P, D, D, D, ctypes.c_int, P, P, ctypes.c_size_t, P], ctypes.c_int),
@@ -398,6 +399,22 @@ def farfield_adjoint(mesh: Mesh, k: float, W, dirs, eta: float = ETA0):
     _check(lib().efie_farfield_adjoint(mesh._h, float(k), float(eta), _ptr(W), W.shape[0], _ptr(d), nd, _ptr(G),
                                        _ptr(ws), nb.value, _stream(dev)))
     return G
+
+
+def farfield_objective(F, with_weight: bool = True):
+    """(J, W): J = sum |F|^2 (a 0-d float64 tensor on F's device) and W = conj(F)
+    (efie_farfield_objective; W is None unless with_weight).  F complex128 on the
+    device, any shape."""
+    torch = _torch()
+    _require_cuda(F, "F")
+    if F.dtype != torch.complex128:
+        raise ValueError("F must be complex128")
+    F = F.contiguous()
+    J = torch.empty((), dtype=torch.float64, device=F.device)
+    W = torch.empty_like(F) if with_weight else None
+    _check(lib().efie_farfield_objective(_ptr(F), F.numel(), _ptr(J), _ptr(W) if W is not None else None,
+                                         _stream(F.device)))
+    return J, W
 
 
 def vertex_grad(mesh: Mesh, k: float, J, lam, W, dirs, khat, pol, e0: float = 1.0, eta: float = ETA0):

@@ -103,6 +103,28 @@ __global__ __launch_bounds__(256) void radiation_adjoint_kernel(const double2* _
     G[size_t(s) * N + n] = make_double2(gr, gi);
 }
 
+// J = sum_i |F_i|^2 over count far-field values, and W = conj(F) (its derivative
+// with respect to F, the weight of the adjoint source).  One block: each thread
+// sums a fixed stride of the values, then a fixed tree over the block, so the sum
+// is the same on every call.
+__global__ __launch_bounds__(256) void farfield_objective_kernel(const double2* __restrict__ F, int64_t count,
+                                                                 double* __restrict__ J, double2* __restrict__ W) {
+    __shared__ double sh[256];
+    double a = 0.0;
+    for (int64_t i = threadIdx.x; i < count; i += 256) {
+        const double2 f = F[i];
+        a += f.x * f.x + f.y * f.y;
+        if (W) W[i] = make_double2(f.x, -f.y);
+    }
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (int(threadIdx.x) < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *J = sh[0];
+}
+
 }  // namespace efie
 
 extern "C" int efie_excite_planewave(efie_mesh mesh, double k, const double* khat, const double* pol, int64_t nrhs,
@@ -168,6 +190,18 @@ extern "C" int efie_farfield_adjoint(efie_mesh mesh, double k, double eta, const
         hipLaunchKernelGGL(efie::radiation_adjoint_kernel, dim3((N + 255) / 256, unsigned(nrhs)), dim3(256), 0, stream,
                            static_cast<const double2*>(ws), static_cast<const double2*>(W), int(2 * ndir), N, int(nrhs),
                            static_cast<double2*>(G));
+        EFIE_HIP_CHECK(hipGetLastError());
+        return int(EFIE_OK);
+    });
+}
+
+extern "C" int efie_farfield_objective(const void* F, int64_t count, void* J, void* W, hipStream_t stream) {
+    return efie::guarded([&]() {
+        EFIE_REQUIRE(F && J, EFIE_ERR_ARG, "farfield_objective: null argument");
+        EFIE_REQUIRE(count >= 1, EFIE_ERR_ARG, "farfield_objective: need count >= 1");
+        EFIE_REQUIRE(W != F, EFIE_ERR_ARG, "farfield_objective: W must not alias F");
+        hipLaunchKernelGGL(efie::farfield_objective_kernel, dim3(1), dim3(256), 0, stream,
+                           static_cast<const double2*>(F), count, static_cast<double*>(J), static_cast<double2*>(W));
         EFIE_HIP_CHECK(hipGetLastError());
         return int(EFIE_OK);
     });

@@ -6,8 +6,9 @@ the discretised EFIE (Sec. II, with the Galerkin matrices of Sec. III) seen as a
 function of the mesh vertices.  Every step runs in libefie:
 
   forward : efie_assemble (FP64) -> efie_excite_planewave -> efie_solve (COCG)
-            -> efie_farfield;  Z, j and F are kept for the backward pass.
-  backward: W = conj(F); g = R^T W (efie_farfield_adjoint); the adjoint solve
+            -> efie_farfield -> efie_farfield_objective (J and W = conj(F));
+            Z, j and W are kept for the backward pass.
+  backward: g = R^T W (efie_farfield_adjoint); the adjoint solve
             Z lambda = g reuses the saved Z because Z = Z^T; then
             dJ/dx = 2 Re[W^T dR/dx j + lambda^T dV/dx - lambda^T dZ/dx j]
             (efie_vertex_grad).
@@ -20,7 +21,8 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from . import C128, COCG, ETA0, Mesh, assemble, excite_planewave, farfield, farfield_adjoint, solve, vertex_grad
+from . import (C128, COCG, ETA0, Mesh, assemble, excite_planewave, farfield, farfield_adjoint, farfield_objective,
+               solve, vertex_grad)
 
 
 class FarFieldObjective(torch.autograd.Function):
@@ -38,17 +40,17 @@ class FarFieldObjective(torch.autograd.Function):
             raise RuntimeError(f"forward solve did not converge (relres {st.relres_true[0]:.3e})")
         d = torch.as_tensor(np.asarray(dirs, dtype=np.float64).reshape(-1, 3), device=dev)
         F = farfield(mesh, k, J, d, eta)
-        ctx.mesh, ctx.Z, ctx.J, ctx.F, ctx.d = mesh, Z, J, F, d
+        obj, W = farfield_objective(F)
+        ctx.mesh, ctx.Z, ctx.J, ctx.W, ctx.d = mesh, Z, J, W, d
         ctx.args = (float(k), np.asarray(khat, np.float64).reshape(3), np.asarray(pol, np.float64).reshape(3),
                     float(e0), float(eta), float(tol), int(maxit))
         ctx.xyz_device = xyz.device
-        return (F.real ** 2 + F.imag ** 2).sum().to(xyz.device)
+        return obj.to(xyz.device)
 
     @staticmethod
     def backward(ctx, gout):
         k, khat, pol, e0, eta, tol, maxit = ctx.args
-        mesh, Z, J, F, d = ctx.mesh, ctx.Z, ctx.J, ctx.F, ctx.d
-        W = torch.conj_physical(F).contiguous()
+        mesh, Z, J, W, d = ctx.mesh, ctx.Z, ctx.J, ctx.W, ctx.d
         g = farfield_adjoint(mesh, k, W, d, eta)
         lam, st = solve(Z, g, COCG, tol=tol, maxit=maxit)
         if int(st.status[0]) != 0:

@@ -130,6 +130,16 @@ def test_ktilde_library_errors():
         P.ktilde(1.0, -1.0)
 
 
+def test_farfield_objective_argument_errors():
+    """Rejected on the host before any device work (fake device addresses)."""
+    L = P.lib()
+    f, j = ctypes.c_void_p(4096), ctypes.c_void_p(8192)
+    assert L.efie_farfield_objective(None, 4, j, None, None) == -1   # EFIE_ERR_ARG
+    assert L.efie_farfield_objective(f, 4, None, None, None) == -1   # EFIE_ERR_ARG
+    assert L.efie_farfield_objective(f, 0, j, None, None) == -1   # EFIE_ERR_ARG
+    assert L.efie_farfield_objective(f, 4, j, f, None) == -1   # EFIE_ERR_ARG
+
+
 def test_fp32_kmax_from_bounding_box():
     """The complex64 assemblies accept |Re k| below 512 pi / (bounding-box diagonal)."""
     v, f = synth.icosphere(2)

@@ -80,6 +80,23 @@ def test_vertex_grad_terms(dev, level, k):
     assert max(e) <= 1e-10
 
 
+@pytest.mark.parametrize("shape", [(1, 32, 2), (3, 700, 2)])
+def test_farfield_objective(dev, shape):
+    """J = sum |F|^2 and W = conj(F) from the library against their definitions on
+    the same seeded F (a count below and above the block's 256 threads); the sum is
+    the same on a second call."""
+    rng = np.random.default_rng(7)
+    Fh = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    F = torch.tensor(Fh, dtype=torch.complex128, device=dev)
+    J1, W = P.farfield_objective(F)
+    J2, none = P.farfield_objective(F, with_weight=False)
+    assert none is None
+    ref = float(np.sum(Fh.real ** 2 + Fh.imag ** 2))
+    assert abs(float(J1) - ref) <= 1e-14 * ref
+    assert float(J1) == float(J2)
+    assert torch.equal(W.cpu(), torch.tensor(np.conj(Fh), dtype=torch.complex128))
+
+
 def test_objective_autograd_l2(dev):
     from paper_2310_15644_amd.objective import far_field_objective
 
