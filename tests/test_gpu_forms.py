@@ -174,6 +174,28 @@ def test_batch_512_rhs_columns_and_reciprocity_l3(dev, l3_oracle, l3_gpu):
     assert e.max() <= np.linalg.cond(Zo) * tol
 
 
+def test_bench_path_is_deterministic_l3(dev, l3_oracle, l3_gpu):
+    """The bench's path run twice on the same inputs gives the same bits: the tile
+    assembly, the preconditioner build (complex64 barycentric pairs, far rule at
+    ratio 4) and the mixed Calderon CGS of 64 plane waves -- no floating-point
+    atomics anywhere on it, every reduction in a fixed order."""
+    om, Zo, Vo, Jo, rhat, khat, pol = l3_oracle
+    m, Z32, _ = l3_gpu
+    flush("bench path L3 k=10 twice: bit-identical Z, P and currents")
+    assert torch.equal(P.assemble(m, K, dtype=P.C64), Z32)
+    cal = P.Calderon(m).upload(dev).set_far_rule(4.0)
+    P1 = cal.assemble(P.ktilde(K), tol=1e-3, bary_dtype=P.C64)
+    P2 = cal.assemble(P.ktilde(K), tol=1e-3, bary_dtype=P.C64)
+    assert torch.equal(P1, P2)
+    Pm = P.convert(P1, P.C64)
+    V = P.excite_planewave(m, K, khat[:64], pol[:64])
+    J1, s1 = P.solve_precond(Z32, Pm, V, tol=1e-6, maxit=2000)
+    J2, s2 = P.solve_precond(Z32, Pm, V, tol=1e-6, maxit=2000)
+    assert np.all(s1.status == 0)
+    assert np.array_equal(s1.iters, s2.iters)
+    assert torch.equal(J1, J2)
+
+
 def test_gemm_autotune_cache(dev, tmp_path):
     """The library's autotuner times every tile, writes its choice to the cache,
     reuses it on the next call, selects it, and re-times on force."""
