@@ -272,6 +272,43 @@ def test_gemm_every_variant(dev, n, nrhs):
         P.gemm_select(True, prev64)
 
 
+def test_gemm_l5_bench_shape_sampled(dev, tmp_path):
+    """The headline product at its full shape and launch configuration: the level-5
+    Z at k = 10 (complex64, N = 30720) times the 512 plane-wave excitations of the
+    monostatic grid, on the tile the autotuner selects, FP64-flush path -- 8 sampled
+    right-hand sides against 64 sampled unknowns, and a ragged 40-column launch,
+    against the FP64 product of the values actually stored."""
+    flush("GEMM at the bench shape: L5 Z (complex64) x 512 plane waves")
+    k = 10.0
+    v, f = icosphere(5)
+    m = P.Mesh(v, f).upload(dev)
+    Z = P.assemble(m, k, dtype=P.C64)
+    _, khat, pol, _, _ = synth.monostatic_grid(16, 32)
+    V = P.excite_planewave(m, k, khat, pol)
+    prev32, prev64 = P.gemm_select(False, 0), P.gemm_select(True, 0)
+    try:
+        tune = P.gemm_autotune(Z, 512, cache=str(tmp_path / "tiles.txt"))
+        P.gemm_select(False, tune["acc32"])
+        P.gemm_select(True, tune["acc64"])
+        flush(f"  selected tile {tune['tiles'][tune['acc64']]}")
+        rng = np.random.default_rng(5)
+        cols = np.sort(rng.choice(m.n, 64, replace=False))
+        Zc = Z[torch.as_tensor(cols, device=dev)].cpu().numpy().astype(np.complex128)   # rows = columns (Z = Z^T)
+        for nrhs in (512, 40):
+            X = V[:nrhs].contiguous()
+            Y = P.zx_flush64(Z, X)
+            rows = np.sort(rng.choice(nrhs, 8, replace=False))
+            Xr = X[torch.as_tensor(rows, device=dev)].to(torch.complex64).cpu().numpy().astype(np.complex128)
+            ref = Xr @ Zc.T
+            got = Y[torch.as_tensor(rows, device=dev)][:, torch.as_tensor(cols, device=dev)].cpu().numpy()
+            err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+            flush(f"  {nrhs} columns: sampled relative error {err:.2e}")
+            assert err <= 5e-7, (nrhs, err)
+    finally:
+        P.gemm_select(False, prev32)
+        P.gemm_select(True, prev64)
+
+
 @pytest.mark.parametrize("n", [480, 481])
 def test_zx_c64_unaligned_operands(dev, n):
     """Matrix-core product with X and Z starting 8 bytes past a 16-byte boundary
