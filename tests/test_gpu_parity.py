@@ -208,6 +208,29 @@ def test_excitation_l2(dev):
     assert rel_max(Vg, Vo) <= 1e-12
 
 
+def test_excitation_and_farfield_l5_bench_shape(dev):
+    """Full size (level 5, N = 30720, k = 10) as the bench runs them: the 512
+    plane waves of the monostatic grid excited at once, 16 of them against the
+    oracle over every RWG; the far field of seeded currents in the 512 grid
+    directions, 32 of them against the oracle."""
+    flush("excitation and far field L5 k=10, bench shape")
+    k = 10.0
+    v, f = icosphere(5)
+    m = gmesh(v, f, dev)
+    om = oracle_mesh(5)
+    rhat, khat, pol, _, _ = synth.monostatic_grid(16, 32)
+    rng = np.random.default_rng(31)
+    s = np.sort(rng.choice(512, 16, replace=False))
+    Vg = P.excite_planewave(m, k, khat, pol)[torch.as_tensor(s, device=dev)].cpu().numpy()
+    Vo = oefie.excitation(om, k, khat[s], pol[s])
+    assert rel_max(Vg, Vo) <= 1e-12
+    J = rng.standard_normal((4, m.n)) + 1j * rng.standard_normal((4, m.n))
+    d = np.sort(rng.choice(512, 32, replace=False))
+    Fg = P.farfield(m, k, torch.as_tensor(J, device=dev), rhat).cpu().numpy()[:, d]
+    Fo = oefie.farfield(om, k, J, rhat[d])
+    assert rel_max(Fg, Fo) <= 1e-12
+
+
 def test_farfield_l2(dev):
     v, f = icosphere(2)
     m = gmesh(v, f, dev)
