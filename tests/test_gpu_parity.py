@@ -300,7 +300,8 @@ def test_gemm_l5_bench_shape_sampled(dev, tmp_path):
     Z at k = 10 (complex64, N = 30720) times the 512 plane-wave excitations of the
     monostatic grid, on the tile the autotuner selects, FP64-flush path -- 8 sampled
     right-hand sides against 64 sampled unknowns, and a ragged 40-column launch,
-    against the FP64 product of the values actually stored."""
+    against the FP64 product of the values actually stored; and the single-column
+    product (GEMV) on the same sampled unknowns."""
     flush("GEMM at the bench shape: L5 Z (complex64) x 512 plane waves")
     k = 10.0
     v, f = icosphere(5)
@@ -327,6 +328,13 @@ def test_gemm_l5_bench_shape_sampled(dev, tmp_path):
             err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
             flush(f"  {nrhs} columns: sampled relative error {err:.2e}")
             assert err <= 5e-7, (nrhs, err)
+        # one right-hand side: the HBM-bound GEMV (complex64 Z and x, FP64 sums)
+        x = V[:1].to(torch.complex64)
+        y = P.zx(Z, x)[0, torch.as_tensor(cols, device=dev)].cpu().numpy().astype(np.complex128)
+        ref1 = Zc @ x[0].cpu().numpy().astype(np.complex128)
+        err1 = np.linalg.norm(y - ref1) / np.linalg.norm(ref1)
+        flush(f"  1 column (GEMV): sampled relative error {err1:.2e}")
+        assert err1 <= 1e-7, err1
     finally:
         P.gemm_select(False, prev32)
         P.gemm_select(True, prev64)
